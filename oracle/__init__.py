@@ -1,0 +1,176 @@
+"""TEST INFRASTRUCTURE: ctypes front end of the FP64 CPU oracle.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` import this package. The HIP library and its Python binding never
+do: they share no code with it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        dp = C.POINTER(C.c_double)
+        L.fo_intersect_d.argtypes = [dp, dp, C.c_int, dp, dp, C.POINTER(C.c_int64)]
+        L.fo_intersect_d.restype = C.c_int
+        L.fo_batch_d.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_int64,
+                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int64,
+                                 C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+        L.fo_batch_d.restype = None
+        L.fo_split_half.argtypes = [dp, dp, dp]
+        L.fo_split_plane.argtypes = [dp, dp, dp]
+        L.fo_unit_ray_cylinder.argtypes = [dp, dp, C.c_double, dp, dp]
+        L.fo_unit_ray_cylinder.restype = C.c_int
+        L.fo_conservative_radius.argtypes = [dp]
+        L.fo_conservative_radius.restype = C.c_double
+        L.fo_cap_interval.argtypes = [dp, C.c_double, dp]
+        L.fo_ray_frame.argtypes = [dp, dp, dp]
+        L.fo_ray_frame.restype = C.c_int
+        L.fo_cubic_constraints.argtypes = [dp]
+        L.fo_cubic_constraints.restype = C.c_int
+        if hasattr(L, "fx_batch"):
+            L.fx_batch.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_int64,
+                                   C.c_void_p, C.c_void_p, C.c_int64, C.c_double,
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+            L.fx_batch.restype = None
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def intersect_depth(rays, fibers, depth=9, pair_ray=None, pair_fiber=None,
+                    pair_depth=None, radius_scale=1.0, stats=False, nthreads=0):
+    """ORACLE-D: the paper's depth-d method in FP64 for every pair.
+
+    Returns (t float64, u float64, hit uint8[, stats int32 (n, 4)]). ``stats``
+    columns: node tests, splits, backtracks (second-child visits), leaf level
+    (-1 on a miss)."""
+    rays = np.ascontiguousarray(rays, dtype=np.float32)
+    fibers = np.ascontiguousarray(fibers, dtype=np.float32)
+    pr = None if pair_ray is None else np.ascontiguousarray(pair_ray, dtype=np.int32)
+    pf = None if pair_fiber is None else np.ascontiguousarray(pair_fiber, dtype=np.int32)
+    pd = None if pair_depth is None else np.ascontiguousarray(pair_depth, dtype=np.uint8)
+    if pr is not None:
+        n = pr.shape[0]
+    elif pf is not None:
+        n = pf.shape[0]
+    else:
+        n = min(rays.shape[1], fibers.shape[1])
+    t = np.empty(n, np.float64)
+    u = np.empty(n, np.float64)
+    hit = np.empty(n, np.uint8)
+    st = np.empty((n, 4), np.int32) if stats else None
+    lib().fo_batch_d(_ptr(rays), rays.shape[1], rays.shape[1], _ptr(fibers), fibers.shape[1],
+                     fibers.shape[1], _ptr(pr), _ptr(pf), _ptr(pd), int(depth), n,
+                     float(radius_scale), _ptr(t), _ptr(u), _ptr(hit), _ptr(st), int(nthreads))
+    return (t, u, hit, st) if stats else (t, u, hit)
+
+
+def intersect_exact(rays, fibers, pair_ray=None, pair_fiber=None, radius_scale=1.0,
+                    nthreads=0):
+    """ORACLE-X: first entry of the ray into the swept-disk solid (the limit
+    of the method), in FP64. Returns (t, u, hit, kind) where kind is 0 miss,
+    1 side surface, 2 start cap, 3 end cap, 4 origin inside."""
+    L = lib()
+    if not hasattr(L, "fx_batch"):
+        raise RuntimeError("exact oracle not built")
+    rays = np.ascontiguousarray(rays, dtype=np.float32)
+    fibers = np.ascontiguousarray(fibers, dtype=np.float32)
+    pr = None if pair_ray is None else np.ascontiguousarray(pair_ray, dtype=np.int32)
+    pf = None if pair_fiber is None else np.ascontiguousarray(pair_fiber, dtype=np.int32)
+    if pr is not None:
+        n = pr.shape[0]
+    elif pf is not None:
+        n = pf.shape[0]
+    else:
+        n = min(rays.shape[1], fibers.shape[1])
+    t = np.empty(n, np.float64)
+    u = np.empty(n, np.float64)
+    kind = np.empty(n, np.int32)
+    L.fx_batch(_ptr(rays), rays.shape[1], rays.shape[1], _ptr(fibers), fibers.shape[1],
+               fibers.shape[1], _ptr(pr), _ptr(pf), n, float(radius_scale),
+               _ptr(t), _ptr(u), _ptr(kind), int(nthreads))
+    return t, u, (kind > 0).astype(np.uint8), kind
+
+
+def single_depth(ray, fiber, depth):
+    """One pair through fo_intersect_d (float64 inputs, no float32 rounding)."""
+    r, rp = _d(ray)
+    f, fp = _d(fiber)
+    t = C.c_double()
+    u = C.c_double()
+    st = (C.c_int64 * 4)()
+    hit = lib().fo_intersect_d(rp, fp, int(depth), C.byref(t), C.byref(u), st)
+    return bool(hit), t.value, u.value, tuple(st)
+
+
+def split_half(q16):
+    q, qp = _d(q16)
+    L = np.empty(16)
+    R = np.empty(16)
+    lib().fo_split_half(qp, L.ctypes.data_as(C.POINTER(C.c_double)),
+                        R.ctypes.data_as(C.POINTER(C.c_double)))
+    return L, R
+
+
+def split_plane(q16):
+    q, qp = _d(q16)
+    s = np.empty(3)
+    n = np.empty(3)
+    lib().fo_split_plane(qp, s.ctypes.data_as(C.POINTER(C.c_double)),
+                         n.ctypes.data_as(C.POINTER(C.c_double)))
+    return s, n
+
+
+def unit_ray_cylinder(o, a, r):
+    o_, op = _d(o)
+    a_, ap = _d(a)
+    t0 = C.c_double()
+    t1 = C.c_double()
+    ok = lib().fo_unit_ray_cylinder(op, ap, float(r), C.byref(t0), C.byref(t1))
+    return bool(ok), t0.value, t1.value
+
+
+def conservative_radius(q16):
+    q, qp = _d(q16)
+    return lib().fo_conservative_radius(qp)
+
+
+def cap_interval(q16, tmax):
+    q, qp = _d(q16)
+    out = np.empty(2)
+    lib().fo_cap_interval(qp, float(tmax), out.ctypes.data_as(C.POINTER(C.c_double)))
+    return out[0], out[1]
+
+
+def ray_frame(ray7, fiber16):
+    r, rp = _d(ray7)
+    f, fp = _d(fiber16)
+    out = np.empty(16)
+    ok = lib().fo_ray_frame(rp, fp, out.ctypes.data_as(C.POINTER(C.c_double)))
+    return (out if ok else None)
+
+
+def cubic_constraints(q16):
+    q, qp = _d(q16)
+    return lib().fo_cubic_constraints(qp)

@@ -1,0 +1,440 @@
+/*
+ * TEST INFRASTRUCTURE -- FP64 CPU oracle for the ray/fiber intersection of
+ * Binder & Keller, "Fast, High Precision Ray/Fiber Intersection using Tight,
+ * Disjoint Bounding Volumes" (arXiv 1811.03374).
+ *
+ * Only the test suite, the smoke entry point and the benchmark's CPU-baseline
+ * leg load this library. The product (HIP) path never calls it and shares no
+ * code, header, table or helper with it.
+ *
+ * What it computes ("ORACLE-D(d)"): the paper's depth-d method executed in
+ * IEEE double precision, written as the recursion that the paper's bit string
+ * encodes (Section 3.3, "Recursive subdivision is performed by an iterative
+ * process ..."). Each node of the recursion is a cubic sub-curve held as its
+ * four 4-D control points (position + radius, Section 3.3); children come from
+ * de Casteljau subdivision at the domain centre (Appendix B.2). Per node:
+ *
+ *   1. conservative radius: largest distance of the two inner control points
+ *      to the chord axis plus the largest radius control value (Section 3.3,
+ *      convex hull property);
+ *   2. unit ray against the infinite cylinder about the chord (Appendix A);
+ *   3. visibility against the current t interval (Section 3.3, cropping by the
+ *      end-cap planes; Section 3.2, cropping by split planes);
+ *   4. at depth d: hit at the entry into the capped leaf cylinder, u from the
+ *      projection of the hit point onto the chord (Section 3.3, last
+ *      paragraph);
+ *   5. otherwise split at u = 1/2 by the plane through the split point normal
+ *      to the split tangent, visit first the half the ray meets first, and
+ *      the other half only if the ray crosses the plane inside the cylinder
+ *      (Section 3.2 and Fig. "bounding_cylinder"); a hit ends the search
+ *      (instant termination, Section 3).
+ *
+ * Interval bookkeeping follows the paper's iteration exactly: descending into
+ * the first child narrows the interval by the split plane; a second child is
+ * reached by backtracking, and there the interval is recomputed from that
+ * node's own end caps (Section 3.3: "one of the interval bounds is updated;
+ * both are recalculated after backtracking").
+ *
+ * Readings where the paper is silent or its listings are inconsistent (each
+ * also listed in the design notes):
+ *   R1  leaf t = max(cylinder entry, interval start): the entry into the
+ *       capped leaf cylinder, never before the cap plane nor behind the origin.
+ *   R2  visible <=> max(t_entry, t_lo) <= min(t_exit, t_hi).
+ *   R3  a plane whose normal is perpendicular to the ray (n.z == 0): the whole
+ *       ray lies on the side given by the sign of <(0,0,t) - s, n>; a split
+ *       sends the ray to that side without narrowing; a ray exactly in the
+ *       plane visits both halves; a cap that excludes the ray empties the
+ *       interval.
+ *   R4  axis parallel to the ray (g == 0): inside -> (-inf, +inf), outside ->
+ *       explicit miss.
+ *   R5  misses are explicit flags, never (FLT_MAX, FLT_MAX) sentinels.
+ *   R6  interval recomputation after backtracking uses the ray's tmax.
+ *   R7  the radius channel passes through the ray-frame rotation unchanged.
+ *   R8  the ray direction is normalised; t and tmax are distances along it.
+ *   R11 hit <=> t < tmax (t >= 0 by construction).
+ *   R12 depth d means leaves of parametric size 2^-d, 0 <= d <= 23.
+ *   R13 a zero tangent (exactly zero vector) is replaced for cap normals by
+ *       the first non-zero of (q1-q0, q2-q0, q3-q0) at the start and
+ *       (q3-q2, q3-q1, q3-q0) at the end; a zero split tangent by the chord.
+ *       A zero-length chord gives distances to the point q0.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct { double x, y, z, w; } v4;
+
+static v4 mk4(double x, double y, double z, double w) { v4 r = {x, y, z, w}; return r; }
+static v4 add4(v4 a, v4 b) { return mk4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w); }
+static v4 sub4(v4 a, v4 b) { return mk4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w); }
+static v4 scale4(v4 a, double s) { return mk4(a.x * s, a.y * s, a.z * s, a.w * s); }
+static double dot3(v4 a, v4 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+static int zero3(v4 a) { return a.x == 0.0 && a.y == 0.0 && a.z == 0.0; }
+
+/* ------------------------------------------------------------------------ */
+/* Ray frame (Section 3.3): the ray starts at the origin and runs along +z.  */
+/* ------------------------------------------------------------------------ */
+
+/* Orthonormal basis (u, v) completing the unit vector w: Duff et al. 2017,
+ * "Building an Orthonormal Basis, Revisited" (the revision of Frisvad's
+ * method cited in Section 3.3). */
+static void onb(const double w[3], double u[3], double v[3])
+{
+    const double s = copysign(1.0, w[2]);
+    const double a = -1.0 / (s + w[2]);
+    const double b = w[0] * w[1] * a;
+    u[0] = 1.0 + s * w[0] * w[0] * a;  u[1] = s * b;  u[2] = -s * w[0];
+    v[0] = b;  v[1] = s + w[1] * w[1] * a;  v[2] = -w[1];
+}
+
+/* Control points of one fiber in the frame of one ray. Returns 0 when the
+ * ray direction is zero or not finite (then the pair is a miss). */
+static int ray_frame(const double O[3], const double D[3], const double P[16],
+                     v4 q[4], double *len_out)
+{
+    const double len = sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+    if (!(len > 0.0) || !isfinite(len)) return 0;
+    const double w[3] = {D[0] / len, D[1] / len, D[2] / len};
+    double u[3], v[3];
+    onb(w, u, v);
+    for (int k = 0; k < 4; ++k) {
+        const double d0 = P[4 * k + 0] - O[0];
+        const double d1 = P[4 * k + 1] - O[1];
+        const double d2 = P[4 * k + 2] - O[2];
+        q[k] = mk4(d0 * u[0] + d1 * u[1] + d2 * u[2],
+                   d0 * v[0] + d1 * v[1] + d2 * v[2],
+                   d0 * w[0] + d1 * w[1] + d2 * w[2],
+                   P[4 * k + 3]);
+        if (!isfinite(q[k].x) || !isfinite(q[k].y) || !isfinite(q[k].z) || !isfinite(q[k].w))
+            return 0;
+    }
+    if (len_out) *len_out = len;
+    return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Geometry of one node                                                      */
+/* ------------------------------------------------------------------------ */
+
+static v4 start_cap_normal(const v4 q[4])
+{
+    v4 n = sub4(q[1], q[0]);
+    if (zero3(n)) n = sub4(q[2], q[0]);
+    if (zero3(n)) n = sub4(q[3], q[0]);
+    return n;
+}
+
+static v4 end_cap_normal(const v4 q[4])
+{
+    v4 n = sub4(q[3], q[2]);
+    if (zero3(n)) n = sub4(q[3], q[1]);
+    if (zero3(n)) n = sub4(q[3], q[0]);
+    return n;
+}
+
+/* t interval of the ray between the node's two end-cap planes, intersected
+ * with [0, tmax] (Section 3.3, cropping of the infinite cylinders). The start
+ * cap passes through q0 with the start tangent as normal (the curve lies on
+ * its positive side); the end cap passes through q3 with the end tangent (the
+ * curve lies on its negative side). */
+static void cap_interval(const v4 q[4], double tmax, double *lo, double *hi)
+{
+    double l = 0.0, h = tmax;
+    const v4 n0 = start_cap_normal(q);
+    const double c0 = dot3(q[0], n0);       /* inside <=> t*n0.z >= c0 */
+    if (n0.z > 0.0)      l = fmax(l, c0 / n0.z);
+    else if (n0.z < 0.0) h = fmin(h, c0 / n0.z);
+    else if (c0 > 0.0)   { l = INFINITY; h = -INFINITY; }
+    const v4 n1 = end_cap_normal(q);
+    const double c1 = dot3(q[3], n1);       /* inside <=> t*n1.z <= c1 */
+    if (n1.z > 0.0)      h = fmin(h, c1 / n1.z);
+    else if (n1.z < 0.0) l = fmax(l, c1 / n1.z);
+    else if (c1 < 0.0)   { l = INFINITY; h = -INFINITY; }
+    *lo = l;
+    *hi = h;
+}
+
+/* Squared distance of point e (relative to the axis origin) to the line
+ * through the origin along a; a zero axis gives the distance to the point. */
+static double dist2_to_axis(v4 e, v4 a)
+{
+    const double c = dot3(a, a);
+    if (c > 0.0) {
+        const double b = dot3(e, a) / c;
+        e = mk4(e.x - b * a.x, e.y - b * a.y, e.z - b * a.z, 0.0);
+    }
+    return dot3(e, e);
+}
+
+/* Conservative radius of the cylinder about the chord q0 -> q3 (Section 3.3):
+ * the end points lie on the axis, so the two inner control points give the
+ * largest distance of the control polygon; the radius Bezier is bounded by its
+ * largest coefficient. */
+static double conservative_radius(const v4 q[4])
+{
+    const v4 a = sub4(q[3], q[0]);
+    const double d1 = dist2_to_axis(sub4(q[1], q[0]), a);
+    const double d2 = dist2_to_axis(sub4(q[2], q[0]), a);
+    const double rmax = fmax(fmax(q[0].w, q[1].w), fmax(q[2].w, q[3].w));
+    return sqrt(fmax(d1, d2)) + rmax;
+}
+
+/* Unit ray (origin, +z) against the infinite cylinder of radius r whose axis
+ * passes through o along a (Appendix A). Returns 0 on a miss. */
+static int unit_ray_cylinder(v4 o, v4 a, double r, double *t0, double *t1)
+{
+    const double g = a.x * a.x + a.y * a.y;
+    if (g == 0.0) {
+        if (o.x * o.x + o.y * o.y < r * r) { *t0 = -INFINITY; *t1 = INFINITY; return 1; }
+        return 0;
+    }
+    const double dd = a.x * o.y - a.y * o.x;      /* sqrt(g) * ray-axis distance */
+    const double e = r * r - dd * dd / g;
+    if (e < 0.0) return 0;
+    const double t_cpa = o.z - a.z * (a.x * o.x + a.y * o.y) / g;
+    const double s = sqrt(e * (a.z * a.z + g) / g);
+    *t0 = t_cpa - s;
+    *t1 = t_cpa + s;
+    return 1;
+}
+
+/* de Casteljau subdivision at u = 1/2 (Appendix B.2). */
+static void split_half(const v4 q[4], v4 L[4], v4 R[4])
+{
+    const v4 m01 = scale4(add4(q[0], q[1]), 0.5);
+    const v4 m12 = scale4(add4(q[1], q[2]), 0.5);
+    const v4 m23 = scale4(add4(q[2], q[3]), 0.5);
+    const v4 m012 = scale4(add4(m01, m12), 0.5);
+    const v4 m123 = scale4(add4(m12, m23), 0.5);
+    const v4 s = scale4(add4(m012, m123), 0.5);
+    L[0] = q[0]; L[1] = m01; L[2] = m012; L[3] = s;
+    R[0] = s; R[1] = m123; R[2] = m23; R[3] = q[3];
+}
+
+/* Normal of the partitioning plane: the curve tangent at the split point,
+ * proportional to -q0 - q1 + q2 + q3 (Appendix B.2); the chord if zero. */
+static v4 split_normal(const v4 q[4])
+{
+    v4 t = sub4(add4(q[2], q[3]), add4(q[0], q[1]));
+    if (zero3(t)) t = sub4(q[3], q[0]);
+    return t;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The recursion                                                             */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int depth;
+    double tmax;
+    int64_t tests, splits, backtracks;
+    double t, u;
+    int level;
+} search_t;
+
+static int visit(search_t *S, const v4 q[4], double lo, double hi,
+                 int level, double u0, double u1)
+{
+    S->tests++;
+    const v4 a = sub4(q[3], q[0]);
+    const double R = conservative_radius(q);
+    double te, tx;
+    if (!unit_ray_cylinder(q[0], a, R, &te, &tx)) return 0;
+    if (fmax(te, lo) > fmin(tx, hi)) return 0;
+
+    if (level >= S->depth) {
+        const double t = fmax(te, lo);
+        const double c = dot3(a, a);
+        double ul = 0.0;
+        if (c > 0.0) {
+            const v4 h = mk4(-q[0].x, -q[0].y, t - q[0].z, 0.0);
+            ul = fmin(1.0, fmax(0.0, dot3(h, a) / c));
+        }
+        S->t = t;
+        S->u = u0 + ul * (u1 - u0);
+        S->level = level;
+        return 1;
+    }
+
+    S->splits++;
+    v4 L[4], Rc[4];
+    split_half(q, L, Rc);
+    const v4 n = split_normal(q);
+    const v4 s = L[3];
+    const double c = dot3(s, n);
+    int go_right, both;
+    double flo = lo, fhi = hi;
+    if (n.z != 0.0) {
+        const double tp = c / n.z;
+        go_right = (tp > te) != (n.z > 0.0);
+        both = (te < tp) && (tp < tx);
+        if (tp > te) fhi = fmin(fhi, tp);
+        else         flo = fmax(flo, tp);
+    } else {
+        const double side = -c;            /* <(0,0,t) - s, n> for every t */
+        go_right = side > 0.0;
+        both = side == 0.0;
+    }
+    const double um = 0.5 * (u0 + u1);
+    const v4 *first = go_right ? Rc : L;
+    const v4 *second = go_right ? L : Rc;
+    const double f0 = go_right ? um : u0, f1 = go_right ? u1 : um;
+    const double s0 = go_right ? u0 : um, s1 = go_right ? um : u1;
+
+    if (visit(S, first, flo, fhi, level + 1, f0, f1)) return 1;
+    if (!both) return 0;
+    S->backtracks++;
+    double blo, bhi;
+    cap_interval(second, S->tmax, &blo, &bhi);
+    return visit(S, second, blo, bhi, level + 1, s0, s1);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exported entry points (ctypes)                                            */
+/* ------------------------------------------------------------------------ */
+
+int fo_version(void) { return 1; }
+
+/* One pair. ray = (ox, oy, oz, dx, dy, dz, tmax); fiber = 16 values p0..p3
+ * (x, y, z, r). stats (may be NULL) receives node tests, splits, backtracks
+ * and the level of the leaf that was hit (-1 on a miss). Returns 1 on a hit. */
+int fo_intersect_d(const double ray[7], const double fiber[16], int depth,
+                   double *t_out, double *u_out, int64_t stats[4])
+{
+    search_t S;
+    memset(&S, 0, sizeof S);
+    S.depth = depth;
+    S.tmax = ray[6];
+    S.level = -1;
+    int hit = 0;
+    v4 q[4];
+    if (depth >= 0 && depth <= 23 && ray[6] == ray[6] &&
+        ray_frame(ray, ray + 3, fiber, q, NULL)) {
+        double lo, hi;
+        cap_interval(q, S.tmax, &lo, &hi);
+        if (visit(&S, q, lo, hi, 0, 0.0, 1.0) && S.t < S.tmax) hit = 1;
+    }
+    if (!hit) { S.t = INFINITY; S.u = NAN; S.level = -1; }
+    *t_out = S.t;
+    *u_out = S.u;
+    if (stats) {
+        stats[0] = S.tests; stats[1] = S.splits; stats[2] = S.backtracks; stats[3] = S.level;
+    }
+    return hit;
+}
+
+/* Many pairs from the structure-of-arrays layout of the library (rays: 7 rows
+ * of ray_stride floats; fibers: 16 rows of fiber_stride floats). Pair i uses
+ * ray pair_ray[i] (or i when NULL) and fiber pair_fiber[i] (or i), at depth
+ * pair_depth[i] (or depth). Radius control values are multiplied by
+ * radius_scale (silhouette-band probes). stats_out (may be NULL) holds 4
+ * int32 per pair. Pairs whose indices fall outside [0, n_rays) or
+ * [0, n_fibers) are misses. */
+void fo_batch_d(const float *rays, int64_t ray_stride, int64_t n_rays,
+                const float *fibers, int64_t fiber_stride, int64_t n_fibers,
+                const int32_t *pair_ray, const int32_t *pair_fiber,
+                const uint8_t *pair_depth, int depth, int64_t n,
+                double radius_scale, double *t_out, double *u_out,
+                uint8_t *hit_out, int32_t *stats_out, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 256)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t ri = pair_ray ? pair_ray[i] : i;
+        const int64_t fi = pair_fiber ? pair_fiber[i] : i;
+        const int d = pair_depth ? (int)pair_depth[i] : depth;
+        double ray[7], fib[16], t = INFINITY, u = NAN;
+        int64_t st[4] = {0, 0, 0, -1};
+        int hit = 0;
+        if (ri >= 0 && ri < n_rays && fi >= 0 && fi < n_fibers) {
+            for (int r = 0; r < 7; ++r) ray[r] = rays[r * ray_stride + ri];
+            for (int r = 0; r < 16; ++r) fib[r] = fibers[r * fiber_stride + fi];
+            for (int k = 0; k < 4; ++k) fib[4 * k + 3] *= radius_scale;
+            hit = fo_intersect_d(ray, fib, d, &t, &u, st);
+        }
+        t_out[i] = t;
+        u_out[i] = u;
+        hit_out[i] = (uint8_t)hit;
+        if (stats_out) {
+            for (int k = 0; k < 4; ++k) stats_out[4 * i + k] = (int32_t)st[k];
+        }
+    }
+}
+
+/* Building blocks exported for the pins in the test suite. */
+
+void fo_split_half(const double q[16], double L[16], double R[16])
+{
+    v4 a[4], l[4], r[4];
+    for (int k = 0; k < 4; ++k) a[k] = mk4(q[4 * k], q[4 * k + 1], q[4 * k + 2], q[4 * k + 3]);
+    split_half(a, l, r);
+    for (int k = 0; k < 4; ++k) {
+        L[4 * k] = l[k].x; L[4 * k + 1] = l[k].y; L[4 * k + 2] = l[k].z; L[4 * k + 3] = l[k].w;
+        R[4 * k] = r[k].x; R[4 * k + 1] = r[k].y; R[4 * k + 2] = r[k].z; R[4 * k + 3] = r[k].w;
+    }
+}
+
+void fo_split_plane(const double q[16], double s[3], double n[3])
+{
+    v4 a[4], l[4], r[4];
+    for (int k = 0; k < 4; ++k) a[k] = mk4(q[4 * k], q[4 * k + 1], q[4 * k + 2], q[4 * k + 3]);
+    split_half(a, l, r);
+    const v4 t = split_normal(a);
+    s[0] = l[3].x; s[1] = l[3].y; s[2] = l[3].z;
+    n[0] = t.x; n[1] = t.y; n[2] = t.z;
+}
+
+int fo_unit_ray_cylinder(const double o[3], const double a[3], double r,
+                         double *t0, double *t1)
+{
+    return unit_ray_cylinder(mk4(o[0], o[1], o[2], 0), mk4(a[0], a[1], a[2], 0), r, t0, t1);
+}
+
+double fo_conservative_radius(const double q[16])
+{
+    v4 a[4];
+    for (int k = 0; k < 4; ++k) a[k] = mk4(q[4 * k], q[4 * k + 1], q[4 * k + 2], q[4 * k + 3]);
+    return conservative_radius(a);
+}
+
+void fo_cap_interval(const double q[16], double tmax, double out[2])
+{
+    v4 a[4];
+    for (int k = 0; k < 4; ++k) a[k] = mk4(q[4 * k], q[4 * k + 1], q[4 * k + 2], q[4 * k + 3]);
+    cap_interval(a, tmax, &out[0], &out[1]);
+}
+
+int fo_ray_frame(const double ray[7], const double fiber[16], double out[16])
+{
+    v4 q[4];
+    if (!ray_frame(ray, ray + 3, fiber, q, NULL)) return 0;
+    for (int k = 0; k < 4; ++k) {
+        out[4 * k] = q[k].x; out[4 * k + 1] = q[k].y; out[4 * k + 2] = q[k].z; out[4 * k + 3] = q[k].w;
+    }
+    return 1;
+}
+
+/* The five cubic constraints of Section 3.4 (proved in Appendix B.2): returns
+ * a bit mask, bit k set when inequality k holds; 31 means the curve can be
+ * split recursively into sub-curves with disjoint bounding volumes. */
+int fo_cubic_constraints(const double q[16])
+{
+    v4 p[4];
+    for (int k = 0; k < 4; ++k) p[k] = mk4(q[4 * k], q[4 * k + 1], q[4 * k + 2], 0.0);
+    const double c[5] = {
+        dot3(sub4(p[2], p[0]), sub4(p[1], p[0])),
+        dot3(sub4(p[3], p[1]), sub4(p[1], p[0])),
+        dot3(sub4(p[3], p[1]), sub4(p[3], p[2])),
+        dot3(sub4(p[2], p[0]), sub4(p[3], p[2])),
+        dot3(sub4(p[2], p[0]), sub4(p[3], p[1])),
+    };
+    int m = 0;
+    for (int k = 0; k < 5; ++k) if (c[k] >= 0.0) m |= 1 << k;
+    return m;
+}

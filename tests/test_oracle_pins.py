@@ -1,0 +1,537 @@
+"""Pins of the FP64 oracle to things other than itself (CPU only).
+
+Each test checks the oracle against what the paper or plain mathematics fixes:
+a textbook closed form, a brute-force search, exact identities, or values
+worked out from the paper's printed examples.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1811_03374_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# independent helpers written from textbook geometry (world space)
+# ---------------------------------------------------------------------------
+
+def bezier(P, u):
+    """Cubic Bezier in power form, P (n, 4, k), u (n, m) -> (n, m, k)."""
+    a0 = P[:, 0]
+    a1 = 3 * (P[:, 1] - P[:, 0])
+    a2 = 3 * (P[:, 2] - 2 * P[:, 1] + P[:, 0])
+    a3 = P[:, 3] - 3 * P[:, 2] + 3 * P[:, 1] - P[:, 0]
+    u = u[..., None]
+    return a0[:, None] + u * (a1[:, None] + u * (a2[:, None] + u * a3[:, None]))
+
+
+def bezier_d(P, u):
+    a1 = 3 * (P[:, 1] - P[:, 0])
+    a2 = 3 * (P[:, 2] - 2 * P[:, 1] + P[:, 0])
+    a3 = P[:, 3] - 3 * P[:, 2] + 3 * P[:, 1] - P[:, 0]
+    u = u[..., None]
+    return a1[:, None] + u * (2 * a2[:, None] + 3 * u * a3[:, None])
+
+
+def capped_cylinder(O, D, A, B, r, tmax):
+    """First entry of the ray O + t D/|D| into the solid cylinder of radius r
+    between the discs at A and B (normal B - A): side quadratic plus two cap
+    discs, in world coordinates (Cychosz & Waggenspack style)."""
+    Dn = D / np.linalg.norm(D, axis=1, keepdims=True)
+    ax = B - A
+    L = np.linalg.norm(ax, axis=1)
+    a = ax / L[:, None]
+    m = O - A
+    dA = np.sum(Dn * a, axis=1)
+    mA = np.sum(m * a, axis=1)
+    Dp = Dn - dA[:, None] * a
+    mp = m - mA[:, None] * a
+    qa = np.sum(Dp * Dp, axis=1)
+    qb = 2 * np.sum(Dp * mp, axis=1)
+    qc = np.sum(mp * mp, axis=1) - r * r
+    n = O.shape[0]
+    best = np.full(n, np.inf)
+    disc = qb * qb - 4 * qa * qc
+    ok = (qa > 0) & (disc >= 0)
+    sq = np.sqrt(np.where(ok, disc, 0.0))
+    for sgn in (-1.0, 1.0):
+        t = np.where(ok, (-qb + sgn * sq) / np.where(qa > 0, 2 * qa, 1.0), np.inf)
+        s = mA + t * dA
+        good = ok & (s >= 0) & (s <= L) & (t >= 0) & (t < tmax)
+        best = np.where(good & (t < best), t, best)
+    for sc in (0.0, 1.0):
+        with np.errstate(divide="ignore", invalid="ignore"):
+            t = (sc * L - mA) / dA
+        rad = mp + t[:, None] * Dp
+        good = (dA != 0) & (np.sum(rad * rad, axis=1) <= r * r) & (t >= 0) & (t < tmax)
+        best = np.where(good & (t < best), t, best)
+    hit = np.isfinite(best)
+    u = np.clip((mA + np.where(hit, best, 0) * dA) / L, 0, 1)
+    return best, u, hit
+
+
+def unpack_rays(R):
+    return R[0:3].T.astype(np.float64), R[3:6].T.astype(np.float64), R[6].astype(np.float64)
+
+
+# ---------------------------------------------------------------------------
+# P1: straight constant-radius fiber == analytic capped cylinder, every depth
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("depth", [0, 1, 2, 4, 9, 16, 22, 23])
+def test_straight_fiber_equals_capped_cylinder(depth):
+    w = W.exact_straight_fibers(1500)
+    P = W.unpack_fibers(w.fibers)
+    O, D, tmax = unpack_rays(w.rays)
+    r = P[:, 0, 3]
+    t_cf, u_cf, h_cf = capped_cylinder(O, D, P[:, 0, :3], P[:, 3, :3], r, tmax)
+    # pairs whose closed-form flag is sensitive to a 1e-7 relative radius change
+    _, _, h_lo = capped_cylinder(O, D, P[:, 0, :3], P[:, 3, :3], r * (1 - 1e-7), tmax)
+    _, _, h_hi = capped_cylinder(O, D, P[:, 0, :3], P[:, 3, :3], r * (1 + 1e-7), tmax)
+    stable = h_lo == h_hi
+    t, u, h = oracle.intersect_depth(w.rays, w.fibers, depth)
+    assert 0.3 < h_cf.mean() < 0.8
+    assert w.meta["cap_ray"][h_cf.astype(bool) & stable].sum() > 50   # caps exercised
+    assert np.array_equal(h[stable].astype(bool), h_cf[stable])
+    both = stable & h_cf & h.astype(bool)
+    rel = np.abs(t[both] - t_cf[both]) / t_cf[both]
+    assert rel.max() < 1e-11, rel.max()
+    # u comes from projecting onto the leaf chord; a 2^-d leaf's chord carries an
+    # FP64 relative error of about 2^d * 1e-16, which bounds u to ~2^d * 2e-15
+    assert np.abs(u[both] - u_cf[both]).max() < 1e-11 + 4e-15 * 2.0 ** depth
+
+
+# ---------------------------------------------------------------------------
+# P2: Appendix A's unit-ray cylinder == world-space ray/cylinder quadratic
+# ---------------------------------------------------------------------------
+
+def test_unit_ray_cylinder_equals_world_space_solution():
+    rng = np.random.default_rng(7)
+    checked = 0
+    for _ in range(3000):
+        O = rng.uniform(-2, 2, 3)
+        D = W.unit_vectors(rng, 1)[0]
+        P = rng.uniform(-2, 2, 3)
+        A = W.unit_vectors(rng, 1)[0] * rng.uniform(0.1, 3)
+        r = rng.uniform(0.05, 1.0)
+        # world-space infinite cylinder
+        a = A / np.linalg.norm(A)
+        m = O - P
+        Dp = D - D.dot(a) * a
+        mp = m - m.dot(a) * a
+        qa, qb, qc = Dp.dot(Dp), 2 * Dp.dot(mp), mp.dot(mp) - r * r
+        disc = qb * qb - 4 * qa * qc
+        # an independent rotation taking D to +z: complete D with QR
+        M = np.linalg.qr(np.column_stack([D, rng.standard_normal((3, 2))]))[0]
+        if M[:, 0].dot(D) < 0:
+            M[:, 0] *= -1
+        frame = np.column_stack([M[:, 1], M[:, 2], M[:, 0]]).T   # rows: x, y, z(=D)
+        ok, t0, t1 = oracle.unit_ray_cylinder(frame @ (P - O), frame @ A, r)
+        assert ok == (disc >= 0)
+        if ok:
+            roots = sorted([(-qb - math.sqrt(disc)) / (2 * qa), (-qb + math.sqrt(disc)) / (2 * qa)])
+            scale = max(1.0, abs(roots[0]), abs(roots[1]))
+            assert abs(t0 - roots[0]) < 1e-11 * scale and abs(t1 - roots[1]) < 1e-11 * scale
+            checked += 1
+    assert checked > 500
+
+
+def test_unit_ray_cylinder_parallel_axis():
+    # axis along the ray (g == 0): inside -> whole line, outside -> miss
+    ok, t0, t1 = oracle.unit_ray_cylinder([0.1, 0.0, 5.0], [0, 0, 2.0], 0.2)
+    assert ok and t0 == -math.inf and t1 == math.inf
+    ok, _, _ = oracle.unit_ray_cylinder([0.3, 0.0, 5.0], [0, 0, -2.0], 0.2)
+    assert not ok
+
+
+# ---------------------------------------------------------------------------
+# P3: de Casteljau halves reproduce the curve; subdivision rules of Sec. 3.1
+# ---------------------------------------------------------------------------
+
+def test_split_halves_reproduce_curve():
+    rng = np.random.default_rng(3)
+    Q = rng.uniform(-1, 1, (200, 16))
+    v = rng.uniform(0, 1, (200, 9))
+    Ls, Rs = zip(*[oracle.split_half(q) for q in Q])
+    P = Q.reshape(-1, 4, 4)
+    L = np.array(Ls).reshape(-1, 4, 4)
+    R = np.array(Rs).reshape(-1, 4, 4)
+    assert np.abs(bezier(L, v) - bezier(P, v / 2)).max() < 1e-14
+    assert np.abs(bezier(R, v) - bezier(P, (1 + v) / 2)).max() < 1e-14
+
+
+def test_delta_form_rules_equal_de_casteljau_exactly():
+    """Section 3.1's {p, d, t0, t1} subdivision rules give exactly the de
+    Casteljau halves (rational arithmetic): the GPU path's representation and
+    the oracle's control points describe the same sub-curves."""
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        q = [[Fraction(int(x), 64) for x in rng.integers(-256, 256, 4)] for _ in range(4)]
+        sub = lambda a, b: [x - y for x, y in zip(a, b)]
+        add = lambda a, b: [x + y for x, y in zip(a, b)]
+        sc = lambda a, s: [x * s for x in a]
+        p, d, t0, t1 = q[0], sub(q[3], q[0]), sub(q[1], q[0]), sub(q[3], q[2])
+        dp = add(add(sc(t0, Fraction(3, 8)), sc(d, Fraction(1, 2))), sc(t1, Fraction(-3, 8)))
+        tc = add(add(sc(t0, Fraction(-1, 8)), sc(d, Fraction(1, 4))), sc(t1, Fraction(-1, 8)))
+        left = (p, dp, sc(t0, Fraction(1, 2)), tc)
+        right = (add(p, dp), sub(d, dp), tc, sc(t1, Fraction(1, 2)))
+        m01 = sc(add(q[0], q[1]), Fraction(1, 2))
+        m12 = sc(add(q[1], q[2]), Fraction(1, 2))
+        m23 = sc(add(q[2], q[3]), Fraction(1, 2))
+        m012 = sc(add(m01, m12), Fraction(1, 2))
+        m123 = sc(add(m12, m23), Fraction(1, 2))
+        s = sc(add(m012, m123), Fraction(1, 2))
+        L = [q[0], m01, m012, s]
+        R = [s, m123, m23, q[3]]
+        for (pp, dd, a0, a1), C in ((left, L), (right, R)):
+            assert pp == C[0] and dd == sub(C[3], C[0])
+            assert a0 == sub(C[1], C[0]) and a1 == sub(C[3], C[2])
+        # and the oracle's FP64 halves are exact on these dyadic inputs
+        qf = np.array([[float(x) for x in row] for row in q]).reshape(16)
+        Lf, Rf = oracle.split_half(qf)
+        assert np.array_equal(Lf, np.array([[float(x) for x in row] for row in L]).reshape(16))
+        assert np.array_equal(Rf, np.array([[float(x) for x in row] for row in R]).reshape(16))
+
+
+# ---------------------------------------------------------------------------
+# P7: constraints of Section 3.4 and the lemma of Appendix B.2
+# ---------------------------------------------------------------------------
+
+def test_paper_polygons_classification():
+    with open(os.path.join(GOLDEN, "paper_polygons.json")) as f:
+        g = json.load(f)
+    for poly in g["polygons"]:
+        q = np.zeros(16)
+        for k, (x, y) in enumerate(poly["points"]):
+            q[4 * k], q[4 * k + 1] = x, y
+        mask = oracle.cubic_constraints(q)
+        expected = sum(1 << k for k, p in enumerate(poly["products"]) if p >= 0)
+        assert mask == expected, poly["source"]
+        assert (mask == 31) == poly["valid"], poly["source"]
+
+
+def test_loop_polygon_breaks_split_plane_separation():
+    q = np.zeros(16)
+    for k, (x, y) in enumerate([[0, 0], [5, 1], [-1, 1], [4, 0]]):
+        q[4 * k], q[4 * k + 1] = x, y
+    L, R = oracle.split_half(q)
+    s, n = oracle.split_plane(q)
+    sideL = [np.dot(L[4 * k:4 * k + 3] - s, n) for k in range(4)]
+    assert max(sideL) > 0       # p0 of the loop lies on the wrong side
+
+
+def _valid_curves(rng, n):
+    out = []
+    while len(out) < n:
+        q = rng.uniform(-1, 1, 16)
+        if oracle.cubic_constraints(q) == 31:
+            p = q.reshape(4, 4)[:, :3]
+            prods = [np.dot(p[2] - p[0], p[1] - p[0]), np.dot(p[3] - p[1], p[1] - p[0]),
+                     np.dot(p[3] - p[1], p[3] - p[2]), np.dot(p[2] - p[0], p[3] - p[2]),
+                     np.dot(p[2] - p[0], p[3] - p[1])]
+            if min(prods) > 1e-3:
+                out.append(q)
+    return out
+
+
+def test_constraints_inherited_and_halves_separated():
+    """Appendix B.2: under the five constraints every split separates the
+    halves by the split plane, and the halves satisfy the constraints again."""
+    rng = np.random.default_rng(5)
+    for q0 in _valid_curves(rng, 40):
+        stack = [(q0, 0)]
+        while stack:
+            q, lvl = stack.pop()
+            assert oracle.cubic_constraints(q) == 31
+            L, R = oracle.split_half(q)
+            s, n = oracle.split_plane(q)
+            scale = np.abs(q).max() ** 2 + 1e-300
+            for k in range(4):
+                assert np.dot(L[4 * k:4 * k + 3] - s, n) <= 1e-12 * scale
+                assert np.dot(R[4 * k:4 * k + 3] - s, n) >= -1e-12 * scale
+            if lvl < 7:
+                stack.append((L, lvl + 1))
+                stack.append((R, lvl + 1))
+
+
+# ---------------------------------------------------------------------------
+# P9: brute force -- dense sampling of the swept discs (world space)
+# ---------------------------------------------------------------------------
+
+def _disc_hits(P, O, Dn, tmax, u):
+    """t of the ray against the disc at C(u) (normal C'(u), radius r(u)), or inf."""
+    C = bezier(P, u)
+    T = bezier_d(P, u)[..., :3]
+    den = np.einsum("nk,nmk->nm", Dn, T)
+    num = np.einsum("nmk,nmk->nm", C[..., :3] - O[:, None, :], T)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t = num / den
+    X = O[:, None, :] + t[..., None] * Dn[:, None, :]
+    d2 = np.sum((X - C[..., :3]) ** 2, axis=2)
+    ok = (den != 0) & (d2 <= C[..., 3] ** 2) & (t >= 0) & (t < tmax[:, None])
+    return np.where(ok, t, np.inf)
+
+
+def brute_force(P, O, D, tmax, samples=1 << 14, rounds=3):
+    Dn = D / np.linalg.norm(D, axis=1, keepdims=True)
+    n = P.shape[0]
+    u = np.broadcast_to(np.linspace(0, 1, samples + 1), (n, samples + 1))
+    t = _disc_hits(P, O, Dn, tmax, u)
+    i = np.argmin(t, axis=1)
+    best = t[np.arange(n), i]
+    bu = u[np.arange(n), i]
+    h = 1.0 / samples
+    for _ in range(rounds):
+        lo = np.clip(bu - h, 0, 1)
+        hi = np.clip(bu + h, 0, 1)
+        uu = lo[:, None] + (hi - lo)[:, None] * np.linspace(0, 1, 257)[None, :]
+        tt = _disc_hits(P, O, Dn, tmax, uu)
+        j = np.argmin(tt, axis=1)
+        tb = tt[np.arange(n), j]
+        better = tb < best
+        best = np.where(better, tb, best)
+        bu = np.where(better, uu[np.arange(n), j], bu)
+        h = h / 128
+    return best, bu, np.isfinite(best)
+
+
+def _band(w, depth):
+    _, _, h_lo = oracle.intersect_depth(w.rays, w.fibers, depth, radius_scale=1 - 1e-4)
+    _, _, h_hi = oracle.intersect_depth(w.rays, w.fibers, depth, radius_scale=1 + 1e-4)
+    return h_lo != h_hi
+
+
+def test_depth22_matches_brute_force_on_valid_fibers():
+    w = W.gentle_valid_curves(400)
+    P = W.unpack_fibers(w.fibers)
+    O, D, tmax = unpack_rays(w.rays)
+    t_bf, u_bf, h_bf = brute_force(P, O, D, tmax)
+    t, u, h = oracle.intersect_depth(w.rays, w.fibers, 22)
+    band = _band(w, 22)
+    out = ~band
+    assert 0.3 < h.mean() < 0.7
+    assert np.array_equal(h[out].astype(bool), h_bf[out])
+    both = out & h.astype(bool) & h_bf
+    # sampled discs are points of the solid: the oracle's entry is not later
+    rel = (t[both] - t_bf[both]) / t_bf[both]
+    assert rel.max() < 1e-7, rel.max()
+    assert rel.min() > -1e-6, rel.min()
+    assert np.abs(u[both] - u_bf[both]).max() < 1e-4
+
+
+def test_depth22_hits_lie_on_surface():
+    """At a side hit P(t) is at distance r(u) from C(u) and in the normal
+    plane of C(u) (up to the depth-22 approximation)."""
+    w = W.gentle_valid_curves(400, seed=99)
+    P = W.unpack_fibers(w.fibers)
+    O, D, tmax = unpack_rays(w.rays)
+    t, u, h = oracle.intersect_depth(w.rays, w.fibers, 22)
+    sel = h.astype(bool) & (u > 1e-6) & (u < 1 - 1e-6)
+    Dn = D / np.linalg.norm(D, axis=1, keepdims=True)
+    X = O[sel] + t[sel, None] * Dn[sel]
+    C = bezier(P[sel], u[sel, None])[:, 0]
+    T = bezier_d(P[sel], u[sel, None])[:, 0, :3]
+    dist = np.linalg.norm(X - C[:, :3], axis=1)
+    assert np.abs(dist - C[:, 3]).max() < 1e-6
+    cosang = np.abs(np.sum((X - C[:, :3]) * T, axis=1)) / (dist * np.linalg.norm(T, axis=1))
+    assert cosang.max() < 1e-4
+
+
+def test_convergence_with_depth():
+    """The depth-d result converges to the swept-disc surface as d grows."""
+    w = W.gentle_valid_curves(300, seed=123)
+    P = W.unpack_fibers(w.fibers)
+    O, D, tmax = unpack_rays(w.rays)
+    t_bf, _, h_bf = brute_force(P, O, D, tmax)
+    errs = []
+    for d in (4, 8, 12, 16):
+        t, u, h = oracle.intersect_depth(w.rays, w.fibers, d)
+        both = h.astype(bool) & h_bf
+        errs.append(np.median(np.abs(t[both] - t_bf[both])))
+    assert errs[0] > errs[1] > errs[2] > errs[3]
+    assert errs[3] < errs[0] / 100
+
+
+# ---------------------------------------------------------------------------
+# Degenerate inputs: defined results, never NaN hits
+# ---------------------------------------------------------------------------
+
+def test_degenerate_inputs_are_misses_or_defined():
+    fib = np.array([0, 0, 0, .1, 1, 0, 0, .1, 2, 0, 0, .1, 3, 0, 0, .1], float)
+    # zero direction, NaN direction, negative tmax
+    for ray in ([0, 0, -5, 0, 0, 0, 100], [0, 0, -5, np.nan, 0, 1, 100], [1.5, 0, -5, 0, 0, 1, -1]):
+        hit, t, u, _ = oracle.single_depth(np.array(ray, float), fib, 9)
+        assert not hit
+    # ray along the fiber axis from behind the start: enters through the start cap
+    hit, t, u, _ = oracle.single_depth(np.array([-2.0, 0.05, 0, 1, 0, 0, 100]), fib, 9)
+    assert hit and abs(t - 2.0) < 1e-12 and u == 0.0
+    # same ray but a zero start tangent (p1 == p0): the cap normal falls back to p2 - p0
+    fz = fib.copy()
+    fz[4:7] = fz[0:3]
+    hit, t, u, _ = oracle.single_depth(np.array([-2.0, 0.05, 0, 1, 0, 0, 100]), fz, 9)
+    assert hit and abs(t - 2.0) < 1e-12
+    # a ray perpendicular to the axis, exactly axis-aligned: split planes parallel to the ray
+    hit, t, u, _ = oracle.single_depth(np.array([1.3, 0.0, -4, 0, 0, 1, 100]), fib, 12)
+    assert hit and abs(t - (4 - 0.1)) < 1e-12 and abs(u - 1.3 / 3) < 1e-3
+
+
+# ---------------------------------------------------------------------------
+# P5, P6: the integer encodings used by the iterative form (Section 3.3)
+# ---------------------------------------------------------------------------
+
+def test_interval_from_integer_start_is_exact():
+    """Or-ing start into the mantissa of 1.0f and subtracting 1 gives exactly
+    start * 2^-23; the end of the last interval is exactly 1."""
+    for size_log in range(0, 24):
+        size = 1 << size_log
+        starts = np.arange(0, 1 << 23, size, dtype=np.int64)
+        if starts.size > 4096:
+            starts = np.concatenate([starts[:2048], starts[-2048:]])
+        bits0 = (0x3F800000 | starts).astype(np.uint32)
+        u0 = bits0.view(np.float32) - np.float32(1.0)
+        bits1 = np.minimum(bits0.astype(np.int64) + size, 0x40000000).astype(np.uint32)
+        u1 = bits1.view(np.float32) - np.float32(1.0)
+        assert np.array_equal(u0.astype(np.float64), starts / 2.0 ** 23)
+        assert np.array_equal(u1.astype(np.float64), (starts + size) / 2.0 ** 23)
+
+
+def _dfs_order(decide, max_level):
+    order = []
+
+    def rec(level, start):
+        order.append((level, start))
+        vis, both, right = decide(level, start)
+        if not vis:
+            return False
+        if level == max_level:
+            return True
+        half = 1 << (23 - level - 1)
+        first = start + half if right else start
+        second = start if right else start + half
+        if rec(level + 1, first):
+            return True
+        return both and rec(level + 1, second)
+
+    rec(0, 0)
+    return order
+
+
+def _bitstring_order(decide, max_level):
+    order = []
+    size, start, bits = 1 << 23, 0, 0
+    min_size = 1 << (23 - max_level)
+    while True:
+        level = 23 - size.bit_length() + 1
+        order.append((level, start))
+        vis, both, right = decide(level, start)
+        if vis:
+            if size <= min_size:
+                break
+            size >>= 1
+            if both:
+                bits ^= size
+            if right:
+                start ^= size
+        else:
+            if bits == 0:
+                break
+            size = bits & -bits
+            start ^= size
+            bits ^= size
+            start &= ~(size - 1)
+    return order
+
+
+def test_bit_string_visits_nodes_in_dfs_order():
+    rng = np.random.default_rng(17)
+    for trial in range(300):
+        max_level = int(rng.integers(1, 13))
+        cache = {}
+        p_vis = rng.uniform(0.3, 0.95)
+
+        def decide(level, start):
+            key = (level, start)
+            if key not in cache:
+                cache[key] = (rng.uniform() < p_vis, rng.uniform() < 0.5, rng.uniform() < 0.5)
+            return cache[key]
+
+        a = _dfs_order(decide, max_level)
+        b = _bitstring_order(decide, max_level)
+        assert a == b
+
+
+# ---------------------------------------------------------------------------
+# depth 0: the root is the leaf -- entry into the capped root cylinder
+# ---------------------------------------------------------------------------
+
+def _capped_root_entry(P, O, Dn, tmax, n_steps=200001):
+    """First t at which the ray is inside the root bounding volume: within the
+    conservative radius of the chord line and between the two end-cap planes
+    (Section 3.3), found by marching along the ray in world space and
+    bisecting the first transition."""
+    p0, p1, p2, p3 = (P[k, :3] for k in range(4))
+    a = p3 - p0
+    aa = a.dot(a)
+
+    def dline(X):
+        e = X - p0
+        e = e - np.outer(e @ a / aa, a)
+        return np.sqrt(np.sum(e * e, axis=-1))
+
+    R = max(dline(p1[None])[0], dline(p2[None])[0]) + P[:, 3].max()
+
+    def inside(t):
+        X = O + np.outer(t, Dn)
+        return ((dline(X) <= R) & ((X - p0) @ (p1 - p0) >= 0) & ((X - p3) @ (p3 - p2) <= 0))
+
+    ts = np.linspace(0.0, min(tmax, 10.0), n_steps)
+    ins = inside(ts)
+    if not ins.any():
+        return np.inf
+    k = int(np.argmax(ins))
+    if k == 0:
+        return 0.0
+    lo, hi = ts[k - 1], ts[k]
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        if inside(np.array([mid]))[0]:
+            hi = mid
+        else:
+            lo = mid
+    return hi
+
+
+def test_depth0_equals_capped_root_cylinder_on_bent_curves():
+    rng = np.random.default_rng(41)
+    n = 300
+    P = np.empty((n, 4, 4))
+    P[:, :, :3] = rng.uniform(-0.5, 0.5, (n, 4, 3))    # strongly bent, often invalid
+    P[:, :, 3] = rng.uniform(0.01, 0.05, (n, 4))
+    O = W.unit_vectors(rng, n) * 3.0
+    target = P[:, rng.integers(0, 4, n), :3][np.arange(n), np.arange(n)] + 0.4 * rng.standard_normal((n, 3))
+    D = target - O
+    fibers = W.pack_fibers(P)
+    P32 = W.unpack_fibers(fibers)
+    rays = W.pack_rays(O, D, np.full(n, 100.0))
+    O32, D32, tmax = unpack_rays(rays)
+    t, u, h = oracle.intersect_depth(rays, fibers, 0)
+    agree = 0
+    for i in range(n):
+        Dn = D32[i] / np.linalg.norm(D32[i])
+        tb = _capped_root_entry(P32[i], O32[i], Dn, tmax[i])
+        if np.isfinite(tb) != bool(h[i]):
+            # only a grazing ray (entry span shorter than the marching step) may differ
+            assert not np.isfinite(tb) and h[i]
+            continue
+        if h[i]:
+            assert abs(t[i] - tb) < 1e-6 * max(1.0, tb), (i, t[i], tb)
+        agree += 1
+    assert agree > n - 5
+    assert 0.2 < h.mean() < 0.9
