@@ -1,0 +1,171 @@
+"""Throughput of the per-pair ray/fiber test on one MI355X.
+
+A step is one pass of the whole per-pair path over the 2^20-pair workload
+(half straight constant-radius fibers, half curved random-walk fibers with a
+linear taper; one ray per fiber aimed for about 50 % hits), once at depth 9
+and once at depth 22. Inputs are resident in device memory before timing.
+
+Prints one JSON line (metric, value in Gpairs/s, roofline of the dominant
+launch, the FP64 oracle timed on the host as a CPU baseline).
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+DEPTHS = (9, 22)
+N_PAIRS = 1 << 20
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the per-pair test has no cross-GPU step, "
+              "and multi-GPU runs are not part of this build (use --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1811_03374_amd import binding, workmodel
+    from paper_1811_03374_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    w = W.straight_and_curved(N_PAIRS, DEPTHS[0])
+    rays = torch.from_numpy(w.rays).to(dev)
+    fibers = torch.from_numpy(w.fibers).to(dev)
+    n = w.n_pairs
+    outs = {d: (torch.empty(n, dtype=torch.float32, device=dev),
+                torch.empty(n, dtype=torch.float32, device=dev),
+                torch.empty(n, dtype=torch.uint8, device=dev)) for d in DEPTHS}
+
+    # algorithmic work of each launch (untimed counting pass; same traversal)
+    work = {}
+    for d in DEPTHS:
+        _, _, h, cn = binding.intersect_pairs(rays, fibers, d, counts=True)
+        s = cn.to(torch.int64).sum(dim=0).cpu().numpy()
+        hits = int(h.sum().item())
+        work[d] = {"tests": int(s[0]), "splits": int(s[1]), "backtracks": int(s[2]), "hits": hits,
+                   "flops": workmodel.flops(n, int(s[0]), int(s[1]), int(s[2]), hits),
+                   "bytes": workmodel.bytes_streamed(n)}
+    torch.cuda.synchronize()
+
+    parity = None
+    if not args.no_check:
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from parity import compare, oracle_with_band
+        idx = np.sort(np.random.default_rng(0).choice(n, 4096, replace=False))
+        ws = w.subset(idx)
+        parity = {}
+        for d in DEPTHS:
+            t, u, h = binding.intersect_pairs(rays, fibers, d, out=outs[d])
+            torch.cuda.synchronize()
+            (t_o, u_o, h_o), band = oracle_with_band(ws, d)
+            st = compare(t.cpu().numpy()[idx], u.cpu().numpy()[idx], h.cpu().numpy()[idx],
+                         t_o, u_o, h_o, band, d)
+            parity[str(d)] = {k: st[k] for k in ("ok", "flag_disagree_outside_band", "max_rel_t",
+                                                 "max_abs_u")}
+
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        for j, d in enumerate(DEPTHS):
+            if ev is not None:
+                ev[j][0].record(stream)
+            binding.intersect_pairs(rays, fibers, d, out=outs[d], stream=stream)
+            if ev is not None:
+                ev[j][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # timed region: exactly K steps, device idle on both sides
+    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+           for _ in DEPTHS] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(ev[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    launch_ms = {d: [ev[k][j][0].elapsed_time(ev[k][j][1]) for k in range(args.steps)]
+                 for j, d in enumerate(DEPTHS)}
+    ms_per_step = wall * 1e3 / args.steps
+    value = len(DEPTHS) * n / (ms_per_step * 1e-3) / 1e9
+
+    per_depth = {}
+    roof = {}
+    for d in DEPTHS:
+        avg = statistics.mean(launch_ms[d])
+        tflops = work[d]["flops"] / (avg * 1e-3) / 1e12
+        gbs = work[d]["bytes"] / (avg * 1e-3) / 1e9
+        per_depth[str(d)] = {
+            "gpairs_per_s": n / (avg * 1e-3) / 1e9,
+            "launch_ms_avg": avg,
+            "launch_ms_median": statistics.median(launch_ms[d]),
+            "algorithmic_tflops": tflops,
+            "frac_fp32_peak": tflops / workmodel.PEAK_FP32_TFLOPS,
+            "hbm_gbs_algorithmic": gbs,
+            "frac_hbm_peak": gbs / workmodel.PEAK_HBM_GBS,
+            "tests_per_pair": work[d]["tests"] / n,
+            "splits_per_pair": work[d]["splits"] / n,
+            "backtracks_per_pair": work[d]["backtracks"] / n,
+            "hit_rate": work[d]["hits"] / n,
+            "flops_per_launch": work[d]["flops"],
+        }
+        roof[d] = {"bound": "alu", "achieved": tflops, "peak": workmodel.PEAK_FP32_TFLOPS,
+                   "unit": "TFLOP/s", "frac": tflops / workmodel.PEAK_FP32_TFLOPS,
+                   "traffic": None, "kernel": "k_pairs<false>", "depth": d}
+    dominant = max(DEPTHS, key=lambda d: statistics.mean(launch_ms[d]))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+        times = []
+        for _ in range(3):
+            c0 = time.perf_counter()
+            for d in DEPTHS:
+                oracle.intersect_depth(w.rays, w.fibers, d, nthreads=threads)
+            times.append(time.perf_counter() - c0)
+        tmed = statistics.median(times)
+        cpu = {"value": len(DEPTHS) * n / tmed / 1e9, "unit": "Gpairs/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"the whole workload ({n} pairs at depths {list(DEPTHS)}), FP64 "
+                         f"depth-d oracle, OpenMP over pairs, median of 3 passes ({tmed:.2f} s)"}
+
+    line = {
+        "metric": "ray-fiber intersections/sec (Gpairs/s) at depth 9 and 22",
+        "value": value, "unit": "Gpairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "straight_and_curved 2^20 pairs (half straight constant-radius, "
+                               "half curved random-walk, ~50% hits)",
+                   "pairs": n, "depths": list(DEPTHS), "pairing": "identity",
+                   "launch": "k_pairs, one pair per lane, 256-lane blocks"},
+        "per_depth": per_depth,
+        "roofline": roof[dominant],
+        "cpu_baseline": cpu,
+        "parity": parity,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

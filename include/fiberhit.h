@@ -1,0 +1,121 @@
+/*
+ * fiberhit -- ray/fiber intersection on AMD MI355X (gfx950), C ABI.
+ *
+ * The method is Binder & Keller, "Fast, High Precision Ray/Fiber Intersection
+ * using Tight, Disjoint Bounding Volumes" (arXiv 1811.03374): a fiber is a
+ * cubic Bezier curve whose control points carry a radius (Section 3.3); the
+ * test moves it into the frame of the ray (Section 3.3), then subdivides it
+ * at the parametric centre down to depth d inside bounding cylinders that are
+ * cropped by end-cap and split planes (Sections 3.1-3.3), visiting the half
+ * that the ray meets first and stopping at the first leaf hit (Section 3).
+ *
+ * Every function returns an int status (FI_OK or a negative FI_ERR_*), throws
+ * nothing, and never allocates or frees device memory on the call path. All
+ * array arguments are caller-owned device pointers (for example the data of
+ * torch tensors); the library only reads inputs and writes outputs. Work is
+ * enqueued asynchronously on `stream` (a hipStream_t; NULL is the legacy
+ * default stream); results are valid once the stream has synchronised.
+ *
+ * Layouts (structure of arrays, 32-bit floats, row-major):
+ *   rays   : 7 rows of ray_stride floats  -- ox, oy, oz, dx, dy, dz, tmax.
+ *            The direction need not be unit length: the library normalises
+ *            it, and t and tmax are distances along the normalised direction.
+ *   fibers : 16 rows of fiber_stride floats -- p0x, p0y, p0z, p0r, p1x, ...,
+ *            p3r: four control points, each with its radius control value.
+ *
+ * Per-pair data that make a pair meaningless (a zero, infinite or NaN
+ * direction, a NaN tmax, an index outside its array, a per-pair depth above
+ * 23) are not errors: that pair is reported as a miss.
+ */
+#ifndef FIBERHIT_H
+#define FIBERHIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define FI_OK             0
+#define FI_ERR_NULL      (-1)   /* a required pointer is NULL                         */
+#define FI_ERR_RANGE     (-2)   /* a count, stride or depth is out of range           */
+#define FI_ERR_HIP       (-3)   /* the HIP runtime reported an error at launch        */
+#define FI_ERR_WORKSPACE (-4)   /* workspace pointer missing or too small             */
+
+/* Largest subdivision depth: one bit per level in 32-bit integers and an
+ * integer parametric position below 2^23 (Section 3.3, interval conversion). */
+#define FI_MAX_DEPTH 23
+
+/* Library version, (major << 16) | (minor << 8) | patch. */
+int fi_version(void);
+
+/* Static English text for a status code. */
+const char *fi_strerror(int status);
+
+/*
+ * fiber_intersect_pairs -- nearest hit of each (ray, fiber) pair at depth d.
+ *
+ * Operation: the per-pair routine of the paper's intersection code
+ * (Appendix C, final listing; Sections 3.2 and 3.3), iterated with one bit
+ * per subdivision level. For pair i it intersects ray pair_ray[i] with fiber
+ * pair_fiber[i] and reports the first leaf cylinder the ray enters at
+ * subdivision depth pair_depth[i] (or `depth`): t is the entry into the
+ * capped leaf cylinder, u is the curve parameter of the hit point projected
+ * onto the leaf chord (Section 3.3, last paragraph), hit is 1 when
+ * 0 <= t < tmax.
+ *
+ * Arguments:
+ *   rays, ray_stride, n_rays       ray table (see layout), ray_stride >= n_rays.
+ *   fibers, fiber_stride, n_fibers fiber table (see layout), fiber_stride >= n_fibers.
+ *   pair_ray, pair_fiber           int32 index per pair, or NULL for the identity
+ *                                  pairing (then n_pairs must not exceed n_rays,
+ *                                  respectively n_fibers).
+ *   pair_depth                     uint8 depth per pair, or NULL to use `depth`.
+ *   depth                          0 .. FI_MAX_DEPTH (checked even when pair_depth
+ *                                  is given).
+ *   n_pairs                        >= 0; 0 enqueues nothing and returns FI_OK.
+ *   flags                          reserved, must be 0.
+ *   t_out, u_out, hit_out          n_pairs each. On a miss: t = +inf, u = NaN, hit = 0.
+ *   stream                         hipStream_t or NULL.
+ *
+ * Errors: FI_ERR_NULL when rays, fibers or an output is NULL with n_pairs > 0;
+ * FI_ERR_RANGE for negative counts, strides below the counts, a depth outside
+ * [0, 23], nonzero flags, or an identity pairing longer than a table;
+ * FI_ERR_HIP when the launch fails. Nothing is enqueued on error.
+ */
+int fiber_intersect_pairs(const float *rays, int64_t ray_stride, int64_t n_rays,
+                          const float *fibers, int64_t fiber_stride, int64_t n_fibers,
+                          const int32_t *pair_ray, const int32_t *pair_fiber,
+                          const uint8_t *pair_depth, int32_t depth, int64_t n_pairs,
+                          uint32_t flags,
+                          float *t_out, float *u_out, uint8_t *hit_out,
+                          void *stream);
+
+/*
+ * fiber_intersect_counts -- the traversal of fiber_intersect_pairs with its
+ * work counted instead of timed.
+ *
+ * Operation: the same per-pair search (same arguments and meaning as
+ * fiber_intersect_pairs), which in addition writes four int32 per pair to
+ * counts_out[4*i .. 4*i+3]: node tests (pruning tests of Section 3.2, one per
+ * loop trip), splits (descents), backtracks (Section 3.3, jumps to a pending
+ * sibling) and the level of the leaf that was hit (-1 on a miss). These are
+ * the units of the algorithmic work model.
+ *
+ * Errors: as fiber_intersect_pairs; counts_out must not be NULL.
+ */
+int fiber_intersect_counts(const float *rays, int64_t ray_stride, int64_t n_rays,
+                           const float *fibers, int64_t fiber_stride, int64_t n_fibers,
+                           const int32_t *pair_ray, const int32_t *pair_fiber,
+                           const uint8_t *pair_depth, int32_t depth, int64_t n_pairs,
+                           uint32_t flags,
+                           float *t_out, float *u_out, uint8_t *hit_out,
+                           int32_t *counts_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FIBERHIT_H */

@@ -38,6 +38,9 @@ def lib():
         L.fo_cap_interval.argtypes = [dp, C.c_double, dp]
         L.fo_ray_frame.argtypes = [dp, dp, dp]
         L.fo_ray_frame.restype = C.c_int
+        L.fo_tie_outcomes.argtypes = [dp, dp, C.c_int, C.c_double, C.c_int, C.c_int, dp, dp,
+                                      C.POINTER(C.c_int)]
+        L.fo_tie_outcomes.restype = C.c_int
         L.fo_cubic_constraints.argtypes = [dp]
         L.fo_cubic_constraints.restype = C.c_int
         if hasattr(L, "fx_batch"):
@@ -122,6 +125,22 @@ def single_depth(ray, fiber, depth):
     st = (C.c_int64 * 4)()
     hit = lib().fo_intersect_d(rp, fp, int(depth), C.byref(t), C.byref(u), st)
     return bool(hit), t.value, u.value, tuple(st)
+
+
+def tie_outcomes(ray, fiber, depth, eps=1e-5, max_flips=2, max_out=512):
+    """Results of one pair reachable by flipping at most ``max_flips`` near-tie
+    comparisons (relative margin <= eps). Returns arrays (t, u, hit), the
+    unflipped result first."""
+    r, rp = _d(ray)
+    f, fp = _d(fiber)
+    t = np.empty(max_out)
+    u = np.empty(max_out)
+    h = np.empty(max_out, np.int32)
+    n = lib().fo_tie_outcomes(rp, fp, int(depth), float(eps), int(max_flips), int(max_out),
+                              t.ctypes.data_as(C.POINTER(C.c_double)),
+                              u.ctypes.data_as(C.POINTER(C.c_double)),
+                              h.ctypes.data_as(C.POINTER(C.c_int)))
+    return t[:n], u[:n], h[:n].astype(bool)
 
 
 def split_half(q16):

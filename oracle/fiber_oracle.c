@@ -57,6 +57,11 @@
  *       the first non-zero of (q1-q0, q2-q0, q3-q0) at the start and
  *       (q3-q2, q3-q1, q3-q0) at the end; a zero split tangent by the chord.
  *       A zero-length chord gives distances to the point q0.
+ *   R14 the method's result is not continuous in its inputs: where a pruning
+ *       or ordering comparison is a near tie, an ulp-sized perturbation
+ *       selects another (equally valid) leaf. fo_tie_outcomes enumerates the
+ *       results reachable by flipping such ties; a lower-precision
+ *       implementation must reproduce the unflipped result or one of these.
  */
 #include <math.h>
 #include <stdint.h>
@@ -228,13 +233,36 @@ static v4 split_normal(const v4 q[4])
 /* The recursion                                                             */
 /* ------------------------------------------------------------------------ */
 
+/* Near ties. A comparison whose two sides differ by at most eps (relative)
+ * is a tie: rounding at a lower precision may decide it either way, and the
+ * method then legitimately returns another leaf. With eps > 0 the search
+ * numbers the ties it meets and flips tie j when bit j of flip_mask is set;
+ * enumerating masks yields every result reachable by flipping ties. */
+typedef struct {
+    double eps;
+    uint64_t flip_mask;
+    int n_ties;
+} ties_t;
+
 typedef struct {
     int depth;
     double tmax;
     int64_t tests, splits, backtracks;
     double t, u;
     int level;
+    ties_t ties;
 } search_t;
+
+/* value is the outcome of comparing a with b; flip it if this is a selected tie */
+static int decide(search_t *S, int value, double a, double b)
+{
+    if (S->ties.eps > 0.0 && isfinite(a) && isfinite(b) &&
+        fabs(a - b) <= S->ties.eps * fmax(1.0, fmax(fabs(a), fabs(b)))) {
+        const int j = S->ties.n_ties++;
+        if (j < 64 && ((S->ties.flip_mask >> j) & 1u)) value = !value;
+    }
+    return value;
+}
 
 static int visit(search_t *S, const v4 q[4], double lo, double hi,
                  int level, double u0, double u1)
@@ -244,10 +272,11 @@ static int visit(search_t *S, const v4 q[4], double lo, double hi,
     const double R = conservative_radius(q);
     double te, tx;
     if (!unit_ray_cylinder(q[0], a, R, &te, &tx)) return 0;
-    if (fmax(te, lo) > fmin(tx, hi)) return 0;
+    const double enter = fmax(te, lo), leave = fmin(tx, hi);
+    if (!decide(S, enter <= leave, leave, enter)) return 0;
 
     if (level >= S->depth) {
-        const double t = fmax(te, lo);
+        const double t = enter;
         const double c = dot3(a, a);
         double ul = 0.0;
         if (c > 0.0) {
@@ -270,10 +299,12 @@ static int visit(search_t *S, const v4 q[4], double lo, double hi,
     double flo = lo, fhi = hi;
     if (n.z != 0.0) {
         const double tp = c / n.z;
-        go_right = (tp > te) != (n.z > 0.0);
-        both = (te < tp) && (tp < tx);
-        if (tp > te) fhi = fmin(fhi, tp);
-        else         flo = fmax(flo, tp);
+        const int beyond_entry = decide(S, tp > te, tp, te);
+        const int before_exit = decide(S, tp < tx, tx, tp);
+        go_right = beyond_entry != (n.z > 0.0);
+        both = beyond_entry && before_exit;
+        if (beyond_entry) fhi = fmin(fhi, tp);
+        else              flo = fmax(flo, tp);
     } else {
         const double side = -c;            /* <(0,0,t) - s, n> for every t */
         go_right = side > 0.0;
@@ -302,11 +333,14 @@ int fo_version(void) { return 1; }
 /* One pair. ray = (ox, oy, oz, dx, dy, dz, tmax); fiber = 16 values p0..p3
  * (x, y, z, r). stats (may be NULL) receives node tests, splits, backtracks
  * and the level of the leaf that was hit (-1 on a miss). Returns 1 on a hit. */
-int fo_intersect_d(const double ray[7], const double fiber[16], int depth,
-                   double *t_out, double *u_out, int64_t stats[4])
+static int intersect_with_ties(const double ray[7], const double fiber[16], int depth,
+                               double eps, uint64_t flip_mask, int *n_ties,
+                               double *t_out, double *u_out, int64_t stats[4])
 {
     search_t S;
     memset(&S, 0, sizeof S);
+    S.ties.eps = eps;
+    S.ties.flip_mask = flip_mask;
     S.depth = depth;
     S.tmax = ray[6];
     S.level = -1;
@@ -324,7 +358,39 @@ int fo_intersect_d(const double ray[7], const double fiber[16], int depth,
     if (stats) {
         stats[0] = S.tests; stats[1] = S.splits; stats[2] = S.backtracks; stats[3] = S.level;
     }
+    if (n_ties) *n_ties = S.ties.n_ties;
     return hit;
+}
+
+int fo_intersect_d(const double ray[7], const double fiber[16], int depth,
+                   double *t_out, double *u_out, int64_t stats[4])
+{
+    return intersect_with_ties(ray, fiber, depth, 0.0, 0, NULL, t_out, u_out, stats);
+}
+
+/* Every result reachable from one pair by flipping at most max_flips (1 or 2)
+ * near-tie decisions (relative margin <= eps). Writes up to max_out results
+ * (t, u, hit), the unflipped one first; returns how many were written. */
+int fo_tie_outcomes(const double ray[7], const double fiber[16], int depth, double eps,
+                    int max_flips, int max_out, double *t_out, double *u_out, int *hit_out)
+{
+    int n = 0, k0 = 0;
+    double t, u;
+    int h = intersect_with_ties(ray, fiber, depth, eps, 0, &k0, &t, &u, NULL);
+    if (max_out < 1) return 0;
+    t_out[n] = t; u_out[n] = u; hit_out[n] = h; n++;
+    for (int j = 0; j < k0 && j < 64 && n < max_out; ++j) {
+        int kj = 0;
+        h = intersect_with_ties(ray, fiber, depth, eps, 1ull << j, &kj, &t, &u, NULL);
+        t_out[n] = t; u_out[n] = u; hit_out[n] = h; n++;
+        if (max_flips < 2) continue;
+        for (int k = j + 1; k < kj && k < 64 && n < max_out; ++k) {
+            h = intersect_with_ties(ray, fiber, depth, eps, (1ull << j) | (1ull << k), NULL,
+                                    &t, &u, NULL);
+            t_out[n] = t; u_out[n] = u; hit_out[n] = h; n++;
+        }
+    }
+    return n;
 }
 
 /* Many pairs from the structure-of-arrays layout of the library (rays: 7 rows

@@ -1,0 +1,74 @@
+"""C-ABI library checks that need no GPU: it loads, exports every function the
+header declares, and rejects bad arguments before touching the device."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1811_03374_amd import binding, build_lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fiberhit.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_function():
+    if not os.path.exists(build_lib.LIB):
+        build_lib.build()
+    names = declared_functions()
+    assert {"fiber_intersect_pairs", "fiber_intersect_counts", "fi_version", "fi_strerror"} <= set(names)
+    out = subprocess.run(["nm", "-D", "--defined-only", build_lib.LIB], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (\w+)$", out, flags=re.M))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    L = binding.lib()
+    for n in names:
+        assert hasattr(L, n)
+    assert set(binding.exported_symbols()) <= exported
+
+
+def test_version_and_strerror():
+    L = binding.lib()
+    assert L.fi_version() > 0
+    for code in (0, -1, -2, -3, -4, -99):
+        assert len(L.fi_strerror(code)) > 0
+
+
+def _call(**kw):
+    a = dict(rays=1, rs=8, nr=8, fibers=1, fs=8, nf=8, pr=None, pf=None, pd=None,
+             depth=9, n=8, flags=0, t=1, u=1, h=1)
+    a.update(kw)
+    vp = lambda x: None if x is None else C.c_void_p(x)
+    return binding.lib().fiber_intersect_pairs(
+        vp(a["rays"]), a["rs"], a["nr"], vp(a["fibers"]), a["fs"], a["nf"], vp(a["pr"]),
+        vp(a["pf"]), vp(a["pd"]), a["depth"], a["n"], a["flags"], vp(a["t"]), vp(a["u"]),
+        vp(a["h"]), None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(depth=24), -2), (dict(depth=-1), -2), (dict(n=-1), -2), (dict(flags=8), -2),
+    (dict(rs=4), -2), (dict(fs=4), -2), (dict(n=9), -2),
+    (dict(rays=None), -1), (dict(fibers=None), -1), (dict(t=None), -1), (dict(h=None), -1),
+])
+def test_argument_errors_before_launch(kw, code):
+    # these return before any HIP call, so they are safe without a device
+    assert _call(**kw) == code
+
+
+def test_empty_batch_is_a_no_op():
+    assert _call(n=0, rays=None, fibers=None, t=None, u=None, h=None) == 0
+
+
+def test_counts_requires_output():
+    L = binding.lib()
+    r = L.fiber_intersect_counts(C.c_void_p(1), 8, 8, C.c_void_p(1), 8, 8, None, None, None,
+                                 9, 8, 0, C.c_void_p(1), C.c_void_p(1), C.c_void_p(1), None, None)
+    assert r == -1

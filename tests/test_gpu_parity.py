@@ -1,0 +1,174 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1811_03374_amd import binding
+from paper_1811_03374_amd import workloads as W
+from parity import compare, oracle_with_band, tie_resolver
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(w, depth=None, counts=False):
+    d = w.depth if depth is None else depth
+    rays = torch.from_numpy(w.rays).to(DEV)
+    fibers = torch.from_numpy(w.fibers).to(DEV)
+    pr = None if w.pair_ray is None else torch.from_numpy(w.pair_ray).to(DEV)
+    pf = None if w.pair_fiber is None else torch.from_numpy(w.pair_fiber).to(DEV)
+    pd = None if w.pair_depth is None else torch.from_numpy(w.pair_depth).to(DEV)
+    out = binding.intersect_pairs(rays, fibers, d, pr, pf, pd, counts=counts)
+    torch.cuda.synchronize()
+    return [o.cpu().numpy() for o in out]
+
+
+def check(w, depth=None, label=""):
+    d = w.depth if depth is None else depth
+    say(f"[parity] {label} {w.name} depth={d} n={w.n_pairs}")
+    (t_o, u_o, h_o), band = oracle_with_band(w, d)
+    t_g, u_g, h_g = run_gpu(w, d)
+    dd = w.pair_depth if w.pair_depth is not None else d
+    st = compare(t_g, u_g, h_g, t_o, u_o, h_o, band, dd, alt=tie_resolver(w, d))
+    say(f"[parity]   {st}")
+    return st
+
+
+def test_plain_unit_cube_depth4():
+    st = check(W.plain_unit_cube())
+    assert st["ok"], st
+    assert 0.35 < st["hit_rate"] < 0.65
+
+
+@pytest.mark.parametrize("depth", [2, 3, 4, 6, 9, 12, 16, 19, 22])
+def test_straight_and_curved_depth_sweep(depth):
+    w = W.straight_and_curved(1 << 14 | 77)    # several blocks plus a ragged tail
+    st = check(w, depth)
+    assert st["ok"], st
+
+
+def test_depth_extremes():
+    w = W.straight_and_curved(3001)
+    for d in (0, 1, 23):
+        st = check(w, d)
+        assert st["ok"], st
+
+
+def test_node_counts_match_oracle():
+    """Integer work: node tests, splits, backtracks and leaf level per pair are
+    the oracle's except where a rounding-level tie flips a decision. Ties grow
+    common once nodes shrink to the FP32 resolution of their coordinates
+    (deep levels), where different paths still end on the same surface point."""
+    w = W.straight_and_curved(1 << 13)
+    for d, need in ((4, 0.999), (9, 0.998), (16, 0.98), (22, 0.95)):
+        _, _, h_o, st_o = oracle.intersect_depth(w.rays, w.fibers, d, stats=True)
+        t_g, u_g, h_g, cn = run_gpu(w, d, counts=True)
+        same = np.all(cn == st_o, axis=1)
+        say(f"[counts] depth={d} identical={same.mean():.5f} "
+            f"tests gpu={cn[:, 0].mean():.3f} oracle={st_o[:, 0].mean():.3f}")
+        assert same.mean() >= need
+        assert abs(cn[:, 0].mean() / st_o[:, 0].mean() - 1) < 0.01
+        assert np.array_equal(h_g.astype(bool)[same], h_o.astype(bool)[same])
+        assert np.array_equal((cn[:, 3] >= 0), h_g.astype(bool))
+        assert np.all(cn[h_g.astype(bool), 3] == d)
+
+
+def test_per_pair_depth_and_gathered_indices():
+    w = W.plain_unit_cube()
+    rng = np.random.default_rng(4)
+    w.pair_depth = rng.integers(0, 24, w.n_pairs).astype(np.uint8)
+    st = check(w, 9, "per-pair depth")
+    assert st["ok"], st
+
+
+def test_strided_tables_and_index_gather():
+    w = W.straight_and_curved(5000)
+    rng = np.random.default_rng(8)
+    n = 7000
+    pr = rng.integers(0, 5000, n).astype(np.int32)
+    pf = pr.copy()
+    # pad the tables: row stride larger than the count
+    R = np.zeros((7, 5200), np.float32); R[:, :5000] = w.rays
+    F = np.zeros((16, 5300), np.float32); F[:, :5000] = w.fibers
+    rays = torch.from_numpy(R).to(DEV)[:, :5000]
+    fibers = torch.from_numpy(F).to(DEV)[:, :5000]
+    t, u, h = binding.intersect_pairs(rays, fibers, 9, torch.from_numpy(pr).to(DEV),
+                                      torch.from_numpy(pf).to(DEV))
+    torch.cuda.synchronize()
+    t_o, u_o, h_o = oracle.intersect_depth(w.rays, w.fibers, 9, pr, pf)
+    same = h.cpu().numpy().astype(bool) == h_o.astype(bool)
+    assert same.mean() > 0.999
+
+
+def test_degenerate_pairs_are_misses():
+    w = W.straight_and_curved(512)
+    R = w.rays.copy()
+    R[3:6, 0] = 0.0                         # zero direction
+    R[3, 1] = np.nan                         # NaN direction
+    R[6, 2] = np.nan                         # NaN tmax
+    R[3:6, 3] = np.inf                       # infinite direction
+    w2 = W.Workload("degenerate", R, w.fibers, None, None, 9)
+    t, u, h = run_gpu(w2)
+    assert not h[:4].any() and np.all(np.isinf(t[:4])) and np.all(np.isnan(u[:4]))
+    # out-of-range indices and per-pair depth above 23
+    pr = np.arange(512, dtype=np.int32); pr[5] = 512; pr[6] = -1
+    pf = np.arange(512, dtype=np.int32); pf[7] = 10 ** 6
+    pd = np.full(512, 9, np.uint8); pd[8] = 24; pd[9] = 255
+    w3 = W.Workload("bad-index", w.rays, w.fibers, pr, pf, 9, pd)
+    t, u, h = run_gpu(w3)
+    assert not h[5:10].any()
+    t_o, u_o, h_o = oracle.intersect_depth(w.rays, w.fibers, 9)
+    keep = np.ones(512, bool); keep[5:10] = False
+    assert (h[keep].astype(bool) == h_o[keep].astype(bool)).mean() > 0.99
+
+
+def test_empty_and_single():
+    w = W.straight_and_curved(1)
+    rays = torch.from_numpy(w.rays).to(DEV)
+    fibers = torch.from_numpy(w.fibers).to(DEV)
+    t, u, h = binding.intersect_pairs(rays[:, :0], fibers[:, :0], 9)
+    torch.cuda.synchronize()
+    assert t.numel() == 0
+    t, u, h = run_gpu(w)
+    t_o, u_o, h_o = oracle.intersect_depth(w.rays, w.fibers, 9)
+    assert bool(h[0]) == bool(h_o[0])
+
+
+def test_argument_errors_on_device():
+    w = W.straight_and_curved(64)
+    rays = torch.from_numpy(w.rays).to(DEV)
+    fibers = torch.from_numpy(w.fibers).to(DEV)
+    with pytest.raises(binding.FiberHitError):
+        binding.intersect_pairs(rays, fibers, 24)
+    with pytest.raises(ValueError):
+        binding.intersect_pairs(rays.double(), fibers, 9)
+
+
+@pytest.mark.parametrize("depth", [9, 22])
+def test_full_size_sampled(depth):
+    """The 2^20-pair workload in the benchmark's launch configuration, checked
+    on a seeded sample of 16384 pairs that the oracle computes one by one."""
+    w = W.straight_and_curved(1 << 20, depth)
+    say(f"[parity] full size 2^20 depth={depth}")
+    t_g, u_g, h_g = run_gpu(w, depth)
+    idx = np.sort(np.random.default_rng(depth).choice(w.n_pairs, 16384, replace=False))
+    ws = w.subset(idx)
+    (t_o, u_o, h_o), band = oracle_with_band(ws, depth)
+    st = compare(t_g[idx], u_g[idx], h_g[idx], t_o, u_o, h_o, band, depth,
+                 alt=tie_resolver(ws, depth))
+    say(f"[parity]   {st}")
+    assert st["ok"], st
+    # properties that hold for every pair: miss encoding, t within [0, tmax)
+    hit = h_g.astype(bool)
+    assert np.all(np.isinf(t_g[~hit])) and np.all(np.isnan(u_g[~hit]))
+    assert np.all((t_g[hit] >= 0) & (t_g[hit] < w.rays[6][hit]))
+    assert np.all((u_g[hit] >= 0) & (u_g[hit] <= 1))
+    assert 0.45 < hit.mean() < 0.55

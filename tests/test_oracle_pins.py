@@ -535,3 +535,16 @@ def test_depth0_equals_capped_root_cylinder_on_bent_curves():
         agree += 1
     assert agree > n - 5
     assert 0.2 < h.mean() < 0.9
+
+
+def test_tie_outcomes_start_with_the_plain_result():
+    w = W.straight_and_curved(300)
+    t, u, h = oracle.intersect_depth(w.rays, w.fibers, 9)
+    multi = 0
+    for i in range(300):
+        ta, ua, ha = oracle.tie_outcomes(w.rays[:, i], w.fibers[:, i], 9, eps=0.0)
+        assert len(ta) == 1
+        tb, ub, hb = oracle.tie_outcomes(w.rays[:, i], w.fibers[:, i], 9, eps=1e-3)
+        assert bool(hb[0]) == bool(h[i]) and (not h[i] or (tb[0] == t[i] and ub[0] == u[i]))
+        multi += len(tb) > 1
+    assert multi > 0      # a loose threshold does find ties
