@@ -48,6 +48,10 @@ def lib():
                                    C.c_void_p, C.c_void_p, C.c_int64, C.c_double,
                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
             L.fx_batch.restype = None
+            L.fx_intersect.argtypes = [dp, dp, dp, dp]
+            L.fx_intersect.restype = C.c_int
+            L.fx_side_polynomial.argtypes = [dp, dp]
+            L.fx_side_polynomial.restype = C.c_int
         _lib = L
     return _lib
 
@@ -114,6 +118,25 @@ def intersect_exact(rays, fibers, pair_ray=None, pair_fiber=None, radius_scale=1
                fibers.shape[1], _ptr(pr), _ptr(pf), n, float(radius_scale),
                _ptr(t), _ptr(u), _ptr(kind), int(nthreads))
     return t, u, (kind > 0).astype(np.uint8), kind
+
+
+def single_exact(ray, fiber):
+    """One pair through fx_intersect (float64 inputs). Returns (kind, t, u)."""
+    r, rp = _d(ray)
+    f, fp = _d(fiber)
+    t = C.c_double()
+    u = C.c_double()
+    kind = lib().fx_intersect(rp, fp, C.byref(t), C.byref(u))
+    return kind, t.value, u.value
+
+
+def side_polynomial(q16):
+    """Bernstein coefficients of the degree-10 side polynomial of a curve
+    already in the ray frame."""
+    q, qp = _d(q16)
+    out = np.zeros(11)
+    n = lib().fx_side_polynomial(qp, out.ctypes.data_as(C.POINTER(C.c_double)))
+    return out[:n + 1]
 
 
 def single_depth(ray, fiber, depth):

@@ -1,0 +1,416 @@
+/*
+ * TEST INFRASTRUCTURE -- FP64 CPU oracle of the exact swept-disc surface
+ * ("ORACLE-X"), the limit that the depth-d method of Binder & Keller
+ * (arXiv 1811.03374) converges to.
+ *
+ * Only the test suite and the benchmark's self-check load this library; the
+ * HIP path shares nothing with it.
+ *
+ * Definition. The fiber is the solid swept by a circular disc of radius r(u)
+ * centred on the cubic Bezier curve C(u) in the plane normal to C'(u),
+ * u in [0, 1] (abstract, Sections 1 and 3.3: circular cross section, radius
+ * interpolated by the same Bezier basis), with flat end caps at u = 0 and
+ * u = 1 (the caps of the end cylinders, Section 3.3). The result is the
+ * smallest t in [0, tmax) at which the ray O + t*D/|D| lies in that solid.
+ *
+ * Computation, in the FP64 frame of the ray (origin at 0, direction +z):
+ *   side  roots u in [0,1] of F(u) = Dz^2 (Cx^2 + Cy^2) + (Cx Dx + Cy Dy)^2
+ *         - r^2 Dz^2 with D = C'/3, where the ray meets the boundary circle of
+ *         the disc at u; that point is at t = <C, D> / Dz;
+ *   caps  u = 0 and u = 1 when the ray meets the end disc (F <= 0);
+ *   inside the origin lies in a disc: a root of <C, D> with |C| <= r (t = 0);
+ *   planar when Dz vanishes identically (every disc plane contains the ray
+ *         direction), the ray lies in the disc at the roots of
+ *         <(Cx, Cy), (Dx, Dy)> and enters it at Cz - sqrt(r^2 - Cx^2 - Cy^2).
+ * Every candidate lies in the solid, and the first point of the solid along
+ * the ray is one of them as long as no disc passes through a focal point of
+ * the sweep (radius below the radius of curvature: the "thin fiber"
+ * condition of Section 3.4). Roots are isolated in Bernstein form by de
+ * Casteljau subdivision with Descartes' rule of signs (variation
+ * diminishing), then bisected to the last bit with the function evaluated
+ * in extended precision (long double).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define MAXDEG 10
+
+typedef struct { double c[MAXDEG + 1]; int n; } bpoly;   /* Bernstein coefficients on [0,1] */
+
+static double binom(int n, int k)
+{
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+
+static bpoly bmul(const bpoly *a, const bpoly *b)
+{
+    bpoly r;
+    r.n = a->n + b->n;
+    for (int k = 0; k <= r.n; ++k) r.c[k] = 0.0;
+    for (int i = 0; i <= a->n; ++i)
+        for (int j = 0; j <= b->n; ++j)
+            r.c[i + j] += binom(a->n, i) * binom(b->n, j) / binom(r.n, i + j) * a->c[i] * b->c[j];
+    return r;
+}
+
+static bpoly belevate(const bpoly *a, int n)
+{
+    /* degree elevation of a to degree n */
+    bpoly r = *a;
+    while (r.n < n) {
+        bpoly e;
+        e.n = r.n + 1;
+        for (int k = 0; k <= e.n; ++k) {
+            const double w = (double)k / e.n;
+            e.c[k] = (k > 0 ? w * r.c[k - 1] : 0.0) + (k < e.n ? (1.0 - w) * r.c[k] : 0.0);
+        }
+        r = e;
+    }
+    return r;
+}
+
+static bpoly badd(const bpoly *a, const bpoly *b, double sb)
+{
+    const int n = a->n > b->n ? a->n : b->n;
+    bpoly x = belevate(a, n), y = belevate(b, n), r;
+    r.n = n;
+    for (int k = 0; k <= n; ++k) r.c[k] = x.c[k] + sb * y.c[k];
+    return r;
+}
+
+/* split a Bernstein polynomial on [0,1] at 1/2 (de Casteljau) */
+static void bsplit(const bpoly *a, bpoly *L, bpoly *R)
+{
+    double w[MAXDEG + 1];
+    const int n = a->n;
+    memcpy(w, a->c, sizeof(double) * (n + 1));
+    L->n = R->n = n;
+    for (int k = 0; k <= n; ++k) {
+        L->c[k] = w[0];
+        R->c[n - k] = w[n - k];
+        for (int i = 0; i < n - k; ++i) w[i] = 0.5 * (w[i] + w[i + 1]);
+    }
+}
+
+static int sign_changes(const bpoly *a)
+{
+    int changes = 0, last = 0;
+    for (int k = 0; k <= a->n; ++k) {
+        const int s = a->c[k] > 0.0 ? 1 : (a->c[k] < 0.0 ? -1 : 0);
+        if (s == 0) continue;
+        if (last != 0 && s != last) changes++;
+        last = s;
+    }
+    return changes;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Curve in the ray frame                                                    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double q[4][4];     /* control points: x, y, z, r */
+} curve_t;
+
+static void eval(const curve_t *c, double u, double C[4], double D[3])
+{
+    const double v = 1.0 - u;
+    const double b[4] = {v * v * v, 3 * u * v * v, 3 * u * u * v, u * u * u};
+    const double e[3] = {v * v, 2 * u * v, u * u};
+    for (int k = 0; k < 4; ++k) {
+        C[k] = 0.0;
+        for (int j = 0; j < 4; ++j) C[k] += b[j] * c->q[j][k];
+    }
+    for (int k = 0; k < 3; ++k) {
+        D[k] = 0.0;
+        for (int j = 0; j < 3; ++j) D[k] += e[j] * (c->q[j + 1][k] - c->q[j][k]);
+    }
+}
+
+/* F(u) evaluated from the curve directly, in long double */
+static long double F_ld(const curve_t *c, long double u)
+{
+    const long double v = 1.0L - u;
+    const long double b[4] = {v * v * v, 3 * u * v * v, 3 * u * u * v, u * u * u};
+    const long double e[3] = {v * v, 2 * u * v, u * u};
+    long double C[4] = {0, 0, 0, 0}, D[3] = {0, 0, 0};
+    for (int k = 0; k < 4; ++k)
+        for (int j = 0; j < 4; ++j) C[k] += b[j] * (long double)c->q[j][k];
+    for (int k = 0; k < 3; ++k)
+        for (int j = 0; j < 3; ++j) D[k] += e[j] * ((long double)c->q[j + 1][k] - (long double)c->q[j][k]);
+    const long double xy = C[0] * D[0] + C[1] * D[1];
+    return D[2] * D[2] * (C[0] * C[0] + C[1] * C[1]) + xy * xy - C[3] * C[3] * D[2] * D[2];
+}
+
+static long double G_ld(const curve_t *c, long double u)
+{
+    const long double v = 1.0L - u;
+    const long double b[4] = {v * v * v, 3 * u * v * v, 3 * u * u * v, u * u * u};
+    const long double e[3] = {v * v, 2 * u * v, u * u};
+    long double C[3] = {0, 0, 0}, D[3] = {0, 0, 0};
+    for (int k = 0; k < 3; ++k)
+        for (int j = 0; j < 4; ++j) C[k] += b[j] * (long double)c->q[j][k];
+    for (int k = 0; k < 3; ++k)
+        for (int j = 0; j < 3; ++j) D[k] += e[j] * ((long double)c->q[j + 1][k] - (long double)c->q[j][k]);
+    return C[0] * D[0] + C[1] * D[1] + C[2] * D[2];
+}
+
+/* <(Cx, Cy), (Dx, Dy)>: zero where the ray line lies in a disc plane that
+ * contains the ray direction */
+static long double XY_ld(const curve_t *c, long double u)
+{
+    const long double v = 1.0L - u;
+    const long double b[4] = {v * v * v, 3 * u * v * v, 3 * u * u * v, u * u * u};
+    const long double e[3] = {v * v, 2 * u * v, u * u};
+    long double C[2] = {0, 0}, D[2] = {0, 0};
+    for (int k = 0; k < 2; ++k)
+        for (int j = 0; j < 4; ++j) C[k] += b[j] * (long double)c->q[j][k];
+    for (int k = 0; k < 2; ++k)
+        for (int j = 0; j < 3; ++j) D[k] += e[j] * ((long double)c->q[j + 1][k] - (long double)c->q[j][k]);
+    return C[0] * D[0] + C[1] * D[1];
+}
+
+typedef long double (*fn_t)(const curve_t *, long double);
+
+/* Root of f in [a, b] where f(a) and f(b) differ in sign: bisection to the
+ * last bit of long double. */
+static double bisect(const curve_t *c, fn_t f, double a, double b)
+{
+    long double lo = a, hi = b;
+    long double flo = f(c, lo);
+    for (int it = 0; it < 200 && hi - lo > 0; ++it) {
+        const long double mid = 0.5L * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        const long double fm = f(c, mid);
+        if (fm == 0.0L) return (double)mid;
+        if ((fm < 0) == (flo < 0)) { lo = mid; flo = fm; }
+        else hi = mid;
+    }
+    return (double)(0.5L * (lo + hi));
+}
+
+/* Collect roots of the Bernstein polynomial p (of function f) on [a, b]. */
+static void isolate(const curve_t *c, fn_t f, const bpoly *p, double a, double b,
+                    double *roots, int *nr, int maxr, int depth)
+{
+    if (*nr >= maxr) return;
+    const int sc = sign_changes(p);
+    if (sc == 0) {
+        /* an exact zero coefficient at an end is a root at that end */
+        if (p->c[0] == 0.0 && a == 0.0) roots[(*nr)++] = 0.0;
+        if (*nr < maxr && p->c[p->n] == 0.0 && b == 1.0) roots[(*nr)++] = 1.0;
+        return;
+    }
+    if (sc == 1 && p->c[0] != 0.0 && p->c[p->n] != 0.0) {
+        roots[(*nr)++] = bisect(c, f, a, b);
+        return;
+    }
+    if (depth > 60 || b - a < 1e-15) {           /* cluster of roots: report its centre */
+        roots[(*nr)++] = 0.5 * (a + b);
+        return;
+    }
+    bpoly L, R;
+    bsplit(p, &L, &R);
+    const double m = 0.5 * (a + b);
+    isolate(c, f, &L, a, m, roots, nr, maxr, depth + 1);
+    isolate(c, f, &R, m, b, roots, nr, maxr, depth + 1);
+}
+
+/* candidate t of the disc at u (Dz != 0): the ray point in the disc plane */
+static int disc_t(const curve_t *c, double u, double *t, double *Fout)
+{
+    double C[4], D[3];
+    eval(c, u, C, D);
+    const double dn = sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+    if (!(dn > 0.0) || D[2] == 0.0) return 0;
+    *t = (C[0] * D[0] + C[1] * D[1] + C[2] * D[2]) / D[2];
+    if (Fout) *Fout = (double)F_ld(c, u);
+    return 1;
+}
+
+/* Exact first entry; kind: 0 miss, 1 side, 2 start cap, 3 end cap, 4 inside */
+static int exact_hit(const curve_t *c, double tmax, double *t_out, double *u_out)
+{
+    /* Bernstein forms of Cx, Cy, Cz, r (degree 3) and Dx, Dy, Dz (degree 2) */
+    bpoly C[4], D[3];
+    for (int k = 0; k < 4; ++k) {
+        C[k].n = 3;
+        for (int j = 0; j < 4; ++j) C[k].c[j] = c->q[j][k];
+    }
+    for (int k = 0; k < 3; ++k) {
+        D[k].n = 2;
+        for (int j = 0; j < 3; ++j) D[k].c[j] = c->q[j + 1][k] - c->q[j][k];
+    }
+    const bpoly Dz2 = bmul(&D[2], &D[2]);
+    const bpoly Cx2 = bmul(&C[0], &C[0]), Cy2 = bmul(&C[1], &C[1]);
+    const bpoly rho = badd(&Cx2, &Cy2, 1.0);
+    const bpoly a1 = bmul(&Dz2, &rho);
+    const bpoly cxdx = bmul(&C[0], &D[0]), cydy = bmul(&C[1], &D[1]);
+    const bpoly xy = badd(&cxdx, &cydy, 1.0);
+    const bpoly a2 = bmul(&xy, &xy);
+    const bpoly r2 = bmul(&C[3], &C[3]);
+    const bpoly a3 = bmul(&r2, &Dz2);
+    bpoly F = badd(&a1, &a2, 1.0);
+    F = badd(&F, &a3, -1.0);
+
+    double best = INFINITY, bu = NAN;
+    int kind = 0;
+
+    /* origin inside the solid */
+    const bpoly czdz = bmul(&C[2], &D[2]);
+    bpoly G = badd(&xy, &czdz, 1.0);
+    double groots[64];
+    int ng = 0;
+    isolate(c, G_ld, &G, 0.0, 1.0, groots, &ng, 64, 0);
+    for (int i = 0; i < ng; ++i) {
+        double Cu[4], Du[3];
+        eval(c, groots[i], Cu, Du);
+        if (Cu[0] * Cu[0] + Cu[1] * Cu[1] + Cu[2] * Cu[2] <= Cu[3] * Cu[3]) {
+            *t_out = 0.0;
+            *u_out = groots[i];
+            return tmax > 0.0 ? 4 : 0;
+        }
+    }
+
+    /* every disc plane contains the ray direction (C'z == 0 identically, e.g.
+     * a straight fiber or a curve in a plane normal to the ray): the ray lies
+     * in the disc at u exactly where <(Cx, Cy), (Dx, Dy)> = 0, and enters it
+     * at t = Cz - sqrt(r^2 - Cx^2 - Cy^2) */
+    if (D[2].c[0] == 0.0 && D[2].c[1] == 0.0 && D[2].c[2] == 0.0) {
+        double proots[64];
+        int np = 0;
+        isolate(c, XY_ld, &xy, 0.0, 1.0, proots, &np, 64, 0);
+        for (int i = 0; i < np; ++i) {
+            double Cu[4], Du[3];
+            eval(c, proots[i], Cu, Du);
+            const double rest = Cu[3] * Cu[3] - Cu[0] * Cu[0] - Cu[1] * Cu[1];
+            if (rest < 0.0) continue;
+            const double t = Cu[2] - sqrt(rest);
+            if (t >= 0.0 && t < tmax && t < best) { best = t; bu = proots[i]; kind = 1; }
+        }
+        *t_out = best;
+        *u_out = bu;
+        return kind;
+    }
+
+    /* side surface */
+    double roots[128];
+    int nr = 0;
+    isolate(c, F_ld, &F, 0.0, 1.0, roots, &nr, 128, 0);
+    double scale = 0.0;
+    for (int j = 0; j < 4; ++j)
+        for (int k = 0; k < 3; ++k) scale = fmax(scale, fabs(c->q[j][k]));
+    for (int i = 0; i < nr; ++i) {
+        double t;
+        double Cu[4], Du[3];
+        eval(c, roots[i], Cu, Du);
+        const double dn = sqrt(Du[0] * Du[0] + Du[1] * Du[1] + Du[2] * Du[2]);
+        if (dn <= 1e-12 * (scale + 1e-300)) continue;      /* cusp: F vanishes with C' */
+        if (!disc_t(c, roots[i], &t, NULL)) continue;
+        if (t >= 0.0 && t < tmax && t < best) { best = t; bu = roots[i]; kind = 1; }
+    }
+    /* end caps */
+    for (int e = 0; e < 2; ++e) {
+        double t, Fv;
+        if (!disc_t(c, (double)e, &t, &Fv)) continue;
+        if (Fv <= 0.0 && t >= 0.0 && t < tmax && t < best) { best = t; bu = (double)e; kind = 2 + e; }
+    }
+    *t_out = best;
+    *u_out = bu;
+    return kind;
+}
+
+/* Duff et al. 2017 basis (same published construction as the depth oracle;
+ * repeated here so that this file stands alone). */
+static void onb_x(const double w[3], double u[3], double v[3])
+{
+    const double s = copysign(1.0, w[2]);
+    const double a = -1.0 / (s + w[2]);
+    const double b = w[0] * w[1] * a;
+    u[0] = 1.0 + s * w[0] * w[0] * a;  u[1] = s * b;  u[2] = -s * w[0];
+    v[0] = b;  v[1] = s + w[1] * w[1] * a;  v[2] = -w[1];
+}
+
+int fx_intersect(const double ray[7], const double fiber[16], double *t_out, double *u_out)
+{
+    *t_out = INFINITY;
+    *u_out = NAN;
+    const double *O = ray, *Dr = ray + 3;
+    const double len = sqrt(Dr[0] * Dr[0] + Dr[1] * Dr[1] + Dr[2] * Dr[2]);
+    if (!(len > 0.0) || !isfinite(len) || !(ray[6] == ray[6])) return 0;
+    const double w[3] = {Dr[0] / len, Dr[1] / len, Dr[2] / len};
+    double u[3], v[3];
+    onb_x(w, u, v);
+    curve_t c;
+    for (int k = 0; k < 4; ++k) {
+        const double d0 = fiber[4 * k] - O[0], d1 = fiber[4 * k + 1] - O[1], d2 = fiber[4 * k + 2] - O[2];
+        c.q[k][0] = d0 * u[0] + d1 * u[1] + d2 * u[2];
+        c.q[k][1] = d0 * v[0] + d1 * v[1] + d2 * v[2];
+        c.q[k][2] = d0 * w[0] + d1 * w[1] + d2 * w[2];
+        c.q[k][3] = fiber[4 * k + 3];
+    }
+    double t, uu;
+    const int kind = exact_hit(&c, ray[6], &t, &uu);
+    if (kind == 0) return 0;
+    *t_out = t;
+    *u_out = uu;
+    return kind;
+}
+
+void fx_batch(const float *rays, int64_t ray_stride, int64_t n_rays,
+              const float *fibers, int64_t fiber_stride, int64_t n_fibers,
+              const int32_t *pair_ray, const int32_t *pair_fiber, int64_t n,
+              double radius_scale, double *t_out, double *u_out, int32_t *kind_out,
+              int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t ri = pair_ray ? pair_ray[i] : i;
+        const int64_t fi = pair_fiber ? pair_fiber[i] : i;
+        double ray[7], fib[16], t = INFINITY, u = NAN;
+        int kind = 0;
+        if (ri >= 0 && ri < n_rays && fi >= 0 && fi < n_fibers) {
+            for (int r = 0; r < 7; ++r) ray[r] = rays[r * ray_stride + ri];
+            for (int r = 0; r < 16; ++r) fib[r] = fibers[r * fiber_stride + fi];
+            for (int k = 0; k < 4; ++k) fib[4 * k + 3] *= radius_scale;
+            kind = fx_intersect(ray, fib, &t, &u);
+        }
+        t_out[i] = t;
+        u_out[i] = u;
+        kind_out[i] = kind;
+    }
+}
+
+/* Bernstein coefficients of F for a curve given in the ray frame (pins). */
+int fx_side_polynomial(const double q16[16], double coef[MAXDEG + 1])
+{
+    curve_t c;
+    for (int j = 0; j < 4; ++j)
+        for (int k = 0; k < 4; ++k) c.q[j][k] = q16[4 * j + k];
+    bpoly C[4], D[3];
+    for (int k = 0; k < 4; ++k) { C[k].n = 3; for (int j = 0; j < 4; ++j) C[k].c[j] = c.q[j][k]; }
+    for (int k = 0; k < 3; ++k) { D[k].n = 2; for (int j = 0; j < 3; ++j) D[k].c[j] = c.q[j + 1][k] - c.q[j][k]; }
+    const bpoly Dz2 = bmul(&D[2], &D[2]);
+    const bpoly Cx2 = bmul(&C[0], &C[0]), Cy2 = bmul(&C[1], &C[1]);
+    const bpoly rho = badd(&Cx2, &Cy2, 1.0);
+    const bpoly a1 = bmul(&Dz2, &rho);
+    const bpoly cxdx = bmul(&C[0], &D[0]), cydy = bmul(&C[1], &D[1]);
+    const bpoly xy = badd(&cxdx, &cydy, 1.0);
+    const bpoly a2 = bmul(&xy, &xy);
+    const bpoly r2 = bmul(&C[3], &C[3]);
+    const bpoly a3 = bmul(&r2, &Dz2);
+    bpoly F = badd(&a1, &a2, 1.0);
+    F = badd(&F, &a3, -1.0);
+    for (int k = 0; k <= MAXDEG; ++k) coef[k] = F.c[k];
+    return F.n;
+}

@@ -1,0 +1,182 @@
+"""Pins of the exact swept-disc oracle (CPU only)."""
+import math
+
+import mpmath
+import numpy as np
+import pytest
+
+import oracle
+from paper_1811_03374_amd import workloads as W
+from test_oracle_pins import (bezier, bezier_d, brute_force, capped_cylinder,
+                              unpack_rays)
+
+
+def test_straight_fibers_equal_capped_cylinder_all_kinds():
+    w = W.exact_straight_fibers(1500)
+    P = W.unpack_fibers(w.fibers)
+    O, D, tmax = unpack_rays(w.rays)
+    r = P[:, 0, 3]
+    t_cf, u_cf, h_cf = capped_cylinder(O, D, P[:, 0, :3], P[:, 3, :3], r, tmax)
+    _, _, h_lo = capped_cylinder(O, D, P[:, 0, :3], P[:, 3, :3], r * (1 - 1e-7), tmax)
+    _, _, h_hi = capped_cylinder(O, D, P[:, 0, :3], P[:, 3, :3], r * (1 + 1e-7), tmax)
+    stable = h_lo == h_hi
+    t, u, h, kind = oracle.intersect_exact(w.rays, w.fibers)
+    assert np.array_equal(h.astype(bool)[stable], h_cf[stable])
+    assert {1, 2, 3} <= set(np.unique(kind[h.astype(bool)]))
+    b = stable & h_cf & h.astype(bool)
+    assert np.max(np.abs(t[b] - t_cf[b]) / t_cf[b]) < 1e-11
+    assert np.abs(u[b] - u_cf[b]).max() < 1e-10
+
+
+def test_exact_not_later_than_sampled_discs():
+    w = W.gentle_valid_curves(400)
+    P = W.unpack_fibers(w.fibers)
+    O, D, tmax = unpack_rays(w.rays)
+    t_bf, u_bf, h_bf = brute_force(P, O, D, tmax)
+    t, u, h, kind = oracle.intersect_exact(w.rays, w.fibers)
+    assert np.array_equal(h.astype(bool), h_bf)
+    b = h.astype(bool)
+    rel = (t[b] - t_bf[b]) / t_bf[b]
+    assert rel.max() <= 1e-12 and rel.min() > -1e-7
+    assert np.abs(u[b] - u_bf[b]).max() < 1e-4
+
+
+def test_side_hits_are_on_the_circle_in_the_normal_plane():
+    w = W.gentle_valid_curves(400, seed=7)
+    P = W.unpack_fibers(w.fibers)
+    O, D, tmax = unpack_rays(w.rays)
+    t, u, h, kind = oracle.intersect_exact(w.rays, w.fibers)
+    sel = kind == 1
+    assert sel.sum() > 100
+    Dn = D / np.linalg.norm(D, axis=1, keepdims=True)
+    X = O[sel] + t[sel, None] * Dn[sel]
+    C = bezier(P[sel], u[sel, None])[:, 0]
+    T = bezier_d(P[sel], u[sel, None])[:, 0, :3]
+    dist = np.linalg.norm(X - C[:, :3], axis=1)
+    assert np.abs(dist - C[:, 3]).max() < 1e-12
+    assert np.abs(np.sum((X - C[:, :3]) * T, axis=1)).max() < 1e-12
+    # cap hits: on the end disc
+    for kk, ue in ((2, 0.0), (3, 1.0)):
+        s = kind == kk
+        if s.any():
+            Xc = O[s] + t[s, None] * Dn[s]
+            Cc = bezier(P[s], np.full((s.sum(), 1), ue))[:, 0]
+            assert np.all(np.linalg.norm(Xc - Cc[:, :3], axis=1) <= Cc[:, 3] * (1 + 1e-12))
+
+
+def _mp_exact(ray, fib, dps=50):
+    """First entry from an independent route: the ray frame in 50-digit
+    arithmetic, F in the power basis, mpmath.polyroots, caps checked directly."""
+    mpmath.mp.dps = dps
+    O = [mpmath.mpf(float(x)) for x in ray[:3]]
+    Dv = [mpmath.mpf(float(x)) for x in ray[3:6]]
+    L = mpmath.sqrt(sum(x * x for x in Dv))
+    w = [x / L for x in Dv]
+    # any orthonormal completion: Gram-Schmidt against the least aligned axis
+    k = int(np.argmin([abs(float(x)) for x in w]))
+    e = [mpmath.mpf(0)] * 3
+    e[k] = mpmath.mpf(1)
+    dot = sum(a * b for a, b in zip(e, w))
+    uvec = [a - dot * b for a, b in zip(e, w)]
+    un = mpmath.sqrt(sum(x * x for x in uvec))
+    uvec = [x / un for x in uvec]
+    vvec = [w[1] * uvec[2] - w[2] * uvec[1], w[2] * uvec[0] - w[0] * uvec[2],
+            w[0] * uvec[1] - w[1] * uvec[0]]
+    q = []
+    for j in range(4):
+        p = [mpmath.mpf(float(fib[4 * j + c])) - O[c] for c in range(3)]
+        q.append([sum(a * b for a, b in zip(p, uvec)), sum(a * b for a, b in zip(p, vvec)),
+                  sum(a * b for a, b in zip(p, w)), mpmath.mpf(float(fib[4 * j + 3]))])
+    # power-basis coefficients (highest first) of each channel
+    def power(c):
+        a0, a1, a2, a3 = c
+        return [-a0 + 3 * a1 - 3 * a2 + a3, 3 * a0 - 6 * a1 + 3 * a2, -3 * a0 + 3 * a1, a0]
+    Cp = [power([q[j][c] for j in range(4)]) for c in range(4)]
+    Dp = [mpmath.polyval if False else None for _ in range(3)]
+    def deriv(p):
+        n = len(p) - 1
+        return [p[i] * (n - i) for i in range(n)]
+    Dp = [deriv(Cp[c]) for c in range(3)]
+    def mul(a, b):
+        r = [mpmath.mpf(0)] * (len(a) + len(b) - 1)
+        for i, x in enumerate(a):
+            for j, y in enumerate(b):
+                r[i + j] += x * y
+        return r
+    def add(a, b, s=1):
+        n = max(len(a), len(b))
+        a = [mpmath.mpf(0)] * (n - len(a)) + a
+        b = [mpmath.mpf(0)] * (n - len(b)) + b
+        return [x + s * y for x, y in zip(a, b)]
+    Dz2 = mul(Dp[2], Dp[2])
+    xy = add(mul(Cp[0], Dp[0]), mul(Cp[1], Dp[1]))
+    F = add(add(mul(Dz2, add(mul(Cp[0], Cp[0]), mul(Cp[1], Cp[1]))), mul(xy, xy)),
+            mul(mul(Cp[3], Cp[3]), Dz2), -1)
+    while abs(F[0]) == 0:
+        F = F[1:]
+    roots = mpmath.polyroots(F, maxsteps=400, extraprec=200)
+    best = (math.inf, None)
+    def cand(uu):
+        C = [mpmath.polyval(Cp[c], uu) for c in range(4)]
+        Dd = [mpmath.polyval(Dp[c], uu) for c in range(3)]
+        if Dd[2] == 0:
+            return None
+        return (C[0] * Dd[0] + C[1] * Dd[1] + C[2] * Dd[2]) / Dd[2], C, Dd
+    for rt in roots:
+        if abs(mpmath.im(rt)) > mpmath.mpf(10) ** -25:
+            continue
+        uu = mpmath.re(rt)
+        if uu < 0 or uu > 1:
+            continue
+        c = cand(uu)
+        if c and 0 <= c[0] < ray[6] and c[0] < best[0]:
+            best = (c[0], uu)
+    for ue in (mpmath.mpf(0), mpmath.mpf(1)):
+        c = cand(ue)
+        if c is None:
+            continue
+        t, C, Dd = c
+        rad2 = C[0] ** 2 + C[1] ** 2 + (t - C[2]) ** 2
+        if rad2 <= C[3] ** 2 and 0 <= t < ray[6] and t < best[0]:
+            best = (t, ue)
+    return best
+
+
+def test_exact_matches_50_digit_polynomial_roots():
+    w = W.gentle_valid_curves(40, seed=3)
+    t, u, h, kind = oracle.intersect_exact(w.rays, w.fibers)
+    for i in range(40):
+        tb, ub = _mp_exact(w.rays[:, i].astype(float), w.fibers[:, i].astype(float))
+        if not h[i]:
+            assert tb == math.inf
+            continue
+        assert abs(float(tb) - t[i]) <= 1e-13 * t[i]
+        assert abs(float(ub) - u[i]) <= 1e-11
+
+
+def test_depth_method_converges_to_exact():
+    w = W.gentle_valid_curves(300, seed=11)
+    t, u, h, kind = oracle.intersect_exact(w.rays, w.fibers)
+    prev = None
+    for d in (6, 10, 14, 18, 22):
+        td, ud, hd = oracle.intersect_depth(w.rays, w.fibers, d)
+        b = hd.astype(bool) & h.astype(bool)
+        err = np.median(np.abs(td[b] - t[b]))
+        if prev is not None:
+            assert err < prev / 6            # about 2x per level on tapered fibers
+        prev = err
+    assert prev < 5e-9
+
+
+def test_exact_degenerate():
+    fib = np.array([0, 0, 0, .1, 1, 0, 0, .1, 2, 0, 0, .1, 3, 0, 0, .1], float)
+    kind, t, u = oracle.single_exact(np.array([-2.0, 0.05, 0, 1, 0, 0, 100]), fib)
+    assert kind == 2 and abs(t - 2.0) < 1e-14 and u == 0.0
+    kind, t, u = oracle.single_exact(np.array([1.3, 0.0, -4, 0, 0, 1, 100]), fib)
+    assert kind == 1 and abs(t - 3.9) < 1e-12 and abs(u - 1.3 / 3) < 1e-12
+    kind, t, u = oracle.single_exact(np.array([1.3, 0.0, 0.05, 0, 0, 1, 100]), fib)
+    assert kind == 4 and t == 0.0            # origin inside the fiber
+    kind, t, u = oracle.single_exact(np.array([1.3, 0.5, -4, 0, 0, 1, 100]), fib)
+    assert kind == 0
+    kind, t, u = oracle.single_exact(np.array([0, 0, -5, 0, 0, 0, 100]), fib)
+    assert kind == 0
