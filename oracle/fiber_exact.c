@@ -40,11 +40,15 @@
 
 #define MAXDEG 10
 
-typedef struct { double c[MAXDEG + 1]; int n; } bpoly;   /* Bernstein coefficients on [0,1] */
+/* Bernstein coefficients on [0,1], in extended precision: near a ray that is
+ * almost parallel to the disc planes, F only dips below zero by ~1e-17 of
+ * coefficients of order 1e-2, which double rounding would hide. */
+typedef long double real;
+typedef struct { real c[MAXDEG + 1]; int n; } bpoly;
 
-static double binom(int n, int k)
+static real binom(int n, int k)
 {
-    double r = 1.0;
+    real r = 1.0L;
     for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
     return r;
 }
@@ -68,15 +72,15 @@ static bpoly belevate(const bpoly *a, int n)
         bpoly e;
         e.n = r.n + 1;
         for (int k = 0; k <= e.n; ++k) {
-            const double w = (double)k / e.n;
-            e.c[k] = (k > 0 ? w * r.c[k - 1] : 0.0) + (k < e.n ? (1.0 - w) * r.c[k] : 0.0);
+            const real w = (real)k / e.n;
+            e.c[k] = (k > 0 ? w * r.c[k - 1] : 0.0L) + (k < e.n ? (1.0L - w) * r.c[k] : 0.0L);
         }
         r = e;
     }
     return r;
 }
 
-static bpoly badd(const bpoly *a, const bpoly *b, double sb)
+static bpoly badd(const bpoly *a, const bpoly *b, real sb)
 {
     const int n = a->n > b->n ? a->n : b->n;
     bpoly x = belevate(a, n), y = belevate(b, n), r;
@@ -88,14 +92,14 @@ static bpoly badd(const bpoly *a, const bpoly *b, double sb)
 /* split a Bernstein polynomial on [0,1] at 1/2 (de Casteljau) */
 static void bsplit(const bpoly *a, bpoly *L, bpoly *R)
 {
-    double w[MAXDEG + 1];
+    real w[MAXDEG + 1];
     const int n = a->n;
-    memcpy(w, a->c, sizeof(double) * (n + 1));
+    memcpy(w, a->c, sizeof(real) * (n + 1));
     L->n = R->n = n;
     for (int k = 0; k <= n; ++k) {
         L->c[k] = w[0];
         R->c[n - k] = w[n - k];
-        for (int i = 0; i < n - k; ++i) w[i] = 0.5 * (w[i] + w[i + 1]);
+        for (int i = 0; i < n - k; ++i) w[i] = 0.5L * (w[i] + w[i + 1]);
     }
 }
 
@@ -103,7 +107,7 @@ static int sign_changes(const bpoly *a)
 {
     int changes = 0, last = 0;
     for (int k = 0; k <= a->n; ++k) {
-        const int s = a->c[k] > 0.0 ? 1 : (a->c[k] < 0.0 ? -1 : 0);
+        const int s = a->c[k] > 0.0L ? 1 : (a->c[k] < 0.0L ? -1 : 0);
         if (s == 0) continue;
         if (last != 0 && s != last) changes++;
         last = s;
@@ -204,11 +208,11 @@ static void isolate(const curve_t *c, fn_t f, const bpoly *p, double a, double b
     const int sc = sign_changes(p);
     if (sc == 0) {
         /* an exact zero coefficient at an end is a root at that end */
-        if (p->c[0] == 0.0 && a == 0.0) roots[(*nr)++] = 0.0;
-        if (*nr < maxr && p->c[p->n] == 0.0 && b == 1.0) roots[(*nr)++] = 1.0;
+        if (p->c[0] == 0.0L && a == 0.0) roots[(*nr)++] = 0.0;
+        if (*nr < maxr && p->c[p->n] == 0.0L && b == 1.0) roots[(*nr)++] = 1.0;
         return;
     }
-    if (sc == 1 && p->c[0] != 0.0 && p->c[p->n] != 0.0) {
+    if (sc == 1 && p->c[0] != 0.0L && p->c[p->n] != 0.0L) {
         roots[(*nr)++] = bisect(c, f, a, b);
         return;
     }
@@ -223,14 +227,33 @@ static void isolate(const curve_t *c, fn_t f, const bpoly *p, double a, double b
     isolate(c, f, &R, m, b, roots, nr, maxr, depth + 1);
 }
 
-/* candidate t of the disc at u (Dz != 0): the ray point in the disc plane */
-static int disc_t(const curve_t *c, double u, double *t, double *Fout)
+/* candidate t of the disc at u: the ray point in the disc plane. From the
+ * plane, t = <C, D> / Dz; on the boundary circle the same point is also
+ * Cz +- sqrt(r^2 - Cx^2 - Cy^2), which stays well conditioned when the disc
+ * plane is nearly parallel to the ray (Dz -> 0). For a point known to lie on
+ * the circle (a root of F) the form with the smaller rounding estimate is
+ * used; an end-cap point may lie anywhere in the disc, so it uses the plane.
+ * F (if requested) is evaluated in long double. */
+static int disc_t(const curve_t *c, double u, int on_circle, double *t, double *Fout)
 {
     double C[4], D[3];
     eval(c, u, C, D);
     const double dn = sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
-    if (!(dn > 0.0) || D[2] == 0.0) return 0;
-    *t = (C[0] * D[0] + C[1] * D[1] + C[2] * D[2]) / D[2];
+    if (!(dn > 0.0)) return 0;
+    const double xy = C[0] * D[0] + C[1] * D[1];
+    const double cn = sqrt(C[0] * C[0] + C[1] * C[1] + C[2] * C[2]);
+    const double rest = C[3] * C[3] - C[0] * C[0] - C[1] * C[1];
+    const double err_div = D[2] != 0.0 ? cn * dn / fabs(D[2]) : INFINITY;
+    double err_sq = INFINITY, tsq = 0.0;
+    if (on_circle && rest >= 0.0) {
+        const double sr = sqrt(rest);
+        const double tm = C[2] - sr, tp = C[2] + sr;
+        /* the sign that satisfies the plane equation (t - Cz) Dz = xy */
+        tsq = fabs((tm - C[2]) * D[2] - xy) <= fabs((tp - C[2]) * D[2] - xy) ? tm : tp;
+        err_sq = C[3] * C[3] / fmax(sr, 1e-300);
+    }
+    if (err_div == INFINITY && err_sq == INFINITY) return 0;
+    *t = err_sq < err_div ? tsq : (xy + C[2] * D[2]) / D[2];
     if (Fout) *Fout = (double)F_ld(c, u);
     return 1;
 }
@@ -313,13 +336,13 @@ static int exact_hit(const curve_t *c, double tmax, double *t_out, double *u_out
         eval(c, roots[i], Cu, Du);
         const double dn = sqrt(Du[0] * Du[0] + Du[1] * Du[1] + Du[2] * Du[2]);
         if (dn <= 1e-12 * (scale + 1e-300)) continue;      /* cusp: F vanishes with C' */
-        if (!disc_t(c, roots[i], &t, NULL)) continue;
+        if (!disc_t(c, roots[i], 1, &t, NULL)) continue;
         if (t >= 0.0 && t < tmax && t < best) { best = t; bu = roots[i]; kind = 1; }
     }
     /* end caps */
     for (int e = 0; e < 2; ++e) {
         double t, Fv;
-        if (!disc_t(c, (double)e, &t, &Fv)) continue;
+        if (!disc_t(c, (double)e, 0, &t, &Fv)) continue;
         if (Fv <= 0.0 && t >= 0.0 && t < tmax && t < best) { best = t; bu = (double)e; kind = 2 + e; }
     }
     *t_out = best;

@@ -285,3 +285,269 @@ def gentle_valid_curves(n: int, seed: int = SEED_BASE + 21,
     rays = pack_rays(O, D, np.full(n, 100.0))
     return Workload(f"gentle_valid_{n}", rays, fibers, None, None, 22,
                     meta={"u0": u0, "offset_over_r": off})
+
+
+# ---------------------------------------------------------------------------
+# Workload 3: hair-like precision stress
+# ---------------------------------------------------------------------------
+
+def _rotate_towards(v, axis_vec, angle):
+    """Rotate unit vectors v by ``angle`` about the unit axes ``axis_vec``."""
+    c, s = np.cos(angle)[:, None], np.sin(angle)[:, None]
+    return v * c + np.cross(axis_vec, v) * s + axis_vec * np.sum(axis_vec * v, axis=1, keepdims=True) * (1 - c)
+
+
+def hair_strands(n_strands: int = 100_000, seed: int = SEED_BASE + 3, offset: float = 1000.0,
+                 r_root: float = 1e-4, r_tip: float = 2e-5, segments: int = 8):
+    """Control points (n_strands * segments, 4, 4) float64 of hair strands:
+    knots K_0..K_8 with chord 1/8 (strand length ~1), roots uniform on
+    [0,1]^2 x {0}, growth direction a smooth random walk turning at most 20
+    degrees per knot; Catmull-Rom tangents (one-sided at the ends) turned into
+    C1 cubic Bezier segments; radius linear along the strand from r_root to
+    r_tip; every coordinate offset by ``offset`` before rounding to float32."""
+    rng = np.random.default_rng(seed)
+    n = int(n_strands)
+    K = np.empty((n, segments + 1, 3))
+    K[:, 0, :2] = rng.uniform(0, 1, (n, 2))
+    K[:, 0, 2] = 0.0
+    d = unit_vectors(rng, n)
+    d[:, 2] = np.abs(d[:, 2]) + 0.5
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    step = 1.0 / segments
+    for k in range(1, segments + 1):
+        K[:, k] = K[:, k - 1] + step * d
+        axis = unit_vectors(rng, n)
+        axis -= np.sum(axis * d, axis=1, keepdims=True) * d
+        axis /= np.linalg.norm(axis, axis=1, keepdims=True)
+        d = _rotate_towards(d, axis, np.radians(rng.uniform(0, 20, n)))
+    T = np.empty_like(K)
+    T[:, 1:-1] = 0.5 * (K[:, 2:] - K[:, :-2])
+    T[:, 0] = K[:, 1] - K[:, 0]
+    T[:, -1] = K[:, -1] - K[:, -2]
+    P = np.empty((n, segments, 4, 4))
+    P[:, :, 0, :3] = K[:, :-1]
+    P[:, :, 1, :3] = K[:, :-1] + T[:, :-1] / 3
+    P[:, :, 2, :3] = K[:, 1:] - T[:, 1:] / 3
+    P[:, :, 3, :3] = K[:, 1:]
+    s0 = np.arange(segments) / segments
+    r0 = r_root + (r_tip - r_root) * s0
+    r1 = r_root + (r_tip - r_root) * (s0 + 1.0 / segments)
+    P[:, :, :, 3] = (r0[:, None] + (np.arange(4) / 3.0)[None, :] * (r1 - r0)[:, None])[None]
+    P[:, :, :, :3] += offset
+    return P.reshape(n * segments, 4, 4)
+
+
+def hair_precision(n_rays: int = 1 << 24, n_strands: int = 100_000, depth: int = 9,
+                   seed: int = SEED_BASE + 3, grazing_fraction: float = 0.1,
+                   rho: float = 0.25, chunk: int = 1 << 21) -> Workload:
+    """Rays aimed at uniformly chosen hair segments and parameters u0, from
+    C(u0) + rho * s (s uniform on the sphere, rho = 0.25): 90 % regular rays
+    displaced sideways by N(0, (1.4826 r)^2), 10 % grazing rays displaced by
+    (1 + delta) r with delta ~ U[-1e-3, 1e-3], both along the direction
+    normal to the view vector and the tangent. The origin is rounded to
+    float32 first, then D = target - O is formed in float64 and rounded.
+    Pairs are (ray i, its target segment) through pair_fiber."""
+    P = hair_strands(n_strands, seed)
+    fibers = pack_fibers(P)
+    P32 = unpack_fibers(fibers)
+    rng = np.random.default_rng(seed + 7)
+    n = int(n_rays)
+    seg = rng.integers(0, P32.shape[0], n).astype(np.int32)
+    rays = np.empty((RAY_ROWS, n), np.float32)
+    graze = np.zeros(n, bool)
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        m = b - a
+        Pp = P32[seg[a:b]]
+        u0 = rng.uniform(0, 1, m)
+        C = bernstein_point(Pp, u0)
+        Tg = bernstein_tangent(Pp, u0)[:, :3]
+        O = C[:, :3] + rho * unit_vectors(rng, m)
+        O32 = O.astype(np.float32).astype(np.float64)
+        view = C[:, :3] - O32
+        side = np.cross(view, Tg)
+        side /= np.maximum(np.linalg.norm(side, axis=1, keepdims=True), 1e-300)
+        g = rng.uniform(0, 1, m) < grazing_fraction
+        off = rng.standard_normal(m) * 1.4826
+        sign = np.where(rng.uniform(0, 1, m) < 0.5, -1.0, 1.0)
+        off = np.where(g, sign * (1.0 + rng.uniform(-1e-3, 1e-3, m)), off) * C[:, 3]
+        target = C[:, :3] + off[:, None] * side
+        D = target - O32
+        rays[0:3, a:b] = O32.T
+        rays[3:6, a:b] = D.T
+        rays[6, a:b] = 100.0
+        graze[a:b] = g
+    return Workload(f"hair_{n}", rays, fibers, None, seg, depth, meta={"grazing": graze})
+
+
+# ---------------------------------------------------------------------------
+# Workload 4: batched uneven scenes with per-segment adaptive depth
+# ---------------------------------------------------------------------------
+
+def adaptive_depth(P: np.ndarray, samples: int = 65, chunk: int = 1 << 14) -> np.ndarray:
+    """d = clamp(ceil(log2(kappa * len / r)), 2, 22) per curve: kappa is the
+    largest curvature |C' x C''| / |C'|^3 over ``samples`` parameters, len the
+    length of the polyline through those samples, r the smallest radius
+    coefficient (kappa = 0 gives depth 2). Evaluated in float32."""
+    u = np.linspace(0, 1, samples, dtype=np.float32)[None, :]
+    out = np.empty(P.shape[0], np.uint8)
+    for s0 in range(0, P.shape[0], chunk):
+        Q = P[s0:s0 + chunk, :, :3].astype(np.float32)
+        a1 = 3 * (Q[:, 1] - Q[:, 0])
+        a2 = 3 * (Q[:, 2] - 2 * Q[:, 1] + Q[:, 0])
+        a3 = Q[:, 3] - 3 * Q[:, 2] + 3 * Q[:, 1] - Q[:, 0]
+        X, T, S = [], [], []
+        for c in range(3):
+            A0, A1, A2, A3 = (Q[:, 0, c][:, None], a1[:, c][:, None], a2[:, c][:, None], a3[:, c][:, None])
+            X.append(A0 + u * (A1 + u * (A2 + u * A3)))
+            T.append(A1 + u * (2 * A2 + 3 * u * A3))
+            S.append(2 * A2 + 6 * u * A3)
+        seg = np.sqrt(sum(np.diff(x, axis=1) ** 2 for x in X))
+        length = seg.sum(axis=1)
+        cx = T[1] * S[2] - T[2] * S[1]
+        cy = T[2] * S[0] - T[0] * S[2]
+        cz = T[0] * S[1] - T[1] * S[0]
+        num = np.sqrt(cx * cx + cy * cy + cz * cz)
+        t2 = T[0] * T[0] + T[1] * T[1] + T[2] * T[2]
+        den = t2 * np.sqrt(t2)
+        kappa = np.max(np.where(den > 0, num / np.maximum(den, 1e-30), 0.0), axis=1).astype(np.float64)
+        r = np.maximum(P[s0:s0 + chunk, :, 3].min(axis=1), 1e-30)
+        with np.errstate(divide="ignore"):
+            d = np.ceil(np.log2(np.maximum(kappa * length / r, 1e-300)))
+        d = np.where(kappa > 0, d, 2)
+        out[s0:s0 + chunk] = np.clip(d, 2, 22)
+    return out
+
+
+def curved_scene(n_pairs: int, seed: int) -> Workload:
+    """One scene: curved random-walk fibers (step 0.1, linear taper in
+    [0.001, 0.01]) with rays aimed as in ``straight_and_curved``, identity
+    pairing, per-pair adaptive depth."""
+    rng = np.random.default_rng(seed)
+    n = int(n_pairs)
+    P = np.empty((n, 4, 4))
+    p0 = rng.uniform(0.0, 1.0, (n, 3))
+    steps = 0.1 * np.stack([unit_vectors(rng, n) for _ in range(3)], axis=1)
+    P[:, :, :3] = np.concatenate([p0[:, None, :], p0[:, None, :] + np.cumsum(steps, axis=1)], axis=1)
+    P[:, :, 3] = linear_taper(rng.uniform(0.001, 0.01, n), rng.uniform(0.001, 0.01, n))
+    fibers = pack_fibers(P)
+    P32 = unpack_fibers(fibers)
+    O, D, u0, off = _aim_rays(rng, P32, 3.0, 1.4826)
+    rays = pack_rays(O, D, np.full(n, 100.0))
+    return Workload(f"scene_{seed}", rays, fibers, None, None, 22, adaptive_depth(P32))
+
+
+def batched_scenes(n_scenes: int = 256, seed: int = SEED_BASE + 4,
+                   lo_log2: float = 10.0, hi_log2: float = 18.0):
+    """``n_scenes`` independent scenes with round(2^U(10, 18)) pairs each
+    (seed + 1000 s for scene s)."""
+    rng = np.random.default_rng(seed)
+    counts = np.round(2.0 ** rng.uniform(lo_log2, hi_log2, n_scenes)).astype(np.int64)
+    return [curved_scene(int(c), seed + 1000 * s) for s, c in enumerate(counts)]
+
+
+# ---------------------------------------------------------------------------
+# Workload 5: degenerate geometry
+# ---------------------------------------------------------------------------
+
+def _random_rotations(rng, n):
+    """n uniformly random rotation matrices (n, 3, 3)."""
+    q = rng.standard_normal((n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    w, x, y, z = q.T
+    return np.stack([
+        np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)], axis=1),
+        np.stack([2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)], axis=1),
+        np.stack([2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)], axis=1),
+    ], axis=1)
+
+
+def degenerate_geometry(n_pairs: int = 1 << 22, seed: int = SEED_BASE + 5,
+                        depth_lo: int = 16, depth_hi: int = 22) -> Workload:
+    """Four families of equal size: (0) cusps, p1 and p2 mirrored so that
+    C'(1/2) = 0; (1) evenly spaced collinear points jittered by 1e-6 N(0, I);
+    (2) zero-length end tangents (p1 = p0 and/or p2 = p3) on random walks;
+    (3) radius ratios up to 1000:1. Half of the rays run along the chord (from
+    one unit before an end, offset sideways by U[0, 1.5 r_max], so many enter
+    through an end cap); the other half cross it perpendicularly. A quarter of
+    all rays use an exactly axis-aligned chord (no rotation) with an exactly
+    axis-aligned direction, so that plane normals and axes meet the ray frame
+    with exact zeros. Depth is uniform in [depth_lo, depth_hi] per pair."""
+    rng = np.random.default_rng(seed)
+    n = int(n_pairs)
+    fam = np.arange(n) % 4
+    P = np.empty((n, 4, 4))
+    # family 0: cusp in the xy-plane, chord along x
+    L = rng.uniform(0.1, 1.0, n)
+    h = rng.uniform(0.05, 0.5, n) * L
+    z = np.zeros(n)
+    cusp = np.stack([np.stack([z, z, z], 1), np.stack([L, h, z], 1), np.stack([z, h, z], 1),
+                     np.stack([L, z, z], 1)], axis=1)
+    # family 1: near-collinear along x
+    k = np.arange(4)[None, :, None] / 3.0
+    col = k * np.stack([L, z, z], 1)[:, None, :] + 1e-6 * rng.standard_normal((n, 4, 3))
+    # family 2: random walk with zero end tangents, chord re-aligned to x
+    steps = 0.1 * rng.standard_normal((n, 3, 3)) / np.sqrt(3)
+    walk = np.concatenate([np.zeros((n, 1, 3)), np.cumsum(steps, axis=1)], axis=1)
+    which = rng.integers(0, 3, n)
+    zt = walk.copy()
+    zt[which != 1, 1] = zt[which != 1, 0]
+    zt[which != 0, 2] = zt[which != 0, 3]
+    # family 3: gentle curve with a steep taper
+    gent = k * np.stack([L, z, z], 1)[:, None, :]
+    gent[:, 1:3, 1] += rng.uniform(-0.1, 0.1, (n, 2)) * L[:, None]
+    shapes = np.where((fam == 0)[:, None, None], cusp,
+             np.where((fam == 1)[:, None, None], col,
+             np.where((fam == 2)[:, None, None], zt, gent)))
+    # radii
+    rmax = rng.uniform(0.001, 0.05, n)
+    rho = np.exp(rng.uniform(0, np.log(1000.0), n))
+    r_lin = linear_taper(rmax, rmax / rho)
+    r_flat = np.repeat(rng.uniform(0.001, 0.02, n)[:, None], 4, axis=1)
+    radii = np.where((fam == 3)[:, None], r_lin, r_flat)
+    # placement: a quarter of the pairs keep the exact axis-aligned chord
+    exact = (np.arange(n) // 4) % 4 == 0
+    Rm = _random_rotations(rng, n)
+    Rm[exact] = np.eye(3)
+    shift = np.where(exact[:, None], np.round(rng.uniform(0, 1, (n, 3)) * 64) / 64,
+                     rng.uniform(0, 1, (n, 3)))
+    P[:, :, :3] = np.einsum("nij,nkj->nki", Rm, shapes) + shift[:, None, :]
+    P[:, :, 3] = radii
+    fibers = pack_fibers(P)
+    P32 = unpack_fibers(fibers)
+    # rays
+    parallel = rng.uniform(0, 1, n) < 0.5
+    chord = P32[:, 3, :3] - P32[:, 0, :3]
+    clen = np.linalg.norm(chord, axis=1)
+    chat = chord / np.maximum(clen, 1e-300)[:, None]
+    flip = rng.uniform(0, 1, n) < 0.5
+    side = unit_vectors(rng, n)
+    side -= np.sum(side * chat, axis=1, keepdims=True) * chat
+    side /= np.maximum(np.linalg.norm(side, axis=1, keepdims=True), 1e-300)
+    rmx = P32[:, :, 3].max(axis=1)
+    # parallel: from one unit before an end, along +/- chord
+    start = np.where(flip[:, None], P32[:, 3, :3] + chat, P32[:, 0, :3] - chat)
+    O_par = start + side * (rng.uniform(0, 1.5, n) * rmx)[:, None]
+    D_par = np.where(flip[:, None], -chat, chat)
+    # perpendicular: aimed at C(u0) from 3 units away along a direction normal to the chord
+    u0 = rng.uniform(0, 1, n)
+    C = bernstein_point(P32, u0)
+    perp = np.cross(chat, side)
+    off = rng.standard_normal(n) * 1.4826 * C[:, 3]
+    target = C[:, :3] + off[:, None] * side
+    O_perp = target + 3.0 * perp
+    D_perp = -perp
+    # exact axis-aligned cases: chord along x, direction exactly +-z or +-x
+    ex_par = exact & parallel
+    ex_perp = exact & ~parallel
+    D_par[ex_par] = np.where(flip[ex_par, None], [-1.0, 0.0, 0.0], [1.0, 0.0, 0.0])
+    D_perp[ex_perp] = [0.0, 0.0, -1.0]
+    O_perp[ex_perp] = np.stack([target[ex_perp, 0], target[ex_perp, 1], target[ex_perp, 2] + 3.0], axis=1)
+    O = np.where(parallel[:, None], O_par, O_perp)
+    D = np.where(parallel[:, None], D_par, D_perp)
+    O32 = O.astype(np.float32).astype(np.float64)
+    D = np.where(exact[:, None], D, D + (O - O32) * 0)   # directions are exact unit axes where exact
+    rays = pack_rays(O32, D, np.full(n, 100.0))
+    pd = rng.integers(depth_lo, depth_hi + 1, n).astype(np.uint8)
+    return Workload(f"degenerate_{n}", rays, fibers, None, None, depth_hi, pd,
+                    meta={"family": fam, "parallel": parallel, "exact_axes": exact})
