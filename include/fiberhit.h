@@ -44,6 +44,12 @@ extern "C" {
 #define FI_ERR_HIP       (-3)   /* the HIP runtime reported an error at launch        */
 #define FI_ERR_WORKSPACE (-4)   /* workspace pointer missing or too small             */
 
+/* Flags. */
+/* FI_FP64_REFINE: for pairs of depth > 16, run the traversal with every
+ * pruning test enlarged by a bound on its FP32 rounding error, then solve for
+ * the hit on the swept-disc surface in FP64 (see fiber_intersect_pairs). */
+#define FI_FP64_REFINE   (1u << 0)
+
 /* Largest subdivision depth: one bit per level in 32-bit integers and an
  * integer parametric position below 2^23 (Section 3.3, interval conversion). */
 #define FI_MAX_DEPTH 23
@@ -76,13 +82,27 @@ const char *fi_strerror(int status);
  *   depth                          0 .. FI_MAX_DEPTH (checked even when pair_depth
  *                                  is given).
  *   n_pairs                        >= 0; 0 enqueues nothing and returns FI_OK.
- *   flags                          reserved, must be 0.
+ *   flags                          0 or FI_FP64_REFINE.
  *   t_out, u_out, hit_out          n_pairs each. On a miss: t = +inf, u = NaN, hit = 0.
+ *   t64_out, u64_out               n_pairs doubles each; required with
+ *                                  FI_FP64_REFINE, ignored (may be NULL) without.
  *   stream                         hipStream_t or NULL.
  *
- * Errors: FI_ERR_NULL when rays, fibers or an output is NULL with n_pairs > 0;
- * FI_ERR_RANGE for negative counts, strides below the counts, a depth outside
- * [0, 23], nonzero flags, or an identity pairing longer than a table;
+ * FI_FP64_REFINE: the method's leaf cylinders converge to the surface swept by
+ * a disc of radius r(u) centred on C(u) in the plane normal to C'(u)
+ * (Section 3.2: the limit surface maps the intersection to the closest point
+ * on the curve). For each pair of depth > 16 whose conservative FP32 search
+ * reports a hit, a second kernel solves <P - C(u), C'(u)> = 0,
+ * |P - C(u)| = r(u) for the entry point P = O + t D/|D| in FP64 near the FP32
+ * leaf, with the end discs as candidates. All five outputs then describe that
+ * surface hit (hit = 0, t = +inf when no surface point lies near the leaf).
+ * Pairs of depth <= 16 keep the plain method's results; their t64/u64 are the
+ * float results widened.
+ *
+ * Errors: FI_ERR_NULL when rays, fibers or an output is NULL with n_pairs > 0
+ * (t64_out/u64_out only with FI_FP64_REFINE); FI_ERR_RANGE for negative
+ * counts, strides below the counts, a depth outside [0, 23], unknown flags,
+ * an identity pairing longer than a table, or n_pairs >= 2^31 - 64;
  * FI_ERR_HIP when the launch fails. Nothing is enqueued on error.
  */
 int fiber_intersect_pairs(const float *rays, int64_t ray_stride, int64_t n_rays,
@@ -91,6 +111,7 @@ int fiber_intersect_pairs(const float *rays, int64_t ray_stride, int64_t n_rays,
                           const uint8_t *pair_depth, int32_t depth, int64_t n_pairs,
                           uint32_t flags,
                           float *t_out, float *u_out, uint8_t *hit_out,
+                          double *t64_out, double *u64_out,
                           void *stream);
 
 /*
@@ -104,7 +125,8 @@ int fiber_intersect_pairs(const float *rays, int64_t ray_stride, int64_t n_rays,
  * sibling) and the level of the leaf that was hit (-1 on a miss). These are
  * the units of the algorithmic work model.
  *
- * Errors: as fiber_intersect_pairs; counts_out must not be NULL.
+ * Errors: as fiber_intersect_pairs; counts_out must not be NULL and flags
+ * must be 0.
  */
 int fiber_intersect_counts(const float *rays, int64_t ray_stride, int64_t n_rays,
                            const float *fibers, int64_t fiber_stride, int64_t n_fibers,
@@ -113,6 +135,85 @@ int fiber_intersect_counts(const float *rays, int64_t ray_stride, int64_t n_rays
                            uint32_t flags,
                            float *t_out, float *u_out, uint8_t *hit_out,
                            int32_t *counts_out, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Many independent problems in one launch                                  */
+/* ------------------------------------------------------------------------ */
+
+/* One problem: the arguments of one fiber_intersect_pairs call (flags 0).
+ * All pointers are device pointers owned by the caller. */
+typedef struct fi_scene {
+    const float *rays;   int64_t ray_stride;   int64_t n_rays;
+    const float *fibers; int64_t fiber_stride; int64_t n_fibers;
+    const int32_t *pair_ray; const int32_t *pair_fiber; const uint8_t *pair_depth;
+    int32_t depth;       int64_t n_pairs;
+    float *t_out; float *u_out; uint8_t *hit_out;
+} fi_scene;
+
+/* Launch tuning of the persistent traversal (not part of the method):
+ *   refill          refill a wave's finished lanes once at least this many
+ *                   (1..64) are free; default 32;
+ *   waves_per_simd  cap on resident waves per SIMD (0 = as many as fit);
+ *   root_in_lds     1: keep each lane's root node in LDS, 0: in registers.
+ * Results never depend on the tuning. */
+typedef struct fi_tuning {
+    int32_t refill;
+    int32_t waves_per_simd;
+    int32_t root_in_lds;
+} fi_tuning;
+
+/* Bytes of device workspace fiber_intersect_batched needs for n_scenes. */
+size_t fiber_batched_workspace_bytes(int32_t n_scenes);
+
+/*
+ * fiber_intersect_batched -- all pairs of n_scenes independent problems in
+ * one persistent launch.
+ *
+ * Operation: for every scene k, exactly what fiber_intersect_pairs computes
+ * for scenes[k] (same per-pair routine; results are bitwise identical to a
+ * separate call per scene). Pairs of all scenes are numbered consecutively
+ * and pulled by the waves of one launch from a shared queue, so small scenes
+ * do not leave the GPU idle.
+ *
+ * Arguments: scenes is a host array of n_scenes descriptors (the library
+ * copies it before returning); tuning may be NULL (defaults); flags must be 0;
+ * workspace is caller-owned device memory of at least
+ * fiber_batched_workspace_bytes(n_scenes) bytes, which must not be used by
+ * another call that is still in flight.
+ *
+ * Errors: FI_ERR_NULL (scenes NULL or a NULL pointer inside a scene),
+ * FI_ERR_RANGE (bad counts, strides, depths, tuning, flags, more than 2^31-64
+ * pairs in total or a scene table over 1 MiB), FI_ERR_WORKSPACE, FI_ERR_HIP.
+ */
+int fiber_intersect_batched(const fi_scene *scenes, int32_t n_scenes, const fi_tuning *tuning,
+                            uint32_t flags, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Plans: the scene table is uploaded once into device memory the plan owns,
+ * and the launch (a queue reset kernel and the persistent traversal) is
+ * captured into a HIP graph that fiber_batch_plan_launch replays on any
+ * stream. Creating and destroying a plan allocates and frees device memory;
+ * launching does not. One plan must not be launched on two streams at once.
+ * The scenes' device buffers must outlive the plan.
+ */
+typedef struct fi_batch_plan fi_batch_plan;
+
+int fiber_batch_plan_create(const fi_scene *scenes, int32_t n_scenes, const fi_tuning *tuning,
+                            uint32_t flags, fi_batch_plan **plan_out);
+int fiber_batch_plan_launch(fi_batch_plan *plan, void *stream);
+int fiber_batch_plan_tuning(const fi_batch_plan *plan, fi_tuning *tuning_out);
+int fiber_batch_plan_destroy(fi_batch_plan *plan);
+
+/*
+ * fiber_batch_autotune -- time fiber_intersect_batched on these scenes over a
+ * grid of tunings (refill 8..48, waves per SIMD 2..max, root in LDS or
+ * registers), each `repeats` times after one warm-up, and return the fastest
+ * in *best (and its time in *best_ms if not NULL). Overwrites the scenes'
+ * outputs. Blocks the host until the timing runs finish.
+ */
+int fiber_batch_autotune(const fi_scene *scenes, int32_t n_scenes, uint32_t flags, void *workspace,
+                         size_t workspace_bytes, void *stream, int32_t repeats,
+                         fi_tuning *best, float *best_ms);
 
 #ifdef __cplusplus
 }

@@ -16,6 +16,7 @@ from . import build_lib
 
 FI_OK = 0
 FI_MAX_DEPTH = 23
+FI_FP64_REFINE = 1
 
 _lib = None
 
@@ -34,7 +35,7 @@ def lib():
         L = C.CDLL(build_lib.LIB)
         i64, vp, u32, i32 = C.c_int64, C.c_void_p, C.c_uint32, C.c_int32
         common = [vp, i64, i64, vp, i64, i64, vp, vp, vp, i32, i64, u32, vp, vp, vp]
-        L.fiber_intersect_pairs.argtypes = common + [vp]
+        L.fiber_intersect_pairs.argtypes = common + [vp, vp, vp]
         L.fiber_intersect_pairs.restype = C.c_int
         L.fiber_intersect_counts.argtypes = common + [vp, vp]
         L.fiber_intersect_counts.restype = C.c_int
@@ -46,7 +47,10 @@ def lib():
 
 
 def exported_symbols():
-    return ["fi_version", "fi_strerror", "fiber_intersect_pairs", "fiber_intersect_counts"]
+    return ["fi_version", "fi_strerror", "fiber_intersect_pairs", "fiber_intersect_counts",
+            "fiber_batched_workspace_bytes", "fiber_intersect_batched", "fiber_batch_plan_create",
+            "fiber_batch_plan_launch", "fiber_batch_plan_tuning", "fiber_batch_plan_destroy",
+            "fiber_batch_autotune"]
 
 
 def _check(status: int):
@@ -86,13 +90,14 @@ def intersect_pairs(rays: torch.Tensor, fibers: torch.Tensor, depth: int = 9,
                     pair_ray: Optional[torch.Tensor] = None,
                     pair_fiber: Optional[torch.Tensor] = None,
                     pair_depth: Optional[torch.Tensor] = None,
-                    out=None, counts: bool = False, stream=None):
+                    out=None, counts: bool = False, refine: bool = False, stream=None):
     """Nearest hit (t, u, hit) of every (ray, fiber) pair at subdivision depth
     ``depth`` (or per-pair ``pair_depth``). See ``fiber_intersect_pairs``.
 
     rays: (7, n_rays) float32; fibers: (16, n_fibers) float32; indices int32.
     Returns (t, u, hit) device tensors, plus an (n, 4) int32 tensor of node
-    tests / splits / backtracks / leaf level when ``counts`` is set."""
+    tests / splits / backtracks / leaf level when ``counts`` is set, or the
+    float64 (t64, u64) of the FP64 surface refinement when ``refine`` is set."""
     rs = _table(rays, 7, "rays")
     fs = _table(fibers, 16, "fibers")
     pr = _index(pair_ray, torch.int32, "pair_ray")
@@ -113,17 +118,183 @@ def intersect_pairs(rays: torch.Tensor, fibers: torch.Tensor, depth: int = 9,
         hit = torch.empty(n, dtype=torch.uint8, device=dev)
     else:
         t, u, hit = out
+    if counts and refine:
+        raise ValueError("counts and refine are separate passes")
     cn = torch.empty((n, 4), dtype=torch.int32, device=dev) if counts else None
+    flags = FI_FP64_REFINE if refine else 0
     args = [_ptr(rays), rs, rays.shape[1], _ptr(fibers), fs, fibers.shape[1],
-            _ptr(pr), _ptr(pf), _ptr(pd), int(depth), n, 0,
+            _ptr(pr), _ptr(pf), _ptr(pd), int(depth), n, flags,
             _ptr(t), _ptr(u), _ptr(hit)]
     if counts:
         _check(lib().fiber_intersect_counts(*args, _ptr(cn), _stream(stream)))
         return t, u, hit, cn
-    _check(lib().fiber_intersect_pairs(*args, _stream(stream)))
+    if refine:
+        t64 = torch.empty(n, dtype=torch.float64, device=dev)
+        u64 = torch.empty(n, dtype=torch.float64, device=dev)
+        _check(lib().fiber_intersect_pairs(*args, _ptr(t64), _ptr(u64), _stream(stream)))
+        return t, u, hit, t64, u64
+    _check(lib().fiber_intersect_pairs(*args, None, None, _stream(stream)))
     return t, u, hit
 
 
 def raw_call(name: str, *args):
     """Call a C-ABI entry point with already-marshalled arguments (tests)."""
     return getattr(lib(), name)(*args)
+
+
+# ---------------------------------------------------------------------------
+# many problems in one launch
+# ---------------------------------------------------------------------------
+
+class FiScene(C.Structure):
+    _fields_ = [("rays", C.c_void_p), ("ray_stride", C.c_int64), ("n_rays", C.c_int64),
+                ("fibers", C.c_void_p), ("fiber_stride", C.c_int64), ("n_fibers", C.c_int64),
+                ("pair_ray", C.c_void_p), ("pair_fiber", C.c_void_p), ("pair_depth", C.c_void_p),
+                ("depth", C.c_int32), ("n_pairs", C.c_int64),
+                ("t_out", C.c_void_p), ("u_out", C.c_void_p), ("hit_out", C.c_void_p)]
+
+
+class FiTuning(C.Structure):
+    _fields_ = [("refill", C.c_int32), ("waves_per_simd", C.c_int32), ("root_in_lds", C.c_int32)]
+
+    def as_dict(self):
+        return {"refill": self.refill, "waves_per_simd": self.waves_per_simd,
+                "root_in_lds": self.root_in_lds}
+
+
+def _batched_lib():
+    L = lib()
+    if not getattr(L, "_batched_ready", False):
+        vp = C.c_void_p
+        L.fiber_batched_workspace_bytes.argtypes = [C.c_int32]
+        L.fiber_batched_workspace_bytes.restype = C.c_size_t
+        L.fiber_intersect_batched.argtypes = [C.POINTER(FiScene), C.c_int32, C.POINTER(FiTuning),
+                                              C.c_uint32, vp, C.c_size_t, vp]
+        L.fiber_intersect_batched.restype = C.c_int
+        L.fiber_batch_plan_create.argtypes = [C.POINTER(FiScene), C.c_int32, C.POINTER(FiTuning),
+                                              C.c_uint32, C.POINTER(vp)]
+        L.fiber_batch_plan_create.restype = C.c_int
+        L.fiber_batch_plan_launch.argtypes = [vp, vp]
+        L.fiber_batch_plan_launch.restype = C.c_int
+        L.fiber_batch_plan_destroy.argtypes = [vp]
+        L.fiber_batch_plan_destroy.restype = C.c_int
+        L.fiber_batch_plan_tuning.argtypes = [vp, C.POINTER(FiTuning)]
+        L.fiber_batch_plan_tuning.restype = C.c_int
+        L.fiber_batch_autotune.argtypes = [C.POINTER(FiScene), C.c_int32, C.c_uint32, vp, C.c_size_t,
+                                           vp, C.c_int32, C.POINTER(FiTuning), C.POINTER(C.c_float)]
+        L.fiber_batch_autotune.restype = C.c_int
+        L._batched_ready = True
+    return L
+
+
+class Problem:
+    """One problem of a batch: device tensors in the layout of intersect_pairs,
+    with its own outputs (allocated here)."""
+
+    def __init__(self, rays, fibers, depth=9, pair_ray=None, pair_fiber=None, pair_depth=None):
+        self.rays, self.fibers = rays, fibers
+        self.pair_ray = _index(pair_ray, torch.int32, "pair_ray")
+        self.pair_fiber = _index(pair_fiber, torch.int32, "pair_fiber")
+        self.pair_depth = _index(pair_depth, torch.uint8, "pair_depth")
+        self.depth = int(depth)
+        if self.pair_ray is not None:
+            n = self.pair_ray.shape[0]
+        elif self.pair_fiber is not None:
+            n = self.pair_fiber.shape[0]
+        elif self.pair_depth is not None:
+            n = self.pair_depth.shape[0]
+        else:
+            n = min(rays.shape[1], fibers.shape[1])
+        self.n = n
+        dev = rays.device
+        self.t = torch.empty(n, dtype=torch.float32, device=dev)
+        self.u = torch.empty(n, dtype=torch.float32, device=dev)
+        self.hit = torch.empty(n, dtype=torch.uint8, device=dev)
+
+    def scene(self):
+        rs = _table(self.rays, 7, "rays")
+        fs = _table(self.fibers, 16, "fibers")
+        return FiScene(self.rays.data_ptr(), rs, self.rays.shape[1], self.fibers.data_ptr(), fs,
+                       self.fibers.shape[1],
+                       None if self.pair_ray is None else self.pair_ray.data_ptr(),
+                       None if self.pair_fiber is None else self.pair_fiber.data_ptr(),
+                       None if self.pair_depth is None else self.pair_depth.data_ptr(),
+                       self.depth, self.n, self.t.data_ptr(), self.u.data_ptr(), self.hit.data_ptr())
+
+
+def _scene_array(problems):
+    arr = (FiScene * len(problems))()
+    for k, p in enumerate(problems):
+        arr[k] = p.scene()
+    return arr
+
+
+def _tuning(t):
+    if t is None:
+        return None
+    if isinstance(t, FiTuning):
+        return C.byref(t)
+    return C.byref(FiTuning(int(t["refill"]), int(t["waves_per_simd"]), int(t["root_in_lds"])))
+
+
+def workspace_for(n_problems: int, device="cuda"):
+    nbytes = _batched_lib().fiber_batched_workspace_bytes(int(n_problems))
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def intersect_batched(problems, tuning=None, workspace=None, stream=None):
+    """All pairs of all problems in one persistent launch (results land in
+    each Problem's t, u, hit)."""
+    L = _batched_lib()
+    arr = _scene_array(problems)
+    if workspace is None:
+        workspace = workspace_for(len(problems), problems[0].rays.device)
+    _check(L.fiber_intersect_batched(arr, len(problems), _tuning(tuning), 0,
+                                     C.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                     _stream(stream)))
+    return workspace
+
+
+class BatchPlan:
+    """A batch captured once into a HIP graph; ``launch`` replays it."""
+
+    def __init__(self, problems, tuning=None):
+        L = _batched_lib()
+        self.problems = problems
+        arr = _scene_array(problems)
+        h = C.c_void_p()
+        _check(L.fiber_batch_plan_create(arr, len(problems), _tuning(tuning), 0, C.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(_batched_lib().fiber_batch_plan_launch(self._h, _stream(stream)))
+
+    def tuning(self):
+        t = FiTuning()
+        _check(_batched_lib().fiber_batch_plan_tuning(self._h, C.byref(t)))
+        return t.as_dict()
+
+    def close(self):
+        if self._h:
+            _check(_batched_lib().fiber_batch_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(problems, repeats=2, workspace=None, stream=None):
+    """Fastest tuning for this batch; returns (dict, milliseconds)."""
+    L = _batched_lib()
+    arr = _scene_array(problems)
+    if workspace is None:
+        workspace = workspace_for(len(problems), problems[0].rays.device)
+    best = FiTuning()
+    ms = C.c_float()
+    _check(L.fiber_batch_autotune(arr, len(problems), 0, C.c_void_p(workspace.data_ptr()),
+                                  workspace.numel(), _stream(stream), int(repeats), C.byref(best),
+                                  C.byref(ms)))
+    return best.as_dict(), ms.value

@@ -5,10 +5,13 @@ Bar (per pair, outside the silhouette band):
   * hit flags identical; a pair is in the band when the oracle's flag changes
     between all radius control values scaled by (1 - 1e-4) and (1 + 1e-4);
   * relative t error <= 1e-5 where both report a hit;
-  * |u error| <= 2^-d + 1e-5 + s_u, where u is resolved to one leaf of size
-    2^-d and s_u is how far the oracle's own u moves between the two band
+  * |u error| <= 2^-d + 1e-5 + s_u + c_u, where u is resolved to one leaf of
+    size 2^-d; s_u is how far the oracle's own u moves between the two band
     radii (1 -/+ 1e-4): near a silhouette a ray grazes the surface, the entry
-    t stays well defined but its curve parameter slides along the fiber.
+    t stays well defined but its curve parameter slides along the fiber; c_u
+    = 2^-20 max(1, t) / |C'(u)| is a position error of 16 float32 ulp at the
+    hit mapped through the curve's speed: where the curve stalls (a zero end
+    tangent makes |C'(u)| ~ u near the end) u is only that well determined.
 
 Near ties: the method's result is discontinuous where a pruning or ordering
 comparison is an exact tie (for example a ray that enters a leaf cylinder
@@ -32,7 +35,7 @@ TIE_EPS = 1e-5
 class Band:
     """Silhouette band of the oracle: ``flag`` marks pairs whose hit flag
     changes between the two band radii; ``u_spread`` is how far u moves
-    between them where both hit."""
+    between them where both hit (plus the speed term c_u)."""
 
     def __init__(self, flag, u_spread):
         self.flag = flag
@@ -40,6 +43,22 @@ class Band:
 
     def __getitem__(self, idx):
         return Band(self.flag[idx], self.u_spread[idx])
+
+
+def speed_term(w, t_o, u_o):
+    """c_u = 2^-20 max(1, t) / |C'(u)| at the oracle's hits (0 on misses)."""
+    hit = np.isfinite(t_o)
+    out = np.zeros(t_o.shape)
+    if not hit.any():
+        return out
+    fi = w.pair_fiber if w.pair_fiber is not None else np.arange(t_o.shape[0])
+    P = np.asarray(w.fibers, np.float64).T.reshape(-1, 4, 4)[np.asarray(fi)[hit], :, :3]
+    u = u_o[hit][:, None]
+    v = 1.0 - u
+    d = 3 * (v * v * (P[:, 1] - P[:, 0]) + 2 * u * v * (P[:, 2] - P[:, 1]) + u * u * (P[:, 3] - P[:, 2]))
+    sp = np.linalg.norm(d, axis=1)
+    out[hit] = 2.0 ** -20 * np.maximum(1.0, np.abs(t_o[hit])) / np.maximum(sp, 1e-300)
+    return out
 
 
 def oracle_with_band(w, depth=None, stats=False):
@@ -52,6 +71,7 @@ def oracle_with_band(w, depth=None, stats=False):
                                            w.pair_depth, radius_scale=1 + BAND)
     both = h_lo.astype(bool) & h_hi.astype(bool)
     spread = np.where(both, np.abs(np.where(both, u_lo, 0) - np.where(both, u_hi, 0)), 0.0)
+    spread = spread + speed_term(w, res[0], res[1])
     return res, Band(h_lo != h_hi, spread)
 
 

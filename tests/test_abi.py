@@ -50,13 +50,14 @@ def _call(**kw):
     return binding.lib().fiber_intersect_pairs(
         vp(a["rays"]), a["rs"], a["nr"], vp(a["fibers"]), a["fs"], a["nf"], vp(a["pr"]),
         vp(a["pf"]), vp(a["pd"]), a["depth"], a["n"], a["flags"], vp(a["t"]), vp(a["u"]),
-        vp(a["h"]), None)
+        vp(a["h"]), vp(a.get("t64")), vp(a.get("u64")), None)
 
 
 @pytest.mark.parametrize("kw,code", [
     (dict(depth=24), -2), (dict(depth=-1), -2), (dict(n=-1), -2), (dict(flags=8), -2),
     (dict(rs=4), -2), (dict(fs=4), -2), (dict(n=9), -2),
     (dict(rays=None), -1), (dict(fibers=None), -1), (dict(t=None), -1), (dict(h=None), -1),
+    (dict(flags=1), -1), (dict(flags=1, t64=1), -1), (dict(flags=3, t64=1, u64=1), -2),
 ])
 def test_argument_errors_before_launch(kw, code):
     # these return before any HIP call, so they are safe without a device

@@ -1,0 +1,131 @@
+"""Batched launches: bitwise equal to one plain call per problem."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1811_03374_amd import binding
+from paper_1811_03374_amd import workloads as W
+from parity import compare, oracle_with_band, tie_resolver
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def make_scenes(k=12, seed=5):
+    rng = np.random.default_rng(seed)
+    sizes = [int(x) for x in np.round(2.0 ** rng.uniform(6, 13, k))]
+    if k > 3:
+        sizes[3] = 0      # an empty problem
+    if k > 5:
+        sizes[5] = 1      # a single pair
+    ws = [W.curved_scene(max(n, 1), 1811033744 + 1000 * s) for s, n in enumerate(sizes)]
+    probs = []
+    for w, n in zip(ws, sizes):
+        g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+        probs.append(binding.Problem(g(w.rays[:, :n]) if n else g(w.rays[:, :0]),
+                                     g(w.fibers[:, :n]) if n else g(w.fibers[:, :0]), 22,
+                                     None, None, g(w.pair_depth[:n])))
+    return ws, sizes, probs
+
+
+def plain_reference(probs):
+    out = []
+    for p in probs:
+        if p.n == 0:
+            out.append((np.zeros(0, np.float32),) * 2 + (np.zeros(0, np.uint8),))
+            continue
+        t, u, h = binding.intersect_pairs(p.rays, p.fibers, p.depth, pair_depth=p.pair_depth)
+        torch.cuda.synchronize()
+        out.append((t.cpu().numpy(), u.cpu().numpy(), h.cpu().numpy()))
+    return out
+
+
+def bits(a):
+    return np.ascontiguousarray(a).view(np.uint32 if a.dtype == np.float32 else np.uint8)
+
+
+def assert_same(probs, ref):
+    for p, (t, u, h) in zip(probs, ref):
+        assert np.array_equal(bits(p.t.cpu().numpy()), bits(t))
+        assert np.array_equal(bits(p.u.cpu().numpy()), bits(u))
+        assert np.array_equal(p.hit.cpu().numpy(), h)
+
+
+def clear(probs):
+    for p in probs:
+        p.t.fill_(-1.0); p.u.fill_(-1.0); p.hit.fill_(7)
+
+
+def test_batched_equals_plain_bitwise():
+    ws, sizes, probs = make_scenes()
+    say(f"[batched] {len(probs)} problems, {sum(sizes)} pairs")
+    ref = plain_reference(probs)
+    clear(probs)
+    binding.intersect_batched(probs)
+    torch.cuda.synchronize()
+    assert_same(probs, ref)
+
+
+def test_results_do_not_depend_on_tuning():
+    ws, sizes, probs = make_scenes(seed=9)
+    ref = plain_reference(probs)
+    for t in ({"refill": 8, "waves_per_simd": 2, "root_in_lds": 0},
+              {"refill": 64, "waves_per_simd": 0, "root_in_lds": 1},
+              {"refill": 1, "waves_per_simd": 1, "root_in_lds": 0}):
+        clear(probs)
+        binding.intersect_batched(probs, tuning=t)
+        torch.cuda.synchronize()
+        assert_same(probs, ref)
+
+
+def test_graph_plan_replays():
+    ws, sizes, probs = make_scenes(seed=13)
+    ref = plain_reference(probs)
+    plan = binding.BatchPlan(probs)
+    for rep in range(3):
+        clear(probs)
+        torch.cuda.synchronize()
+        plan.launch()
+        torch.cuda.synchronize()
+        assert_same(probs, ref)
+        x = torch.randn(1000, device=DEV).sum().item()     # eager work between replays
+    plan.close()
+
+
+def test_batched_parity_against_oracle():
+    ws, sizes, probs = make_scenes(k=6, seed=21)
+    binding.intersect_batched(probs)
+    torch.cuda.synchronize()
+    for w, n, p in zip(ws, sizes, probs):
+        if n == 0:
+            continue
+        ws_ = w.subset(np.arange(n))
+        ws_.pair_depth = w.pair_depth[:n]
+        (t_o, u_o, h_o), band = oracle_with_band(ws_)
+        st = compare(p.t.cpu().numpy(), p.u.cpu().numpy(), p.hit.cpu().numpy(), t_o, u_o, h_o,
+                     band, ws_.pair_depth, alt=tie_resolver(ws_))
+        assert st["ok"], st
+
+
+def test_autotune_returns_a_grid_point():
+    ws, sizes, probs = make_scenes(seed=17)
+    best, ms = binding.autotune(probs, repeats=1)
+    say(f"[autotune] {best} {ms:.3f} ms")
+    assert best["refill"] in (8, 16, 24, 32, 48) and best["root_in_lds"] in (0, 1)
+    assert ms > 0
+
+
+def test_batched_argument_errors():
+    ws, sizes, probs = make_scenes(k=3)
+    small = torch.empty(16, dtype=torch.uint8, device=DEV)
+    with pytest.raises(binding.FiberHitError):
+        binding.intersect_batched(probs, workspace=small)
+    with pytest.raises(binding.FiberHitError):
+        binding.intersect_batched(probs, tuning={"refill": 0, "waves_per_simd": 0, "root_in_lds": 1})

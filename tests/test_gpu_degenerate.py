@@ -1,0 +1,92 @@
+"""Degenerate geometry on the GPU: cusps, near-collinear control points, zero
+tangents and 1000:1 tapers, with rays along and across the chord (including
+exactly axis-aligned cases). Curves that break the constraints of Section 3.4
+are reported, not asserted: the paper requires splitting them beforehand."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1811_03374_amd import binding
+from paper_1811_03374_amd import workloads as W
+from parity import compare, oracle_with_band, tie_resolver
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+FAMILIES = ("cusp", "near-collinear", "zero tangent", "steep taper")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def validity(w):
+    P = W.unpack_fibers(w.fibers)
+    return np.array([oracle.cubic_constraints(P[i].reshape(16)) == 31 for i in range(P.shape[0])])
+
+
+@pytest.fixture(scope="module")
+def degenerate():
+    w = W.degenerate_geometry(1 << 15)
+    return w, validity(w)
+
+
+def test_degenerate_plain_against_depth_oracle(degenerate):
+    w, valid = degenerate
+    g = lambda a: torch.from_numpy(a).to(DEV)
+    t, u, h = [o.cpu().numpy() for o in binding.intersect_pairs(
+        g(w.rays), g(w.fibers), 22, pair_depth=g(w.pair_depth))]
+    torch.cuda.synchronize()
+    (t_o, u_o, h_o), band = oracle_with_band(w)
+    alt = tie_resolver(w)
+    for f, name in enumerate(FAMILIES):
+        for val in (True, False):
+            m = (w.meta["family"] == f) & (valid == val)
+            if not m.any():
+                continue
+            idx = np.nonzero(m)[0]
+            st = compare(t[idx], u[idx], h[idx], t_o[idx], u_o[idx], h_o[idx], band[idx],
+                         w.pair_depth[idx], alt=lambda i, idx=idx: alt(int(idx[i])))
+            say(f"[degenerate] {name:15s} valid={val!s:5s} n={m.sum():6d} "
+                f"flag_disagree={st['flag_disagree_rate']:.2e} unresolved={st['unresolved']} "
+                f"max_rel_t={st['max_rel_t']:.2e} tie_resolved={st['tie_resolved']}")
+            if val:
+                assert st["ok"], (name, st)
+    # exact axis-aligned cases (zero plane-normal z, axes parallel to the ray)
+    ex = w.meta["exact_axes"] & valid
+    idx = np.nonzero(ex)[0]
+    st = compare(t[idx], u[idx], h[idx], t_o[idx], u_o[idx], h_o[idx], band[idx],
+                 w.pair_depth[idx], alt=lambda i: alt(int(idx[i])))
+    say(f"[degenerate] exact axes (valid) n={len(idx)} {st}")
+    assert st["ok"], st
+
+
+def test_degenerate_refined_against_exact_oracle(degenerate):
+    w, valid = degenerate
+    g = lambda a: torch.from_numpy(a).to(DEV)
+    t32, u32, h, t64, u64 = [o.cpu().numpy() for o in binding.intersect_pairs(
+        g(w.rays), g(w.fibers), 22, pair_depth=g(w.pair_depth), refine=True)]
+    torch.cuda.synchronize()
+    t_x, u_x, h_x, kind = oracle.intersect_exact(w.rays, w.fibers)
+    _, _, hl, _ = oracle.intersect_exact(w.rays, w.fibers, radius_scale=1 - 1e-4)
+    _, _, hh, _ = oracle.intersect_exact(w.rays, w.fibers, radius_scale=1 + 1e-4)
+    band = hl != hh
+    hg = h.astype(bool)
+    hx = h_x.astype(bool)
+    refined = w.pair_depth > 16          # shallower pairs keep the depth-d result
+    for f, name in enumerate(FAMILIES):
+        for val in (True, False):
+            m = (w.meta["family"] == f) & (valid == val) & ~band & refined
+            if not m.any():
+                continue
+            both = m & hg & hx
+            rel = np.abs(t64[both] - t_x[both]) / t_x[both]
+            rate = float((hg[m] != hx[m]).mean())
+            say(f"[refined]    {name:15s} valid={val!s:5s} n={m.sum():6d} flag_disagree={rate:.2e} "
+                f"max_rel_t={rel.max() if rel.size else 0:.2e} "
+                f"p99.9_rel_t={np.quantile(rel, 0.999) if rel.size else 0:.2e}")
+            if val and name in ("near-collinear", "steep taper"):
+                assert rate == 0.0, name
+                assert rel.max() <= 1e-12, (name, rel.max())
