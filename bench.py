@@ -29,6 +29,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--workload", choices=("straight_and_curved", "batched", "hair"),
+                    default="straight_and_curved",
+                    help="batched: 256 uneven scenes (~13 M pairs, adaptive depth), one graph launch "
+                         "against 256 plain launches; hair: precision stress with error report")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for counter runs: one 256 MiB device copy (calibration), then one launch "
                          "per depth, nothing else")
@@ -58,12 +62,161 @@ def measured_traffic(depth):
     return tr.get("bytes_per_launch", {}).get(str(depth))
 
 
+def _scene(args):
+    from paper_1811_03374_amd import workloads as W
+    n, seed = args
+    return W.curved_scene(n, seed)
+
+
+def _timed(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def bench_batched(args):
+    """256 independent scenes of round(2^U(10, 18)) pairs with per-segment
+    adaptive depth: autotune, then one captured-graph launch against one
+    plain launch per scene, on the same stream."""
+    import numpy as np
+    import torch
+    from concurrent.futures import ProcessPoolExecutor
+    from paper_1811_03374_amd import binding
+    from paper_1811_03374_amd import workloads as W
+
+    rng = np.random.default_rng(W.SEED_BASE + 4)
+    counts = np.round(2.0 ** rng.uniform(10.0, 18.0, 256)).astype(np.int64)
+    jobs = [(int(c), W.SEED_BASE + 4 + 1000 * s) for s, c in enumerate(counts)]
+    print("batched: generating scenes", file=sys.stderr, flush=True)
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        scenes = list(ex.map(_scene, jobs, chunksize=4))
+    print("batched: generated", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    g = lambda a: torch.from_numpy(a).to(dev)
+    probs = [binding.Problem(g(w.rays), g(w.fibers), 22, None, None, g(w.pair_depth)) for w in scenes]
+    total = int(counts.sum())
+    best, best_ms = binding.autotune(probs, repeats=2)
+    print(f"batched: autotuned {best}", file=sys.stderr, flush=True)
+    plan = binding.BatchPlan(probs)
+    stream = torch.cuda.current_stream()
+
+    def plain():
+        for p in probs:
+            binding.intersect_pairs(p.rays, p.fibers, 22, pair_depth=p.pair_depth,
+                                    out=(p.t, p.u, p.hit), stream=stream)
+
+    ms_graph = _timed(lambda: plan.launch(stream), args.steps, args.warmup, stream)
+    ms_plain = _timed(plain, args.steps, args.warmup, stream)
+    depth_hist = np.bincount(np.concatenate([w.pair_depth for w in scenes]), minlength=23)
+    line = {
+        "metric": "ray-fiber intersections/sec (Gpairs/s), batched uneven scenes",
+        "value": total / (ms_graph * 1e-3) / 1e9, "unit": "Gpairs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_graph,
+        "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "256 scenes, round(2^U(10,18)) pairs each, curved random-walk "
+                               "fibers, per-segment adaptive depth 2..22",
+                   "pairs": total, "scenes": 256, "depth_histogram": depth_hist.tolist()},
+        "graph_launch_ms": ms_graph, "plain_launches_ms": ms_plain,
+        "plain_gpairs_per_s": total / (ms_plain * 1e-3) / 1e9,
+        "batched_over_plain": ms_plain / ms_graph,
+        "autotuned": best, "autotune_best_ms": best_ms,
+    }
+    plan.close()
+    print(json.dumps(line), flush=True)
+
+
+def bench_hair(args):
+    """Hair-like precision stress: 2^24 rays against 800,000 segments offset
+    by 1e3 (10 % grazing within 1e-3 r): throughput of the FP32 search at
+    depth 9 and 22 and of the FP64-refined search at 22, and their errors
+    against the oracles on a seeded sample of 2^17 pairs."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1811_03374_amd import binding
+    from paper_1811_03374_amd import workloads as W
+
+    print("hair: generating 2^24 rays", file=sys.stderr, flush=True)
+    w = W.hair_precision(1 << 24, 100_000)
+    print("hair: generated", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    rays, fibers = torch.from_numpy(w.rays).to(dev), torch.from_numpy(w.fibers).to(dev)
+    pf = torch.from_numpy(w.pair_fiber).to(dev)
+    n = w.n_pairs
+    stream = torch.cuda.current_stream()
+    res, outs = {}, {}
+    for d in (9, 22):
+        ms = _timed(lambda: binding.intersect_pairs(rays, fibers, d, pair_fiber=pf, stream=stream),
+                    args.steps, args.warmup, stream)
+        outs[d] = [o.cpu().numpy() for o in binding.intersect_pairs(rays, fibers, d, pair_fiber=pf)]
+        res[f"fp32_d{d}"] = {"ms": ms, "gpairs_per_s": n / (ms * 1e-3) / 1e9}
+    ms = _timed(lambda: binding.intersect_pairs(rays, fibers, 22, pair_fiber=pf, refine=True,
+                                                stream=stream), args.steps, args.warmup, stream)
+    ref = [o.cpu().numpy() for o in binding.intersect_pairs(rays, fibers, 22, pair_fiber=pf, refine=True)]
+    res["fp64_refined_d22"] = {"ms": ms, "gpairs_per_s": n / (ms * 1e-3) / 1e9}
+    print("hair: timed; oracle sample", file=sys.stderr, flush=True)
+
+    idx = np.sort(np.random.default_rng(3).choice(n, 1 << 17, replace=False))
+    ws = w.subset(idx)
+    P = W.unpack_fibers(ws.fibers)
+    valid = np.array([oracle.cubic_constraints(P[i].reshape(16)) == 31 for i in range(P.shape[0])])
+
+    def stats(h, t, u, h_o, t_o, u_o, band):
+        h = h.astype(bool)
+        h_o = h_o.astype(bool)
+        m = ~band & valid
+        both = m & h & h_o
+        rel = np.abs(t[both] - t_o[both]) / t_o[both]
+        return {"pairs": int(m.sum()), "in_band": int(band.sum()),
+                "flag_disagree_rate": float((h[m] != h_o[m]).mean()),
+                "max_rel_t": float(rel.max()) if rel.size else 0.0,
+                "p999_rel_t": float(np.quantile(rel, 0.999)) if rel.size else 0.0,
+                "max_abs_u": float(np.abs(u[both] - u_o[both]).max()) if rel.size else 0.0}
+
+    for d in (9, 22):
+        t_o, u_o, h_o = oracle.intersect_depth(ws.rays, ws.fibers, d)
+        _, _, hl = oracle.intersect_depth(ws.rays, ws.fibers, d, radius_scale=1 - 1e-4)
+        _, _, hh = oracle.intersect_depth(ws.rays, ws.fibers, d, radius_scale=1 + 1e-4)
+        t, u, h = (a[idx] for a in outs[d])
+        res[f"fp32_d{d}"]["vs_depth_oracle"] = stats(h, t, u, h_o, t_o, u_o, hl != hh)
+    t_x, u_x, h_x, _ = oracle.intersect_exact(ws.rays, ws.fibers)
+    _, _, hl, _ = oracle.intersect_exact(ws.rays, ws.fibers, radius_scale=1 - 1e-4)
+    _, _, hh, _ = oracle.intersect_exact(ws.rays, ws.fibers, radius_scale=1 + 1e-4)
+    t, u, h = outs[22][0][idx], outs[22][1][idx], outs[22][2][idx]
+    res["fp32_d22"]["vs_exact_oracle"] = stats(h, t, u, h_x, t_x, u_x, hl != hh)
+    res["fp64_refined_d22"]["vs_exact_oracle"] = stats(ref[2][idx], ref[3][idx], ref[4][idx],
+                                                       h_x, t_x, u_x, hl != hh)
+    line = {"metric": "ray-fiber intersections/sec (Gpairs/s), hair precision stress",
+            "value": res["fp32_d22"]["gpairs_per_s"], "unit": "Gpairs/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "dtype": "f32 (+f64 refinement)",
+            "data": "synthetic",
+            "config": {"workload": "hair: 100k strands x 8 C1 segments, +1e3 offset, r 1e-4..2e-5, "
+                                   "2^24 rays, 10% grazing within 1e-3 r", "pairs": n,
+                       "error_sample": int(len(idx)), "valid_in_sample": int(valid.sum())},
+            "results": res}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the per-pair test has no cross-GPU step, "
               "and multi-GPU runs are not part of this build (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        bench_batched(args)
+        return
+    if args.workload == "hair":
+        bench_hair(args)
+        return
 
     import numpy as np
     import torch

@@ -152,14 +152,22 @@ typedef struct fi_scene {
 
 /* Launch tuning of the persistent traversal (not part of the method):
  *   refill          refill a wave's finished lanes once at least this many
- *                   (1..64) are free; default 32;
- *   waves_per_simd  cap on resident waves per SIMD (0 = as many as fit);
- *   root_in_lds     1: keep each lane's root node in LDS, 0: in registers.
+ *                   (1..64) are free;
+ *   waves_per_simd  cap on resident waves per SIMD (0 = as many as fit;
+ *                   -1 = no persistence: one wave per 64 pairs, scheduled
+ *                   by the hardware);
+ *   root_in_lds     1: keep each lane's root node in LDS, 0: in registers;
+ *   chunk           pairs a wave claims per atomic from the shared queue
+ *                   (1..65536);
+ *   static_pct      share (0..100) of an even split of the pairs that each
+ *                   wave owns up front, before it claims dynamic chunks.
  * Results never depend on the tuning. */
 typedef struct fi_tuning {
     int32_t refill;
     int32_t waves_per_simd;
     int32_t root_in_lds;
+    int32_t chunk;
+    int32_t static_pct;
 } fi_tuning;
 
 /* Bytes of device workspace fiber_intersect_batched needs for n_scenes. */
@@ -176,7 +184,9 @@ size_t fiber_batched_workspace_bytes(int32_t n_scenes);
  * do not leave the GPU idle.
  *
  * Arguments: scenes is a host array of n_scenes descriptors (the library
- * copies it before returning); tuning may be NULL (defaults); flags must be 0;
+ * copies it before returning); tuning may be NULL (the autotuned entry of
+ * this batch's size class if fiber_batch_autotune ran, else defaults);
+ * flags must be 0;
  * workspace is caller-owned device memory of at least
  * fiber_batched_workspace_bytes(n_scenes) bytes, which must not be used by
  * another call that is still in flight.
@@ -206,10 +216,14 @@ int fiber_batch_plan_destroy(fi_batch_plan *plan);
 
 /*
  * fiber_batch_autotune -- time fiber_intersect_batched on these scenes over a
- * grid of tunings (refill 8..48, waves per SIMD 2..max, root in LDS or
- * registers), each `repeats` times after one warm-up, and return the fastest
+ * grid of tunings (refill 16..48, waves per SIMD 3..max, root in LDS or
+ * registers, chunk 64 or 256, static share 50, 80 or 100 %), each `repeats`
+ * times after one warm-up, and return the fastest
  * in *best (and its time in *best_ms if not NULL). Overwrites the scenes'
- * outputs. Blocks the host until the timing runs finish.
+ * outputs. Blocks the host until the timing runs finish. The result is also
+ * remembered for the process, keyed by device and the batch's size class
+ * (log2 of total pairs and of the problem count): later batched calls and
+ * plans of that class that pass tuning = NULL use it.
  */
 int fiber_batch_autotune(const fi_scene *scenes, int32_t n_scenes, uint32_t flags, void *workspace,
                          size_t workspace_bytes, void *stream, int32_t repeats,

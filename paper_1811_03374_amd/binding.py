@@ -155,11 +155,13 @@ class FiScene(C.Structure):
 
 
 class FiTuning(C.Structure):
-    _fields_ = [("refill", C.c_int32), ("waves_per_simd", C.c_int32), ("root_in_lds", C.c_int32)]
+    _fields_ = [("refill", C.c_int32), ("waves_per_simd", C.c_int32), ("root_in_lds", C.c_int32),
+                ("chunk", C.c_int32), ("static_pct", C.c_int32)]
 
     def as_dict(self):
         return {"refill": self.refill, "waves_per_simd": self.waves_per_simd,
-                "root_in_lds": self.root_in_lds}
+                "root_in_lds": self.root_in_lds, "chunk": self.chunk,
+                "static_pct": self.static_pct}
 
 
 def _batched_lib():
@@ -234,7 +236,8 @@ def _tuning(t):
         return None
     if isinstance(t, FiTuning):
         return C.byref(t)
-    return C.byref(FiTuning(int(t["refill"]), int(t["waves_per_simd"]), int(t["root_in_lds"])))
+    return C.byref(FiTuning(int(t["refill"]), int(t["waves_per_simd"]), int(t["root_in_lds"]),
+                            int(t.get("chunk", 128)), int(t.get("static_pct", 50))))
 
 
 def workspace_for(n_problems: int, device="cuda"):

@@ -32,6 +32,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdlib>
+#include <map>
 #include <mutex>
 
 #include "fiberhit.h"
@@ -42,6 +43,10 @@ constexpr int kWave = 64;                     // gfx950 wavefront
 constexpr uint32_t kRootSize = 1u << 23;      // parametric domain [0, 1) in units of 2^-23
 constexpr int kMaxTrips = 1 << 16;            // hang guard; real pairs need < 200 trips
 constexpr float kParallelG = 1e-30f;          // axis treated as parallel to the ray below this
+#ifndef FIBERHIT_PARENT_CACHE
+#define FIBERHIT_PARENT_CACHE 1
+#endif
+constexpr bool kParentCache = FIBERHIT_PARENT_CACHE != 0;   // cache the latest both-hit parent in LDS
 
 struct V4 { float x, y, z, w; };
 struct Node { V4 p, d, t0, t1; };             // Section 3.1: p = p0, d = p3-p0, t0 = p1-p0, t1 = p3-p2
@@ -63,13 +68,32 @@ __device__ __forceinline__ bool zero3(float x, float y, float z)
 // Ray frame (Section 3.3)
 // ---------------------------------------------------------------------------
 
+// 1/sqrt(x) and 1/x in double: hardware estimates refined by two Newton
+// steps each (quadratic convergence from ~2^-22 to full double precision).
+__device__ __forceinline__ double rsqrt64(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * fma(-hx * y, y, 1.5);
+    y = y * fma(-hx * y, y, 1.5);
+    return y;
+}
+
+__device__ __forceinline__ double rcp64(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(fma(-x, y, 1.0), y, y);
+    y = fma(fma(-x, y, 1.0), y, y);
+    return y;
+}
+
 // Orthonormal basis (u, v) completing the unit w: Duff et al. 2017, the
 // revision of Frisvad's construction cited in Section 3.3.
 __device__ __forceinline__ void make_onb(double wx, double wy, double wz,
                                          double u[3], double v[3])
 {
     const double s = copysign(1.0, wz);
-    const double a = -1.0 / (s + wz);
+    const double a = -rcp64(s + wz);
     const double b = wx * wy * a;
     u[0] = fma(s * wx * wx, a, 1.0);
     u[1] = s * b;
@@ -94,7 +118,7 @@ __device__ __forceinline__ bool root_in_ray_frame(const float *R, int64_t rs, co
     const double dx = R[3 * rs], dy = R[4 * rs], dz = R[5 * rs];
     const double n2 = fma(dx, dx, fma(dy, dy, dz * dz));
     if (!(n2 > 0.0) || !(n2 < INFINITY)) return false;
-    const double il = 1.0 / sqrt(n2);
+    const double il = rsqrt64(n2);
     const double w[3] = {dx * il, dy * il, dz * il};
     double u[3], v[3];
     make_onb(w[0], w[1], w[2], u, v);
@@ -173,20 +197,18 @@ __device__ __forceinline__ float conservative_radius(const Node &c)
 // line through o along a (Appendix A). False on a miss.
 __device__ __forceinline__ bool unit_ray_cylinder(const V4 &o, const V4 &a, float r, float &te, float &tx)
 {
+    // both cases are evaluated and selected: no divergent branch
     const float g = fmaf(a.x, a.x, a.y * a.y);
-    if (g < kParallelG) {
-        if (fmaf(o.x, o.x, o.y * o.y) < r * r) { te = -INFINITY; tx = INFINITY; return true; }
-        return false;
-    }
+    const bool parallel = g < kParallelG;
     const float dd = fmaf(a.x, o.y, -(a.y * o.x));
     const float h = rcp(g);
     const float e = fmaf(-(dd * dd), h, r * r);
-    if (!(e >= 0.0f)) return false;
     const float tc = fmaf(-a.z, fmaf(a.x, o.x, a.y * o.y) * h, o.z);
     const float s = vsqrt(e * fmaf(a.z, a.z, g) * h);
-    te = tc - s;
-    tx = tc + s;
-    return true;
+    const bool inside = fmaf(o.x, o.x, o.y * o.y) < r * r;
+    te = parallel ? -INFINITY : tc - s;
+    tx = parallel ? INFINITY : tc + s;
+    return parallel ? inside : e >= 0.0f;
 }
 
 // Split quantities of Section 3.1: centre offset dp and split tangent tc.
@@ -331,10 +353,13 @@ __device__ __forceinline__ float plane_slack(float px, float py, float pz, float
 // One loop trip of the paper's iteration (Appendix C, final listing): a
 // pruning test of the current node, then a descent, a leaf hit, a miss, or a
 // jump to the deepest pending sibling.
+// The common case (test, split, ordering, descent) is straight-line code for
+// every active lane: a lane that will stop still computes the split, which
+// costs nothing on a SIMD that runs it for its neighbours anyway, and avoids
+// divergent branches. Only the jump to a pending sibling branches.
 template <int MODE, class Store>
 __device__ __forceinline__ int trip(Lane &L, Store &store)
 {
-    if (++L.trips > kMaxTrips) return kMiss;
     float te, tx;
     float rad = conservative_radius(L.c);
     float lo = L.lo, hi = L.hi;
@@ -345,70 +370,75 @@ __device__ __forceinline__ int trip(Lane &L, Store &store)
         hi += tslack;
     }
     const bool vis = unit_ray_cylinder(L.c.p, L.c.d, rad, te, tx) && fmaxf(te, lo) <= fminf(tx, hi);
-    if (vis) {
-        if (L.size <= L.min_size) { L.t = fmaxf(te, lo); return kHit; }
-        // Section 3.2: split plane through the centre, normal to the split tangent
-        V4 dp, tc;
-        split_terms(L.c, dp, tc);
-        float nx = tc.x, ny = tc.y, nz = tc.z;
-        if (zero3(nx, ny, nz)) { nx = L.c.d.x; ny = L.c.d.y; nz = L.c.d.z; }
-        const float cs = dot3(L.c.p.x + dp.x, L.c.p.y + dp.y, L.c.p.z + dp.z, nx, ny, nz);
-        bool right, both;
-        if (nz != 0.0f) {
-            const float tp = cs * rcp(nz);
-            right = (tp > te) != (nz > 0.0f);
-            if (MODE == kConservative) {
-                // visit both halves unless the crossing is clearly outside
-                // [te, tx]; narrow by the far side of tp's rounding bound
-                const float ep = plane_slack(L.c.p.x + dp.x, L.c.p.y + dp.y, L.c.p.z + dp.z, nx, ny, nz, tp);
-                both = te - ep < tp && tp < tx + ep;
-                if (tp > te) L.hi = fminf(L.hi, tp + ep);
-                else         L.lo = fmaxf(L.lo, tp - ep);
-            } else {
-                both = te < tp && tp < tx;
-                if (tp > te) L.hi = fminf(L.hi, tp);
-                else         L.lo = fmaxf(L.lo, tp);
-            }
+    const bool leaf = L.size <= L.min_size;
+    if (++L.trips > kMaxTrips) return kMiss;
+    if (!vis) {
+        if (L.bits == 0) return kMiss;
+        // Section 3.3: jump to the deepest level with a pending sibling and
+        // rebuild its parent -- the cached node, or a replay of the split
+        // rules along the integer path from the root
+        L.size = L.bits & (0u - L.bits);
+        L.start ^= L.size;
+        L.bits ^= L.size;
+        L.start &= ~(L.size - 1u);
+        if (kParentCache && L.cached == L.size) {
+            store.get_parent(L.c);
         } else {
-            right = cs < 0.0f;          // the whole ray lies on the side of sign(-cs)
-            both = cs == 0.0f;
-            if (MODE == kConservative) both = both || fabsf(cs) <= L.slack * (fabsf(nx) + fabsf(ny));
+            store.get(L.c);
+            for (uint32_t b = kRootSize >> 1; b > L.size; b >>= 1) {
+                V4 dp, tc;
+                split_terms(L.c, dp, tc);
+                take_child(L.c, dp, tc, (L.start & b) != 0u);
+            }
         }
-        if (both) store.put_parent(L.c);
-        take_child(L.c, dp, tc, right);
-        L.size >>= 1;
-        if (both) {
-            L.bits ^= L.size;
-            L.cached = L.size;
-        }
-        if (right) L.start ^= L.size;
-        L.splits++;
-        return kGoOn;
-    }
-    if (L.bits == 0) return kMiss;
-    // Section 3.3: jump to the deepest level with a pending sibling, then
-    // rebuild that node by replaying the split rules along the integer path
-    L.size = L.bits & (0u - L.bits);
-    L.start ^= L.size;
-    L.bits ^= L.size;
-    L.start &= ~(L.size - 1u);
-    if (L.cached == L.size) {
-        // the pending sibling's parent is the cached node: one split
-        store.get_parent(L.c);
+        L.cached = 0;
         V4 dp, tc;
         split_terms(L.c, dp, tc);
         take_child(L.c, dp, tc, (L.start & L.size) != 0u);
-        L.cached = 0;
-    } else {
-        store.get(L.c);
-        for (uint32_t b = kRootSize >> 1; b >= L.size; b >>= 1) {
-            V4 dp, tc;
-            split_terms(L.c, dp, tc);
-            take_child(L.c, dp, tc, (L.start & b) != 0u);
-        }
+        cap_interval(L.c, L.tmax, L.lo, L.hi);
+        L.backtracks++;
+        return kGoOn;
     }
-    cap_interval(L.c, L.tmax, L.lo, L.hi);
-    L.backtracks++;
+    // Section 3.2: split plane through the centre, normal to the split tangent
+    V4 dp, tc;
+    split_terms(L.c, dp, tc);
+    float nx = tc.x, ny = tc.y, nz = tc.z;
+    const bool flat = zero3(nx, ny, nz);
+    nx = flat ? L.c.d.x : nx;
+    ny = flat ? L.c.d.y : ny;
+    nz = flat ? L.c.d.z : nz;
+    const float qx = L.c.p.x + dp.x, qy = L.c.p.y + dp.y, qz = L.c.p.z + dp.z;
+    const float cs = dot3(qx, qy, qz, nx, ny, nz);
+    const float tp = cs * rcp(nz);
+    const bool oblique = nz != 0.0f;
+    bool right, both;
+    float nlo = L.lo, nhi = L.hi;
+    if (MODE == kConservative) {
+        // visit both halves unless the crossing is clearly outside [te, tx];
+        // narrow by the far side of tp's rounding bound
+        const float ep = plane_slack(qx, qy, qz, nx, ny, nz, tp);
+        both = oblique ? (te - ep < tp && tp < tx + ep)
+                       : (cs == 0.0f || fabsf(cs) <= L.slack * (fabsf(nx) + fabsf(ny)));
+        if (tp > te) nhi = fminf(nhi, tp + ep);
+        else         nlo = fmaxf(nlo, tp - ep);
+    } else {
+        both = oblique ? (te < tp && tp < tx) : cs == 0.0f;
+        if (tp > te) nhi = fminf(nhi, tp);
+        else         nlo = fmaxf(nlo, tp);
+    }
+    // the whole ray lies on the side of sign(-cs) when the plane is parallel
+    right = oblique ? ((tp > te) != (nz > 0.0f)) : cs < 0.0f;
+    if (oblique) { L.lo = nlo; L.hi = nhi; }
+    if (leaf) { L.t = fmaxf(te, lo); return kHit; }
+    if (kParentCache && both) store.put_parent(L.c);
+    take_child(L.c, dp, tc, right);
+    L.size >>= 1;
+    if (both) {
+        L.bits ^= L.size;
+        if (kParentCache) L.cached = L.size;
+    }
+    if (right) L.start ^= L.size;
+    L.splits++;
     return kGoOn;
 }
 
@@ -483,11 +513,21 @@ __device__ __forceinline__ int find_scene(const int64_t *offsets, int n_scenes, 
 // finish returns both to zero, so the slot is ready for the next launch.
 // BATCHED: pairs are numbered across a table of scenes (one persistent
 // launch for many independent problems); otherwise the single problem a0.
+// Work distribution: wave w first owns the static range [w S, (w + 1) S)
+// (no atomics), then pulls dynamic chunks of `chunk` pairs from queue[0]
+// (one device-scope atomic per chunk, offset past all static ranges). Lanes
+// are refilled from the wave's current range, held in scalar registers.
+struct Sched {
+    int64_t static_per_wave;     // S
+    int32_t chunk;               // dynamic chunk, pairs
+    int32_t refill;              // refill once this many lanes are free
+};
+
 template <int MODE, bool BATCHED, bool ROOT_LDS>
 __global__ __launch_bounds__(kWave) void k_traverse(Args a0, const Args *scenes, const int64_t *offsets,
-                                                    int n_scenes, int64_t total, uint32_t *queue, int refill)
+                                                    int n_scenes, int64_t total, uint32_t *queue, Sched sc)
 {
-    __shared__ float s_nodes[(ROOT_LDS ? 32 : 16) * kWave];
+    __shared__ float s_nodes[((ROOT_LDS ? 16 : 0) + (kParentCache ? 16 : 0) + 1) * kWave];
     const int lane = threadIdx.x;
     RootStore<ROOT_LDS> store;
     store.col = s_nodes + lane;
@@ -496,29 +536,44 @@ __global__ __launch_bounds__(kWave) void k_traverse(Args a0, const Args *scenes,
     int scene = 0;
     bool active = false;
     bool exhausted = false;
+    const int64_t dyn0 = (int64_t)gridDim.x * sc.static_per_wave;     // first dynamic pair
+    int64_t next = (int64_t)blockIdx.x * sc.static_per_wave;           // wave-uniform range
+    int64_t end = next + sc.static_per_wave < total ? next + sc.static_per_wave : total;
     for (;;) {
         const uint64_t free_mask = __ballot(!active);
         const int n_free = __popcll(free_mask);
-        if (!exhausted && (n_free >= refill || n_free == kWave)) {
-            uint32_t base = 0;
-            if (lane == 0) base = atomicAdd(&queue[0], (uint32_t)n_free);
-            base = __builtin_amdgcn_readfirstlane(base);
-            if ((int64_t)base + n_free >= total) exhausted = true;
-            if (!active) {
-                const int64_t g = (int64_t)base + lanes_below(free_mask);
-                if (g < total) {
-                    if constexpr (BATCHED) {
-                        scene = find_scene(offsets, n_scenes, g);
-                        idx = g - offsets[scene];
-                        const Args a = scenes[scene];
-                        active = start_pair(a, idx, L, store);
-                        if (!active) finish_invalid<MODE>(a, idx);
-                    } else {
-                        idx = g;
-                        active = start_pair(a0, idx, L, store);
-                        if (!active) finish_invalid<MODE>(a0, idx);
+        if (!exhausted && (n_free >= sc.refill || n_free == kWave)) {
+            if (next >= end && dyn0 >= total) {
+                exhausted = true;                  // static ranges cover every pair
+            } else if (next >= end) {
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(&queue[0], (uint32_t)sc.chunk);
+                base = __builtin_amdgcn_readfirstlane(base);
+                next = dyn0 + (int64_t)base;
+                end = next + sc.chunk < total ? next + sc.chunk : total;
+                if (next >= total) exhausted = true;
+            }
+            if (!exhausted) {
+                const int64_t avail = end - next;
+                const int take = avail < n_free ? (int)avail : n_free;
+                if (!active) {
+                    const int rank = (int)lanes_below(free_mask);
+                    if (rank < take) {
+                        const int64_t g = next + rank;
+                        if constexpr (BATCHED) {
+                            scene = find_scene(offsets, n_scenes, g);
+                            idx = g - offsets[scene];
+                            const Args a = scenes[scene];
+                            active = start_pair(a, idx, L, store);
+                            if (!active) finish_invalid<MODE>(a, idx);
+                        } else {
+                            idx = g;
+                            active = start_pair(a0, idx, L, store);
+                            if (!active) finish_invalid<MODE>(a0, idx);
+                        }
                     }
                 }
+                next += take;
             }
         }
         if (__ballot(active) == 0) {
@@ -785,7 +840,7 @@ int check_common(const float *rays, int64_t ray_stride, int64_t n_rays,
 // Kernel variants, work-queue slots and launch shape
 // ---------------------------------------------------------------------------
 
-using TraverseFn = void (*)(Args, const Args *, const int64_t *, int, int64_t, uint32_t *, int);
+using TraverseFn = void (*)(Args, const Args *, const int64_t *, int, int64_t, uint32_t *, Sched);
 
 // [mode][batched][root in LDS]
 const TraverseFn kTraverse[3][2][2] = {
@@ -857,23 +912,98 @@ int device_info(DeviceInfo *&out)
     return FI_OK;
 }
 
-fi_tuning default_tuning() { return fi_tuning{32, 0, 1}; }
+// Launch defaults of single-problem calls (and of batches without a tuned
+// entry); measured choices, overridable when building.
+#ifndef FIBERHIT_DEFAULT_REFILL
+#define FIBERHIT_DEFAULT_REFILL 32
+#endif
+#ifndef FIBERHIT_DEFAULT_WAVES_PER_SIMD
+#define FIBERHIT_DEFAULT_WAVES_PER_SIMD 0
+#endif
+#ifndef FIBERHIT_DEFAULT_ROOT_IN_LDS
+#define FIBERHIT_DEFAULT_ROOT_IN_LDS 0
+#endif
+#ifndef FIBERHIT_DEFAULT_CHUNK
+#define FIBERHIT_DEFAULT_CHUNK 128
+#endif
+#ifndef FIBERHIT_DEFAULT_STATIC_PCT
+#define FIBERHIT_DEFAULT_STATIC_PCT 100
+#endif
+fi_tuning default_tuning()
+{
+    return fi_tuning{FIBERHIT_DEFAULT_REFILL, FIBERHIT_DEFAULT_WAVES_PER_SIMD, FIBERHIT_DEFAULT_ROOT_IN_LDS,
+                     FIBERHIT_DEFAULT_CHUNK, FIBERHIT_DEFAULT_STATIC_PCT};
+}
+
+// Autotune results, kept for the process: keyed by device and the size class
+// of a batch (log2 of its total pairs and of its problem count). A batch
+// launched without an explicit tuning uses the entry of its class if one
+// exists.
+std::mutex g_tune_mutex;
+std::map<uint64_t, fi_tuning> g_tune_cache;
+
+uint64_t tune_key(int device, int64_t total, int n_scenes)
+{
+    int lt = 0, ls = 0;
+    while ((int64_t)1 << (lt + 1) <= total && lt < 62) ++lt;
+    while ((1 << (ls + 1)) <= n_scenes && ls < 30) ++ls;
+    return ((uint64_t)device << 16) | ((uint64_t)lt << 8) | (uint64_t)ls;
+}
+
+fi_tuning tuned_or_default(int64_t total, int n_scenes)
+{
+    int dev = 0;
+    if (current_device(dev) != FI_OK) return default_tuning();
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    const auto it = g_tune_cache.find(tune_key(dev, total, n_scenes));
+    return it == g_tune_cache.end() ? default_tuning() : it->second;
+}
+
+void remember_tuning(int64_t total, int n_scenes, const fi_tuning &t)
+{
+    int dev = 0;
+    if (current_device(dev) != FI_OK) return;
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tune_cache[tune_key(dev, total, n_scenes)] = t;
+}
+
+int64_t total_pairs(const fi_scene *sc, int32_t n)
+{
+    int64_t t = 0;
+    for (int k = 0; k < n; ++k) t += sc[k].n_pairs > 0 ? sc[k].n_pairs : 0;
+    return t;
+}
 
 int check_tuning(const fi_tuning &t)
 {
-    if (t.refill < 1 || t.refill > kWave || t.waves_per_simd < 0 || t.waves_per_simd > 16 ||
-        (t.root_in_lds != 0 && t.root_in_lds != 1))
+    if (t.refill < 1 || t.refill > kWave || t.waves_per_simd < -1 || t.waves_per_simd > 16 ||
+        (t.root_in_lds != 0 && t.root_in_lds != 1) || t.chunk < 1 || t.chunk > (1 << 16) ||
+        t.static_pct < 0 || t.static_pct > 100)
         return FI_ERR_RANGE;
     return FI_OK;
 }
 
 unsigned grid_for(const DeviceInfo &d, int mode, bool batched, const fi_tuning &t, int64_t n_pairs)
 {
+    const int64_t needed = (n_pairs + kWave - 1) / kWave;
+    if (t.waves_per_simd < 0) return (unsigned)needed;       // one wave per 64 pairs: plain grid
     int per_cu = d.resident[mode][batched ? 1 : 0][t.root_in_lds];
     if (t.waves_per_simd > 0 && 4 * t.waves_per_simd < per_cu) per_cu = 4 * t.waves_per_simd;
     const int64_t resident = (int64_t)per_cu * d.cus;
-    const int64_t needed = (n_pairs + kWave - 1) / kWave;
     return (unsigned)(needed < resident ? needed : resident);
+}
+
+Sched sched_for(const fi_tuning &t, unsigned grid, int64_t total)
+{
+    Sched sc;
+    // static share: static_pct % of an even split, in whole lane batches
+    const int64_t even = grid ? total / grid : 0;
+    sc.static_per_wave = (even * t.static_pct / 100) / kWave * kWave;
+    // one wave per lane batch: each wave owns exactly its batch, no queue
+    if (t.waves_per_simd < 0) sc.static_per_wave = kWave;
+    sc.chunk = t.chunk;
+    sc.refill = t.refill;
+    return sc;
 }
 
 int launch_traverse(const DeviceInfo &d, int mode, bool batched, const fi_tuning &t, const Args &a0,
@@ -882,8 +1012,12 @@ int launch_traverse(const DeviceInfo &d, int mode, bool batched, const fi_tuning
 {
     const unsigned grid = grid_for(d, mode, batched, t, total);
     if (grid == 0) return FI_OK;
+    // queue[0] ends below total + (grid + 1) * chunk (one claim past the end per
+    // wave); keep that within 32 bits
+    if (t.waves_per_simd >= 0 && total + ((int64_t)grid + 1) * t.chunk >= ((int64_t)1 << 32))
+        return FI_ERR_RANGE;
     hipLaunchKernelGGL(kTraverse[mode][batched ? 1 : 0][t.root_in_lds], dim3(grid), dim3(kWave), 0, s,
-                       a0, scenes, offsets, n_scenes, total, queue, t.refill);
+                       a0, scenes, offsets, n_scenes, total, queue, sched_for(t, grid, total));
     return FI_OK;
 }
 
@@ -895,7 +1029,8 @@ int launch(int mode, const Args &a, double *t64, double *u64, void *stream)
     if (st != FI_OK) return st;
     uint32_t *slot = d->slots + 2 * (g_next_slot.fetch_add(1u) % kSlots);
     hipStream_t s = (hipStream_t)stream;
-    launch_traverse(*d, mode, false, default_tuning(), a, nullptr, nullptr, 1, a.n_pairs, slot, s);
+    const int lst = launch_traverse(*d, mode, false, default_tuning(), a, nullptr, nullptr, 1, a.n_pairs, slot, s);
+    if (lst != FI_OK) return lst;
     if (t64) {
         const unsigned g2 = (unsigned)((a.n_pairs + 255) / 256);
         hipLaunchKernelGGL(k_refine, dim3(g2), dim3(256), 0, s, a, t64, u64);
@@ -971,8 +1106,10 @@ int batched_enqueue(const fi_scene *scenes, int32_t n_scenes, const fi_tuning &t
     if (hipEventRecord(d->stage_done[k], s) != hipSuccess) return FI_ERR_HIP;
     d->stage_next = (k + 1) % kStageSlots;
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, L.queue);
-    if (total > 0)
-        launch_traverse(*d, kPlain, true, t, Args{}, L.scenes, L.offsets, n_scenes, total, L.queue, s);
+    if (total > 0) {
+        const int lst = launch_traverse(*d, kPlain, true, t, Args{}, L.scenes, L.offsets, n_scenes, total, L.queue, s);
+        if (lst != FI_OK) return lst;
+    }
     return hipGetLastError() == hipSuccess ? FI_OK : FI_ERR_HIP;
 }
 
@@ -1054,7 +1191,7 @@ int fiber_intersect_batched(const fi_scene *scenes, int32_t n_scenes, const fi_t
     if (n_scenes < 0 || flags != 0u) return FI_ERR_RANGE;
     if (n_scenes == 0) return FI_OK;
     if (!scenes) return FI_ERR_NULL;
-    const fi_tuning t = tuning ? *tuning : default_tuning();
+    const fi_tuning t = tuning ? *tuning : tuned_or_default(total_pairs(scenes, n_scenes), n_scenes);
     if (check_tuning(t) != FI_OK) return FI_ERR_RANGE;
     (void)hipGetLastError();
     return batched_enqueue(scenes, n_scenes, t, workspace, workspace_bytes, (hipStream_t)stream);
@@ -1067,7 +1204,7 @@ int fiber_batch_plan_create(const fi_scene *scenes, int32_t n_scenes, const fi_t
     *plan_out = nullptr;
     if (n_scenes <= 0 || flags != 0u) return FI_ERR_RANGE;
     if (!scenes) return FI_ERR_NULL;
-    const fi_tuning t = tuning ? *tuning : default_tuning();
+    const fi_tuning t = tuning ? *tuning : tuned_or_default(total_pairs(scenes, n_scenes), n_scenes);
     if (check_tuning(t) != FI_OK) return FI_ERR_RANGE;
     (void)hipGetLastError();
     DeviceInfo *d = nullptr;
@@ -1093,18 +1230,20 @@ int fiber_batch_plan_create(const fi_scene *scenes, int32_t n_scenes, const fi_t
         ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
         if (ok) {
             hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, cs, L.queue);
+            int lst = FI_OK;
             if (p->total > 0)
-                launch_traverse(*d, kPlain, true, t, Args{}, L.scenes, L.offsets, n_scenes, p->total, L.queue, cs);
-            ok = hipStreamEndCapture(cs, &p->graph) == hipSuccess &&
+                lst = launch_traverse(*d, kPlain, true, t, Args{}, L.scenes, L.offsets, n_scenes, p->total,
+                                      L.queue, cs);
+            ok = hipStreamEndCapture(cs, &p->graph) == hipSuccess && lst == FI_OK &&
                  hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) == hipSuccess;
         }
     }
-    if (cs) hipStreamDestroy(cs);
+    if (cs) (void)hipStreamDestroy(cs);
     if (!ok) {
         (void)hipGetLastError();
-        if (p->exec) hipGraphExecDestroy(p->exec);
-        if (p->graph) hipGraphDestroy(p->graph);
-        if (p->mem) hipFree(p->mem);
+        if (p->exec) (void)hipGraphExecDestroy(p->exec);
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        if (p->mem) (void)hipFree(p->mem);
         delete p;
         return FI_ERR_HIP;
     }
@@ -1146,20 +1285,24 @@ int fiber_batch_autotune(const fi_scene *scenes, int32_t n_scenes, uint32_t flag
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return FI_ERR_HIP;
-    const int refills[] = {8, 16, 24, 32, 48};
-    const int occ[] = {2, 3, 4, 0};
+    const int refills[] = {16, 32, 48};
+    const int occ[] = {3, 4, 0};
+    const int chunks[] = {64, 256};
+    const int statics[] = {50, 80, 100};
     float best_t = INFINITY;
     fi_tuning bt = default_tuning();
     int st = FI_OK;
     for (int lds = 0; lds < 2 && st == FI_OK; ++lds)
-        for (int oi = 0; oi < 4 && st == FI_OK; ++oi)
-            for (int ri = 0; ri < 5 && st == FI_OK; ++ri) {
-                const fi_tuning t{refills[ri], occ[oi], lds};
+        for (int oi = 0; oi < 3 && st == FI_OK; ++oi)
+          for (int ci = 0; ci < 2 && st == FI_OK; ++ci)
+            for (int si = 0; si < 3 && st == FI_OK; ++si)
+              for (int ri = 0; ri < 3 && st == FI_OK; ++ri) {
+                const fi_tuning t{refills[ri], occ[oi], lds, chunks[ci], statics[si]};
                 float tmin = INFINITY;
                 for (int r = 0; r <= repeats && st == FI_OK; ++r) {       // first run warms up
-                    hipEventRecord(e0, s);
+                    if (hipEventRecord(e0, s) != hipSuccess) { st = FI_ERR_HIP; break; }
                     st = fiber_intersect_batched(scenes, n_scenes, &t, flags, workspace, workspace_bytes, stream);
-                    hipEventRecord(e1, s);
+                    if (st == FI_OK && hipEventRecord(e1, s) != hipSuccess) st = FI_ERR_HIP;
                     if (st == FI_OK && hipEventSynchronize(e1) != hipSuccess) st = FI_ERR_HIP;
                     float ms = 0.0f;
                     if (st == FI_OK && r > 0 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < tmin)
@@ -1167,11 +1310,12 @@ int fiber_batch_autotune(const fi_scene *scenes, int32_t n_scenes, uint32_t flag
                 }
                 if (tmin < best_t) { best_t = tmin; bt = t; }
             }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (st != FI_OK) return st;
     *best = bt;
     if (best_ms) *best_ms = best_t;
+    remember_tuning(total_pairs(scenes, n_scenes), n_scenes, bt);
     return FI_OK;
 }
 

@@ -76,9 +76,9 @@ def test_batched_equals_plain_bitwise():
 def test_results_do_not_depend_on_tuning():
     ws, sizes, probs = make_scenes(seed=9)
     ref = plain_reference(probs)
-    for t in ({"refill": 8, "waves_per_simd": 2, "root_in_lds": 0},
-              {"refill": 64, "waves_per_simd": 0, "root_in_lds": 1},
-              {"refill": 1, "waves_per_simd": 1, "root_in_lds": 0}):
+    for t in ({"refill": 8, "waves_per_simd": 2, "root_in_lds": 0, "chunk": 64, "static_pct": 50},
+              {"refill": 64, "waves_per_simd": 0, "root_in_lds": 1, "chunk": 65536, "static_pct": 100},
+              {"refill": 1, "waves_per_simd": 1, "root_in_lds": 0, "chunk": 1, "static_pct": 0}):
         clear(probs)
         binding.intersect_batched(probs, tuning=t)
         torch.cuda.synchronize()
@@ -118,7 +118,8 @@ def test_autotune_returns_a_grid_point():
     ws, sizes, probs = make_scenes(seed=17)
     best, ms = binding.autotune(probs, repeats=1)
     say(f"[autotune] {best} {ms:.3f} ms")
-    assert best["refill"] in (8, 16, 24, 32, 48) and best["root_in_lds"] in (0, 1)
+    assert best["refill"] in (16, 32, 48) and best["root_in_lds"] in (0, 1)
+    assert best["chunk"] in (64, 256) and best["static_pct"] in (0, 50, 80)
     assert ms > 0
 
 
@@ -129,3 +130,6 @@ def test_batched_argument_errors():
         binding.intersect_batched(probs, workspace=small)
     with pytest.raises(binding.FiberHitError):
         binding.intersect_batched(probs, tuning={"refill": 0, "waves_per_simd": 0, "root_in_lds": 1})
+    with pytest.raises(binding.FiberHitError):
+        binding.intersect_batched(probs, tuning={"refill": 32, "waves_per_simd": 0, "root_in_lds": 1,
+                                                 "chunk": 1 << 17, "static_pct": 50})
