@@ -9,12 +9,23 @@
  * cropped by end-cap and split planes (Sections 3.1-3.3), visiting the half
  * that the ray meets first and stopping at the first leaf hit (Section 3).
  *
- * Every function returns an int status (FI_OK or a negative FI_ERR_*), throws
- * nothing, and never allocates or frees device memory on the call path. All
- * array arguments are caller-owned device pointers (for example the data of
- * torch tensors); the library only reads inputs and writes outputs. Work is
- * enqueued asynchronously on `stream` (a hipStream_t; NULL is the legacy
- * default stream); results are valid once the stream has synchronised.
+ * Every function returns an int status (FI_OK or a negative FI_ERR_*) and
+ * throws nothing. All array arguments are caller-owned device pointers (for
+ * example the data of torch tensors); the library only reads inputs and writes
+ * outputs. Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is
+ * the legacy default stream); results are valid once the stream has
+ * synchronised.
+ *
+ * Each call runs as two kernels per chunk of up to 2^20 pairs: a setup kernel
+ * (one lane per pair: load, FP64 move into the ray frame, root test; pairs
+ * decided at the root are written out) and a persistent traversal kernel over
+ * the survivors, which it reads from a survivor table (85 bytes per row).
+ * fiber_intersect_pairs and fiber_intersect_counts own two such tables per
+ * device (2 x 85 MiB), allocated at their first call on that device and kept
+ * for the process; calls that share a table are ordered on the GPU through an
+ * event, so calls on different streams stay correct. Batched calls take
+ * theirs from the caller's workspace or plan and allocate nothing on the
+ * call path.
  *
  * Layouts (structure of arrays, 32-bit floats, row-major):
  *   rays   : 7 rows of ray_stride floats  -- ox, oy, oz, dx, dy, dz, tmax.
@@ -46,8 +57,9 @@ extern "C" {
 
 /* Flags. */
 /* FI_FP64_REFINE: for pairs of depth > 16, run the traversal with every
- * pruning test enlarged by a bound on its FP32 rounding error, then solve for
- * the hit on the swept-disc surface in FP64 (see fiber_intersect_pairs). */
+ * pruning test enlarged by a bound on its FP32 rounding error and check each
+ * leaf it reaches against the swept-disc solid in FP64 (see
+ * fiber_intersect_pairs). */
 #define FI_FP64_REFINE   (1u << 0)
 
 /* Largest subdivision depth: one bit per level in 32-bit integers and an
@@ -88,22 +100,26 @@ const char *fi_strerror(int status);
  *                                  FI_FP64_REFINE, ignored (may be NULL) without.
  *   stream                         hipStream_t or NULL.
  *
- * FI_FP64_REFINE: the method's leaf cylinders converge to the surface swept by
- * a disc of radius r(u) centred on C(u) in the plane normal to C'(u)
- * (Section 3.2: the limit surface maps the intersection to the closest point
- * on the curve). For each pair of depth > 16 whose conservative FP32 search
- * reports a hit, a second kernel solves <P - C(u), C'(u)> = 0,
- * |P - C(u)| = r(u) for the entry point P = O + t D/|D| in FP64 near the FP32
- * leaf, with the end discs as candidates. All five outputs then describe that
- * surface hit (hit = 0, t = +inf when no surface point lies near the leaf).
- * Pairs of depth <= 16 keep the plain method's results; their t64/u64 are the
- * float results widened.
+ * FI_FP64_REFINE: the method's leaf cylinders converge to the solid swept by
+ * a disc of radius r(u) centred on C(u) in the plane normal to C'(u), closed by
+ * the end discs (Section 3.2: the limit surface maps the intersection to the
+ * closest point on the curve). For each pair of depth > 16 the search runs
+ * with every pruning test enlarged by a bound on its FP32 rounding, and every
+ * leaf it reaches is checked in FP64: the first point of that solid along the
+ * ray whose u lies in the leaf (boundary points from Newton's method on
+ * <P - C(u), C'(u)> = 0, |P - C(u)| = r(u) and from bracketing, the end discs,
+ * t = 0 for an origin inside). A leaf without one counts as missed and the
+ * search goes on. All five outputs then describe the first such point (hit
+ * decided in FP64; hit = 0, t = +inf when there is none). Pairs of depth
+ * <= 16 keep the plain method's results; their t64/u64 are the float results
+ * widened.
  *
  * Errors: FI_ERR_NULL when rays, fibers or an output is NULL with n_pairs > 0
  * (t64_out/u64_out only with FI_FP64_REFINE); FI_ERR_RANGE for negative
  * counts, strides below the counts, a depth outside [0, 23], unknown flags,
  * an identity pairing longer than a table, or n_pairs >= 2^31 - 64;
- * FI_ERR_HIP when the launch fails. Nothing is enqueued on error.
+ * FI_ERR_HIP when the launch fails or the first call on a device cannot
+ * allocate its survivor table. Nothing is enqueued on an argument error.
  */
 int fiber_intersect_pairs(const float *rays, int64_t ray_stride, int64_t n_rays,
                           const float *fibers, int64_t fiber_stride, int64_t n_fibers,
@@ -150,28 +166,22 @@ typedef struct fi_scene {
     float *t_out; float *u_out; uint8_t *hit_out;
 } fi_scene;
 
-/* Launch tuning of the persistent traversal (not part of the method):
+/* Launch tuning of the traversal kernel (not part of the method):
  *   refill          refill a wave's finished lanes once at least this many
  *                   (1..64) are free;
- *   waves_per_simd  cap on resident waves per SIMD (0 = as many as fit;
- *                   -1 = no persistence: one wave per 64 pairs, scheduled
- *                   by the hardware);
- *   root_in_lds     1: keep each lane's root node in LDS, 0: in registers;
- *   chunk           pairs a wave claims per atomic from the shared queue
- *                   (1..65536);
- *   static_pct      share (0..100) of an even split of the pairs that each
- *                   wave owns up front, before it claims dynamic chunks.
+ *   waves_per_simd  cap on resident waves per SIMD (0..16, 0 = as many as fit,
+ *                   which is 8).
  * Results never depend on the tuning. */
 typedef struct fi_tuning {
     int32_t refill;
     int32_t waves_per_simd;
-    int32_t root_in_lds;
-    int32_t chunk;
-    int32_t static_pct;
 } fi_tuning;
 
-/* Bytes of device workspace fiber_intersect_batched needs for n_scenes. */
-size_t fiber_batched_workspace_bytes(int32_t n_scenes);
+/* Bytes of device workspace fiber_intersect_batched needs for n_scenes
+ * problems of total_pairs pairs in all (0 for negative arguments): the scene
+ * table, the bucket counters and a survivor table of min(total_pairs, 2^20)
+ * rows, rounded up to a multiple of 65536. */
+size_t fiber_batched_workspace_bytes(int32_t n_scenes, int64_t total_pairs);
 
 /*
  * fiber_intersect_batched -- all pairs of n_scenes independent problems in
@@ -179,17 +189,18 @@ size_t fiber_batched_workspace_bytes(int32_t n_scenes);
  *
  * Operation: for every scene k, exactly what fiber_intersect_pairs computes
  * for scenes[k] (same per-pair routine; results are bitwise identical to a
- * separate call per scene). Pairs of all scenes are numbered consecutively
- * and pulled by the waves of one launch from a shared queue, so small scenes
- * do not leave the GPU idle.
+ * separate call per scene). Pairs of all scenes are numbered consecutively;
+ * one setup launch covers them all (per chunk of 2^20) and one traversal
+ * launch drains the survivors of all scenes together, so small scenes do not
+ * leave the GPU idle.
  *
  * Arguments: scenes is a host array of n_scenes descriptors (the library
  * copies it before returning); tuning may be NULL (the autotuned entry of
  * this batch's size class if fiber_batch_autotune ran, else defaults);
  * flags must be 0;
  * workspace is caller-owned device memory of at least
- * fiber_batched_workspace_bytes(n_scenes) bytes, which must not be used by
- * another call that is still in flight.
+ * fiber_batched_workspace_bytes(n_scenes, total pairs) bytes, which must not
+ * be used by another call that is still in flight.
  *
  * Errors: FI_ERR_NULL (scenes NULL or a NULL pointer inside a scene),
  * FI_ERR_RANGE (bad counts, strides, depths, tuning, flags, more than 2^31-64
@@ -199,10 +210,10 @@ int fiber_intersect_batched(const fi_scene *scenes, int32_t n_scenes, const fi_t
                             uint32_t flags, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
- * Plans: the scene table is uploaded once into device memory the plan owns,
- * and the launch (a queue reset kernel and the persistent traversal) is
- * captured into a HIP graph that fiber_batch_plan_launch replays on any
- * stream. Creating and destroying a plan allocates and frees device memory;
+ * Plans: the scene table is uploaded once into device memory the plan owns
+ * (with its counters and survivor table), and the launch (a counter reset
+ * kernel, then setup and traversal per chunk) is captured into a HIP graph
+ * that fiber_batch_plan_launch replays on any stream. Creating and destroying a plan allocates and frees device memory;
  * launching does not. One plan must not be launched on two streams at once.
  * The scenes' device buffers must outlive the plan.
  */
@@ -216,8 +227,8 @@ int fiber_batch_plan_destroy(fi_batch_plan *plan);
 
 /*
  * fiber_batch_autotune -- time fiber_intersect_batched on these scenes over a
- * grid of tunings (refill 16..48, waves per SIMD 3..max, root in LDS or
- * registers, chunk 64 or 256, static share 50, 80 or 100 %), each `repeats`
+ * grid of tunings (refill 16, 32 or 48; waves per SIMD 4, 6 or as many as
+ * fit), each `repeats`
  * times after one warm-up, and return the fastest
  * in *best (and its time in *best_ms if not NULL). Overwrites the scenes'
  * outputs. Blocks the host until the timing runs finish. The result is also

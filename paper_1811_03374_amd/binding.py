@@ -155,20 +155,17 @@ class FiScene(C.Structure):
 
 
 class FiTuning(C.Structure):
-    _fields_ = [("refill", C.c_int32), ("waves_per_simd", C.c_int32), ("root_in_lds", C.c_int32),
-                ("chunk", C.c_int32), ("static_pct", C.c_int32)]
+    _fields_ = [("refill", C.c_int32), ("waves_per_simd", C.c_int32)]
 
     def as_dict(self):
-        return {"refill": self.refill, "waves_per_simd": self.waves_per_simd,
-                "root_in_lds": self.root_in_lds, "chunk": self.chunk,
-                "static_pct": self.static_pct}
+        return {"refill": self.refill, "waves_per_simd": self.waves_per_simd}
 
 
 def _batched_lib():
     L = lib()
     if not getattr(L, "_batched_ready", False):
         vp = C.c_void_p
-        L.fiber_batched_workspace_bytes.argtypes = [C.c_int32]
+        L.fiber_batched_workspace_bytes.argtypes = [C.c_int32, C.c_int64]
         L.fiber_batched_workspace_bytes.restype = C.c_size_t
         L.fiber_intersect_batched.argtypes = [C.POINTER(FiScene), C.c_int32, C.POINTER(FiTuning),
                                               C.c_uint32, vp, C.c_size_t, vp]
@@ -236,22 +233,26 @@ def _tuning(t):
         return None
     if isinstance(t, FiTuning):
         return C.byref(t)
-    return C.byref(FiTuning(int(t["refill"]), int(t["waves_per_simd"]), int(t["root_in_lds"]),
-                            int(t.get("chunk", 128)), int(t.get("static_pct", 50))))
+    return C.byref(FiTuning(int(t["refill"]), int(t["waves_per_simd"])))
 
 
-def workspace_for(n_problems: int, device="cuda"):
-    nbytes = _batched_lib().fiber_batched_workspace_bytes(int(n_problems))
+def workspace_for(problems, device=None):
+    """Device workspace for a batched call over ``problems`` (a list of
+    Problem): scene table, bucket counters and survivor table."""
+    total = sum(int(p.n) for p in problems)
+    nbytes = _batched_lib().fiber_batched_workspace_bytes(len(problems), total)
+    if device is None:
+        device = problems[0].rays.device
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
 def intersect_batched(problems, tuning=None, workspace=None, stream=None):
-    """All pairs of all problems in one persistent launch (results land in
-    each Problem's t, u, hit)."""
+    """All pairs of all problems in one setup and one persistent traversal
+    launch per chunk (results land in each Problem's t, u, hit)."""
     L = _batched_lib()
     arr = _scene_array(problems)
     if workspace is None:
-        workspace = workspace_for(len(problems), problems[0].rays.device)
+        workspace = workspace_for(problems)
     _check(L.fiber_intersect_batched(arr, len(problems), _tuning(tuning), 0,
                                      C.c_void_p(workspace.data_ptr()), workspace.numel(),
                                      _stream(stream)))
@@ -294,7 +295,7 @@ def autotune(problems, repeats=2, workspace=None, stream=None):
     L = _batched_lib()
     arr = _scene_array(problems)
     if workspace is None:
-        workspace = workspace_for(len(problems), problems[0].rays.device)
+        workspace = workspace_for(problems)
     best = FiTuning()
     ms = C.c_float()
     _check(L.fiber_batch_autotune(arr, len(problems), 0, C.c_void_p(workspace.data_ptr()),

@@ -47,6 +47,9 @@ constexpr float kParallelG = 1e-30f;          // axis treated as parallel to the
 #define FIBERHIT_PARENT_CACHE 1
 #endif
 constexpr bool kParentCache = FIBERHIT_PARENT_CACHE != 0;   // cache the latest both-hit parent in LDS
+#ifndef FIBERHIT_TRAVERSE_WAVES
+#define FIBERHIT_TRAVERSE_WAVES 8                  // traversal waves per SIMD the register budget must allow
+#endif
 
 struct V4 { float x, y, z, w; };
 struct Node { V4 p, d, t0, t1; };             // Section 3.1: p = p0, d = p3-p0, t0 = p1-p0, t1 = p3-p2
@@ -250,384 +253,34 @@ struct Args {
     const int32_t *pair_ray; const int32_t *pair_fiber; const uint8_t *pair_depth;
     int32_t depth; int64_t n_pairs;
     float *t_out; float *u_out; uint8_t *hit_out;
-    int32_t *counts;
+    int32_t *counts;                       // counting mode
+    double *t64_out; double *u64_out;      // refinement
 };
-
-struct Lane {
-    Node c;                       // current node, {p, d, t0, t1} in the ray frame
-    float lo, hi;                 // cropped t interval of the current node
-    float tmax, t;                // ray tmax; hit distance once found
-    uint32_t bits, start, size;   // Section 3.3: pending-sibling bits, integer interval
-    uint32_t min_size;            // leaf size 2^(23 - depth)
-    uint32_t cached;              // size of the pending children whose parent is cached (0: none)
-    float slack;                  // conservative mode: bound on across-ray rounding of any node
-    int32_t trips, splits, backtracks;
-};
-
-// Per-lane node storage for backtracking. The root is read only when a
-// backtrack replays the path from it; the parent of the most recent split
-// that left a sibling pending is cached so that the usual backtrack (to that
-// sibling) rebuilds it with one split instead of a replay. Both layouts keep
-// the cache in an LDS column per lane (conflict-free); the root lives in LDS
-// as well (frees 16 VGPRs) or in registers -- a tuning choice.
-template <bool LDS> struct RootStore;
-
-__device__ __forceinline__ void lds_put(float *col, const Node &r)
-{
-    const float *f = &r.p.x;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) col[k * kWave] = f[k];
-}
-
-__device__ __forceinline__ void lds_get(const float *col, Node &r)
-{
-    float *f = &r.p.x;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) f[k] = col[k * kWave];
-}
-
-template <> struct RootStore<true> {
-    float *col;                               // this lane's column of a [32][64] tile
-    __device__ __forceinline__ void put(const Node &r) { lds_put(col, r); }
-    __device__ __forceinline__ void get(Node &r) const { lds_get(col, r); }
-    __device__ __forceinline__ void put_parent(const Node &r) { lds_put(col + 16 * kWave, r); }
-    __device__ __forceinline__ void get_parent(Node &r) const { lds_get(col + 16 * kWave, r); }
-};
-
-template <> struct RootStore<false> {
-    Node root;
-    float *col;                               // this lane's column of a [16][64] tile
-    __device__ __forceinline__ void put(const Node &r) { root = r; }
-    __device__ __forceinline__ void get(Node &r) const { r = root; }
-    __device__ __forceinline__ void put_parent(const Node &r) { lds_put(col, r); }
-    __device__ __forceinline__ void get_parent(Node &r) const { lds_get(col, r); }
-};
-
-// Load pair i, move it into the ray frame and start the search. False when
-// the pair is a definite miss (bad index, depth, direction or tmax).
-template <class Store>
-__device__ __forceinline__ bool start_pair(const Args &a, int64_t i, Lane &L, Store &store)
-{
-    const int64_t ri = a.pair_ray ? (int64_t)a.pair_ray[i] : i;
-    const int64_t fi = a.pair_fiber ? (int64_t)a.pair_fiber[i] : i;
-    const uint32_t depth = a.pair_depth ? (uint32_t)a.pair_depth[i] : (uint32_t)a.depth;
-    if (ri < 0 || ri >= a.n_rays || fi < 0 || fi >= a.n_fibers || depth > FI_MAX_DEPTH) return false;
-    const float *R = a.rays + ri;
-    L.tmax = R[6 * a.ray_stride];
-    if (!(L.tmax == L.tmax)) return false;
-    Node root;
-    if (!root_in_ray_frame(R, a.ray_stride, a.fibers + fi, a.fiber_stride, root)) return false;
-    store.put(root);
-    L.c = root;
-    cap_interval(L.c, L.tmax, L.lo, L.hi);
-    L.bits = 0;
-    L.start = 0;
-    L.size = kRootSize;
-    L.min_size = kRootSize >> depth;
-    L.cached = 0;
-    // Each split rounds a node's position at the magnitude of its partial sum,
-    // which starts at the root's across-ray extent, so deep nodes inherit
-    // errors of a few ulp of that extent; 2^-18 of it is a generous bound.
-    L.slack = (fabsf(root.p.x) + fabsf(root.p.y) + fabsf(root.d.x) + fabsf(root.d.y) +
-               fabsf(root.t0.x) + fabsf(root.t0.y) + fabsf(root.t1.x) + fabsf(root.t1.y)) * 0x1p-18f;
-    L.trips = L.splits = L.backtracks = 0;
-    return true;
-}
-
-enum { kGoOn = 0, kHit = 1, kMiss = 2 };
-
-// Traversal variants: plain, counting, and conservative (for FP64 refinement:
-// every pruning test is enlarged by a bound on its FP32 rounding error, so no
-// surface point within that error is pruned; FP64 then decides).
-enum { kPlain = 0, kCount = 1, kConservative = 2 };
-
-// Bound on the rounding of a ray-plane distance c / n_z with c = <point, n>:
-// the products' magnitudes over |n_z| (obliquity amplifies), plus the size
-// of the result, at 2^-18 (64 ulp).
-__device__ __forceinline__ float plane_slack(float px, float py, float pz, float nx, float ny, float nz, float t)
-{
-    return (fabsf(px * nx) + fabsf(py * ny) + fabsf(pz * nz)) * rcp(fabsf(nz)) * 0x1p-18f +
-           fabsf(t) * 0x1p-18f;
-}
-
-// One loop trip of the paper's iteration (Appendix C, final listing): a
-// pruning test of the current node, then a descent, a leaf hit, a miss, or a
-// jump to the deepest pending sibling.
-// The common case (test, split, ordering, descent) is straight-line code for
-// every active lane: a lane that will stop still computes the split, which
-// costs nothing on a SIMD that runs it for its neighbours anyway, and avoids
-// divergent branches. Only the jump to a pending sibling branches.
-template <int MODE, class Store>
-__device__ __forceinline__ int trip(Lane &L, Store &store)
-{
-    float te, tx;
-    float rad = conservative_radius(L.c);
-    float lo = L.lo, hi = L.hi;
-    if (MODE == kConservative) {
-        rad += L.slack + rad * 0x1p-18f;
-        const float tslack = (fabsf(lo) + fabsf(hi < INFINITY ? hi : lo)) * 0x1p-17f;
-        lo -= tslack;
-        hi += tslack;
-    }
-    const bool vis = unit_ray_cylinder(L.c.p, L.c.d, rad, te, tx) && fmaxf(te, lo) <= fminf(tx, hi);
-    const bool leaf = L.size <= L.min_size;
-    if (++L.trips > kMaxTrips) return kMiss;
-    if (!vis) {
-        if (L.bits == 0) return kMiss;
-        // Section 3.3: jump to the deepest level with a pending sibling and
-        // rebuild its parent -- the cached node, or a replay of the split
-        // rules along the integer path from the root
-        L.size = L.bits & (0u - L.bits);
-        L.start ^= L.size;
-        L.bits ^= L.size;
-        L.start &= ~(L.size - 1u);
-        if (kParentCache && L.cached == L.size) {
-            store.get_parent(L.c);
-        } else {
-            store.get(L.c);
-            for (uint32_t b = kRootSize >> 1; b > L.size; b >>= 1) {
-                V4 dp, tc;
-                split_terms(L.c, dp, tc);
-                take_child(L.c, dp, tc, (L.start & b) != 0u);
-            }
-        }
-        L.cached = 0;
-        V4 dp, tc;
-        split_terms(L.c, dp, tc);
-        take_child(L.c, dp, tc, (L.start & L.size) != 0u);
-        cap_interval(L.c, L.tmax, L.lo, L.hi);
-        L.backtracks++;
-        return kGoOn;
-    }
-    // Section 3.2: split plane through the centre, normal to the split tangent
-    V4 dp, tc;
-    split_terms(L.c, dp, tc);
-    float nx = tc.x, ny = tc.y, nz = tc.z;
-    const bool flat = zero3(nx, ny, nz);
-    nx = flat ? L.c.d.x : nx;
-    ny = flat ? L.c.d.y : ny;
-    nz = flat ? L.c.d.z : nz;
-    const float qx = L.c.p.x + dp.x, qy = L.c.p.y + dp.y, qz = L.c.p.z + dp.z;
-    const float cs = dot3(qx, qy, qz, nx, ny, nz);
-    const float tp = cs * rcp(nz);
-    const bool oblique = nz != 0.0f;
-    bool right, both;
-    float nlo = L.lo, nhi = L.hi;
-    if (MODE == kConservative) {
-        // visit both halves unless the crossing is clearly outside [te, tx];
-        // narrow by the far side of tp's rounding bound
-        const float ep = plane_slack(qx, qy, qz, nx, ny, nz, tp);
-        both = oblique ? (te - ep < tp && tp < tx + ep)
-                       : (cs == 0.0f || fabsf(cs) <= L.slack * (fabsf(nx) + fabsf(ny)));
-        if (tp > te) nhi = fminf(nhi, tp + ep);
-        else         nlo = fmaxf(nlo, tp - ep);
-    } else {
-        both = oblique ? (te < tp && tp < tx) : cs == 0.0f;
-        if (tp > te) nhi = fminf(nhi, tp);
-        else         nlo = fmaxf(nlo, tp);
-    }
-    // the whole ray lies on the side of sign(-cs) when the plane is parallel
-    right = oblique ? ((tp > te) != (nz > 0.0f)) : cs < 0.0f;
-    if (oblique) { L.lo = nlo; L.hi = nhi; }
-    if (leaf) { L.t = fmaxf(te, lo); return kHit; }
-    if (kParentCache && both) store.put_parent(L.c);
-    take_child(L.c, dp, tc, right);
-    L.size >>= 1;
-    if (both) {
-        L.bits ^= L.size;
-        if (kParentCache) L.cached = L.size;
-    }
-    if (right) L.start ^= L.size;
-    L.splits++;
-    return kGoOn;
-}
-
-// Write the result of pair i (Section 3.3: u from projecting the hit point
-// onto the leaf chord; hit when t < tmax).
-template <int MODE>
-__device__ __forceinline__ void finish(const Args &a, int64_t i, const Lane &L, bool reached)
-{
-    float t = INFINITY, u = __builtin_nanf("");
-    bool hit = false;
-    if (reached && L.t < L.tmax) {
-        const float cc = dot3(L.c.d.x, L.c.d.y, L.c.d.z, L.c.d.x, L.c.d.y, L.c.d.z);
-        float ul = 0.0f;
-        if (cc > 0.0f) {
-            ul = dot3(-L.c.p.x, -L.c.p.y, L.t - L.c.p.z, L.c.d.x, L.c.d.y, L.c.d.z) * rcp(cc);
-            ul = fminf(1.0f, fmaxf(0.0f, ul));
-        }
-        t = L.t;
-        u = fmaf(ul, (float)L.size * 0x1p-23f, (float)L.start * 0x1p-23f);
-        hit = true;
-    }
-    a.t_out[i] = t;
-    a.u_out[i] = u;
-    a.hit_out[i] = hit ? 1 : 0;
-    if (MODE == kCount) {
-        int32_t *cn = a.counts + 4 * i;
-        cn[0] = L.trips;
-        cn[1] = L.splits;
-        cn[2] = L.backtracks;
-        cn[3] = hit ? (int32_t)(23 - (31 - __builtin_clz(L.size))) : -1;
-    }
-}
-
-template <int MODE>
-__device__ __forceinline__ void finish_invalid(const Args &a, int64_t i)
-{
-    a.t_out[i] = INFINITY;
-    a.u_out[i] = __builtin_nanf("");
-    a.hit_out[i] = 0;
-    if (MODE == kCount) {
-        int32_t *cn = a.counts + 4 * i;
-        cn[0] = 0; cn[1] = 0; cn[2] = 0; cn[3] = -1;
-    }
-}
 
 // ---------------------------------------------------------------------------
-// Persistent kernel: each 64-lane wave pulls pairs from a device queue and
-// refills finished lanes in batches, so lanes of uneven trip counts (a miss
-// ends after one or a few trips, a hit needs depth + 1 or more) keep the SIMD
-// busy instead of idling until the slowest lane of a fixed batch finishes.
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
-{
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
-// Scene of global pair g: offsets[s] <= g < offsets[s + 1] (empty scenes skipped).
-__device__ __forceinline__ int find_scene(const int64_t *offsets, int n_scenes, int64_t g)
-{
-    int lo = 0, hi = n_scenes;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (offsets[mid] <= g) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
-// queue[0]: next unclaimed pair; queue[1]: waves finished. The last wave to
-// finish returns both to zero, so the slot is ready for the next launch.
-// BATCHED: pairs are numbered across a table of scenes (one persistent
-// launch for many independent problems); otherwise the single problem a0.
-// Work distribution: wave w first owns the static range [w S, (w + 1) S)
-// (no atomics), then pulls dynamic chunks of `chunk` pairs from queue[0]
-// (one device-scope atomic per chunk, offset past all static ranges). Lanes
-// are refilled from the wave's current range, held in scalar registers.
-struct Sched {
-    int64_t static_per_wave;     // S
-    int32_t chunk;               // dynamic chunk, pairs
-    int32_t refill;              // refill once this many lanes are free
-};
-
-template <int MODE, bool BATCHED, bool ROOT_LDS>
-__global__ __launch_bounds__(kWave) void k_traverse(Args a0, const Args *scenes, const int64_t *offsets,
-                                                    int n_scenes, int64_t total, uint32_t *queue, Sched sc)
-{
-    __shared__ float s_nodes[((ROOT_LDS ? 16 : 0) + (kParentCache ? 16 : 0) + 1) * kWave];
-    const int lane = threadIdx.x;
-    RootStore<ROOT_LDS> store;
-    store.col = s_nodes + lane;
-    Lane L;
-    int64_t idx = 0;
-    int scene = 0;
-    bool active = false;
-    bool exhausted = false;
-    const int64_t dyn0 = (int64_t)gridDim.x * sc.static_per_wave;     // first dynamic pair
-    int64_t next = (int64_t)blockIdx.x * sc.static_per_wave;           // wave-uniform range
-    int64_t end = next + sc.static_per_wave < total ? next + sc.static_per_wave : total;
-    for (;;) {
-        const uint64_t free_mask = __ballot(!active);
-        const int n_free = __popcll(free_mask);
-        if (!exhausted && (n_free >= sc.refill || n_free == kWave)) {
-            if (next >= end && dyn0 >= total) {
-                exhausted = true;                  // static ranges cover every pair
-            } else if (next >= end) {
-                uint32_t base = 0;
-                if (lane == 0) base = atomicAdd(&queue[0], (uint32_t)sc.chunk);
-                base = __builtin_amdgcn_readfirstlane(base);
-                next = dyn0 + (int64_t)base;
-                end = next + sc.chunk < total ? next + sc.chunk : total;
-                if (next >= total) exhausted = true;
-            }
-            if (!exhausted) {
-                const int64_t avail = end - next;
-                const int take = avail < n_free ? (int)avail : n_free;
-                if (!active) {
-                    const int rank = (int)lanes_below(free_mask);
-                    if (rank < take) {
-                        const int64_t g = next + rank;
-                        if constexpr (BATCHED) {
-                            scene = find_scene(offsets, n_scenes, g);
-                            idx = g - offsets[scene];
-                            const Args a = scenes[scene];
-                            active = start_pair(a, idx, L, store);
-                            if (!active) finish_invalid<MODE>(a, idx);
-                        } else {
-                            idx = g;
-                            active = start_pair(a0, idx, L, store);
-                            if (!active) finish_invalid<MODE>(a0, idx);
-                        }
-                    }
-                }
-                next += take;
-            }
-        }
-        if (__ballot(active) == 0) {
-            if (exhausted) break;
-            continue;
-        }
-        if (active) {
-            const int st = trip<MODE>(L, store);
-            if (st != kGoOn) {
-                if constexpr (BATCHED) {
-                    const Args a = scenes[scene];
-                    finish<MODE>(a, idx, L, st == kHit);
-                } else {
-                    finish<MODE>(a0, idx, L, st == kHit);
-                }
-                active = false;
-            }
-        }
-    }
-    if (lane == 0) {
-        __threadfence();
-        const uint32_t done = atomicAdd(&queue[1], 1u);
-        if (done == gridDim.x - 1) {
-            atomicExch(&queue[0], 0u);
-            atomicExch(&queue[1], 0u);
-        }
-    }
-}
-
-// Zero a queue slot from inside a stream or graph (a kernel, not a memset
-// node, so that graph replays see a fresh queue).
-__global__ void k_reset_queue(uint32_t *queue)
-{
-    if (threadIdx.x < 2) queue[threadIdx.x] = 0u;
-}
-
-// ---------------------------------------------------------------------------
-// FP64 refinement of a hit onto the swept-disc surface
+// FP64 surface solve inside a leaf (FI_FP64_REFINE)
 // ---------------------------------------------------------------------------
 //
-// The leaf cylinders converge to the surface swept by a disc of radius r(u)
-// centred on C(u) and normal to C'(u) (Sec. 3.2: the limit surface of the
-// cylinders maps the intersection to the closest point on the curve). At
-// depth > 16 the FP32 leaf locates the entry to within a few leaf widths;
-// this step solves for the surface point in FP64:
-//   f1(t, u) = <P - C(u), C'(u)> = 0      (P = (0, 0, t): the ray point)
-//   f2(t, u) = |P - C(u)|^2 - r(u)^2 = 0
-// by Newton's method from the FP32 (t, u), accepts the root if it is an entry
-// (the signed distance decreases along the ray) close to the FP32 estimate,
-// and otherwise brackets the entry on a window of leaves around the FP32 u.
-// The end discs at u = 0 and u = 1 are candidates when the window reaches
-// them. No surface point near the leaf means the exact surface is missed.
+// The leaf cylinders converge to the solid swept by a disc of radius r(u)
+// centred on C(u) in the plane normal to C'(u) (Sec. 3.2: the limit surface
+// of the cylinders maps the intersection to the closest point on the curve),
+// closed by the end discs. With refinement, a pair of depth > 16 runs the
+// traversal with every pruning test enlarged by a bound on its FP32 rounding,
+// so that no leaf holding part of that solid along the ray is pruned, and each
+// leaf the search reaches is checked in FP64: the first point of the solid
+// along the ray whose disc parameter u lies in the leaf's interval. A leaf
+// with no such point counts as missed and the search goes on; leaves are
+// reached front to back, so the first leaf that holds the solid gives the hit.
+// In the ray frame (ray point P = (0, 0, t)):
+//   the ray meets the disc plane of u at   t(u) = <C, C'> / C'_z
+//   it lies in that disc when              phi(u) = |P(t(u)) - C(u)|^2 - r(u)^2 <= 0
+//   boundary points solve                  f1 = <P - C, C'> = 0, f2 = |P - C|^2 - r^2 = 0
+// Candidates: Newton's method on (f1, f2) from the FP32 leaf hit; roots of
+// phi on the leaf interval (sampled, bisected, then polished by Newton);
+// the end discs when the leaf touches u = 0 or 1; t = 0 when the origin lies
+// in one of the leaf's discs. The smallest candidate in [0, tmax) is the hit.
 
-constexpr int kRefineAbove = 16;         // refine hits at depth > 16
+constexpr int kRefineAbove = 16;         // refine pairs of depth > 16
 
 struct Curve64 { double q[4][4]; };      // control points in the FP64 ray frame (x, y, z, r)
 
@@ -728,94 +381,600 @@ __device__ __forceinline__ bool newton_surface(const Curve64 &c, double &t, doub
 
 // Bracketed search of the entry on [ua, ub]: sample the disc excess, take the
 // first sign change towards smaller t, bisect it.
-__device__ __forceinline__ bool bracket_surface(const Curve64 &c, double ua, double ub, double tmax,
-                                                double &t_best, double &u_best)
+
+// First point of the swept solid along the ray with u in [ua, ub] and t in
+// [0, tmax); (t0, u0) is the FP32 leaf hit. False when there is none.
+__device__ __forceinline__ bool refine_leaf(const Curve64 &c, double ua, double ub, double tmax, double t0,
+                                            double u0, double &t_best, double &u_best)
 {
-    constexpr int kSamples = 48;
-    bool found = false;
+    t_best = INFINITY;
+    u_best = __builtin_nan("");
+    {
+        double t = t0, u = u0;
+        if (newton_surface(c, t, u) && u >= ua && u <= ub && t >= 0.0 && t < tmax) {
+            t_best = t;
+            u_best = u;
+        }
+    }
+    constexpr int kSamples = 8;
+    const double h = (ub - ua) / kSamples;
     double pu = ua, pt = 0.0, pphi = 0.0;
     bool pok = disc_point(c, pu, pt, pphi);
     for (int k = 1; k <= kSamples; ++k) {
-        const double cu = ua + (ub - ua) * k / kSamples;
-        double ct, cphi;
+        const double cu = k == kSamples ? ub : ua + h * k;
+        double ct = 0.0, cphi = 0.0;
         const bool cok = disc_point(c, cu, ct, cphi);
         if (pok && cok && ((pphi <= 0.0) != (cphi <= 0.0))) {
+            // a boundary point: bisect phi, then polish on (f1, f2)
             double lo = pu, hi = cu;
-            const bool lo_inside = pphi <= 0.0;
-            for (int it = 0; it < 60; ++it) {
+            const bool lo_in = pphi <= 0.0;
+            for (int it = 0; it < 64; ++it) {
                 const double mid = 0.5 * (lo + hi);
                 double mt, mphi;
                 if (!disc_point(c, mid, mt, mphi)) break;
-                if ((mphi <= 0.0) == lo_inside) lo = mid; else hi = mid;
+                if ((mphi <= 0.0) == lo_in) lo = mid; else hi = mid;
             }
-            const double ur = 0.5 * (lo + hi);
-            double tr, phir;
+            double ur = 0.5 * (lo + hi), tr = 0.0, phir = 0.0;
             if (disc_point(c, ur, tr, phir)) {
-                double C[4], D[4], E[3];
-                eval_curve(c, ur, C, D, E);
-                if (tr >= 0.0 && tr < tmax && tr < t_best && entry_slope(C, D, E, tr) < 0.0) {
+                double tn = tr, un = ur;
+                bool entry;
+                if (newton_surface(c, tn, un) && fabs(un - ur) <= h) {
+                    tr = tn;
+                    ur = un;
+                    entry = true;
+                } else {
+                    double C[4], D[4], E[3];
+                    eval_curve(c, ur, C, D, E);
+                    entry = entry_slope(C, D, E, tr) < 0.0;
+                }
+                if (entry && tr >= 0.0 && tr < tmax && tr < t_best) {
                     t_best = tr;
                     u_best = ur;
-                    found = true;
                 }
+            }
+        }
+        if (pok && cok && ((pt <= 0.0) != (ct <= 0.0)) && (pphi <= 0.0 || cphi <= 0.0)) {
+            // the disc plane sweeps through the origin: is the origin in that disc?
+            double lo = pu, hi = cu;
+            const bool lo_neg = pt <= 0.0;
+            for (int it = 0; it < 64; ++it) {
+                const double mid = 0.5 * (lo + hi);
+                double mt, mphi;
+                if (!disc_point(c, mid, mt, mphi)) break;
+                if ((mt <= 0.0) == lo_neg) lo = mid; else hi = mid;
+            }
+            const double uz = 0.5 * (lo + hi);
+            double C[4], D[4], E[3];
+            eval_curve(c, uz, C, D, E);
+            if (C[0] * C[0] + C[1] * C[1] + C[2] * C[2] <= C[3] * C[3] && tmax > 0.0) {
+                t_best = 0.0;
+                u_best = uz;
             }
         }
         pu = cu; pt = ct; pphi = cphi; pok = cok;
     }
-    return found;
+    // end discs
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const double ue = (double)e;
+        if ((e == 0 && ua > 0.0) || (e == 1 && ub < 1.0)) continue;
+        double C[4], D[4], E[3];
+        eval_curve(c, ue, C, D, E);
+        if (D[2] == 0.0) continue;
+        const double tc = (C[0] * D[0] + C[1] * D[1] + C[2] * D[2]) / D[2];
+        const double hz = tc - C[2];
+        if (C[0] * C[0] + C[1] * C[1] + hz * hz <= C[3] * C[3] && tc >= 0.0 && tc < tmax && tc < t_best) {
+            t_best = tc;
+            u_best = ue;
+        }
+    }
+    return t_best < INFINITY;
 }
 
-__global__ __launch_bounds__(256) void k_refine(Args a, double *t64, double *u64)
+
+struct Lane {
+    Node c;                       // current node, {p, d, t0, t1} in the ray frame
+    float lo, hi;                 // cropped t interval of the current node
+    float tmax, t;                // ray tmax; hit distance once found
+    uint32_t bits, start, size;   // Section 3.3: pending-sibling bits, integer interval
+    uint32_t min_size;            // leaf size 2^(23 - depth)
+    uint32_t cached;              // size of the pending children whose parent is cached (0: none)
+    int32_t row;                  // row of this pair in the survivor table
+    float slack;                  // conservative mode: bound on across-ray rounding of any node
+                                  // (negative: a pair of depth <= 16, searched by the plain rules)
+    int32_t trips, splits, backtracks;
+    double t64, u64;              // refined hit
+};
+
+enum { kGoOn = 0, kHit = 1, kMiss = 2 };
+
+// Traversal variants: plain, counting, and conservative (for FP64 refinement:
+// every pruning test is enlarged by a bound on its FP32 rounding error, so no
+// surface point within that error is pruned; FP64 then decides).
+enum { kPlain = 0, kCount = 1, kConservative = 2 };
+
+// ---------------------------------------------------------------------------
+// Survivor table
+// ---------------------------------------------------------------------------
+//
+// The work of one call is split in two kernels. The setup kernel (one lane per
+// pair, no persistence) loads a pair, moves it into the ray frame in FP64 and
+// tests the root cylinder; a pair that misses its root (or is decided at the
+// root, depth 0) is written out at once, every other pair is appended to this
+// table: its root node, cap interval and tmax, in structure-of-arrays rows so
+// that the traversal kernel's refills are coalesced loads. The traversal
+// kernel then never holds FP64 state, which keeps its register count low
+// enough for twice the resident waves.
+constexpr int kTableFloats = 19;              // node (16), lo, hi, tmax
+
+struct Table {
+    float *f;                                 // kTableFloats rows of cap floats
+    int32_t *pair;                            // pair index within its problem
+    int32_t *scene;                           // problem of the pair (batched calls)
+    uint8_t *depth;                           // subdivision depth of the pair
+    int32_t cap;                              // rows (at most 2^20)
+};
+
+// Output arrays of one problem (what the kernels write).
+struct Outs {
+    float *t;
+    float *u;
+    uint8_t *hit;
+    int32_t *counts;
+    double *t64;
+    double *u64;
+};
+
+__host__ __device__ __forceinline__ Outs outs_of(const Args &a)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= a.n_pairs) return;
-    const uint32_t depth = a.pair_depth ? (uint32_t)a.pair_depth[i] : (uint32_t)a.depth;
-    const bool hit = a.hit_out[i] != 0;
-    const float t32 = a.t_out[i], u32 = a.u_out[i];
-    if (!hit || depth <= (uint32_t)kRefineAbove) {
-        t64[i] = hit ? (double)t32 : INFINITY;
-        u64[i] = hit ? (double)u32 : __builtin_nan("");
-        return;
-    }
+    return Outs{a.t_out, a.u_out, a.hit_out, a.counts, a.t64_out, a.u64_out};
+}
+
+__device__ __forceinline__ void table_put(const Table &tab, int32_t row, const Node &r, float lo, float hi,
+                                          float tmax, int32_t pair, int32_t scene, uint32_t depth)
+{
+    const float *f = &r.p.x;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) tab.f[k * tab.cap + row] = f[k];
+    tab.f[16 * tab.cap + row] = lo;
+    tab.f[17 * tab.cap + row] = hi;
+    tab.f[18 * tab.cap + row] = tmax;
+    tab.pair[row] = pair;
+    tab.scene[row] = scene;
+    tab.depth[row] = (uint8_t)depth;
+}
+
+__device__ __forceinline__ void table_root(const Table &tab, int32_t row, Node &r)
+{
+    float *f = &r.p.x;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) f[k] = tab.f[k * tab.cap + row];
+}
+
+// Per-lane LDS column (conflict-free: lane-contiguous rows of 64 floats) that
+// caches the parent of the most recent split that left a sibling pending, so
+// that the usual backtrack (to that sibling) rebuilds it with one split. Other
+// backtracks replay the split rules from the root, re-read from the table.
+__device__ __forceinline__ void lds_put(float *col, const Node &r)
+{
+    const float *f = &r.p.x;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) col[k * kWave] = f[k];
+}
+
+__device__ __forceinline__ void lds_get(const float *col, Node &r)
+{
+    float *f = &r.p.x;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) f[k] = col[k * kWave];
+}
+
+// Load pair i and move it into the ray frame. False when the pair is a
+// definite miss (bad index, depth, direction or tmax).
+__device__ __forceinline__ bool load_pair(const Args &a, int64_t i, Node &root, float &tmax, uint32_t &depth)
+{
     const int64_t ri = a.pair_ray ? (int64_t)a.pair_ray[i] : i;
     const int64_t fi = a.pair_fiber ? (int64_t)a.pair_fiber[i] : i;
+    depth = a.pair_depth ? (uint32_t)a.pair_depth[i] : (uint32_t)a.depth;
+    if (ri < 0 || ri >= a.n_rays || fi < 0 || fi >= a.n_fibers || depth > FI_MAX_DEPTH) return false;
     const float *R = a.rays + ri;
-    const double tmax = R[6 * a.ray_stride];
-    Curve64 c;
-    double t_best = INFINITY, u_best = __builtin_nan("");
-    if (curve_in_ray_frame(R, a.ray_stride, a.fibers + fi, a.fiber_stride, c)) {
-        double t = t32, u = u32;
-        const double leaf = ldexp(1.0, -(int)depth);
-        if (newton_surface(c, t, u) && u >= 0.0 && u <= 1.0 && t >= 0.0 && t < tmax &&
-            fabs(t - (double)t32) <= 1e-5 * fmax(1.0, fabs((double)t32)) && fabs(u - (double)u32) <= 256.0 * leaf + 1e-4) {
-            t_best = t;
-            u_best = u;
+    tmax = R[6 * a.ray_stride];
+    if (!(tmax == tmax)) return false;
+    return root_in_ray_frame(R, a.ray_stride, a.fibers + fi, a.fiber_stride, root);
+}
+
+// Each split rounds a node's position at the magnitude of its partial sum,
+// which starts at the root's across-ray extent, so deep nodes inherit errors
+// of a few ulp of that extent; 2^-18 of it is a generous bound.
+__device__ __forceinline__ float root_slack(const Node &r)
+{
+    return (fabsf(r.p.x) + fabsf(r.p.y) + fabsf(r.d.x) + fabsf(r.d.y) +
+            fabsf(r.t0.x) + fabsf(r.t0.y) + fabsf(r.t1.x) + fabsf(r.t1.y)) * 0x1p-18f;
+}
+
+// Pruning test of a node (Section 3.2): does the ray meet the conservative
+// cylinder inside the node's cropped interval? `lo_used` is the interval start
+// the test used (enlarged in conservative mode), from which a leaf's t is taken.
+template <int MODE>
+__device__ __forceinline__ bool node_visible(const Node &c, float lo, float hi, float slack, float &te,
+                                             float &tx, float &lo_used)
+{
+    float rad = conservative_radius(c);
+    if (MODE == kConservative && slack >= 0.0f) {
+        rad += slack + rad * 0x1p-18f;
+        const float tslack = (fabsf(lo) + fabsf(hi < INFINITY ? hi : lo)) * 0x1p-17f;
+        lo -= tslack;
+        hi += tslack;
+    }
+    lo_used = lo;
+    return unit_ray_cylinder(c.p, c.d, rad, te, tx) && fmaxf(te, lo) <= fminf(tx, hi);
+}
+
+// Bound on the rounding of a ray-plane distance c / n_z with c = <point, n>:
+// the products' magnitudes over |n_z| (obliquity amplifies), plus the size
+// of the result, at 2^-18 (64 ulp).
+__device__ __forceinline__ float plane_slack(float px, float py, float pz, float nx, float ny, float nz, float t)
+{
+    return (fabsf(px * nx) + fabsf(py * ny) + fabsf(pz * nz)) * rcp(fabsf(nz)) * 0x1p-18f +
+           fabsf(t) * 0x1p-18f;
+}
+
+// FP64 check of a leaf reached by the conservative search (pair of depth
+// > 16): sets L.t64 / L.u64 and returns true when the swept solid is entered
+// inside the leaf's u interval (widened by an eighth of a leaf on each side).
+// u of a leaf hit (Section 3.3): the hit point projected onto the leaf chord.
+__device__ __forceinline__ float leaf_u(const Lane &L)
+{
+    const float cc = dot3(L.c.d.x, L.c.d.y, L.c.d.z, L.c.d.x, L.c.d.y, L.c.d.z);
+    float ul = 0.0f;
+    if (cc > 0.0f) {
+        ul = dot3(-L.c.p.x, -L.c.p.y, L.t - L.c.p.z, L.c.d.x, L.c.d.y, L.c.d.z) * rcp(cc);
+        ul = fminf(1.0f, fmaxf(0.0f, ul));
+    }
+    return fmaf(ul, (float)L.size * 0x1p-23f, (float)L.start * 0x1p-23f);
+}
+
+__device__ __noinline__ bool refine_at_leaf(Lane &L, const Table &tab, const Args &in)
+{
+    const int64_t i = tab.pair[L.row];
+    const int64_t ri = in.pair_ray ? (int64_t)in.pair_ray[i] : i;
+    const int64_t fi = in.pair_fiber ? (int64_t)in.pair_fiber[i] : i;
+    Curve64 cv;
+    if (!curve_in_ray_frame(in.rays + ri, in.ray_stride, in.fibers + fi, in.fiber_stride, cv)) return false;
+    const double w = (double)L.size * 0x1p-23;
+    const double ua = fmax(0.0, (double)L.start * 0x1p-23 - 0.125 * w);
+    const double ub = fmin(1.0, (double)(L.start + L.size) * 0x1p-23 + 0.125 * w);
+    double t, u;
+    if (!refine_leaf(cv, ua, ub, (double)L.tmax, (double)L.t, (double)leaf_u(L), t, u)) return false;
+    L.t64 = t;
+    L.u64 = u;
+    return true;
+}
+
+// One loop trip of the paper's iteration (Appendix C, final listing): a
+// pruning test of the current node, then a descent, a leaf hit, a miss, or a
+// jump to the deepest pending sibling.
+// The common case (test, split, ordering, descent) is straight-line code for
+// every active lane: a lane that will stop still computes the split, which
+// costs nothing on a SIMD that runs it for its neighbours anyway, and avoids
+// divergent branches. Only the jump to a pending sibling branches.
+template <int MODE>
+__device__ __forceinline__ int trip(Lane &L, const Table &tab, float *col, const Args &in)
+{
+    float te, tx, lo;
+    bool vis = node_visible<MODE>(L.c, L.lo, L.hi, L.slack, te, tx, lo);
+    const bool leaf = L.size <= L.min_size;
+    if (++L.trips > kMaxTrips) return kMiss;
+    if (MODE == kConservative && vis && leaf && L.slack >= 0.0f) {
+        // refinement: the first point of the swept solid in this leaf, else go on
+        L.t = fmaxf(te, lo);
+        if (refine_at_leaf(L, tab, in)) return kHit;
+        vis = false;
+    }
+    if (!vis) {
+        if (L.bits == 0) return kMiss;
+        // Section 3.3: jump to the deepest level with a pending sibling and
+        // rebuild it -- one split of the cached parent, or a replay of the
+        // split rules along the integer path from the root
+        L.size = L.bits & (0u - L.bits);
+        L.start ^= L.size;
+        L.bits ^= L.size;
+        L.start &= ~(L.size - 1u);
+        if (kParentCache && L.cached == L.size) {
+            lds_get(col, L.c);
         } else {
-            const double w = fmax(256.0 * leaf, 1e-4);
-            bracket_surface(c, fmax(0.0, (double)u32 - w), fmin(1.0, (double)u32 + w), tmax, t_best, u_best);
+            table_root(tab, L.row, L.c);
+            for (uint32_t b = kRootSize >> 1; b > L.size; b >>= 1) {
+                V4 dp, tc;
+                split_terms(L.c, dp, tc);
+                take_child(L.c, dp, tc, (L.start & b) != 0u);
+            }
         }
-        // end discs within reach of the FP32 estimate
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const double ue = (double)e;
-            if (fabs(ue - (double)u32) > fmax(256.0 * leaf, 1e-4)) continue;
-            double C[4], D[4], E[3];
-            eval_curve(c, ue, C, D, E);
-            if (D[2] == 0.0) continue;
-            const double tc = (C[0] * D[0] + C[1] * D[1] + C[2] * D[2]) / D[2];
-            const double h = tc - C[2];
-            if (C[0] * C[0] + C[1] * C[1] + h * h <= C[3] * C[3] && tc >= 0.0 && tc < tmax && tc < t_best) {
-                t_best = tc;
-                u_best = ue;
+        L.cached = 0;
+        V4 dp, tc;
+        split_terms(L.c, dp, tc);
+        take_child(L.c, dp, tc, (L.start & L.size) != 0u);
+        cap_interval(L.c, L.tmax, L.lo, L.hi);
+        L.backtracks++;
+        return kGoOn;
+    }
+    // Section 3.2: split plane through the centre, normal to the split tangent
+    V4 dp, tc;
+    split_terms(L.c, dp, tc);
+    float nx = tc.x, ny = tc.y, nz = tc.z;
+    const bool flat = zero3(nx, ny, nz);
+    nx = flat ? L.c.d.x : nx;
+    ny = flat ? L.c.d.y : ny;
+    nz = flat ? L.c.d.z : nz;
+    const float qx = L.c.p.x + dp.x, qy = L.c.p.y + dp.y, qz = L.c.p.z + dp.z;
+    const float cs = dot3(qx, qy, qz, nx, ny, nz);
+    const float tp = cs * rcp(nz);
+    const bool oblique = nz != 0.0f;
+    bool both;
+    float nlo = L.lo, nhi = L.hi;
+    if (MODE == kConservative && L.slack >= 0.0f) {
+        // visit both halves unless the crossing is clearly outside [te, tx];
+        // narrow by the far side of tp's rounding bound
+        const float ep = plane_slack(qx, qy, qz, nx, ny, nz, tp);
+        both = oblique ? (te - ep < tp && tp < tx + ep)
+                       : (cs == 0.0f || fabsf(cs) <= L.slack * (fabsf(nx) + fabsf(ny)));
+        if (tp > te) nhi = fminf(nhi, tp + ep);
+        else         nlo = fmaxf(nlo, tp - ep);
+    } else {
+        both = oblique ? (te < tp && tp < tx) : cs == 0.0f;
+        if (tp > te) nhi = fminf(nhi, tp);
+        else         nlo = fmaxf(nlo, tp);
+    }
+    // a plane parallel to the ray leaves the whole ray on the side of sign(-cs)
+    const bool right = oblique ? ((tp > te) != (nz > 0.0f)) : cs < 0.0f;
+    if (oblique) { L.lo = nlo; L.hi = nhi; }
+    if (leaf) { L.t = fmaxf(te, lo); return kHit; }
+    if (kParentCache && both) lds_put(col, L.c);
+    take_child(L.c, dp, tc, right);
+    L.size >>= 1;
+    if (both) {
+        L.bits ^= L.size;
+        if (kParentCache) L.cached = L.size;
+    }
+    if (right) L.start ^= L.size;
+    L.splits++;
+    return kGoOn;
+}
+
+// Write the result of pair i (Section 3.3: u from projecting the hit point
+// onto the leaf chord; hit when t < tmax). A refined pair (depth > 16 under
+// FI_FP64_REFINE) reports its FP64 surface hit, decided in FP64.
+template <int MODE>
+__device__ __forceinline__ void finish(const Outs &a, int64_t i, const Lane &L, bool reached)
+{
+    float t = INFINITY, u = __builtin_nanf("");
+    double t64 = INFINITY, u64 = __builtin_nan("");
+    bool hit = false;
+    if (MODE == kConservative && L.slack >= 0.0f) {
+        if (reached) {
+            t64 = L.t64;
+            u64 = L.u64;
+            t = (float)t64;
+            u = (float)u64;
+            hit = true;
+        }
+    } else if (reached && L.t < L.tmax) {
+        t = L.t;
+        u = leaf_u(L);
+        t64 = t;
+        u64 = u;
+        hit = true;
+    }
+    a.t[i] = t;
+    a.u[i] = u;
+    a.hit[i] = hit ? 1 : 0;
+    if (MODE == kConservative) {
+        a.t64[i] = t64;
+        a.u64[i] = u64;
+    }
+    if (MODE == kCount) {
+        int32_t *cn = a.counts + 4 * i;
+        cn[0] = L.trips;
+        cn[1] = L.splits;
+        cn[2] = L.backtracks;
+        cn[3] = hit ? (int32_t)(23 - (31 - __builtin_clz(L.size))) : -1;
+    }
+}
+
+template <int MODE>
+__device__ __forceinline__ void finish_invalid(const Args &a, int64_t i)
+{
+    a.t_out[i] = INFINITY;
+    a.u_out[i] = __builtin_nanf("");
+    a.hit_out[i] = 0;
+    if (MODE == kConservative) {
+        a.t64_out[i] = INFINITY;
+        a.u64_out[i] = __builtin_nan("");
+    }
+    if (MODE == kCount) {
+        int32_t *cn = a.counts + 4 * i;
+        cn[0] = 0; cn[1] = 0; cn[2] = 0; cn[3] = -1;
+    }
+}
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Scene of global pair g: offsets[s] <= g < offsets[s + 1] (empty scenes skipped).
+__device__ __forceinline__ int find_scene(const int64_t *offsets, int n_scenes, int64_t g)
+{
+    int lo = 0, hi = n_scenes;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (offsets[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Survivor rows are grouped in kBuckets buckets of cap / kBuckets rows each:
+// setup block k appends its survivors to bucket k mod kBuckets with one
+// atomic on that bucket's counter. Spreading the appends over many counters
+// matters on this chip: device-scope atomics on one address serialise across
+// all eight XCDs. Traversal wave w drains an even share of bucket
+// w mod n_buckets with no atomics at all. Two sets of counters alternate
+// between consecutive chunks: the setup kernel of a chunk zeroes the set the
+// previous chunk used, so no reset kernel is needed between chunks.
+constexpr int kSetupBlock = 256;
+constexpr int kBuckets = 256;                 // equal to kSetupBlock: block 0 zeroes one counter per thread
+static_assert(kBuckets == kSetupBlock, "setup block 0 clears one counter per thread");
+constexpr int kCounterWords = 2 * kBuckets;   // two sets
+
+// Setup kernel: pairs [begin, begin + count) of the call (numbered across the
+// scene table when BATCHED), one lane each.
+template <int MODE, bool BATCHED>
+__global__ __launch_bounds__(kSetupBlock) void k_setup(Args a0, const Args *scenes, const int64_t *offsets,
+                                                      int n_scenes, int64_t begin, int64_t count, Table tab,
+                                                      uint32_t *counts, uint32_t *stale)
+{
+    __shared__ uint32_t s_wave[kSetupBlock / kWave];
+    __shared__ uint32_t s_base;
+    if (blockIdx.x == 0) stale[threadIdx.x] = 0u;     // counters of the previous chunk
+    const int64_t k = (int64_t)blockIdx.x * kSetupBlock + threadIdx.x;
+    bool keep = false;
+    Node root;
+    float lo = 0.0f, hi = 0.0f, tmax = 0.0f;
+    uint32_t depth = 0;
+    int64_t idx = 0;
+    int scene = 0;
+    if (k < count) {
+        const int64_t g = begin + k;
+        Args a = a0;
+        if constexpr (BATCHED) {
+            scene = find_scene(offsets, n_scenes, g);
+            idx = g - offsets[scene];
+            a = scenes[scene];
+        } else {
+            idx = g;
+        }
+        if (!load_pair(a, idx, root, tmax, depth)) {
+            finish_invalid<MODE>(a, idx);
+        } else {
+            cap_interval(root, tmax, lo, hi);
+            float te, tx, lu;
+            const float slack = MODE == kConservative && depth > kRefineAbove ? root_slack(root) : -1.0f;
+            const bool vis = node_visible<MODE>(root, lo, hi, slack, te, tx, lu);
+            if (vis && depth > 0) {
+                keep = true;
+            } else {
+                // decided at the root: a miss, or the root is the leaf
+                Lane L;
+                L.c = root;
+                L.slack = slack;
+                L.t = fmaxf(te, lu);
+                L.tmax = tmax;
+                L.start = 0;
+                L.size = kRootSize;
+                L.trips = 1;
+                L.splits = 0;
+                L.backtracks = 0;
+                finish<MODE>(outs_of(a), idx, L, vis);
             }
         }
     }
-    const bool ok = t_best < INFINITY;
-    t64[i] = t_best;
-    u64[i] = u_best;
-    a.hit_out[i] = ok ? 1 : 0;
-    a.t_out[i] = ok ? (float)t_best : INFINITY;
-    a.u_out[i] = ok ? (float)u_best : __builtin_nanf("");
+    // append the block's survivors to its bucket: one atomic per block
+    const uint64_t m = __ballot(keep);
+    const int wave = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) s_wave[wave] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t n = 0;
+        for (int w = 0; w < kSetupBlock / kWave; ++w) n += s_wave[w];
+        s_base = n ? atomicAdd(&counts[blockIdx.x % kBuckets], n) : 0u;
+    }
+    __syncthreads();
+    if (keep) {
+        uint32_t off = s_base + lanes_below(m);
+        for (int w = 0; w < wave; ++w) off += s_wave[w];
+        const int32_t bucket_rows = tab.cap / kBuckets;
+        table_put(tab, (int32_t)(blockIdx.x % kBuckets) * bucket_rows + (int32_t)off, root, lo, hi, tmax,
+                  (int32_t)idx, scene, depth);
+    }
+}
+
+// Traversal kernel: each 64-lane wave drains an even share of one bucket and
+// refills finished lanes in batches, so lanes of uneven trip counts keep the
+// SIMD busy instead of idling until the slowest lane of a fixed batch
+// finishes. The attribute sets the register budget: 64 VGPRs (eight waves
+// per SIMD, the most gfx950 runs) hold the plain traversal without spills;
+// the counting and conservative variants get 80 (six waves).
+template <int MODE, bool BATCHED>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MODE == kPlain ? FIBERHIT_TRAVERSE_WAVES : 6, 8)))
+void k_traverse(Args a0, const Args *scenes, Table tab, const uint32_t *counts, int n_buckets, int refill)
+{
+    __shared__ float s_cache[(kParentCache ? 16 : 1) * kWave];
+    const int lane = threadIdx.x;
+    float *col = s_cache + lane;
+    const int b = (int)(blockIdx.x % (unsigned)n_buckets);
+    const int j = (int)(blockIdx.x / (unsigned)n_buckets);
+    const int waves = (int)((gridDim.x - (unsigned)b + (unsigned)n_buckets - 1) / (unsigned)n_buckets);
+    const int rows = (int)counts[b];
+    const int share = (rows + waves - 1) / waves;
+    const int first = b * (tab.cap / kBuckets);
+    int next = first + (j * share < rows ? j * share : rows);          // wave-uniform range
+    const int end = first + ((j + 1) * share < rows ? (j + 1) * share : rows);
+    Lane L;
+    bool active = false;
+    for (;;) {
+        const uint64_t free_mask = __ballot(!active);
+        const int n_free = __popcll(free_mask);
+        if (next < end && (n_free >= refill || n_free == kWave)) {
+            const int avail = end - next;
+            const int take = avail < n_free ? avail : n_free;
+            if (!active) {
+                const int rank = (int)lanes_below(free_mask);
+                if (rank < take) {
+                    const int r = next + rank;
+                    table_root(tab, r, L.c);
+                    L.lo = tab.f[16 * tab.cap + r];
+                    L.hi = tab.f[17 * tab.cap + r];
+                    L.tmax = tab.f[18 * tab.cap + r];
+                    const uint32_t depth = tab.depth[r];
+                    L.min_size = kRootSize >> depth;
+                    L.row = r;
+                    L.bits = 0;
+                    L.start = 0;
+                    L.size = kRootSize;
+                    L.cached = 0;
+                    L.slack = MODE == kConservative && depth > kRefineAbove ? root_slack(L.c) : -1.0f;
+                    L.trips = L.splits = L.backtracks = 0;
+                    active = true;
+                }
+            }
+            next += take;
+        }
+        if (__ballot(active) == 0) {
+            if (next >= end) break;
+            continue;
+        }
+        if (active) {
+            const int st = trip<MODE>(L, tab, col, a0);
+            if (st != kGoOn) {
+                const int64_t i = tab.pair[L.row];
+                if constexpr (BATCHED) {
+                    finish<MODE>(outs_of(scenes[tab.scene[L.row]]), i, L, st == kHit);
+                } else {
+                    finish<MODE>(outs_of(a0), i, L, st == kHit);
+                }
+                active = false;
+            }
+        }
+    }
+}
+
+// Zero both counter sets from inside a stream or graph (a kernel, not a
+// memset node, so that graph replays see fresh counters).
+__global__ void k_reset_counters(uint32_t *counters)
+{
+    for (int k = threadIdx.x; k < kCounterWords; k += blockDim.x) counters[k] = 0u;
 }
 
 int check_common(const float *rays, int64_t ray_stride, int64_t n_rays,
@@ -832,41 +991,98 @@ int check_common(const float *rays, int64_t ray_stride, int64_t n_rays,
     if (ray_stride < n_rays || fiber_stride < n_fibers) return FI_ERR_RANGE;
     if (!pair_ray && n_pairs > n_rays) return FI_ERR_RANGE;
     if (!pair_fiber && n_pairs > n_fibers) return FI_ERR_RANGE;
-    if (n_pairs > (int64_t)0x7fffffff - 64) return FI_ERR_RANGE;   // 32-bit work queue
+    if (n_pairs > (int64_t)0x7fffffff - 64) return FI_ERR_RANGE;   // int32 pair indices in the table
     return FI_OK;
 }
 
 // ---------------------------------------------------------------------------
-// Kernel variants, work-queue slots and launch shape
+// Kernel variants, counters, survivor tables and launch shape
 // ---------------------------------------------------------------------------
 
-using TraverseFn = void (*)(Args, const Args *, const int64_t *, int, int64_t, uint32_t *, Sched);
+using SetupFn = void (*)(Args, const Args *, const int64_t *, int, int64_t, int64_t, Table, uint32_t *,
+                         uint32_t *);
+using TraverseFn = void (*)(Args, const Args *, Table, const uint32_t *, int, int);
 
-// [mode][batched][root in LDS]
-const TraverseFn kTraverse[3][2][2] = {
-    {{k_traverse<kPlain, false, false>, k_traverse<kPlain, false, true>},
-     {k_traverse<kPlain, true, false>, k_traverse<kPlain, true, true>}},
-    {{k_traverse<kCount, false, false>, k_traverse<kCount, false, true>},
-     {k_traverse<kCount, true, false>, k_traverse<kCount, true, true>}},
-    {{k_traverse<kConservative, false, false>, k_traverse<kConservative, false, true>},
-     {k_traverse<kConservative, true, false>, k_traverse<kConservative, true, true>}},
+// [mode][batched]. Batched calls take neither counts nor refinement: their
+// table rows for those modes hold the plain kernels and are never launched.
+const SetupFn kSetup[3][2] = {
+    {k_setup<kPlain, false>, k_setup<kPlain, true>},
+    {k_setup<kCount, false>, k_setup<kPlain, true>},
+    {k_setup<kConservative, false>, k_setup<kPlain, true>},
+};
+const TraverseFn kTraverse[3][2] = {
+    {k_traverse<kPlain, false>, k_traverse<kPlain, true>},
+    {k_traverse<kCount, false>, k_traverse<kPlain, true>},
+    {k_traverse<kConservative, false>, k_traverse<kPlain, true>},
 };
 
-// Queue slots in a file-scope device array (zero at load; each launch leaves
-// its slot zero). Launches take slots round-robin, so up to kSlots launches
-// may be in flight at once on one device without sharing a slot.
-constexpr int kSlots = 256;
-__device__ __align__(256) uint32_t g_queue_slots[kSlots * 2];
+// Pairs per chunk: the setup kernel covers at most this many pairs before the
+// traversal kernel drains their survivors. Table sizes are multiples of
+// kBuckets * kSetupBlock rows, so that every setup block's survivors fit its
+// bucket (a bucket holds rows of at most cap / (kBuckets * kSetupBlock)
+// blocks of kSetupBlock pairs each).
+constexpr int64_t kTableQuantum = (int64_t)kBuckets * kSetupBlock;
+constexpr int64_t kChunkRows = 1 << 20;
+static_assert(kChunkRows % kTableQuantum == 0, "chunk must be a whole number of table quanta");
+
+constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Bytes of a survivor table of `rows` rows, and its layout at `base`.
+size_t table_region_bytes(int64_t rows)
+{
+    return align256((size_t)rows * kTableFloats * sizeof(float)) + 2 * align256((size_t)rows * sizeof(int32_t)) +
+           align256((size_t)rows);
+}
+
+Table table_at(void *base, int64_t rows)
+{
+    char *p = (char *)base;
+    Table t;
+    t.cap = (int32_t)rows;
+    t.f = (float *)p;
+    p += align256((size_t)rows * kTableFloats * sizeof(float));
+    t.pair = (int32_t *)p;
+    p += align256((size_t)rows * sizeof(int32_t));
+    t.scene = (int32_t *)p;
+    p += align256((size_t)rows * sizeof(int32_t));
+    t.depth = (uint8_t *)p;
+    return t;
+}
+
+// Rows a call of `total` pairs uses: one chunk at most, a whole number of
+// table quanta.
+int64_t rows_for(int64_t total)
+{
+    const int64_t r = total < kChunkRows ? total : kChunkRows;
+    return ((r > 0 ? r : 1) + kTableQuantum - 1) / kTableQuantum * kTableQuantum;
+}
+
+// Single-problem calls keep kRegions survivor tables per device, allocated at
+// the first call that needs one and used round-robin; a call waits on its
+// stream (through an event) for the previous call that used its table. Their
+// bucket counters live in a file-scope device array, zero at load.
+constexpr int kRegions = 2;
+__device__ __align__(256) uint32_t g_counters[kRegions * kCounterWords];
 
 constexpr int kMaxDevices = 64;
 constexpr int kStageSlots = 4;                 // pinned staging for batched scene tables
 constexpr size_t kStageBytes = 1u << 20;
 
+struct Region {
+    std::mutex m;
+    void *mem;                                 // survivor table of kChunkRows rows
+    uint32_t *counters;                        // two sets of kBuckets counters
+    int parity;                                // the set that is zero for the next chunk
+    hipEvent_t done;                           // recorded after the last call that used it
+    bool pending;
+};
+
 struct DeviceInfo {
     std::atomic<bool> ready;
-    uint32_t *slots;                           // device address of g_queue_slots on this device
     int cus;
-    int resident[3][2][2];                     // resident 64-lane workgroups per CU, per variant
+    int resident[3][2];                        // resident traversal waves per CU, per variant
+    Region region[kRegions];
+    std::atomic<uint32_t> next_region;
     std::mutex stage_mutex;
     void *stage[kStageSlots];                  // pinned host buffers (allocated on first batched call)
     hipEvent_t stage_done[kStageSlots];
@@ -874,7 +1090,6 @@ struct DeviceInfo {
 };
 DeviceInfo g_dev[kMaxDevices];
 std::mutex g_dev_mutex;
-std::atomic<uint32_t> g_next_slot{0};
 
 int current_device(int &dev)
 {
@@ -891,19 +1106,25 @@ int device_info(DeviceInfo *&out)
         std::lock_guard<std::mutex> lock(g_dev_mutex);
         if (!d.ready.load(std::memory_order_relaxed)) {
             void *p = nullptr;
-            if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_queue_slots)) != hipSuccess || !p) return FI_ERR_HIP;
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_counters)) != hipSuccess || !p) return FI_ERR_HIP;
             if (hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
                 return FI_ERR_HIP;
             for (int m = 0; m < 3; ++m)
-                for (int b = 0; b < 2; ++b)
-                    for (int l = 0; l < 2; ++l) {
-                        int nb = 0;
-                        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)kTraverse[m][b][l],
-                                                                         kWave, 0) != hipSuccess)
-                            return FI_ERR_HIP;
-                        d.resident[m][b][l] = nb > 0 ? nb : 1;
-                    }
-            d.slots = (uint32_t *)p;
+                for (int b = 0; b < 2; ++b) {
+                    int nb = 0;
+                    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)kTraverse[m][b], kWave, 0) !=
+                        hipSuccess)
+                        return FI_ERR_HIP;
+                    d.resident[m][b] = nb > 0 ? nb : 1;
+                }
+            for (int r = 0; r < kRegions; ++r) {
+                d.region[r].mem = nullptr;
+                d.region[r].counters = (uint32_t *)p + r * kCounterWords;
+                d.region[r].parity = 0;
+                d.region[r].done = nullptr;
+                d.region[r].pending = false;
+            }
+            d.next_region.store(0u);
             d.stage_next = 0;
             d.ready.store(true, std::memory_order_release);
         }
@@ -920,19 +1141,9 @@ int device_info(DeviceInfo *&out)
 #ifndef FIBERHIT_DEFAULT_WAVES_PER_SIMD
 #define FIBERHIT_DEFAULT_WAVES_PER_SIMD 0
 #endif
-#ifndef FIBERHIT_DEFAULT_ROOT_IN_LDS
-#define FIBERHIT_DEFAULT_ROOT_IN_LDS 0
-#endif
-#ifndef FIBERHIT_DEFAULT_CHUNK
-#define FIBERHIT_DEFAULT_CHUNK 128
-#endif
-#ifndef FIBERHIT_DEFAULT_STATIC_PCT
-#define FIBERHIT_DEFAULT_STATIC_PCT 100
-#endif
 fi_tuning default_tuning()
 {
-    return fi_tuning{FIBERHIT_DEFAULT_REFILL, FIBERHIT_DEFAULT_WAVES_PER_SIMD, FIBERHIT_DEFAULT_ROOT_IN_LDS,
-                     FIBERHIT_DEFAULT_CHUNK, FIBERHIT_DEFAULT_STATIC_PCT};
+    return fi_tuning{FIBERHIT_DEFAULT_REFILL, FIBERHIT_DEFAULT_WAVES_PER_SIMD};
 }
 
 // Autotune results, kept for the process: keyed by device and the size class
@@ -976,64 +1187,70 @@ int64_t total_pairs(const fi_scene *sc, int32_t n)
 
 int check_tuning(const fi_tuning &t)
 {
-    if (t.refill < 1 || t.refill > kWave || t.waves_per_simd < -1 || t.waves_per_simd > 16 ||
-        (t.root_in_lds != 0 && t.root_in_lds != 1) || t.chunk < 1 || t.chunk > (1 << 16) ||
-        t.static_pct < 0 || t.static_pct > 100)
-        return FI_ERR_RANGE;
+    if (t.refill < 1 || t.refill > kWave || t.waves_per_simd < 0 || t.waves_per_simd > 16) return FI_ERR_RANGE;
     return FI_OK;
 }
 
-unsigned grid_for(const DeviceInfo &d, int mode, bool batched, const fi_tuning &t, int64_t n_pairs)
+// Traversal grid for a chunk of `count` pairs: about one wave per 64 pairs, at
+// most the resident waves, and a whole number of waves per used bucket.
+unsigned traverse_grid(const DeviceInfo &d, int mode, bool batched, const fi_tuning &t, int64_t count,
+                       int n_buckets)
 {
-    const int64_t needed = (n_pairs + kWave - 1) / kWave;
-    if (t.waves_per_simd < 0) return (unsigned)needed;       // one wave per 64 pairs: plain grid
-    int per_cu = d.resident[mode][batched ? 1 : 0][t.root_in_lds];
+    int per_cu = d.resident[mode][batched ? 1 : 0];
     if (t.waves_per_simd > 0 && 4 * t.waves_per_simd < per_cu) per_cu = 4 * t.waves_per_simd;
     const int64_t resident = (int64_t)per_cu * d.cus;
-    return (unsigned)(needed < resident ? needed : resident);
+    int64_t g = (count + kWave - 1) / kWave;
+    if (g > resident) g = resident;
+    g = (g + n_buckets - 1) / n_buckets * n_buckets;
+    return (unsigned)g;
 }
 
-Sched sched_for(const fi_tuning &t, unsigned grid, int64_t total)
+// Enqueue setup + traversal for `total` pairs, chunk by chunk through `tab`.
+// counters[parity * kBuckets ..] must be zero; returns the set that is zero
+// after the last chunk.
+int launch_chain(const DeviceInfo &d, int mode, bool batched, const fi_tuning &t, const Args &a0,
+                 const Args *scenes, const int64_t *offsets, int n_scenes, int64_t total, const Table &tab,
+                 uint32_t *counters, int parity, hipStream_t s)
 {
-    Sched sc;
-    // static share: static_pct % of an even split, in whole lane batches
-    const int64_t even = grid ? total / grid : 0;
-    sc.static_per_wave = (even * t.static_pct / 100) / kWave * kWave;
-    // one wave per lane batch: each wave owns exactly its batch, no queue
-    if (t.waves_per_simd < 0) sc.static_per_wave = kWave;
-    sc.chunk = t.chunk;
-    sc.refill = t.refill;
-    return sc;
+    const int b = batched ? 1 : 0;
+    for (int64_t begin = 0; begin < total; begin += tab.cap) {
+        const int64_t count = total - begin < tab.cap ? total - begin : tab.cap;
+        const int64_t blocks = (count + kSetupBlock - 1) / kSetupBlock;
+        const int n_buckets = blocks < kBuckets ? (int)blocks : kBuckets;
+        uint32_t *cur = counters + parity * kBuckets;
+        uint32_t *other = counters + (1 - parity) * kBuckets;
+        hipLaunchKernelGGL(kSetup[mode][b], dim3((unsigned)blocks), dim3(kSetupBlock), 0, s, a0, scenes, offsets,
+                           n_scenes, begin, count, tab, cur, other);
+        hipLaunchKernelGGL(kTraverse[mode][b], dim3(traverse_grid(d, mode, batched, t, count, n_buckets)),
+                           dim3(kWave), 0, s, a0, scenes, tab, (const uint32_t *)cur, n_buckets, t.refill);
+        parity = 1 - parity;
+    }
+    return parity;
 }
 
-int launch_traverse(const DeviceInfo &d, int mode, bool batched, const fi_tuning &t, const Args &a0,
-                    const Args *scenes, const int64_t *offsets, int n_scenes, int64_t total,
-                    uint32_t *queue, hipStream_t s)
-{
-    const unsigned grid = grid_for(d, mode, batched, t, total);
-    if (grid == 0) return FI_OK;
-    // queue[0] ends below total + (grid + 1) * chunk (one claim past the end per
-    // wave); keep that within 32 bits
-    if (t.waves_per_simd >= 0 && total + ((int64_t)grid + 1) * t.chunk >= ((int64_t)1 << 32))
-        return FI_ERR_RANGE;
-    hipLaunchKernelGGL(kTraverse[mode][batched ? 1 : 0][t.root_in_lds], dim3(grid), dim3(kWave), 0, s,
-                       a0, scenes, offsets, n_scenes, total, queue, sched_for(t, grid, total));
-    return FI_OK;
-}
-
-int launch(int mode, const Args &a, double *t64, double *u64, void *stream)
+int launch(int mode, const Args &a, void *stream)
 {
     (void)hipGetLastError();
     DeviceInfo *d = nullptr;
     const int st = device_info(d);
     if (st != FI_OK) return st;
-    uint32_t *slot = d->slots + 2 * (g_next_slot.fetch_add(1u) % kSlots);
     hipStream_t s = (hipStream_t)stream;
-    const int lst = launch_traverse(*d, mode, false, default_tuning(), a, nullptr, nullptr, 1, a.n_pairs, slot, s);
-    if (lst != FI_OK) return lst;
-    if (t64) {
-        const unsigned g2 = (unsigned)((a.n_pairs + 255) / 256);
-        hipLaunchKernelGGL(k_refine, dim3(g2), dim3(256), 0, s, a, t64, u64);
+    Region &R = d->region[d->next_region.fetch_add(1u) % kRegions];
+    {
+        std::lock_guard<std::mutex> lock(R.m);
+        if (!R.mem) {
+            if (hipMalloc(&R.mem, table_region_bytes(kChunkRows)) != hipSuccess) {
+                R.mem = nullptr;
+                (void)hipGetLastError();
+                return FI_ERR_HIP;
+            }
+            if (hipEventCreateWithFlags(&R.done, hipEventDisableTiming) != hipSuccess) return FI_ERR_HIP;
+        }
+        if (R.pending && hipStreamWaitEvent(s, R.done, 0) != hipSuccess) return FI_ERR_HIP;
+        R.parity = launch_chain(*d, mode, false, default_tuning(), a, nullptr, nullptr, 1, a.n_pairs,
+                                table_at(R.mem, kChunkRows), R.counters, R.parity, s);
+        if (hipEventRecord(R.done, s) != hipSuccess) return FI_ERR_HIP;
+        R.pending = true;
     }
     return hipGetLastError() == hipSuccess ? FI_OK : FI_ERR_HIP;
 }
@@ -1042,9 +1259,14 @@ int launch(int mode, const Args &a, double *t64, double *u64, void *stream)
 // Batched problems
 // ---------------------------------------------------------------------------
 
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
 size_t table_bytes(int n) { return align256((size_t)n * sizeof(Args)) + align256((size_t)(n + 1) * sizeof(int64_t)); }
+
+constexpr size_t kCounterBytes = align256(kCounterWords * sizeof(uint32_t));
+
+size_t batched_bytes(int n, int64_t total)
+{
+    return table_bytes(n) + kCounterBytes + table_region_bytes(rows_for(total));
+}
 
 int scenes_to_table(const fi_scene *sc, int32_t n, Args *tab, int64_t *off)
 {
@@ -1056,27 +1278,30 @@ int scenes_to_table(const fi_scene *sc, int32_t n, Args *tab, int64_t *off)
         if (st != FI_OK) return st;
         tab[k] = Args{x.rays, x.ray_stride, x.n_rays, x.fibers, x.fiber_stride, x.n_fibers,
                       x.pair_ray, x.pair_fiber, x.pair_depth, x.depth, x.n_pairs,
-                      x.t_out, x.u_out, x.hit_out, nullptr};
+                      x.t_out, x.u_out, x.hit_out, nullptr, nullptr, nullptr};
         off[k + 1] = off[k] + x.n_pairs;
     }
     if (off[n] > (int64_t)0x7fffffff - 64) return FI_ERR_RANGE;
     return FI_OK;
 }
 
-// Layout of a batched workspace: scene table, pair offsets, queue.
+// Layout of a batched workspace: scene table, pair offsets, counters,
+// survivor table.
 struct BatchLayout {
     Args *scenes;
     int64_t *offsets;
-    uint32_t *queue;
+    uint32_t *counters;
+    Table tab;
 };
 
-BatchLayout layout_of(void *ws, int n)
+BatchLayout layout_of(void *ws, int n, int64_t total)
 {
     char *p = (char *)ws;
     BatchLayout L;
     L.scenes = (Args *)p;
     L.offsets = (int64_t *)(p + align256((size_t)n * sizeof(Args)));
-    L.queue = (uint32_t *)(p + table_bytes(n));
+    L.counters = (uint32_t *)(p + table_bytes(n));
+    L.tab = table_at(p + table_bytes(n) + kCounterBytes, rows_for(total));
     return L;
 }
 
@@ -1087,8 +1312,9 @@ int batched_enqueue(const fi_scene *scenes, int32_t n_scenes, const fi_tuning &t
     int st = device_info(d);
     if (st != FI_OK) return st;
     const size_t tb = table_bytes(n_scenes);
-    if (!workspace || workspace_bytes < tb + 256) return FI_ERR_WORKSPACE;
     if (tb > kStageBytes) return FI_ERR_RANGE;
+    if (!workspace || workspace_bytes < batched_bytes(n_scenes, total_pairs(scenes, n_scenes)))
+        return FI_ERR_WORKSPACE;
     std::lock_guard<std::mutex> lock(d->stage_mutex);
     const int k = d->stage_next;
     if (!d->stage[k]) {
@@ -1101,15 +1327,12 @@ int batched_enqueue(const fi_scene *scenes, int32_t n_scenes, const fi_tuning &t
     st = scenes_to_table(scenes, n_scenes, (Args *)host, (int64_t *)(host + align256((size_t)n_scenes * sizeof(Args))));
     if (st != FI_OK) return st;
     const int64_t total = ((int64_t *)(host + align256((size_t)n_scenes * sizeof(Args))))[n_scenes];
-    const BatchLayout L = layout_of(workspace, n_scenes);
+    const BatchLayout L = layout_of(workspace, n_scenes, total);
     if (hipMemcpyAsync(workspace, host, tb, hipMemcpyHostToDevice, s) != hipSuccess) return FI_ERR_HIP;
     if (hipEventRecord(d->stage_done[k], s) != hipSuccess) return FI_ERR_HIP;
     d->stage_next = (k + 1) % kStageSlots;
-    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, L.queue);
-    if (total > 0) {
-        const int lst = launch_traverse(*d, kPlain, true, t, Args{}, L.scenes, L.offsets, n_scenes, total, L.queue, s);
-        if (lst != FI_OK) return lst;
-    }
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(256), 0, s, L.counters);
+    launch_chain(*d, kPlain, true, t, Args{}, L.scenes, L.offsets, n_scenes, total, L.tab, L.counters, 0, s);
     return hipGetLastError() == hipSuccess ? FI_OK : FI_ERR_HIP;
 }
 
@@ -1117,7 +1340,7 @@ int batched_enqueue(const fi_scene *scenes, int32_t n_scenes, const fi_tuning &t
 
 struct fi_batch_plan {
     int device;
-    void *mem;                 // device copy of the scene table, offsets and queue
+    void *mem;                 // device copy of the scene table and offsets; counters; survivor table
     int n_scenes;
     int64_t total;
     fi_tuning tuning;
@@ -1126,7 +1349,7 @@ struct fi_batch_plan {
 };
 
 extern "C" {
-int fi_version(void) { return (0 << 16) | (3 << 8) | 0; }
+int fi_version(void) { return (0 << 16) | (4 << 8) | 0; }
 
 const char *fi_strerror(int status)
 {
@@ -1155,9 +1378,9 @@ int fiber_intersect_pairs(const float *rays, int64_t ray_stride, int64_t n_rays,
     const bool refine = (flags & FI_FP64_REFINE) != 0u;
     if (refine && (!t64_out || !u64_out)) return FI_ERR_NULL;
     Args a{rays, ray_stride, n_rays, fibers, fiber_stride, n_fibers,
-           pair_ray, pair_fiber, pair_depth, depth, n_pairs, t_out, u_out, hit_out, nullptr};
-    return launch(refine ? kConservative : kPlain, a, refine ? t64_out : nullptr,
-                  refine ? u64_out : nullptr, stream);
+           pair_ray, pair_fiber, pair_depth, depth, n_pairs, t_out, u_out, hit_out, nullptr,
+           refine ? t64_out : nullptr, refine ? u64_out : nullptr};
+    return launch(refine ? kConservative : kPlain, a, stream);
 }
 
 int fiber_intersect_counts(const float *rays, int64_t ray_stride, int64_t n_rays,
@@ -1174,15 +1397,15 @@ int fiber_intersect_counts(const float *rays, int64_t ray_stride, int64_t n_rays
     if (!counts_out) return FI_ERR_NULL;
     if (flags != 0u) return FI_ERR_RANGE;
     Args a{rays, ray_stride, n_rays, fibers, fiber_stride, n_fibers,
-           pair_ray, pair_fiber, pair_depth, depth, n_pairs, t_out, u_out, hit_out, counts_out};
-    return launch(kCount, a, nullptr, nullptr, stream);
+           pair_ray, pair_fiber, pair_depth, depth, n_pairs, t_out, u_out, hit_out, counts_out, nullptr, nullptr};
+    return launch(kCount, a, stream);
 }
 
 
-size_t fiber_batched_workspace_bytes(int32_t n_scenes)
+size_t fiber_batched_workspace_bytes(int32_t n_scenes, int64_t total_pairs)
 {
-    if (n_scenes < 0) return 0;
-    return table_bytes(n_scenes) + 256;
+    if (n_scenes < 0 || total_pairs < 0) return 0;
+    return batched_bytes(n_scenes, total_pairs);
 }
 
 int fiber_intersect_batched(const fi_scene *scenes, int32_t n_scenes, const fi_tuning *tuning,
@@ -1221,20 +1444,18 @@ int fiber_batch_plan_create(const fi_scene *scenes, int32_t n_scenes, const fi_t
     p->tuning = t;
     current_device(p->device);
     hipStream_t cs = nullptr;
-    bool ok = hipMalloc(&p->mem, tb + 256) == hipSuccess &&
+    bool ok = hipMalloc(&p->mem, batched_bytes(n_scenes, p->total)) == hipSuccess &&
               hipMemcpy(p->mem, host, tb, hipMemcpyHostToDevice) == hipSuccess &&
               hipStreamCreate(&cs) == hipSuccess;
     free(host);
     if (ok) {
-        const BatchLayout L = layout_of(p->mem, n_scenes);
+        const BatchLayout L = layout_of(p->mem, n_scenes, p->total);
         ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
         if (ok) {
-            hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, cs, L.queue);
-            int lst = FI_OK;
-            if (p->total > 0)
-                lst = launch_traverse(*d, kPlain, true, t, Args{}, L.scenes, L.offsets, n_scenes, p->total,
-                                      L.queue, cs);
-            ok = hipStreamEndCapture(cs, &p->graph) == hipSuccess && lst == FI_OK &&
+            hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(256), 0, cs, L.counters);
+            launch_chain(*d, kPlain, true, t, Args{}, L.scenes, L.offsets, n_scenes, p->total, L.tab, L.counters,
+                         0, cs);
+            ok = hipStreamEndCapture(cs, &p->graph) == hipSuccess &&
                  hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) == hipSuccess;
         }
     }
@@ -1286,30 +1507,25 @@ int fiber_batch_autotune(const fi_scene *scenes, int32_t n_scenes, uint32_t flag
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return FI_ERR_HIP;
     const int refills[] = {16, 32, 48};
-    const int occ[] = {3, 4, 0};
-    const int chunks[] = {64, 256};
-    const int statics[] = {50, 80, 100};
+    const int occ[] = {4, 6, 0};
     float best_t = INFINITY;
     fi_tuning bt = default_tuning();
     int st = FI_OK;
-    for (int lds = 0; lds < 2 && st == FI_OK; ++lds)
-        for (int oi = 0; oi < 3 && st == FI_OK; ++oi)
-          for (int ci = 0; ci < 2 && st == FI_OK; ++ci)
-            for (int si = 0; si < 3 && st == FI_OK; ++si)
-              for (int ri = 0; ri < 3 && st == FI_OK; ++ri) {
-                const fi_tuning t{refills[ri], occ[oi], lds, chunks[ci], statics[si]};
-                float tmin = INFINITY;
-                for (int r = 0; r <= repeats && st == FI_OK; ++r) {       // first run warms up
-                    if (hipEventRecord(e0, s) != hipSuccess) { st = FI_ERR_HIP; break; }
-                    st = fiber_intersect_batched(scenes, n_scenes, &t, flags, workspace, workspace_bytes, stream);
-                    if (st == FI_OK && hipEventRecord(e1, s) != hipSuccess) st = FI_ERR_HIP;
-                    if (st == FI_OK && hipEventSynchronize(e1) != hipSuccess) st = FI_ERR_HIP;
-                    float ms = 0.0f;
-                    if (st == FI_OK && r > 0 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < tmin)
-                        tmin = ms;
-                }
-                if (tmin < best_t) { best_t = tmin; bt = t; }
+    for (int oi = 0; oi < 3 && st == FI_OK; ++oi)
+        for (int ri = 0; ri < 3 && st == FI_OK; ++ri) {
+            const fi_tuning t{refills[ri], occ[oi]};
+            float tmin = INFINITY;
+            for (int r = 0; r <= repeats && st == FI_OK; ++r) {       // first run warms up
+                if (hipEventRecord(e0, s) != hipSuccess) { st = FI_ERR_HIP; break; }
+                st = fiber_intersect_batched(scenes, n_scenes, &t, flags, workspace, workspace_bytes, stream);
+                if (st == FI_OK && hipEventRecord(e1, s) != hipSuccess) st = FI_ERR_HIP;
+                if (st == FI_OK && hipEventSynchronize(e1) != hipSuccess) st = FI_ERR_HIP;
+                float ms = 0.0f;
+                if (st == FI_OK && r > 0 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < tmin)
+                    tmin = ms;
             }
+            if (tmin < best_t) { best_t = tmin; bt = t; }
+        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != FI_OK) return st;

@@ -1,0 +1,138 @@
+"""Summaries of rocprofv3 runs of the benchmark, for the files under profiles/.
+
+Usage (on the results of the commands named in the summary it writes):
+
+    python -m paper_1811_03374_amd.profsummary \
+        --stats <dir>/kt/kt_kernel_stats.csv \
+        --fetch <dir>/fetch/fetch_counter_collection.csv \
+        --write <dir>/write/write_counter_collection.csv \
+        --name <summary name> --out profiles
+
+* ``--stats``: a ``rocprofv3 --kernel-trace --stats`` run of ``bench.py``;
+  the summary lists every kernel's call count and average duration.
+* ``--fetch`` / ``--write``: ``rocprofv3 --pmc FETCH_SIZE`` and
+  ``--pmc WRITE_SIZE`` runs of ``bench.py --traffic-probe``, which copies
+  256 MiB with a plain device copy and then makes one call per depth. The
+  copy calibrates the counters (bytes the counter reports for a copy of known
+  size); every call's setup and traversal dispatches are summed and scaled by
+  that factor. The result is written to ``traffic.json`` together with the
+  hash of the kernel source it was measured on, which ``bench.py`` checks
+  before it reports the figure.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+COPY_BYTES = 256 << 20
+DEPTHS = (9, 22)
+
+
+def kernel_source_hash():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1811_03374_amd", "csrc", "fiberhit.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def short(name):
+    name = name.replace("(anonymous namespace)::", "")
+    if name.startswith("void "):
+        name = name[5:]
+    return name.split("(")[0] if "(" in name else name
+
+
+def read_stats(path):
+    rows = list(csv.DictReader(open(path)))
+    out = []
+    for r in rows:
+        out.append({"kernel": short(r["Name"]), "calls": int(r["Calls"]),
+                    "avg_us": float(r["AverageNs"]) / 1e3, "min_us": float(r["MinNs"]) / 1e3,
+                    "max_us": float(r["MaxNs"]) / 1e3, "percent": float(r["Percentage"])})
+    return out
+
+
+def read_counter(path, counter):
+    per = collections.OrderedDict()
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        key = int(r["Dispatch_Id"])
+        per.setdefault(key, [short(r["Kernel_Name"]), 0.0])
+        per[key][1] += float(r["Counter_Value"])
+    return [(k, v[0], v[1]) for k, v in sorted(per.items())]
+
+
+def per_call(dispatches, factor):
+    """Bytes per call: the setup and traversal dispatches after the copy, in
+    call order (one call per depth)."""
+    calls, cur = [], None
+    for _, name, kib in dispatches:
+        if name.startswith("k_setup"):
+            cur = {"k_setup": kib * 1024 * factor}
+            calls.append(cur)
+        elif name.startswith("k_traverse") and cur is not None:
+            cur["k_traverse"] = kib * 1024 * factor
+    return calls
+
+
+def calibration(dispatches):
+    for _, name, kib in dispatches:
+        if "copyBuffer" in name:
+            return COPY_BYTES / (kib * 1024)
+    raise SystemExit("no copy dispatch found for calibration")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--stats", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--name", required=True)
+    ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
+    ap.add_argument("--command", action="append", default=[],
+                    help="command line that produced an input (repeatable)")
+    a = ap.parse_args(argv)
+    os.makedirs(a.out, exist_ok=True)
+    stats = read_stats(a.stats)
+    lines = [f"# {a.name}", "", "Commands:", ""]
+    lines += [f"    {c}" for c in a.command] + [""]
+    lines += ["| kernel | calls | avg us | min us | max us | % of GPU time |", "|---|---|---|---|---|---|"]
+    for s in stats:
+        lines.append(f"| {s['kernel']} | {s['calls']} | {s['avg_us']:.1f} | {s['min_us']:.1f} | "
+                     f"{s['max_us']:.1f} | {s['percent']:.1f} |")
+    traffic = None
+    if a.fetch and a.write:
+        fd = read_counter(a.fetch, "FETCH_SIZE")
+        wd = read_counter(a.write, "WRITE_SIZE")
+        ff, wf = calibration(fd), calibration(wd)
+        fc, wc = per_call(fd, ff), per_call(wd, wf)
+        traffic = {"kernel_source_sha256_16": kernel_source_hash(),
+                   "calibration": {"copy_bytes": COPY_BYTES, "fetch_factor": ff, "write_factor": wf},
+                   "bytes_per_launch": {}, "per_kernel": {}}
+        lines += ["", "HBM traffic per call (FETCH_SIZE and WRITE_SIZE, scaled by a "
+                  f"{COPY_BYTES >> 20} MiB copy: fetch x{ff:.3f}, write x{wf:.3f}):", "",
+                  "| depth | kernel | fetch MB | write MB |", "|---|---|---|---|"]
+        for d, f, w in zip(DEPTHS, fc, wc):
+            total = sum(f.values()) + sum(w.values())
+            traffic["bytes_per_launch"][str(d)] = total
+            traffic["per_kernel"][str(d)] = {k: {"fetch": f.get(k, 0.0), "write": w.get(k, 0.0)}
+                                            for k in ("k_setup", "k_traverse")}
+            for k in ("k_setup", "k_traverse"):
+                lines.append(f"| {d} | {k} | {f.get(k, 0.0) / 1e6:.1f} | {w.get(k, 0.0) / 1e6:.1f} |")
+            lines.append(f"| {d} | total | {sum(f.values()) / 1e6:.1f} | {sum(w.values()) / 1e6:.1f} |")
+        with open(os.path.join(a.out, "traffic.json"), "w") as fh:
+            json.dump(traffic, fh, indent=1)
+    path = os.path.join(a.out, a.name + ".md")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(path)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

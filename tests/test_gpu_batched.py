@@ -76,9 +76,8 @@ def test_batched_equals_plain_bitwise():
 def test_results_do_not_depend_on_tuning():
     ws, sizes, probs = make_scenes(seed=9)
     ref = plain_reference(probs)
-    for t in ({"refill": 8, "waves_per_simd": 2, "root_in_lds": 0, "chunk": 64, "static_pct": 50},
-              {"refill": 64, "waves_per_simd": 0, "root_in_lds": 1, "chunk": 65536, "static_pct": 100},
-              {"refill": 1, "waves_per_simd": 1, "root_in_lds": 0, "chunk": 1, "static_pct": 0}):
+    for t in ({"refill": 8, "waves_per_simd": 2}, {"refill": 64, "waves_per_simd": 0},
+              {"refill": 1, "waves_per_simd": 1}, {"refill": 32, "waves_per_simd": 16}):
         clear(probs)
         binding.intersect_batched(probs, tuning=t)
         torch.cuda.synchronize()
@@ -118,8 +117,7 @@ def test_autotune_returns_a_grid_point():
     ws, sizes, probs = make_scenes(seed=17)
     best, ms = binding.autotune(probs, repeats=1)
     say(f"[autotune] {best} {ms:.3f} ms")
-    assert best["refill"] in (16, 32, 48) and best["root_in_lds"] in (0, 1)
-    assert best["chunk"] in (64, 256) and best["static_pct"] in (0, 50, 80)
+    assert best["refill"] in (16, 32, 48) and best["waves_per_simd"] in (4, 6, 0)
     assert ms > 0
 
 
@@ -129,7 +127,28 @@ def test_batched_argument_errors():
     with pytest.raises(binding.FiberHitError):
         binding.intersect_batched(probs, workspace=small)
     with pytest.raises(binding.FiberHitError):
-        binding.intersect_batched(probs, tuning={"refill": 0, "waves_per_simd": 0, "root_in_lds": 1})
+        binding.intersect_batched(probs, tuning={"refill": 0, "waves_per_simd": 0})
     with pytest.raises(binding.FiberHitError):
-        binding.intersect_batched(probs, tuning={"refill": 32, "waves_per_simd": 0, "root_in_lds": 1,
-                                                 "chunk": 1 << 17, "static_pct": 50})
+        binding.intersect_batched(probs, tuning={"refill": 32, "waves_per_simd": -1})
+    with pytest.raises(binding.FiberHitError):
+        binding.intersect_batched(probs, tuning={"refill": 65, "waves_per_simd": 0})
+    with pytest.raises(binding.FiberHitError):
+        binding.intersect_batched(probs, tuning={"refill": 32, "waves_per_simd": 17})
+
+
+def test_batched_longer_than_one_chunk():
+    """1.2 million pairs in three problems: the batch runs as two
+    setup/traversal chunks whose boundary falls inside a problem; results
+    stay bitwise equal to one call per problem."""
+    sizes = [400_000, 3, 800_000]
+    probs = []
+    for k, n in enumerate(sizes):
+        w = W.straight_and_curved(n, 22, seed=4242 + k)
+        g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+        probs.append(binding.Problem(g(w.rays), g(w.fibers), 22 if k != 1 else 9))
+    say(f"[batched] chunks: {sum(sizes)} pairs")
+    ref = plain_reference(probs)
+    clear(probs)
+    binding.intersect_batched(probs)
+    torch.cuda.synchronize()
+    assert_same(probs, ref)

@@ -87,6 +87,10 @@ def test_degenerate_refined_against_exact_oracle(degenerate):
             say(f"[refined]    {name:15s} valid={val!s:5s} n={m.sum():6d} flag_disagree={rate:.2e} "
                 f"max_rel_t={rel.max() if rel.size else 0:.2e} "
                 f"p99.9_rel_t={np.quantile(rel, 0.999) if rel.size else 0:.2e}")
+            for i in np.nonzero((m & (hg != hx)) | (both & (np.abs(t64 - t_x) > 1e-12 * np.abs(t_x))))[0][:6]:
+                say(f"[refined]      pair {i}: depth={w.pair_depth[i]} gpu hit={hg[i]} t64={t64[i]!r} "
+                    f"u64={u64[i]!r} t32={t32[i]!r} | exact hit={hx[i]} t={t_x[i]!r} u={u_x[i]!r} "
+                    f"kind={kind[i]}")
             if val and name in ("near-collinear", "steep taper"):
                 assert rate == 0.0, name
                 assert rel.max() <= 1e-12, (name, rel.max())

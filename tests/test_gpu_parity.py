@@ -172,3 +172,48 @@ def test_full_size_sampled(depth):
     assert np.all((t_g[hit] >= 0) & (t_g[hit] < w.rays[6][hit]))
     assert np.all((u_g[hit] >= 0) & (u_g[hit] <= 1))
     assert 0.45 < hit.mean() < 0.55
+
+
+def _bits(a):
+    return np.ascontiguousarray(a).view(np.uint32 if a.dtype == np.float32 else np.uint8)
+
+
+def test_calls_longer_than_one_chunk():
+    """A call of 2^20 + 4099 pairs runs as two setup/traversal chunks: every
+    pair's result equals that of a separate call on a subset of the pairs
+    (bitwise), on both sides of the chunk boundary."""
+    n = (1 << 20) + 4099
+    w = W.straight_and_curved(n, 22)
+    say(f"[chunks] n={n}")
+    t_g, u_g, h_g = run_gpu(w, 22)
+    rays = torch.from_numpy(w.rays).to(DEV)
+    fibers = torch.from_numpy(w.fibers).to(DEV)
+    for lo, hi in ((0, 3000), ((1 << 20) - 1500, (1 << 20) + 1500), (n - 3000, n)):
+        idx = torch.arange(lo, hi, dtype=torch.int32, device=DEV)
+        t, u, h = (o.cpu().numpy() for o in binding.intersect_pairs(rays, fibers, 22, idx, idx))
+        torch.cuda.synchronize()
+        assert np.array_equal(_bits(t), _bits(t_g[lo:hi]))
+        assert np.array_equal(_bits(u), _bits(u_g[lo:hi]))
+        assert np.array_equal(h, h_g[lo:hi])
+
+
+def test_concurrent_streams():
+    """Calls enqueued alternately on two streams (more calls than survivor
+    tables, so tables are reused across streams) give the results of the same
+    calls made one after another."""
+    ws = [W.straight_and_curved(50_000 + 1000 * k, 9, seed=77 + k) for k in range(6)]
+    dev_in = [(torch.from_numpy(w.rays).to(DEV), torch.from_numpy(w.fibers).to(DEV)) for w in ws]
+    ref = []
+    for (r, f), d in zip(dev_in, (9, 22, 4, 16, 9, 22)):
+        ref.append([o.cpu().numpy() for o in binding.intersect_pairs(r, f, d)])
+        torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = []
+    for k, ((r, f), d) in enumerate(zip(dev_in, (9, 22, 4, 16, 9, 22))):
+        outs.append(binding.intersect_pairs(r, f, d, stream=streams[k % 2]))
+    torch.cuda.synchronize()
+    for got, want in zip(outs, ref):
+        got = [o.cpu().numpy() for o in got]
+        assert np.array_equal(_bits(got[0]), _bits(want[0]))
+        assert np.array_equal(_bits(got[1]), _bits(want[1]))
+        assert np.array_equal(got[2], want[2])

@@ -70,6 +70,14 @@ def check_refined(w, depth, label):
           "max_du": float(du.max()) if du.size else 0.0, "u_bad": int((du > utol).sum()),
           "cap_hits": int(((kind == 2) | (kind == 3)).sum())}
     say(f"[refine]   {st}")
+    bi = np.nonzero(both)[0]
+    for j in np.argsort(-rel)[:3] if rel.size else []:
+        i = bi[j]
+        say(f"[refine]     worst pair {i}: rel_t={rel[j]:.3e} t64={t64[i]!r} t_x={t_x[i]!r} "
+            f"u64={u64[i]!r} u_x={u_x[i]!r} kind={kind[i]} t32={t32[i]!r}")
+    for i in np.nonzero(flag_bad)[0][:5]:
+        say(f"[refine]     flag pair {i}: gpu hit={hg[i]} t64={t64[i]!r} u64={u64[i]!r} | exact "
+            f"hit={h_x[i]} t={t_x[i]!r} u={u_x[i]!r} kind={kind[i]}")
     # float outputs are the rounded refined values; misses are encoded as usual
     assert np.all(np.isinf(t64[~hg])) and np.all(np.isnan(u64[~hg]))
     assert np.array_equal(t32[hg], t64[hg].astype(np.float32))
@@ -92,12 +100,22 @@ def test_refine_hair_precision_stress():
 
 
 def test_refine_keeps_shallow_pairs_plain():
+    """Depth <= 16 is not refined: the refined call gives the plain results bit
+    for bit, with t64/u64 the widened floats (pairs of depths 12 and 19 mixed
+    in one call)."""
     w = W.straight_and_curved(4096)
-    t, u, h = [o.cpu().numpy() for o in binding.intersect_pairs(
-        torch.from_numpy(w.rays).to(DEV), torch.from_numpy(w.fibers).to(DEV), 12)]
-    t2, u2, h2, t64, u64 = run_refined(w, 12)
-    # depth <= 16 is not refined; the conservative traversal may only add ties
-    same = h.astype(bool) == h2.astype(bool)
-    assert same.mean() > 0.999
-    hit = h2.astype(bool)
+    pd = np.where(np.arange(w.n_pairs) % 3 == 0, 19, 12).astype(np.uint8)
+    g = lambda a: torch.from_numpy(a).to(DEV)
+    t, u, h = [o.cpu().numpy() for o in binding.intersect_pairs(g(w.rays), g(w.fibers), 12,
+                                                              pair_depth=g(pd))]
+    t2, u2, h2, t64, u64 = [o.cpu().numpy() for o in binding.intersect_pairs(
+        g(w.rays), g(w.fibers), 12, pair_depth=g(pd), refine=True)]
+    torch.cuda.synchronize()
+    shallow = pd == 12
+    bits = lambda a: a.view(np.uint32)
+    assert np.array_equal(bits(t[shallow]), bits(t2[shallow]))
+    assert np.array_equal(bits(u[shallow]), bits(u2[shallow]))
+    assert np.array_equal(h[shallow], h2[shallow])
+    hit = h2.astype(bool) & shallow
     assert np.array_equal(t64[hit], t2[hit].astype(np.float64))
+    assert np.array_equal(u64[hit], u2[hit].astype(np.float64))
