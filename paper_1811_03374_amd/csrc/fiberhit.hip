@@ -281,8 +281,14 @@ struct Args {
 // in one of the leaf's discs. The smallest candidate in [0, tmax) is the hit.
 
 constexpr int kRefineAbove = 16;         // refine pairs of depth > 16
+constexpr int kLeafSamples = 16;         // phi samples over a leaf's u window (three leaves)
+constexpr int kRefineFails = 16;         // leaves without the solid before the whole-curve search
+constexpr int kCurveSamples = 1024;      // phi samples over the whole curve
 
-struct Curve64 { double q[4][4]; };      // control points in the FP64 ray frame (x, y, z, r)
+struct Curve64 {
+    double q[4][4];                      // control points in the FP64 ray frame (x, y, z, r)
+    double scale;                        // largest control-point coordinate
+};
 
 __device__ __forceinline__ bool curve_in_ray_frame(const float *R, int64_t rs, const float *F,
                                                    int64_t fs, Curve64 &c)
@@ -305,7 +311,19 @@ __device__ __forceinline__ bool curve_in_ray_frame(const float *R, int64_t rs, c
         c.q[k][2] = fma(ex, w[0], fma(ey, w[1], ez * w[2]));
         c.q[k][3] = F[(4 * k + 3) * fs];
     }
+    c.scale = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        c.scale = fmax(c.scale, fmax(fabs(c.q[k][0]), fmax(fabs(c.q[k][1]), fabs(c.q[k][2]))));
     return true;
+}
+
+// A boundary point needs a disc plane: where C'(u) vanishes (a zero end
+// tangent, a cusp) <P - C, C'> = 0 holds for every P, and |P - C| = r(u)
+// would describe a sphere, not the swept solid.
+__device__ __forceinline__ bool has_disc(const Curve64 &c, const double D[4])
+{
+    return sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]) > 1e-12 * c.scale;
 }
 
 // C(u) (with radius), D = C'(u)/3 (with r'/3) and E = C''(u)/6 (xyz)
@@ -336,20 +354,11 @@ __device__ __forceinline__ bool disc_point(const Curve64 &c, double u, double &t
     return true;
 }
 
-// Derivative along the ray of the signed excess at a surface point: negative
-// at an entry.
-__device__ __forceinline__ double entry_slope(const double C[4], const double D[4], const double E[3], double t)
-{
-    const double h = t - C[2];
-    const double pe = -C[0] * E[0] - C[1] * E[1] + h * E[2];
-    const double dd = D[0] * D[0] + D[1] * D[1] + D[2] * D[2];
-    const double den = 9.0 * dd - 6.0 * pe;
-    return 2.0 * h - (den != 0.0 ? 2.0 * C[3] * 9.0 * D[3] * D[2] / den : 0.0);
-}
-
+// Newton's method on (f1, f2) from (t, u): true when it converges to a
+// boundary point of the swept solid (entry or exit).
 __device__ __forceinline__ bool newton_surface(const Curve64 &c, double &t, double &u)
 {
-    for (int it = 0; it < 8; ++it) {
+    for (int it = 0; it < 10; ++it) {
         double C[4], D[4], E[3];
         eval_curve(c, u, C, D, E);
         const double h = t - C[2];
@@ -367,7 +376,7 @@ __device__ __forceinline__ bool newton_surface(const Curve64 &c, double &t, doub
         t += dt;
         u += du;
         if (!(fabs(u) < 4.0) || !isfinite(t)) return false;
-        if (fabs(du) <= 1e-16 && fabs(dt) <= 1e-16 * fabs(t)) break;
+        if (fabs(du) <= 4e-16 && fabs(dt) <= 4e-16 * fabs(t)) break;
     }
     double C[4], D[4], E[3];
     eval_curve(c, u, C, D, E);
@@ -376,101 +385,121 @@ __device__ __forceinline__ bool newton_surface(const Curve64 &c, double &t, doub
     const double f1 = h * D[2] - C[0] * D[0] - C[1] * D[1];
     const double f2 = C[0] * C[0] + C[1] * C[1] + h * h - C[3] * C[3];
     const double dn = sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
-    return fabs(f2) <= 1e-9 * scale && fabs(f1) <= 1e-9 * C[3] * dn && entry_slope(C, D, E, t) < 0.0;
+    return has_disc(c, D) && fabs(f2) <= 1e-9 * scale && fabs(f1) <= 1e-9 * C[3] * dn;
 }
 
-// Bracketed search of the entry on [ua, ub]: sample the disc excess, take the
-// first sign change towards smaller t, bisect it.
-
-// First point of the swept solid along the ray with u in [ua, ub] and t in
-// [0, tmax); (t0, u0) is the FP32 leaf hit. False when there is none.
-__device__ __forceinline__ bool refine_leaf(const Curve64 &c, double ua, double ub, double tmax, double t0,
-                                            double u0, double &t_best, double &u_best)
+// Bisect a sign change of phi on [lo, hi] (lo_in: phi(lo) <= 0), then polish
+// the root by Newton's method; returns the boundary point in (t, u).
+__device__ __forceinline__ bool boundary_root(const Curve64 &c, double lo, double hi, bool lo_in, double &t,
+                                              double &u)
 {
-    t_best = INFINITY;
-    u_best = __builtin_nan("");
+    for (int it = 0; it < 64; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        double mt, mphi;
+        if (!disc_point(c, mid, mt, mphi)) return false;
+        if ((mphi <= 0.0) == lo_in) lo = mid; else hi = mid;
+    }
+    u = 0.5 * (lo + hi);
+    double phi;
+    if (!disc_point(c, u, t, phi)) return false;
+    {
+        double C[4], D[4], E[3];
+        eval_curve(c, u, C, D, E);
+        if (!has_disc(c, D)) return false;
+    }
+    double tn = t, un = u;
+    if (newton_surface(c, tn, un) && fabs(un - u) <= 4.0 * (hi - lo) + 1e-12) {
+        t = tn;
+        u = un;
+    }
+    return true;
+}
+
+// Boundary points of the swept solid along the ray with u in [ua, ub]; the
+// earliest with t in [tlo, thi] (the part of the ray the leaf owns) and below
+// tmax is kept in (t_best, u_best). (t0, u0) is the FP32 leaf hit. Also the
+// end discs when the interval reaches u = 0 or 1, and t = 0 when the origin
+// lies in one of the discs. The earliest boundary point of the solid is its
+// entry (or the origin, when inside), so no entry/exit classification is
+// needed.
+__device__ __forceinline__ void leaf_candidates(const Curve64 &c, double ua, double ub, double tlo, double thi,
+                                                double tmax, double t0, double u0, int samples, double &t_best,
+                                                double &u_best)
+{
+    auto take = [&](double t, double u) {
+        if (t >= tlo && t <= thi && t < tmax && t < t_best) { t_best = t; u_best = u; }
+    };
     {
         double t = t0, u = u0;
-        if (newton_surface(c, t, u) && u >= ua && u <= ub && t >= 0.0 && t < tmax) {
-            t_best = t;
-            u_best = u;
-        }
+        if (newton_surface(c, t, u) && u >= ua && u <= ub) take(t, u);
     }
-    constexpr int kSamples = 8;
-    const double h = (ub - ua) / kSamples;
-    double pu = ua, pt = 0.0, pphi = 0.0;
+    const double h = (ub - ua) / samples;
+    double pu = ua, pt = 0.0, pphi = 0.0, ppu = ua, ppphi = INFINITY;
     bool pok = disc_point(c, pu, pt, pphi);
-    for (int k = 1; k <= kSamples; ++k) {
-        const double cu = k == kSamples ? ub : ua + h * k;
+    for (int k = 1; k <= samples; ++k) {
+        const double cu = k == samples ? ub : ua + h * k;
         double ct = 0.0, cphi = 0.0;
         const bool cok = disc_point(c, cu, ct, cphi);
-        if (pok && cok && ((pphi <= 0.0) != (cphi <= 0.0))) {
-            // a boundary point: bisect phi, then polish on (f1, f2)
-            double lo = pu, hi = cu;
-            const bool lo_in = pphi <= 0.0;
-            for (int it = 0; it < 64; ++it) {
-                const double mid = 0.5 * (lo + hi);
-                double mt, mphi;
-                if (!disc_point(c, mid, mt, mphi)) break;
-                if ((mphi <= 0.0) == lo_in) lo = mid; else hi = mid;
+        if (pok && cok) {
+            if ((pphi <= 0.0) != (cphi <= 0.0)) {
+                double t, u;
+                if (boundary_root(c, pu, cu, pphi <= 0.0, t, u)) take(t, u);
+            } else if (pphi > 0.0 && cphi > pphi && ppphi > pphi) {
+                // a local minimum of phi near pu: a dip below zero narrower
+                // than the sampling has two boundary points in (ppu, cu)
+                constexpr double g = 0.38196601125010515;         // golden-section step
+                double a = ppu, b = cu, tt;
+                double x1 = a + g * (b - a), x2 = b - g * (b - a), f1 = 0.0, f2 = 0.0;
+                bool ok = disc_point(c, x1, tt, f1) && disc_point(c, x2, tt, f2);
+                for (int it = 0; ok && it < 48 && f1 > 0.0 && f2 > 0.0; ++it) {
+                    if (f1 < f2) {
+                        b = x2; x2 = x1; f2 = f1; x1 = a + g * (b - a);
+                        ok = disc_point(c, x1, tt, f1);
+                    } else {
+                        a = x1; x1 = x2; f1 = f2; x2 = b - g * (b - a);
+                        ok = disc_point(c, x2, tt, f2);
+                    }
+                }
+                if (ok && fmin(f1, f2) <= 0.0) {
+                    const double um = f1 <= f2 ? x1 : x2;
+                    double t, u;
+                    if (boundary_root(c, ppu, um, false, t, u)) take(t, u);
+                    if (boundary_root(c, um, cu, true, t, u)) take(t, u);
+                }
             }
-            double ur = 0.5 * (lo + hi), tr = 0.0, phir = 0.0;
-            if (disc_point(c, ur, tr, phir)) {
-                double tn = tr, un = ur;
-                bool entry;
-                if (newton_surface(c, tn, un) && fabs(un - ur) <= h) {
-                    tr = tn;
-                    ur = un;
-                    entry = true;
-                } else {
-                    double C[4], D[4], E[3];
-                    eval_curve(c, ur, C, D, E);
-                    entry = entry_slope(C, D, E, tr) < 0.0;
+            if ((pt <= 0.0) != (ct <= 0.0) && (pphi <= 0.0 || cphi <= 0.0) && tlo <= 0.0) {
+                // the disc plane sweeps through the origin: is the origin in that disc?
+                double lo = pu, hi = cu;
+                const bool lo_neg = pt <= 0.0;
+                for (int it = 0; it < 64; ++it) {
+                    const double mid = 0.5 * (lo + hi);
+                    double mt, mphi;
+                    if (!disc_point(c, mid, mt, mphi)) break;
+                    if ((mt <= 0.0) == lo_neg) lo = mid; else hi = mid;
                 }
-                if (entry && tr >= 0.0 && tr < tmax && tr < t_best) {
-                    t_best = tr;
-                    u_best = ur;
-                }
+                const double uz = 0.5 * (lo + hi);
+                double C[4], D[4], E[3];
+                eval_curve(c, uz, C, D, E);
+                if (C[0] * C[0] + C[1] * C[1] + C[2] * C[2] <= C[3] * C[3]) take(0.0, uz);
             }
         }
-        if (pok && cok && ((pt <= 0.0) != (ct <= 0.0)) && (pphi <= 0.0 || cphi <= 0.0)) {
-            // the disc plane sweeps through the origin: is the origin in that disc?
-            double lo = pu, hi = cu;
-            const bool lo_neg = pt <= 0.0;
-            for (int it = 0; it < 64; ++it) {
-                const double mid = 0.5 * (lo + hi);
-                double mt, mphi;
-                if (!disc_point(c, mid, mt, mphi)) break;
-                if ((mt <= 0.0) == lo_neg) lo = mid; else hi = mid;
-            }
-            const double uz = 0.5 * (lo + hi);
-            double C[4], D[4], E[3];
-            eval_curve(c, uz, C, D, E);
-            if (C[0] * C[0] + C[1] * C[1] + C[2] * C[2] <= C[3] * C[3] && tmax > 0.0) {
-                t_best = 0.0;
-                u_best = uz;
-            }
-        }
+        ppu = pu;
+        ppphi = pok ? pphi : INFINITY;
         pu = cu; pt = ct; pphi = cphi; pok = cok;
     }
     // end discs
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-        const double ue = (double)e;
         if ((e == 0 && ua > 0.0) || (e == 1 && ub < 1.0)) continue;
         double C[4], D[4], E[3];
-        eval_curve(c, ue, C, D, E);
+        eval_curve(c, (double)e, C, D, E);
         if (D[2] == 0.0) continue;
         const double tc = (C[0] * D[0] + C[1] * D[1] + C[2] * D[2]) / D[2];
         const double hz = tc - C[2];
-        if (C[0] * C[0] + C[1] * C[1] + hz * hz <= C[3] * C[3] && tc >= 0.0 && tc < tmax && tc < t_best) {
-            t_best = tc;
-            u_best = ue;
-        }
+        if (C[0] * C[0] + C[1] * C[1] + hz * hz <= C[3] * C[3]) take(tc, (double)e);
     }
-    return t_best < INFINITY;
 }
-
 
 struct Lane {
     Node c;                       // current node, {p, d, t0, t1} in the ray frame
@@ -479,11 +508,14 @@ struct Lane {
     uint32_t bits, start, size;   // Section 3.3: pending-sibling bits, integer interval
     uint32_t min_size;            // leaf size 2^(23 - depth)
     uint32_t cached;              // size of the pending children whose parent is cached (0: none)
+    int32_t fails;                // refinement: leaves reached that held no part of the solid
     int32_t row;                  // row of this pair in the survivor table
     float slack;                  // conservative mode: bound on across-ray rounding of any node
                                   // (negative: a pair of depth <= 16, searched by the plain rules)
     int32_t trips, splits, backtracks;
     double t64, u64;              // refined hit
+    float u;                      // u of a leaf hit
+    int32_t level;                // level of a leaf hit
 };
 
 enum { kGoOn = 0, kHit = 1, kMiss = 2 };
@@ -593,11 +625,12 @@ __device__ __forceinline__ float root_slack(const Node &r)
 }
 
 // Pruning test of a node (Section 3.2): does the ray meet the conservative
-// cylinder inside the node's cropped interval? `lo_used` is the interval start
-// the test used (enlarged in conservative mode), from which a leaf's t is taken.
+// cylinder inside the node's cropped interval? `lo_used` / `hi_used` are the
+// interval the test used (enlarged in conservative mode); a leaf's t is taken
+// from its start.
 template <int MODE>
 __device__ __forceinline__ bool node_visible(const Node &c, float lo, float hi, float slack, float &te,
-                                             float &tx, float &lo_used)
+                                             float &tx, float &lo_used, float &hi_used)
 {
     float rad = conservative_radius(c);
     if (MODE == kConservative && slack >= 0.0f) {
@@ -607,6 +640,7 @@ __device__ __forceinline__ bool node_visible(const Node &c, float lo, float hi, 
         hi += tslack;
     }
     lo_used = lo;
+    hi_used = hi;
     return unit_ray_cylinder(c.p, c.d, rad, te, tx) && fmaxf(te, lo) <= fminf(tx, hi);
 }
 
@@ -619,9 +653,6 @@ __device__ __forceinline__ float plane_slack(float px, float py, float pz, float
            fabsf(t) * 0x1p-18f;
 }
 
-// FP64 check of a leaf reached by the conservative search (pair of depth
-// > 16): sets L.t64 / L.u64 and returns true when the swept solid is entered
-// inside the leaf's u interval (widened by an eighth of a leaf on each side).
 // u of a leaf hit (Section 3.3): the hit point projected onto the leaf chord.
 __device__ __forceinline__ float leaf_u(const Lane &L)
 {
@@ -634,7 +665,12 @@ __device__ __forceinline__ float leaf_u(const Lane &L)
     return fmaf(ul, (float)L.size * 0x1p-23f, (float)L.start * 0x1p-23f);
 }
 
-__device__ __noinline__ bool refine_at_leaf(Lane &L, const Table &tab, const Args &in)
+// FP64 check of a leaf reached by the conservative search (pair of depth
+// > 16): the earliest boundary point of the swept solid within the part of
+// the ray the leaf owns, [tin, tout] (the enlarged test's interval, widened
+// by 2^-20 of its size and of t), among discs with u up to one leaf beyond
+// the leaf on either side. Sets L.t64 / L.u64 and returns true when found.
+__device__ __noinline__ bool refine_at_leaf(Lane &L, const Table &tab, const Args &in, float tin, float tout)
 {
     const int64_t i = tab.pair[L.row];
     const int64_t ri = in.pair_ray ? (int64_t)in.pair_ray[i] : i;
@@ -642,10 +678,35 @@ __device__ __noinline__ bool refine_at_leaf(Lane &L, const Table &tab, const Arg
     Curve64 cv;
     if (!curve_in_ray_frame(in.rays + ri, in.ray_stride, in.fibers + fi, in.fiber_stride, cv)) return false;
     const double w = (double)L.size * 0x1p-23;
-    const double ua = fmax(0.0, (double)L.start * 0x1p-23 - 0.125 * w);
-    const double ub = fmin(1.0, (double)(L.start + L.size) * 0x1p-23 + 0.125 * w);
-    double t, u;
-    if (!refine_leaf(cv, ua, ub, (double)L.tmax, (double)L.t, (double)leaf_u(L), t, u)) return false;
+    const double ua = fmax(0.0, (double)L.start * 0x1p-23 - w);
+    const double ub = fmin(1.0, (double)(L.start + L.size) * 0x1p-23 + w);
+    const double t0 = tin, t1 = tout < INFINITY ? (double)tout : (double)L.tmax;
+    const double pad = ((t1 - t0) + fmax(fabs(t0), fabs(t1))) * 0x1p-20;
+    double t = INFINITY, u = __builtin_nan("");
+    leaf_candidates(cv, ua, ub, fmax(0.0, t0 - pad), t1 + pad, (double)L.tmax, (double)L.t, (double)leaf_u(L),
+                    kLeafSamples, t, u);
+    if (!(t < INFINITY)) return false;
+    L.t64 = t;
+    L.u64 = u;
+    return true;
+}
+
+// Where many consecutive leaves are reached without holding the solid (a
+// curve that stalls at a zero end tangent keeps thousands of tiny end
+// cylinders around one point, all on the ray), the leaf-by-leaf check stops
+// after kRefineFails leaves and searches the whole curve once: the earliest
+// boundary point with t in [0, tmax), sampled at kCurveSamples parameters.
+__device__ __noinline__ bool refine_whole_curve(Lane &L, const Table &tab, const Args &in)
+{
+    const int64_t i = tab.pair[L.row];
+    const int64_t ri = in.pair_ray ? (int64_t)in.pair_ray[i] : i;
+    const int64_t fi = in.pair_fiber ? (int64_t)in.pair_fiber[i] : i;
+    Curve64 cv;
+    if (!curve_in_ray_frame(in.rays + ri, in.ray_stride, in.fibers + fi, in.fiber_stride, cv)) return false;
+    double t = INFINITY, u = __builtin_nan("");
+    leaf_candidates(cv, 0.0, 1.0, 0.0, (double)L.tmax, (double)L.tmax, (double)L.t, (double)leaf_u(L),
+                    kCurveSamples, t, u);
+    if (!(t < INFINITY)) return false;
     L.t64 = t;
     L.u64 = u;
     return true;
@@ -654,51 +715,38 @@ __device__ __noinline__ bool refine_at_leaf(Lane &L, const Table &tab, const Arg
 // One loop trip of the paper's iteration (Appendix C, final listing): a
 // pruning test of the current node, then a descent, a leaf hit, a miss, or a
 // jump to the deepest pending sibling.
-// The common case (test, split, ordering, descent) is straight-line code for
-// every active lane: a lane that will stop still computes the split, which
-// costs nothing on a SIMD that runs it for its neighbours anyway, and avoids
-// divergent branches. Only the jump to a pending sibling branches.
+// The descent (split, ordering, child) is straight-line code computed for
+// every continuing lane; a lane that backtracks then overwrites its result
+// with the rebuilt sibling. The new node thus has a single definition point,
+// which spares the copies of the whole lane state that a merge of separately
+// computed nodes costs, and a backtracking lane only adds the rebuild.
 template <int MODE>
 __device__ __forceinline__ int trip(Lane &L, const Table &tab, float *col, const Args &in)
 {
-    float te, tx, lo;
-    bool vis = node_visible<MODE>(L.c, L.lo, L.hi, L.slack, te, tx, lo);
+    float te, tx, lo, hi;
+    bool vis = node_visible<MODE>(L.c, L.lo, L.hi, L.slack, te, tx, lo, hi);
     const bool leaf = L.size <= L.min_size;
-    if (++L.trips > kMaxTrips) return kMiss;
     if (MODE == kConservative && vis && leaf && L.slack >= 0.0f) {
         // refinement: the first point of the swept solid in this leaf, else go on
         L.t = fmaxf(te, lo);
-        if (refine_at_leaf(L, tab, in)) return kHit;
+        if (refine_at_leaf(L, tab, in, L.t, fminf(tx, hi))) return kHit;
+        if (++L.fails >= kRefineFails) return refine_whole_curve(L, tab, in) ? kHit : kMiss;
         vis = false;
     }
-    if (!vis) {
-        if (L.bits == 0) return kMiss;
-        // Section 3.3: jump to the deepest level with a pending sibling and
-        // rebuild it -- one split of the cached parent, or a replay of the
-        // split rules along the integer path from the root
-        L.size = L.bits & (0u - L.bits);
-        L.start ^= L.size;
-        L.bits ^= L.size;
-        L.start &= ~(L.size - 1u);
-        if (kParentCache && L.cached == L.size) {
-            lds_get(col, L.c);
-        } else {
-            table_root(tab, L.row, L.c);
-            for (uint32_t b = kRootSize >> 1; b > L.size; b >>= 1) {
-                V4 dp, tc;
-                split_terms(L.c, dp, tc);
-                take_child(L.c, dp, tc, (L.start & b) != 0u);
-            }
-        }
-        L.cached = 0;
-        V4 dp, tc;
-        split_terms(L.c, dp, tc);
-        take_child(L.c, dp, tc, (L.start & L.size) != 0u);
-        cap_interval(L.c, L.tmax, L.lo, L.hi);
-        L.backtracks++;
-        return kGoOn;
+    // A lane that stops here still runs the rest of the trip (its state is
+    // not used again): without early returns the lane state keeps one set of
+    // registers across the loop instead of being copied at every exit.
+    int st = kGoOn;
+    if (vis && leaf) {
+        L.t = fmaxf(te, lo);
+        L.u = leaf_u(L);
+        L.level = 23 - (31 - __builtin_clz(L.size));
+        st = kHit;
     }
-    // Section 3.2: split plane through the centre, normal to the split tangent
+    const bool over = ++L.trips > kMaxTrips;          // hang guard (each trip is a test)
+    if ((!vis && L.bits == 0) || over) st = kMiss;
+    // Section 3.1 / 3.2: split plane through the centre, normal to the split
+    // tangent; the half the ray meets first is the child
     V4 dp, tc;
     split_terms(L.c, dp, tc);
     float nx = tc.x, ny = tc.y, nz = tc.z;
@@ -727,18 +775,49 @@ __device__ __forceinline__ int trip(Lane &L, const Table &tab, float *col, const
     }
     // a plane parallel to the ray leaves the whole ray on the side of sign(-cs)
     const bool right = oblique ? ((tp > te) != (nz > 0.0f)) : cs < 0.0f;
-    if (oblique) { L.lo = nlo; L.hi = nhi; }
-    if (leaf) { L.t = fmaxf(te, lo); return kHit; }
-    if (kParentCache && both) lds_put(col, L.c);
-    take_child(L.c, dp, tc, right);
-    L.size >>= 1;
-    if (both) {
+    Node nc = L.c;
+    take_child(nc, dp, tc, right);
+    float new_lo = oblique ? nlo : L.lo, new_hi = oblique ? nhi : L.hi;
+    if (st != kGoOn) {
+        // the pair ends here; its state is not used again
+    } else if (vis) {
+        if (kParentCache && both) lds_put(col, L.c);
+        L.size >>= 1;
+        if (both) {
+            L.bits ^= L.size;
+            if (kParentCache) L.cached = L.size;
+        }
+        if (right) L.start ^= L.size;
+        L.splits++;
+    } else {
+        // Section 3.3: jump to the deepest level with a pending sibling and
+        // rebuild it -- one split of the cached parent, or a replay of the
+        // split rules along the integer path from the root
+        L.size = L.bits & (0u - L.bits);
+        L.start ^= L.size;
         L.bits ^= L.size;
-        if (kParentCache) L.cached = L.size;
+        L.start &= ~(L.size - 1u);
+        if (kParentCache && L.cached == L.size) {
+            lds_get(col, nc);
+        } else {
+            table_root(tab, L.row, nc);
+            for (uint32_t b = kRootSize >> 1; b > L.size; b >>= 1) {
+                V4 rdp, rtc;
+                split_terms(nc, rdp, rtc);
+                take_child(nc, rdp, rtc, (L.start & b) != 0u);
+            }
+        }
+        L.cached = 0;
+        V4 rdp, rtc;
+        split_terms(nc, rdp, rtc);
+        take_child(nc, rdp, rtc, (L.start & L.size) != 0u);
+        cap_interval(nc, L.tmax, new_lo, new_hi);
+        L.backtracks++;
     }
-    if (right) L.start ^= L.size;
-    L.splits++;
-    return kGoOn;
+    L.c = nc;
+    L.lo = new_lo;
+    L.hi = new_hi;
+    return st;
 }
 
 // Write the result of pair i (Section 3.3: u from projecting the hit point
@@ -760,7 +839,7 @@ __device__ __forceinline__ void finish(const Outs &a, int64_t i, const Lane &L, 
         }
     } else if (reached && L.t < L.tmax) {
         t = L.t;
-        u = leaf_u(L);
+        u = L.u;
         t64 = t;
         u64 = u;
         hit = true;
@@ -777,7 +856,7 @@ __device__ __forceinline__ void finish(const Outs &a, int64_t i, const Lane &L, 
         cn[0] = L.trips;
         cn[1] = L.splits;
         cn[2] = L.backtracks;
-        cn[3] = hit ? (int32_t)(23 - (31 - __builtin_clz(L.size))) : -1;
+        cn[3] = hit ? L.level : -1;
     }
 }
 
@@ -859,9 +938,9 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(Args a0, const Args *scen
             finish_invalid<MODE>(a, idx);
         } else {
             cap_interval(root, tmax, lo, hi);
-            float te, tx, lu;
+            float te, tx, lu, hu;
             const float slack = MODE == kConservative && depth > kRefineAbove ? root_slack(root) : -1.0f;
-            const bool vis = node_visible<MODE>(root, lo, hi, slack, te, tx, lu);
+            const bool vis = node_visible<MODE>(root, lo, hi, slack, te, tx, lu, hu);
             if (vis && depth > 0) {
                 keep = true;
             } else {
@@ -873,6 +952,8 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(Args a0, const Args *scen
                 L.tmax = tmax;
                 L.start = 0;
                 L.size = kRootSize;
+                L.u = leaf_u(L);
+                L.level = 0;
                 L.trips = 1;
                 L.splits = 0;
                 L.backtracks = 0;
@@ -921,7 +1002,9 @@ void k_traverse(Args a0, const Args *scenes, Table tab, const uint32_t *counts, 
     const int first = b * (tab.cap / kBuckets);
     int next = first + (j * share < rows ? j * share : rows);          // wave-uniform range
     const int end = first + ((j + 1) * share < rows ? (j + 1) * share : rows);
-    Lane L;
+    Lane L = {};
+    L.lo = INFINITY;                                                   // parked: see below
+    L.hi = -INFINITY;
     bool active = false;
     for (;;) {
         const uint64_t free_mask = __ballot(!active);
@@ -944,6 +1027,7 @@ void k_traverse(Args a0, const Args *scenes, Table tab, const uint32_t *counts, 
                     L.start = 0;
                     L.size = kRootSize;
                     L.cached = 0;
+                    L.fails = 0;
                     L.slack = MODE == kConservative && depth > kRefineAbove ? root_slack(L.c) : -1.0f;
                     L.trips = L.splits = L.backtracks = 0;
                     active = true;
@@ -951,21 +1035,28 @@ void k_traverse(Args a0, const Args *scenes, Table tab, const uint32_t *counts, 
             }
             next += take;
         }
-        if (__ballot(active) == 0) {
-            if (next >= end) break;
-            continue;
-        }
-        if (active) {
-            const int st = trip<MODE>(L, tab, col, a0);
-            if (st != kGoOn) {
-                const int64_t i = tab.pair[L.row];
-                if constexpr (BATCHED) {
-                    finish<MODE>(outs_of(scenes[tab.scene[L.row]]), i, L, st == kHit);
-                } else {
-                    finish<MODE>(outs_of(a0), i, L, st == kHit);
-                }
-                active = false;
+        // a wave with every lane free refills all of them, so an all-idle
+        // wave here has no rows left
+        if (__ballot(active) == 0) break;
+        // every lane runs the trip: an idle lane is parked with an empty
+        // interval and no pending sibling, so its test fails and it leaves at
+        // the first check, never taking the backtrack or descent paths; the
+        // compiler then keeps one copy of the lane state instead of merging
+        // active and idle ones
+        const int st = trip<MODE>(L, tab, col, a0);
+        if (active && st != kGoOn) {
+            const int64_t i = tab.pair[L.row];
+            if constexpr (BATCHED) {
+                finish<MODE>(outs_of(scenes[tab.scene[L.row]]), i, L, st == kHit);
+            } else {
+                finish<MODE>(outs_of(a0), i, L, st == kHit);
             }
+            active = false;
+        }
+        if (!active) {
+            L.lo = INFINITY;
+            L.hi = -INFINITY;
+            L.bits = 0;
         }
     }
 }
