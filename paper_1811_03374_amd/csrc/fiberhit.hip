@@ -282,8 +282,9 @@ struct Args {
 
 constexpr int kRefineAbove = 16;         // refine pairs of depth > 16
 constexpr int kLeafSamples = 16;         // phi samples over a leaf's u window (three leaves)
-constexpr int kRefineFails = 16;         // leaves without the solid before the whole-curve search
-constexpr int kCurveSamples = 1024;      // phi samples over the whole curve
+constexpr int kRefineFails = 4;          // leaves without the solid before the whole-curve search
+constexpr int kCurveSamples = 128;       // phi samples over the whole curve (local minima are searched)
+constexpr int kRefineBatch = 16;         // parked lanes that trigger a wave's FP64 leaf checks
 
 struct Curve64 {
     double q[4][4];                      // control points in the FP64 ray frame (x, y, z, r)
@@ -393,7 +394,7 @@ __device__ __forceinline__ bool newton_surface(const Curve64 &c, double &t, doub
 __device__ __forceinline__ bool boundary_root(const Curve64 &c, double lo, double hi, bool lo_in, double &t,
                                               double &u)
 {
-    for (int it = 0; it < 64; ++it) {
+    for (int it = 0; it < 44; ++it) {               // to 2^-44 of the bracket; Newton finishes
         const double mid = 0.5 * (lo + hi);
         if (!(mid > lo && mid < hi)) break;
         double mt, mphi;
@@ -509,6 +510,9 @@ struct Lane {
     uint32_t min_size;            // leaf size 2^(23 - depth)
     uint32_t cached;              // size of the pending children whose parent is cached (0: none)
     int32_t fails;                // refinement: leaves reached that held no part of the solid
+    int32_t waiting;              // refinement: parked at a leaf until the wave checks its batch
+    uint32_t rbits;               //   pending bits to resume with if the leaf holds no solid
+    float ru, rtin, rtout;        //   the leaf's FP32 u and the ray interval it owns
     int32_t row;                  // row of this pair in the survivor table
     float slack;                  // conservative mode: bound on across-ray rounding of any node
                                   // (negative: a pair of depth <= 16, searched by the plain rules)
@@ -635,7 +639,11 @@ __device__ __forceinline__ bool node_visible(const Node &c, float lo, float hi, 
     float rad = conservative_radius(c);
     if (MODE == kConservative && slack >= 0.0f) {
         rad += slack + rad * 0x1p-18f;
-        const float tslack = (fabsf(lo) + fabsf(hi < INFINITY ? hi : lo)) * 0x1p-17f;
+        // an interval emptied on purpose (a parked lane, a cap plane parallel
+        // to the ray that excludes it) must stay empty: no slack, since
+        // infinite bounds would turn it into NaN, which fmaxf/fminf ignore
+        const bool open = lo < INFINITY && hi > -INFINITY;
+        const float tslack = open ? (fabsf(lo) + fabsf(hi < INFINITY ? hi : lo)) * 0x1p-17f : 0.0f;
         lo -= tslack;
         hi += tslack;
     }
@@ -670,8 +678,9 @@ __device__ __forceinline__ float leaf_u(const Lane &L)
 // the ray the leaf owns, [tin, tout] (the enlarged test's interval, widened
 // by 2^-20 of its size and of t), among discs with u up to one leaf beyond
 // the leaf on either side. Sets L.t64 / L.u64 and returns true when found.
-__device__ __noinline__ bool refine_at_leaf(Lane &L, const Table &tab, const Args &in, float tin, float tout)
+__device__ __noinline__ bool refine_at_leaf(Lane &L, const Table &tab, const Args &in)
 {
+    const float tin = L.rtin, tout = L.rtout;
     const int64_t i = tab.pair[L.row];
     const int64_t ri = in.pair_ray ? (int64_t)in.pair_ray[i] : i;
     const int64_t fi = in.pair_fiber ? (int64_t)in.pair_fiber[i] : i;
@@ -683,7 +692,7 @@ __device__ __noinline__ bool refine_at_leaf(Lane &L, const Table &tab, const Arg
     const double t0 = tin, t1 = tout < INFINITY ? (double)tout : (double)L.tmax;
     const double pad = ((t1 - t0) + fmax(fabs(t0), fabs(t1))) * 0x1p-20;
     double t = INFINITY, u = __builtin_nan("");
-    leaf_candidates(cv, ua, ub, fmax(0.0, t0 - pad), t1 + pad, (double)L.tmax, (double)L.t, (double)leaf_u(L),
+    leaf_candidates(cv, ua, ub, fmax(0.0, t0 - pad), t1 + pad, (double)L.tmax, (double)L.t, (double)L.ru,
                     kLeafSamples, t, u);
     if (!(t < INFINITY)) return false;
     L.t64 = t;
@@ -704,7 +713,7 @@ __device__ __noinline__ bool refine_whole_curve(Lane &L, const Table &tab, const
     Curve64 cv;
     if (!curve_in_ray_frame(in.rays + ri, in.ray_stride, in.fibers + fi, in.fiber_stride, cv)) return false;
     double t = INFINITY, u = __builtin_nan("");
-    leaf_candidates(cv, 0.0, 1.0, 0.0, (double)L.tmax, (double)L.tmax, (double)L.t, (double)leaf_u(L),
+    leaf_candidates(cv, 0.0, 1.0, 0.0, (double)L.tmax, (double)L.tmax, (double)L.t, (double)L.ru,
                     kCurveSamples, t, u);
     if (!(t < INFINITY)) return false;
     L.t64 = t;
@@ -727,10 +736,18 @@ __device__ __forceinline__ int trip(Lane &L, const Table &tab, float *col, const
     bool vis = node_visible<MODE>(L.c, L.lo, L.hi, L.slack, te, tx, lo, hi);
     const bool leaf = L.size <= L.min_size;
     if (MODE == kConservative && vis && leaf && L.slack >= 0.0f) {
-        // refinement: the first point of the swept solid in this leaf, else go on
+        // refinement: park the lane at this leaf (empty interval, no pending
+        // sibling) until the wave checks a batch of leaves in FP64; the leaf's
+        // data and the pending bits are kept for that check
         L.t = fmaxf(te, lo);
-        if (refine_at_leaf(L, tab, in, L.t, fminf(tx, hi))) return kHit;
-        if (++L.fails >= kRefineFails) return refine_whole_curve(L, tab, in) ? kHit : kMiss;
+        L.ru = leaf_u(L);
+        L.rtin = L.t;
+        L.rtout = fminf(tx, hi);
+        L.rbits = L.bits;
+        L.bits = 0;
+        L.lo = INFINITY;
+        L.hi = -INFINITY;
+        L.waiting = 1;
         vis = false;
     }
     // A lane that stops here still runs the rest of the trip (its state is
@@ -1028,6 +1045,7 @@ void k_traverse(Args a0, const Args *scenes, Table tab, const uint32_t *counts, 
                     L.size = kRootSize;
                     L.cached = 0;
                     L.fails = 0;
+                    L.waiting = 0;
                     L.slack = MODE == kConservative && depth > kRefineAbove ? root_slack(L.c) : -1.0f;
                     L.trips = L.splits = L.backtracks = 0;
                     active = true;
@@ -1044,7 +1062,7 @@ void k_traverse(Args a0, const Args *scenes, Table tab, const uint32_t *counts, 
         // compiler then keeps one copy of the lane state instead of merging
         // active and idle ones
         const int st = trip<MODE>(L, tab, col, a0);
-        if (active && st != kGoOn) {
+        if (active && st != kGoOn && !(MODE == kConservative && L.waiting)) {
             const int64_t i = tab.pair[L.row];
             if constexpr (BATCHED) {
                 finish<MODE>(outs_of(scenes[tab.scene[L.row]]), i, L, st == kHit);
@@ -1052,6 +1070,25 @@ void k_traverse(Args a0, const Args *scenes, Table tab, const uint32_t *counts, 
                 finish<MODE>(outs_of(a0), i, L, st == kHit);
             }
             active = false;
+        }
+        if constexpr (MODE == kConservative && !BATCHED) {
+            // FP64 leaf checks run for a batch of parked lanes at once (SIMD
+            // lanes of one call), once 16 are parked or no other lane is busy
+            const uint64_t parked = __ballot(L.waiting != 0);
+            if (parked != 0 && (__popcll(parked) >= kRefineBatch || __ballot(active && !L.waiting) == 0)) {
+                if (L.waiting) {
+                    L.waiting = 0;
+                    int done = refine_at_leaf(L, tab, a0) ? kHit : kGoOn;
+                    if (done == kGoOn && ++L.fails >= kRefineFails)
+                        done = refine_whole_curve(L, tab, a0) ? kHit : kMiss;
+                    if (done != kGoOn) {
+                        finish<MODE>(outs_of(a0), tab.pair[L.row], L, done == kHit);
+                        active = false;
+                    } else {
+                        L.bits = L.rbits;          // the leaf holds no solid: go on past it
+                    }
+                }
+            }
         }
         if (!active) {
             L.lo = INFINITY;
@@ -1227,7 +1264,7 @@ int device_info(DeviceInfo *&out)
 // Launch defaults of single-problem calls (and of batches without a tuned
 // entry); measured choices, overridable when building.
 #ifndef FIBERHIT_DEFAULT_REFILL
-#define FIBERHIT_DEFAULT_REFILL 32
+#define FIBERHIT_DEFAULT_REFILL 48
 #endif
 #ifndef FIBERHIT_DEFAULT_WAVES_PER_SIMD
 #define FIBERHIT_DEFAULT_WAVES_PER_SIMD 0
