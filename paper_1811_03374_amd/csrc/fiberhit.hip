@@ -762,8 +762,34 @@ __device__ __forceinline__ int trip(Lane &L, const Table &tab, float *col, const
     }
     const bool over = ++L.trips > kMaxTrips;          // hang guard (each trip is a test)
     if ((!vis && L.bits == 0) || over) st = kMiss;
+    // A backtracking lane first rebuilds the parent of its pending sibling
+    // (Section 3.3: the deepest level with a pending sibling) -- the cached
+    // parent, or a replay of the split rules from the root along the integer
+    // path -- and then takes the same split as a descending lane: one split
+    // per trip for every continuing lane.
+    const bool back = !vis && st == kGoOn;
+    if (back) {
+        L.size = L.bits & (0u - L.bits);
+        L.start ^= L.size;
+        L.bits ^= L.size;
+        L.start &= ~(L.size - 1u);
+        if (kParentCache && L.cached == L.size) {
+            lds_get(col, L.c);
+        } else {
+            // keep the root's global loads inside this branch: hoisted above it
+            // they would delay every cached rebuild by a memory round trip
+            asm volatile("" ::: "memory");
+            table_root(tab, L.row, L.c);
+            for (uint32_t b = kRootSize >> 1; b > L.size; b >>= 1) {
+                V4 rdp, rtc;
+                split_terms(L.c, rdp, rtc);
+                take_child(L.c, rdp, rtc, (L.start & b) != 0u);
+            }
+        }
+        L.cached = 0;
+    }
     // Section 3.1 / 3.2: split plane through the centre, normal to the split
-    // tangent; the half the ray meets first is the child
+    // tangent; a descending lane goes to the half the ray meets first
     V4 dp, tc;
     split_terms(L.c, dp, tc);
     float nx = tc.x, ny = tc.y, nz = tc.z;
@@ -791,49 +817,24 @@ __device__ __forceinline__ int trip(Lane &L, const Table &tab, float *col, const
         else         nlo = fmaxf(nlo, tp);
     }
     // a plane parallel to the ray leaves the whole ray on the side of sign(-cs)
-    const bool right = oblique ? ((tp > te) != (nz > 0.0f)) : cs < 0.0f;
-    Node nc = L.c;
-    take_child(nc, dp, tc, right);
-    float new_lo = oblique ? nlo : L.lo, new_hi = oblique ? nhi : L.hi;
-    if (st != kGoOn) {
-        // the pair ends here; its state is not used again
-    } else if (vis) {
-        if (kParentCache && both) lds_put(col, L.c);
+    const bool near_right = oblique ? ((tp > te) != (nz > 0.0f)) : cs < 0.0f;
+    const bool descend = vis && st == kGoOn;
+    if (kParentCache && descend && both) lds_put(col, L.c);
+    const bool right = back ? (L.start & L.size) != 0u : near_right;
+    take_child(L.c, dp, tc, right);
+    if (back) {
+        cap_interval(L.c, L.tmax, L.lo, L.hi);
+        L.backtracks++;
+    } else if (descend) {
+        if (oblique) { L.lo = nlo; L.hi = nhi; }
         L.size >>= 1;
         if (both) {
             L.bits ^= L.size;
             if (kParentCache) L.cached = L.size;
         }
-        if (right) L.start ^= L.size;
+        if (near_right) L.start ^= L.size;
         L.splits++;
-    } else {
-        // Section 3.3: jump to the deepest level with a pending sibling and
-        // rebuild it -- one split of the cached parent, or a replay of the
-        // split rules along the integer path from the root
-        L.size = L.bits & (0u - L.bits);
-        L.start ^= L.size;
-        L.bits ^= L.size;
-        L.start &= ~(L.size - 1u);
-        if (kParentCache && L.cached == L.size) {
-            lds_get(col, nc);
-        } else {
-            table_root(tab, L.row, nc);
-            for (uint32_t b = kRootSize >> 1; b > L.size; b >>= 1) {
-                V4 rdp, rtc;
-                split_terms(nc, rdp, rtc);
-                take_child(nc, rdp, rtc, (L.start & b) != 0u);
-            }
-        }
-        L.cached = 0;
-        V4 rdp, rtc;
-        split_terms(nc, rdp, rtc);
-        take_child(nc, rdp, rtc, (L.start & L.size) != 0u);
-        cap_interval(nc, L.tmax, new_lo, new_hi);
-        L.backtracks++;
     }
-    L.c = nc;
-    L.lo = new_lo;
-    L.hi = new_hi;
     return st;
 }
 
@@ -1264,7 +1265,7 @@ int device_info(DeviceInfo *&out)
 // Launch defaults of single-problem calls (and of batches without a tuned
 // entry); measured choices, overridable when building.
 #ifndef FIBERHIT_DEFAULT_REFILL
-#define FIBERHIT_DEFAULT_REFILL 48
+#define FIBERHIT_DEFAULT_REFILL 32
 #endif
 #ifndef FIBERHIT_DEFAULT_WAVES_PER_SIMD
 #define FIBERHIT_DEFAULT_WAVES_PER_SIMD 0
