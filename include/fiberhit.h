@@ -16,16 +16,16 @@
  * the legacy default stream); results are valid once the stream has
  * synchronised.
  *
- * Each call runs as two kernels per chunk of up to 2^20 pairs: a setup kernel
- * (one lane per pair: load, FP64 move into the ray frame, root test; pairs
- * decided at the root are written out) and a persistent traversal kernel over
- * the survivors, which it reads from a survivor table (85 bytes per row).
- * fiber_intersect_pairs and fiber_intersect_counts own two such tables per
- * device (2 x 85 MiB), allocated at their first call on that device and kept
- * for the process; calls that share a table are ordered on the GPU through an
- * event, so calls on different streams stay correct. Batched calls take
- * theirs from the caller's workspace or plan and allocate nothing on the
- * call path.
+ * Each call runs as two kernels per chunk of pairs: a setup kernel (one lane
+ * per pair: load, FP64 move into the ray frame, root test; pairs decided at
+ * the root are written out) and a persistent traversal kernel over the
+ * survivors, which it reads from a survivor table (85 bytes per row).
+ * fiber_intersect_pairs and fiber_intersect_counts use chunks of 2^20 pairs
+ * and own two such tables per device (2 x 85 MiB), allocated at their first
+ * call on that device and kept for the process; calls that share a table are
+ * ordered on the GPU through an event, so calls on different streams stay
+ * correct. Batched calls use chunks of 2^22 pairs in a table from the
+ * caller's workspace or the plan, and allocate nothing on the call path.
  *
  * Layouts (structure of arrays, 32-bit floats, row-major):
  *   rays   : 7 rows of ray_stride floats  -- ox, oy, oz, dx, dy, dz, tmax.
@@ -179,8 +179,8 @@ typedef struct fi_tuning {
 
 /* Bytes of device workspace fiber_intersect_batched needs for n_scenes
  * problems of total_pairs pairs in all (0 for negative arguments): the scene
- * table, the bucket counters and a survivor table of min(total_pairs, 2^20)
- * rows, rounded up to a multiple of 65536. */
+ * table, the bucket counters and a survivor table of min(total_pairs, 2^22)
+ * rows, rounded up to a multiple of 65536 (85 bytes per row). */
 size_t fiber_batched_workspace_bytes(int32_t n_scenes, int64_t total_pairs);
 
 /*
@@ -190,7 +190,7 @@ size_t fiber_batched_workspace_bytes(int32_t n_scenes, int64_t total_pairs);
  * Operation: for every scene k, exactly what fiber_intersect_pairs computes
  * for scenes[k] (same per-pair routine; results are bitwise identical to a
  * separate call per scene). Pairs of all scenes are numbered consecutively;
- * one setup launch covers them all (per chunk of 2^20) and one traversal
+ * one setup launch covers them all (per chunk of 2^22) and one traversal
  * launch drains the survivors of all scenes together, so small scenes do not
  * leave the GPU idle.
  *

@@ -1151,8 +1151,10 @@ const TraverseFn kTraverse[3][2] = {
 // bucket (a bucket holds rows of at most cap / (kBuckets * kSetupBlock)
 // blocks of kSetupBlock pairs each).
 constexpr int64_t kTableQuantum = (int64_t)kBuckets * kSetupBlock;
-constexpr int64_t kChunkRows = 1 << 20;
+constexpr int64_t kChunkRows = 1 << 20;         // single-problem calls: tables the library owns
+constexpr int64_t kBatchChunkRows = 1 << 22;    // batched calls and plans: the caller's workspace
 static_assert(kChunkRows % kTableQuantum == 0, "chunk must be a whole number of table quanta");
+static_assert(kBatchChunkRows % kTableQuantum == 0, "chunk must be a whole number of table quanta");
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -1178,11 +1180,12 @@ Table table_at(void *base, int64_t rows)
     return t;
 }
 
-// Rows a call of `total` pairs uses: one chunk at most, a whole number of
-// table quanta.
+// Rows a batched call of `total` pairs uses: one chunk at most, a whole number
+// of table quanta. Larger chunks than single calls use: fewer setup passes and
+// traversal tails for a big batch, and more rows per traversal wave.
 int64_t rows_for(int64_t total)
 {
-    const int64_t r = total < kChunkRows ? total : kChunkRows;
+    const int64_t r = total < kBatchChunkRows ? total : kBatchChunkRows;
     return ((r > 0 ? r : 1) + kTableQuantum - 1) / kTableQuantum * kTableQuantum;
 }
 

@@ -137,10 +137,10 @@ def test_batched_argument_errors():
 
 
 def test_batched_longer_than_one_chunk():
-    """1.2 million pairs in three problems: the batch runs as two
-    setup/traversal chunks whose boundary falls inside a problem; results
-    stay bitwise equal to one call per problem."""
-    sizes = [400_000, 3, 800_000]
+    """4.3 million pairs in three problems: the batch runs as two
+    setup/traversal chunks of 2^22 whose boundary falls inside a problem;
+    results stay bitwise equal to one call per problem."""
+    sizes = [1_500_000, 3, 2_800_000]
     probs = []
     for k, n in enumerate(sizes):
         w = W.straight_and_curved(n, 22, seed=4242 + k)
