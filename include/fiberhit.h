@@ -24,8 +24,13 @@
  * and own two such tables per device (2 x 85 MiB), allocated at their first
  * call on that device and kept for the process; calls that share a table are
  * ordered on the GPU through an event, so calls on different streams stay
- * correct. Batched calls use chunks of 2^22 pairs in a table from the
- * caller's workspace or the plan, and allocate nothing on the call path.
+ * correct. When a single call gathers fibers through pair_fiber with at least
+ * as many pairs as fibers, the fibers are first copied to 64-byte records (one
+ * gathered fiber is then one or two cache lines instead of sixteen), in a
+ * per-table buffer that grows to the largest such call (up to 1 GiB; beyond
+ * that the gather reads the rows directly). Batched calls use chunks of 2^22
+ * pairs in a table from the caller's workspace or the plan, and allocate
+ * nothing on the call path.
  *
  * Layouts (structure of arrays, 32-bit floats, row-major):
  *   rays   : 7 rows of ray_stride floats  -- ox, oy, oz, dx, dy, dz, tmax.

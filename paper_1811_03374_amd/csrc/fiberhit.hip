@@ -607,7 +607,11 @@ __device__ __forceinline__ void lds_get(const float *col, Node &r)
 
 // Load pair i and move it into the ray frame. False when the pair is a
 // definite miss (bad index, depth, direction or tmax).
-__device__ __forceinline__ bool load_pair(const Args &a, int64_t i, Node &root, float &tmax, uint32_t &depth)
+// `aos`, when given, holds the fibers as 16 consecutive floats each (see
+// k_fibers_aos): a gathered fiber is then one or two cache lines instead of
+// one line per coordinate row.
+__device__ __forceinline__ bool load_pair(const Args &a, int64_t i, Node &root, float &tmax, uint32_t &depth,
+                                          const float *aos)
 {
     const int64_t ri = a.pair_ray ? (int64_t)a.pair_ray[i] : i;
     const int64_t fi = a.pair_fiber ? (int64_t)a.pair_fiber[i] : i;
@@ -616,6 +620,7 @@ __device__ __forceinline__ bool load_pair(const Args &a, int64_t i, Node &root, 
     const float *R = a.rays + ri;
     tmax = R[6 * a.ray_stride];
     if (!(tmax == tmax)) return false;
+    if (aos) return root_in_ray_frame(R, a.ray_stride, aos + 16 * fi, 1, root);
     return root_in_ray_frame(R, a.ray_stride, a.fibers + fi, a.fiber_stride, root);
 }
 
@@ -930,7 +935,7 @@ constexpr int kCounterWords = 2 * kBuckets;   // two sets
 template <int MODE, bool BATCHED>
 __global__ __launch_bounds__(kSetupBlock) void k_setup(Args a0, const Args *scenes, const int64_t *offsets,
                                                       int n_scenes, int64_t begin, int64_t count, Table tab,
-                                                      uint32_t *counts, uint32_t *stale)
+                                                      uint32_t *counts, uint32_t *stale, const float *aos)
 {
     __shared__ uint32_t s_wave[kSetupBlock / kWave];
     __shared__ uint32_t s_base;
@@ -952,7 +957,7 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(Args a0, const Args *scen
         } else {
             idx = g;
         }
-        if (!load_pair(a, idx, root, tmax, depth)) {
+        if (!load_pair(a, idx, root, tmax, depth, BATCHED ? nullptr : aos)) {
             finish_invalid<MODE>(a, idx);
         } else {
             cap_interval(root, tmax, lo, hi);
@@ -1099,6 +1104,19 @@ void k_traverse(Args a0, const Args *scenes, Table tab, const uint32_t *counts, 
     }
 }
 
+// Fibers transposed to 16 consecutive floats each, for calls that gather them
+// through pair indices (one lane per fiber: coalesced row reads, 64-byte
+// records written as four 16-byte stores).
+__global__ __launch_bounds__(256) void k_fibers_aos(const float *F, int64_t fs, int64_t nf, float4 *out)
+{
+    const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (f >= nf) return;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        out[4 * f + k] = make_float4(F[(4 * k) * fs + f], F[(4 * k + 1) * fs + f], F[(4 * k + 2) * fs + f],
+                                     F[(4 * k + 3) * fs + f]);
+}
+
 // Zero both counter sets from inside a stream or graph (a kernel, not a
 // memset node, so that graph replays see fresh counters).
 __global__ void k_reset_counters(uint32_t *counters)
@@ -1129,7 +1147,7 @@ int check_common(const float *rays, int64_t ray_stride, int64_t n_rays,
 // ---------------------------------------------------------------------------
 
 using SetupFn = void (*)(Args, const Args *, const int64_t *, int, int64_t, int64_t, Table, uint32_t *,
-                         uint32_t *);
+                         uint32_t *, const float *);
 using TraverseFn = void (*)(Args, const Args *, Table, const uint32_t *, int, int);
 
 // [mode][batched]. Batched calls take neither counts nor refinement: their
@@ -1203,6 +1221,8 @@ constexpr size_t kStageBytes = 1u << 20;
 struct Region {
     std::mutex m;
     void *mem;                                 // survivor table of kChunkRows rows
+    float *aos;                                // fibers as 16-float records (gathered calls)
+    size_t aos_bytes;
     uint32_t *counters;                        // two sets of kBuckets counters
     int parity;                                // the set that is zero for the next chunk
     hipEvent_t done;                           // recorded after the last call that used it
@@ -1251,6 +1271,8 @@ int device_info(DeviceInfo *&out)
                 }
             for (int r = 0; r < kRegions; ++r) {
                 d.region[r].mem = nullptr;
+                d.region[r].aos = nullptr;
+                d.region[r].aos_bytes = 0;
                 d.region[r].counters = (uint32_t *)p + r * kCounterWords;
                 d.region[r].parity = 0;
                 d.region[r].done = nullptr;
@@ -1342,7 +1364,7 @@ unsigned traverse_grid(const DeviceInfo &d, int mode, bool batched, const fi_tun
 // after the last chunk.
 int launch_chain(const DeviceInfo &d, int mode, bool batched, const fi_tuning &t, const Args &a0,
                  const Args *scenes, const int64_t *offsets, int n_scenes, int64_t total, const Table &tab,
-                 uint32_t *counters, int parity, hipStream_t s)
+                 uint32_t *counters, int parity, hipStream_t s, const float *aos = nullptr)
 {
     const int b = batched ? 1 : 0;
     for (int64_t begin = 0; begin < total; begin += tab.cap) {
@@ -1352,7 +1374,7 @@ int launch_chain(const DeviceInfo &d, int mode, bool batched, const fi_tuning &t
         uint32_t *cur = counters + parity * kBuckets;
         uint32_t *other = counters + (1 - parity) * kBuckets;
         hipLaunchKernelGGL(kSetup[mode][b], dim3((unsigned)blocks), dim3(kSetupBlock), 0, s, a0, scenes, offsets,
-                           n_scenes, begin, count, tab, cur, other);
+                           n_scenes, begin, count, tab, cur, other, aos);
         hipLaunchKernelGGL(kTraverse[mode][b], dim3(traverse_grid(d, mode, batched, t, count, n_buckets)),
                            dim3(kWave), 0, s, a0, scenes, tab, (const uint32_t *)cur, n_buckets, t.refill);
         parity = 1 - parity;
@@ -1378,9 +1400,34 @@ int launch(int mode, const Args &a, void *stream)
             }
             if (hipEventCreateWithFlags(&R.done, hipEventDisableTiming) != hipSuccess) return FI_ERR_HIP;
         }
+        // a gathered pairing that reads each fiber about once or more: copy
+        // the fibers to 16-float records first (one pass over them; the
+        // buffer grows to the largest such call, up to 1 GiB)
+        const float *aos = nullptr;
+        const size_t need = (size_t)a.n_fibers * 16 * sizeof(float);
+        if (a.pair_fiber && a.n_fibers > 0 && a.n_pairs >= a.n_fibers && need <= ((size_t)1 << 30)) {
+            if (R.aos_bytes < need) {
+                if (R.aos) {
+                    if (R.pending && hipEventSynchronize(R.done) != hipSuccess) return FI_ERR_HIP;
+                    (void)hipFree(R.aos);
+                    R.aos = nullptr;
+                    R.aos_bytes = 0;
+                }
+                if (hipMalloc(&R.aos, need) != hipSuccess) {
+                    R.aos = nullptr;
+                    (void)hipGetLastError();
+                    return FI_ERR_HIP;
+                }
+                R.aos_bytes = need;
+            }
+            aos = R.aos;
+        }
         if (R.pending && hipStreamWaitEvent(s, R.done, 0) != hipSuccess) return FI_ERR_HIP;
+        if (aos)
+            hipLaunchKernelGGL(k_fibers_aos, dim3((unsigned)((a.n_fibers + 255) / 256)), dim3(256), 0, s,
+                               a.fibers, a.fiber_stride, a.n_fibers, (float4 *)R.aos);
         R.parity = launch_chain(*d, mode, false, default_tuning(), a, nullptr, nullptr, 1, a.n_pairs,
-                                table_at(R.mem, kChunkRows), R.counters, R.parity, s);
+                                table_at(R.mem, kChunkRows), R.counters, R.parity, s, aos);
         if (hipEventRecord(R.done, s) != hipSuccess) return FI_ERR_HIP;
         R.pending = true;
     }
