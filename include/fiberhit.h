@@ -232,7 +232,7 @@ int fiber_batch_plan_destroy(fi_batch_plan *plan);
 
 /*
  * fiber_batch_autotune -- time fiber_intersect_batched on these scenes over a
- * grid of tunings (refill 16, 32 or 48; waves per SIMD 4, 6 or as many as
+ * grid of tunings (refill 8, 16 or 32; waves per SIMD 4, 6 or as many as
  * fit), each `repeats`
  * times after one warm-up, and return the fastest
  * in *best (and its time in *best_ms if not NULL). Overwrites the scenes'

@@ -159,24 +159,30 @@ __device__ __forceinline__ bool root_in_ray_frame(const float *R, int64_t rs, co
 __device__ __forceinline__ void cap_interval(const Node &c, float tmax, float &lo, float &hi)
 {
     float n0x = c.t0.x, n0y = c.t0.y, n0z = c.t0.z;
-    if (zero3(n0x, n0y, n0z)) { n0x = c.d.x - c.t1.x; n0y = c.d.y - c.t1.y; n0z = c.d.z - c.t1.z; }
-    if (zero3(n0x, n0y, n0z)) { n0x = c.d.x; n0y = c.d.y; n0z = c.d.z; }
     float n1x = c.t1.x, n1y = c.t1.y, n1z = c.t1.z;
-    if (zero3(n1x, n1y, n1z)) { n1x = c.d.x - c.t0.x; n1y = c.d.y - c.t0.y; n1z = c.d.z - c.t0.z; }
-    if (zero3(n1x, n1y, n1z)) { n1x = c.d.x; n1y = c.d.y; n1z = c.d.z; }
+    if (zero3(n0x, n0y, n0z) || zero3(n1x, n1y, n1z)) {
+        // rare (a vanishing end tangent): kept out of the common path
+        if (zero3(n0x, n0y, n0z)) { n0x = c.d.x - c.t1.x; n0y = c.d.y - c.t1.y; n0z = c.d.z - c.t1.z; }
+        if (zero3(n0x, n0y, n0z)) { n0x = c.d.x; n0y = c.d.y; n0z = c.d.z; }
+        if (zero3(n1x, n1y, n1z)) { n1x = c.d.x - c.t0.x; n1y = c.d.y - c.t0.y; n1z = c.d.z - c.t0.z; }
+        if (zero3(n1x, n1y, n1z)) { n1x = c.d.x; n1y = c.d.y; n1z = c.d.z; }
+    }
 
-    float l = 0.0f, h = tmax;
+    // both crossings are computed and selected by the signs of the normals'
+    // z (no divergent branches); a plane parallel to the ray keeps the whole
+    // ray or none of it
     const float c0 = dot3(c.p.x, c.p.y, c.p.z, n0x, n0y, n0z);
-    if (n0z > 0.0f)      l = fmaxf(l, c0 * rcp(n0z));
-    else if (n0z < 0.0f) h = fminf(h, c0 * rcp(n0z));
-    else if (c0 > 0.0f)  { l = INFINITY; h = -INFINITY; }
+    const float q0 = c0 * rcp(n0z);
     const float ex = c.p.x + c.d.x, ey = c.p.y + c.d.y, ez = c.p.z + c.d.z;
     const float c1 = dot3(ex, ey, ez, n1x, n1y, n1z);
-    if (n1z > 0.0f)      h = fminf(h, c1 * rcp(n1z));
-    else if (n1z < 0.0f) l = fmaxf(l, c1 * rcp(n1z));
-    else if (c1 < 0.0f)  { l = INFINITY; h = -INFINITY; }
-    lo = l;
-    hi = h;
+    const float q1 = c1 * rcp(n1z);
+    float l = n0z > 0.0f ? fmaxf(0.0f, q0) : 0.0f;
+    float h = n0z < 0.0f ? fminf(tmax, q0) : tmax;
+    h = n1z > 0.0f ? fminf(h, q1) : h;
+    l = n1z < 0.0f ? fmaxf(l, q1) : l;
+    const bool empty = (n0z == 0.0f && c0 > 0.0f) || (n1z == 0.0f && c1 < 0.0f);
+    lo = empty ? INFINITY : l;
+    hi = empty ? -INFINITY : h;
 }
 
 // Conservative cylinder radius (Section 3.3): largest distance of the inner
@@ -514,6 +520,7 @@ struct Lane {
     uint32_t rbits;               //   pending bits to resume with if the leaf holds no solid
     float ru, rtin, rtout;        //   the leaf's FP32 u and the ray interval it owns
     int32_t row;                  // row of this pair in the survivor table
+    int32_t pair;                 // index of the pair within its problem
     float slack;                  // conservative mode: bound on across-ray rounding of any node
                                   // (negative: a pair of depth <= 16, searched by the plain rules)
     int32_t trips, splits, backtracks;
@@ -580,11 +587,19 @@ __device__ __forceinline__ void table_put(const Table &tab, int32_t row, const N
     tab.depth[row] = (uint8_t)depth;
 }
 
+// Element `row` of table row k: a wave-uniform row base plus a 32-bit byte
+// offset, so each load needs no per-lane 64-bit address arithmetic.
+__device__ __forceinline__ float table_at(const Table &tab, int k, uint32_t row)
+{
+    const char *base = (const char *)(tab.f + (size_t)k * (uint32_t)tab.cap);
+    return *(const float *)(base + row * 4u);
+}
+
 __device__ __forceinline__ void table_root(const Table &tab, int32_t row, Node &r)
 {
     float *f = &r.p.x;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) f[k] = tab.f[k * tab.cap + row];
+    for (int k = 0; k < 16; ++k) f[k] = table_at(tab, k, (uint32_t)row);
 }
 
 // Per-lane LDS column (conflict-free: lane-contiguous rows of 64 floats) that
@@ -686,7 +701,7 @@ __device__ __forceinline__ float leaf_u(const Lane &L)
 __device__ __noinline__ bool refine_at_leaf(Lane &L, const Table &tab, const Args &in)
 {
     const float tin = L.rtin, tout = L.rtout;
-    const int64_t i = tab.pair[L.row];
+    const int64_t i = L.pair;
     const int64_t ri = in.pair_ray ? (int64_t)in.pair_ray[i] : i;
     const int64_t fi = in.pair_fiber ? (int64_t)in.pair_fiber[i] : i;
     Curve64 cv;
@@ -712,7 +727,7 @@ __device__ __noinline__ bool refine_at_leaf(Lane &L, const Table &tab, const Arg
 // boundary point with t in [0, tmax), sampled at kCurveSamples parameters.
 __device__ __noinline__ bool refine_whole_curve(Lane &L, const Table &tab, const Args &in)
 {
-    const int64_t i = tab.pair[L.row];
+    const int64_t i = L.pair;
     const int64_t ri = in.pair_ray ? (int64_t)in.pair_ray[i] : i;
     const int64_t fi = in.pair_fiber ? (int64_t)in.pair_fiber[i] : i;
     Curve64 cv;
@@ -798,10 +813,11 @@ __device__ __forceinline__ int trip(Lane &L, const Table &tab, float *col, const
     V4 dp, tc;
     split_terms(L.c, dp, tc);
     float nx = tc.x, ny = tc.y, nz = tc.z;
-    const bool flat = zero3(nx, ny, nz);
-    nx = flat ? L.c.d.x : nx;
-    ny = flat ? L.c.d.y : ny;
-    nz = flat ? L.c.d.z : nz;
+    if (zero3(nx, ny, nz)) {            // rare: no split tangent, split normal to the chord
+        nx = L.c.d.x;
+        ny = L.c.d.y;
+        nz = L.c.d.z;
+    }
     const float qx = L.c.p.x + dp.x, qy = L.c.p.y + dp.y, qz = L.c.p.z + dp.z;
     const float cs = dot3(qx, qy, qz, nx, ny, nz);
     const float tp = cs * rcp(nz);
@@ -1040,12 +1056,13 @@ void k_traverse(Args a0, const Args *scenes, Table tab, const uint32_t *counts, 
                 if (rank < take) {
                     const int r = next + rank;
                     table_root(tab, r, L.c);
-                    L.lo = tab.f[16 * tab.cap + r];
-                    L.hi = tab.f[17 * tab.cap + r];
-                    L.tmax = tab.f[18 * tab.cap + r];
+                    L.lo = table_at(tab, 16, (uint32_t)r);
+                    L.hi = table_at(tab, 17, (uint32_t)r);
+                    L.tmax = table_at(tab, 18, (uint32_t)r);
                     const uint32_t depth = tab.depth[r];
                     L.min_size = kRootSize >> depth;
                     L.row = r;
+                    L.pair = tab.pair[r];
                     L.bits = 0;
                     L.start = 0;
                     L.size = kRootSize;
@@ -1069,7 +1086,7 @@ void k_traverse(Args a0, const Args *scenes, Table tab, const uint32_t *counts, 
         // active and idle ones
         const int st = trip<MODE>(L, tab, col, a0);
         if (active && st != kGoOn && !(MODE == kConservative && L.waiting)) {
-            const int64_t i = tab.pair[L.row];
+            const int64_t i = L.pair;
             if constexpr (BATCHED) {
                 finish<MODE>(outs_of(scenes[tab.scene[L.row]]), i, L, st == kHit);
             } else {
@@ -1088,7 +1105,7 @@ void k_traverse(Args a0, const Args *scenes, Table tab, const uint32_t *counts, 
                     if (done == kGoOn && ++L.fails >= kRefineFails)
                         done = refine_whole_curve(L, tab, a0) ? kHit : kMiss;
                     if (done != kGoOn) {
-                        finish<MODE>(outs_of(a0), tab.pair[L.row], L, done == kHit);
+                        finish<MODE>(outs_of(a0), L.pair, L, done == kHit);
                         active = false;
                     } else {
                         L.bits = L.rbits;          // the leaf holds no solid: go on past it
@@ -1290,7 +1307,7 @@ int device_info(DeviceInfo *&out)
 // Launch defaults of single-problem calls (and of batches without a tuned
 // entry); measured choices, overridable when building.
 #ifndef FIBERHIT_DEFAULT_REFILL
-#define FIBERHIT_DEFAULT_REFILL 32
+#define FIBERHIT_DEFAULT_REFILL 8
 #endif
 #ifndef FIBERHIT_DEFAULT_WAVES_PER_SIMD
 #define FIBERHIT_DEFAULT_WAVES_PER_SIMD 0
@@ -1685,7 +1702,7 @@ int fiber_batch_autotune(const fi_scene *scenes, int32_t n_scenes, uint32_t flag
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return FI_ERR_HIP;
-    const int refills[] = {16, 32, 48};
+    const int refills[] = {8, 16, 32};
     const int occ[] = {4, 6, 0};
     float best_t = INFINITY;
     fi_tuning bt = default_tuning();

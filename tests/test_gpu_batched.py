@@ -117,7 +117,7 @@ def test_autotune_returns_a_grid_point():
     ws, sizes, probs = make_scenes(seed=17)
     best, ms = binding.autotune(probs, repeats=1)
     say(f"[autotune] {best} {ms:.3f} ms")
-    assert best["refill"] in (16, 32, 48) and best["waves_per_simd"] in (4, 6, 0)
+    assert best["refill"] in (8, 16, 32) and best["waves_per_simd"] in (4, 6, 0)
     assert ms > 0
 
 
