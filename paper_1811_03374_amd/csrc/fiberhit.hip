@@ -430,10 +430,19 @@ __device__ __forceinline__ bool boundary_root(const Curve64 &c, double lo, doubl
 // lies in one of the discs. The earliest boundary point of the solid is its
 // entry (or the origin, when inside), so no entry/exit classification is
 // needed.
+// The search runs in two passes so that the lanes of a wave stay together:
+// the first samples phi at the NS + 1 parameters and records, per sample
+// interval, the events that need a search (a sign change of phi, a local
+// minimum of phi above zero, a crossing of the disc plane through the origin)
+// as bit masks; the second searches the recorded events one after another.
+// A wave then runs one search per event of its busiest lane, not the union
+// of every lane's searches at every sample.
+template <int NS>
 __device__ __forceinline__ void leaf_candidates(const Curve64 &c, double ua, double ub, double tlo, double thi,
-                                                double tmax, double t0, double u0, int samples, double &t_best,
+                                                double tmax, double t0, double u0, double &t_best,
                                                 double &u_best)
 {
+    constexpr int kWords = (NS + 1 + 31) / 32;
     auto take = [&](double t, double u) {
         if (t >= tlo && t <= thi && t < tmax && t < t_best) { t_best = t; u_best = u; }
     };
@@ -441,59 +450,95 @@ __device__ __forceinline__ void leaf_candidates(const Curve64 &c, double ua, dou
         double t = t0, u = u0;
         if (newton_surface(c, t, u) && u >= ua && u <= ub) take(t, u);
     }
-    const double h = (ub - ua) / samples;
-    double pu = ua, pt = 0.0, pphi = 0.0, ppu = ua, ppphi = INFINITY;
-    bool pok = disc_point(c, pu, pt, pphi);
-    for (int k = 1; k <= samples; ++k) {
-        const double cu = k == samples ? ub : ua + h * k;
+    const double h = (ub - ua) / NS;
+    auto at = [&](int k) { return k == NS ? ub : ua + h * k; };
+    // sample k (0..NS): inside (phi <= 0) and t <= 0 flags; events on (k-1, k]
+    uint32_t in_m[kWords], tneg_m[kWords], sign_m[kWords], min_m[kWords], org_m[kWords];
+#pragma unroll
+    for (int q = 0; q < kWords; ++q) in_m[q] = tneg_m[q] = sign_m[q] = min_m[q] = org_m[q] = 0u;
+    double pt = 0.0, pphi = 0.0, ppphi = INFINITY;
+    bool pok = disc_point(c, ua, pt, pphi);
+    if (pok && pphi <= 0.0) in_m[0] |= 1u;
+    if (pok && pt <= 0.0) tneg_m[0] |= 1u;
+    for (int k = 1; k <= NS; ++k) {
         double ct = 0.0, cphi = 0.0;
-        const bool cok = disc_point(c, cu, ct, cphi);
+        const bool cok = disc_point(c, at(k), ct, cphi);
+        const uint32_t bit = 1u << (k & 31);
+        if (cok && cphi <= 0.0) in_m[k >> 5] |= bit;
+        if (cok && ct <= 0.0) tneg_m[k >> 5] |= bit;
         if (pok && cok) {
-            if ((pphi <= 0.0) != (cphi <= 0.0)) {
-                double t, u;
-                if (boundary_root(c, pu, cu, pphi <= 0.0, t, u)) take(t, u);
-            } else if (pphi > 0.0 && cphi > pphi && ppphi > pphi) {
-                // a local minimum of phi near pu: a dip below zero narrower
-                // than the sampling has two boundary points in (ppu, cu)
-                constexpr double g = 0.38196601125010515;         // golden-section step
-                double a = ppu, b = cu, tt;
-                double x1 = a + g * (b - a), x2 = b - g * (b - a), f1 = 0.0, f2 = 0.0;
-                bool ok = disc_point(c, x1, tt, f1) && disc_point(c, x2, tt, f2);
-                for (int it = 0; ok && it < 48 && f1 > 0.0 && f2 > 0.0; ++it) {
-                    if (f1 < f2) {
-                        b = x2; x2 = x1; f2 = f1; x1 = a + g * (b - a);
-                        ok = disc_point(c, x1, tt, f1);
-                    } else {
-                        a = x1; x1 = x2; f1 = f2; x2 = b - g * (b - a);
-                        ok = disc_point(c, x2, tt, f2);
-                    }
-                }
-                if (ok && fmin(f1, f2) <= 0.0) {
-                    const double um = f1 <= f2 ? x1 : x2;
-                    double t, u;
-                    if (boundary_root(c, ppu, um, false, t, u)) take(t, u);
-                    if (boundary_root(c, um, cu, true, t, u)) take(t, u);
+            if ((pphi <= 0.0) != (cphi <= 0.0)) sign_m[k >> 5] |= bit;
+            else if (pphi > 0.0 && cphi > pphi && ppphi > pphi) min_m[k >> 5] |= bit;
+            if ((pt <= 0.0) != (ct <= 0.0) && (pphi <= 0.0 || cphi <= 0.0) && tlo <= 0.0) org_m[k >> 5] |= bit;
+        }
+        ppphi = pok ? pphi : INFINITY;
+        pt = ct; pphi = cphi; pok = cok;
+    }
+    // masks are indexed with unrolled selects (no dynamic register indexing)
+    auto flag = [&](const uint32_t *m, int k) {
+        uint32_t w = 0u;
+#pragma unroll
+        for (int q = 0; q < kWords; ++q) w = q == (k >> 5) ? m[q] : w;
+        return ((w >> (k & 31)) & 1u) != 0u;
+    };
+    auto next_event = [&](uint32_t *m) {       // lowest recorded event, removed from the mask
+        int k = -1;
+#pragma unroll
+        for (int q = kWords - 1; q >= 0; --q)
+            if (m[q]) k = 32 * q + __builtin_ctz(m[q]);
+#pragma unroll
+        for (int q = 0; q < kWords; ++q)
+            if (k >= 0 && q == (k >> 5)) m[q] &= m[q] - 1u;
+        return k;
+    };
+    // sign changes: one boundary point between the samples
+    for (int k; (k = next_event(sign_m)) >= 0;) {
+        {
+            double t, u;
+            if (boundary_root(c, at(k - 1), at(k), flag(in_m, k - 1), t, u)) take(t, u);
+        }
+    }
+    // a local minimum of phi above zero at sample k-1: a dip below zero
+    // narrower than the sampling has two boundary points in (u[k-2], u[k])
+    for (int k; (k = next_event(min_m)) >= 0;) {
+        {
+            constexpr double g = 0.38196601125010515;         // golden-section step
+            double a = at(k >= 2 ? k - 2 : 0), b = at(k), tt;
+            double x1 = a + g * (b - a), x2 = b - g * (b - a), f1 = 0.0, f2 = 0.0;
+            bool ok = disc_point(c, x1, tt, f1) && disc_point(c, x2, tt, f2);
+            for (int it = 0; ok && it < 48 && f1 > 0.0 && f2 > 0.0; ++it) {
+                if (f1 < f2) {
+                    b = x2; x2 = x1; f2 = f1; x1 = a + g * (b - a);
+                    ok = disc_point(c, x1, tt, f1);
+                } else {
+                    a = x1; x1 = x2; f1 = f2; x2 = b - g * (b - a);
+                    ok = disc_point(c, x2, tt, f2);
                 }
             }
-            if ((pt <= 0.0) != (ct <= 0.0) && (pphi <= 0.0 || cphi <= 0.0) && tlo <= 0.0) {
-                // the disc plane sweeps through the origin: is the origin in that disc?
-                double lo = pu, hi = cu;
-                const bool lo_neg = pt <= 0.0;
-                for (int it = 0; it < 64; ++it) {
-                    const double mid = 0.5 * (lo + hi);
-                    double mt, mphi;
-                    if (!disc_point(c, mid, mt, mphi)) break;
-                    if ((mt <= 0.0) == lo_neg) lo = mid; else hi = mid;
-                }
-                const double uz = 0.5 * (lo + hi);
-                double C[4], D[4], E[3];
-                eval_curve(c, uz, C, D, E);
-                if (C[0] * C[0] + C[1] * C[1] + C[2] * C[2] <= C[3] * C[3]) take(0.0, uz);
+            if (ok && fmin(f1, f2) <= 0.0) {
+                const double um = f1 <= f2 ? x1 : x2;
+                double t, u;
+                if (boundary_root(c, at(k >= 2 ? k - 2 : 0), um, false, t, u)) take(t, u);
+                if (boundary_root(c, um, at(k), true, t, u)) take(t, u);
             }
         }
-        ppu = pu;
-        ppphi = pok ? pphi : INFINITY;
-        pu = cu; pt = ct; pphi = cphi; pok = cok;
+    }
+    // the disc plane sweeps through the origin: is the origin in that disc?
+    for (int k; (k = next_event(org_m)) >= 0;) {
+        {
+            double lo = at(k - 1), hi = at(k);
+            const bool lo_neg = flag(tneg_m, k - 1);
+            for (int it = 0; it < 64; ++it) {
+                const double mid = 0.5 * (lo + hi);
+                double mt, mphi;
+                if (!disc_point(c, mid, mt, mphi)) break;
+                if ((mt <= 0.0) == lo_neg) lo = mid; else hi = mid;
+            }
+            const double uz = 0.5 * (lo + hi);
+            double C[4], D[4], E[3];
+            eval_curve(c, uz, C, D, E);
+            if (C[0] * C[0] + C[1] * C[1] + C[2] * C[2] <= C[3] * C[3]) take(0.0, uz);
+        }
     }
     // end discs
 #pragma unroll
@@ -712,8 +757,8 @@ __device__ __noinline__ bool refine_at_leaf(Lane &L, const Table &tab, const Arg
     const double t0 = tin, t1 = tout < INFINITY ? (double)tout : (double)L.tmax;
     const double pad = ((t1 - t0) + fmax(fabs(t0), fabs(t1))) * 0x1p-20;
     double t = INFINITY, u = __builtin_nan("");
-    leaf_candidates(cv, ua, ub, fmax(0.0, t0 - pad), t1 + pad, (double)L.tmax, (double)L.t, (double)L.ru,
-                    kLeafSamples, t, u);
+    leaf_candidates<kLeafSamples>(cv, ua, ub, fmax(0.0, t0 - pad), t1 + pad, (double)L.tmax, (double)L.t,
+                                  (double)L.ru, t, u);
     if (!(t < INFINITY)) return false;
     L.t64 = t;
     L.u64 = u;
@@ -733,8 +778,8 @@ __device__ __noinline__ bool refine_whole_curve(Lane &L, const Table &tab, const
     Curve64 cv;
     if (!curve_in_ray_frame(in.rays + ri, in.ray_stride, in.fibers + fi, in.fiber_stride, cv)) return false;
     double t = INFINITY, u = __builtin_nan("");
-    leaf_candidates(cv, 0.0, 1.0, 0.0, (double)L.tmax, (double)L.tmax, (double)L.t, (double)L.ru,
-                    kCurveSamples, t, u);
+    leaf_candidates<kCurveSamples>(cv, 0.0, 1.0, 0.0, (double)L.tmax, (double)L.tmax, (double)L.t,
+                                   (double)L.ru, t, u);
     if (!(t < INFINITY)) return false;
     L.t64 = t;
     L.u64 = u;
@@ -1027,7 +1072,7 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(Args a0, const Args *scen
 // per SIMD, the most gfx950 runs) hold the plain traversal without spills;
 // the counting and conservative variants get 80 (six waves).
 template <int MODE, bool BATCHED>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MODE == kPlain ? FIBERHIT_TRAVERSE_WAVES : 6, 8)))
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MODE == kPlain ? FIBERHIT_TRAVERSE_WAVES : MODE == kCount ? 6 : 4, 8)))
 void k_traverse(Args a0, const Args *scenes, Table tab, const uint32_t *counts, int n_buckets, int refill)
 {
     __shared__ float s_cache[(kParentCache ? 16 : 1) * kWave];
