@@ -288,7 +288,14 @@ struct Args {
 
 constexpr int kRefineAbove = 16;         // refine pairs of depth > 16
 constexpr int kLeafSamples = 16;         // phi samples over a leaf's u window (three leaves)
-constexpr int kRefineFails = 4;          // leaves without the solid before the whole-curve search
+#ifndef FIBERHIT_NEWTON_TOL
+#define FIBERHIT_NEWTON_TOL 1e-9
+#endif
+constexpr double kNewtonTol = FIBERHIT_NEWTON_TOL;   // relative residuals of an accepted boundary point
+#ifndef FIBERHIT_REFINE_FAILS
+#define FIBERHIT_REFINE_FAILS 1
+#endif
+constexpr int kRefineFails = FIBERHIT_REFINE_FAILS;   // leaves without the solid before the whole-curve search
 constexpr int kCurveSamples = 128;       // phi samples over the whole curve (local minima are searched)
 constexpr int kRefineBatch = 16;         // parked lanes that trigger a wave's FP64 leaf checks
 
@@ -392,11 +399,16 @@ __device__ __forceinline__ bool newton_surface(const Curve64 &c, double &t, doub
     const double f1 = h * D[2] - C[0] * D[0] - C[1] * D[1];
     const double f2 = C[0] * C[0] + C[1] * C[1] + h * h - C[3] * C[3];
     const double dn = sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
-    return has_disc(c, D) && fabs(f2) <= 1e-9 * scale && fabs(f1) <= 1e-9 * C[3] * dn;
+    // the residual floor is set by cancellation in C (control points far
+    // from the ray), so the test is loose; near a tangent ray a point that
+    // passes it can still lie measurably off the surface (see bracket_polish)
+    return has_disc(c, D) && fabs(f2) <= kNewtonTol * scale && fabs(f1) <= kNewtonTol * C[3] * dn;
 }
 
 // Bisect a sign change of phi on [lo, hi] (lo_in: phi(lo) <= 0), then polish
-// the root by Newton's method; returns the boundary point in (t, u).
+// the root by Newton's method, kept only if it stays within a few final
+// brackets (a polish that wanders further follows the residual's rounding,
+// not the root); returns the boundary point in (t, u).
 __device__ __forceinline__ bool boundary_root(const Curve64 &c, double lo, double hi, bool lo_in, double &t,
                                               double &u)
 {
@@ -416,11 +428,34 @@ __device__ __forceinline__ bool boundary_root(const Curve64 &c, double lo, doubl
         if (!has_disc(c, D)) return false;
     }
     double tn = t, un = u;
-    if (newton_surface(c, tn, un) && fabs(un - u) <= 4.0 * (hi - lo) + 1e-12) {
+    if (newton_surface(c, tn, un) && fabs(un - u) <= 4.0 * (hi - lo) + 0x1p-50) {
         t = tn;
         u = un;
     }
     return true;
+}
+
+// A Newton point re-derived from a sign change of phi around it. Near a
+// tangent ray the boundary point is ill-conditioned: a residual small enough
+// to pass Newton's test still moves t by far more than rounding (a residual
+// e * r^2 moves t by about e * r / sqrt(2 * penetration / r)). Brackets of
+// growing width around u are tried; the first with a sign change is
+// bisected. Without one the point is kept.
+__device__ __forceinline__ void bracket_polish(const Curve64 &c, double &t, double &u)
+{
+    double w = 0x1p-32;
+    for (int it = 0; it < 8; ++it, w *= 8.0) {
+        double ta, pa, tb, pb;
+        if (!disc_point(c, u - w, ta, pa) || !disc_point(c, u + w, tb, pb)) return;
+        if ((pa <= 0.0) != (pb <= 0.0)) {
+            double tt, uu;
+            if (boundary_root(c, u - w, u + w, pa <= 0.0, tt, uu)) {
+                t = tt;
+                u = uu;
+            }
+            return;
+        }
+    }
 }
 
 // Boundary points of the swept solid along the ray with u in [ua, ub]; the
@@ -448,7 +483,10 @@ __device__ __forceinline__ void leaf_candidates(const Curve64 &c, double ua, dou
     };
     {
         double t = t0, u = u0;
-        if (newton_surface(c, t, u) && u >= ua && u <= ub) take(t, u);
+        if (newton_surface(c, t, u)) {
+            bracket_polish(c, t, u);
+            if (u >= ua && u <= ub) take(t, u);
+        }
     }
     const double h = (ub - ua) / NS;
     auto at = [&](int k) { return k == NS ? ub : ua + h * k; };

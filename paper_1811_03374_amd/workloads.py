@@ -339,11 +339,12 @@ def hair_strands(n_strands: int = 100_000, seed: int = SEED_BASE + 3, offset: fl
 
 def hair_precision(n_rays: int = 1 << 24, n_strands: int = 100_000, depth: int = 9,
                    seed: int = SEED_BASE + 3, grazing_fraction: float = 0.1,
-                   rho: float = 0.25, chunk: int = 1 << 21) -> Workload:
+                   rho: float = 0.25, chunk: int = 1 << 21, graze_width: float = 1e-3) -> Workload:
     """Rays aimed at uniformly chosen hair segments and parameters u0, from
     C(u0) + rho * s (s uniform on the sphere, rho = 0.25): 90 % regular rays
     displaced sideways by N(0, (1.4826 r)^2), 10 % grazing rays displaced by
-    (1 + delta) r with delta ~ U[-1e-3, 1e-3], both along the direction
+    (1 + delta) r with delta ~ U[-w, w] (w = graze_width, 1e-3 by default),
+    both along the direction
     normal to the view vector and the tangent. The origin is rounded to
     float32 first, then D = target - O is formed in float64 and rounded.
     Pairs are (ray i, its target segment) through pair_fiber."""
@@ -370,7 +371,7 @@ def hair_precision(n_rays: int = 1 << 24, n_strands: int = 100_000, depth: int =
         g = rng.uniform(0, 1, m) < grazing_fraction
         off = rng.standard_normal(m) * 1.4826
         sign = np.where(rng.uniform(0, 1, m) < 0.5, -1.0, 1.0)
-        off = np.where(g, sign * (1.0 + rng.uniform(-1e-3, 1e-3, m)), off) * C[:, 3]
+        off = np.where(g, sign * (1.0 + rng.uniform(-graze_width, graze_width, m)), off) * C[:, 3]
         target = C[:, :3] + off[:, None] * side
         D = target - O32
         rays[0:3, a:b] = O32.T

@@ -92,6 +92,30 @@ def test_refine_straight_and_curved(depth):
     assert st["max_rel_t"] <= T_REL_TOL64, st
 
 
+def test_refine_near_tangent_rays():
+    # every ray within 1e-6 r of the silhouette: the entry point is ill-
+    # conditioned (a residual that passes Newton's test can still move t far
+    # beyond rounding), so a refined t must come from a bracketed root. All
+    # pairs lie in the flag band; t is checked wherever both sides hit.
+    # Bound: FP64 evaluation of C(u) rounds at eps times the control points'
+    # spread across the ray (about 0.1 here, against r ~ 5e-5), and at a
+    # penetration of delta * r the entry moves by that error over
+    # |dphi/du| ~ r sqrt(delta); down to delta ~ 1e-8 this keeps t within
+    # about 1e-12 relative. The tail is asserted at 1e-11 (a Newton point
+    # accepted on its residual alone was off by up to 5e-10), the bulk at
+    # 1e-12. The exact oracle bisects in extended precision.
+    w = W.hair_precision(1 << 14, 2000, depth=22, grazing_fraction=1.0, graze_width=1e-6)
+    t32, u32, h, t64, u64 = run_refined(w, 22)
+    t_x, u_x, h_x, kind = oracle.intersect_exact(w.rays, w.fibers, w.pair_ray, w.pair_fiber)
+    both = h.astype(bool) & h_x.astype(bool)
+    rel = np.abs(t64[both] - t_x[both]) / t_x[both]
+    say(f"[refine] near-tangent n={w.n_pairs} gpu hits={int(h.sum())} exact hits={int(h_x.sum())} "
+        f"both={int(both.sum())} max_rel_t={rel.max():.3e} p99.9={np.quantile(rel, 0.999):.3e}")
+    assert both.sum() > 1000
+    assert np.quantile(rel, 0.999) <= T_REL_TOL64
+    assert rel.max() <= 10 * T_REL_TOL64
+
+
 def test_refine_hair_precision_stress():
     w = W.hair_precision(1 << 16, 20000, depth=22)
     st = check_refined(w, 22, "hair (10% grazing within 1e-3 r)")
