@@ -321,7 +321,7 @@ def main():
         }
         roof[d] = {"bound": "alu", "achieved": tflops, "peak": workmodel.PEAK_FP32_TFLOPS,
                    "unit": "TFLOP/s", "frac": tflops / workmodel.PEAK_FP32_TFLOPS,
-                   "traffic": measured_traffic(d), "kernel": "k_setup + k_traverse (one call)", "depth": d,
+                   "traffic": measured_traffic(d), "kernel": "k_fused (one call)", "depth": d,
                    "algorithmic_bytes": work[d]["bytes"]}
     dominant = max(DEPTHS, key=lambda d: statistics.mean(launch_ms[d]))
 
@@ -350,8 +350,9 @@ def main():
         "config": {"workload": "straight_and_curved 2^20 pairs (half straight constant-radius, "
                                "half curved random-walk, ~50% hits)",
                    "pairs": n, "depths": list(DEPTHS), "pairing": "identity",
-                   "launch": "per call: k_setup (one lane per pair, FP64 frame, root test) then "
-                             "k_traverse (64-lane waves draining a survivor table with lane refill)"},
+                   "launch": "per call: k_fused (persistent 64-lane waves, each draining an even share of "
+                             "the pairs: FP64 frame and root test in the lane refill, then the FP32 "
+                             "subdivision search)"},
         "per_depth": per_depth,
         "roofline": roof[dominant],
         "cpu_baseline": cpu,

@@ -16,18 +16,23 @@
  * the legacy default stream); results are valid once the stream has
  * synchronised.
  *
- * Each call runs as two kernels per chunk of pairs: a setup kernel (one lane
- * per pair: load, FP64 move into the ray frame, root test; pairs decided at
- * the root are written out) and a persistent traversal kernel over the
- * survivors, which it reads from a survivor table (85 bytes per row).
- * fiber_intersect_pairs and fiber_intersect_counts use chunks of 2^20 pairs
- * and own two such tables per device (2 x 85 MiB), allocated at their first
- * call on that device and kept for the process; calls that share a table are
+ * A single call without FI_FP64_REFINE (fiber_intersect_pairs,
+ * fiber_intersect_counts; fewer than 2^31 pairs) runs one persistent kernel:
+ * each wave takes an even share of the pairs and loads them into its free
+ * lanes (load, FP64 move into the ray frame, root test; pairs decided at the
+ * root are written out at once), keeping each busy lane's root in a slot of
+ * its own (64 bytes). Other calls run two kernels per chunk of pairs: a setup
+ * kernel (one lane per pair, the same steps) and a persistent traversal kernel
+ * over the survivors, which it reads from a survivor table (85 bytes per
+ * row); single calls use chunks of 2^20 pairs. The library owns two sets of
+ * these buffers per device (each: a 2^20-row table, 85 MiB, and the root
+ * slots, 4 KiB per resident wave, about 24 MiB), allocated at the first call
+ * on that device and kept for the process; calls that share a set are
  * ordered on the GPU through an event, so calls on different streams stay
  * correct. When a single call gathers fibers through pair_fiber with at least
  * as many pairs as fibers, the fibers are first copied to 64-byte records (one
  * gathered fiber is then one or two cache lines instead of sixteen), in a
- * per-table buffer that grows to the largest such call (up to 1 GiB; beyond
+ * per-set buffer that grows to the largest such call (up to 1 GiB; beyond
  * that the gather reads the rows directly). Batched calls use chunks of 2^22
  * pairs in a table from the caller's workspace or the plan, and allocate
  * nothing on the call path.
@@ -124,7 +129,7 @@ const char *fi_strerror(int status);
  * counts, strides below the counts, a depth outside [0, 23], unknown flags,
  * an identity pairing longer than a table, or n_pairs >= 2^31 - 64;
  * FI_ERR_HIP when the launch fails or the first call on a device cannot
- * allocate its survivor table. Nothing is enqueued on an argument error.
+ * allocate its buffers. Nothing is enqueued on an argument error.
  */
 int fiber_intersect_pairs(const float *rays, int64_t ray_stride, int64_t n_rays,
                           const float *fibers, int64_t fiber_stride, int64_t n_fibers,

@@ -47,6 +47,18 @@ constexpr float kParallelG = 1e-30f;          // axis treated as parallel to the
 #define FIBERHIT_PARENT_CACHE 1
 #endif
 constexpr bool kParentCache = FIBERHIT_PARENT_CACHE != 0;   // cache the latest both-hit parent in LDS
+#ifndef FIBERHIT_FUSED
+#define FIBERHIT_FUSED 1                           // single calls: one kernel, no survivor table
+#endif
+#ifndef FIBERHIT_FUSED_ROUNDS
+#define FIBERHIT_FUSED_ROUNDS 1                    // refill batches per trip of the one-kernel path
+#endif
+#ifndef FIBERHIT_FUSED_REFILL
+#define FIBERHIT_FUSED_REFILL 48                   // free lanes that trigger a one-kernel refill
+#endif
+#ifndef FIBERHIT_FUSED_WAVES
+#define FIBERHIT_FUSED_WAVES 6                     // register budget of the one-kernel path (waves per SIMD)
+#endif
 #ifndef FIBERHIT_TRAVERSE_WAVES
 #define FIBERHIT_TRAVERSE_WAVES 8                  // traversal waves per SIMD the register budget must allow
 #endif
@@ -832,8 +844,26 @@ __device__ __noinline__ bool refine_whole_curve(Lane &L, const Table &tab, const
 // with the rebuilt sibling. The new node thus has a single definition point,
 // which spares the copies of the whole lane state that a merge of separately
 // computed nodes costs, and a backtracking lane only adds the rebuild.
-template <int MODE>
-__device__ __forceinline__ int trip(Lane &L, const Table &tab, float *col, const Args &in)
+// Where a backtrack that misses the parent cache re-reads its pair's root:
+// the survivor table (two-kernel path) or the lane's own slot (one-kernel
+// path).
+struct TableRoot {
+    Table tab;
+    __device__ __forceinline__ void get(const Lane &L, Node &n) const { table_root(tab, L.row, n); }
+};
+
+struct SlotRoot {
+    const float *slot;                        // this lane's root: 16 floats, one wave apart
+    __device__ __forceinline__ void get(const Lane &, Node &n) const
+    {
+        float *f = &n.p.x;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) f[k] = slot[k * kWave];
+    }
+};
+
+template <int MODE, class Root>
+__device__ __forceinline__ int trip(Lane &L, const Root &root, float *col)
 {
     float te, tx, lo, hi;
     bool vis = node_visible<MODE>(L.c, L.lo, L.hi, L.slack, te, tx, lo, hi);
@@ -882,7 +912,7 @@ __device__ __forceinline__ int trip(Lane &L, const Table &tab, float *col, const
             // keep the root's global loads inside this branch: hoisted above it
             // they would delay every cached rebuild by a memory round trip
             asm volatile("" ::: "memory");
-            table_root(tab, L.row, L.c);
+            root.get(L, L.c);
             for (uint32_t b = kRootSize >> 1; b > L.size; b >>= 1) {
                 V4 rdp, rtc;
                 split_terms(L.c, rdp, rtc);
@@ -1167,7 +1197,7 @@ void k_traverse(Args a0, const Args *scenes, Table tab, const uint32_t *counts, 
         // the first check, never taking the backtrack or descent paths; the
         // compiler then keeps one copy of the lane state instead of merging
         // active and idle ones
-        const int st = trip<MODE>(L, tab, col, a0);
+        const int st = trip<MODE>(L, TableRoot{tab}, col);
         if (active && st != kGoOn && !(MODE == kConservative && L.waiting)) {
             const int64_t i = L.pair;
             if constexpr (BATCHED) {
@@ -1195,6 +1225,148 @@ void k_traverse(Args a0, const Args *scenes, Table tab, const uint32_t *counts, 
                     }
                 }
             }
+        }
+        if (!active) {
+            L.lo = INFINITY;
+            L.hi = -INFINITY;
+            L.bits = 0;
+        }
+    }
+}
+
+// load_pair with the frame projection ordered for few live registers (one
+// control point at a time; the one-kernel path runs it while the busy lanes'
+// state stays live). Same arithmetic as root_in_ray_frame, same results.
+__device__ __forceinline__ bool load_pair_lean(const Args &a, int64_t i, Node &root, float &tmax, uint32_t &depth,
+                                               const float *aos)
+{
+    const int64_t ri = a.pair_ray ? (int64_t)a.pair_ray[i] : i;
+    const int64_t fi = a.pair_fiber ? (int64_t)a.pair_fiber[i] : i;
+    depth = a.pair_depth ? (uint32_t)a.pair_depth[i] : (uint32_t)a.depth;
+    if (ri < 0 || ri >= a.n_rays || fi < 0 || fi >= a.n_fibers || depth > FI_MAX_DEPTH) return false;
+    const float *R = a.rays + ri;
+    const int64_t rs = a.ray_stride;
+    tmax = R[6 * rs];
+    if (!(tmax == tmax)) return false;
+    const float *F = aos ? aos + 16 * fi : a.fibers + fi;
+    const int64_t fs = aos ? 1 : a.fiber_stride;
+    const double dx = R[3 * rs], dy = R[4 * rs], dz = R[5 * rs];
+    const double n2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    if (!(n2 > 0.0) || !(n2 < INFINITY)) return false;
+    const double il = rsqrt64(n2);
+    const double w[3] = {dx * il, dy * il, dz * il};
+    double u[3], v[3];
+    make_onb(w[0], w[1], w[2], u, v);
+    auto proj = [&](double ex, double ey, double ez, double ew, V4 &q) {
+        q.x = (float)fma(ex, u[0], fma(ey, u[1], ez * u[2]));
+        q.y = (float)fma(ex, v[0], fma(ey, v[1], ez * v[2]));
+        q.z = (float)fma(ex, w[0], fma(ey, w[1], ez * w[2]));
+        q.w = (float)ew;
+    };
+    const float p0x = F[0], p0y = F[fs], p0z = F[2 * fs], p0w = F[3 * fs];
+    proj((double)p0x - (double)R[0], (double)p0y - (double)R[rs], (double)p0z - (double)R[2 * rs], (double)p0w,
+         root.p);
+    const float p3x = F[12 * fs], p3y = F[13 * fs], p3z = F[14 * fs], p3w = F[15 * fs];
+    proj((double)p3x - p0x, (double)p3y - p0y, (double)p3z - p0z, (double)p3w - p0w, root.d);
+    proj((double)F[4 * fs] - p0x, (double)F[5 * fs] - p0y, (double)F[6 * fs] - p0z, (double)F[7 * fs] - p0w,
+         root.t0);
+    proj((double)p3x - F[8 * fs], (double)p3y - F[9 * fs], (double)p3z - F[10 * fs], (double)p3w - F[11 * fs],
+         root.t1);
+    return isfinite(root.p.x) && isfinite(root.p.y) && isfinite(root.p.z) &&
+           isfinite(root.d.x) && isfinite(root.d.y) && isfinite(root.d.z);
+}
+
+// One-kernel path for single calls (plain and counting variants): each
+// persistent wave takes an even share of the call's pairs and loads them
+// straight into its free lanes -- pair fetch, FP64 frame and root test in the
+// refill, as the setup kernel does -- so no survivor table is written or read.
+// A lane that survives its root test keeps the root in its own slot (16
+// floats, a wave's lanes side by side) for the backtracks that miss the
+// parent cache; pairs decided at the root are written out during the refill,
+// which takes up to kFusedRounds batches of pairs per trip so that lanes freed
+// by root misses are refilled at once.
+constexpr int kFusedRounds = FIBERHIT_FUSED_ROUNDS;
+
+template <int MODE>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MODE == kPlain ? FIBERHIT_FUSED_WAVES : 5, 8)))
+void k_fused(Args a, int64_t count, float *slots, int refill, const float *aos)
+{
+    __shared__ float s_cache[16 * kWave];
+    const int lane = (int)threadIdx.x;
+    float *col = s_cache + lane;
+    const int64_t w = blockIdx.x, waves = gridDim.x;
+    const int64_t share = (count + waves - 1) / waves;
+    int64_t next = w * share < count ? w * share : count;               // wave-uniform range
+    const int64_t end = (w + 1) * share < count ? (w + 1) * share : count;
+    float *slot = slots + (size_t)w * 16 * kWave + lane;
+    const SlotRoot root{slot};
+    Lane L = {};
+    L.lo = INFINITY;                                                   // parked, as in k_traverse
+    L.hi = -INFINITY;
+    bool active = false;
+    for (;;) {
+        for (int round = 0; round < kFusedRounds; ++round) {
+            const uint64_t free_mask = __ballot(!active);
+            const int n_free = __popcll(free_mask);
+            if (next >= end || !(n_free >= refill || n_free == kWave)) break;
+            const int take = end - next < n_free ? (int)(end - next) : n_free;
+            if (!active) {
+                const int rank = (int)lanes_below(free_mask);
+                if (rank < take) {
+                    // the new pair goes straight into the (free) lane's state
+                    const int64_t idx = next + rank;
+                    uint32_t depth = 0;
+                    if (!load_pair_lean(a, idx, L.c, L.tmax, depth, aos)) {
+                        finish_invalid<MODE>(a, idx);
+                        L.lo = INFINITY;
+                        L.hi = -INFINITY;
+                        L.bits = 0;
+                    } else {
+                        cap_interval(L.c, L.tmax, L.lo, L.hi);
+                        float te, tx, lu, hu;
+                        const float slack = MODE == kConservative && depth > kRefineAbove ? root_slack(L.c) : -1.0f;
+                        const bool vis = node_visible<MODE>(L.c, L.lo, L.hi, slack, te, tx, lu, hu);
+                        L.slack = slack;
+                        L.start = 0;
+                        L.size = kRootSize;
+                        if (vis && depth > 0) {
+                            const float *f = &L.c.p.x;
+#pragma unroll
+                            for (int k = 0; k < 16; ++k) slot[k * kWave] = f[k];
+                            L.min_size = kRootSize >> depth;
+                            L.pair = (int32_t)idx;
+                            L.bits = 0;
+                            L.cached = 0;
+                            L.fails = 0;
+                            L.waiting = 0;
+                            L.trips = L.splits = L.backtracks = 0;
+                            active = true;
+                        } else {
+                            // decided at the root: a miss, or the root is the leaf
+                            L.t = fmaxf(te, lu);
+                            L.u = leaf_u(L);
+                            L.level = 0;
+                            L.trips = 1;
+                            L.splits = 0;
+                            L.backtracks = 0;
+                            finish<MODE>(outs_of(a), idx, L, vis);
+                            L.lo = INFINITY;
+                            L.hi = -INFINITY;
+                            L.bits = 0;
+                        }
+                    }
+                }
+            }
+            next += take;
+        }
+        if (__ballot(active) == 0) {
+            if (next >= end) break;
+            continue;
+        }
+        const int st = trip<MODE>(L, root, col);
+        if (active && st != kGoOn) {
+            finish<MODE>(outs_of(a), L.pair, L, st == kHit);
+            active = false;
         }
         if (!active) {
             L.lo = INFINITY;
@@ -1257,6 +1429,9 @@ const SetupFn kSetup[3][2] = {
     {k_setup<kCount, false>, k_setup<kPlain, true>},
     {k_setup<kConservative, false>, k_setup<kPlain, true>},
 };
+using FusedFn = void (*)(Args, int64_t, float *, int, const float *);
+const FusedFn kFused[2] = {k_fused<kPlain>, k_fused<kCount>};
+
 const TraverseFn kTraverse[3][2] = {
     {k_traverse<kPlain, false>, k_traverse<kPlain, true>},
     {k_traverse<kCount, false>, k_traverse<kPlain, true>},
@@ -1321,6 +1496,7 @@ constexpr size_t kStageBytes = 1u << 20;
 struct Region {
     std::mutex m;
     void *mem;                                 // survivor table of kChunkRows rows
+    float *slots;                              // root slots of the one-kernel path (resident waves x 4 KB)
     float *aos;                                // fibers as 16-float records (gathered calls)
     size_t aos_bytes;
     uint32_t *counters;                        // two sets of kBuckets counters
@@ -1333,6 +1509,7 @@ struct DeviceInfo {
     std::atomic<bool> ready;
     int cus;
     int resident[3][2];                        // resident traversal waves per CU, per variant
+    int fused_resident[2];                     // resident one-kernel waves per CU (plain, counting)
     Region region[kRegions];
     std::atomic<uint32_t> next_region;
     std::mutex stage_mutex;
@@ -1369,10 +1546,17 @@ int device_info(DeviceInfo *&out)
                         return FI_ERR_HIP;
                     d.resident[m][b] = nb > 0 ? nb : 1;
                 }
+            for (int m = 0; m < 2; ++m) {
+                int nb = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)kFused[m], kWave, 0) != hipSuccess)
+                    return FI_ERR_HIP;
+                d.fused_resident[m] = nb > 0 ? nb : 1;
+            }
             for (int r = 0; r < kRegions; ++r) {
                 d.region[r].mem = nullptr;
                 d.region[r].aos = nullptr;
                 d.region[r].aos_bytes = 0;
+                d.region[r].slots = nullptr;
                 d.region[r].counters = (uint32_t *)p + r * kCounterWords;
                 d.region[r].parity = 0;
                 d.region[r].done = nullptr;
@@ -1522,12 +1706,31 @@ int launch(int mode, const Args &a, void *stream)
             }
             aos = R.aos;
         }
+        const bool fused = FIBERHIT_FUSED && mode != kConservative && a.n_pairs < ((int64_t)1 << 31);
+        const int64_t fused_waves = (int64_t)d->fused_resident[fused ? mode : 0] * d->cus;
+        if (fused && !R.slots) {
+            // sized for the larger grid of the two variants
+            const int most = d->fused_resident[0] > d->fused_resident[1] ? d->fused_resident[0] : d->fused_resident[1];
+            if (hipMalloc(&R.slots, (size_t)most * d->cus * 16 * kWave * sizeof(float)) != hipSuccess) {
+                R.slots = nullptr;
+                (void)hipGetLastError();
+                return FI_ERR_HIP;
+            }
+        }
         if (R.pending && hipStreamWaitEvent(s, R.done, 0) != hipSuccess) return FI_ERR_HIP;
         if (aos)
             hipLaunchKernelGGL(k_fibers_aos, dim3((unsigned)((a.n_fibers + 255) / 256)), dim3(256), 0, s,
                                a.fibers, a.fiber_stride, a.n_fibers, (float4 *)R.aos);
-        R.parity = launch_chain(*d, mode, false, default_tuning(), a, nullptr, nullptr, 1, a.n_pairs,
-                                table_at(R.mem, kChunkRows), R.counters, R.parity, s, aos);
+        if (fused) {
+            int64_t g = (a.n_pairs + kWave - 1) / kWave;
+            if (g > fused_waves) g = fused_waves;
+            if (g > 0)
+                hipLaunchKernelGGL(kFused[mode], dim3((unsigned)g), dim3(kWave), 0, s, a, a.n_pairs, R.slots,
+                                   FIBERHIT_FUSED_REFILL, aos);
+        } else {
+            R.parity = launch_chain(*d, mode, false, default_tuning(), a, nullptr, nullptr, 1, a.n_pairs,
+                                    table_at(R.mem, kChunkRows), R.counters, R.parity, s, aos);
+        }
         if (hipEventRecord(R.done, s) != hipSuccess) return FI_ERR_HIP;
         R.pending = true;
     }

@@ -14,8 +14,8 @@ Usage (on the results of the commands named in the summary it writes):
   ``--pmc WRITE_SIZE`` runs of ``bench.py --traffic-probe``, which copies
   256 MiB with a plain device copy and then makes one call per depth. The
   copy calibrates the counters (bytes the counter reports for a copy of known
-  size); every call's setup and traversal dispatches are summed and scaled by
-  that factor. The result is written to ``traffic.json`` together with the
+  size); every call's dispatches (k_fused, or k_setup and k_traverse) are
+  summed and scaled by that factor. The result is written to ``traffic.json`` together with the
   hash of the kernel source it was measured on, which ``bench.py`` checks
   before it reports the figure.
 """
@@ -67,12 +67,18 @@ def read_counter(path, counter):
     return [(k, v[0], v[1]) for k, v in sorted(per.items())]
 
 
+CALL_KERNELS = ("k_fused", "k_setup", "k_traverse")
+
+
 def per_call(dispatches, factor):
-    """Bytes per call: the setup and traversal dispatches after the copy, in
-    call order (one call per depth)."""
+    """Bytes per call, in call order (one call per depth): a call is one
+    k_fused dispatch, or a k_setup dispatch and the k_traverse after it."""
     calls, cur = [], None
     for _, name, kib in dispatches:
-        if name.startswith("k_setup"):
+        if name.startswith("k_fused"):
+            cur = {"k_fused": kib * 1024 * factor}
+            calls.append(cur)
+        elif name.startswith("k_setup"):
             cur = {"k_setup": kib * 1024 * factor}
             calls.append(cur)
         elif name.startswith("k_traverse") and cur is not None:
@@ -120,9 +126,10 @@ def main(argv=None):
         for d, f, w in zip(DEPTHS, fc, wc):
             total = sum(f.values()) + sum(w.values())
             traffic["bytes_per_launch"][str(d)] = total
+            names = [k for k in CALL_KERNELS if k in f or k in w]
             traffic["per_kernel"][str(d)] = {k: {"fetch": f.get(k, 0.0), "write": w.get(k, 0.0)}
-                                            for k in ("k_setup", "k_traverse")}
-            for k in ("k_setup", "k_traverse"):
+                                            for k in names}
+            for k in names:
                 lines.append(f"| {d} | {k} | {f.get(k, 0.0) / 1e6:.1f} | {w.get(k, 0.0) / 1e6:.1f} |")
             lines.append(f"| {d} | total | {sum(f.values()) / 1e6:.1f} | {sum(w.values()) / 1e6:.1f} |")
         with open(os.path.join(a.out, "traffic.json"), "w") as fh:
