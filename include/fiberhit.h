@@ -17,15 +17,16 @@
  * synchronised.
  *
  * A single call without FI_FP64_REFINE (fiber_intersect_pairs,
- * fiber_intersect_counts; fewer than 2^31 pairs) runs one persistent kernel:
+ * fiber_intersect_counts; fewer than 2^31 pairs) and a batched call run one
+ * persistent kernel:
  * each wave takes an even share of the pairs and loads them into its free
  * lanes (load, FP64 move into the ray frame, root test; pairs decided at the
  * root are written out at once), keeping each busy lane's root in a slot of
- * its own (64 bytes). Other calls run two kernels per chunk of pairs: a setup
- * kernel (one lane per pair, the same steps) and a persistent traversal kernel
- * over the survivors, which it reads from a survivor table (85 bytes per
- * row); single calls use chunks of 2^20 pairs. The library owns two sets of
- * these buffers per device (each: a 2^20-row table, 85 MiB, and the root
+ * its own (64 bytes). A refined call runs two kernels per chunk of 2^20
+ * pairs: a setup kernel (one lane per pair, the same steps) and a persistent
+ * traversal kernel over the survivors, which it reads from a survivor table
+ * (81 bytes per row). For single calls the library owns two sets of
+ * these buffers per device (each: a 2^20-row table, 81 MiB, and the root
  * slots, 4 KiB per resident wave, about 24 MiB), allocated at the first call
  * on that device and kept for the process; calls that share a set are
  * ordered on the GPU through an event, so calls on different streams stay
@@ -33,9 +34,9 @@
  * as many pairs as fibers, the fibers are first copied to 64-byte records (one
  * gathered fiber is then one or two cache lines instead of sixteen), in a
  * per-set buffer that grows to the largest such call (up to 1 GiB; beyond
- * that the gather reads the rows directly). Batched calls use chunks of 2^22
- * pairs in a table from the caller's workspace or the plan, and allocate
- * nothing on the call path.
+ * that the gather reads the rows directly). Batched calls keep their root
+ * slots in the caller's workspace or the plan, and allocate nothing on the
+ * call path.
  *
  * Layouts (structure of arrays, 32-bit floats, row-major):
  *   rays   : 7 rows of ray_stride floats  -- ox, oy, oz, dx, dy, dz, tmax.
@@ -176,11 +177,11 @@ typedef struct fi_scene {
     float *t_out; float *u_out; uint8_t *hit_out;
 } fi_scene;
 
-/* Launch tuning of the traversal kernel (not part of the method):
+/* Launch tuning of the batched kernel (not part of the method):
  *   refill          refill a wave's finished lanes once at least this many
  *                   (1..64) are free;
  *   waves_per_simd  cap on resident waves per SIMD (0..16, 0 = as many as fit,
- *                   which is 8).
+ *                   which is 6 for the batched kernel).
  * Results never depend on the tuning. */
 typedef struct fi_tuning {
     int32_t refill;
@@ -188,9 +189,10 @@ typedef struct fi_tuning {
 } fi_tuning;
 
 /* Bytes of device workspace fiber_intersect_batched needs for n_scenes
- * problems of total_pairs pairs in all (0 for negative arguments): the scene
- * table, the bucket counters and a survivor table of min(total_pairs, 2^22)
- * rows, rounded up to a multiple of 65536 (85 bytes per row). */
+ * problems of total_pairs pairs in all, on the current device (0 for negative
+ * arguments or when the device cannot be queried): the scene table and the
+ * root slots of the resident waves (4 KiB each, about 24 MiB on MI355X); it
+ * does not grow with total_pairs. */
 size_t fiber_batched_workspace_bytes(int32_t n_scenes, int64_t total_pairs);
 
 /*
@@ -199,10 +201,9 @@ size_t fiber_batched_workspace_bytes(int32_t n_scenes, int64_t total_pairs);
  *
  * Operation: for every scene k, exactly what fiber_intersect_pairs computes
  * for scenes[k] (same per-pair routine; results are bitwise identical to a
- * separate call per scene). Pairs of all scenes are numbered consecutively;
- * one setup launch covers them all (per chunk of 2^22) and one traversal
- * launch drains the survivors of all scenes together, so small scenes do not
- * leave the GPU idle.
+ * separate call per scene). Pairs of all scenes are numbered consecutively
+ * and one persistent launch covers them all (each wave an even share), so
+ * small scenes do not leave the GPU idle.
  *
  * Arguments: scenes is a host array of n_scenes descriptors (the library
  * copies it before returning); tuning may be NULL (the autotuned entry of
@@ -221,8 +222,7 @@ int fiber_intersect_batched(const fi_scene *scenes, int32_t n_scenes, const fi_t
 
 /*
  * Plans: the scene table is uploaded once into device memory the plan owns
- * (with its counters and survivor table), and the launch (a counter reset
- * kernel, then setup and traversal per chunk) is captured into a HIP graph
+ * (with its root slots), and the launch (one kernel) is captured into a HIP graph
  * that fiber_batch_plan_launch replays on any stream. Creating and destroying a plan allocates and frees device memory;
  * launching does not. One plan must not be launched on two streams at once.
  * The scenes' device buffers must outlive the plan.
@@ -237,7 +237,7 @@ int fiber_batch_plan_destroy(fi_batch_plan *plan);
 
 /*
  * fiber_batch_autotune -- time fiber_intersect_batched on these scenes over a
- * grid of tunings (refill 8, 16 or 32; waves per SIMD 4, 6 or as many as
+ * grid of tunings (refill 32, 48 or 56; waves per SIMD 4, 5 or as many as
  * fit), each `repeats`
  * times after one warm-up, and return the fastest
  * in *best (and its time in *best_ms if not NULL). Overwrites the scenes'

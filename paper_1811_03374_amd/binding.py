@@ -238,7 +238,7 @@ def _tuning(t):
 
 def workspace_for(problems, device=None):
     """Device workspace for a batched call over ``problems`` (a list of
-    Problem): scene table, bucket counters and survivor table."""
+    Problem): scene table and root slots (sized for the current device)."""
     total = sum(int(p.n) for p in problems)
     nbytes = _batched_lib().fiber_batched_workspace_bytes(len(problems), total)
     if device is None:

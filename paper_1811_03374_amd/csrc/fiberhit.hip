@@ -635,20 +635,20 @@ enum { kPlain = 0, kCount = 1, kConservative = 2 };
 // Survivor table
 // ---------------------------------------------------------------------------
 //
-// The work of one call is split in two kernels. The setup kernel (one lane per
-// pair, no persistence) loads a pair, moves it into the ray frame in FP64 and
-// tests the root cylinder; a pair that misses its root (or is decided at the
-// root, depth 0) is written out at once, every other pair is appended to this
-// table: its root node, cap interval and tmax, in structure-of-arrays rows so
-// that the traversal kernel's refills are coalesced loads. The traversal
-// kernel then never holds FP64 state, which keeps its register count low
-// enough for twice the resident waves.
+// A refined call (and, with a compile-time switch, any single call) is split
+// in two kernels. The setup kernel (one lane per pair, no persistence) loads a
+// pair, moves it into the ray frame in FP64 and tests the root cylinder; a
+// pair that misses its root (or is decided at the root, depth 0) is written
+// out at once, every other pair is appended to this table: its root node, cap
+// interval and tmax, in structure-of-arrays rows so that the traversal
+// kernel's refills are coalesced loads. The traversal kernel then never holds
+// FP64 state, which keeps its register count low. The one-kernel path
+// (k_fused) does the setup steps in its lane refill instead and needs no table.
 constexpr int kTableFloats = 19;              // node (16), lo, hi, tmax
 
 struct Table {
     float *f;                                 // kTableFloats rows of cap floats
     int32_t *pair;                            // pair index within its problem
-    int32_t *scene;                           // problem of the pair (batched calls)
     uint8_t *depth;                           // subdivision depth of the pair
     int32_t cap;                              // rows (at most 2^20)
 };
@@ -669,7 +669,7 @@ __host__ __device__ __forceinline__ Outs outs_of(const Args &a)
 }
 
 __device__ __forceinline__ void table_put(const Table &tab, int32_t row, const Node &r, float lo, float hi,
-                                          float tmax, int32_t pair, int32_t scene, uint32_t depth)
+                                          float tmax, int32_t pair, uint32_t depth)
 {
     const float *f = &r.p.x;
 #pragma unroll
@@ -678,7 +678,6 @@ __device__ __forceinline__ void table_put(const Table &tab, int32_t row, const N
     tab.f[17 * tab.cap + row] = hi;
     tab.f[18 * tab.cap + row] = tmax;
     tab.pair[row] = pair;
-    tab.scene[row] = scene;
     tab.depth[row] = (uint8_t)depth;
 }
 
@@ -1059,11 +1058,9 @@ constexpr int kBuckets = 256;                 // equal to kSetupBlock: block 0 z
 static_assert(kBuckets == kSetupBlock, "setup block 0 clears one counter per thread");
 constexpr int kCounterWords = 2 * kBuckets;   // two sets
 
-// Setup kernel: pairs [begin, begin + count) of the call (numbered across the
-// scene table when BATCHED), one lane each.
-template <int MODE, bool BATCHED>
-__global__ __launch_bounds__(kSetupBlock) void k_setup(Args a0, const Args *scenes, const int64_t *offsets,
-                                                      int n_scenes, int64_t begin, int64_t count, Table tab,
+// Setup kernel: pairs [begin, begin + count) of the call, one lane each.
+template <int MODE>
+__global__ __launch_bounds__(kSetupBlock) void k_setup(Args a, int64_t begin, int64_t count, Table tab,
                                                       uint32_t *counts, uint32_t *stale, const float *aos)
 {
     __shared__ uint32_t s_wave[kSetupBlock / kWave];
@@ -1075,18 +1072,9 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(Args a0, const Args *scen
     float lo = 0.0f, hi = 0.0f, tmax = 0.0f;
     uint32_t depth = 0;
     int64_t idx = 0;
-    int scene = 0;
     if (k < count) {
-        const int64_t g = begin + k;
-        Args a = a0;
-        if constexpr (BATCHED) {
-            scene = find_scene(offsets, n_scenes, g);
-            idx = g - offsets[scene];
-            a = scenes[scene];
-        } else {
-            idx = g;
-        }
-        if (!load_pair(a, idx, root, tmax, depth, BATCHED ? nullptr : aos)) {
+        idx = begin + k;
+        if (!load_pair(a, idx, root, tmax, depth, aos)) {
             finish_invalid<MODE>(a, idx);
         } else {
             cap_interval(root, tmax, lo, hi);
@@ -1129,7 +1117,7 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(Args a0, const Args *scen
         for (int w = 0; w < wave; ++w) off += s_wave[w];
         const int32_t bucket_rows = tab.cap / kBuckets;
         table_put(tab, (int32_t)(blockIdx.x % kBuckets) * bucket_rows + (int32_t)off, root, lo, hi, tmax,
-                  (int32_t)idx, scene, depth);
+                  (int32_t)idx, depth);
     }
 }
 
@@ -1139,9 +1127,9 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(Args a0, const Args *scen
 // finishes. The attribute sets the register budget: 64 VGPRs (eight waves
 // per SIMD, the most gfx950 runs) hold the plain traversal without spills;
 // the counting and conservative variants get 80 (six waves).
-template <int MODE, bool BATCHED>
+template <int MODE>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MODE == kPlain ? FIBERHIT_TRAVERSE_WAVES : MODE == kCount ? 6 : 4, 8)))
-void k_traverse(Args a0, const Args *scenes, Table tab, const uint32_t *counts, int n_buckets, int refill)
+void k_traverse(Args a0, Table tab, const uint32_t *counts, int n_buckets, int refill)
 {
     __shared__ float s_cache[(kParentCache ? 16 : 1) * kWave];
     const int lane = threadIdx.x;
@@ -1199,15 +1187,10 @@ void k_traverse(Args a0, const Args *scenes, Table tab, const uint32_t *counts, 
         // active and idle ones
         const int st = trip<MODE>(L, TableRoot{tab}, col);
         if (active && st != kGoOn && !(MODE == kConservative && L.waiting)) {
-            const int64_t i = L.pair;
-            if constexpr (BATCHED) {
-                finish<MODE>(outs_of(scenes[tab.scene[L.row]]), i, L, st == kHit);
-            } else {
-                finish<MODE>(outs_of(a0), i, L, st == kHit);
-            }
+            finish<MODE>(outs_of(a0), L.pair, L, st == kHit);
             active = false;
         }
-        if constexpr (MODE == kConservative && !BATCHED) {
+        if constexpr (MODE == kConservative) {
             // FP64 leaf checks run for a batch of parked lanes at once (SIMD
             // lanes of one call), once 16 are parked or no other lane is busy
             const uint64_t parked = __ballot(L.waiting != 0);
@@ -1287,9 +1270,10 @@ __device__ __forceinline__ bool load_pair_lean(const Args &a, int64_t i, Node &r
 // by root misses are refilled at once.
 constexpr int kFusedRounds = FIBERHIT_FUSED_ROUNDS;
 
-template <int MODE>
+template <int MODE, bool BATCHED>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MODE == kPlain ? FIBERHIT_FUSED_WAVES : 5, 8)))
-void k_fused(Args a, int64_t count, float *slots, int refill, const float *aos)
+void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, int64_t count, float *slots,
+             int refill, const float *aos)
 {
     __shared__ float s_cache[16 * kWave];
     const int lane = (int)threadIdx.x;
@@ -1300,6 +1284,14 @@ void k_fused(Args a, int64_t count, float *slots, int refill, const float *aos)
     const int64_t end = (w + 1) * share < count ? (w + 1) * share : count;
     float *slot = slots + (size_t)w * 16 * kWave + lane;
     const SlotRoot root{slot};
+    // batched: pairs are numbered across the scene table; the wave's share
+    // is contiguous, so the scene of its next pair only moves forward
+    int scene0 = 0;
+    Outs cur = outs_of(a0);              // outputs of scene0 (wave-uniform)
+    if constexpr (BATCHED) {
+        scene0 = __builtin_amdgcn_readfirstlane(next < count ? find_scene(offsets, n_scenes, next) : 0);
+        cur = outs_of(scenes[scene0]);
+    }
     Lane L = {};
     L.lo = INFINITY;                                                   // parked, as in k_traverse
     L.hi = -INFINITY;
@@ -1314,7 +1306,15 @@ void k_fused(Args a, int64_t count, float *slots, int refill, const float *aos)
                 const int rank = (int)lanes_below(free_mask);
                 if (rank < take) {
                     // the new pair goes straight into the (free) lane's state
-                    const int64_t idx = next + rank;
+                    int64_t idx = next + rank;
+                    Args a = a0;
+                    if constexpr (BATCHED) {
+                        int sc = scene0;
+                        while (sc + 1 < n_scenes && offsets[sc + 1] <= idx) ++sc;
+                        idx -= offsets[sc];
+                        a = scenes[sc];
+                        L.row = sc;                // the lane's scene (no table row here)
+                    }
                     uint32_t depth = 0;
                     if (!load_pair_lean(a, idx, L.c, L.tmax, depth, aos)) {
                         finish_invalid<MODE>(a, idx);
@@ -1358,6 +1358,12 @@ void k_fused(Args a, int64_t count, float *slots, int refill, const float *aos)
                 }
             }
             next += take;
+            if constexpr (BATCHED) {
+                const int before = scene0;
+                while (scene0 + 1 < n_scenes && next < count && offsets[scene0 + 1] <= next) ++scene0;
+                scene0 = __builtin_amdgcn_readfirstlane(scene0);
+                if (scene0 != before) cur = outs_of(scenes[scene0]);
+            }
         }
         if (__ballot(active) == 0) {
             if (next >= end) break;
@@ -1365,7 +1371,15 @@ void k_fused(Args a, int64_t count, float *slots, int refill, const float *aos)
         }
         const int st = trip<MODE>(L, root, col);
         if (active && st != kGoOn) {
-            finish<MODE>(outs_of(a), L.pair, L, st == kHit);
+            if constexpr (BATCHED) {
+                // lanes of the wave's current scene write through its
+                // uniform output pointers; others (a scene boundary inside
+                // the wave) load their scene's
+                if (L.row == scene0) finish<MODE>(cur, L.pair, L, st == kHit);
+                else finish<MODE>(outs_of(scenes[L.row]), L.pair, L, st == kHit);
+            } else {
+                finish<MODE>(outs_of(a0), L.pair, L, st == kHit);
+            }
             active = false;
         }
         if (!active) {
@@ -1387,13 +1401,6 @@ __global__ __launch_bounds__(256) void k_fibers_aos(const float *F, int64_t fs, 
     for (int k = 0; k < 4; ++k)
         out[4 * f + k] = make_float4(F[(4 * k) * fs + f], F[(4 * k + 1) * fs + f], F[(4 * k + 2) * fs + f],
                                      F[(4 * k + 3) * fs + f]);
-}
-
-// Zero both counter sets from inside a stream or graph (a kernel, not a
-// memset node, so that graph replays see fresh counters).
-__global__ void k_reset_counters(uint32_t *counters)
-{
-    for (int k = threadIdx.x; k < kCounterWords; k += blockDim.x) counters[k] = 0u;
 }
 
 int check_common(const float *rays, int64_t ray_stride, int64_t n_rays,
@@ -1418,25 +1425,16 @@ int check_common(const float *rays, int64_t ray_stride, int64_t n_rays,
 // Kernel variants, counters, survivor tables and launch shape
 // ---------------------------------------------------------------------------
 
-using SetupFn = void (*)(Args, const Args *, const int64_t *, int, int64_t, int64_t, Table, uint32_t *,
-                         uint32_t *, const float *);
-using TraverseFn = void (*)(Args, const Args *, Table, const uint32_t *, int, int);
+using SetupFn = void (*)(Args, int64_t, int64_t, Table, uint32_t *, uint32_t *, const float *);
+using TraverseFn = void (*)(Args, Table, const uint32_t *, int, int);
 
-// [mode][batched]. Batched calls take neither counts nor refinement: their
-// table rows for those modes hold the plain kernels and are never launched.
-const SetupFn kSetup[3][2] = {
-    {k_setup<kPlain, false>, k_setup<kPlain, true>},
-    {k_setup<kCount, false>, k_setup<kPlain, true>},
-    {k_setup<kConservative, false>, k_setup<kPlain, true>},
-};
-using FusedFn = void (*)(Args, int64_t, float *, int, const float *);
-const FusedFn kFused[2] = {k_fused<kPlain>, k_fused<kCount>};
+// [mode]: plain, counting, conservative
+const SetupFn kSetup[3] = {k_setup<kPlain>, k_setup<kCount>, k_setup<kConservative>};
+using FusedFn = void (*)(Args, const Args *, const int64_t *, int, int64_t, float *, int, const float *);
+// [0] plain, [1] counting (single calls), [2] plain over a scene table
+const FusedFn kFused[3] = {k_fused<kPlain, false>, k_fused<kCount, false>, k_fused<kPlain, true>};
 
-const TraverseFn kTraverse[3][2] = {
-    {k_traverse<kPlain, false>, k_traverse<kPlain, true>},
-    {k_traverse<kCount, false>, k_traverse<kPlain, true>},
-    {k_traverse<kConservative, false>, k_traverse<kPlain, true>},
-};
+const TraverseFn kTraverse[3] = {k_traverse<kPlain>, k_traverse<kCount>, k_traverse<kConservative>};
 
 // Pairs per chunk: the setup kernel covers at most this many pairs before the
 // traversal kernel drains their survivors. Table sizes are multiples of
@@ -1445,16 +1443,14 @@ const TraverseFn kTraverse[3][2] = {
 // blocks of kSetupBlock pairs each).
 constexpr int64_t kTableQuantum = (int64_t)kBuckets * kSetupBlock;
 constexpr int64_t kChunkRows = 1 << 20;         // single-problem calls: tables the library owns
-constexpr int64_t kBatchChunkRows = 1 << 22;    // batched calls and plans: the caller's workspace
 static_assert(kChunkRows % kTableQuantum == 0, "chunk must be a whole number of table quanta");
-static_assert(kBatchChunkRows % kTableQuantum == 0, "chunk must be a whole number of table quanta");
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Bytes of a survivor table of `rows` rows, and its layout at `base`.
 size_t table_region_bytes(int64_t rows)
 {
-    return align256((size_t)rows * kTableFloats * sizeof(float)) + 2 * align256((size_t)rows * sizeof(int32_t)) +
+    return align256((size_t)rows * kTableFloats * sizeof(float)) + align256((size_t)rows * sizeof(int32_t)) +
            align256((size_t)rows);
 }
 
@@ -1467,25 +1463,16 @@ Table table_at(void *base, int64_t rows)
     p += align256((size_t)rows * kTableFloats * sizeof(float));
     t.pair = (int32_t *)p;
     p += align256((size_t)rows * sizeof(int32_t));
-    t.scene = (int32_t *)p;
-    p += align256((size_t)rows * sizeof(int32_t));
     t.depth = (uint8_t *)p;
     return t;
 }
 
-// Rows a batched call of `total` pairs uses: one chunk at most, a whole number
-// of table quanta. Larger chunks than single calls use: fewer setup passes and
-// traversal tails for a big batch, and more rows per traversal wave.
-int64_t rows_for(int64_t total)
-{
-    const int64_t r = total < kBatchChunkRows ? total : kBatchChunkRows;
-    return ((r > 0 ? r : 1) + kTableQuantum - 1) / kTableQuantum * kTableQuantum;
-}
 
-// Single-problem calls keep kRegions survivor tables per device, allocated at
-// the first call that needs one and used round-robin; a call waits on its
-// stream (through an event) for the previous call that used its table. Their
-// bucket counters live in a file-scope device array, zero at load.
+// Single-problem calls keep kRegions sets of buffers per device (survivor
+// table, root slots, fiber records), allocated at the first call that needs
+// one and used round-robin; a call waits on its stream (through an event) for
+// the previous call that used its set. The tables' bucket counters live in a
+// file-scope device array, zero at load.
 constexpr int kRegions = 2;
 __device__ __align__(256) uint32_t g_counters[kRegions * kCounterWords];
 
@@ -1508,8 +1495,8 @@ struct Region {
 struct DeviceInfo {
     std::atomic<bool> ready;
     int cus;
-    int resident[3][2];                        // resident traversal waves per CU, per variant
-    int fused_resident[2];                     // resident one-kernel waves per CU (plain, counting)
+    int resident[3];                           // resident traversal waves per CU, per variant
+    int fused_resident[3];                     // resident one-kernel waves per CU (as kFused)
     Region region[kRegions];
     std::atomic<uint32_t> next_region;
     std::mutex stage_mutex;
@@ -1538,15 +1525,13 @@ int device_info(DeviceInfo *&out)
             if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_counters)) != hipSuccess || !p) return FI_ERR_HIP;
             if (hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
                 return FI_ERR_HIP;
-            for (int m = 0; m < 3; ++m)
-                for (int b = 0; b < 2; ++b) {
-                    int nb = 0;
-                    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)kTraverse[m][b], kWave, 0) !=
-                        hipSuccess)
-                        return FI_ERR_HIP;
-                    d.resident[m][b] = nb > 0 ? nb : 1;
-                }
-            for (int m = 0; m < 2; ++m) {
+            for (int m = 0; m < 3; ++m) {
+                int nb = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)kTraverse[m], kWave, 0) != hipSuccess)
+                    return FI_ERR_HIP;
+                d.resident[m] = nb > 0 ? nb : 1;
+            }
+            for (int m = 0; m < 3; ++m) {
                 int nb = 0;
                 if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)kFused[m], kWave, 0) != hipSuccess)
                     return FI_ERR_HIP;
@@ -1573,8 +1558,11 @@ int device_info(DeviceInfo *&out)
 
 // Launch defaults of single-problem calls (and of batches without a tuned
 // entry); measured choices, overridable when building.
+#ifndef FIBERHIT_TABLE_REFILL
+#define FIBERHIT_TABLE_REFILL 8                    // free lanes that trigger a survivor-table refill
+#endif
 #ifndef FIBERHIT_DEFAULT_REFILL
-#define FIBERHIT_DEFAULT_REFILL 8
+#define FIBERHIT_DEFAULT_REFILL 48
 #endif
 #ifndef FIBERHIT_DEFAULT_WAVES_PER_SIMD
 #define FIBERHIT_DEFAULT_WAVES_PER_SIMD 0
@@ -1631,10 +1619,9 @@ int check_tuning(const fi_tuning &t)
 
 // Traversal grid for a chunk of `count` pairs: about one wave per 64 pairs, at
 // most the resident waves, and a whole number of waves per used bucket.
-unsigned traverse_grid(const DeviceInfo &d, int mode, bool batched, const fi_tuning &t, int64_t count,
-                       int n_buckets)
+unsigned traverse_grid(const DeviceInfo &d, int mode, const fi_tuning &t, int64_t count, int n_buckets)
 {
-    int per_cu = d.resident[mode][batched ? 1 : 0];
+    int per_cu = d.resident[mode];
     if (t.waves_per_simd > 0 && 4 * t.waves_per_simd < per_cu) per_cu = 4 * t.waves_per_simd;
     const int64_t resident = (int64_t)per_cu * d.cus;
     int64_t g = (count + kWave - 1) / kWave;
@@ -1646,21 +1633,19 @@ unsigned traverse_grid(const DeviceInfo &d, int mode, bool batched, const fi_tun
 // Enqueue setup + traversal for `total` pairs, chunk by chunk through `tab`.
 // counters[parity * kBuckets ..] must be zero; returns the set that is zero
 // after the last chunk.
-int launch_chain(const DeviceInfo &d, int mode, bool batched, const fi_tuning &t, const Args &a0,
-                 const Args *scenes, const int64_t *offsets, int n_scenes, int64_t total, const Table &tab,
-                 uint32_t *counters, int parity, hipStream_t s, const float *aos = nullptr)
+int launch_chain(const DeviceInfo &d, int mode, const fi_tuning &t, const Args &a0, int64_t total,
+                 const Table &tab, uint32_t *counters, int parity, hipStream_t s, const float *aos)
 {
-    const int b = batched ? 1 : 0;
     for (int64_t begin = 0; begin < total; begin += tab.cap) {
         const int64_t count = total - begin < tab.cap ? total - begin : tab.cap;
         const int64_t blocks = (count + kSetupBlock - 1) / kSetupBlock;
         const int n_buckets = blocks < kBuckets ? (int)blocks : kBuckets;
         uint32_t *cur = counters + parity * kBuckets;
         uint32_t *other = counters + (1 - parity) * kBuckets;
-        hipLaunchKernelGGL(kSetup[mode][b], dim3((unsigned)blocks), dim3(kSetupBlock), 0, s, a0, scenes, offsets,
-                           n_scenes, begin, count, tab, cur, other, aos);
-        hipLaunchKernelGGL(kTraverse[mode][b], dim3(traverse_grid(d, mode, batched, t, count, n_buckets)),
-                           dim3(kWave), 0, s, a0, scenes, tab, (const uint32_t *)cur, n_buckets, t.refill);
+        hipLaunchKernelGGL(kSetup[mode], dim3((unsigned)blocks), dim3(kSetupBlock), 0, s, a0, begin, count, tab,
+                           cur, other, aos);
+        hipLaunchKernelGGL(kTraverse[mode], dim3(traverse_grid(d, mode, t, count, n_buckets)), dim3(kWave), 0, s,
+                           a0, tab, (const uint32_t *)cur, n_buckets, t.refill);
         parity = 1 - parity;
     }
     return parity;
@@ -1725,10 +1710,10 @@ int launch(int mode, const Args &a, void *stream)
             int64_t g = (a.n_pairs + kWave - 1) / kWave;
             if (g > fused_waves) g = fused_waves;
             if (g > 0)
-                hipLaunchKernelGGL(kFused[mode], dim3((unsigned)g), dim3(kWave), 0, s, a, a.n_pairs, R.slots,
-                                   FIBERHIT_FUSED_REFILL, aos);
+                hipLaunchKernelGGL(kFused[mode], dim3((unsigned)g), dim3(kWave), 0, s, a, nullptr, nullptr, 0,
+                                   a.n_pairs, R.slots, FIBERHIT_FUSED_REFILL, aos);
         } else {
-            R.parity = launch_chain(*d, mode, false, default_tuning(), a, nullptr, nullptr, 1, a.n_pairs,
+            R.parity = launch_chain(*d, mode, fi_tuning{FIBERHIT_TABLE_REFILL, 0}, a, a.n_pairs,
                                     table_at(R.mem, kChunkRows), R.counters, R.parity, s, aos);
         }
         if (hipEventRecord(R.done, s) != hipSuccess) return FI_ERR_HIP;
@@ -1743,11 +1728,20 @@ int launch(int mode, const Args &a, void *stream)
 
 size_t table_bytes(int n) { return align256((size_t)n * sizeof(Args)) + align256((size_t)(n + 1) * sizeof(int64_t)); }
 
-constexpr size_t kCounterBytes = align256(kCounterWords * sizeof(uint32_t));
+// Root slots of the one-kernel batched path: one 4 KB block per resident
+// wave of the current device (0 if the device cannot be queried).
+size_t batched_slot_bytes()
+{
+    DeviceInfo *d = nullptr;
+    if (device_info(d) != FI_OK) return 0;
+    return align256((size_t)d->fused_resident[2] * d->cus * 16 * kWave * sizeof(float));
+}
 
 size_t batched_bytes(int n, int64_t total)
 {
-    return table_bytes(n) + kCounterBytes + table_region_bytes(rows_for(total));
+    (void)total;
+    const size_t slots = batched_slot_bytes();
+    return slots ? table_bytes(n) + slots : 0;
 }
 
 int scenes_to_table(const fi_scene *sc, int32_t n, Args *tab, int64_t *off)
@@ -1767,24 +1761,36 @@ int scenes_to_table(const fi_scene *sc, int32_t n, Args *tab, int64_t *off)
     return FI_OK;
 }
 
-// Layout of a batched workspace: scene table, pair offsets, counters,
-// survivor table.
+// Layout of a batched workspace: scene table, pair offsets, root slots.
 struct BatchLayout {
     Args *scenes;
     int64_t *offsets;
-    uint32_t *counters;
-    Table tab;
+    float *slots;
 };
 
-BatchLayout layout_of(void *ws, int n, int64_t total)
+BatchLayout layout_of(void *ws, int n)
 {
     char *p = (char *)ws;
     BatchLayout L;
     L.scenes = (Args *)p;
     L.offsets = (int64_t *)(p + align256((size_t)n * sizeof(Args)));
-    L.counters = (uint32_t *)(p + table_bytes(n));
-    L.tab = table_at(p + table_bytes(n) + kCounterBytes, rows_for(total));
+    L.slots = (float *)(p + table_bytes(n));
     return L;
+}
+
+// One persistent launch over all scenes of a batch: about one wave per 64
+// pairs, at most the resident waves (fewer when the tuning caps the waves
+// per SIMD).
+void launch_batched(const DeviceInfo &d, const fi_tuning &t, const BatchLayout &L, int n_scenes, int64_t total,
+                    hipStream_t s)
+{
+    int per_cu = d.fused_resident[2];
+    if (t.waves_per_simd > 0 && 4 * t.waves_per_simd < per_cu) per_cu = 4 * t.waves_per_simd;
+    int64_t g = (total + kWave - 1) / kWave;
+    if (g > (int64_t)per_cu * d.cus) g = (int64_t)per_cu * d.cus;
+    if (g > 0)
+        hipLaunchKernelGGL(kFused[2], dim3((unsigned)g), dim3(kWave), 0, s, Args{}, L.scenes, L.offsets, n_scenes,
+                           total, L.slots, t.refill, nullptr);
 }
 
 int batched_enqueue(const fi_scene *scenes, int32_t n_scenes, const fi_tuning &t, void *workspace,
@@ -1809,12 +1815,11 @@ int batched_enqueue(const fi_scene *scenes, int32_t n_scenes, const fi_tuning &t
     st = scenes_to_table(scenes, n_scenes, (Args *)host, (int64_t *)(host + align256((size_t)n_scenes * sizeof(Args))));
     if (st != FI_OK) return st;
     const int64_t total = ((int64_t *)(host + align256((size_t)n_scenes * sizeof(Args))))[n_scenes];
-    const BatchLayout L = layout_of(workspace, n_scenes, total);
+    const BatchLayout L = layout_of(workspace, n_scenes);
     if (hipMemcpyAsync(workspace, host, tb, hipMemcpyHostToDevice, s) != hipSuccess) return FI_ERR_HIP;
     if (hipEventRecord(d->stage_done[k], s) != hipSuccess) return FI_ERR_HIP;
     d->stage_next = (k + 1) % kStageSlots;
-    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(256), 0, s, L.counters);
-    launch_chain(*d, kPlain, true, t, Args{}, L.scenes, L.offsets, n_scenes, total, L.tab, L.counters, 0, s);
+    launch_batched(*d, t, L, n_scenes, total, s);
     return hipGetLastError() == hipSuccess ? FI_OK : FI_ERR_HIP;
 }
 
@@ -1822,7 +1827,7 @@ int batched_enqueue(const fi_scene *scenes, int32_t n_scenes, const fi_tuning &t
 
 struct fi_batch_plan {
     int device;
-    void *mem;                 // device copy of the scene table and offsets; counters; survivor table
+    void *mem;                 // device copy of the scene table and offsets; root slots
     int n_scenes;
     int64_t total;
     fi_tuning tuning;
@@ -1926,17 +1931,16 @@ int fiber_batch_plan_create(const fi_scene *scenes, int32_t n_scenes, const fi_t
     p->tuning = t;
     current_device(p->device);
     hipStream_t cs = nullptr;
-    bool ok = hipMalloc(&p->mem, batched_bytes(n_scenes, p->total)) == hipSuccess &&
+    const size_t bytes = batched_bytes(n_scenes, p->total);
+    bool ok = bytes > 0 && hipMalloc(&p->mem, bytes) == hipSuccess &&
               hipMemcpy(p->mem, host, tb, hipMemcpyHostToDevice) == hipSuccess &&
               hipStreamCreate(&cs) == hipSuccess;
     free(host);
     if (ok) {
-        const BatchLayout L = layout_of(p->mem, n_scenes, p->total);
+        const BatchLayout L = layout_of(p->mem, n_scenes);
         ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
         if (ok) {
-            hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(256), 0, cs, L.counters);
-            launch_chain(*d, kPlain, true, t, Args{}, L.scenes, L.offsets, n_scenes, p->total, L.tab, L.counters,
-                         0, cs);
+            launch_batched(*d, t, L, n_scenes, p->total, cs);
             ok = hipStreamEndCapture(cs, &p->graph) == hipSuccess &&
                  hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) == hipSuccess;
         }
@@ -1988,8 +1992,8 @@ int fiber_batch_autotune(const fi_scene *scenes, int32_t n_scenes, uint32_t flag
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return FI_ERR_HIP;
-    const int refills[] = {8, 16, 32};
-    const int occ[] = {4, 6, 0};
+    const int refills[] = {32, 48, 56};
+    const int occ[] = {4, 5, 0};
     float best_t = INFINITY;
     fi_tuning bt = default_tuning();
     int st = FI_OK;
