@@ -29,7 +29,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--workload", choices=("straight_and_curved", "batched", "hair"),
+    ap.add_argument("--workload", choices=("straight_and_curved", "batched", "hair", "degenerate"),
                     default="straight_and_curved",
                     help="batched: 256 uneven scenes (~13 M pairs, adaptive depth), one graph launch "
                          "against 256 plain launches; hair: precision stress with error report")
@@ -205,6 +205,83 @@ def bench_hair(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_degenerate(args):
+    """Degenerate-geometry batch: 2^22 pairs in four families (cusps,
+    near-collinear points, zero end tangents, steep tapers), per-pair depth
+    16..22, FP32 and with FP64 refinement. Errors per family on a seeded
+    sample of 2^15 pairs: FP32 against the depth oracle at each pair's depth,
+    refined against the exact oracle, both outside the 1e-4 r band; curves
+    that break the constraints of Section 3.4 (which the paper splits
+    beforehand) are counted apart."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1811_03374_amd import binding
+    from paper_1811_03374_amd import workloads as W
+
+    w = W.degenerate_geometry(1 << 22)
+    dev = torch.device("cuda:0")
+    g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    rays, fibers, pd = g(w.rays), g(w.fibers), g(w.pair_depth)
+    n = w.n_pairs
+    stream = torch.cuda.current_stream()
+    res = {}
+    ms = _timed(lambda: binding.intersect_pairs(rays, fibers, 22, pair_depth=pd, stream=stream),
+                args.steps, args.warmup, stream)
+    plain = [o.cpu().numpy() for o in binding.intersect_pairs(rays, fibers, 22, pair_depth=pd)]
+    res["fp32"] = {"ms": ms, "gpairs_per_s": n / (ms * 1e-3) / 1e9}
+    ms = _timed(lambda: binding.intersect_pairs(rays, fibers, 22, pair_depth=pd, refine=True, stream=stream),
+                args.steps, args.warmup, stream)
+    ref = [o.cpu().numpy() for o in binding.intersect_pairs(rays, fibers, 22, pair_depth=pd, refine=True)]
+    res["fp64_refined"] = {"ms": ms, "gpairs_per_s": n / (ms * 1e-3) / 1e9}
+    print("degenerate: timed; oracle sample", file=sys.stderr, flush=True)
+
+    idx = np.sort(np.random.default_rng(5).choice(n, 1 << 15, replace=False))
+    ws = w.subset(idx)
+    P = W.unpack_fibers(ws.fibers)
+    valid = np.array([oracle.cubic_constraints(P[i].reshape(16)) == 31 for i in range(P.shape[0])])
+    fam = w.meta["family"][idx]
+    t_d, u_d, h_d = oracle.intersect_depth(ws.rays, ws.fibers, pair_depth=ws.pair_depth)
+    _, _, hl = oracle.intersect_depth(ws.rays, ws.fibers, pair_depth=ws.pair_depth, radius_scale=1 - 1e-4)
+    _, _, hh = oracle.intersect_depth(ws.rays, ws.fibers, pair_depth=ws.pair_depth, radius_scale=1 + 1e-4)
+    band_d = hl != hh
+    t_x, u_x, h_x, _ = oracle.intersect_exact(ws.rays, ws.fibers)
+    _, _, hl, _ = oracle.intersect_exact(ws.rays, ws.fibers, radius_scale=1 - 1e-4)
+    _, _, hh, _ = oracle.intersect_exact(ws.rays, ws.fibers, radius_scale=1 + 1e-4)
+    band_x = hl != hh
+    refined = ws.pair_depth > 16
+
+    def stats(h, t, m, h_o, t_o):
+        h, h_o = h.astype(bool), h_o.astype(bool)
+        both = m & h & h_o
+        rel = np.abs(t[both] - t_o[both]) / np.maximum(np.abs(t_o[both]), 1e-300)   # t = 0: origin inside
+        return {"pairs": int(m.sum()), "flag_disagree_rate": float((h[m] != h_o[m]).mean()) if m.any() else 0.0,
+                "max_rel_t": float(rel.max()) if rel.size else 0.0,
+                "p999_rel_t": float(np.quantile(rel, 0.999)) if rel.size else 0.0}
+
+    names = ("cusp", "near-collinear", "zero tangent", "steep taper")
+    for key, (h, t), (h_o, t_o), band, extra in (
+            ("fp32", (plain[2][idx], plain[0][idx]), (h_d, t_d), band_d, np.ones(len(idx), bool)),
+            ("fp64_refined", (ref[2][idx], ref[3][idx]), (h_x, t_x), band_x, refined)):
+        per = {}
+        for f, name in enumerate(names):
+            for val in (True, False):
+                m = (fam == f) & (valid == val) & ~band & extra
+                if m.any():
+                    per[f"{name}{'' if val else ' (breaks Sec. 3.4 constraints)'}"] = stats(h, t, m, h_o, t_o)
+        res[key]["vs_oracle"] = per
+    line = {"metric": "ray-fiber intersections/sec (Gpairs/s), degenerate geometry",
+            "value": res["fp32"]["gpairs_per_s"], "unit": "Gpairs/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "dtype": "f32 (+f64 refinement)",
+            "data": "synthetic",
+            "config": {"workload": "degenerate: cusps, near-collinear (jitter 1e-6), zero end tangents, "
+                                   "radius ratios to 1000:1; rays along and across the chord; depth 16..22",
+                       "pairs": n, "error_sample": int(len(idx)),
+                       "refined_sample": "pairs of depth > 16 (shallower pairs keep the FP32 result)"},
+            "results": res}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -216,6 +293,9 @@ def main():
         return
     if args.workload == "hair":
         bench_hair(args)
+        return
+    if args.workload == "degenerate":
+        bench_degenerate(args)
         return
 
     import numpy as np
