@@ -843,6 +843,63 @@ __device__ __noinline__ bool refine_whole_curve(Lane &L, const Table &tab, const
 // with the rebuilt sibling. The new node thus has a single definition point,
 // which spares the copies of the whole lane state that a merge of separately
 // computed nodes costs, and a backtracking lane only adds the rebuild.
+// The split of the current node (Section 3.1 / 3.2): centre offset and split
+// tangent, the split plane's crossing tp with the ray, whether the ray meets
+// both halves inside [te, tx], which half it meets first, and the interval
+// of that half (narrowed at tp).
+struct Split {
+    V4 dp, tc;
+    float nlo, nhi;
+    bool both, near_right, oblique;
+};
+
+template <int MODE>
+__device__ __forceinline__ void split_plane(const Lane &L, float te, float tx, Split &sp)
+{
+    split_terms(L.c, sp.dp, sp.tc);
+    float nx = sp.tc.x, ny = sp.tc.y, nz = sp.tc.z;
+    if (zero3(nx, ny, nz)) {            // rare: no split tangent, split normal to the chord
+        nx = L.c.d.x;
+        ny = L.c.d.y;
+        nz = L.c.d.z;
+    }
+    const float qx = L.c.p.x + sp.dp.x, qy = L.c.p.y + sp.dp.y, qz = L.c.p.z + sp.dp.z;
+    const float cs = dot3(qx, qy, qz, nx, ny, nz);
+    const float tp = cs * rcp(nz);
+    sp.oblique = nz != 0.0f;
+    sp.nlo = L.lo;
+    sp.nhi = L.hi;
+    if (MODE == kConservative && L.slack >= 0.0f) {
+        // visit both halves unless the crossing is clearly outside [te, tx];
+        // narrow by the far side of tp's rounding bound
+        const float ep = plane_slack(qx, qy, qz, nx, ny, nz, tp);
+        sp.both = sp.oblique ? (te - ep < tp && tp < tx + ep)
+                             : (cs == 0.0f || fabsf(cs) <= L.slack * (fabsf(nx) + fabsf(ny)));
+        if (tp > te) sp.nhi = fminf(sp.nhi, tp + ep);
+        else         sp.nlo = fmaxf(sp.nlo, tp - ep);
+    } else {
+        sp.both = sp.oblique ? (te < tp && tp < tx) : cs == 0.0f;
+        if (tp > te) sp.nhi = fminf(sp.nhi, tp);
+        else         sp.nlo = fmaxf(sp.nlo, tp);
+    }
+    // a plane parallel to the ray leaves the whole ray on the side of sign(-cs)
+    sp.near_right = sp.oblique ? ((tp > te) != (nz > 0.0f)) : cs < 0.0f;
+}
+
+// Bookkeeping of a descent into the near half (Section 3.3: one level down,
+// the far half pending when the ray meets both).
+__device__ __forceinline__ void descend_state(Lane &L, const Split &sp)
+{
+    if (sp.oblique) { L.lo = sp.nlo; L.hi = sp.nhi; }
+    L.size >>= 1;
+    if (sp.both) {
+        L.bits ^= L.size;
+        if (kParentCache) L.cached = L.size;
+    }
+    if (sp.near_right) L.start ^= L.size;
+    L.splits++;
+}
+
 // Where a backtrack that misses the parent cache re-reads its pair's root:
 // the survivor table (two-kernel path) or the lane's own slot (one-kernel
 // path).
@@ -922,51 +979,17 @@ __device__ __forceinline__ int trip(Lane &L, const Root &root, float *col)
     }
     // Section 3.1 / 3.2: split plane through the centre, normal to the split
     // tangent; a descending lane goes to the half the ray meets first
-    V4 dp, tc;
-    split_terms(L.c, dp, tc);
-    float nx = tc.x, ny = tc.y, nz = tc.z;
-    if (zero3(nx, ny, nz)) {            // rare: no split tangent, split normal to the chord
-        nx = L.c.d.x;
-        ny = L.c.d.y;
-        nz = L.c.d.z;
-    }
-    const float qx = L.c.p.x + dp.x, qy = L.c.p.y + dp.y, qz = L.c.p.z + dp.z;
-    const float cs = dot3(qx, qy, qz, nx, ny, nz);
-    const float tp = cs * rcp(nz);
-    const bool oblique = nz != 0.0f;
-    bool both;
-    float nlo = L.lo, nhi = L.hi;
-    if (MODE == kConservative && L.slack >= 0.0f) {
-        // visit both halves unless the crossing is clearly outside [te, tx];
-        // narrow by the far side of tp's rounding bound
-        const float ep = plane_slack(qx, qy, qz, nx, ny, nz, tp);
-        both = oblique ? (te - ep < tp && tp < tx + ep)
-                       : (cs == 0.0f || fabsf(cs) <= L.slack * (fabsf(nx) + fabsf(ny)));
-        if (tp > te) nhi = fminf(nhi, tp + ep);
-        else         nlo = fmaxf(nlo, tp - ep);
-    } else {
-        both = oblique ? (te < tp && tp < tx) : cs == 0.0f;
-        if (tp > te) nhi = fminf(nhi, tp);
-        else         nlo = fmaxf(nlo, tp);
-    }
-    // a plane parallel to the ray leaves the whole ray on the side of sign(-cs)
-    const bool near_right = oblique ? ((tp > te) != (nz > 0.0f)) : cs < 0.0f;
+    Split sp;
+    split_plane<MODE>(L, te, tx, sp);
     const bool descend = vis && st == kGoOn;
-    if (kParentCache && descend && both) lds_put(col, L.c);
-    const bool right = back ? (L.start & L.size) != 0u : near_right;
-    take_child(L.c, dp, tc, right);
+    if (kParentCache && descend && sp.both) lds_put(col, L.c);
+    const bool right = back ? (L.start & L.size) != 0u : sp.near_right;
+    take_child(L.c, sp.dp, sp.tc, right);
     if (back) {
         cap_interval(L.c, L.tmax, L.lo, L.hi);
         L.backtracks++;
     } else if (descend) {
-        if (oblique) { L.lo = nlo; L.hi = nhi; }
-        L.size >>= 1;
-        if (both) {
-            L.bits ^= L.size;
-            if (kParentCache) L.cached = L.size;
-        }
-        if (near_right) L.start ^= L.size;
-        L.splits++;
+        descend_state(L, sp);
     }
     return st;
 }
@@ -1339,7 +1362,16 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
                             L.cached = 0;
                             L.fails = 0;
                             L.waiting = 0;
-                            L.trips = L.splits = L.backtracks = 0;
+                            L.trips = 1;                 // the root test above
+                            L.splits = L.backtracks = 0;
+                            // the root is visible and not a leaf: its first
+                            // split is taken here, as the trip would take it
+                            // (a trip would only repeat the root test)
+                            Split sp;
+                            split_plane<MODE>(L, te, tx, sp);
+                            if (kParentCache && sp.both) lds_put(col, L.c);
+                            take_child(L.c, sp.dp, sp.tc, sp.near_right);
+                            descend_state(L, sp);
                             active = true;
                         } else {
                             // decided at the root: a miss, or the root is the leaf
