@@ -68,8 +68,8 @@ extern "C" {
 
 /* Flags. */
 /* FI_FP64_REFINE: for pairs of depth > 16, run the traversal with every
- * pruning test enlarged by a bound on its FP32 rounding error and check each
- * leaf it reaches against the swept-disc solid in FP64 (see
+ * pruning test enlarged by a bound on its FP32 rounding error and, once it
+ * reaches a leaf, decide the pair against the swept-disc solid in FP64 (see
  * fiber_intersect_pairs). */
 #define FI_FP64_REFINE   (1u << 0)
 
@@ -115,13 +115,16 @@ const char *fi_strerror(int status);
  * a disc of radius r(u) centred on C(u) in the plane normal to C'(u), closed by
  * the end discs (Section 3.2: the limit surface maps the intersection to the
  * closest point on the curve). For each pair of depth > 16 the search runs
- * with every pruning test enlarged by a bound on its FP32 rounding, and every
- * leaf it reaches is checked in FP64: the first point of that solid along the
- * ray whose u lies in the leaf (boundary points from Newton's method on
- * <P - C(u), C'(u)> = 0, |P - C(u)| = r(u) and from bracketing, the end discs,
- * t = 0 for an origin inside). A leaf without one counts as missed and the
- * search goes on. All five outputs then describe the first such point (hit
- * decided in FP64; hit = 0, t = +inf when there is none). Pairs of depth
+ * with every pruning test enlarged by a bound on its FP32 rounding, so that
+ * no leaf holding part of that solid is pruned; a pair whose search reaches
+ * no leaf misses. Once it reaches a leaf, the pair is decided in FP64: the
+ * first point of that solid along the ray, t in [0, tmax), over the whole
+ * curve (boundary points from Newton's method on <P - C(u), C'(u)> = 0,
+ * |P - C(u)| = r(u) started at the FP32 leaf hit, from 128 samples of the
+ * disc excess with bisection at sign changes and golden-section search at
+ * local minima, the end discs, t = 0 for an origin inside). All five outputs
+ * then describe that point (hit decided in FP64; hit = 0, t = +inf when
+ * there is none). Pairs of depth
  * <= 16 keep the plain method's results; their t64/u64 are the float results
  * widened.
  *

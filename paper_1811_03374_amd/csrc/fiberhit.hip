@@ -299,17 +299,8 @@ struct Args {
 // in one of the leaf's discs. The smallest candidate in [0, tmax) is the hit.
 
 constexpr int kRefineAbove = 16;         // refine pairs of depth > 16
-constexpr int kLeafSamples = 16;         // phi samples over a leaf's u window (three leaves)
-#ifndef FIBERHIT_NEWTON_TOL
-#define FIBERHIT_NEWTON_TOL 1e-9
-#endif
-constexpr double kNewtonTol = FIBERHIT_NEWTON_TOL;   // relative residuals of an accepted boundary point
-#ifndef FIBERHIT_REFINE_FAILS
-#define FIBERHIT_REFINE_FAILS 1
-#endif
-constexpr int kRefineFails = FIBERHIT_REFINE_FAILS;   // leaves without the solid before the whole-curve search
+constexpr double kNewtonTol = 1e-9;      // relative residuals of an accepted Newton point
 constexpr int kCurveSamples = 128;       // phi samples over the whole curve (local minima are searched)
-constexpr int kRefineBatch = 16;         // parked lanes that trigger a wave's FP64 leaf checks
 
 struct Curve64 {
     double q[4][4];                      // control points in the FP64 ray frame (x, y, z, r)
@@ -610,10 +601,8 @@ struct Lane {
     uint32_t bits, start, size;   // Section 3.3: pending-sibling bits, integer interval
     uint32_t min_size;            // leaf size 2^(23 - depth)
     uint32_t cached;              // size of the pending children whose parent is cached (0: none)
-    int32_t fails;                // refinement: leaves reached that held no part of the solid
-    int32_t waiting;              // refinement: parked at a leaf until the wave checks its batch
-    uint32_t rbits;               //   pending bits to resume with if the leaf holds no solid
-    float ru, rtin, rtout;        //   the leaf's FP32 u and the ray interval it owns
+    int32_t waiting;              // refinement: parked at its first leaf until the wave decides it
+    float ru;                     //   the FP32 u of the leaf hit (Newton's start)
     int32_t row;                  // row of this pair in the survivor table
     int32_t pair;                 // index of the pair within its problem
     float slack;                  // conservative mode: bound on across-ray rounding of any node
@@ -787,39 +776,15 @@ __device__ __forceinline__ float leaf_u(const Lane &L)
     return fmaf(ul, (float)L.size * 0x1p-23f, (float)L.start * 0x1p-23f);
 }
 
-// FP64 check of a leaf reached by the conservative search (pair of depth
-// > 16): the earliest boundary point of the swept solid within the part of
-// the ray the leaf owns, [tin, tout] (the enlarged test's interval, widened
-// by 2^-20 of its size and of t), among discs with u up to one leaf beyond
-// the leaf on either side. Sets L.t64 / L.u64 and returns true when found.
-__device__ __noinline__ bool refine_at_leaf(Lane &L, const Table &tab, const Args &in)
-{
-    const float tin = L.rtin, tout = L.rtout;
-    const int64_t i = L.pair;
-    const int64_t ri = in.pair_ray ? (int64_t)in.pair_ray[i] : i;
-    const int64_t fi = in.pair_fiber ? (int64_t)in.pair_fiber[i] : i;
-    Curve64 cv;
-    if (!curve_in_ray_frame(in.rays + ri, in.ray_stride, in.fibers + fi, in.fiber_stride, cv)) return false;
-    const double w = (double)L.size * 0x1p-23;
-    const double ua = fmax(0.0, (double)L.start * 0x1p-23 - w);
-    const double ub = fmin(1.0, (double)(L.start + L.size) * 0x1p-23 + w);
-    const double t0 = tin, t1 = tout < INFINITY ? (double)tout : (double)L.tmax;
-    const double pad = ((t1 - t0) + fmax(fabs(t0), fabs(t1))) * 0x1p-20;
-    double t = INFINITY, u = __builtin_nan("");
-    leaf_candidates<kLeafSamples>(cv, ua, ub, fmax(0.0, t0 - pad), t1 + pad, (double)L.tmax, (double)L.t,
-                                  (double)L.ru, t, u);
-    if (!(t < INFINITY)) return false;
-    L.t64 = t;
-    L.u64 = u;
-    return true;
-}
-
-// Where many consecutive leaves are reached without holding the solid (a
-// curve that stalls at a zero end tangent keeps thousands of tiny end
-// cylinders around one point, all on the ray), the leaf-by-leaf check stops
-// after kRefineFails leaves and searches the whole curve once: the earliest
-// boundary point with t in [0, tmax), sampled at kCurveSamples parameters.
-__device__ __noinline__ bool refine_whole_curve(Lane &L, const Table &tab, const Args &in)
+// FP64 decision of a pair of depth > 16 once the conservative search reaches
+// its first leaf: the earliest boundary point of the swept solid along the
+// ray over the whole curve, t in [0, tmax), from kCurveSamples samples of the
+// disc excess (with the FP32 leaf hit as Newton's start). A leaf-local check
+// (three leaves around the FP32 hit, then the whole curve if it failed) was
+// measured first: at hair scale almost every leaf check failed (the FP32
+// leaf lies more than a leaf from the entry), so it only added work. Sets
+// L.t64 / L.u64 and returns true on a hit.
+__device__ __noinline__ bool refine_whole_curve(Lane &L, const Args &in)
 {
     const int64_t i = L.pair;
     const int64_t ri = in.pair_ray ? (int64_t)in.pair_ray[i] : i;
@@ -925,14 +890,11 @@ __device__ __forceinline__ int trip(Lane &L, const Root &root, float *col)
     bool vis = node_visible<MODE>(L.c, L.lo, L.hi, L.slack, te, tx, lo, hi);
     const bool leaf = L.size <= L.min_size;
     if (MODE == kConservative && vis && leaf && L.slack >= 0.0f) {
-        // refinement: park the lane at this leaf (empty interval, no pending
-        // sibling) until the wave checks a batch of leaves in FP64; the leaf's
-        // data and the pending bits are kept for that check
+        // refinement: the first leaf reached means the solid may be hit; park
+        // the lane (empty interval, no pending sibling) until the wave decides
+        // its parked pairs in FP64, keeping the leaf hit as Newton's start
         L.t = fmaxf(te, lo);
         L.ru = leaf_u(L);
-        L.rtin = L.t;
-        L.rtout = fminf(tx, hi);
-        L.rbits = L.bits;
         L.bits = 0;
         L.lo = INFINITY;
         L.hi = -INFINITY;
@@ -1191,7 +1153,6 @@ void k_traverse(Args a0, Table tab, const uint32_t *counts, int n_buckets, int r
                     L.start = 0;
                     L.size = kRootSize;
                     L.cached = 0;
-                    L.fails = 0;
                     L.waiting = 0;
                     L.slack = MODE == kConservative && depth > kRefineAbove ? root_slack(L.c) : -1.0f;
                     L.trips = L.splits = L.backtracks = 0;
@@ -1214,21 +1175,16 @@ void k_traverse(Args a0, Table tab, const uint32_t *counts, int n_buckets, int r
             active = false;
         }
         if constexpr (MODE == kConservative) {
-            // FP64 leaf checks run for a batch of parked lanes at once (SIMD
-            // lanes of one call), once 16 are parked or no other lane is busy
+            // the FP64 searches run for all parked lanes at once (SIMD lanes
+            // of one call) when no busy lane is left: every lane of the wave
+            // then shares the search's passes (measured: 2x faster on hair
+            // than batches of 16 parked lanes)
             const uint64_t parked = __ballot(L.waiting != 0);
-            if (parked != 0 && (__popcll(parked) >= kRefineBatch || __ballot(active && !L.waiting) == 0)) {
+            if (parked != 0 && __ballot(active && !L.waiting) == 0) {
                 if (L.waiting) {
                     L.waiting = 0;
-                    int done = refine_at_leaf(L, tab, a0) ? kHit : kGoOn;
-                    if (done == kGoOn && ++L.fails >= kRefineFails)
-                        done = refine_whole_curve(L, tab, a0) ? kHit : kMiss;
-                    if (done != kGoOn) {
-                        finish<MODE>(outs_of(a0), L.pair, L, done == kHit);
-                        active = false;
-                    } else {
-                        L.bits = L.rbits;          // the leaf holds no solid: go on past it
-                    }
+                    finish<MODE>(outs_of(a0), L.pair, L, refine_whole_curve(L, a0));
+                    active = false;
                 }
             }
         }
@@ -1360,7 +1316,6 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
                             L.pair = (int32_t)idx;
                             L.bits = 0;
                             L.cached = 0;
-                            L.fails = 0;
                             L.waiting = 0;
                             L.trips = 1;                 // the root test above
                             L.splits = L.backtracks = 0;
