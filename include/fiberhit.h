@@ -16,22 +16,17 @@
  * the legacy default stream); results are valid once the stream has
  * synchronised.
  *
- * A single call without FI_FP64_REFINE (fiber_intersect_pairs,
- * fiber_intersect_counts; fewer than 2^31 pairs) and a batched call run one
- * persistent kernel:
- * each wave takes an even share of the pairs and loads them into its free
- * lanes (load, FP64 move into the ray frame, root test; pairs decided at the
- * root are written out at once), keeping each busy lane's root in a slot of
- * its own (64 bytes). A refined call runs two kernels per chunk of 2^20
- * pairs: a setup kernel (one lane per pair, the same steps) and a persistent
- * traversal kernel over the survivors, which it reads from a survivor table
- * (81 bytes per row). For single calls the library owns two sets of
- * these buffers per device (each: a 2^20-row table, 81 MiB, and the root
- * slots, 4 KiB per resident wave, about 24 MiB), allocated at the first call
- * on that device and kept for the process; calls that share a set are
- * ordered on the GPU through an event, so calls on different streams stay
- * correct. When a single call gathers fibers through pair_fiber with at least
- * as many pairs as fibers, the fibers are first copied to 64-byte records (one
+ * Every call (and every batch) runs one persistent kernel: each 64-lane wave
+ * takes an even share of the pairs and loads them into its free lanes (load,
+ * FP64 move into the ray frame, root test; pairs decided at the root are
+ * written out at once), keeping each busy lane's root in a slot of its own
+ * (64 bytes) for the subdivision search. For single calls the library owns
+ * two sets of buffers per device (root slots, 4 KiB per resident wave, about
+ * 24 MiB on MI355X; fiber records, below), allocated at the first call on
+ * that device and kept for the process; calls that share a set are ordered on
+ * the GPU through an event, so calls on different streams stay correct. When
+ * a single call gathers fibers through pair_fiber with at least as many
+ * pairs as fibers, the fibers are first copied to 64-byte records (one
  * gathered fiber is then one or two cache lines instead of sixteen), in a
  * per-set buffer that grows to the largest such call (up to 1 GiB; beyond
  * that the gather reads the rows directly). Batched calls keep their root
@@ -131,7 +126,8 @@ const char *fi_strerror(int status);
  * Errors: FI_ERR_NULL when rays, fibers or an output is NULL with n_pairs > 0
  * (t64_out/u64_out only with FI_FP64_REFINE); FI_ERR_RANGE for negative
  * counts, strides below the counts, a depth outside [0, 23], unknown flags,
- * an identity pairing longer than a table, or n_pairs >= 2^31 - 64;
+ * an identity pairing longer than its ray or fiber table, or
+ * n_pairs >= 2^31 - 64;
  * FI_ERR_HIP when the launch fails or the first call on a device cannot
  * allocate its buffers. Nothing is enqueued on an argument error.
  */

@@ -247,8 +247,8 @@ def workspace_for(problems, device=None):
 
 
 def intersect_batched(problems, tuning=None, workspace=None, stream=None):
-    """All pairs of all problems in one setup and one persistent traversal
-    launch per chunk (results land in each Problem's t, u, hit)."""
+    """All pairs of all problems in one persistent-kernel launch (results
+    land in each Problem's t, u, hit)."""
     L = _batched_lib()
     arr = _scene_array(problems)
     if workspace is None:

@@ -47,20 +47,17 @@ constexpr float kParallelG = 1e-30f;          // axis treated as parallel to the
 #define FIBERHIT_PARENT_CACHE 1
 #endif
 constexpr bool kParentCache = FIBERHIT_PARENT_CACHE != 0;   // cache the latest both-hit parent in LDS
-#ifndef FIBERHIT_FUSED
-#define FIBERHIT_FUSED 1                           // single calls: one kernel, no survivor table
-#endif
 #ifndef FIBERHIT_FUSED_ROUNDS
 #define FIBERHIT_FUSED_ROUNDS 1                    // refill batches per trip of the one-kernel path
 #endif
 #ifndef FIBERHIT_FUSED_REFILL
 #define FIBERHIT_FUSED_REFILL 48                   // free lanes that trigger a one-kernel refill
 #endif
+#ifndef FIBERHIT_REFINE_REFILL
+#define FIBERHIT_REFINE_REFILL 8                   // the same for refined calls (parked lanes wait for the others)
+#endif
 #ifndef FIBERHIT_FUSED_WAVES
 #define FIBERHIT_FUSED_WAVES 6                     // register budget of the one-kernel path (waves per SIMD)
-#endif
-#ifndef FIBERHIT_TRAVERSE_WAVES
-#define FIBERHIT_TRAVERSE_WAVES 8                  // traversal waves per SIMD the register budget must allow
 #endif
 
 struct V4 { float x, y, z, w; };
@@ -118,47 +115,6 @@ __device__ __forceinline__ void make_onb(double wx, double wy, double wz,
     v[2] = -wy;
 }
 
-// Root node of one pair in the ray frame, in the {p, d, t0, t1} form.
-// The projection runs once per pair in FP64 (full rate on this chip): the
-// differences of the float32 control points and of the origin are exact in
-// double, so p is the rounded frame position of p0 and d, t0, t1 are the
-// rounded frame images of p3-p0, p1-p0, p3-p2 -- each component accurate to
-// its own float32 ulp, including the tiny across-ray or along-ray parts of
-// nearly parallel or nearly perpendicular tangents. Returns false for a zero
-// or non-finite direction.
-__device__ __forceinline__ bool root_in_ray_frame(const float *R, int64_t rs, const float *F,
-                                                  int64_t fs, Node &root)
-{
-    const double ox = R[0], oy = R[rs], oz = R[2 * rs];
-    const double dx = R[3 * rs], dy = R[4 * rs], dz = R[5 * rs];
-    const double n2 = fma(dx, dx, fma(dy, dy, dz * dz));
-    if (!(n2 > 0.0) || !(n2 < INFINITY)) return false;
-    const double il = rsqrt64(n2);
-    const double w[3] = {dx * il, dy * il, dz * il};
-    double u[3], v[3];
-    make_onb(w[0], w[1], w[2], u, v);
-
-    double P[4][4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) P[k][c] = F[(4 * k + c) * fs];
-
-    auto proj = [&](double ex, double ey, double ez, double ew) {
-        V4 q;
-        q.x = (float)fma(ex, u[0], fma(ey, u[1], ez * u[2]));
-        q.y = (float)fma(ex, v[0], fma(ey, v[1], ez * v[2]));
-        q.z = (float)fma(ex, w[0], fma(ey, w[1], ez * w[2]));
-        q.w = (float)ew;
-        return q;
-    };
-    root.p = proj(P[0][0] - ox, P[0][1] - oy, P[0][2] - oz, P[0][3]);
-    root.d = proj(P[3][0] - P[0][0], P[3][1] - P[0][1], P[3][2] - P[0][2], P[3][3] - P[0][3]);
-    root.t0 = proj(P[1][0] - P[0][0], P[1][1] - P[0][1], P[1][2] - P[0][2], P[1][3] - P[0][3]);
-    root.t1 = proj(P[3][0] - P[2][0], P[3][1] - P[2][1], P[3][2] - P[2][2], P[3][3] - P[2][3]);
-    return isfinite(root.p.x) && isfinite(root.p.y) && isfinite(root.p.z) &&
-           isfinite(root.d.x) && isfinite(root.d.y) && isfinite(root.d.z);
-}
 
 // ---------------------------------------------------------------------------
 // Node geometry
@@ -603,7 +559,7 @@ struct Lane {
     uint32_t cached;              // size of the pending children whose parent is cached (0: none)
     int32_t waiting;              // refinement: parked at its first leaf until the wave decides it
     float ru;                     //   the FP32 u of the leaf hit (Newton's start)
-    int32_t row;                  // row of this pair in the survivor table
+    int32_t scene;                // batched: the problem this pair belongs to
     int32_t pair;                 // index of the pair within its problem
     float slack;                  // conservative mode: bound on across-ray rounding of any node
                                   // (negative: a pair of depth <= 16, searched by the plain rules)
@@ -620,28 +576,6 @@ enum { kGoOn = 0, kHit = 1, kMiss = 2 };
 // surface point within that error is pruned; FP64 then decides).
 enum { kPlain = 0, kCount = 1, kConservative = 2 };
 
-// ---------------------------------------------------------------------------
-// Survivor table
-// ---------------------------------------------------------------------------
-//
-// A refined call (and, with a compile-time switch, any single call) is split
-// in two kernels. The setup kernel (one lane per pair, no persistence) loads a
-// pair, moves it into the ray frame in FP64 and tests the root cylinder; a
-// pair that misses its root (or is decided at the root, depth 0) is written
-// out at once, every other pair is appended to this table: its root node, cap
-// interval and tmax, in structure-of-arrays rows so that the traversal
-// kernel's refills are coalesced loads. The traversal kernel then never holds
-// FP64 state, which keeps its register count low. The one-kernel path
-// (k_fused) does the setup steps in its lane refill instead and needs no table.
-constexpr int kTableFloats = 19;              // node (16), lo, hi, tmax
-
-struct Table {
-    float *f;                                 // kTableFloats rows of cap floats
-    int32_t *pair;                            // pair index within its problem
-    uint8_t *depth;                           // subdivision depth of the pair
-    int32_t cap;                              // rows (at most 2^20)
-};
-
 // Output arrays of one problem (what the kernels write).
 struct Outs {
     float *t;
@@ -657,38 +591,11 @@ __host__ __device__ __forceinline__ Outs outs_of(const Args &a)
     return Outs{a.t_out, a.u_out, a.hit_out, a.counts, a.t64_out, a.u64_out};
 }
 
-__device__ __forceinline__ void table_put(const Table &tab, int32_t row, const Node &r, float lo, float hi,
-                                          float tmax, int32_t pair, uint32_t depth)
-{
-    const float *f = &r.p.x;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) tab.f[k * tab.cap + row] = f[k];
-    tab.f[16 * tab.cap + row] = lo;
-    tab.f[17 * tab.cap + row] = hi;
-    tab.f[18 * tab.cap + row] = tmax;
-    tab.pair[row] = pair;
-    tab.depth[row] = (uint8_t)depth;
-}
-
-// Element `row` of table row k: a wave-uniform row base plus a 32-bit byte
-// offset, so each load needs no per-lane 64-bit address arithmetic.
-__device__ __forceinline__ float table_at(const Table &tab, int k, uint32_t row)
-{
-    const char *base = (const char *)(tab.f + (size_t)k * (uint32_t)tab.cap);
-    return *(const float *)(base + row * 4u);
-}
-
-__device__ __forceinline__ void table_root(const Table &tab, int32_t row, Node &r)
-{
-    float *f = &r.p.x;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) f[k] = table_at(tab, k, (uint32_t)row);
-}
-
 // Per-lane LDS column (conflict-free: lane-contiguous rows of 64 floats) that
 // caches the parent of the most recent split that left a sibling pending, so
 // that the usual backtrack (to that sibling) rebuilds it with one split. Other
-// backtracks replay the split rules from the root, re-read from the table.
+// backtracks replay the split rules from the root, re-read from the lane's
+// root slot.
 __device__ __forceinline__ void lds_put(float *col, const Node &r)
 {
     const float *f = &r.p.x;
@@ -703,24 +610,6 @@ __device__ __forceinline__ void lds_get(const float *col, Node &r)
     for (int k = 0; k < 16; ++k) f[k] = col[k * kWave];
 }
 
-// Load pair i and move it into the ray frame. False when the pair is a
-// definite miss (bad index, depth, direction or tmax).
-// `aos`, when given, holds the fibers as 16 consecutive floats each (see
-// k_fibers_aos): a gathered fiber is then one or two cache lines instead of
-// one line per coordinate row.
-__device__ __forceinline__ bool load_pair(const Args &a, int64_t i, Node &root, float &tmax, uint32_t &depth,
-                                          const float *aos)
-{
-    const int64_t ri = a.pair_ray ? (int64_t)a.pair_ray[i] : i;
-    const int64_t fi = a.pair_fiber ? (int64_t)a.pair_fiber[i] : i;
-    depth = a.pair_depth ? (uint32_t)a.pair_depth[i] : (uint32_t)a.depth;
-    if (ri < 0 || ri >= a.n_rays || fi < 0 || fi >= a.n_fibers || depth > FI_MAX_DEPTH) return false;
-    const float *R = a.rays + ri;
-    tmax = R[6 * a.ray_stride];
-    if (!(tmax == tmax)) return false;
-    if (aos) return root_in_ray_frame(R, a.ray_stride, aos + 16 * fi, 1, root);
-    return root_in_ray_frame(R, a.ray_stride, a.fibers + fi, a.fiber_stride, root);
-}
 
 // Each split rounds a node's position at the magnitude of its partial sum,
 // which starts at the root's across-ray extent, so deep nodes inherit errors
@@ -865,14 +754,7 @@ __device__ __forceinline__ void descend_state(Lane &L, const Split &sp)
     L.splits++;
 }
 
-// Where a backtrack that misses the parent cache re-reads its pair's root:
-// the survivor table (two-kernel path) or the lane's own slot (one-kernel
-// path).
-struct TableRoot {
-    Table tab;
-    __device__ __forceinline__ void get(const Lane &L, Node &n) const { table_root(tab, L.row, n); }
-};
-
+// Where a backtrack that misses the parent cache re-reads its pair's root.
 struct SlotRoot {
     const float *slot;                        // this lane's root: 16 floats, one wave apart
     __device__ __forceinline__ void get(const Lane &, Node &n) const
@@ -1030,177 +912,21 @@ __device__ __forceinline__ int find_scene(const int64_t *offsets, int n_scenes, 
     return lo;
 }
 
-// Survivor rows are grouped in kBuckets buckets of cap / kBuckets rows each:
-// setup block k appends its survivors to bucket k mod kBuckets with one
-// atomic on that bucket's counter. Spreading the appends over many counters
-// matters on this chip: device-scope atomics on one address serialise across
-// all eight XCDs. Traversal wave w drains an even share of bucket
-// w mod n_buckets with no atomics at all. Two sets of counters alternate
-// between consecutive chunks: the setup kernel of a chunk zeroes the set the
-// previous chunk used, so no reset kernel is needed between chunks.
-constexpr int kSetupBlock = 256;
-constexpr int kBuckets = 256;                 // equal to kSetupBlock: block 0 zeroes one counter per thread
-static_assert(kBuckets == kSetupBlock, "setup block 0 clears one counter per thread");
-constexpr int kCounterWords = 2 * kBuckets;   // two sets
-
-// Setup kernel: pairs [begin, begin + count) of the call, one lane each.
-template <int MODE>
-__global__ __launch_bounds__(kSetupBlock) void k_setup(Args a, int64_t begin, int64_t count, Table tab,
-                                                      uint32_t *counts, uint32_t *stale, const float *aos)
-{
-    __shared__ uint32_t s_wave[kSetupBlock / kWave];
-    __shared__ uint32_t s_base;
-    if (blockIdx.x == 0) stale[threadIdx.x] = 0u;     // counters of the previous chunk
-    const int64_t k = (int64_t)blockIdx.x * kSetupBlock + threadIdx.x;
-    bool keep = false;
-    Node root;
-    float lo = 0.0f, hi = 0.0f, tmax = 0.0f;
-    uint32_t depth = 0;
-    int64_t idx = 0;
-    if (k < count) {
-        idx = begin + k;
-        if (!load_pair(a, idx, root, tmax, depth, aos)) {
-            finish_invalid<MODE>(a, idx);
-        } else {
-            cap_interval(root, tmax, lo, hi);
-            float te, tx, lu, hu;
-            const float slack = MODE == kConservative && depth > kRefineAbove ? root_slack(root) : -1.0f;
-            const bool vis = node_visible<MODE>(root, lo, hi, slack, te, tx, lu, hu);
-            if (vis && depth > 0) {
-                keep = true;
-            } else {
-                // decided at the root: a miss, or the root is the leaf
-                Lane L;
-                L.c = root;
-                L.slack = slack;
-                L.t = fmaxf(te, lu);
-                L.tmax = tmax;
-                L.start = 0;
-                L.size = kRootSize;
-                L.u = leaf_u(L);
-                L.level = 0;
-                L.trips = 1;
-                L.splits = 0;
-                L.backtracks = 0;
-                finish<MODE>(outs_of(a), idx, L, vis);
-            }
-        }
-    }
-    // append the block's survivors to its bucket: one atomic per block
-    const uint64_t m = __ballot(keep);
-    const int wave = threadIdx.x / kWave;
-    if ((threadIdx.x & (kWave - 1)) == 0) s_wave[wave] = (uint32_t)__popcll(m);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t n = 0;
-        for (int w = 0; w < kSetupBlock / kWave; ++w) n += s_wave[w];
-        s_base = n ? atomicAdd(&counts[blockIdx.x % kBuckets], n) : 0u;
-    }
-    __syncthreads();
-    if (keep) {
-        uint32_t off = s_base + lanes_below(m);
-        for (int w = 0; w < wave; ++w) off += s_wave[w];
-        const int32_t bucket_rows = tab.cap / kBuckets;
-        table_put(tab, (int32_t)(blockIdx.x % kBuckets) * bucket_rows + (int32_t)off, root, lo, hi, tmax,
-                  (int32_t)idx, depth);
-    }
-}
-
-// Traversal kernel: each 64-lane wave drains an even share of one bucket and
-// refills finished lanes in batches, so lanes of uneven trip counts keep the
-// SIMD busy instead of idling until the slowest lane of a fixed batch
-// finishes. The attribute sets the register budget: 64 VGPRs (eight waves
-// per SIMD, the most gfx950 runs) hold the plain traversal without spills;
-// the counting and conservative variants get 80 (six waves).
-template <int MODE>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MODE == kPlain ? FIBERHIT_TRAVERSE_WAVES : MODE == kCount ? 6 : 4, 8)))
-void k_traverse(Args a0, Table tab, const uint32_t *counts, int n_buckets, int refill)
-{
-    __shared__ float s_cache[(kParentCache ? 16 : 1) * kWave];
-    const int lane = threadIdx.x;
-    float *col = s_cache + lane;
-    const int b = (int)(blockIdx.x % (unsigned)n_buckets);
-    const int j = (int)(blockIdx.x / (unsigned)n_buckets);
-    const int waves = (int)((gridDim.x - (unsigned)b + (unsigned)n_buckets - 1) / (unsigned)n_buckets);
-    const int rows = (int)counts[b];
-    const int share = (rows + waves - 1) / waves;
-    const int first = b * (tab.cap / kBuckets);
-    int next = first + (j * share < rows ? j * share : rows);          // wave-uniform range
-    const int end = first + ((j + 1) * share < rows ? (j + 1) * share : rows);
-    Lane L = {};
-    L.lo = INFINITY;                                                   // parked: see below
-    L.hi = -INFINITY;
-    bool active = false;
-    for (;;) {
-        const uint64_t free_mask = __ballot(!active);
-        const int n_free = __popcll(free_mask);
-        if (next < end && (n_free >= refill || n_free == kWave)) {
-            const int avail = end - next;
-            const int take = avail < n_free ? avail : n_free;
-            if (!active) {
-                const int rank = (int)lanes_below(free_mask);
-                if (rank < take) {
-                    const int r = next + rank;
-                    table_root(tab, r, L.c);
-                    L.lo = table_at(tab, 16, (uint32_t)r);
-                    L.hi = table_at(tab, 17, (uint32_t)r);
-                    L.tmax = table_at(tab, 18, (uint32_t)r);
-                    const uint32_t depth = tab.depth[r];
-                    L.min_size = kRootSize >> depth;
-                    L.row = r;
-                    L.pair = tab.pair[r];
-                    L.bits = 0;
-                    L.start = 0;
-                    L.size = kRootSize;
-                    L.cached = 0;
-                    L.waiting = 0;
-                    L.slack = MODE == kConservative && depth > kRefineAbove ? root_slack(L.c) : -1.0f;
-                    L.trips = L.splits = L.backtracks = 0;
-                    active = true;
-                }
-            }
-            next += take;
-        }
-        // a wave with every lane free refills all of them, so an all-idle
-        // wave here has no rows left
-        if (__ballot(active) == 0) break;
-        // every lane runs the trip: an idle lane is parked with an empty
-        // interval and no pending sibling, so its test fails and it leaves at
-        // the first check, never taking the backtrack or descent paths; the
-        // compiler then keeps one copy of the lane state instead of merging
-        // active and idle ones
-        const int st = trip<MODE>(L, TableRoot{tab}, col);
-        if (active && st != kGoOn && !(MODE == kConservative && L.waiting)) {
-            finish<MODE>(outs_of(a0), L.pair, L, st == kHit);
-            active = false;
-        }
-        if constexpr (MODE == kConservative) {
-            // the FP64 searches run for all parked lanes at once (SIMD lanes
-            // of one call) when no busy lane is left: every lane of the wave
-            // then shares the search's passes (measured: 2x faster on hair
-            // than batches of 16 parked lanes)
-            const uint64_t parked = __ballot(L.waiting != 0);
-            if (parked != 0 && __ballot(active && !L.waiting) == 0) {
-                if (L.waiting) {
-                    L.waiting = 0;
-                    finish<MODE>(outs_of(a0), L.pair, L, refine_whole_curve(L, a0));
-                    active = false;
-                }
-            }
-        }
-        if (!active) {
-            L.lo = INFINITY;
-            L.hi = -INFINITY;
-            L.bits = 0;
-        }
-    }
-}
-
-// load_pair with the frame projection ordered for few live registers (one
-// control point at a time; the one-kernel path runs it while the busy lanes'
-// state stays live). Same arithmetic as root_in_ray_frame, same results.
-__device__ __forceinline__ bool load_pair_lean(const Args &a, int64_t i, Node &root, float &tmax, uint32_t &depth,
-                                               const float *aos)
+// Load pair i and move it into the ray frame: the root node in the
+// {p, d, t0, t1} form (Section 3.1). False when the pair is a definite miss
+// (bad index, depth, direction or tmax).
+// The projection runs once per pair in FP64 (full rate on this chip): the
+// differences of the float32 control points and of the origin are exact in
+// double, so p is the rounded frame position of p0 and d, t0, t1 are the
+// rounded frame images of p3-p0, p1-p0, p3-p2 -- each component accurate to
+// its own float32 ulp, including the tiny across-ray or along-ray parts of
+// nearly parallel or nearly perpendicular tangents. It goes one control point
+// at a time so that it fits beside the busy lanes' state in the refill.
+// `aos`, when given, holds the fibers as 16 consecutive floats each (see
+// k_fibers_aos): a gathered fiber is then one or two cache lines instead of
+// one line per coordinate row.
+__device__ __forceinline__ bool load_pair(const Args &a, int64_t i, Node &root, float &tmax, uint32_t &depth,
+                                          const float *aos)
 {
     const int64_t ri = a.pair_ray ? (int64_t)a.pair_ray[i] : i;
     const int64_t fi = a.pair_fiber ? (int64_t)a.pair_fiber[i] : i;
@@ -1238,19 +964,22 @@ __device__ __forceinline__ bool load_pair_lean(const Args &a, int64_t i, Node &r
            isfinite(root.d.x) && isfinite(root.d.y) && isfinite(root.d.z);
 }
 
-// One-kernel path for single calls (plain and counting variants): each
-// persistent wave takes an even share of the call's pairs and loads them
-// straight into its free lanes -- pair fetch, FP64 frame and root test in the
-// refill, as the setup kernel does -- so no survivor table is written or read.
-// A lane that survives its root test keeps the root in its own slot (16
-// floats, a wave's lanes side by side) for the backtracks that miss the
-// parent cache; pairs decided at the root are written out during the refill,
-// which takes up to kFusedRounds batches of pairs per trip so that lanes freed
-// by root misses are refilled at once.
+// The kernel of every call: each persistent 64-lane wave takes an even share
+// of the call's pairs (of the whole scene table for a batch) and loads them
+// straight into its free lanes once `refill` lanes are free -- pair fetch,
+// FP64 move into the ray frame, root test and the root's first split in the
+// refill -- so that lanes of uneven trip counts keep the SIMD busy instead of
+// idling until the slowest lane of a fixed batch finishes. A lane that
+// survives its root test keeps the root in its own slot (16 floats, a wave's
+// lanes side by side) for the backtracks that miss the parent cache; pairs
+// decided at the root are written out during the refill, which takes up to
+// kFusedRounds batches of pairs per trip. The attribute sets the register
+// budget: the plain variant fits 6 waves per SIMD, counting 5, the refining
+// variant (FP64 search called as a function) 4.
 constexpr int kFusedRounds = FIBERHIT_FUSED_ROUNDS;
 
 template <int MODE, bool BATCHED>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MODE == kPlain ? FIBERHIT_FUSED_WAVES : 5, 8)))
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MODE == kPlain ? FIBERHIT_FUSED_WAVES : MODE == kCount ? 5 : 4, 8)))
 void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, int64_t count, float *slots,
              int refill, const float *aos)
 {
@@ -1272,7 +1001,7 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
         cur = outs_of(scenes[scene0]);
     }
     Lane L = {};
-    L.lo = INFINITY;                                                   // parked, as in k_traverse
+    L.lo = INFINITY;                                                   // an empty interval: no work
     L.hi = -INFINITY;
     bool active = false;
     for (;;) {
@@ -1292,10 +1021,10 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
                         while (sc + 1 < n_scenes && offsets[sc + 1] <= idx) ++sc;
                         idx -= offsets[sc];
                         a = scenes[sc];
-                        L.row = sc;                // the lane's scene (no table row here)
+                        L.scene = sc;
                     }
                     uint32_t depth = 0;
-                    if (!load_pair_lean(a, idx, L.c, L.tmax, depth, aos)) {
+                    if (!load_pair(a, idx, L.c, L.tmax, depth, aos)) {
                         finish_invalid<MODE>(a, idx);
                         L.lo = INFINITY;
                         L.hi = -INFINITY;
@@ -1357,17 +1086,31 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
             continue;
         }
         const int st = trip<MODE>(L, root, col);
-        if (active && st != kGoOn) {
+        if (active && st != kGoOn && !(MODE == kConservative && L.waiting)) {
             if constexpr (BATCHED) {
                 // lanes of the wave's current scene write through its
                 // uniform output pointers; others (a scene boundary inside
                 // the wave) load their scene's
-                if (L.row == scene0) finish<MODE>(cur, L.pair, L, st == kHit);
-                else finish<MODE>(outs_of(scenes[L.row]), L.pair, L, st == kHit);
+                if (L.scene == scene0) finish<MODE>(cur, L.pair, L, st == kHit);
+                else finish<MODE>(outs_of(scenes[L.scene]), L.pair, L, st == kHit);
             } else {
                 finish<MODE>(outs_of(a0), L.pair, L, st == kHit);
             }
             active = false;
+        }
+        if constexpr (MODE == kConservative && !BATCHED) {
+            // the FP64 searches run for all parked lanes at once (SIMD lanes
+            // of one call) when no busy lane is left: every lane of the wave
+            // then shares the search's passes (measured: 2x faster on hair
+            // than batches of 16 parked lanes)
+            const uint64_t parked = __ballot(L.waiting != 0);
+            if (parked != 0 && __ballot(active && !L.waiting) == 0) {
+                if (L.waiting) {
+                    L.waiting = 0;
+                    finish<MODE>(outs_of(a0), L.pair, L, refine_whole_curve(L, a0));
+                    active = false;
+                }
+            }
         }
         if (!active) {
             L.lo = INFINITY;
@@ -1404,64 +1147,28 @@ int check_common(const float *rays, int64_t ray_stride, int64_t n_rays,
     if (ray_stride < n_rays || fiber_stride < n_fibers) return FI_ERR_RANGE;
     if (!pair_ray && n_pairs > n_rays) return FI_ERR_RANGE;
     if (!pair_fiber && n_pairs > n_fibers) return FI_ERR_RANGE;
-    if (n_pairs > (int64_t)0x7fffffff - 64) return FI_ERR_RANGE;   // int32 pair indices in the table
+    if (n_pairs > (int64_t)0x7fffffff - 64) return FI_ERR_RANGE;   // int32 pair indices in the lanes
     return FI_OK;
 }
 
 // ---------------------------------------------------------------------------
-// Kernel variants, counters, survivor tables and launch shape
+// Kernel variants and per-device state
 // ---------------------------------------------------------------------------
 
-using SetupFn = void (*)(Args, int64_t, int64_t, Table, uint32_t *, uint32_t *, const float *);
-using TraverseFn = void (*)(Args, Table, const uint32_t *, int, int);
-
-// [mode]: plain, counting, conservative
-const SetupFn kSetup[3] = {k_setup<kPlain>, k_setup<kCount>, k_setup<kConservative>};
 using FusedFn = void (*)(Args, const Args *, const int64_t *, int, int64_t, float *, int, const float *);
-// [0] plain, [1] counting (single calls), [2] plain over a scene table
-const FusedFn kFused[3] = {k_fused<kPlain, false>, k_fused<kCount, false>, k_fused<kPlain, true>};
-
-const TraverseFn kTraverse[3] = {k_traverse<kPlain>, k_traverse<kCount>, k_traverse<kConservative>};
-
-// Pairs per chunk: the setup kernel covers at most this many pairs before the
-// traversal kernel drains their survivors. Table sizes are multiples of
-// kBuckets * kSetupBlock rows, so that every setup block's survivors fit its
-// bucket (a bucket holds rows of at most cap / (kBuckets * kSetupBlock)
-// blocks of kSetupBlock pairs each).
-constexpr int64_t kTableQuantum = (int64_t)kBuckets * kSetupBlock;
-constexpr int64_t kChunkRows = 1 << 20;         // single-problem calls: tables the library owns
-static_assert(kChunkRows % kTableQuantum == 0, "chunk must be a whole number of table quanta");
+// [0] plain, [1] counting, [2] conservative (single calls), [3] plain over a
+// scene table
+const FusedFn kFused[4] = {k_fused<kPlain, false>, k_fused<kCount, false>, k_fused<kConservative, false>,
+                           k_fused<kPlain, true>};
+constexpr int kBatchedVariant = 3;
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Bytes of a survivor table of `rows` rows, and its layout at `base`.
-size_t table_region_bytes(int64_t rows)
-{
-    return align256((size_t)rows * kTableFloats * sizeof(float)) + align256((size_t)rows * sizeof(int32_t)) +
-           align256((size_t)rows);
-}
-
-Table table_at(void *base, int64_t rows)
-{
-    char *p = (char *)base;
-    Table t;
-    t.cap = (int32_t)rows;
-    t.f = (float *)p;
-    p += align256((size_t)rows * kTableFloats * sizeof(float));
-    t.pair = (int32_t *)p;
-    p += align256((size_t)rows * sizeof(int32_t));
-    t.depth = (uint8_t *)p;
-    return t;
-}
-
-
-// Single-problem calls keep kRegions sets of buffers per device (survivor
-// table, root slots, fiber records), allocated at the first call that needs
-// one and used round-robin; a call waits on its stream (through an event) for
-// the previous call that used its set. The tables' bucket counters live in a
-// file-scope device array, zero at load.
+// Single-problem calls keep kRegions sets of buffers per device (root slots,
+// fiber records), allocated at the first call that needs one and used
+// round-robin; a call waits on its stream (through an event) for the
+// previous call that used its set.
 constexpr int kRegions = 2;
-__device__ __align__(256) uint32_t g_counters[kRegions * kCounterWords];
 
 constexpr int kMaxDevices = 64;
 constexpr int kStageSlots = 4;                 // pinned staging for batched scene tables
@@ -1469,12 +1176,9 @@ constexpr size_t kStageBytes = 1u << 20;
 
 struct Region {
     std::mutex m;
-    void *mem;                                 // survivor table of kChunkRows rows
-    float *slots;                              // root slots of the one-kernel path (resident waves x 4 KB)
+    float *slots;                              // root slots (resident waves x 4 KB)
     float *aos;                                // fibers as 16-float records (gathered calls)
     size_t aos_bytes;
-    uint32_t *counters;                        // two sets of kBuckets counters
-    int parity;                                // the set that is zero for the next chunk
     hipEvent_t done;                           // recorded after the last call that used it
     bool pending;
 };
@@ -1482,8 +1186,7 @@ struct Region {
 struct DeviceInfo {
     std::atomic<bool> ready;
     int cus;
-    int resident[3];                           // resident traversal waves per CU, per variant
-    int fused_resident[3];                     // resident one-kernel waves per CU (as kFused)
+    int fused_resident[4];                     // resident waves per CU, per variant (as kFused)
     Region region[kRegions];
     std::atomic<uint32_t> next_region;
     std::mutex stage_mutex;
@@ -1508,29 +1211,18 @@ int device_info(DeviceInfo *&out)
     if (!d.ready.load(std::memory_order_acquire)) {
         std::lock_guard<std::mutex> lock(g_dev_mutex);
         if (!d.ready.load(std::memory_order_relaxed)) {
-            void *p = nullptr;
-            if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_counters)) != hipSuccess || !p) return FI_ERR_HIP;
             if (hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
                 return FI_ERR_HIP;
-            for (int m = 0; m < 3; ++m) {
-                int nb = 0;
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)kTraverse[m], kWave, 0) != hipSuccess)
-                    return FI_ERR_HIP;
-                d.resident[m] = nb > 0 ? nb : 1;
-            }
-            for (int m = 0; m < 3; ++m) {
+            for (int m = 0; m < 4; ++m) {
                 int nb = 0;
                 if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)kFused[m], kWave, 0) != hipSuccess)
                     return FI_ERR_HIP;
                 d.fused_resident[m] = nb > 0 ? nb : 1;
             }
             for (int r = 0; r < kRegions; ++r) {
-                d.region[r].mem = nullptr;
                 d.region[r].aos = nullptr;
                 d.region[r].aos_bytes = 0;
                 d.region[r].slots = nullptr;
-                d.region[r].counters = (uint32_t *)p + r * kCounterWords;
-                d.region[r].parity = 0;
                 d.region[r].done = nullptr;
                 d.region[r].pending = false;
             }
@@ -1545,9 +1237,6 @@ int device_info(DeviceInfo *&out)
 
 // Launch defaults of single-problem calls (and of batches without a tuned
 // entry); measured choices, overridable when building.
-#ifndef FIBERHIT_TABLE_REFILL
-#define FIBERHIT_TABLE_REFILL 8                    // free lanes that trigger a survivor-table refill
-#endif
 #ifndef FIBERHIT_DEFAULT_REFILL
 #define FIBERHIT_DEFAULT_REFILL 48
 #endif
@@ -1604,40 +1293,6 @@ int check_tuning(const fi_tuning &t)
     return FI_OK;
 }
 
-// Traversal grid for a chunk of `count` pairs: about one wave per 64 pairs, at
-// most the resident waves, and a whole number of waves per used bucket.
-unsigned traverse_grid(const DeviceInfo &d, int mode, const fi_tuning &t, int64_t count, int n_buckets)
-{
-    int per_cu = d.resident[mode];
-    if (t.waves_per_simd > 0 && 4 * t.waves_per_simd < per_cu) per_cu = 4 * t.waves_per_simd;
-    const int64_t resident = (int64_t)per_cu * d.cus;
-    int64_t g = (count + kWave - 1) / kWave;
-    if (g > resident) g = resident;
-    g = (g + n_buckets - 1) / n_buckets * n_buckets;
-    return (unsigned)g;
-}
-
-// Enqueue setup + traversal for `total` pairs, chunk by chunk through `tab`.
-// counters[parity * kBuckets ..] must be zero; returns the set that is zero
-// after the last chunk.
-int launch_chain(const DeviceInfo &d, int mode, const fi_tuning &t, const Args &a0, int64_t total,
-                 const Table &tab, uint32_t *counters, int parity, hipStream_t s, const float *aos)
-{
-    for (int64_t begin = 0; begin < total; begin += tab.cap) {
-        const int64_t count = total - begin < tab.cap ? total - begin : tab.cap;
-        const int64_t blocks = (count + kSetupBlock - 1) / kSetupBlock;
-        const int n_buckets = blocks < kBuckets ? (int)blocks : kBuckets;
-        uint32_t *cur = counters + parity * kBuckets;
-        uint32_t *other = counters + (1 - parity) * kBuckets;
-        hipLaunchKernelGGL(kSetup[mode], dim3((unsigned)blocks), dim3(kSetupBlock), 0, s, a0, begin, count, tab,
-                           cur, other, aos);
-        hipLaunchKernelGGL(kTraverse[mode], dim3(traverse_grid(d, mode, t, count, n_buckets)), dim3(kWave), 0, s,
-                           a0, tab, (const uint32_t *)cur, n_buckets, t.refill);
-        parity = 1 - parity;
-    }
-    return parity;
-}
-
 int launch(int mode, const Args &a, void *stream)
 {
     (void)hipGetLastError();
@@ -1648,9 +1303,12 @@ int launch(int mode, const Args &a, void *stream)
     Region &R = d->region[d->next_region.fetch_add(1u) % kRegions];
     {
         std::lock_guard<std::mutex> lock(R.m);
-        if (!R.mem) {
-            if (hipMalloc(&R.mem, table_region_bytes(kChunkRows)) != hipSuccess) {
-                R.mem = nullptr;
+        if (!R.slots) {
+            // root slots for the largest grid of the single-call variants
+            int most = 0;
+            for (int m = 0; m < 3; ++m) most = d->fused_resident[m] > most ? d->fused_resident[m] : most;
+            if (hipMalloc(&R.slots, (size_t)most * d->cus * 16 * kWave * sizeof(float)) != hipSuccess) {
+                R.slots = nullptr;
                 (void)hipGetLastError();
                 return FI_ERR_HIP;
             }
@@ -1678,31 +1336,19 @@ int launch(int mode, const Args &a, void *stream)
             }
             aos = R.aos;
         }
-        const bool fused = FIBERHIT_FUSED && mode != kConservative && a.n_pairs < ((int64_t)1 << 31);
-        const int64_t fused_waves = (int64_t)d->fused_resident[fused ? mode : 0] * d->cus;
-        if (fused && !R.slots) {
-            // sized for the larger grid of the two variants
-            const int most = d->fused_resident[0] > d->fused_resident[1] ? d->fused_resident[0] : d->fused_resident[1];
-            if (hipMalloc(&R.slots, (size_t)most * d->cus * 16 * kWave * sizeof(float)) != hipSuccess) {
-                R.slots = nullptr;
-                (void)hipGetLastError();
-                return FI_ERR_HIP;
-            }
-        }
         if (R.pending && hipStreamWaitEvent(s, R.done, 0) != hipSuccess) return FI_ERR_HIP;
         if (aos)
             hipLaunchKernelGGL(k_fibers_aos, dim3((unsigned)((a.n_fibers + 255) / 256)), dim3(256), 0, s,
                                a.fibers, a.fiber_stride, a.n_fibers, (float4 *)R.aos);
-        if (fused) {
-            int64_t g = (a.n_pairs + kWave - 1) / kWave;
-            if (g > fused_waves) g = fused_waves;
-            if (g > 0)
-                hipLaunchKernelGGL(kFused[mode], dim3((unsigned)g), dim3(kWave), 0, s, a, nullptr, nullptr, 0,
-                                   a.n_pairs, R.slots, FIBERHIT_FUSED_REFILL, aos);
-        } else {
-            R.parity = launch_chain(*d, mode, fi_tuning{FIBERHIT_TABLE_REFILL, 0}, a, a.n_pairs,
-                                    table_at(R.mem, kChunkRows), R.counters, R.parity, s, aos);
-        }
+        // one persistent launch: about one wave per 64 pairs, at most the
+        // resident waves
+        int64_t g = (a.n_pairs + kWave - 1) / kWave;
+        const int64_t resident = (int64_t)d->fused_resident[mode] * d->cus;
+        if (g > resident) g = resident;
+        if (g > 0)
+            hipLaunchKernelGGL(kFused[mode], dim3((unsigned)g), dim3(kWave), 0, s, a, nullptr, nullptr, 0,
+                               a.n_pairs, R.slots, mode == kConservative ? FIBERHIT_REFINE_REFILL : FIBERHIT_FUSED_REFILL,
+                               aos);
         if (hipEventRecord(R.done, s) != hipSuccess) return FI_ERR_HIP;
         R.pending = true;
     }
@@ -1713,7 +1359,7 @@ int launch(int mode, const Args &a, void *stream)
 // Batched problems
 // ---------------------------------------------------------------------------
 
-size_t table_bytes(int n) { return align256((size_t)n * sizeof(Args)) + align256((size_t)(n + 1) * sizeof(int64_t)); }
+size_t scene_table_bytes(int n) { return align256((size_t)n * sizeof(Args)) + align256((size_t)(n + 1) * sizeof(int64_t)); }
 
 // Root slots of the one-kernel batched path: one 4 KB block per resident
 // wave of the current device (0 if the device cannot be queried).
@@ -1721,14 +1367,14 @@ size_t batched_slot_bytes()
 {
     DeviceInfo *d = nullptr;
     if (device_info(d) != FI_OK) return 0;
-    return align256((size_t)d->fused_resident[2] * d->cus * 16 * kWave * sizeof(float));
+    return align256((size_t)d->fused_resident[kBatchedVariant] * d->cus * 16 * kWave * sizeof(float));
 }
 
 size_t batched_bytes(int n, int64_t total)
 {
     (void)total;
     const size_t slots = batched_slot_bytes();
-    return slots ? table_bytes(n) + slots : 0;
+    return slots ? scene_table_bytes(n) + slots : 0;
 }
 
 int scenes_to_table(const fi_scene *sc, int32_t n, Args *tab, int64_t *off)
@@ -1761,7 +1407,7 @@ BatchLayout layout_of(void *ws, int n)
     BatchLayout L;
     L.scenes = (Args *)p;
     L.offsets = (int64_t *)(p + align256((size_t)n * sizeof(Args)));
-    L.slots = (float *)(p + table_bytes(n));
+    L.slots = (float *)(p + scene_table_bytes(n));
     return L;
 }
 
@@ -1771,12 +1417,12 @@ BatchLayout layout_of(void *ws, int n)
 void launch_batched(const DeviceInfo &d, const fi_tuning &t, const BatchLayout &L, int n_scenes, int64_t total,
                     hipStream_t s)
 {
-    int per_cu = d.fused_resident[2];
+    int per_cu = d.fused_resident[kBatchedVariant];
     if (t.waves_per_simd > 0 && 4 * t.waves_per_simd < per_cu) per_cu = 4 * t.waves_per_simd;
     int64_t g = (total + kWave - 1) / kWave;
     if (g > (int64_t)per_cu * d.cus) g = (int64_t)per_cu * d.cus;
     if (g > 0)
-        hipLaunchKernelGGL(kFused[2], dim3((unsigned)g), dim3(kWave), 0, s, Args{}, L.scenes, L.offsets, n_scenes,
+        hipLaunchKernelGGL(kFused[kBatchedVariant], dim3((unsigned)g), dim3(kWave), 0, s, Args{}, L.scenes, L.offsets, n_scenes,
                            total, L.slots, t.refill, nullptr);
 }
 
@@ -1786,7 +1432,7 @@ int batched_enqueue(const fi_scene *scenes, int32_t n_scenes, const fi_tuning &t
     DeviceInfo *d = nullptr;
     int st = device_info(d);
     if (st != FI_OK) return st;
-    const size_t tb = table_bytes(n_scenes);
+    const size_t tb = scene_table_bytes(n_scenes);
     if (tb > kStageBytes) return FI_ERR_RANGE;
     if (!workspace || workspace_bytes < batched_bytes(n_scenes, total_pairs(scenes, n_scenes)))
         return FI_ERR_WORKSPACE;
@@ -1907,7 +1553,7 @@ int fiber_batch_plan_create(const fi_scene *scenes, int32_t n_scenes, const fi_t
     DeviceInfo *d = nullptr;
     int st = device_info(d);
     if (st != FI_OK) return st;
-    const size_t tb = table_bytes(n_scenes);
+    const size_t tb = scene_table_bytes(n_scenes);
     char *host = (char *)malloc(tb);
     if (!host) return FI_ERR_RANGE;
     st = scenes_to_table(scenes, n_scenes, (Args *)host, (int64_t *)(host + align256((size_t)n_scenes * sizeof(Args))));

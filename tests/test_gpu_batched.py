@@ -136,7 +136,7 @@ def test_batched_argument_errors():
         binding.intersect_batched(probs, tuning={"refill": 32, "waves_per_simd": 17})
 
 
-def test_batched_longer_than_one_chunk():
+def test_batched_four_million_pairs():
     """4.3 million pairs in three problems in one launch: wave shares cross
     problem boundaries (one problem has 3 pairs); results stay bitwise equal
     to one call per problem."""
@@ -146,7 +146,7 @@ def test_batched_longer_than_one_chunk():
         w = W.straight_and_curved(n, 22, seed=4242 + k)
         g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
         probs.append(binding.Problem(g(w.rays), g(w.fibers), 22 if k != 1 else 9))
-    say(f"[batched] chunks: {sum(sizes)} pairs")
+    say(f"[batched] {sum(sizes)} pairs in three problems")
     ref = plain_reference(probs)
     clear(probs)
     binding.intersect_batched(probs)

@@ -178,13 +178,13 @@ def _bits(a):
     return np.ascontiguousarray(a).view(np.uint32 if a.dtype == np.float32 else np.uint8)
 
 
-def test_calls_longer_than_one_chunk():
-    """A call of 2^20 + 4099 pairs runs as two setup/traversal chunks: every
-    pair's result equals that of a separate call on a subset of the pairs
-    (bitwise), on both sides of the chunk boundary."""
+def test_results_independent_of_call_size():
+    """A call of 2^20 + 4099 pairs (wave shares of uneven length, a ragged
+    tail): every pair's result equals that of a separate call on a subset of
+    the pairs (bitwise), at the start, across the 2^20 mark and at the end."""
     n = (1 << 20) + 4099
     w = W.straight_and_curved(n, 22)
-    say(f"[chunks] n={n}")
+    say(f"[call size] n={n}")
     t_g, u_g, h_g = run_gpu(w, 22)
     rays = torch.from_numpy(w.rays).to(DEV)
     fibers = torch.from_numpy(w.fibers).to(DEV)
@@ -198,9 +198,9 @@ def test_calls_longer_than_one_chunk():
 
 
 def test_concurrent_streams():
-    """Calls enqueued alternately on two streams (more calls than survivor
-    tables, so tables are reused across streams) give the results of the same
-    calls made one after another."""
+    """Calls enqueued alternately on two streams (they share the per-device
+    root slots, so a call waits for the one before it) give the results of
+    the same calls made one after another."""
     ws = [W.straight_and_curved(50_000 + 1000 * k, 9, seed=77 + k) for k in range(6)]
     dev_in = [(torch.from_numpy(w.rays).to(DEV), torch.from_numpy(w.fibers).to(DEV)) for w in ws]
     ref = []
