@@ -813,6 +813,12 @@ __device__ __forceinline__ int trip(Lane &L, const Root &root, float *col)
             // they would delay every cached rebuild by a memory round trip
             asm volatile("" ::: "memory");
             root.get(L, L.c);
+            // wait for the root here (vmcnt(0); expcnt, lgkmcnt untouched):
+            // left pending (a sibling of the root's child replays no level),
+            // its loads made the cached lanes' LDS reads into the same
+            // registers, and the end of the trip, wait for every outstanding
+            // memory operation, finish stores included
+            __builtin_amdgcn_s_waitcnt(0x0F70);
             for (uint32_t b = kRootSize >> 1; b > L.size; b >>= 1) {
                 V4 rdp, rtc;
                 split_terms(L.c, rdp, rtc);
@@ -1081,10 +1087,13 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
                 if (scene0 != before) cur = outs_of(scenes[scene0]);
             }
         }
-        if (__ballot(active) == 0) {
-            if (next >= end) break;
-            continue;
-        }
+        // No edge back to the refill that bypasses the trip: a wave whose
+        // fresh pairs were all decided at the root runs one idle trip instead.
+        // With a single path around the loop the lane state keeps one set of
+        // registers; a bypass edge had made the compiler copy the node and
+        // the traversal state at every trip (about 45 moves, measured 12-14 %
+        // of the call).
+        if (__ballot(active) == 0 && next >= end) break;
         const int st = trip<MODE>(L, root, col);
         if (active && st != kGoOn && !(MODE == kConservative && L.waiting)) {
             if constexpr (BATCHED) {
