@@ -108,6 +108,36 @@ def test_strided_tables_and_index_gather():
     assert same.mean() > 0.999
 
 
+def test_gathered_fiber_records_bitwise():
+    """A gathered call with at least as many pairs as fibers reads the fibers
+    through 64-byte records copied first; its results equal, bit for bit,
+    those of the same pairs materialised as tables and called with identity
+    pairing (no records), and agree with the oracle."""
+    w = W.straight_and_curved(3000, seed=515)
+    rng = np.random.default_rng(9)
+    n = 9000
+    pr = rng.integers(0, 3000, n).astype(np.int32)
+    pf = pr.copy()                                   # rays aim at their own fiber ...
+    pf[::3] = rng.integers(0, 3000, n)[::3]          # ... except a third (mostly misses)
+    rays = torch.from_numpy(w.rays).to(DEV)
+    fibers = torch.from_numpy(w.fibers).to(DEV)
+    for d in (9, 22):
+        t, u, h = (o.cpu().numpy() for o in binding.intersect_pairs(
+            rays, fibers, d, torch.from_numpy(pr).to(DEV), torch.from_numpy(pf).to(DEV)))
+        R = torch.from_numpy(np.ascontiguousarray(w.rays[:, pr])).to(DEV)
+        F = torch.from_numpy(np.ascontiguousarray(w.fibers[:, pf])).to(DEV)
+        t2, u2, h2 = (o.cpu().numpy() for o in binding.intersect_pairs(R, F, d))
+        torch.cuda.synchronize()
+        say(f"[gather] depth={d} pairs={n} hits={h.mean():.3f}")
+        assert np.array_equal(_bits(t), _bits(t2))
+        assert np.array_equal(_bits(u), _bits(u2))
+        assert np.array_equal(h, h2)
+        ws = W.Workload("gathered", w.rays, w.fibers, pr, pf, d)
+        (t_o, u_o, h_o), band = oracle_with_band(ws, d)
+        st = compare(t, u, h, t_o, u_o, h_o, band, np.full(n, d, np.uint8), alt=tie_resolver(ws, d))
+        assert st["ok"], st
+
+
 def test_degenerate_pairs_are_misses():
     w = W.straight_and_curved(512)
     R = w.rays.copy()
