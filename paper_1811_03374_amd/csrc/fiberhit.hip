@@ -671,22 +671,29 @@ __device__ __forceinline__ float leaf_u(const Lane &L)
 // disc excess (with the FP32 leaf hit as Newton's start). A leaf-local check
 // (three leaves around the FP32 hit, then the whole curve if it failed) was
 // measured first: at hair scale almost every leaf check failed (the FP32
-// leaf lies more than a leaf from the entry), so it only added work. Sets
-// L.t64 / L.u64 and returns true on a hit.
-__device__ __noinline__ bool refine_whole_curve(Lane &L, const Args &in)
+// leaf lies more than a leaf from the entry), so it only added work.
+// Arguments and result go by value: a reference to the caller's lane state
+// or to the kernel's arguments would keep them in scratch memory for the
+// whole kernel (the call is not inlined), every trip included.
+struct Refined {
+    double t, u;
+    bool hit;
+};
+
+__device__ __noinline__ Refined refine_whole_curve(const float *rays, int64_t ray_stride, const float *fibers,
+                                                   int64_t fiber_stride, const int32_t *pair_ray,
+                                                   const int32_t *pair_fiber, int64_t i, float tmax, float t0,
+                                                   float u0)
 {
-    const int64_t i = L.pair;
-    const int64_t ri = in.pair_ray ? (int64_t)in.pair_ray[i] : i;
-    const int64_t fi = in.pair_fiber ? (int64_t)in.pair_fiber[i] : i;
+    Refined r{INFINITY, __builtin_nan(""), false};
+    const int64_t ri = pair_ray ? (int64_t)pair_ray[i] : i;
+    const int64_t fi = pair_fiber ? (int64_t)pair_fiber[i] : i;
     Curve64 cv;
-    if (!curve_in_ray_frame(in.rays + ri, in.ray_stride, in.fibers + fi, in.fiber_stride, cv)) return false;
+    if (!curve_in_ray_frame(rays + ri, ray_stride, fibers + fi, fiber_stride, cv)) return r;
     double t = INFINITY, u = __builtin_nan("");
-    leaf_candidates<kCurveSamples>(cv, 0.0, 1.0, 0.0, (double)L.tmax, (double)L.tmax, (double)L.t,
-                                   (double)L.ru, t, u);
-    if (!(t < INFINITY)) return false;
-    L.t64 = t;
-    L.u64 = u;
-    return true;
+    leaf_candidates<kCurveSamples>(cv, 0.0, 1.0, 0.0, (double)tmax, (double)tmax, (double)t0, (double)u0, t, u);
+    if (t < INFINITY) r = Refined{t, u, true};
+    return r;
 }
 
 // One loop trip of the paper's iteration (Appendix C, final listing): a
@@ -1116,7 +1123,11 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
             if (parked != 0 && __ballot(active && !L.waiting) == 0) {
                 if (L.waiting) {
                     L.waiting = 0;
-                    finish<MODE>(outs_of(a0), L.pair, L, refine_whole_curve(L, a0));
+                    const Refined r = refine_whole_curve(a0.rays, a0.ray_stride, a0.fibers, a0.fiber_stride,
+                                                         a0.pair_ray, a0.pair_fiber, L.pair, L.tmax, L.t, L.ru);
+                    L.t64 = r.t;
+                    L.u64 = r.u;
+                    finish<MODE>(outs_of(a0), L.pair, L, r.hit);
                     active = false;
                 }
             }
