@@ -351,8 +351,29 @@ def main():
                                                  "max_abs_u", "tie_resolved")}
 
     stream = torch.cuda.current_stream()
+    # A step's calls (one per depth) are independent: each depth has a
+    # stream of its own, on which its calls run in order, the longer one
+    # (depth 22) issued first, so that one call's waves fill the SIMDs the
+    # other's finishing waves leave empty. The streams fork from the main
+    # stream before the steps and join it after them. Per-call figures (per
+    # depth, roofline) come from the same calls made one after another on
+    # one stream, each between HIP events.
+    side = {d: torch.cuda.Stream() for d in DEPTHS}
+    order = sorted(DEPTHS, reverse=True)
 
-    def step(ev=None):
+    def fork():
+        for d in order:
+            side[d].wait_stream(stream)
+
+    def join():
+        for d in order:
+            stream.wait_stream(side[d])
+
+    def step():
+        for d in order:
+            binding.intersect_pairs(rays, fibers, d, out=outs[d], stream=side[d])
+
+    def isolated_step(ev=None):
         for j, d in enumerate(DEPTHS):
             if ev is not None:
                 ev[j][0].record(stream)
@@ -360,24 +381,37 @@ def main():
             if ev is not None:
                 ev[j][1].record(stream)
 
+    fork()
     for _ in range(args.warmup):
         step()
+    join()
+    for _ in range(args.warmup):
+        isolated_step()
     torch.cuda.synchronize()
 
     # timed region: exactly K steps, device idle on both sides
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fork()
+    for k in range(args.steps):
+        step()
+    join()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    value = len(DEPTHS) * n / (ms_per_step * 1e-3) / 1e9
+
+    # per-call timing: the same K steps with the calls one after another
     ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
            for _ in DEPTHS] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(ev[k])
+        isolated_step(ev[k])
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-
+    sequential_ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
     launch_ms = {d: [ev[k][j][0].elapsed_time(ev[k][j][1]) for k in range(args.steps)]
                  for j, d in enumerate(DEPTHS)}
-    ms_per_step = wall * 1e3 / args.steps
-    value = len(DEPTHS) * n / (ms_per_step * 1e-3) / 1e9
 
     per_depth = {}
     roof = {}
@@ -404,6 +438,7 @@ def main():
                    "traffic": measured_traffic(d), "kernel": "k_fused (one call)", "depth": d,
                    "algorithmic_bytes": work[d]["bytes"]}
     dominant = max(DEPTHS, key=lambda d: statistics.mean(launch_ms[d]))
+    step_flops = sum(work[d]["flops"] for d in DEPTHS)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -432,9 +467,16 @@ def main():
                    "pairs": n, "depths": list(DEPTHS), "pairing": "identity",
                    "launch": "per call: k_fused (persistent 64-lane waves, each draining an even share of "
                              "the pairs: FP64 frame and root test in the lane refill, then the FP32 "
-                             "subdivision search)"},
+                             "subdivision search); a step's two calls on two streams",
+                   "sequential_ms_per_step": sequential_ms_per_step,
+                   "sequential_gpairs_per_s": len(DEPTHS) * n / (sequential_ms_per_step * 1e-3) / 1e9},
         "per_depth": per_depth,
         "roofline": roof[dominant],
+        "step_roofline": {
+            "bound": "alu", "unit": "TFLOP/s", "peak": workmodel.PEAK_FP32_TFLOPS,
+            "achieved": step_flops / (ms_per_step * 1e-3) / 1e12,
+            "frac": step_flops / (ms_per_step * 1e-3) / 1e12 / workmodel.PEAK_FP32_TFLOPS,
+            "what": "both calls' algorithmic flops over the step time (calls overlapped on two streams)"},
         "cpu_baseline": cpu,
         "parity": parity,
     }

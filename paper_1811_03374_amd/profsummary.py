@@ -10,12 +10,18 @@ Usage (on the results of the commands named in the summary it writes):
 
 * ``--stats``: a ``rocprofv3 --kernel-trace --stats`` run of ``bench.py``;
   the summary lists every kernel's call count and average duration.
+* ``--trace`` with ``--steps K``: the kernel trace of that run. ``bench.py``
+  makes the timed steps' calls on two streams, one per depth (overlapping),
+  then repeats the K steps with the calls one after another for the
+  per-call figures; the summary gives the average duration per depth of
+  both kinds of call: the last 2K plain dispatches are the one-after-another
+  calls (depth 9, then 22), the 2K before them the overlapped ones (issued
+  22, then 9).
 * ``--fetch`` / ``--write``: ``rocprofv3 --pmc FETCH_SIZE`` and
   ``--pmc WRITE_SIZE`` runs of ``bench.py --traffic-probe``, which copies
   256 MiB with a plain device copy and then makes one call per depth. The
   copy calibrates the counters (bytes the counter reports for a copy of known
-  size); every call's dispatches (k_fused, or k_setup and k_traverse) are
-  summed and scaled by that factor. The result is written to ``traffic.json`` together with the
+  size); every call's k_fused dispatch is scaled by that factor. The result is written to ``traffic.json`` together with the
   hash of the kernel source it was measured on, which ``bench.py`` checks
   before it reports the figure.
 """
@@ -67,23 +73,27 @@ def read_counter(path, counter):
     return [(k, v[0], v[1]) for k, v in sorted(per.items())]
 
 
-CALL_KERNELS = ("k_fused", "k_setup", "k_traverse")
+CALL_KERNELS = ("k_fused",)
 
 
 def per_call(dispatches, factor):
-    """Bytes per call, in call order (one call per depth): a call is one
-    k_fused dispatch, or a k_setup dispatch and the k_traverse after it."""
-    calls, cur = [], None
-    for _, name, kib in dispatches:
-        if name.startswith("k_fused"):
-            cur = {"k_fused": kib * 1024 * factor}
-            calls.append(cur)
-        elif name.startswith("k_setup"):
-            cur = {"k_setup": kib * 1024 * factor}
-            calls.append(cur)
-        elif name.startswith("k_traverse") and cur is not None:
-            cur["k_traverse"] = kib * 1024 * factor
-    return calls
+    """Bytes per call, in call order (one call per depth, one k_fused
+    dispatch each)."""
+    return [{"k_fused": kib * 1024 * factor} for _, name, kib in dispatches if name.startswith("k_fused")]
+
+
+def call_durations(trace_path, steps):
+    """Average duration (us) per depth of the plain-mode calls of a bench
+    run: (isolated, overlapped), each a dict depth -> us."""
+    rows = [r for r in csv.DictReader(open(trace_path)) if short(r["Kernel_Name"]) == "k_fused<0, false>"]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    us = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows]
+    if len(us) < 4 * steps:
+        raise SystemExit(f"{len(us)} plain dispatches in the trace, fewer than 4 x {steps}")
+    iso, ovl = us[-2 * steps:], us[-4 * steps:-2 * steps]
+    avg = lambda x: sum(x) / len(x)
+    return ({DEPTHS[0]: avg(iso[0::2]), DEPTHS[1]: avg(iso[1::2])},
+            {DEPTHS[1]: avg(ovl[0::2]), DEPTHS[0]: avg(ovl[1::2])})
 
 
 def calibration(dispatches):
@@ -100,6 +110,8 @@ def main(argv=None):
     ap.add_argument("--write")
     ap.add_argument("--name", required=True)
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
+    ap.add_argument("--trace")
+    ap.add_argument("--steps", type=int, default=0)
     ap.add_argument("--command", action="append", default=[],
                     help="command line that produced an input (repeatable)")
     a = ap.parse_args(argv)
@@ -111,6 +123,12 @@ def main(argv=None):
     for s in stats:
         lines.append(f"| {s['kernel']} | {s['calls']} | {s['avg_us']:.1f} | {s['min_us']:.1f} | "
                      f"{s['max_us']:.1f} | {s['percent']:.1f} |")
+    if a.trace and a.steps > 0:
+        iso, ovl = call_durations(a.trace, a.steps)
+        lines += ["", f"Per-call durations of `k_fused<0, false>` from the kernel trace ({a.steps} steps):", "",
+                  "| depth | one after another, us | overlapped (two streams), us |", "|---|---|---|"]
+        for d in DEPTHS:
+            lines.append(f"| {d} | {iso[d]:.1f} | {ovl[d]:.1f} |")
     traffic = None
     if a.fetch and a.write:
         fd = read_counter(a.fetch, "FETCH_SIZE")
