@@ -98,6 +98,28 @@ def test_graph_plan_replays():
     plan.close()
 
 
+def test_plan_on_a_side_stream():
+    """A plan replayed on a stream other than the current one: work enqueued
+    on that stream right after the launch (here, copies of every output) sees
+    every scene's results, on two replays in a row."""
+    ws, sizes, probs = make_scenes(seed=29)
+    ref = plain_reference(probs)
+    plan = binding.BatchPlan(probs)
+    s = torch.cuda.Stream()
+    for rep in range(2):
+        clear(probs)
+        s.wait_stream(torch.cuda.current_stream())
+        plan.launch(s)
+        with torch.cuda.stream(s):
+            copies = [(p.t.clone(), p.u.clone(), p.hit.clone()) for p in probs]
+        torch.cuda.synchronize()
+        for (t, u, h), (tr, ur, hr) in zip(copies, ref):
+            assert np.array_equal(bits(t.cpu().numpy()), bits(tr))
+            assert np.array_equal(bits(u.cpu().numpy()), bits(ur))
+            assert np.array_equal(h.cpu().numpy(), hr)
+    plan.close()
+
+
 def test_batched_parity_against_oracle():
     ws, sizes, probs = make_scenes(k=6, seed=21)
     binding.intersect_batched(probs)
