@@ -820,11 +820,12 @@ __device__ __forceinline__ int trip(Lane &L, const Root &root, float *col)
             // they would delay every cached rebuild by a memory round trip
             asm volatile("" ::: "memory");
             root.get(L, L.c);
-            // wait for the root here (vmcnt(0); expcnt, lgkmcnt untouched):
-            // left pending (a sibling of the root's child replays no level),
-            // its loads made the cached lanes' LDS reads into the same
-            // registers, and the end of the trip, wait for every outstanding
-            // memory operation, finish stores included
+            // Wait for the root here: 0x0F70 is vmcnt(0) with expcnt and
+            // lgkmcnt at their maxima (no wait). Left pending, as it is when
+            // no level is replayed (a sibling of the root's child), its loads
+            // made the cached lanes' LDS reads into the same registers wait
+            // for them, and the end of the trip wait for every outstanding
+            // memory operation, finish stores included.
             __builtin_amdgcn_s_waitcnt(0x0F70);
             for (uint32_t b = kRootSize >> 1; b > L.size; b >>= 1) {
                 V4 rdp, rtc;
