@@ -36,6 +36,9 @@ def parse():
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for counter runs: one 256 MiB device copy (calibration), then one launch "
                          "per depth, nothing else")
+    ap.add_argument("--refine-probe", action="store_true",
+                    help="for counter runs: two FP64-refined depth-22 calls on 2^22 hair pairs, "
+                         "nothing else")
     return ap.parse_args()
 
 
@@ -131,6 +134,27 @@ def bench_batched(args):
     }
     plan.close()
     print(json.dumps(line), flush=True)
+
+
+def refine_probe():
+    """Two refined depth-22 calls (the second is the one to read) on the hair
+    workload with 2^22 rays: the input of counter runs on the refining
+    kernel."""
+    import torch
+    from paper_1811_03374_amd import binding
+    from paper_1811_03374_amd import workloads as W
+
+    w = W.hair_precision(1 << 22, 100_000)
+    dev = torch.device("cuda:0")
+    rays = torch.from_numpy(w.rays).to(dev)
+    fibers = torch.from_numpy(w.fibers).to(dev)
+    pf = torch.from_numpy(w.pair_fiber).to(dev)
+    for _ in range(2):
+        out = binding.intersect_pairs(rays, fibers, 22, pair_fiber=pf, refine=True)
+        torch.cuda.synchronize()
+    print(json.dumps({"refine_probe": True, "pairs": w.n_pairs,
+                      "hit_rate": float(out[2].float().mean().item()),
+                      "kernel_source_sha256_16": kernel_source_hash()}))
 
 
 def bench_hair(args):
@@ -288,6 +312,9 @@ def main():
         print("bench.py measures one GPU: the per-pair test has no cross-GPU step, "
               "and multi-GPU runs are not part of this build (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
+    if args.refine_probe:
+        refine_probe()
+        return
     if args.workload == "batched":
         bench_batched(args)
         return
