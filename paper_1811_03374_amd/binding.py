@@ -80,6 +80,20 @@ def _index(t: Optional[torch.Tensor], dtype, name: str):
     return t
 
 
+def _outs(out, n: int, dev):
+    """Output tensors (t, u, hit) for n pairs: new ones, or the caller's after
+    a check that the kernel cannot write past them."""
+    if out is None:
+        return (torch.empty(n, dtype=torch.float32, device=dev),
+                torch.empty(n, dtype=torch.float32, device=dev),
+                torch.empty(n, dtype=torch.uint8, device=dev))
+    t, u, hit = out
+    for x, dt, name in ((t, torch.float32, "t"), (u, torch.float32, "u"), (hit, torch.uint8, "hit")):
+        if x.dtype != dt or not x.is_cuda or not x.is_contiguous() or x.numel() < n:
+            raise ValueError(f"out {name} must be a contiguous {dt} device tensor of at least {n} elements")
+    return t, u, hit
+
+
 def _stream(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -112,12 +126,7 @@ def intersect_pairs(rays: torch.Tensor, fibers: torch.Tensor, depth: int = 9,
     else:
         n = min(rays.shape[1], fibers.shape[1])
     dev = rays.device
-    if out is None:
-        t = torch.empty(n, dtype=torch.float32, device=dev)
-        u = torch.empty(n, dtype=torch.float32, device=dev)
-        hit = torch.empty(n, dtype=torch.uint8, device=dev)
-    else:
-        t, u, hit = out
+    t, u, hit = _outs(out, n, dev)
     if counts and refine:
         raise ValueError("counts and refine are separate passes")
     cn = torch.empty((n, 4), dtype=torch.int32, device=dev) if counts else None
@@ -135,6 +144,41 @@ def intersect_pairs(rays: torch.Tensor, fibers: torch.Tensor, depth: int = 9,
         return t, u, hit, t64, u64
     _check(lib().fiber_intersect_pairs(*args, None, None, _stream(stream)))
     return t, u, hit
+
+
+class PreparedPairs:
+    """One plain ``fiber_intersect_pairs`` call (no counts, no refinement),
+    checked and marshalled once and then enqueued as often as needed, on any
+    stream (serving loops, benchmarks): ``launch`` skips the per-call tensor
+    checks and argument building of ``intersect_pairs``. The object keeps its
+    input tensors alive and owns (or takes, via ``out``) the output tensors
+    t, u, hit, which every launch overwrites."""
+
+    def __init__(self, rays, fibers, depth=9, pair_ray=None, pair_fiber=None, pair_depth=None,
+                 out=None):
+        rs = _table(rays, 7, "rays")
+        fs = _table(fibers, 16, "fibers")
+        pr = _index(pair_ray, torch.int32, "pair_ray")
+        pf = _index(pair_fiber, torch.int32, "pair_fiber")
+        pd = _index(pair_depth, torch.uint8, "pair_depth")
+        if pr is not None:
+            n = pr.shape[0]
+        elif pf is not None:
+            n = pf.shape[0]
+        elif pd is not None:
+            n = pd.shape[0]
+        else:
+            n = min(rays.shape[1], fibers.shape[1])
+        self.t, self.u, self.hit = _outs(out, n, rays.device)
+        self._keep = (rays, fibers, pr, pf, pd)
+        self._fn = lib().fiber_intersect_pairs
+        self._args = (_ptr(rays), rs, rays.shape[1], _ptr(fibers), fs, fibers.shape[1],
+                      _ptr(pr), _ptr(pf), _ptr(pd), int(depth), n, 0,
+                      _ptr(self.t), _ptr(self.u), _ptr(self.hit), None, None)
+
+    def launch(self, stream=None):
+        _check(self._fn(*self._args, _stream(stream)))
+        return self.t, self.u, self.hit
 
 
 def raw_call(name: str, *args):

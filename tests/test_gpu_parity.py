@@ -138,6 +138,35 @@ def test_gathered_fiber_records_bitwise():
         assert st["ok"], st
 
 
+def test_prepared_calls_on_two_streams():
+    """binding.PreparedPairs (checked and marshalled once) launched repeatedly
+    on two streams at once gives, bit for bit, the results of intersect_pairs;
+    outputs too small for the call are refused before any launch."""
+    w = W.straight_and_curved(20_000, seed=616)
+    rays = torch.from_numpy(w.rays).to(DEV)
+    fibers = torch.from_numpy(w.fibers).to(DEV)
+    ref = {d: [o.cpu().numpy() for o in binding.intersect_pairs(rays, fibers, d)] for d in (9, 22)}
+    calls = {d: binding.PreparedPairs(rays, fibers, d) for d in (9, 22)}
+    side = {9: torch.cuda.Stream(), 22: torch.cuda.Stream()}
+    for d in (9, 22):
+        side[d].wait_stream(torch.cuda.current_stream())
+    for _ in range(3):
+        for d in (22, 9):
+            calls[d].launch(side[d])
+    torch.cuda.synchronize()
+    for d in (9, 22):
+        t, u, h = (o.cpu().numpy() for o in (calls[d].t, calls[d].u, calls[d].hit))
+        assert np.array_equal(_bits(t), _bits(ref[d][0]))
+        assert np.array_equal(_bits(u), _bits(ref[d][1]))
+        assert np.array_equal(h, ref[d][2])
+    small = (torch.empty(100, device=DEV), torch.empty(20_000, device=DEV),
+             torch.empty(20_000, dtype=torch.uint8, device=DEV))
+    with pytest.raises(ValueError):
+        binding.PreparedPairs(rays, fibers, 9, out=small)
+    with pytest.raises(ValueError):
+        binding.intersect_pairs(rays, fibers, 9, out=small)
+
+
 def test_degenerate_pairs_are_misses():
     w = W.straight_and_curved(512)
     R = w.rays.copy()
