@@ -19,9 +19,12 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
+        # FIBER_ORACLE_LIB: another build of these sources (the mutation test
+        # loads copies with planted mistakes through it)
+        path = os.environ.get("FIBER_ORACLE_LIB") or _build.LIB
+        if path == _build.LIB and not os.path.exists(path):
             _build.build()
-        L = C.CDLL(_build.LIB)
+        L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
         L.fo_intersect_d.argtypes = [dp, dp, C.c_int, dp, dp, C.POINTER(C.c_int64)]
         L.fo_intersect_d.restype = C.c_int
@@ -150,16 +153,17 @@ def single_depth(ray, fiber, depth):
     return bool(hit), t.value, u.value, tuple(st)
 
 
-def tie_outcomes(ray, fiber, depth, eps=1e-5, max_flips=2, max_out=512):
+def tie_outcomes(ray, fiber, depth, scale=1.0, max_flips=2, max_out=512):
     """Results of one pair reachable by flipping at most ``max_flips`` near-tie
-    comparisons (relative margin <= eps). Returns arrays (t, u, hit), the
-    unflipped result first."""
+    comparisons: comparisons whose two sides differ by at most ``scale`` times
+    the sum of their FP32 error bounds (reading R14 of the oracle). Returns
+    arrays (t, u, hit), the unflipped result first."""
     r, rp = _d(ray)
     f, fp = _d(fiber)
     t = np.empty(max_out)
     u = np.empty(max_out)
     h = np.empty(max_out, np.int32)
-    n = lib().fo_tie_outcomes(rp, fp, int(depth), float(eps), int(max_flips), int(max_out),
+    n = lib().fo_tie_outcomes(rp, fp, int(depth), float(scale), int(max_flips), int(max_out),
                               t.ctypes.data_as(C.POINTER(C.c_double)),
                               u.ctypes.data_as(C.POINTER(C.c_double)),
                               h.ctypes.data_as(C.POINTER(C.c_int)))

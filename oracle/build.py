@@ -15,11 +15,15 @@ SOURCES = ["fiber_oracle.c", "fiber_exact.c"]
 LIB = os.path.join(HERE, "liboracle_fiber.so")
 
 
+def gcc_cmd(srcs, out):
+    return ["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-fopenmp",
+            "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wno-unused-function",
+            "-o", out, *srcs, "-lm"]
+
+
 def build(verbose: bool = False) -> str:
     srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
-    cmd = ["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-fopenmp",
-           "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wno-unused-function",
-           "-o", LIB + ".tmp", *srcs, "-lm"]
+    cmd = gcc_cmd(srcs, LIB + ".tmp")
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -17,7 +17,9 @@
  *   side  roots u in [0,1] of F(u) = Dz^2 (Cx^2 + Cy^2) + (Cx Dx + Cy Dy)^2
  *         - r^2 Dz^2 with D = C'/3, where the ray meets the boundary circle of
  *         the disc at u; that point is at t = <C, D> / Dz;
- *   caps  u = 0 and u = 1 when the ray meets the end disc (F <= 0);
+ *   caps  u = 0 and u = 1 when the ray meets the end disc (F <= 0); where
+ *         the end tangent vanishes the disc is normal to its limit direction
+ *         (the next control-polygon edge from that end);
  *   inside the origin lies in a disc: a root of <C, D> with |C| <= r (t = 0);
  *   planar when Dz vanishes identically (every disc plane contains the ray
  *         direction), the ray lies in the disc at the roots of
@@ -258,6 +260,45 @@ static int disc_t(const curve_t *c, double u, int on_circle, double *t, double *
     return 1;
 }
 
+/* Normal of the end disc at u = e (0 or 1): the end tangent, or where it is
+ * negligible (squared length at most 2^-40 of the squared chord) the next
+ * control-polygon edge from that end, then the chord -- the limit of the
+ * tangent direction at the end. */
+static void end_normal(const curve_t *c, int e, double n[3])
+{
+    const double (*q)[4] = c->q;
+    double a[3], cand[3][3];
+    for (int k = 0; k < 3; ++k) {
+        a[k] = q[3][k] - q[0][k];
+        cand[0][k] = e == 0 ? q[1][k] - q[0][k] : q[3][k] - q[2][k];
+        cand[1][k] = e == 0 ? q[2][k] - q[0][k] : q[3][k] - q[1][k];
+        cand[2][k] = a[k];
+    }
+    const double aa = a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
+    int j = 0;
+    while (j < 2 && cand[j][0] * cand[j][0] + cand[j][1] * cand[j][1] + cand[j][2] * cand[j][2] <= 0x1p-40 * aa)
+        ++j;
+    for (int k = 0; k < 3; ++k) n[k] = cand[j][k];
+}
+
+/* Does the ray meet the end disc at u = e, and where: the ray point in the
+ * disc's plane, inside the disc when its distance to C(e) is at most r(e)
+ * (evaluated in long double: F of the side polynomial with the disc normal
+ * in place of C', which is homogeneous in it). */
+static int end_disc(const curve_t *c, int e, double *t)
+{
+    double n[3];
+    end_normal(c, e, n);
+    if (n[2] == 0.0) return 0;
+    const long double Cx = c->q[3 * e][0], Cy = c->q[3 * e][1], Cz = c->q[3 * e][2], r = c->q[3 * e][3];
+    const long double xy = Cx * n[0] + Cy * n[1];
+    const long double nz = n[2];
+    const long double F = nz * nz * (Cx * Cx + Cy * Cy) + xy * xy - r * r * nz * nz;
+    if (F > 0.0L) return 0;
+    *t = (double)((xy + Cz * nz) / nz);
+    return 1;
+}
+
 /* Exact first entry; kind: 0 miss, 1 side, 2 start cap, 3 end cap, 4 inside */
 static int exact_hit(const curve_t *c, double tmax, double *t_out, double *u_out)
 {
@@ -339,11 +380,15 @@ static int exact_hit(const curve_t *c, double tmax, double *t_out, double *u_out
         if (!disc_t(c, roots[i], 1, &t, NULL)) continue;
         if (t >= 0.0 && t < tmax && t < best) { best = t; bu = roots[i]; kind = 1; }
     }
-    /* end caps */
+    /* end caps: the disc at u = 0 (1) lies in the plane normal to the end
+     * tangent. Where that tangent vanishes (p1 = p0 or p2 = p3) the disc
+     * planes of the nearby u still converge: to the plane normal to the
+     * first non-negligible of p2 - p0, p3 - p0 (p3 - p1, p3 - p0), the
+     * direction C'(u) takes as u approaches the end. */
     for (int e = 0; e < 2; ++e) {
-        double t, Fv;
-        if (!disc_t(c, (double)e, 0, &t, &Fv)) continue;
-        if (Fv <= 0.0 && t >= 0.0 && t < tmax && t < best) { best = t; bu = (double)e; kind = 2 + e; }
+        double t;
+        if (!end_disc(c, e, &t)) continue;
+        if (t >= 0.0 && t < tmax && t < best) { best = t; bu = (double)e; kind = 2 + e; }
     }
     *t_out = best;
     *u_out = bu;

@@ -53,14 +53,19 @@
  *   R8  the ray direction is normalised; t and tmax are distances along it.
  *   R11 hit <=> t < tmax (t >= 0 by construction).
  *   R12 depth d means leaves of parametric size 2^-d, 0 <= d <= 23.
- *   R13 a zero tangent (exactly zero vector) is replaced for cap normals by
- *       the first non-zero of (q1-q0, q2-q0, q3-q0) at the start and
- *       (q3-q2, q3-q1, q3-q0) at the end; a zero split tangent by the chord.
- *       A zero-length chord gives distances to the point q0.
+ *   R13 a negligible tangent -- squared length at most 2^-40 of the squared
+ *       chord q3 - q0, below which its direction is rounding noise (a zero
+ *       end tangent, a cusp) -- is replaced for cap normals by the first
+ *       non-negligible of (q1-q0, q2-q0, q3-q0) at the start and
+ *       (q3-q2, q3-q1, q3-q0) at the end; a split tangent (1/8 of
+ *       -q0 - q1 + q2 + q3, the children's tangent at the split point) by
+ *       the chord. A zero-length chord gives distances to the point q0.
  *   R14 the method's result is not continuous in its inputs: where a pruning
- *       or ordering comparison is a near tie, an ulp-sized perturbation
- *       selects another (equally valid) leaf. fo_tie_outcomes enumerates the
- *       results reachable by flipping such ties; a lower-precision
+ *       or ordering comparison is a near tie, a rounding-sized perturbation
+ *       selects another (equally valid) leaf. A comparison is a tie when its
+ *       two sides differ by at most the error bound of an FP32 evaluation
+ *       (see node_err and the *_err terms below); fo_tie_outcomes enumerates
+ *       the results reachable by flipping such ties, and a lower-precision
  *       implementation must reproduce the unflipped result or one of these.
  */
 #include <math.h>
@@ -125,42 +130,76 @@ static int ray_frame(const double O[3], const double D[3], const double P[16],
 /* Geometry of one node                                                      */
 /* ------------------------------------------------------------------------ */
 
+/* R13: a tangent whose squared length is at most 2^-40 of the squared chord
+ * has no reliable direction. With a zero chord only the zero vector is
+ * negligible. */
+static int negligible(v4 v, v4 chord)
+{
+    return dot3(v, v) <= 0x1p-40 * dot3(chord, chord);
+}
+
 static v4 start_cap_normal(const v4 q[4])
 {
+    const v4 a = sub4(q[3], q[0]);
     v4 n = sub4(q[1], q[0]);
-    if (zero3(n)) n = sub4(q[2], q[0]);
-    if (zero3(n)) n = sub4(q[3], q[0]);
+    if (negligible(n, a)) n = sub4(q[2], q[0]);
+    if (negligible(n, a)) n = a;
     return n;
 }
 
 static v4 end_cap_normal(const v4 q[4])
 {
+    const v4 a = sub4(q[3], q[0]);
     v4 n = sub4(q[3], q[2]);
-    if (zero3(n)) n = sub4(q[3], q[1]);
-    if (zero3(n)) n = sub4(q[3], q[0]);
+    if (negligible(n, a)) n = sub4(q[3], q[1]);
+    if (negligible(n, a)) n = a;
     return n;
+}
+
+/* Error bound of the crossing t = <s, n> / n_z of a plane through s with
+ * normal n, for node coordinates known to +-delta in an FP32 evaluation: the
+ * point error seen along the ray through the plane's obliquity (the normal's
+ * own error, relative to it, is of the same order and covered by the factor
+ * 2), plus the rounding of the quotient. */
+static double plane_err(double delta, v4 n, double t)
+{
+    return 2.0 * delta * sqrt(dot3(n, n)) / fabs(n.z) + 4.0 * 0x1p-24 * fabs(t);
 }
 
 /* t interval of the ray between the node's two end-cap planes, intersected
  * with [0, tmax] (Section 3.3, cropping of the infinite cylinders). The start
  * cap passes through q0 with the start tangent as normal (the curve lies on
  * its positive side); the end cap passes through q3 with the end tangent (the
- * curve lies on its negative side). */
-static void cap_interval(const v4 q[4], double tmax, double *lo, double *hi)
+ * curve lies on its negative side). The node is given as its first control
+ * point o and the control points relative to it (see node_t). elo/ehi (may be
+ * NULL) receive the error bounds of the two ends for node coordinates known
+ * to +-delta (0 for the ends 0 and tmax). */
+static void cap_interval_e(v4 o, const v4 q[4], double tmax, double delta, double *lo, double *hi,
+                           double *elo, double *ehi)
 {
-    double l = 0.0, h = tmax;
+    double l = 0.0, h = tmax, el = 0.0, eh = 0.0;
     const v4 n0 = start_cap_normal(q);
-    const double c0 = dot3(q[0], n0);       /* inside <=> t*n0.z >= c0 */
-    if (n0.z > 0.0)      l = fmax(l, c0 / n0.z);
-    else if (n0.z < 0.0) h = fmin(h, c0 / n0.z);
-    else if (c0 > 0.0)   { l = INFINITY; h = -INFINITY; }
+    const double c0 = dot3(o, n0) + dot3(q[0], n0);       /* inside <=> t*n0.z >= c0 */
+    if (n0.z != 0.0) {
+        const double t = c0 / n0.z;
+        if (n0.z > 0.0 && t > l) { l = t; el = plane_err(delta, n0, t); }
+        if (n0.z < 0.0 && t < h) { h = t; eh = plane_err(delta, n0, t); }
+    } else if (c0 > 0.0) {
+        l = INFINITY; h = -INFINITY;
+    }
     const v4 n1 = end_cap_normal(q);
-    const double c1 = dot3(q[3], n1);       /* inside <=> t*n1.z <= c1 */
-    if (n1.z > 0.0)      h = fmin(h, c1 / n1.z);
-    else if (n1.z < 0.0) l = fmax(l, c1 / n1.z);
-    else if (c1 < 0.0)   { l = INFINITY; h = -INFINITY; }
+    const double c1 = dot3(o, n1) + dot3(q[3], n1);       /* inside <=> t*n1.z <= c1 */
+    if (n1.z != 0.0) {
+        const double t = c1 / n1.z;
+        if (n1.z > 0.0 && t < h) { h = t; eh = plane_err(delta, n1, t); }
+        if (n1.z < 0.0 && t > l) { l = t; el = plane_err(delta, n1, t); }
+    } else if (c1 < 0.0) {
+        l = INFINITY; h = -INFINITY;
+    }
     *lo = l;
     *hi = h;
+    if (elo) *elo = el;
+    if (ehi) *ehi = eh;
 }
 
 /* Squared distance of point e (relative to the axis origin) to the line
@@ -189,21 +228,43 @@ static double conservative_radius(const v4 q[4])
 }
 
 /* Unit ray (origin, +z) against the infinite cylinder of radius r whose axis
- * passes through o along a (Appendix A). Returns 0 on a miss. */
-static int unit_ray_cylinder(v4 o, v4 a, double r, double *t0, double *t1)
+ * passes through o along a (Appendix A). With g = a.x^2 + a.y^2 the ray
+ * meets it where e = r^2 - dist^2 >= 0 (dist: distance between the ray and
+ * the axis line), over [t_cpa - s, t_cpa + s]. */
+typedef struct {
+    int parallel;          /* g == 0: axis parallel to the ray (R4) */
+    double g, e, dist, t_cpa, s;
+} cyl_t;
+
+static cyl_t cylinder_terms(v4 o, v4 a, double r)
 {
-    const double g = a.x * a.x + a.y * a.y;
-    if (g == 0.0) {
-        if (o.x * o.x + o.y * o.y < r * r) { *t0 = -INFINITY; *t1 = INFINITY; return 1; }
-        return 0;
+    cyl_t c;
+    memset(&c, 0, sizeof c);
+    c.g = a.x * a.x + a.y * a.y;
+    if (c.g == 0.0) {
+        c.parallel = 1;
+        c.e = r * r - (o.x * o.x + o.y * o.y);
+        return c;
     }
     const double dd = a.x * o.y - a.y * o.x;      /* sqrt(g) * ray-axis distance */
-    const double e = r * r - dd * dd / g;
-    if (e < 0.0) return 0;
-    const double t_cpa = o.z - a.z * (a.x * o.x + a.y * o.y) / g;
-    const double s = sqrt(e * (a.z * a.z + g) / g);
-    *t0 = t_cpa - s;
-    *t1 = t_cpa + s;
+    c.dist = fabs(dd) / sqrt(c.g);
+    c.e = r * r - dd * dd / c.g;
+    c.t_cpa = o.z - a.z * (a.x * o.x + a.y * o.y) / c.g;
+    c.s = c.e > 0.0 ? sqrt(c.e * (a.z * a.z + c.g) / c.g) : 0.0;
+    return c;
+}
+
+/* Returns 0 on a miss. */
+static int unit_ray_cylinder(v4 o, v4 a, double r, double *t0, double *t1)
+{
+    const cyl_t c = cylinder_terms(o, a, r);
+    if (c.parallel) {
+        if (c.e > 0.0) { *t0 = -INFINITY; *t1 = INFINITY; return 1; }
+        return 0;
+    }
+    if (c.e < 0.0) return 0;
+    *t0 = c.t_cpa - c.s;
+    *t1 = c.t_cpa + c.s;
     return 1;
 }
 
@@ -221,25 +282,72 @@ static void split_half(const v4 q[4], v4 L[4], v4 R[4])
 }
 
 /* Normal of the partitioning plane: the curve tangent at the split point,
- * proportional to -q0 - q1 + q2 + q3 (Appendix B.2); the chord if zero. */
+ * proportional to -q0 - q1 + q2 + q3 (Appendix B.2), which is 8 times the
+ * children's tangent there; the chord when that tangent is negligible (R13). */
 static v4 split_normal(const v4 q[4])
 {
     v4 t = sub4(add4(q[2], q[3]), add4(q[0], q[1]));
-    if (zero3(t)) t = sub4(q[3], q[0]);
+    const v4 a = sub4(q[3], q[0]);
+    if (negligible(scale4(t, 0.125), a)) t = a;
     return t;
+}
+
+/* A node of the recursion: its first control point o (xyz in the ray frame)
+ * and its four control points relative to o (q[0] = 0; .w holds the radius
+ * control values themselves). Subdividing relative points keeps a deep
+ * node's shape at full relative precision: averaging absolute points would
+ * round it at the magnitude of the node's position, which matters where the
+ * parametrisation stalls (a zero end tangent makes the end nodes' chords
+ * shrink like 4^-depth). In exact arithmetic this is de Casteljau's
+ * subdivision of the absolute points. */
+typedef struct {
+    v4 o;
+    v4 q[4];
+} node_t;
+
+static node_t anchored(const v4 qa[4])
+{
+    node_t n;
+    n.o = mk4(qa[0].x, qa[0].y, qa[0].z, 0.0);
+    for (int k = 0; k < 4; ++k) n.q[k] = mk4(qa[k].x - n.o.x, qa[k].y - n.o.y, qa[k].z - n.o.z, qa[k].w);
+    return n;
+}
+
+/* the two halves at u = 1/2; the right half is re-anchored at the split point */
+static void split_node(const node_t *a, node_t *L, node_t *R)
+{
+    v4 l[4], r[4];
+    split_half(a->q, l, r);
+    const v4 s = l[3];
+    L->o = a->o;
+    R->o = mk4(a->o.x + s.x, a->o.y + s.y, a->o.z + s.z, 0.0);
+    for (int k = 0; k < 4; ++k) {
+        L->q[k] = l[k];
+        R->q[k] = mk4(r[k].x - s.x, r[k].y - s.y, r[k].z - s.z, r[k].w);
+    }
 }
 
 /* ------------------------------------------------------------------------ */
 /* The recursion                                                             */
 /* ------------------------------------------------------------------------ */
 
-/* Near ties. A comparison whose two sides differ by at most eps (relative)
- * is a tie: rounding at a lower precision may decide it either way, and the
- * method then legitimately returns another leaf. With eps > 0 the search
- * numbers the ties it meets and flips tie j when bit j of flip_mask is set;
- * enumerating masks yields every result reachable by flipping ties. */
+/* Near ties (R14). An FP32 implementation starts from the root correctly
+ * rounded in its {p, d, t0, t1} form and forms each child with a few
+ * roundings at the magnitude of the root's coordinates, so the coordinates
+ * of a node at `level` are known to
+ *     delta = (2 + 2 level) u X,   u = 2^-24,
+ * X the largest |x|, |y|, |z| of the root control points in the ray frame
+ * (measured growth: at most (1 + level) u X). Every t the search compares is
+ * a function of those coordinates; its error bound is delta times the
+ * function's sensitivity (plane_err for plane crossings, cyl_err for the
+ * cylinder), plus a few roundings of its own. A comparison whose sides differ
+ * by at most the sum of their bounds (times `scale`) is a tie. With scale > 0
+ * the search numbers the ties it meets and flips tie j when bit j of
+ * flip_mask is set; enumerating masks yields the results reachable by
+ * flipping ties. */
 typedef struct {
-    double eps;
+    double scale;
+    double X;
     uint64_t flip_mask;
     int n_ties;
 } ties_t;
@@ -253,34 +361,66 @@ typedef struct {
     ties_t ties;
 } search_t;
 
-/* value is the outcome of comparing a with b; flip it if this is a selected tie */
-static int decide(search_t *S, int value, double a, double b)
+static double node_err(const search_t *S, int level)
 {
-    if (S->ties.eps > 0.0 && isfinite(a) && isfinite(b) &&
-        fabs(a - b) <= S->ties.eps * fmax(1.0, fmax(fabs(a), fabs(b)))) {
+    return (2.0 + 2.0 * level) * 0x1p-24 * S->ties.X;
+}
+
+/* Error bound of the cylinder's entry and exit: moving the axis by delta
+ * moves t_cpa by up to delta (1 + |a.z| / sqrt(g)) and, through dist and r,
+ * the half-length s by delta |a| / sqrt(g) * (dist + r) / sqrt(e) (large
+ * near a tangent ray). */
+static double cyl_err(double delta, const cyl_t *c, v4 a, double r)
+{
+    const double amp = sqrt(a.z * a.z + c->g) / sqrt(c->g);
+    const double root = sqrt(fmax(c->e, 0.0));
+    return amp * delta * (2.0 + (c->dist + r) / fmax(root, 1e-300)) +
+           4.0 * 0x1p-24 * (fabs(c->t_cpa) + c->s);
+}
+
+/* `value` is the outcome of a comparison whose sides differ by `diff`, each
+ * known to within the bounds that sum to `margin`; flip it if this is a
+ * selected tie. */
+static int decide(search_t *S, int value, double diff, double margin)
+{
+    if (S->ties.scale > 0.0 && isfinite(diff) && fabs(diff) <= S->ties.scale * margin) {
         const int j = S->ties.n_ties++;
         if (j < 64 && ((S->ties.flip_mask >> j) & 1u)) value = !value;
     }
     return value;
 }
 
-static int visit(search_t *S, const v4 q[4], double lo, double hi,
+static int visit(search_t *S, const node_t *N, double lo, double hi, double elo, double ehi,
                  int level, double u0, double u1)
 {
     S->tests++;
+    const v4 *q = N->q;
     const v4 a = sub4(q[3], q[0]);
     const double R = conservative_radius(q);
-    double te, tx;
-    if (!unit_ray_cylinder(q[0], a, R, &te, &tx)) return 0;
+    const double delta = node_err(S, level);
+    double te, tx, ec = 0.0;
+    const cyl_t cy = cylinder_terms(N->o, a, R);
+    if (cy.parallel) {                                   /* R4 */
+        if (!(cy.e > 0.0)) return 0;
+        te = -INFINITY;
+        tx = INFINITY;
+    } else {
+        /* e = R^2 - dist^2 moves by up to 2 (R + dist) delta per unit of R and dist */
+        if (!decide(S, cy.e >= 0.0, cy.e, 4.0 * (R + cy.dist) * delta)) return 0;
+        te = cy.t_cpa - cy.s;                            /* a flipped tangency: s = 0 */
+        tx = cy.t_cpa + cy.s;
+        ec = cyl_err(delta, &cy, a, R);
+    }
     const double enter = fmax(te, lo), leave = fmin(tx, hi);
-    if (!decide(S, enter <= leave, leave, enter)) return 0;
+    const double e_enter = te >= lo ? ec : elo, e_leave = tx <= hi ? ec : ehi;
+    if (!decide(S, enter <= leave, leave - enter, e_enter + e_leave)) return 0;
 
     if (level >= S->depth) {
         const double t = enter;
         const double c = dot3(a, a);
         double ul = 0.0;
         if (c > 0.0) {
-            const v4 h = mk4(-q[0].x, -q[0].y, t - q[0].z, 0.0);
+            const v4 h = mk4(-N->o.x, -N->o.y, t - N->o.z, 0.0);
             ul = fmin(1.0, fmax(0.0, dot3(h, a) / c));
         }
         S->t = t;
@@ -290,38 +430,38 @@ static int visit(search_t *S, const v4 q[4], double lo, double hi,
     }
 
     S->splits++;
-    v4 L[4], Rc[4];
-    split_half(q, L, Rc);
+    node_t Lc, Rc;
+    split_node(N, &Lc, &Rc);
     const v4 n = split_normal(q);
-    const v4 s = L[3];
-    const double c = dot3(s, n);
+    const double c = dot3(N->o, n) + dot3(Lc.q[3], n);    /* <split point, n> */
     int go_right, both;
-    double flo = lo, fhi = hi;
+    double flo = lo, fhi = hi, eflo = elo, efhi = ehi;
     if (n.z != 0.0) {
         const double tp = c / n.z;
-        const int beyond_entry = decide(S, tp > te, tp, te);
-        const int before_exit = decide(S, tp < tx, tx, tp);
+        const double ep = plane_err(delta, n, tp);
+        const int beyond_entry = decide(S, tp > te, tp - te, ep + ec);
+        const int before_exit = decide(S, tp < tx, tx - tp, ep + ec);
         go_right = beyond_entry != (n.z > 0.0);
         both = beyond_entry && before_exit;
-        if (beyond_entry) fhi = fmin(fhi, tp);
-        else              flo = fmax(flo, tp);
+        if (beyond_entry) { if (tp < fhi) { fhi = tp; efhi = ep; } }
+        else              { if (tp > flo) { flo = tp; eflo = ep; } }
     } else {
         const double side = -c;            /* <(0,0,t) - s, n> for every t */
         go_right = side > 0.0;
         both = side == 0.0;
     }
     const double um = 0.5 * (u0 + u1);
-    const v4 *first = go_right ? Rc : L;
-    const v4 *second = go_right ? L : Rc;
+    const node_t *first = go_right ? &Rc : &Lc;
+    const node_t *second = go_right ? &Lc : &Rc;
     const double f0 = go_right ? um : u0, f1 = go_right ? u1 : um;
     const double s0 = go_right ? u0 : um, s1 = go_right ? um : u1;
 
-    if (visit(S, first, flo, fhi, level + 1, f0, f1)) return 1;
+    if (visit(S, first, flo, fhi, eflo, efhi, level + 1, f0, f1)) return 1;
     if (!both) return 0;
     S->backtracks++;
-    double blo, bhi;
-    cap_interval(second, S->tmax, &blo, &bhi);
-    return visit(S, second, blo, bhi, level + 1, s0, s1);
+    double blo, bhi, eblo, ebhi;
+    cap_interval_e(second->o, second->q, S->tmax, node_err(S, level + 1), &blo, &bhi, &eblo, &ebhi);
+    return visit(S, second, blo, bhi, eblo, ebhi, level + 1, s0, s1);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -334,12 +474,12 @@ int fo_version(void) { return 1; }
  * (x, y, z, r). stats (may be NULL) receives node tests, splits, backtracks
  * and the level of the leaf that was hit (-1 on a miss). Returns 1 on a hit. */
 static int intersect_with_ties(const double ray[7], const double fiber[16], int depth,
-                               double eps, uint64_t flip_mask, int *n_ties,
+                               double scale, uint64_t flip_mask, int *n_ties,
                                double *t_out, double *u_out, int64_t stats[4])
 {
     search_t S;
     memset(&S, 0, sizeof S);
-    S.ties.eps = eps;
+    S.ties.scale = scale;
     S.ties.flip_mask = flip_mask;
     S.depth = depth;
     S.tmax = ray[6];
@@ -348,9 +488,12 @@ static int intersect_with_ties(const double ray[7], const double fiber[16], int 
     v4 q[4];
     if (depth >= 0 && depth <= 23 && ray[6] == ray[6] &&
         ray_frame(ray, ray + 3, fiber, q, NULL)) {
-        double lo, hi;
-        cap_interval(q, S.tmax, &lo, &hi);
-        if (visit(&S, q, lo, hi, 0, 0.0, 1.0) && S.t < S.tmax) hit = 1;
+        double lo, hi, elo, ehi;
+        for (int k = 0; k < 4; ++k)
+            S.ties.X = fmax(S.ties.X, fmax(fabs(q[k].x), fmax(fabs(q[k].y), fabs(q[k].z))));
+        const node_t root = anchored(q);
+        cap_interval_e(root.o, root.q, S.tmax, node_err(&S, 0), &lo, &hi, &elo, &ehi);
+        if (visit(&S, &root, lo, hi, elo, ehi, 0, 0.0, 1.0) && S.t < S.tmax) hit = 1;
     }
     if (!hit) { S.t = INFINITY; S.u = NAN; S.level = -1; }
     *t_out = S.t;
@@ -369,23 +512,24 @@ int fo_intersect_d(const double ray[7], const double fiber[16], int depth,
 }
 
 /* Every result reachable from one pair by flipping at most max_flips (1 or 2)
- * near-tie decisions (relative margin <= eps). Writes up to max_out results
- * (t, u, hit), the unflipped one first; returns how many were written. */
-int fo_tie_outcomes(const double ray[7], const double fiber[16], int depth, double eps,
+ * near-tie decisions (sides within `scale` times their FP32 error bounds,
+ * R14). Writes up to max_out results (t, u, hit), the unflipped one first;
+ * returns how many were written. */
+int fo_tie_outcomes(const double ray[7], const double fiber[16], int depth, double scale,
                     int max_flips, int max_out, double *t_out, double *u_out, int *hit_out)
 {
     int n = 0, k0 = 0;
     double t, u;
-    int h = intersect_with_ties(ray, fiber, depth, eps, 0, &k0, &t, &u, NULL);
+    int h = intersect_with_ties(ray, fiber, depth, scale, 0, &k0, &t, &u, NULL);
     if (max_out < 1) return 0;
     t_out[n] = t; u_out[n] = u; hit_out[n] = h; n++;
     for (int j = 0; j < k0 && j < 64 && n < max_out; ++j) {
         int kj = 0;
-        h = intersect_with_ties(ray, fiber, depth, eps, 1ull << j, &kj, &t, &u, NULL);
+        h = intersect_with_ties(ray, fiber, depth, scale, 1ull << j, &kj, &t, &u, NULL);
         t_out[n] = t; u_out[n] = u; hit_out[n] = h; n++;
         if (max_flips < 2) continue;
         for (int k = j + 1; k < kj && k < 64 && n < max_out; ++k) {
-            h = intersect_with_ties(ray, fiber, depth, eps, (1ull << j) | (1ull << k), NULL,
+            h = intersect_with_ties(ray, fiber, depth, scale, (1ull << j) | (1ull << k), NULL,
                                     &t, &u, NULL);
             t_out[n] = t; u_out[n] = u; hit_out[n] = h; n++;
         }
@@ -473,7 +617,8 @@ void fo_cap_interval(const double q[16], double tmax, double out[2])
 {
     v4 a[4];
     for (int k = 0; k < 4; ++k) a[k] = mk4(q[4 * k], q[4 * k + 1], q[4 * k + 2], q[4 * k + 3]);
-    cap_interval(a, tmax, &out[0], &out[1]);
+    const node_t n = anchored(a);
+    cap_interval_e(n.o, n.q, tmax, 0.0, &out[0], &out[1], NULL, NULL);
 }
 
 int fo_ray_frame(const double ray[7], const double fiber[16], double out[16])

@@ -18,8 +18,10 @@ comparison is an exact tie (for example a ray that enters a leaf cylinder
 exactly where it crosses an ancestor's split plane). A pair that misses the
 bar above is accepted when the device result meets the same bar against one
 of the results the oracle reaches by flipping at most two comparisons whose
-relative margin is below TIE_EPS; such pairs are counted as
-``tie_resolved``.
+sides differ by less than their FP32 error bounds (the oracle derives them
+from a bound on the rounding of an FP32 node's coordinates, (2 + 2 level)
+2^-24 times the root's extent, times each comparison's sensitivity); such
+pairs are counted as ``tie_resolved``, and callers bound that count.
 """
 from __future__ import annotations
 
@@ -29,7 +31,7 @@ import oracle
 
 BAND = 1e-4
 T_REL_TOL = 1e-5
-TIE_EPS = 1e-5
+TIE_SCALE = 1.0      # multiple of the oracle's FP32 error bounds that makes a tie
 
 
 class Band:
@@ -83,7 +85,7 @@ def tie_resolver(w, depth=None):
         ri = int(w.pair_ray[i]) if w.pair_ray is not None else i
         fi = int(w.pair_fiber[i]) if w.pair_fiber is not None else i
         d = int(w.pair_depth[i]) if w.pair_depth is not None else d0
-        return oracle.tie_outcomes(w.rays[:, ri], w.fibers[:, fi], d, eps=TIE_EPS)
+        return oracle.tie_outcomes(w.rays[:, ri], w.fibers[:, fi], d, scale=TIE_SCALE)
     return alt
 
 

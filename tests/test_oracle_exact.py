@@ -180,3 +180,46 @@ def test_exact_degenerate():
     assert kind == 0
     kind, t, u = oracle.single_exact(np.array([0, 0, -5, 0, 0, 0, 100]), fib)
     assert kind == 0
+
+
+@pytest.mark.parametrize("ends", ["start", "both"])
+def test_zero_end_tangent_straight_fiber_is_the_capped_cylinder(ends):
+    """p1 = p0 (and p2 = p3): the straight fiber's parametrisation stalls at
+    the end, C'(0) = 0, but the swept solid is still the capped cylinder. Its
+    end disc is normal to the limit of C'(u) as u -> 0 (p2 - p0); without it
+    the rays that enter through that cap would be missed. The depth-d method
+    gives the same solid (its zero-tangent caps fall back to the same edge)."""
+    w = W.exact_straight_fibers(1500, seed=W.SEED_BASE + 23, cap_fraction=0.5)
+    P = W.unpack_fibers(w.fibers).copy()
+    P[:, 1, :3] = P[:, 0, :3]
+    if ends == "both":
+        P[:, 2, :3] = P[:, 3, :3]
+    fibers = W.pack_fibers(P)
+    assert np.array_equal(W.unpack_fibers(fibers), P)      # exact in float32
+    O, D, tmax = unpack_rays(w.rays)
+    r = P[:, 0, 3]
+    A, B = P[:, 0, :3], P[:, 3, :3]
+    t_cf, u_cf, h_cf = capped_cylinder(O, D, A, B, r, tmax)
+    _, _, h_lo = capped_cylinder(O, D, A, B, r * (1 - 1e-7), tmax)
+    _, _, h_hi = capped_cylinder(O, D, A, B, r * (1 + 1e-7), tmax)
+    stable = h_lo == h_hi
+    t, u, h, kind = oracle.intersect_exact(w.rays, fibers)
+    h = h.astype(bool)
+    assert np.array_equal(h[stable], h_cf[stable])
+    assert (kind == 2).sum() > 50 and (kind == 3).sum() > 50
+    b = stable & h_cf & h
+    assert np.max(np.abs(t[b] - t_cf[b]) / t_cf[b]) < 1e-11
+    # cap hits report the end parameter; side hits a parameter whose point
+    # lies at the closed form's axial position
+    cap = b & ((kind == 2) | (kind == 3))
+    assert np.all(u[cap] == np.where(kind[cap] == 2, 0.0, 1.0))
+    side = b & (kind == 1)
+    Cu = bezier(P[side][:, :, :3], u[side][:, None])[:, 0]
+    axial = np.sum((Cu - A[side]) * (B[side] - A[side]), axis=1) / np.sum((B[side] - A[side]) ** 2, axis=1)
+    assert np.abs(axial - u_cf[side]).max() < 1e-9
+    for d in (4, 22):
+        td, ud, hd = oracle.intersect_depth(w.rays, fibers, d)
+        hd = hd.astype(bool)
+        assert np.array_equal(hd[stable], h_cf[stable]), d
+        bd = stable & h_cf & hd
+        assert np.max(np.abs(td[bd] - t_cf[bd]) / t_cf[bd]) < 1e-11, d

@@ -1,0 +1,86 @@
+"""The pins catch plausible mistakes in the oracle (CPU only).
+
+Each mutant is a copy of the oracle's C sources with one planted mistake (a
+flipped comparison, a dropped term, a wrong index or sign). It is built into
+a temporary library and the pin suites run against it; every mutant must
+make at least one pin fail. The mistakes are planted in copies only: the
+oracle in the tree is never changed."""
+import os
+import subprocess
+import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+from oracle import build as oracle_build
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+D, X = "fiber_oracle.c", "fiber_exact.c"
+
+# (name, file, text, replacement): the first occurrence of text is replaced
+MUTANTS = [
+    ("first child chosen the wrong way", D, "go_right = beyond_entry != (n.z > 0.0);",
+     "go_right = beyond_entry == (n.z > 0.0);"),
+    ("second child never visited", D, "if (!both) return 0;", "if (1) return 0;"),
+    ("radius without the control-point distance", D, "return sqrt(fmax(d1, d2)) + rmax;", "return rmax;"),
+    ("interval narrowed on the wrong side", D, "if (beyond_entry) { if (tp < fhi)", "if (!beyond_entry) { if (tp < fhi)"),
+    ("leaf t without the cap plane", D, "const double t = enter;", "const double t = te;"),
+    ("visibility without the cropped interval", D, "decide(S, enter <= leave,", "decide(S, tx >= lo && te <= hi,"),
+    ("wrong sign in the ray-axis distance", D, "const double dd = a.x * o.y - a.y * o.x;",
+     "const double dd = a.x * o.y + a.y * o.x;"),
+    ("wrong de Casteljau split point", D, "const v4 s = scale4(add4(m012, m123), 0.5);",
+     "const v4 s = scale4(add4(m012, m12), 0.5);"),
+    ("chord instead of tangent as split normal", D, "v4 t = sub4(add4(q[2], q[3]), add4(q[0], q[1]));",
+     "v4 t = sub4(q[3], q[0]);"),
+    ("no interval recomputation after backtracking", D,
+     "return visit(S, second, blo, bhi, eblo, ebhi, level + 1, s0, s1);",
+     "return visit(S, second, lo, hi, elo, ehi, level + 1, s0, s1);"),
+    ("tangents negligible only when exactly zero", D, "return dot3(v, v) <= 0x1p-40 * dot3(chord, chord);",
+     "return zero3(v);"),
+    ("tie margin 2^10 too wide", D, "return (2.0 + 2.0 * level) * 0x1p-24 * S->ties.X;",
+     "return (2.0 + 2.0 * level) * 0x1p-14 * S->ties.X;"),
+    ("exact oracle: radius term with the wrong sign", X, "F = badd(&F, &a3, -1.0);", "F = badd(&F, &a3, 1.0);"),
+    ("exact oracle: no limit disc at a zero end tangent", X, "while (j < 2 && cand[j][0]", "while (0 && cand[j][0]"),
+    ("exact oracle: circle point on the wrong side", X,
+     "tsq = fabs((tm - C[2]) * D[2] - xy) <= fabs((tp - C[2]) * D[2] - xy) ? tm : tp;",
+     "tsq = fabs((tm - C[2]) * D[2] - xy) <= fabs((tp - C[2]) * D[2] - xy) ? tp : tm;"),
+]
+
+
+def _run_mutant(m, tmp):
+    name, fname, text, repl = m
+    srcs = []
+    for f in oracle_build.SOURCES:
+        with open(os.path.join(oracle_build.HERE, f)) as fh:
+            src = fh.read()
+        if f == fname:
+            assert text in src, f"mutation site gone: {name}"
+            src = src.replace(text, repl, 1)
+        path = os.path.join(tmp, f)
+        with open(path, "w") as fh:
+            fh.write(src)
+        srcs.append(path)
+    lib = os.path.join(tmp, "libmutant.so")
+    subprocess.run(oracle_build.gcc_cmd(srcs, lib), check=True, capture_output=True)
+    env = dict(os.environ, FIBER_ORACLE_LIB=lib, OMP_NUM_THREADS="2")
+    res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                          "tests/test_oracle_pins.py", "tests/test_oracle_exact.py"],
+                         cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    return name, res.returncode, res.stdout[-400:]
+
+
+def test_every_planted_mistake_fails_a_pin():
+    with tempfile.TemporaryDirectory() as top:
+        dirs = []
+        for k in range(len(MUTANTS)):
+            d = os.path.join(top, str(k))
+            os.makedirs(d)
+            dirs.append(d)
+        with ThreadPoolExecutor(max_workers=4) as ex:
+            results = list(ex.map(_run_mutant, MUTANTS, dirs))
+    survivors = [(name, out) for name, rc, out in results if rc == 0]
+    assert not survivors, survivors
+    # a failure must be a failed pin, not a crash or a collection error
+    for name, rc, out in results:
+        assert rc == 1, (name, rc, out)
