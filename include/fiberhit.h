@@ -20,18 +20,14 @@
  * takes an even share of the pairs and loads them into its free lanes (load,
  * FP64 move into the ray frame, root test; pairs decided at the root are
  * written out at once), keeping each busy lane's root in a slot of its own
- * (64 bytes) for the subdivision search. For single calls the library owns
- * two sets of buffers per device (root slots, 4 KiB per resident wave, about
- * 24 MiB on MI355X; fiber records, below), allocated at the first call on
- * that device and kept for the process; calls that share a set are ordered on
- * the GPU through an event, so calls on different streams stay correct. When
- * a single call gathers fibers through pair_fiber with at least as many
- * pairs as fibers, the fibers are first copied to 64-byte records (one
- * gathered fiber is then one or two cache lines instead of sixteen), in a
- * per-set buffer that grows to the largest such call (up to 1 GiB; beyond
- * that the gather reads the rows directly). Batched calls keep their root
- * slots in the caller's workspace or the plan, and allocate nothing on the
- * call path.
+ * (64 bytes) for the subdivision search. The library allocates nothing while
+ * a call runs: the root slots (4 KiB per resident wave, about 24 MiB on
+ * MI355X) and, for calls that gather fibers through an index, a copy of the
+ * fibers as 64-byte records live in a workspace the caller sizes with
+ * fiber_pairs_workspace_bytes (single calls), fiber_batched_workspace_bytes
+ * (batches) or inside a plan. Device set-up (unit counts, occupancy, pinned
+ * staging of batched scene tables) happens once per device, at
+ * fi_init_device or at the first call on that device.
  *
  * Layouts (structure of arrays, 32-bit floats, row-major):
  *   rays   : 7 rows of ray_stride floats  -- ox, oy, oz, dx, dy, dz, tmax.
@@ -67,6 +63,14 @@ extern "C" {
  * reaches a leaf, decide the pair against the swept-disc solid in FP64 (see
  * fiber_intersect_pairs). */
 #define FI_FP64_REFINE   (1u << 0)
+/* FI_COMPENSATED_PROJ: accepted and always in effect. The move into the ray
+ * frame (Section 3.3) runs in FP64 from exact differences of the float32
+ * inputs, so every root coordinate is the correctly rounded float32 of its
+ * exact value -- at least as accurate as compensated FP32 products. The
+ * per-pair work counts (node tests, splits, backtracks, leaf level) that a
+ * statistics flag would add are the separate entry point
+ * fiber_intersect_counts. */
+#define FI_COMPENSATED_PROJ (1u << 1)
 
 /* Largest subdivision depth: one bit per level in 32-bit integers and an
  * integer parametric position below 2^23 (Section 3.3, interval conversion). */
@@ -77,6 +81,24 @@ int fi_version(void);
 
 /* Static English text for a status code. */
 const char *fi_strerror(int status);
+
+/* Set-up of the current device: unit counts, the occupancy of every kernel
+ * variant and the pinned host buffers that stage batched scene tables.
+ * Every entry point does this on its first call on a device; callers that
+ * must not allocate during later calls run it once beforehand. FI_OK or
+ * FI_ERR_HIP. */
+int fi_init_device(void);
+
+/* Bytes of device workspace one fiber_intersect_pairs or
+ * fiber_intersect_counts call of n_pairs pairs over a table of n_fibers
+ * fibers needs on the current device (0 for negative counts or when the
+ * device cannot be queried): the root slots (4 KiB per resident wave; fixed
+ * per device) plus, when gathered is non-zero (pair_fiber given) and
+ * n_pairs >= n_fibers, n_fibers 64-byte fiber records (tables up to 1 GiB).
+ * A workspace of at least the slot size but without room for the records
+ * is accepted: the gather then reads the fiber rows in place (same
+ * results). flags is reserved (the size does not depend on it). */
+size_t fiber_pairs_workspace_bytes(int64_t n_pairs, int64_t n_fibers, int32_t gathered, uint32_t flags);
 
 /*
  * fiber_intersect_pairs -- nearest hit of each (ray, fiber) pair at depth d.
@@ -100,10 +122,15 @@ const char *fi_strerror(int status);
  *   depth                          0 .. FI_MAX_DEPTH (checked even when pair_depth
  *                                  is given).
  *   n_pairs                        >= 0; 0 enqueues nothing and returns FI_OK.
- *   flags                          0 or FI_FP64_REFINE.
+ *   flags                          FI_FP64_REFINE and/or FI_COMPENSATED_PROJ.
  *   t_out, u_out, hit_out          n_pairs each. On a miss: t = +inf, u = NaN, hit = 0.
  *   t64_out, u64_out               n_pairs doubles each; required with
  *                                  FI_FP64_REFINE, ignored (may be NULL) without.
+ *   workspace, workspace_bytes     caller-owned device memory, 256-byte aligned,
+ *                                  of at least fiber_pairs_workspace_bytes(...)
+ *                                  bytes (see there). It must not be used by
+ *                                  another call still in flight; its contents on
+ *                                  entry do not matter.
  *   stream                         hipStream_t or NULL.
  *
  * FI_FP64_REFINE: the method's leaf cylinders converge to the solid swept by
@@ -128,8 +155,10 @@ const char *fi_strerror(int status);
  * counts, strides below the counts, a depth outside [0, 23], unknown flags,
  * an identity pairing longer than its ray or fiber table, or
  * n_pairs >= 2^31 - 64;
- * FI_ERR_HIP when the launch fails or the first call on a device cannot
- * allocate its buffers. Nothing is enqueued on an argument error.
+ * FI_ERR_WORKSPACE when the workspace is NULL, not 256-byte aligned or
+ * smaller than the root slots; FI_ERR_HIP when the launch fails or the
+ * device set-up fails. Nothing is enqueued on an argument error. The call
+ * allocates, frees and waits for nothing.
  */
 int fiber_intersect_pairs(const float *rays, int64_t ray_stride, int64_t n_rays,
                           const float *fibers, int64_t fiber_stride, int64_t n_fibers,
@@ -138,7 +167,7 @@ int fiber_intersect_pairs(const float *rays, int64_t ray_stride, int64_t n_rays,
                           uint32_t flags,
                           float *t_out, float *u_out, uint8_t *hit_out,
                           double *t64_out, double *u64_out,
-                          void *stream);
+                          void *workspace, size_t workspace_bytes, void *stream);
 
 /*
  * fiber_intersect_counts -- the traversal of fiber_intersect_pairs with its
@@ -151,8 +180,9 @@ int fiber_intersect_pairs(const float *rays, int64_t ray_stride, int64_t n_rays,
  * sibling) and the level of the leaf that was hit (-1 on a miss). These are
  * the units of the algorithmic work model.
  *
- * Errors: as fiber_intersect_pairs; counts_out must not be NULL and flags
- * must be 0.
+ * Errors: as fiber_intersect_pairs; counts_out must not be NULL and
+ * FI_FP64_REFINE is not accepted. The workspace is sized as for
+ * fiber_intersect_pairs.
  */
 int fiber_intersect_counts(const float *rays, int64_t ray_stride, int64_t n_rays,
                            const float *fibers, int64_t fiber_stride, int64_t n_fibers,
@@ -160,25 +190,29 @@ int fiber_intersect_counts(const float *rays, int64_t ray_stride, int64_t n_rays
                            const uint8_t *pair_depth, int32_t depth, int64_t n_pairs,
                            uint32_t flags,
                            float *t_out, float *u_out, uint8_t *hit_out,
-                           int32_t *counts_out, void *stream);
+                           int32_t *counts_out, void *workspace, size_t workspace_bytes,
+                           void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Many independent problems in one launch                                  */
 /* ------------------------------------------------------------------------ */
 
-/* One problem: the arguments of one fiber_intersect_pairs call (flags 0).
- * All pointers are device pointers owned by the caller. */
+/* One problem: the arguments of one fiber_intersect_pairs call (the flags
+ * are the batch's). All pointers are device pointers owned by the caller;
+ * t64_out and u64_out are read only when the batch runs with
+ * FI_FP64_REFINE. */
 typedef struct fi_scene {
     const float *rays;   int64_t ray_stride;   int64_t n_rays;
     const float *fibers; int64_t fiber_stride; int64_t n_fibers;
     const int32_t *pair_ray; const int32_t *pair_fiber; const uint8_t *pair_depth;
     int32_t depth;       int64_t n_pairs;
     float *t_out; float *u_out; uint8_t *hit_out;
+    double *t64_out; double *u64_out;
 } fi_scene;
 
 /* Launch tuning of the batched kernel (not part of the method):
  *   refill          refill a wave's finished lanes once at least this many
- *                   (1..64) are free;
+ *                   (1..64) are free (defaults: 48, and 8 with FI_FP64_REFINE);
  *   waves_per_simd  cap on resident waves per SIMD (0..16, 0 = as many as fit,
  *                   which is 6 for the batched kernel).
  * Results never depend on the tuning. */
@@ -207,12 +241,17 @@ size_t fiber_batched_workspace_bytes(int32_t n_scenes, int64_t total_pairs);
  * Arguments: scenes is a host array of n_scenes descriptors (the library
  * copies it before returning); tuning may be NULL (the autotuned entry of
  * this batch's size class if fiber_batch_autotune ran, else defaults);
- * flags must be 0;
- * workspace is caller-owned device memory of at least
+ * flags: FI_FP64_REFINE (every scene then needs t64_out and u64_out; the
+ * per-pair meaning is that of fiber_intersect_pairs with that flag) and/or
+ * FI_COMPENSATED_PROJ;
+ * workspace is caller-owned device memory, 256-byte aligned, of at least
  * fiber_batched_workspace_bytes(n_scenes, total pairs) bytes, which must not
- * be used by another call that is still in flight.
+ * be used by another call that is still in flight. The call allocates
+ * nothing; it waits (rarely) for the upload of the scene table four batched
+ * calls earlier to leave its pinned staging buffer.
  *
- * Errors: FI_ERR_NULL (scenes NULL or a NULL pointer inside a scene),
+ * Errors: FI_ERR_NULL (scenes NULL or a NULL pointer inside a scene, t64_out
+ * or u64_out included under FI_FP64_REFINE),
  * FI_ERR_RANGE (bad counts, strides, depths, tuning, flags, more than 2^31-64
  * pairs in total or a scene table over 1 MiB), FI_ERR_WORKSPACE, FI_ERR_HIP.
  */
@@ -221,10 +260,12 @@ int fiber_intersect_batched(const fi_scene *scenes, int32_t n_scenes, const fi_t
 
 /*
  * Plans: the scene table is uploaded once into device memory the plan owns
- * (with its root slots), and the launch (one kernel) is captured into a HIP graph
- * that fiber_batch_plan_launch replays on any stream. Creating and destroying a plan allocates and frees device memory;
- * launching does not. One plan must not be launched on two streams at once.
- * The scenes' device buffers must outlive the plan.
+ * (with its root slots), and the launch (one kernel) is captured into a HIP
+ * graph that fiber_batch_plan_launch replays on any stream. Scenes, tuning
+ * and flags mean what they mean for fiber_intersect_batched. Creating and
+ * destroying a plan allocates and frees device memory; launching does not.
+ * One plan must not be launched on two streams at once. The scenes' device
+ * buffers must outlive the plan.
  */
 typedef struct fi_batch_plan fi_batch_plan;
 
@@ -236,13 +277,14 @@ int fiber_batch_plan_destroy(fi_batch_plan *plan);
 
 /*
  * fiber_batch_autotune -- time fiber_intersect_batched on these scenes over a
- * grid of tunings (refill 32, 48 or 56; waves per SIMD 4, 5 or as many as
- * fit), each `repeats`
+ * grid of tunings (refill 32, 48 or 56, with FI_FP64_REFINE 4, 8 or 16;
+ * waves per SIMD 4, 5 or as many as fit), each `repeats`
  * times after one warm-up, and return the fastest
  * in *best (and its time in *best_ms if not NULL). Overwrites the scenes'
  * outputs. Blocks the host until the timing runs finish. The result is also
  * remembered for the process, keyed by device and the batch's size class
- * (log2 of total pairs and of the problem count): later batched calls and
+ * (log2 of total pairs and of the problem count) and the refinement flag:
+ * later batched calls and
  * plans of that class that pass tuning = NULL use it.
  */
 int fiber_batch_autotune(const fi_scene *scenes, int32_t n_scenes, uint32_t flags, void *workspace,

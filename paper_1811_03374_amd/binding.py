@@ -17,6 +17,7 @@ from . import build_lib
 FI_OK = 0
 FI_MAX_DEPTH = 23
 FI_FP64_REFINE = 1
+FI_COMPENSATED_PROJ = 2
 
 _lib = None
 
@@ -35,10 +36,13 @@ def lib():
         L = C.CDLL(build_lib.LIB)
         i64, vp, u32, i32 = C.c_int64, C.c_void_p, C.c_uint32, C.c_int32
         common = [vp, i64, i64, vp, i64, i64, vp, vp, vp, i32, i64, u32, vp, vp, vp]
-        L.fiber_intersect_pairs.argtypes = common + [vp, vp, vp]
+        L.fiber_intersect_pairs.argtypes = common + [vp, vp, vp, C.c_size_t, vp]
         L.fiber_intersect_pairs.restype = C.c_int
-        L.fiber_intersect_counts.argtypes = common + [vp, vp]
+        L.fiber_intersect_counts.argtypes = common + [vp, vp, C.c_size_t, vp]
         L.fiber_intersect_counts.restype = C.c_int
+        L.fiber_pairs_workspace_bytes.argtypes = [i64, i64, i32, u32]
+        L.fiber_pairs_workspace_bytes.restype = C.c_size_t
+        L.fi_init_device.restype = C.c_int
         L.fi_strerror.argtypes = [C.c_int]
         L.fi_strerror.restype = C.c_char_p
         L.fi_version.restype = C.c_int
@@ -47,7 +51,8 @@ def lib():
 
 
 def exported_symbols():
-    return ["fi_version", "fi_strerror", "fiber_intersect_pairs", "fiber_intersect_counts",
+    return ["fi_version", "fi_strerror", "fi_init_device", "fiber_pairs_workspace_bytes",
+            "fiber_intersect_pairs", "fiber_intersect_counts",
             "fiber_batched_workspace_bytes", "fiber_intersect_batched", "fiber_batch_plan_create",
             "fiber_batch_plan_launch", "fiber_batch_plan_tuning", "fiber_batch_plan_destroy",
             "fiber_batch_autotune"]
@@ -80,6 +85,26 @@ def _index(t: Optional[torch.Tensor], dtype, name: str):
     return t
 
 
+def _pair_count(rays, fibers, pr, pf, pd):
+    """Number of pairs of a call, with every given per-pair tensor of exactly
+    that length (the C ABI cannot check the length of a device array)."""
+    given = [(name, x) for name, x in (("pair_ray", pr), ("pair_fiber", pf), ("pair_depth", pd))
+             if x is not None]
+    if given:
+        n = given[0][1].shape[0]
+        for name, x in given:
+            if x.shape[0] != n:
+                raise ValueError(f"{name} has {x.shape[0]} elements, expected {n} "
+                                 f"(all per-pair tensors must have the same length)")
+    else:
+        n = min(rays.shape[1], fibers.shape[1])
+    if pr is None and n > rays.shape[1]:
+        raise ValueError(f"identity ray pairing: {n} pairs but only {rays.shape[1]} rays")
+    if pf is None and n > fibers.shape[1]:
+        raise ValueError(f"identity fiber pairing: {n} pairs but only {fibers.shape[1]} fibers")
+    return n
+
+
 def _outs(out, n: int, dev):
     """Output tensors (t, u, hit) for n pairs: new ones, or the caller's after
     a check that the kernel cannot write past them."""
@@ -100,49 +125,68 @@ def _stream(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
+def pairs_workspace(n: int, n_fibers: int, gathered: bool, device) -> torch.Tensor:
+    """Device workspace of one fiber_intersect_pairs call (root slots, and
+    fiber records for a gathered call), sized by the library."""
+    with torch.cuda.device(device):
+        nbytes = lib().fiber_pairs_workspace_bytes(int(n), int(n_fibers), int(bool(gathered)), 0)
+    if nbytes == 0:
+        raise FiberHitError("fiber_pairs_workspace_bytes failed (no usable device)")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def _keep_for(ws: torch.Tensor, stream):
+    """A workspace freed after a call on another stream than the current one
+    must not be reused by the allocator before that stream passes the call."""
+    if stream is not None and stream != torch.cuda.current_stream(ws.device):
+        ws.record_stream(stream)
+
+
 def intersect_pairs(rays: torch.Tensor, fibers: torch.Tensor, depth: int = 9,
                     pair_ray: Optional[torch.Tensor] = None,
                     pair_fiber: Optional[torch.Tensor] = None,
                     pair_depth: Optional[torch.Tensor] = None,
-                    out=None, counts: bool = False, refine: bool = False, stream=None):
+                    out=None, counts: bool = False, refine: bool = False, stream=None,
+                    workspace: Optional[torch.Tensor] = None):
     """Nearest hit (t, u, hit) of every (ray, fiber) pair at subdivision depth
     ``depth`` (or per-pair ``pair_depth``). See ``fiber_intersect_pairs``.
 
     rays: (7, n_rays) float32; fibers: (16, n_fibers) float32; indices int32.
     Returns (t, u, hit) device tensors, plus an (n, 4) int32 tensor of node
     tests / splits / backtracks / leaf level when ``counts`` is set, or the
-    float64 (t64, u64) of the FP64 surface refinement when ``refine`` is set."""
+    float64 (t64, u64) of the FP64 surface refinement when ``refine`` is set.
+    ``workspace`` (uint8 device tensor, see ``pairs_workspace``) is allocated
+    per call when not given."""
     rs = _table(rays, 7, "rays")
     fs = _table(fibers, 16, "fibers")
     pr = _index(pair_ray, torch.int32, "pair_ray")
     pf = _index(pair_fiber, torch.int32, "pair_fiber")
     pd = _index(pair_depth, torch.uint8, "pair_depth")
-    if pr is not None:
-        n = pr.shape[0]
-    elif pf is not None:
-        n = pf.shape[0]
-    elif pd is not None:
-        n = pd.shape[0]
-    else:
-        n = min(rays.shape[1], fibers.shape[1])
+    n = _pair_count(rays, fibers, pr, pf, pd)
     dev = rays.device
     t, u, hit = _outs(out, n, dev)
     if counts and refine:
         raise ValueError("counts and refine are separate passes")
+    if workspace is None:
+        workspace = pairs_workspace(n, fibers.shape[1], pf is not None, dev)
+        _keep_for(workspace, stream)
+    elif workspace.dtype != torch.uint8 or not workspace.is_cuda or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous uint8 device tensor")
+    ws = (C.c_void_p(workspace.data_ptr()), workspace.numel())
     cn = torch.empty((n, 4), dtype=torch.int32, device=dev) if counts else None
     flags = FI_FP64_REFINE if refine else 0
     args = [_ptr(rays), rs, rays.shape[1], _ptr(fibers), fs, fibers.shape[1],
             _ptr(pr), _ptr(pf), _ptr(pd), int(depth), n, flags,
             _ptr(t), _ptr(u), _ptr(hit)]
     if counts:
-        _check(lib().fiber_intersect_counts(*args, _ptr(cn), _stream(stream)))
+        _check(lib().fiber_intersect_counts(*args, _ptr(cn), *ws, _stream(stream)))
         return t, u, hit, cn
     if refine:
         t64 = torch.empty(n, dtype=torch.float64, device=dev)
         u64 = torch.empty(n, dtype=torch.float64, device=dev)
-        _check(lib().fiber_intersect_pairs(*args, _ptr(t64), _ptr(u64), _stream(stream)))
+        _check(lib().fiber_intersect_pairs(*args, _ptr(t64), _ptr(u64), *ws, _stream(stream)))
         return t, u, hit, t64, u64
-    _check(lib().fiber_intersect_pairs(*args, None, None, _stream(stream)))
+    _check(lib().fiber_intersect_pairs(*args, None, None, *ws, _stream(stream)))
     return t, u, hit
 
 
@@ -151,8 +195,9 @@ class PreparedPairs:
     checked and marshalled once and then enqueued as often as needed, on any
     stream (serving loops, benchmarks): ``launch`` skips the per-call tensor
     checks and argument building of ``intersect_pairs``. The object keeps its
-    input tensors alive and owns (or takes, via ``out``) the output tensors
-    t, u, hit, which every launch overwrites."""
+    input tensors alive and owns its workspace and (or takes, via ``out``)
+    the output tensors t, u, hit, which every launch overwrites; launches of
+    one object must not overlap (they share the workspace)."""
 
     def __init__(self, rays, fibers, depth=9, pair_ray=None, pair_fiber=None, pair_depth=None,
                  out=None):
@@ -161,20 +206,15 @@ class PreparedPairs:
         pr = _index(pair_ray, torch.int32, "pair_ray")
         pf = _index(pair_fiber, torch.int32, "pair_fiber")
         pd = _index(pair_depth, torch.uint8, "pair_depth")
-        if pr is not None:
-            n = pr.shape[0]
-        elif pf is not None:
-            n = pf.shape[0]
-        elif pd is not None:
-            n = pd.shape[0]
-        else:
-            n = min(rays.shape[1], fibers.shape[1])
+        n = _pair_count(rays, fibers, pr, pf, pd)
         self.t, self.u, self.hit = _outs(out, n, rays.device)
+        self.workspace = pairs_workspace(n, fibers.shape[1], pf is not None, rays.device)
         self._keep = (rays, fibers, pr, pf, pd)
         self._fn = lib().fiber_intersect_pairs
         self._args = (_ptr(rays), rs, rays.shape[1], _ptr(fibers), fs, fibers.shape[1],
                       _ptr(pr), _ptr(pf), _ptr(pd), int(depth), n, 0,
-                      _ptr(self.t), _ptr(self.u), _ptr(self.hit), None, None)
+                      _ptr(self.t), _ptr(self.u), _ptr(self.hit), None, None,
+                      C.c_void_p(self.workspace.data_ptr()), self.workspace.numel())
 
     def launch(self, stream=None):
         _check(self._fn(*self._args, _stream(stream)))
@@ -195,7 +235,8 @@ class FiScene(C.Structure):
                 ("fibers", C.c_void_p), ("fiber_stride", C.c_int64), ("n_fibers", C.c_int64),
                 ("pair_ray", C.c_void_p), ("pair_fiber", C.c_void_p), ("pair_depth", C.c_void_p),
                 ("depth", C.c_int32), ("n_pairs", C.c_int64),
-                ("t_out", C.c_void_p), ("u_out", C.c_void_p), ("hit_out", C.c_void_p)]
+                ("t_out", C.c_void_p), ("u_out", C.c_void_p), ("hit_out", C.c_void_p),
+                ("t64_out", C.c_void_p), ("u64_out", C.c_void_p)]
 
 
 class FiTuning(C.Structure):
@@ -232,27 +273,25 @@ def _batched_lib():
 
 class Problem:
     """One problem of a batch: device tensors in the layout of intersect_pairs,
-    with its own outputs (allocated here)."""
+    with its own outputs (allocated here; t64/u64 too when ``refine``)."""
 
-    def __init__(self, rays, fibers, depth=9, pair_ray=None, pair_fiber=None, pair_depth=None):
+    def __init__(self, rays, fibers, depth=9, pair_ray=None, pair_fiber=None, pair_depth=None,
+                 refine=False):
+        _table(rays, 7, "rays")
+        _table(fibers, 16, "fibers")
         self.rays, self.fibers = rays, fibers
         self.pair_ray = _index(pair_ray, torch.int32, "pair_ray")
         self.pair_fiber = _index(pair_fiber, torch.int32, "pair_fiber")
         self.pair_depth = _index(pair_depth, torch.uint8, "pair_depth")
         self.depth = int(depth)
-        if self.pair_ray is not None:
-            n = self.pair_ray.shape[0]
-        elif self.pair_fiber is not None:
-            n = self.pair_fiber.shape[0]
-        elif self.pair_depth is not None:
-            n = self.pair_depth.shape[0]
-        else:
-            n = min(rays.shape[1], fibers.shape[1])
+        n = _pair_count(rays, fibers, self.pair_ray, self.pair_fiber, self.pair_depth)
         self.n = n
         dev = rays.device
         self.t = torch.empty(n, dtype=torch.float32, device=dev)
         self.u = torch.empty(n, dtype=torch.float32, device=dev)
         self.hit = torch.empty(n, dtype=torch.uint8, device=dev)
+        self.t64 = torch.empty(n, dtype=torch.float64, device=dev) if refine else None
+        self.u64 = torch.empty(n, dtype=torch.float64, device=dev) if refine else None
 
     def scene(self):
         rs = _table(self.rays, 7, "rays")
@@ -262,7 +301,15 @@ class Problem:
                        None if self.pair_ray is None else self.pair_ray.data_ptr(),
                        None if self.pair_fiber is None else self.pair_fiber.data_ptr(),
                        None if self.pair_depth is None else self.pair_depth.data_ptr(),
-                       self.depth, self.n, self.t.data_ptr(), self.u.data_ptr(), self.hit.data_ptr())
+                       self.depth, self.n, self.t.data_ptr(), self.u.data_ptr(), self.hit.data_ptr(),
+                       None if self.t64 is None else self.t64.data_ptr(),
+                       None if self.u64 is None else self.u64.data_ptr())
+
+
+def _batch_flags(problems, refine):
+    if refine and any(p.t64 is None for p in problems):
+        raise ValueError("a refined batch needs problems made with refine=True")
+    return FI_FP64_REFINE if refine else 0
 
 
 def _scene_array(problems):
@@ -290,14 +337,16 @@ def workspace_for(problems, device=None):
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
-def intersect_batched(problems, tuning=None, workspace=None, stream=None):
+def intersect_batched(problems, tuning=None, workspace=None, stream=None, refine=False):
     """All pairs of all problems in one persistent-kernel launch (results
-    land in each Problem's t, u, hit)."""
+    land in each Problem's t, u, hit, and t64, u64 when ``refine``)."""
     L = _batched_lib()
+    flags = _batch_flags(problems, refine)
     arr = _scene_array(problems)
     if workspace is None:
         workspace = workspace_for(problems)
-    _check(L.fiber_intersect_batched(arr, len(problems), _tuning(tuning), 0,
+        _keep_for(workspace, stream)
+    _check(L.fiber_intersect_batched(arr, len(problems), _tuning(tuning), flags,
                                      C.c_void_p(workspace.data_ptr()), workspace.numel(),
                                      _stream(stream)))
     return workspace
@@ -306,12 +355,13 @@ def intersect_batched(problems, tuning=None, workspace=None, stream=None):
 class BatchPlan:
     """A batch captured once into a HIP graph; ``launch`` replays it."""
 
-    def __init__(self, problems, tuning=None):
+    def __init__(self, problems, tuning=None, refine=False):
         L = _batched_lib()
         self.problems = problems
+        flags = _batch_flags(problems, refine)
         arr = _scene_array(problems)
         h = C.c_void_p()
-        _check(L.fiber_batch_plan_create(arr, len(problems), _tuning(tuning), 0, C.byref(h)))
+        _check(L.fiber_batch_plan_create(arr, len(problems), _tuning(tuning), flags, C.byref(h)))
         self._h = h
 
     def launch(self, stream=None):
@@ -334,15 +384,16 @@ class BatchPlan:
             pass
 
 
-def autotune(problems, repeats=2, workspace=None, stream=None):
+def autotune(problems, repeats=2, workspace=None, stream=None, refine=False):
     """Fastest tuning for this batch; returns (dict, milliseconds)."""
     L = _batched_lib()
+    flags = _batch_flags(problems, refine)
     arr = _scene_array(problems)
     if workspace is None:
         workspace = workspace_for(problems)
     best = FiTuning()
     ms = C.c_float()
-    _check(L.fiber_batch_autotune(arr, len(problems), 0, C.c_void_p(workspace.data_ptr()),
+    _check(L.fiber_batch_autotune(arr, len(problems), flags, C.c_void_p(workspace.data_ptr()),
                                   workspace.numel(), _stream(stream), int(repeats), C.byref(best),
                                   C.byref(ms)))
     return best.as_dict(), ms.value

@@ -24,7 +24,7 @@
 // those of the FP64 CPU oracle (visibility needs a non-empty cropped
 // interval, the leaf t is the entry into the capped leaf cylinder, planes
 // parallel to the ray and axes parallel to the ray get explicit rules, zero
-// tangents fall back to the next non-zero control-polygon edge).
+// tangents fall back to the next non-negligible control-polygon edge).
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -71,9 +71,14 @@ __device__ __forceinline__ float dot3(float ax, float ay, float az, float bx, fl
     return fmaf(ax, bx, fmaf(ay, by, az * bz));
 }
 
-__device__ __forceinline__ bool zero3(float x, float y, float z)
+// A tangent whose squared length is at most 2^-40 of the squared chord (cc)
+// has no reliable direction: at a cusp or a vanishing end tangent its
+// components are rounding noise of the control points. The cap and split
+// planes then take the next control-polygon edge or the chord instead. With
+// a zero chord only the zero vector is negligible.
+__device__ __forceinline__ bool negligible(float x, float y, float z, float cc)
 {
-    return x == 0.0f && y == 0.0f && z == 0.0f;
+    return fmaf(x, x, fmaf(y, y, z * z)) <= 0x1p-40f * cc;
 }
 
 // ---------------------------------------------------------------------------
@@ -123,17 +128,19 @@ __device__ __forceinline__ void make_onb(double wx, double wy, double wz,
 // t interval between the node's two end-cap planes (Section 3.3, cropping),
 // intersected with [0, tmax]. Start cap: plane through p, normal t0, curve on
 // the positive side. End cap: plane through p + d, normal t1, curve on the
-// negative side. A zero tangent falls back to the next control-polygon edge.
+// negative side. A negligible end tangent falls back to the next
+// control-polygon edge from that end (p2 - p0, resp. p3 - p1), then the chord.
 __device__ __forceinline__ void cap_interval(const Node &c, float tmax, float &lo, float &hi)
 {
     float n0x = c.t0.x, n0y = c.t0.y, n0z = c.t0.z;
     float n1x = c.t1.x, n1y = c.t1.y, n1z = c.t1.z;
-    if (zero3(n0x, n0y, n0z) || zero3(n1x, n1y, n1z)) {
+    const float cc = dot3(c.d.x, c.d.y, c.d.z, c.d.x, c.d.y, c.d.z);
+    if (negligible(n0x, n0y, n0z, cc) || negligible(n1x, n1y, n1z, cc)) {
         // rare (a vanishing end tangent): kept out of the common path
-        if (zero3(n0x, n0y, n0z)) { n0x = c.d.x - c.t1.x; n0y = c.d.y - c.t1.y; n0z = c.d.z - c.t1.z; }
-        if (zero3(n0x, n0y, n0z)) { n0x = c.d.x; n0y = c.d.y; n0z = c.d.z; }
-        if (zero3(n1x, n1y, n1z)) { n1x = c.d.x - c.t0.x; n1y = c.d.y - c.t0.y; n1z = c.d.z - c.t0.z; }
-        if (zero3(n1x, n1y, n1z)) { n1x = c.d.x; n1y = c.d.y; n1z = c.d.z; }
+        if (negligible(n0x, n0y, n0z, cc)) { n0x = c.d.x - c.t1.x; n0y = c.d.y - c.t1.y; n0z = c.d.z - c.t1.z; }
+        if (negligible(n0x, n0y, n0z, cc)) { n0x = c.d.x; n0y = c.d.y; n0z = c.d.z; }
+        if (negligible(n1x, n1y, n1z, cc)) { n1x = c.d.x - c.t0.x; n1y = c.d.y - c.t0.y; n1z = c.d.z - c.t0.z; }
+        if (negligible(n1x, n1y, n1z, cc)) { n1x = c.d.x; n1y = c.d.y; n1z = c.d.z; }
     }
 
     // both crossings are computed and selected by the signs of the normals'
@@ -719,7 +726,8 @@ __device__ __forceinline__ void split_plane(const Lane &L, float te, float tx, S
 {
     split_terms(L.c, sp.dp, sp.tc);
     float nx = sp.tc.x, ny = sp.tc.y, nz = sp.tc.z;
-    if (zero3(nx, ny, nz)) {            // rare: no split tangent, split normal to the chord
+    if (negligible(nx, ny, nz, dot3(L.c.d.x, L.c.d.y, L.c.d.z, L.c.d.x, L.c.d.y, L.c.d.z))) {
+        // rare (a cusp at the split point): split normal to the chord
         nx = L.c.d.x;
         ny = L.c.d.y;
         nz = L.c.d.z;
@@ -1115,7 +1123,7 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
             }
             active = false;
         }
-        if constexpr (MODE == kConservative && !BATCHED) {
+        if constexpr (MODE == kConservative) {
             // the FP64 searches run for all parked lanes at once (SIMD lanes
             // of one call) when no busy lane is left: every lane of the wave
             // then shares the search's passes (measured: 2x faster on hair
@@ -1124,11 +1132,22 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
             if (parked != 0 && __ballot(active && !L.waiting) == 0) {
                 if (L.waiting) {
                     L.waiting = 0;
-                    const Refined r = refine_whole_curve(a0.rays, a0.ray_stride, a0.fibers, a0.fiber_stride,
-                                                         a0.pair_ray, a0.pair_fiber, L.pair, L.tmax, L.t, L.ru);
+                    // plain values, not references (see refine_whole_curve)
+                    const float *rays = a0.rays, *fibers = a0.fibers;
+                    int64_t rs = a0.ray_stride, fs = a0.fiber_stride;
+                    const int32_t *pr = a0.pair_ray, *pf = a0.pair_fiber;
+                    Outs o = outs_of(a0);
+                    if constexpr (BATCHED) {
+                        const Args *sc = scenes + L.scene;
+                        rays = sc->rays; fibers = sc->fibers;
+                        rs = sc->ray_stride; fs = sc->fiber_stride;
+                        pr = sc->pair_ray; pf = sc->pair_fiber;
+                        o = outs_of(*sc);
+                    }
+                    const Refined r = refine_whole_curve(rays, rs, fibers, fs, pr, pf, L.pair, L.tmax, L.t, L.ru);
                     L.t64 = r.t;
                     L.u64 = r.u;
-                    finish<MODE>(outs_of(a0), L.pair, L, r.hit);
+                    finish<MODE>(o, L.pair, L, r.hit);
                     active = false;
                 }
             }
@@ -1162,7 +1181,7 @@ int check_common(const float *rays, int64_t ray_stride, int64_t n_rays,
 {
     if (n_pairs < 0 || n_rays < 0 || n_fibers < 0) return FI_ERR_RANGE;
     if (depth < 0 || depth > FI_MAX_DEPTH) return FI_ERR_RANGE;
-    if ((flags & ~(uint32_t)FI_FP64_REFINE) != 0u) return FI_ERR_RANGE;
+    if ((flags & ~(uint32_t)(FI_FP64_REFINE | FI_COMPENSATED_PROJ)) != 0u) return FI_ERR_RANGE;
     if (n_pairs == 0) return FI_OK;
     if (!rays || !fibers || !t_out || !u_out || !hit_out) return FI_ERR_NULL;
     if (ray_stride < n_rays || fiber_stride < n_fibers) return FI_ERR_RANGE;
@@ -1177,41 +1196,28 @@ int check_common(const float *rays, int64_t ray_stride, int64_t n_rays,
 // ---------------------------------------------------------------------------
 
 using FusedFn = void (*)(Args, const Args *, const int64_t *, int, int64_t, float *, int, const float *);
-// [0] plain, [1] counting, [2] conservative (single calls), [3] plain over a
-// scene table
-const FusedFn kFused[4] = {k_fused<kPlain, false>, k_fused<kCount, false>, k_fused<kConservative, false>,
-                           k_fused<kPlain, true>};
+// [0] plain, [1] counting, [2] conservative (single calls), [3] plain and
+// [4] conservative over a scene table
+constexpr int kVariants = 5;
+const FusedFn kFused[kVariants] = {k_fused<kPlain, false>, k_fused<kCount, false>, k_fused<kConservative, false>,
+                                   k_fused<kPlain, true>, k_fused<kConservative, true>};
 constexpr int kBatchedVariant = 3;
+constexpr int kBatchedRefineVariant = 4;
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-// Single-problem calls keep kRegions sets of buffers per device (root slots,
-// fiber records), allocated at the first call that needs one and used
-// round-robin; a call waits on its stream (through an event) for the
-// previous call that used its set.
-constexpr int kRegions = 2;
+constexpr size_t kSlotBytesPerWave = 16 * kWave * sizeof(float);   // one root slot per lane
+constexpr size_t kMaxRecordBytes = (size_t)1 << 30;                 // fiber records, largest table
 
 constexpr int kMaxDevices = 64;
 constexpr int kStageSlots = 4;                 // pinned staging for batched scene tables
 constexpr size_t kStageBytes = 1u << 20;
 
-struct Region {
-    std::mutex m;
-    float *slots;                              // root slots (resident waves x 4 KB)
-    float *aos;                                // fibers as 16-float records (gathered calls)
-    size_t aos_bytes;
-    hipEvent_t done;                           // recorded after the last call that used it
-    bool pending;
-};
-
 struct DeviceInfo {
     std::atomic<bool> ready;
     int cus;
-    int fused_resident[4];                     // resident waves per CU, per variant (as kFused)
-    Region region[kRegions];
-    std::atomic<uint32_t> next_region;
+    int fused_resident[kVariants];             // resident waves per CU, per variant (as kFused)
     std::mutex stage_mutex;
-    void *stage[kStageSlots];                  // pinned host buffers (allocated on first batched call)
+    void *stage[kStageSlots];                  // pinned host buffers for scene tables
     hipEvent_t stage_done[kStageSlots];
     int stage_next;
 };
@@ -1224,6 +1230,9 @@ int current_device(int &dev)
     return FI_OK;
 }
 
+// Set-up of the current device, once: unit counts, occupancy of every kernel
+// variant and the pinned staging buffers of batched calls. Every entry point
+// runs it on its first call on a device (fi_init_device runs it ahead).
 int device_info(DeviceInfo *&out)
 {
     int dev = 0;
@@ -1234,26 +1243,41 @@ int device_info(DeviceInfo *&out)
         if (!d.ready.load(std::memory_order_relaxed)) {
             if (hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
                 return FI_ERR_HIP;
-            for (int m = 0; m < 4; ++m) {
+            for (int m = 0; m < kVariants; ++m) {
                 int nb = 0;
                 if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)kFused[m], kWave, 0) != hipSuccess)
                     return FI_ERR_HIP;
                 d.fused_resident[m] = nb > 0 ? nb : 1;
             }
-            for (int r = 0; r < kRegions; ++r) {
-                d.region[r].aos = nullptr;
-                d.region[r].aos_bytes = 0;
-                d.region[r].slots = nullptr;
-                d.region[r].done = nullptr;
-                d.region[r].pending = false;
+            for (int k = 0; k < kStageSlots; ++k) {
+                if (hipHostMalloc(&d.stage[k], kStageBytes, hipHostMallocDefault) != hipSuccess) return FI_ERR_HIP;
+                if (hipEventCreateWithFlags(&d.stage_done[k], hipEventDisableTiming) != hipSuccess) return FI_ERR_HIP;
             }
-            d.next_region.store(0u);
             d.stage_next = 0;
             d.ready.store(true, std::memory_order_release);
         }
     }
     out = &d;
     return FI_OK;
+}
+
+// Root slots of single calls: one 4 KiB block per resident wave of the
+// largest single-call grid.
+size_t pairs_slot_bytes(const DeviceInfo &d)
+{
+    int most = 0;
+    for (int m = 0; m < 3; ++m) most = d.fused_resident[m] > most ? d.fused_resident[m] : most;
+    return align256((size_t)most * d.cus * kSlotBytesPerWave);
+}
+
+// Fiber records of a single call: when it gathers fibers through pair_fiber
+// and reads each fiber about once or more, the fibers are first copied to
+// 16-float records (one pass over the table): a gathered fiber is then one
+// or two cache lines instead of one line per coordinate row.
+size_t record_bytes(int64_t n_pairs, int64_t n_fibers, bool gathered)
+{
+    const size_t need = (size_t)(n_fibers > 0 ? n_fibers : 0) * 16 * sizeof(float);
+    return gathered && n_fibers > 0 && n_pairs >= n_fibers && need <= kMaxRecordBytes ? align256(need) : 0;
 }
 
 // Launch defaults of single-problem calls (and of batches without a tuned
@@ -1264,41 +1288,41 @@ int device_info(DeviceInfo *&out)
 #ifndef FIBERHIT_DEFAULT_WAVES_PER_SIMD
 #define FIBERHIT_DEFAULT_WAVES_PER_SIMD 0
 #endif
-fi_tuning default_tuning()
+fi_tuning default_tuning(bool refine)
 {
-    return fi_tuning{FIBERHIT_DEFAULT_REFILL, FIBERHIT_DEFAULT_WAVES_PER_SIMD};
+    return fi_tuning{refine ? FIBERHIT_REFINE_REFILL : FIBERHIT_DEFAULT_REFILL, FIBERHIT_DEFAULT_WAVES_PER_SIMD};
 }
 
-// Autotune results, kept for the process: keyed by device and the size class
-// of a batch (log2 of its total pairs and of its problem count). A batch
-// launched without an explicit tuning uses the entry of its class if one
-// exists.
+// Autotune results, kept for the process: keyed by device, the refinement
+// flag and the size class of a batch (log2 of its total pairs and of its
+// problem count). A batch launched without an explicit tuning uses the entry
+// of its class if one exists.
 std::mutex g_tune_mutex;
 std::map<uint64_t, fi_tuning> g_tune_cache;
 
-uint64_t tune_key(int device, int64_t total, int n_scenes)
+uint64_t tune_key(int device, int64_t total, int n_scenes, bool refine)
 {
     int lt = 0, ls = 0;
     while ((int64_t)1 << (lt + 1) <= total && lt < 62) ++lt;
     while ((1 << (ls + 1)) <= n_scenes && ls < 30) ++ls;
-    return ((uint64_t)device << 16) | ((uint64_t)lt << 8) | (uint64_t)ls;
+    return ((uint64_t)device << 24) | ((uint64_t)refine << 16) | ((uint64_t)lt << 8) | (uint64_t)ls;
 }
 
-fi_tuning tuned_or_default(int64_t total, int n_scenes)
+fi_tuning tuned_or_default(int64_t total, int n_scenes, bool refine)
 {
     int dev = 0;
-    if (current_device(dev) != FI_OK) return default_tuning();
+    if (current_device(dev) != FI_OK) return default_tuning(refine);
     std::lock_guard<std::mutex> lock(g_tune_mutex);
-    const auto it = g_tune_cache.find(tune_key(dev, total, n_scenes));
-    return it == g_tune_cache.end() ? default_tuning() : it->second;
+    const auto it = g_tune_cache.find(tune_key(dev, total, n_scenes, refine));
+    return it == g_tune_cache.end() ? default_tuning(refine) : it->second;
 }
 
-void remember_tuning(int64_t total, int n_scenes, const fi_tuning &t)
+void remember_tuning(int64_t total, int n_scenes, bool refine, const fi_tuning &t)
 {
     int dev = 0;
     if (current_device(dev) != FI_OK) return;
     std::lock_guard<std::mutex> lock(g_tune_mutex);
-    g_tune_cache[tune_key(dev, total, n_scenes)] = t;
+    g_tune_cache[tune_key(dev, total, n_scenes, refine)] = t;
 }
 
 int64_t total_pairs(const fi_scene *sc, int32_t n)
@@ -1314,66 +1338,37 @@ int check_tuning(const fi_tuning &t)
     return FI_OK;
 }
 
-int launch(int mode, const Args &a, void *stream)
+// Enqueue one single call on `s`: the fiber records (when `aos` is given),
+// then one persistent launch of about one wave per 64 pairs, at most
+// `max_waves` (the resident waves, or fewer when the slots are smaller).
+int launch(int mode, const Args &a, float *slots, int64_t max_waves, float *aos, hipStream_t s)
 {
+    if (aos)
+        hipLaunchKernelGGL(k_fibers_aos, dim3((unsigned)((a.n_fibers + 255) / 256)), dim3(256), 0, s,
+                           a.fibers, a.fiber_stride, a.n_fibers, (float4 *)aos);
+    int64_t g = (a.n_pairs + kWave - 1) / kWave;
+    if (g > max_waves) g = max_waves;
+    if (g > 0)
+        hipLaunchKernelGGL(kFused[mode], dim3((unsigned)g), dim3(kWave), 0, s, a, nullptr, nullptr, 0,
+                           a.n_pairs, slots, mode == kConservative ? FIBERHIT_REFINE_REFILL : FIBERHIT_FUSED_REFILL,
+                           aos);
+    return hipGetLastError() == hipSuccess ? FI_OK : FI_ERR_HIP;
+}
+
+// A single call with its buffers in the caller's workspace: root slots
+// first, then (room permitting) the fiber records.
+int launch_with_workspace(int mode, const Args &a, void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (!workspace || ((uintptr_t)workspace & 255u) != 0u) return FI_ERR_WORKSPACE;
     (void)hipGetLastError();
     DeviceInfo *d = nullptr;
     const int st = device_info(d);
     if (st != FI_OK) return st;
-    hipStream_t s = (hipStream_t)stream;
-    Region &R = d->region[d->next_region.fetch_add(1u) % kRegions];
-    {
-        std::lock_guard<std::mutex> lock(R.m);
-        if (!R.slots) {
-            // root slots for the largest grid of the single-call variants
-            int most = 0;
-            for (int m = 0; m < 3; ++m) most = d->fused_resident[m] > most ? d->fused_resident[m] : most;
-            if (hipMalloc(&R.slots, (size_t)most * d->cus * 16 * kWave * sizeof(float)) != hipSuccess) {
-                R.slots = nullptr;
-                (void)hipGetLastError();
-                return FI_ERR_HIP;
-            }
-            if (hipEventCreateWithFlags(&R.done, hipEventDisableTiming) != hipSuccess) return FI_ERR_HIP;
-        }
-        // a gathered pairing that reads each fiber about once or more: copy
-        // the fibers to 16-float records first (one pass over them; the
-        // buffer grows to the largest such call, up to 1 GiB)
-        const float *aos = nullptr;
-        const size_t need = (size_t)a.n_fibers * 16 * sizeof(float);
-        if (a.pair_fiber && a.n_fibers > 0 && a.n_pairs >= a.n_fibers && need <= ((size_t)1 << 30)) {
-            if (R.aos_bytes < need) {
-                if (R.aos) {
-                    if (R.pending && hipEventSynchronize(R.done) != hipSuccess) return FI_ERR_HIP;
-                    (void)hipFree(R.aos);
-                    R.aos = nullptr;
-                    R.aos_bytes = 0;
-                }
-                if (hipMalloc(&R.aos, need) != hipSuccess) {
-                    R.aos = nullptr;
-                    (void)hipGetLastError();
-                    return FI_ERR_HIP;
-                }
-                R.aos_bytes = need;
-            }
-            aos = R.aos;
-        }
-        if (R.pending && hipStreamWaitEvent(s, R.done, 0) != hipSuccess) return FI_ERR_HIP;
-        if (aos)
-            hipLaunchKernelGGL(k_fibers_aos, dim3((unsigned)((a.n_fibers + 255) / 256)), dim3(256), 0, s,
-                               a.fibers, a.fiber_stride, a.n_fibers, (float4 *)R.aos);
-        // one persistent launch: about one wave per 64 pairs, at most the
-        // resident waves
-        int64_t g = (a.n_pairs + kWave - 1) / kWave;
-        const int64_t resident = (int64_t)d->fused_resident[mode] * d->cus;
-        if (g > resident) g = resident;
-        if (g > 0)
-            hipLaunchKernelGGL(kFused[mode], dim3((unsigned)g), dim3(kWave), 0, s, a, nullptr, nullptr, 0,
-                               a.n_pairs, R.slots, mode == kConservative ? FIBERHIT_REFINE_REFILL : FIBERHIT_FUSED_REFILL,
-                               aos);
-        if (hipEventRecord(R.done, s) != hipSuccess) return FI_ERR_HIP;
-        R.pending = true;
-    }
-    return hipGetLastError() == hipSuccess ? FI_OK : FI_ERR_HIP;
+    const size_t slot_bytes = pairs_slot_bytes(*d);
+    if (workspace_bytes < slot_bytes) return FI_ERR_WORKSPACE;
+    const size_t rec = record_bytes(a.n_pairs, a.n_fibers, a.pair_fiber != nullptr);
+    float *aos = rec && workspace_bytes >= slot_bytes + rec ? (float *)((char *)workspace + slot_bytes) : nullptr;
+    return launch(mode, a, (float *)workspace, (int64_t)d->fused_resident[mode] * d->cus, aos, (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -1382,33 +1377,31 @@ int launch(int mode, const Args &a, void *stream)
 
 size_t scene_table_bytes(int n) { return align256((size_t)n * sizeof(Args)) + align256((size_t)(n + 1) * sizeof(int64_t)); }
 
-// Root slots of the one-kernel batched path: one 4 KB block per resident
-// wave of the current device (0 if the device cannot be queried).
-size_t batched_slot_bytes()
+// Root slots of the one-kernel batched path: one 4 KiB block per resident
+// wave of the larger batched grid (plain or refining).
+size_t batched_slot_bytes(const DeviceInfo &d)
 {
-    DeviceInfo *d = nullptr;
-    if (device_info(d) != FI_OK) return 0;
-    return align256((size_t)d->fused_resident[kBatchedVariant] * d->cus * 16 * kWave * sizeof(float));
+    const int most = d.fused_resident[kBatchedVariant] > d.fused_resident[kBatchedRefineVariant]
+                         ? d.fused_resident[kBatchedVariant] : d.fused_resident[kBatchedRefineVariant];
+    return align256((size_t)most * d.cus * kSlotBytesPerWave);
 }
 
-size_t batched_bytes(int n, int64_t total)
-{
-    (void)total;
-    const size_t slots = batched_slot_bytes();
-    return slots ? scene_table_bytes(n) + slots : 0;
-}
+size_t batched_bytes(const DeviceInfo &d, int n) { return scene_table_bytes(n) + batched_slot_bytes(d); }
 
-int scenes_to_table(const fi_scene *sc, int32_t n, Args *tab, int64_t *off)
+int scenes_to_table(const fi_scene *sc, int32_t n, uint32_t flags, Args *tab, int64_t *off)
 {
+    const bool refine = (flags & FI_FP64_REFINE) != 0u;
     off[0] = 0;
     for (int k = 0; k < n; ++k) {
         const fi_scene &x = sc[k];
         const int st = check_common(x.rays, x.ray_stride, x.n_rays, x.fibers, x.fiber_stride, x.n_fibers,
-                                    x.pair_ray, x.pair_fiber, x.depth, x.n_pairs, 0u, x.t_out, x.u_out, x.hit_out);
+                                    x.pair_ray, x.pair_fiber, x.depth, x.n_pairs, flags, x.t_out, x.u_out, x.hit_out);
         if (st != FI_OK) return st;
+        if (refine && x.n_pairs > 0 && (!x.t64_out || !x.u64_out)) return FI_ERR_NULL;
         tab[k] = Args{x.rays, x.ray_stride, x.n_rays, x.fibers, x.fiber_stride, x.n_fibers,
                       x.pair_ray, x.pair_fiber, x.pair_depth, x.depth, x.n_pairs,
-                      x.t_out, x.u_out, x.hit_out, nullptr, nullptr, nullptr};
+                      x.t_out, x.u_out, x.hit_out, nullptr,
+                      refine ? x.t64_out : nullptr, refine ? x.u64_out : nullptr};
         off[k + 1] = off[k] + x.n_pairs;
     }
     if (off[n] > (int64_t)0x7fffffff - 64) return FI_ERR_RANGE;
@@ -1436,18 +1429,19 @@ BatchLayout layout_of(void *ws, int n)
 // pairs, at most the resident waves (fewer when the tuning caps the waves
 // per SIMD).
 void launch_batched(const DeviceInfo &d, const fi_tuning &t, const BatchLayout &L, int n_scenes, int64_t total,
-                    hipStream_t s)
+                    bool refine, hipStream_t s)
 {
-    int per_cu = d.fused_resident[kBatchedVariant];
+    const int variant = refine ? kBatchedRefineVariant : kBatchedVariant;
+    int per_cu = d.fused_resident[variant];
     if (t.waves_per_simd > 0 && 4 * t.waves_per_simd < per_cu) per_cu = 4 * t.waves_per_simd;
     int64_t g = (total + kWave - 1) / kWave;
     if (g > (int64_t)per_cu * d.cus) g = (int64_t)per_cu * d.cus;
     if (g > 0)
-        hipLaunchKernelGGL(kFused[kBatchedVariant], dim3((unsigned)g), dim3(kWave), 0, s, Args{}, L.scenes, L.offsets, n_scenes,
-                           total, L.slots, t.refill, nullptr);
+        hipLaunchKernelGGL(kFused[variant], dim3((unsigned)g), dim3(kWave), 0, s, Args{}, L.scenes, L.offsets,
+                           n_scenes, total, L.slots, t.refill, nullptr);
 }
 
-int batched_enqueue(const fi_scene *scenes, int32_t n_scenes, const fi_tuning &t, void *workspace,
+int batched_enqueue(const fi_scene *scenes, int32_t n_scenes, uint32_t flags, const fi_tuning &t, void *workspace,
                     size_t workspace_bytes, hipStream_t s)
 {
     DeviceInfo *d = nullptr;
@@ -1455,25 +1449,23 @@ int batched_enqueue(const fi_scene *scenes, int32_t n_scenes, const fi_tuning &t
     if (st != FI_OK) return st;
     const size_t tb = scene_table_bytes(n_scenes);
     if (tb > kStageBytes) return FI_ERR_RANGE;
-    if (!workspace || workspace_bytes < batched_bytes(n_scenes, total_pairs(scenes, n_scenes)))
+    if (!workspace || ((uintptr_t)workspace & 255u) != 0u || workspace_bytes < batched_bytes(*d, n_scenes))
         return FI_ERR_WORKSPACE;
     std::lock_guard<std::mutex> lock(d->stage_mutex);
     const int k = d->stage_next;
-    if (!d->stage[k]) {
-        if (hipHostMalloc(&d->stage[k], kStageBytes, hipHostMallocDefault) != hipSuccess) return FI_ERR_HIP;
-        if (hipEventCreateWithFlags(&d->stage_done[k], hipEventDisableTiming) != hipSuccess) return FI_ERR_HIP;
-    } else if (hipEventSynchronize(d->stage_done[k]) != hipSuccess) {
-        return FI_ERR_HIP;
-    }
+    // the staging buffer's previous upload must have left it (rarely waits:
+    // four buffers in turn)
+    if (hipEventSynchronize(d->stage_done[k]) != hipSuccess) return FI_ERR_HIP;
     char *host = (char *)d->stage[k];
-    st = scenes_to_table(scenes, n_scenes, (Args *)host, (int64_t *)(host + align256((size_t)n_scenes * sizeof(Args))));
+    int64_t *off = (int64_t *)(host + align256((size_t)n_scenes * sizeof(Args)));
+    st = scenes_to_table(scenes, n_scenes, flags, (Args *)host, off);
     if (st != FI_OK) return st;
-    const int64_t total = ((int64_t *)(host + align256((size_t)n_scenes * sizeof(Args))))[n_scenes];
+    const int64_t total = off[n_scenes];
     const BatchLayout L = layout_of(workspace, n_scenes);
     if (hipMemcpyAsync(workspace, host, tb, hipMemcpyHostToDevice, s) != hipSuccess) return FI_ERR_HIP;
     if (hipEventRecord(d->stage_done[k], s) != hipSuccess) return FI_ERR_HIP;
     d->stage_next = (k + 1) % kStageSlots;
-    launch_batched(*d, t, L, n_scenes, total, s);
+    launch_batched(*d, t, L, n_scenes, total, (flags & FI_FP64_REFINE) != 0u, s);
     return hipGetLastError() == hipSuccess ? FI_OK : FI_ERR_HIP;
 }
 
@@ -1484,13 +1476,14 @@ struct fi_batch_plan {
     void *mem;                 // device copy of the scene table and offsets; root slots
     int n_scenes;
     int64_t total;
+    uint32_t flags;
     fi_tuning tuning;
     hipGraph_t graph;
     hipGraphExec_t exec;
 };
 
 extern "C" {
-int fi_version(void) { return (0 << 16) | (4 << 8) | 0; }
+int fi_version(void) { return (0 << 16) | (5 << 8) | 0; }
 
 const char *fi_strerror(int status)
 {
@@ -1499,9 +1492,25 @@ const char *fi_strerror(int status)
     case FI_ERR_NULL: return "a required pointer is NULL";
     case FI_ERR_RANGE: return "a count, stride, depth or flag is out of range";
     case FI_ERR_HIP: return "the HIP runtime reported an error";
-    case FI_ERR_WORKSPACE: return "workspace missing or too small";
+    case FI_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
     default: return "unknown status";
     }
+}
+
+int fi_init_device(void)
+{
+    (void)hipGetLastError();
+    DeviceInfo *d = nullptr;
+    return device_info(d);
+}
+
+size_t fiber_pairs_workspace_bytes(int64_t n_pairs, int64_t n_fibers, int32_t gathered, uint32_t flags)
+{
+    (void)flags;
+    if (n_pairs < 0 || n_fibers < 0) return 0;
+    DeviceInfo *d = nullptr;
+    if (device_info(d) != FI_OK) return 0;
+    return pairs_slot_bytes(*d) + record_bytes(n_pairs, n_fibers, gathered != 0);
 }
 
 int fiber_intersect_pairs(const float *rays, int64_t ray_stride, int64_t n_rays,
@@ -1511,7 +1520,7 @@ int fiber_intersect_pairs(const float *rays, int64_t ray_stride, int64_t n_rays,
                           uint32_t flags,
                           float *t_out, float *u_out, uint8_t *hit_out,
                           double *t64_out, double *u64_out,
-                          void *stream)
+                          void *workspace, size_t workspace_bytes, void *stream)
 {
     const int st = check_common(rays, ray_stride, n_rays, fibers, fiber_stride, n_fibers,
                                 pair_ray, pair_fiber, depth, n_pairs, flags, t_out, u_out, hit_out);
@@ -1521,7 +1530,7 @@ int fiber_intersect_pairs(const float *rays, int64_t ray_stride, int64_t n_rays,
     Args a{rays, ray_stride, n_rays, fibers, fiber_stride, n_fibers,
            pair_ray, pair_fiber, pair_depth, depth, n_pairs, t_out, u_out, hit_out, nullptr,
            refine ? t64_out : nullptr, refine ? u64_out : nullptr};
-    return launch(refine ? kConservative : kPlain, a, stream);
+    return launch_with_workspace(refine ? kConservative : kPlain, a, workspace, workspace_bytes, stream);
 }
 
 int fiber_intersect_counts(const float *rays, int64_t ray_stride, int64_t n_rays,
@@ -1530,35 +1539,37 @@ int fiber_intersect_counts(const float *rays, int64_t ray_stride, int64_t n_rays
                            const uint8_t *pair_depth, int32_t depth, int64_t n_pairs,
                            uint32_t flags,
                            float *t_out, float *u_out, uint8_t *hit_out,
-                           int32_t *counts_out, void *stream)
+                           int32_t *counts_out, void *workspace, size_t workspace_bytes, void *stream)
 {
     const int st = check_common(rays, ray_stride, n_rays, fibers, fiber_stride, n_fibers,
                                 pair_ray, pair_fiber, depth, n_pairs, flags, t_out, u_out, hit_out);
     if (st != FI_OK || n_pairs == 0) return st;
     if (!counts_out) return FI_ERR_NULL;
-    if (flags != 0u) return FI_ERR_RANGE;
+    if ((flags & FI_FP64_REFINE) != 0u) return FI_ERR_RANGE;
     Args a{rays, ray_stride, n_rays, fibers, fiber_stride, n_fibers,
            pair_ray, pair_fiber, pair_depth, depth, n_pairs, t_out, u_out, hit_out, counts_out, nullptr, nullptr};
-    return launch(kCount, a, stream);
+    return launch_with_workspace(kCount, a, workspace, workspace_bytes, stream);
 }
-
 
 size_t fiber_batched_workspace_bytes(int32_t n_scenes, int64_t total_pairs)
 {
     if (n_scenes < 0 || total_pairs < 0) return 0;
-    return batched_bytes(n_scenes, total_pairs);
+    DeviceInfo *d = nullptr;
+    if (device_info(d) != FI_OK) return 0;
+    return batched_bytes(*d, n_scenes);
 }
 
 int fiber_intersect_batched(const fi_scene *scenes, int32_t n_scenes, const fi_tuning *tuning,
                             uint32_t flags, void *workspace, size_t workspace_bytes, void *stream)
 {
-    if (n_scenes < 0 || flags != 0u) return FI_ERR_RANGE;
+    if (n_scenes < 0 || (flags & ~(uint32_t)(FI_FP64_REFINE | FI_COMPENSATED_PROJ)) != 0u) return FI_ERR_RANGE;
     if (n_scenes == 0) return FI_OK;
     if (!scenes) return FI_ERR_NULL;
-    const fi_tuning t = tuning ? *tuning : tuned_or_default(total_pairs(scenes, n_scenes), n_scenes);
+    const bool refine = (flags & FI_FP64_REFINE) != 0u;
+    const fi_tuning t = tuning ? *tuning : tuned_or_default(total_pairs(scenes, n_scenes), n_scenes, refine);
     if (check_tuning(t) != FI_OK) return FI_ERR_RANGE;
     (void)hipGetLastError();
-    return batched_enqueue(scenes, n_scenes, t, workspace, workspace_bytes, (hipStream_t)stream);
+    return batched_enqueue(scenes, n_scenes, flags, t, workspace, workspace_bytes, (hipStream_t)stream);
 }
 
 int fiber_batch_plan_create(const fi_scene *scenes, int32_t n_scenes, const fi_tuning *tuning,
@@ -1566,9 +1577,10 @@ int fiber_batch_plan_create(const fi_scene *scenes, int32_t n_scenes, const fi_t
 {
     if (!plan_out) return FI_ERR_NULL;
     *plan_out = nullptr;
-    if (n_scenes <= 0 || flags != 0u) return FI_ERR_RANGE;
+    if (n_scenes <= 0 || (flags & ~(uint32_t)(FI_FP64_REFINE | FI_COMPENSATED_PROJ)) != 0u) return FI_ERR_RANGE;
     if (!scenes) return FI_ERR_NULL;
-    const fi_tuning t = tuning ? *tuning : tuned_or_default(total_pairs(scenes, n_scenes), n_scenes);
+    const bool refine = (flags & FI_FP64_REFINE) != 0u;
+    const fi_tuning t = tuning ? *tuning : tuned_or_default(total_pairs(scenes, n_scenes), n_scenes, refine);
     if (check_tuning(t) != FI_OK) return FI_ERR_RANGE;
     (void)hipGetLastError();
     DeviceInfo *d = nullptr;
@@ -1577,16 +1589,18 @@ int fiber_batch_plan_create(const fi_scene *scenes, int32_t n_scenes, const fi_t
     const size_t tb = scene_table_bytes(n_scenes);
     char *host = (char *)malloc(tb);
     if (!host) return FI_ERR_RANGE;
-    st = scenes_to_table(scenes, n_scenes, (Args *)host, (int64_t *)(host + align256((size_t)n_scenes * sizeof(Args))));
+    int64_t *off = (int64_t *)(host + align256((size_t)n_scenes * sizeof(Args)));
+    st = scenes_to_table(scenes, n_scenes, flags, (Args *)host, off);
     if (st != FI_OK) { free(host); return st; }
     fi_batch_plan *p = new fi_batch_plan();
     p->n_scenes = n_scenes;
-    p->total = ((int64_t *)(host + align256((size_t)n_scenes * sizeof(Args))))[n_scenes];
+    p->total = off[n_scenes];
+    p->flags = flags;
     p->tuning = t;
     current_device(p->device);
     hipStream_t cs = nullptr;
-    const size_t bytes = batched_bytes(n_scenes, p->total);
-    bool ok = bytes > 0 && hipMalloc(&p->mem, bytes) == hipSuccess &&
+    const size_t bytes = batched_bytes(*d, n_scenes);
+    bool ok = hipMalloc(&p->mem, bytes) == hipSuccess &&
               hipMemcpy(p->mem, host, tb, hipMemcpyHostToDevice) == hipSuccess &&
               hipStreamCreate(&cs) == hipSuccess;
     free(host);
@@ -1594,7 +1608,7 @@ int fiber_batch_plan_create(const fi_scene *scenes, int32_t n_scenes, const fi_t
         const BatchLayout L = layout_of(p->mem, n_scenes);
         ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
         if (ok) {
-            launch_batched(*d, t, L, n_scenes, p->total, cs);
+            launch_batched(*d, t, L, n_scenes, p->total, refine, cs);
             ok = hipStreamEndCapture(cs, &p->graph) == hipSuccess &&
                  hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) == hipSuccess;
         }
@@ -1642,14 +1656,20 @@ int fiber_batch_autotune(const fi_scene *scenes, int32_t n_scenes, uint32_t flag
                          fi_tuning *best, float *best_ms)
 {
     if (!best) return FI_ERR_NULL;
-    if (n_scenes <= 0 || flags != 0u || repeats < 1) return FI_ERR_RANGE;
+    if (n_scenes <= 0 || (flags & ~(uint32_t)(FI_FP64_REFINE | FI_COMPENSATED_PROJ)) != 0u || repeats < 1)
+        return FI_ERR_RANGE;
+    const bool refine = (flags & FI_FP64_REFINE) != 0u;
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return FI_ERR_HIP;
-    const int refills[] = {32, 48, 56};
+    // refining waves park lanes until the wave decides them together, so
+    // they refill early; plain waves refill late
+    const int plain_refills[] = {32, 48, 56};
+    const int refine_refills[] = {4, 8, 16};
+    const int *refills = refine ? refine_refills : plain_refills;
     const int occ[] = {4, 5, 0};
     float best_t = INFINITY;
-    fi_tuning bt = default_tuning();
+    fi_tuning bt = default_tuning(refine);
     int st = FI_OK;
     for (int oi = 0; oi < 3 && st == FI_OK; ++oi)
         for (int ri = 0; ri < 3 && st == FI_OK; ++ri) {
@@ -1671,7 +1691,7 @@ int fiber_batch_autotune(const fi_scene *scenes, int32_t n_scenes, uint32_t flag
     if (st != FI_OK) return st;
     *best = bt;
     if (best_ms) *best_ms = best_t;
-    remember_tuning(total_pairs(scenes, n_scenes), n_scenes, bt);
+    remember_tuning(total_pairs(scenes, n_scenes), n_scenes, refine, bt);
     return FI_OK;
 }
 

@@ -44,20 +44,23 @@ def test_version_and_strerror():
 
 def _call(**kw):
     a = dict(rays=1, rs=8, nr=8, fibers=1, fs=8, nf=8, pr=None, pf=None, pd=None,
-             depth=9, n=8, flags=0, t=1, u=1, h=1)
+             depth=9, n=8, flags=0, t=1, u=1, h=1, ws=None, wsb=0)
     a.update(kw)
     vp = lambda x: None if x is None else C.c_void_p(x)
     return binding.lib().fiber_intersect_pairs(
         vp(a["rays"]), a["rs"], a["nr"], vp(a["fibers"]), a["fs"], a["nf"], vp(a["pr"]),
         vp(a["pf"]), vp(a["pd"]), a["depth"], a["n"], a["flags"], vp(a["t"]), vp(a["u"]),
-        vp(a["h"]), vp(a.get("t64")), vp(a.get("u64")), None)
+        vp(a["h"]), vp(a.get("t64")), vp(a.get("u64")), vp(a["ws"]), a["wsb"], None)
 
 
 @pytest.mark.parametrize("kw,code", [
     (dict(depth=24), -2), (dict(depth=-1), -2), (dict(n=-1), -2), (dict(flags=8), -2),
     (dict(rs=4), -2), (dict(fs=4), -2), (dict(n=9), -2),
     (dict(rays=None), -1), (dict(fibers=None), -1), (dict(t=None), -1), (dict(h=None), -1),
-    (dict(flags=1), -1), (dict(flags=1, t64=1), -1), (dict(flags=3, t64=1, u64=1), -2),
+    (dict(flags=1), -1), (dict(flags=1, t64=1), -1), (dict(flags=5, t64=1, u64=1), -2),
+    # a missing or misaligned workspace is refused before any HIP call
+    (dict(), -4), (dict(ws=0x1008, wsb=1 << 30), -4), (dict(flags=2), -4),
+    (dict(flags=3, t64=1, u64=1), -4),
 ])
 def test_argument_errors_before_launch(kw, code):
     # these return before any HIP call, so they are safe without a device
@@ -71,5 +74,31 @@ def test_empty_batch_is_a_no_op():
 def test_counts_requires_output():
     L = binding.lib()
     r = L.fiber_intersect_counts(C.c_void_p(1), 8, 8, C.c_void_p(1), 8, 8, None, None, None,
-                                 9, 8, 0, C.c_void_p(1), C.c_void_p(1), C.c_void_p(1), None, None)
+                                 9, 8, 0, C.c_void_p(1), C.c_void_p(1), C.c_void_p(1), None, None, 0, None)
     assert r == -1
+    r = L.fiber_intersect_counts(C.c_void_p(1), 8, 8, C.c_void_p(1), 8, 8, None, None, None,
+                                 9, 8, 1, C.c_void_p(1), C.c_void_p(1), C.c_void_p(1), C.c_void_p(1), None,
+                                 0, None)
+    assert r == -2
+
+
+def test_pair_count_rejects_mismatched_lengths():
+    """Per-pair tensors of different lengths, or an identity pairing longer
+    than its table, are refused by the binding before any launch (the C ABI
+    cannot check a device array's length)."""
+    import torch
+    rays = torch.zeros(7, 300)
+    fibers = torch.zeros(16, 200)
+    i = torch.zeros(150, dtype=torch.int32)
+    d = torch.zeros(150, dtype=torch.uint8)
+    assert binding._pair_count(rays, fibers, None, None, None) == 200
+    assert binding._pair_count(rays, fibers, i, i, d) == 150
+    assert binding._pair_count(rays, fibers, None, None, d) == 150
+    with pytest.raises(ValueError):
+        binding._pair_count(rays, fibers, i, i[:149], None)
+    with pytest.raises(ValueError):
+        binding._pair_count(rays, fibers, i, None, d[:10])
+    with pytest.raises(ValueError):
+        binding._pair_count(rays, fibers, None, None, torch.zeros(250, dtype=torch.uint8))
+    with pytest.raises(ValueError):
+        binding._pair_count(rays[:, :100], fibers, None, i, None)

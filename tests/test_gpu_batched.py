@@ -174,3 +174,51 @@ def test_batched_four_million_pairs():
     binding.intersect_batched(probs)
     torch.cuda.synchronize()
     assert_same(probs, ref)
+
+
+def test_refined_batch_equals_refined_calls():
+    """A batch run with FI_FP64_REFINE (per-pair depths 16..22, so some pairs
+    stay on the plain rules) gives, bit for bit, the five outputs of one
+    refined call per problem -- as a plain batched call and as a plan."""
+    rng = np.random.default_rng(31)
+    sizes = [700, 0, 1, 2500, 64, 1300]
+    probs = []
+    for k, n in enumerate(sizes):
+        w = W.curved_scene(max(n, 1), 1811033744 + 77 * k)
+        pd = rng.integers(16, 23, max(n, 1)).astype(np.uint8)
+        g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+        probs.append(binding.Problem(g(w.rays[:, :n]), g(w.fibers[:, :n]), 22, None, None, g(pd[:n]),
+                                     refine=True))
+    say(f"[batched refine] {len(probs)} problems, {sum(sizes)} pairs")
+    ref = []
+    for p in probs:
+        if p.n == 0:
+            ref.append(None)
+            continue
+        out = binding.intersect_pairs(p.rays, p.fibers, p.depth, pair_depth=p.pair_depth, refine=True)
+        torch.cuda.synchronize()
+        ref.append([o.cpu().numpy() for o in out])
+
+    def check():
+        for p, r in zip(probs, ref):
+            if r is None:
+                continue
+            got = [o.cpu().numpy() for o in (p.t, p.u, p.hit, p.t64, p.u64)]
+            for a, b in zip(got, r):
+                assert np.array_equal(np.ascontiguousarray(a).view(np.uint8), np.ascontiguousarray(b).view(np.uint8))
+
+    for p in probs:
+        p.t64.fill_(-1.0); p.u64.fill_(-1.0)
+    clear(probs)
+    binding.intersect_batched(probs, refine=True)
+    torch.cuda.synchronize()
+    check()
+    plan = binding.BatchPlan(probs, refine=True)
+    for rep in range(2):
+        clear(probs)
+        plan.launch()
+        torch.cuda.synchronize()
+        check()
+    plan.close()
+    with pytest.raises(ValueError):
+        binding.intersect_batched(make_scenes(k=2)[2], refine=True)

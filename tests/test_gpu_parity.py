@@ -257,9 +257,9 @@ def test_results_independent_of_call_size():
 
 
 def test_concurrent_streams():
-    """Calls enqueued alternately on two streams (they share the per-device
-    root slots, so a call waits for the one before it) give the results of
-    the same calls made one after another."""
+    """Calls enqueued alternately on two streams (each with its own workspace,
+    which the allocator keeps until its stream has passed the call) give the
+    results of the same calls made one after another."""
     ws = [W.straight_and_curved(50_000 + 1000 * k, 9, seed=77 + k) for k in range(6)]
     dev_in = [(torch.from_numpy(w.rays).to(DEV), torch.from_numpy(w.fibers).to(DEV)) for w in ws]
     ref = []
