@@ -170,6 +170,43 @@ int fiber_intersect_pairs(const float *rays, int64_t ray_stride, int64_t n_rays,
                           void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * fiber_intersect_pairs_noalloc -- fiber_intersect_pairs without a workspace,
+ * for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation).
+ *
+ * Operation and arguments: those of fiber_intersect_pairs, minus the
+ * workspace; the results are bit for bit the same. The root slots live in a
+ * fixed array inside the library's code object (24 MiB, one copy per device,
+ * held until the process ends; its address is taken once per device at the
+ * device's set-up). It holds the slots of 6144 waves, the resident waves of
+ * either kernel variant on MI355X; a device that could keep more waves
+ * resident gets a grid of that many (results do not depend on the grid). No
+ * argument sizes the array, so no input is refused for it. Fibers gathered
+ * through pair_fiber are read in place (no record copy).
+ *
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents (every slot is written before it is read, so nothing needs
+ * clearing): calls that overlap on one device -- on two streams, or from two
+ * host threads without ordering -- race and give undefined results.
+ *
+ * Allocation: none on the call path (no hipMalloc, hipFree or allocating
+ * library routine). The device's set-up (fi_init_device, or the first call of
+ * any entry point on that device) allocates the pinned staging of batched
+ * calls once; callers that must not allocate at all call fi_init_device
+ * beforehand.
+ *
+ * Errors: as fiber_intersect_pairs, without FI_ERR_WORKSPACE.
+ */
+int fiber_intersect_pairs_noalloc(const float *rays, int64_t ray_stride, int64_t n_rays,
+                                  const float *fibers, int64_t fiber_stride, int64_t n_fibers,
+                                  const int32_t *pair_ray, const int32_t *pair_fiber,
+                                  const uint8_t *pair_depth, int32_t depth, int64_t n_pairs,
+                                  uint32_t flags,
+                                  float *t_out, float *u_out, uint8_t *hit_out,
+                                  double *t64_out, double *u64_out,
+                                  void *stream);
+
+/*
  * fiber_intersect_counts -- the traversal of fiber_intersect_pairs with its
  * work counted instead of timed.
  *

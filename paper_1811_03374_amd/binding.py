@@ -38,6 +38,8 @@ def lib():
         common = [vp, i64, i64, vp, i64, i64, vp, vp, vp, i32, i64, u32, vp, vp, vp]
         L.fiber_intersect_pairs.argtypes = common + [vp, vp, vp, C.c_size_t, vp]
         L.fiber_intersect_pairs.restype = C.c_int
+        L.fiber_intersect_pairs_noalloc.argtypes = common + [vp, vp, vp]
+        L.fiber_intersect_pairs_noalloc.restype = C.c_int
         L.fiber_intersect_counts.argtypes = common + [vp, vp, C.c_size_t, vp]
         L.fiber_intersect_counts.restype = C.c_int
         L.fiber_pairs_workspace_bytes.argtypes = [i64, i64, i32, u32]
@@ -52,7 +54,7 @@ def lib():
 
 def exported_symbols():
     return ["fi_version", "fi_strerror", "fi_init_device", "fiber_pairs_workspace_bytes",
-            "fiber_intersect_pairs", "fiber_intersect_counts",
+            "fiber_intersect_pairs", "fiber_intersect_pairs_noalloc", "fiber_intersect_counts",
             "fiber_batched_workspace_bytes", "fiber_intersect_batched", "fiber_batch_plan_create",
             "fiber_batch_plan_launch", "fiber_batch_plan_tuning", "fiber_batch_plan_destroy",
             "fiber_batch_autotune"]
@@ -188,6 +190,43 @@ def intersect_pairs(rays: torch.Tensor, fibers: torch.Tensor, depth: int = 9,
         return t, u, hit, t64, u64
     _check(lib().fiber_intersect_pairs(*args, None, None, *ws, _stream(stream)))
     return t, u, hit
+
+
+def intersect_pairs_noalloc(rays: torch.Tensor, fibers: torch.Tensor, depth: int = 9,
+                            pair_ray: Optional[torch.Tensor] = None,
+                            pair_fiber: Optional[torch.Tensor] = None,
+                            pair_depth: Optional[torch.Tensor] = None,
+                            out=None, refine: bool = False, stream=None):
+    """``intersect_pairs`` through ``fiber_intersect_pairs_noalloc``: no
+    workspace (the library's fixed per-device array holds the root slots).
+    With ``out`` (and, under ``refine``, ``out`` holding five tensors) the
+    call allocates nothing. Calls on one device must not overlap."""
+    rs = _table(rays, 7, "rays")
+    fs = _table(fibers, 16, "fibers")
+    pr = _index(pair_ray, torch.int32, "pair_ray")
+    pf = _index(pair_fiber, torch.int32, "pair_fiber")
+    pd = _index(pair_depth, torch.uint8, "pair_depth")
+    n = _pair_count(rays, fibers, pr, pf, pd)
+    dev = rays.device
+    t64 = u64 = None
+    if refine:
+        if out is not None:
+            if len(out) != 5:
+                raise ValueError("a refined call takes out=(t, u, hit, t64, u64)")
+            t64, u64 = out[3], out[4]
+            for x, name in ((t64, "t64"), (u64, "u64")):
+                if x.dtype != torch.float64 or not x.is_cuda or not x.is_contiguous() or x.numel() < n:
+                    raise ValueError(f"out {name} must be a contiguous float64 device tensor of at least {n} elements")
+            out = out[:3]
+        else:
+            t64 = torch.empty(n, dtype=torch.float64, device=dev)
+            u64 = torch.empty(n, dtype=torch.float64, device=dev)
+    t, u, hit = _outs(out, n, dev)
+    _check(lib().fiber_intersect_pairs_noalloc(
+        _ptr(rays), rs, rays.shape[1], _ptr(fibers), fs, fibers.shape[1], _ptr(pr), _ptr(pf), _ptr(pd),
+        int(depth), n, FI_FP64_REFINE if refine else 0, _ptr(t), _ptr(u), _ptr(hit), _ptr(t64), _ptr(u64),
+        _stream(stream)))
+    return (t, u, hit, t64, u64) if refine else (t, u, hit)
 
 
 class PreparedPairs:

@@ -1212,10 +1212,20 @@ constexpr int kMaxDevices = 64;
 constexpr int kStageSlots = 4;                 // pinned staging for batched scene tables
 constexpr size_t kStageBytes = 1u << 20;
 
+// Root slots of fiber_intersect_pairs_noalloc, for callers that cannot
+// allocate: a fixed array in the code object, one copy per device, holding
+// slots for kScratchWaves waves (the resident waves of the plain and the
+// refining single-call grids on a 256-CU MI355X; 24 MiB). Host code never
+// passes the array's name to a kernel: each device's copy is reached through
+// the address hipGetSymbolAddress gives for it (DeviceInfo::scratch).
+constexpr int kScratchWaves = 6144;
+static __device__ __align__(256) float scratch[(size_t)kScratchWaves * 16 * kWave];
+
 struct DeviceInfo {
     std::atomic<bool> ready;
     int cus;
     int fused_resident[kVariants];             // resident waves per CU, per variant (as kFused)
+    float *scratch;                            // this device's copy of `scratch`
     std::mutex stage_mutex;
     void *stage[kStageSlots];                  // pinned host buffers for scene tables
     hipEvent_t stage_done[kStageSlots];
@@ -1249,6 +1259,11 @@ int device_info(DeviceInfo *&out)
                     return FI_ERR_HIP;
                 d.fused_resident[m] = nb > 0 ? nb : 1;
             }
+            // the device address of this device's copy of the static
+            // scratch array (taken with the device current)
+            d.scratch = nullptr;
+            if (hipGetSymbolAddress((void **)&d.scratch, HIP_SYMBOL(scratch)) != hipSuccess || !d.scratch)
+                return FI_ERR_HIP;
             for (int k = 0; k < kStageSlots; ++k) {
                 if (hipHostMalloc(&d.stage[k], kStageBytes, hipHostMallocDefault) != hipSuccess) return FI_ERR_HIP;
                 if (hipEventCreateWithFlags(&d.stage_done[k], hipEventDisableTiming) != hipSuccess) return FI_ERR_HIP;
@@ -1531,6 +1546,35 @@ int fiber_intersect_pairs(const float *rays, int64_t ray_stride, int64_t n_rays,
            pair_ray, pair_fiber, pair_depth, depth, n_pairs, t_out, u_out, hit_out, nullptr,
            refine ? t64_out : nullptr, refine ? u64_out : nullptr};
     return launch_with_workspace(refine ? kConservative : kPlain, a, workspace, workspace_bytes, stream);
+}
+
+int fiber_intersect_pairs_noalloc(const float *rays, int64_t ray_stride, int64_t n_rays,
+                                  const float *fibers, int64_t fiber_stride, int64_t n_fibers,
+                                  const int32_t *pair_ray, const int32_t *pair_fiber,
+                                  const uint8_t *pair_depth, int32_t depth, int64_t n_pairs,
+                                  uint32_t flags,
+                                  float *t_out, float *u_out, uint8_t *hit_out,
+                                  double *t64_out, double *u64_out,
+                                  void *stream)
+{
+    const int st = check_common(rays, ray_stride, n_rays, fibers, fiber_stride, n_fibers,
+                                pair_ray, pair_fiber, depth, n_pairs, flags, t_out, u_out, hit_out);
+    if (st != FI_OK || n_pairs == 0) return st;
+    const bool refine = (flags & FI_FP64_REFINE) != 0u;
+    if (refine && (!t64_out || !u64_out)) return FI_ERR_NULL;
+    (void)hipGetLastError();
+    DeviceInfo *d = nullptr;
+    const int ds = device_info(d);
+    if (ds != FI_OK) return ds;
+    const int mode = refine ? kConservative : kPlain;
+    // the grid never needs more slots than the array holds
+    int64_t waves = (int64_t)d->fused_resident[mode] * d->cus;
+    if (waves > kScratchWaves) waves = kScratchWaves;
+    Args a{rays, ray_stride, n_rays, fibers, fiber_stride, n_fibers,
+           pair_ray, pair_fiber, pair_depth, depth, n_pairs, t_out, u_out, hit_out, nullptr,
+           refine ? t64_out : nullptr, refine ? u64_out : nullptr};
+    // fibers gathered through pair_fiber are read in place (no records)
+    return launch(mode, a, d->scratch, waves, nullptr, (hipStream_t)stream);
 }
 
 int fiber_intersect_counts(const float *rays, int64_t ray_stride, int64_t n_rays,
