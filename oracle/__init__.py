@@ -30,10 +30,12 @@ def lib():
         L.fo_intersect_d.restype = C.c_int
         L.fo_batch_d.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_int64,
                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int64,
-                                 C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+                                 C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
+                                 C.c_void_p]
         L.fo_batch_d.restype = None
         L.fo_split_half.argtypes = [dp, dp, dp]
         L.fo_split_plane.argtypes = [dp, dp, dp]
+        L.fo_split_children.argtypes = [dp, dp, dp]
         L.fo_unit_ray_cylinder.argtypes = [dp, dp, C.c_double, dp, dp]
         L.fo_unit_ray_cylinder.restype = C.c_int
         L.fo_conservative_radius.argtypes = [dp]
@@ -69,12 +71,13 @@ def _d(a):
 
 
 def intersect_depth(rays, fibers, depth=9, pair_ray=None, pair_fiber=None,
-                    pair_depth=None, radius_scale=1.0, stats=False, nthreads=0):
+                    pair_depth=None, radius_scale=1.0, stats=False, nthreads=0, t_err=False):
     """ORACLE-D: the paper's depth-d method in FP64 for every pair.
 
-    Returns (t float64, u float64, hit uint8[, stats int32 (n, 4)]). ``stats``
-    columns: node tests, splits, backtracks (second-child visits), leaf level
-    (-1 on a miss)."""
+    Returns (t float64, u float64, hit uint8[, stats int32 (n, 4)][, t_err
+    float64]). ``stats`` columns: node tests, splits, backtracks (second-child
+    visits), leaf level (-1 on a miss). ``t_err``: error bound of each hit's t
+    in an FP32 evaluation (reading R14's node error model; 0 on a miss)."""
     rays = np.ascontiguousarray(rays, dtype=np.float32)
     fibers = np.ascontiguousarray(fibers, dtype=np.float32)
     pr = None if pair_ray is None else np.ascontiguousarray(pair_ray, dtype=np.int32)
@@ -90,10 +93,13 @@ def intersect_depth(rays, fibers, depth=9, pair_ray=None, pair_fiber=None,
     u = np.empty(n, np.float64)
     hit = np.empty(n, np.uint8)
     st = np.empty((n, 4), np.int32) if stats else None
+    te = np.empty(n, np.float64) if t_err else None
     lib().fo_batch_d(_ptr(rays), rays.shape[1], rays.shape[1], _ptr(fibers), fibers.shape[1],
                      fibers.shape[1], _ptr(pr), _ptr(pf), _ptr(pd), int(depth), n,
-                     float(radius_scale), _ptr(t), _ptr(u), _ptr(hit), _ptr(st), int(nthreads))
-    return (t, u, hit, st) if stats else (t, u, hit)
+                     float(radius_scale), _ptr(t), _ptr(u), _ptr(hit), _ptr(st), int(nthreads),
+                     _ptr(te))
+    out = (t, u, hit) + ((st,) if stats else ()) + ((te,) if t_err else ())
+    return out
 
 
 def intersect_exact(rays, fibers, pair_ray=None, pair_fiber=None, radius_scale=1.0,
@@ -176,6 +182,17 @@ def split_half(q16):
     R = np.empty(16)
     lib().fo_split_half(qp, L.ctypes.data_as(C.POINTER(C.c_double)),
                         R.ctypes.data_as(C.POINTER(C.c_double)))
+    return L, R
+
+
+def split_children(q16):
+    """The two children the depth-d recursion uses (de Casteljau halves with
+    the cusp rule of reading R13)."""
+    q, qp = _d(q16)
+    L = np.empty(16)
+    R = np.empty(16)
+    lib().fo_split_children(qp, L.ctypes.data_as(C.POINTER(C.c_double)),
+                            R.ctypes.data_as(C.POINTER(C.c_double)))
     return L, R
 
 

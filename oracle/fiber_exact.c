@@ -23,7 +23,11 @@
  *   inside the origin lies in a disc: a root of <C, D> with |C| <= r (t = 0);
  *   planar when Dz vanishes identically (every disc plane contains the ray
  *         direction), the ray lies in the disc at the roots of
- *         <(Cx, Cy), (Dx, Dy)> and enters it at Cz - sqrt(r^2 - Cx^2 - Cy^2).
+ *         <(Cx, Cy), (Dx, Dy)> and enters it at Cz - sqrt(r^2 - Cx^2 - Cy^2);
+ *   edge-on when every disc plane lies within 1e-6 rad of the ray (a curve
+ *         in a plane nearly normal to the ray), the side roots come from the
+ *         two factors of F (see edge_on_sides), whose roots F's expanded
+ *         coefficients cannot separate.
  * Every candidate lies in the solid, and the first point of the solid along
  * the ray is one of them as long as no disc passes through a focal point of
  * the sweep (radius below the radius of curvature: the "thin fiber"
@@ -181,6 +185,81 @@ static long double XY_ld(const curve_t *c, long double u)
     for (int k = 0; k < 2; ++k)
         for (int j = 0; j < 3; ++j) D[k] += e[j] * ((long double)c->q[j + 1][k] - (long double)c->q[j][k]);
     return C[0] * D[0] + C[1] * D[1];
+}
+
+/* The factors of F for an edge-on ray: g_s(u) = xy - s Dz sqrt(r^2 - rho^2)
+ * (s = +1 or -1), where F = -g_{+1} g_{-1}. A root of g_s with rho <= r is a
+ * point of the ray on the boundary circle of the disc at u, at
+ * t = Cz + s sqrt(r^2 - rho^2). *ok is 0 outside rho <= r. */
+static long double gs_ld(const curve_t *c, long double u, int s, int *ok, long double *t)
+{
+    const long double v = 1.0L - u;
+    const long double b[4] = {v * v * v, 3 * u * v * v, 3 * u * u * v, u * u * u};
+    const long double e[3] = {v * v, 2 * u * v, u * u};
+    long double C[4] = {0, 0, 0, 0}, D[3] = {0, 0, 0};
+    for (int k = 0; k < 4; ++k)
+        for (int j = 0; j < 4; ++j) C[k] += b[j] * (long double)c->q[j][k];
+    for (int k = 0; k < 3; ++k)
+        for (int j = 0; j < 3; ++j) D[k] += e[j] * ((long double)c->q[j + 1][k] - (long double)c->q[j][k]);
+    const long double rest = C[3] * C[3] - C[0] * C[0] - C[1] * C[1];
+    *ok = rest >= 0.0L;
+    const long double sr = *ok ? sqrtl(rest) : 0.0L;
+    if (t) *t = C[2] + s * sr;
+    return C[0] * D[0] + C[1] * D[1] - s * D[2] * sr;
+}
+
+/* Is the ray edge-on to the curve: every disc plane within 1e-6 rad of the
+ * ray direction (|C'z| <= 1e-6 |C'| wherever C' does not vanish)? Checked at
+ * 257 parameters. */
+static int edge_on(const curve_t *c)
+{
+    for (int k = 0; k <= 256; ++k) {
+        const double u = k / 256.0, v = 1.0 - u;
+        const double e[3] = {v * v, 2 * u * v, u * u};
+        double D[3] = {0, 0, 0};
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) D[i] += e[j] * (c->q[j + 1][i] - c->q[j][i]);
+        const double dn = sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+        if (fabs(D[2]) > 1e-6 * dn) return 0;
+    }
+    return 1;
+}
+
+/* Side points of an edge-on ray: crossings of g_{+1} and g_{-1} where
+ * rho <= r, found on 2^14 + 1 parameters and bisected in long double. Near
+ * each zero of xy each factor crosses once, so the entry and the exit of
+ * the disc there (1e-9 apart in u) are found separately. The earliest
+ * t in [0, tmax) is kept in (best, bu). */
+static void edge_on_sides(const curve_t *c, double tmax, double *best, double *bu)
+{
+    enum { N = 1 << 14 };
+    for (int s = -1; s <= 1; s += 2) {
+        int pok;
+        long double pg = gs_ld(c, 0.0L, s, &pok, NULL);
+        for (int k = 1; k <= N; ++k) {
+            const long double u = (long double)k / N;
+            int cok;
+            const long double cg = gs_ld(c, u, s, &cok, NULL);
+            if (pok && cok && (pg < 0.0L) != (cg < 0.0L)) {
+                long double lo = (long double)(k - 1) / N, hi = u, glo = pg;
+                for (int it = 0; it < 200; ++it) {
+                    const long double mid = 0.5L * (lo + hi);
+                    if (mid <= lo || mid >= hi) break;
+                    int mok;
+                    const long double gm = gs_ld(c, mid, s, &mok, NULL);
+                    if (!mok) break;
+                    if ((gm < 0.0L) == (glo < 0.0L)) { lo = mid; glo = gm; }
+                    else hi = mid;
+                }
+                long double t;
+                int tok;
+                gs_ld(c, 0.5L * (lo + hi), s, &tok, &t);
+                if (tok && t >= 0.0L && t < tmax && t < *best) { *best = (double)t; *bu = (double)(0.5L * (lo + hi)); }
+            }
+            pg = cg;
+            pok = cok;
+        }
+    }
 }
 
 typedef long double (*fn_t)(const curve_t *, long double);
@@ -367,7 +446,15 @@ static int exact_hit(const curve_t *c, double tmax, double *t_out, double *u_out
     /* side surface */
     double roots[128];
     int nr = 0;
-    isolate(c, F_ld, &F, 0.0, 1.0, roots, &nr, 128, 0);
+    if (edge_on(c)) {
+        /* F's two roots about each zero of xy are then closer than the
+         * rounding of its coefficients resolves: use its factors */
+        double bs = INFINITY, bus = NAN;
+        edge_on_sides(c, tmax, &bs, &bus);
+        if (bs < best) { best = bs; bu = bus; kind = 1; }
+    } else {
+        isolate(c, F_ld, &F, 0.0, 1.0, roots, &nr, 128, 0);
+    }
     double scale = 0.0;
     for (int j = 0; j < 4; ++j)
         for (int k = 0; k < 3; ++k) scale = fmax(scale, fabs(c->q[j][k]));

@@ -59,7 +59,9 @@
  *       non-negligible of (q1-q0, q2-q0, q3-q0) at the start and
  *       (q3-q2, q3-q1, q3-q0) at the end; a split tangent (1/8 of
  *       -q0 - q1 + q2 + q3, the children's tangent at the split point) by
- *       the chord. A zero-length chord gives distances to the point q0.
+ *       the chord as the split plane's normal, and the children take that
+ *       tangent as exactly zero (a cusp: snap_cusp). A zero-length chord
+ *       gives distances to the point q0.
  *   R14 the method's result is not continuous in its inputs: where a pruning
  *       or ordering comparison is a near tie, a rounding-sized perturbation
  *       selects another (equally valid) leaf. A comparison is a tie when its
@@ -314,10 +316,25 @@ static node_t anchored(const v4 qa[4])
 }
 
 /* the two halves at u = 1/2; the right half is re-anchored at the split point */
+/* R13 at a split: where the split tangent (l3 - l2 = r1 - r0, 1/8 of
+ * -q0 - q1 + q2 + q3) is negligible against the parent chord, its direction
+ * is rounding noise of the exact value zero -- the split point is a cusp. The
+ * children then take the exact value: their control points next to the split
+ * point coincide with it (xyz; the radius channel is untouched). This is
+ * what splitting the curve at the cusp beforehand gives (Sec. 3.4 requires
+ * splitting curves with cusps): two curves whose end tangents vanish there. */
+static void snap_cusp(const v4 q[4], v4 l[4], v4 r[4])
+{
+    if (!negligible(sub4(l[3], l[2]), sub4(q[3], q[0]))) return;
+    l[2] = mk4(l[3].x, l[3].y, l[3].z, l[2].w);
+    r[1] = mk4(r[0].x, r[0].y, r[0].z, r[1].w);
+}
+
 static void split_node(const node_t *a, node_t *L, node_t *R)
 {
     v4 l[4], r[4];
     split_half(a->q, l, r);
+    snap_cusp(a->q, l, r);
     const v4 s = l[3];
     L->o = a->o;
     R->o = mk4(a->o.x + s.x, a->o.y + s.y, a->o.z + s.z, 0.0);
@@ -350,6 +367,7 @@ typedef struct {
     double X;
     uint64_t flip_mask;
     int n_ties;
+    int force_vis;      /* +1: every visibility tie decided visible */
 } ties_t;
 
 typedef struct {
@@ -357,6 +375,7 @@ typedef struct {
     double tmax;
     int64_t tests, splits, backtracks;
     double t, u;
+    double t_err;       /* error bound of t in an FP32 evaluation (as for ties) */
     int level;
     ties_t ties;
 } search_t;
@@ -390,6 +409,24 @@ static int decide(search_t *S, int value, double diff, double margin)
     return value;
 }
 
+/* A visibility test (does the ray meet the node's cylinder inside its
+ * interval?). A grazing ray meets the nodes on its path to a leaf near their
+ * tangent point, so their visibility tests tie together, with correlated
+ * rounding: force_vis > 0 decides all of them visible (as a radius larger
+ * by the error bound would), which no choice of two single flips can reach.
+ * The opposite choice is not offered: below the FP32 resolution every leaf's
+ * visibility is a tie, and deciding all of them invisible would drop a ray
+ * that passes through the union of neighbouring leaves. */
+static int decide_vis(search_t *S, int value, double diff, double margin)
+{
+    if (S->ties.force_vis != 0 && S->ties.scale > 0.0 && isfinite(diff) &&
+        fabs(diff) <= S->ties.scale * margin) {
+        S->ties.n_ties++;
+        return S->ties.force_vis > 0;
+    }
+    return decide(S, value, diff, margin);
+}
+
 static int visit(search_t *S, const node_t *N, double lo, double hi, double elo, double ehi,
                  int level, double u0, double u1)
 {
@@ -406,14 +443,14 @@ static int visit(search_t *S, const node_t *N, double lo, double hi, double elo,
         tx = INFINITY;
     } else {
         /* e = R^2 - dist^2 moves by up to 2 (R + dist) delta per unit of R and dist */
-        if (!decide(S, cy.e >= 0.0, cy.e, 4.0 * (R + cy.dist) * delta)) return 0;
+        if (!decide_vis(S, cy.e >= 0.0, cy.e, 4.0 * (R + cy.dist) * delta)) return 0;
         te = cy.t_cpa - cy.s;                            /* a flipped tangency: s = 0 */
         tx = cy.t_cpa + cy.s;
         ec = cyl_err(delta, &cy, a, R);
     }
     const double enter = fmax(te, lo), leave = fmin(tx, hi);
     const double e_enter = te >= lo ? ec : elo, e_leave = tx <= hi ? ec : ehi;
-    if (!decide(S, enter <= leave, leave - enter, e_enter + e_leave)) return 0;
+    if (!decide_vis(S, enter <= leave, leave - enter, e_enter + e_leave)) return 0;
 
     if (level >= S->depth) {
         const double t = enter;
@@ -424,6 +461,7 @@ static int visit(search_t *S, const node_t *N, double lo, double hi, double elo,
             ul = fmin(1.0, fmax(0.0, dot3(h, a) / c));
         }
         S->t = t;
+        S->t_err = e_enter;
         S->u = u0 + ul * (u1 - u0);
         S->level = level;
         return 1;
@@ -441,10 +479,16 @@ static int visit(search_t *S, const node_t *N, double lo, double hi, double elo,
         const double ep = plane_err(delta, n, tp);
         const int beyond_entry = decide(S, tp > te, tp - te, ep + ec);
         const int before_exit = decide(S, tp < tx, tx - tp, ep + ec);
+        /* a flipped side of the entry stands for an FP32 crossing on the
+         * other side of it: the half it narrows takes the crossing at the
+         * far end of its error bound (for a plane nearly parallel to the
+         * ray, ep is large and the crossing's sign itself is undetermined) */
+        double tpn = tp;
+        if (beyond_entry != (tp > te)) tpn = beyond_entry ? tp + ep : tp - ep;
         go_right = beyond_entry != (n.z > 0.0);
         both = beyond_entry && before_exit;
-        if (beyond_entry) { if (tp < fhi) { fhi = tp; efhi = ep; } }
-        else              { if (tp > flo) { flo = tp; eflo = ep; } }
+        if (beyond_entry) { if (tpn < fhi) { fhi = tpn; efhi = ep; } }
+        else              { if (tpn > flo) { flo = tpn; eflo = ep; } }
     } else {
         const double side = -c;            /* <(0,0,t) - s, n> for every t */
         go_right = side > 0.0;
@@ -474,13 +518,14 @@ int fo_version(void) { return 1; }
  * (x, y, z, r). stats (may be NULL) receives node tests, splits, backtracks
  * and the level of the leaf that was hit (-1 on a miss). Returns 1 on a hit. */
 static int intersect_with_ties(const double ray[7], const double fiber[16], int depth,
-                               double scale, uint64_t flip_mask, int *n_ties,
-                               double *t_out, double *u_out, int64_t stats[4])
+                               double scale, uint64_t flip_mask, int force_vis, int *n_ties,
+                               double *t_out, double *u_out, int64_t stats[4], double *t_err)
 {
     search_t S;
     memset(&S, 0, sizeof S);
     S.ties.scale = scale;
     S.ties.flip_mask = flip_mask;
+    S.ties.force_vis = force_vis;
     S.depth = depth;
     S.tmax = ray[6];
     S.level = -1;
@@ -502,35 +547,44 @@ static int intersect_with_ties(const double ray[7], const double fiber[16], int 
         stats[0] = S.tests; stats[1] = S.splits; stats[2] = S.backtracks; stats[3] = S.level;
     }
     if (n_ties) *n_ties = S.ties.n_ties;
+    if (t_err) {
+        /* the node error model needs X, which the tie search sets up */
+        *t_err = hit ? S.t_err : 0.0;
+    }
     return hit;
 }
 
 int fo_intersect_d(const double ray[7], const double fiber[16], int depth,
                    double *t_out, double *u_out, int64_t stats[4])
 {
-    return intersect_with_ties(ray, fiber, depth, 0.0, 0, NULL, t_out, u_out, stats);
+    return intersect_with_ties(ray, fiber, depth, 0.0, 0, 0, NULL, t_out, u_out, stats, NULL);
 }
 
 /* Every result reachable from one pair by flipping at most max_flips (1 or 2)
  * near-tie decisions (sides within `scale` times their FP32 error bounds,
- * R14). Writes up to max_out results (t, u, hit), the unflipped one first;
- * returns how many were written. */
+ * R14), and the result with every visibility tie decided visible
+ * (decide_vis). Writes up to max_out results (t, u, hit), the unflipped one
+ * first; returns how many were written. */
 int fo_tie_outcomes(const double ray[7], const double fiber[16], int depth, double scale,
                     int max_flips, int max_out, double *t_out, double *u_out, int *hit_out)
 {
     int n = 0, k0 = 0;
     double t, u;
-    int h = intersect_with_ties(ray, fiber, depth, scale, 0, &k0, &t, &u, NULL);
+    int h = intersect_with_ties(ray, fiber, depth, scale, 0, 0, &k0, &t, &u, NULL, NULL);
     if (max_out < 1) return 0;
     t_out[n] = t; u_out[n] = u; hit_out[n] = h; n++;
+    if (scale > 0.0 && n < max_out) {
+        h = intersect_with_ties(ray, fiber, depth, scale, 0, 1, NULL, &t, &u, NULL, NULL);
+        t_out[n] = t; u_out[n] = u; hit_out[n] = h; n++;
+    }
     for (int j = 0; j < k0 && j < 64 && n < max_out; ++j) {
         int kj = 0;
-        h = intersect_with_ties(ray, fiber, depth, scale, 1ull << j, &kj, &t, &u, NULL);
+        h = intersect_with_ties(ray, fiber, depth, scale, 1ull << j, 0, &kj, &t, &u, NULL, NULL);
         t_out[n] = t; u_out[n] = u; hit_out[n] = h; n++;
         if (max_flips < 2) continue;
         for (int k = j + 1; k < kj && k < 64 && n < max_out; ++k) {
-            h = intersect_with_ties(ray, fiber, depth, scale, (1ull << j) | (1ull << k), NULL,
-                                    &t, &u, NULL);
+            h = intersect_with_ties(ray, fiber, depth, scale, (1ull << j) | (1ull << k), 0, NULL,
+                                    &t, &u, NULL, NULL);
             t_out[n] = t; u_out[n] = u; hit_out[n] = h; n++;
         }
     }
@@ -542,14 +596,16 @@ int fo_tie_outcomes(const double ray[7], const double fiber[16], int depth, doub
  * ray pair_ray[i] (or i when NULL) and fiber pair_fiber[i] (or i), at depth
  * pair_depth[i] (or depth). Radius control values are multiplied by
  * radius_scale (silhouette-band probes). stats_out (may be NULL) holds 4
- * int32 per pair. Pairs whose indices fall outside [0, n_rays) or
- * [0, n_fibers) are misses. */
+ * int32 per pair; terr_out (may be NULL) the error bound of each hit's t in
+ * an FP32 evaluation (the entry's bound from the tie model, R14; 0 on a
+ * miss). Pairs whose indices fall outside [0, n_rays) or [0, n_fibers) are
+ * misses. */
 void fo_batch_d(const float *rays, int64_t ray_stride, int64_t n_rays,
                 const float *fibers, int64_t fiber_stride, int64_t n_fibers,
                 const int32_t *pair_ray, const int32_t *pair_fiber,
                 const uint8_t *pair_depth, int depth, int64_t n,
                 double radius_scale, double *t_out, double *u_out,
-                uint8_t *hit_out, int32_t *stats_out, int nthreads)
+                uint8_t *hit_out, int32_t *stats_out, int nthreads, double *terr_out)
 {
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -559,15 +615,16 @@ void fo_batch_d(const float *rays, int64_t ray_stride, int64_t n_rays,
         const int64_t ri = pair_ray ? pair_ray[i] : i;
         const int64_t fi = pair_fiber ? pair_fiber[i] : i;
         const int d = pair_depth ? (int)pair_depth[i] : depth;
-        double ray[7], fib[16], t = INFINITY, u = NAN;
+        double ray[7], fib[16], t = INFINITY, u = NAN, te = 0.0;
         int64_t st[4] = {0, 0, 0, -1};
         int hit = 0;
         if (ri >= 0 && ri < n_rays && fi >= 0 && fi < n_fibers) {
             for (int r = 0; r < 7; ++r) ray[r] = rays[r * ray_stride + ri];
             for (int r = 0; r < 16; ++r) fib[r] = fibers[r * fiber_stride + fi];
             for (int k = 0; k < 4; ++k) fib[4 * k + 3] *= radius_scale;
-            hit = fo_intersect_d(ray, fib, d, &t, &u, st);
+            hit = intersect_with_ties(ray, fib, d, 0.0, 0, 0, NULL, &t, &u, st, &te);
         }
+        if (terr_out) terr_out[i] = te;
         t_out[i] = t;
         u_out[i] = u;
         hit_out[i] = (uint8_t)hit;
@@ -584,6 +641,20 @@ void fo_split_half(const double q[16], double L[16], double R[16])
     v4 a[4], l[4], r[4];
     for (int k = 0; k < 4; ++k) a[k] = mk4(q[4 * k], q[4 * k + 1], q[4 * k + 2], q[4 * k + 3]);
     split_half(a, l, r);
+    for (int k = 0; k < 4; ++k) {
+        L[4 * k] = l[k].x; L[4 * k + 1] = l[k].y; L[4 * k + 2] = l[k].z; L[4 * k + 3] = l[k].w;
+        R[4 * k] = r[k].x; R[4 * k + 1] = r[k].y; R[4 * k + 2] = r[k].z; R[4 * k + 3] = r[k].w;
+    }
+}
+
+/* The children the recursion uses: de Casteljau halves with the cusp rule
+ * (snap_cusp). */
+void fo_split_children(const double q[16], double L[16], double R[16])
+{
+    v4 a[4], l[4], r[4];
+    for (int k = 0; k < 4; ++k) a[k] = mk4(q[4 * k], q[4 * k + 1], q[4 * k + 2], q[4 * k + 3]);
+    split_half(a, l, r);
+    snap_cusp(a, l, r);
     for (int k = 0; k < 4; ++k) {
         L[4 * k] = l[k].x; L[4 * k + 1] = l[k].y; L[4 * k + 2] = l[k].z; L[4 * k + 3] = l[k].w;
         R[4 * k] = r[k].x; R[4 * k + 1] = r[k].y; R[4 * k + 2] = r[k].z; R[4 * k + 3] = r[k].w;

@@ -42,7 +42,6 @@ namespace {
 constexpr int kWave = 64;                     // gfx950 wavefront
 constexpr uint32_t kRootSize = 1u << 23;      // parametric domain [0, 1) in units of 2^-23
 constexpr int kMaxTrips = 1 << 16;            // hang guard; real pairs need < 200 trips
-constexpr float kParallelG = 1e-30f;          // axis treated as parallel to the ray below this
 #ifndef FIBERHIT_PARENT_CACHE
 #define FIBERHIT_PARENT_CACHE 1
 #endif
@@ -181,9 +180,15 @@ __device__ __forceinline__ float conservative_radius(const Node &c)
 // line through o along a (Appendix A). False on a miss.
 __device__ __forceinline__ bool unit_ray_cylinder(const V4 &o, const V4 &a, float r, float &te, float &tx)
 {
-    // both cases are evaluated and selected: no divergent branch
+    // both cases are evaluated and selected: no divergent branch. The axis
+    // counts as parallel to the ray when its across-ray part is below 2^-50
+    // of its along-ray part (or zero): beyond that the general formula's
+    // terms (up to a.z^2 / g) would leave the float range, while the
+    // cylinder it describes already spans the whole ray. The test is relative:
+    // the chord of a node next to a cusp or a stalled end shrinks like 4^-level,
+    // and an absolute threshold took such nodes for parallel ones.
     const float g = fmaf(a.x, a.x, a.y * a.y);
-    const bool parallel = g < kParallelG;
+    const bool parallel = g <= 0x1p-100f * (a.z * a.z);
     const float dd = fmaf(a.x, o.y, -(a.y * o.x));
     const float h = rcp(g);
     const float e = fmaf(-(dd * dd), h, r * r);
@@ -195,8 +200,13 @@ __device__ __forceinline__ bool unit_ray_cylinder(const V4 &o, const V4 &a, floa
     return parallel ? inside : e >= 0.0f;
 }
 
-// Split quantities of Section 3.1: centre offset dp and split tangent tc.
-__device__ __forceinline__ void split_terms(const Node &c, V4 &dp, V4 &tc)
+// Split quantities of Section 3.1: centre offset dp and split tangent tc
+// (1/8 of -q0 - q1 + q2 + q3, the children's tangent at the split point).
+// A negligible split tangent is rounding noise of the exact value zero: the
+// split point is a cusp, and the children take a zero tangent there (xyz;
+// the radius channel keeps its slope), as if the curve had been split at the
+// cusp beforehand. Returns whether that happened.
+__device__ __forceinline__ bool split_terms(const Node &c, V4 &dp, V4 &tc)
 {
     dp.x = fmaf(0.375f, c.t0.x - c.t1.x, 0.5f * c.d.x);
     dp.y = fmaf(0.375f, c.t0.y - c.t1.y, 0.5f * c.d.y);
@@ -206,6 +216,11 @@ __device__ __forceinline__ void split_terms(const Node &c, V4 &dp, V4 &tc)
     tc.y = fmaf(-0.125f, c.t0.y + c.t1.y, 0.25f * c.d.y);
     tc.z = fmaf(-0.125f, c.t0.z + c.t1.z, 0.25f * c.d.z);
     tc.w = fmaf(-0.125f, c.t0.w + c.t1.w, 0.25f * c.d.w);
+    const bool cusp = negligible(tc.x, tc.y, tc.z, dot3(c.d.x, c.d.y, c.d.z, c.d.x, c.d.y, c.d.z));
+    tc.x = cusp ? 0.0f : tc.x;
+    tc.y = cusp ? 0.0f : tc.y;
+    tc.z = cusp ? 0.0f : tc.z;
+    return cusp;
 }
 
 // Keep one half (Section 3.1): left (p, dp, t0/2, tc) or right (p+dp, d-dp, tc, t1/2).
@@ -322,16 +337,57 @@ __device__ __forceinline__ void eval_curve(const Curve64 &c, double u, double C[
         E[k] = fma(v, c.q[2][k] - 2.0 * c.q[1][k] + c.q[0][k], u * (c.q[3][k] - 2.0 * c.q[2][k] + c.q[1][k]));
 }
 
+// Normal of the disc at an end of the curve whose tangent vanishes (squared
+// length at most 2^-40 of the squared chord; p1 = p0 or p2 = p3): the disc
+// planes of the nearby u converge to the plane normal to the next
+// control-polygon edge from that end (p2 - p0, resp. p3 - p1), or to the
+// chord if that vanishes too. D (C'/3 at u) is replaced by that direction;
+// elsewhere it is left alone.
+__device__ __forceinline__ void end_disc_normal(const Curve64 &c, double u, double D[4])
+{
+    if (u != 0.0 && u != 1.0) return;
+    const double ax = c.q[3][0] - c.q[0][0], ay = c.q[3][1] - c.q[0][1], az = c.q[3][2] - c.q[0][2];
+    const double lim = 0x1p-40 * (ax * ax + ay * ay + az * az);
+    if (D[0] * D[0] + D[1] * D[1] + D[2] * D[2] > lim) return;
+    const int from = u == 0.0 ? 0 : 1, to = u == 0.0 ? 2 : 3;     // p2 - p0 or p3 - p1
+    double nx = c.q[to][0] - c.q[from][0], ny = c.q[to][1] - c.q[from][1], nz = c.q[to][2] - c.q[from][2];
+    if (nx * nx + ny * ny + nz * nz <= lim) { nx = ax; ny = ay; nz = az; }
+    D[0] = nx;
+    D[1] = ny;
+    D[2] = nz;
+}
+
 // Ray point in the disc plane at u, and its signed excess |P-C|^2 - r^2.
 __device__ __forceinline__ bool disc_point(const Curve64 &c, double u, double &t, double &phi)
 {
     double C[4], D[4], E[3];
     eval_curve(c, u, C, D, E);
+    end_disc_normal(c, u, D);
     if (D[2] == 0.0) return false;
     t = (C[0] * D[0] + C[1] * D[1] + C[2] * D[2]) / D[2];
     const double h = t - C[2];
     phi = C[0] * C[0] + C[1] * C[1] + h * h - C[3] * C[3];
     return true;
+}
+
+// t of a boundary point known to lie on the circle of the disc at u (C, D
+// from eval_curve) whose plane crossing is t_plane = <C, D> / D_z. On the
+// circle the same point is also C_z +- sqrt(r^2 - C_x^2 - C_y^2). The plane
+// form loses about |C| |D| / |D_z| units of rounding as the disc plane turns
+// towards the ray (D_z -> 0, near-collinear curves seen along their normal);
+// the circle form loses about r^2 / sqrt(r^2 - C_x^2 - C_y^2) as the ray
+// grazes the circle. The better conditioned form is returned, its sign
+// taken from the plane form.
+__device__ __forceinline__ double circle_t(const double C[4], const double D[4], double t_plane)
+{
+    const double rest = C[3] * C[3] - C[0] * C[0] - C[1] * C[1];
+    if (!(rest > 0.0)) return t_plane;
+    const double sr = sqrt(rest);
+    const double e_plane = sqrt((C[0] * C[0] + C[1] * C[1] + C[2] * C[2]) * (D[0] * D[0] + D[1] * D[1] + D[2] * D[2])) /
+                           fabs(D[2]);
+    const double e_circle = C[3] * C[3] / sr;
+    if (!(e_circle < e_plane)) return t_plane;
+    return t_plane >= C[2] ? C[2] + sr : C[2] - sr;
 }
 
 // Newton's method on (f1, f2) from (t, u): true when it converges to a
@@ -392,6 +448,7 @@ __device__ __forceinline__ bool boundary_root(const Curve64 &c, double lo, doubl
         double C[4], D[4], E[3];
         eval_curve(c, u, C, D, E);
         if (!has_disc(c, D)) return false;
+        t = circle_t(C, D, t);
     }
     double tn = t, un = u;
     if (newton_surface(c, tn, un) && fabs(un - u) <= 4.0 * (hi - lo) + 0x1p-50) {
@@ -550,6 +607,7 @@ __device__ __forceinline__ void leaf_candidates(const Curve64 &c, double ua, dou
         if ((e == 0 && ua > 0.0) || (e == 1 && ub < 1.0)) continue;
         double C[4], D[4], E[3];
         eval_curve(c, (double)e, C, D, E);
+        end_disc_normal(c, (double)e, D);      // a vanishing end tangent: the limit plane
         if (D[2] == 0.0) continue;
         const double tc = (C[0] * D[0] + C[1] * D[1] + C[2] * D[2]) / D[2];
         const double hz = tc - C[2];
@@ -724,14 +782,11 @@ struct Split {
 template <int MODE>
 __device__ __forceinline__ void split_plane(const Lane &L, float te, float tx, Split &sp)
 {
-    split_terms(L.c, sp.dp, sp.tc);
-    float nx = sp.tc.x, ny = sp.tc.y, nz = sp.tc.z;
-    if (negligible(nx, ny, nz, dot3(L.c.d.x, L.c.d.y, L.c.d.z, L.c.d.x, L.c.d.y, L.c.d.z))) {
-        // rare (a cusp at the split point): split normal to the chord
-        nx = L.c.d.x;
-        ny = L.c.d.y;
-        nz = L.c.d.z;
-    }
+    // at a cusp (no split tangent) the split plane is normal to the chord
+    const bool cusp = split_terms(L.c, sp.dp, sp.tc);
+    const float nx = cusp ? L.c.d.x : sp.tc.x;
+    const float ny = cusp ? L.c.d.y : sp.tc.y;
+    const float nz = cusp ? L.c.d.z : sp.tc.z;
     const float qx = L.c.p.x + sp.dp.x, qy = L.c.p.y + sp.dp.y, qz = L.c.p.z + sp.dp.z;
     const float cs = dot3(qx, qy, qz, nx, ny, nz);
     const float tp = cs * rcp(nz);

@@ -1,7 +1,14 @@
 """Degenerate geometry on the GPU: cusps, near-collinear control points, zero
 tangents and 1000:1 tapers, with rays along and across the chord (including
-exactly axis-aligned cases). Curves that break the constraints of Section 3.4
-are reported, not asserted: the paper requires splitting them beforehand."""
+exactly axis-aligned cases).
+
+FP32 results are held to the depth oracle's bar for every family, cusps and
+other curves outside the constraints of Section 3.4 included: both sides
+apply the same rules to them (a negligible split tangent is a cusp, where the
+children take a zero tangent). Refined results are held to the exact oracle's
+bar for every curve that meets the constraints; curves outside them (the
+paper splits them beforehand) have no swept-disc surface of the method's
+kind and are reported only."""
 import sys
 
 import numpy as np
@@ -52,8 +59,7 @@ def test_degenerate_plain_against_depth_oracle(degenerate):
             say(f"[degenerate] {name:15s} valid={val!s:5s} n={m.sum():6d} "
                 f"flag_disagree={st['flag_disagree_rate']:.2e} unresolved={st['unresolved']} "
                 f"max_rel_t={st['max_rel_t']:.2e} tie_resolved={st['tie_resolved']}")
-            if val:
-                assert st["ok"], (name, st)
+            assert st["ok"], (name, val, st)
     # exact axis-aligned cases (zero plane-normal z, axes parallel to the ray)
     ex = w.meta["exact_axes"] & valid
     idx = np.nonzero(ex)[0]
@@ -82,15 +88,18 @@ def test_degenerate_refined_against_exact_oracle(degenerate):
             if not m.any():
                 continue
             both = m & hg & hx
-            rel = np.abs(t64[both] - t_x[both]) / t_x[both]
+            with np.errstate(invalid="ignore"):
+                rel = np.abs(t64[both] - t_x[both]) / t_x[both]
             rate = float((hg[m] != hx[m]).mean())
             say(f"[refined]    {name:15s} valid={val!s:5s} n={m.sum():6d} flag_disagree={rate:.2e} "
                 f"max_rel_t={rel.max() if rel.size else 0:.2e} "
                 f"p99.9_rel_t={np.quantile(rel, 0.999) if rel.size else 0:.2e}")
-            for i in np.nonzero((m & (hg != hx)) | (both & (np.abs(t64 - t_x) > 1e-12 * np.abs(t_x))))[0][:6]:
+            with np.errstate(invalid="ignore"):
+                far = both & (np.abs(t64 - t_x) > 1e-12 * np.abs(t_x))
+            for i in np.nonzero((m & (hg != hx)) | far)[0][:6]:
                 say(f"[refined]      pair {i}: depth={w.pair_depth[i]} gpu hit={hg[i]} t64={t64[i]!r} "
                     f"u64={u64[i]!r} t32={t32[i]!r} | exact hit={hx[i]} t={t_x[i]!r} u={u_x[i]!r} "
                     f"kind={kind[i]}")
-            if val and name in ("near-collinear", "steep taper"):
+            if val:
                 assert rate == 0.0, name
-                assert rel.max() <= 1e-12, (name, rel.max())
+                assert rel.size == 0 or rel.max() <= 1e-12, (name, rel.max())

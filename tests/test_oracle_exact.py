@@ -223,3 +223,46 @@ def test_zero_end_tangent_straight_fiber_is_the_capped_cylinder(ends):
         assert np.array_equal(hd[stable], h_cf[stable]), d
         bd = stable & h_cf & hd
         assert np.max(np.abs(td[bd] - t_cf[bd]) / t_cf[bd]) < 1e-11, d
+
+
+@pytest.mark.parametrize("zero_tangents", [False, True])
+def test_edge_on_rays_equal_capped_cylinder(zero_tangents):
+    """Rays within 1e-10..1e-7 rad of perpendicular to straight constant-
+    radius fibers: every disc plane is nearly parallel to the ray, and the
+    entry and exit of the disc the ray crosses are two roots of the side
+    polynomial about 1e-9 apart. The oracle must still give the analytic
+    capped-cylinder entry (side hits, relative t 1e-12), with evenly spaced
+    control points and with p1 = p0, p2 = p3 (a stalled parametrisation)."""
+    rng = np.random.default_rng(61 + zero_tangents)
+    n = 300
+    a = rng.uniform(0, 1, (n, 3))
+    ax = rng.standard_normal((n, 3))
+    ax /= np.linalg.norm(ax, axis=1, keepdims=True)
+    L = rng.uniform(0.05, 0.5, n)
+    r = rng.uniform(0.001, 0.01, n)
+    # a unit vector normal to the axis, tilted towards it by a tiny angle
+    perp = np.cross(ax, rng.standard_normal((n, 3)))
+    perp /= np.linalg.norm(perp, axis=1, keepdims=True)
+    tilt = 10.0 ** rng.uniform(-10, -7, n)
+    Dn = perp * np.cos(tilt)[:, None] + ax * np.sin(tilt)[:, None]
+    s = rng.uniform(0.1, 0.9, n)              # where along the fiber the ray passes
+    off = rng.uniform(-0.9, 0.9, n) * r       # and how far from the axis
+    side = np.cross(Dn, ax)
+    side /= np.linalg.norm(side, axis=1, keepdims=True)
+    target = a + (s * L)[:, None] * ax + off[:, None] * side
+    O = target - 2.0 * Dn
+    P = np.empty((n, 4, 4))
+    for k in range(4):
+        f = (0.0 if k < 2 else 1.0) if zero_tangents else k / 3.0
+        P[:, k, :3] = a + (f * L)[:, None] * ax
+        P[:, k, 3] = r
+    rays = np.concatenate([O, Dn, np.full((n, 1), 10.0)], axis=1).T.copy()
+    fibers = P.reshape(n, 16).T.copy()
+    t_cf, u_cf, h_cf = capped_cylinder(O, Dn, P[:, 0, :3], P[:, 3, :3], r, np.full(n, 10.0))
+    assert h_cf.all()
+    t = np.empty(n)
+    kind = np.empty(n, int)
+    for i in range(n):
+        kind[i], t[i], _ = oracle.single_exact(rays[:, i], fibers[:, i])
+    assert np.all(kind == 1), np.unique(kind, return_counts=True)
+    assert np.max(np.abs(t - t_cf) / t_cf) < 1e-12

@@ -24,9 +24,9 @@ MUTANTS = [
      "go_right = beyond_entry == (n.z > 0.0);"),
     ("second child never visited", D, "if (!both) return 0;", "if (1) return 0;"),
     ("radius without the control-point distance", D, "return sqrt(fmax(d1, d2)) + rmax;", "return rmax;"),
-    ("interval narrowed on the wrong side", D, "if (beyond_entry) { if (tp < fhi)", "if (!beyond_entry) { if (tp < fhi)"),
+    ("interval narrowed on the wrong side", D, "if (beyond_entry) { if (tpn < fhi)", "if (!beyond_entry) { if (tpn < fhi)"),
     ("leaf t without the cap plane", D, "const double t = enter;", "const double t = te;"),
-    ("visibility without the cropped interval", D, "decide(S, enter <= leave,", "decide(S, tx >= lo && te <= hi,"),
+    ("visibility without the cropped interval", D, "decide_vis(S, enter <= leave,", "decide_vis(S, tx >= lo && te <= hi,"),
     ("wrong sign in the ray-axis distance", D, "const double dd = a.x * o.y - a.y * o.x;",
      "const double dd = a.x * o.y + a.y * o.x;"),
     ("wrong de Casteljau split point", D, "const v4 s = scale4(add4(m012, m123), 0.5);",
@@ -38,10 +38,20 @@ MUTANTS = [
      "return visit(S, second, lo, hi, elo, ehi, level + 1, s0, s1);"),
     ("tangents negligible only when exactly zero", D, "return dot3(v, v) <= 0x1p-40 * dot3(chord, chord);",
      "return zero3(v);"),
+    ("grazing ties never decided together", D, "return S->ties.force_vis > 0;", "return value;"),
+    ("visibility forced outside ties", D,
+     "if (S->ties.force_vis != 0 && S->ties.scale > 0.0 && isfinite(diff) &&\n        fabs(diff) <= S->ties.scale * margin) {",
+     "if (S->ties.force_vis != 0) {"),
+    ("flipped crossing kept at its value", D,
+     "if (beyond_entry != (tp > te)) tpn = beyond_entry ? tp + ep : tp - ep;", "(void)0;"),
+    ("cusp children keep the noise of the split tangent", D,
+     "if (!negligible(sub4(l[3], l[2]), sub4(q[3], q[0]))) return;", "return;"),
     ("tie margin 2^10 too wide", D, "return (2.0 + 2.0 * level) * 0x1p-24 * S->ties.X;",
      "return (2.0 + 2.0 * level) * 0x1p-14 * S->ties.X;"),
     ("exact oracle: radius term with the wrong sign", X, "F = badd(&F, &a3, -1.0);", "F = badd(&F, &a3, 1.0);"),
     ("exact oracle: no limit disc at a zero end tangent", X, "while (j < 2 && cand[j][0]", "while (0 && cand[j][0]"),
+    ("exact oracle: edge-on rays through the expanded polynomial", X, "if (edge_on(c)) {", "if (0) {"),
+    ("exact oracle: edge-on exit taken for the entry", X, "if (t) *t = C[2] + s * sr;", "if (t) *t = C[2] + sr;"),
     ("exact oracle: circle point on the wrong side", X,
      "tsq = fabs((tm - C[2]) * D[2] - xy) <= fabs((tp - C[2]) * D[2] - xy) ? tm : tp;",
      "tsq = fabs((tm - C[2]) * D[2] - xy) <= fabs((tp - C[2]) * D[2] - xy) ? tp : tm;"),

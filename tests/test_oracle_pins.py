@@ -582,6 +582,35 @@ def test_cusp_split_plane_is_normal_to_the_chord():
             assert cos > 1 - 1e-9, (eps, cos)
 
 
+def test_cusp_children_take_a_zero_tangent():
+    """At an exact cusp the children the recursion uses have zero tangents at
+    the split point -- their control points next to it coincide with it, in
+    any rigid motion -- and are otherwise de Casteljau's halves; a curve whose
+    split tangent is 1e-4 of the chord keeps de Casteljau's halves exactly."""
+    rng = np.random.default_rng(47)
+    for _ in range(40):
+        L = rng.uniform(0.1, 1.0)
+        h = rng.uniform(0.05, 0.5) * L
+        R, shift = _rotation(rng), rng.uniform(-1, 1, 3)
+        for eps in (0.0, 1e-7 * L, 1e-4 * L):
+            Q = _cusp(L, h, eps) @ R.T + shift
+            radii = rng.uniform(0.001, 0.02, (4, 1))
+            q16 = np.concatenate([Q, radii], axis=1).reshape(16)
+            Lc, Rc = (x.reshape(4, 4) for x in oracle.split_children(q16))
+            Lh, Rh = (x.reshape(4, 4) for x in oracle.split_half(q16))
+            mid = bezier(Q[None], np.array([[0.5]]))[0, 0]
+            assert np.allclose(Lc[3, :3], mid, atol=1e-13) and np.array_equal(Lc[3], Rc[0])
+            if eps < 1e-6 * L:
+                assert np.array_equal(Lc[2, :3], Lc[3, :3]) and np.array_equal(Rc[1, :3], Rc[0, :3])
+                assert Lc[2, 3] == Lh[2, 3] and Rc[1, 3] == Rh[1, 3]      # radius slope kept
+                keep = [(Lc, Lh, (0, 1, 3)), (Rc, Rh, (0, 2, 3))]
+            else:
+                keep = [(Lc, Lh, (0, 1, 2, 3)), (Rc, Rh, (0, 1, 2, 3))]
+            for a, b, rows in keep:
+                for k in rows:
+                    assert np.array_equal(a[k], b[k])
+
+
 def test_cusp_results_survive_a_rigid_motion_of_the_scene():
     """On exact cusps the tangent at the split point is rounding noise; with
     the threshold the split plane is normal to the chord, so moving the whole
@@ -620,19 +649,18 @@ STRAIGHT = np.array([0, 0, 0, R_TIE, 1 / 3, 0, 0, R_TIE, 2 / 3, 0, 0, R_TIE, 1, 
 def test_tie_at_a_cap_rim_gives_hit_and_miss():
     """A ray that leaves the cylinder exactly on the rim of the start cap
     touches the capped solid in one point: entering at t = 3 sqrt(2) r or
-    missing are both results of the method within rounding. (The rim is a
+    missing are both results of the method within rounding. The rim is a
     tie at every node on the path to the first leaf, so a hit needs every
-    one of them decided as visible; with at most two flips the outcomes
-    span both results up to depth 2.) Moving the ray by 1e-3 r decides it at
-    every depth."""
+    one of them decided as visible: single flips reach it only up to depth
+    2, the outcome with every visibility tie decided visible at every depth.
+    Moving the ray by 1e-3 r decides it at every depth."""
     r = R_TIE
     t_star = 3 * math.sqrt(2) * r
     for depth in (0, 1, 2, 9, 22):
         ray = np.array([-3 * r, 0, 2 * r, 1, 0, -1, 100.0])
         t, u, h = oracle.tie_outcomes(ray, STRAIGHT, depth, scale=1.0)
         assert len(t) > 1, depth
-        if depth <= 2:
-            assert h.any() and (~h).any(), depth
+        assert h.any() and (~h).any(), depth
         assert np.all(np.abs(t[h] - t_star) <= 1e-12 * t_star) and np.all(np.abs(u[h]) <= 1e-12)
         assert len(oracle.tie_outcomes(ray, STRAIGHT, depth, scale=0.0)[0]) == 1
         for dz, want in ((1e-3 * r, True), (-1e-3 * r, False)):
@@ -664,6 +692,51 @@ def test_tie_at_a_split_plane_keeps_the_entry():
             assert np.all(np.abs(u - 0.5) <= 1e-12)
         else:   # leaves below the FP32 node error: neighbouring leaves within it
             assert np.all(np.abs(t - t_star) <= 2 * (2 + 2 * depth) * 2.0 ** -24 * 3)
+
+
+def test_tie_at_a_nearly_parallel_split_plane_reaches_the_mirror_leaf():
+    """An exact cusp is symmetric about the plane through its cusp normal to
+    the chord, which is also the root's split plane. A ray running within
+    2e-9 rad of that plane and 1e-10 from it meets the two mirror-image
+    branches at the same t; where the FP32 crossing of the plane falls is
+    undetermined (its error bound spans both sides of the ray), so the
+    mirror-image leaf at u' = 1 - u is an outcome of the method, at the same
+    t."""
+    L, h, r = 0.6, 0.2, 0.01
+    cusp = np.array([[0, 0, 0, r], [L, h, 0, r], [0, h, 0, r], [L, 0, 0, r]], float).reshape(16)
+    for eps, tilt in ((1e-10, 1e-9), (-1e-10, 1e-9), (1e-10, -1e-9), (3e-10, 2e-9)):
+        Dv = np.array([tilt, math.sin(0.7), math.cos(0.7)])
+        Dv /= np.linalg.norm(Dv)
+        O = np.array([L / 2 + eps, 0.75 * h + 0.5 * r, 0.0]) - 2.0 * Dv
+        ray = np.concatenate([O, Dv, [100.0]])
+        for depth in (6, 12, 22):
+            t, u, hit = oracle.tie_outcomes(ray, cusp, depth, scale=1.0)
+            assert hit[0] and abs(u[0] - 0.5) > 0.05, (eps, tilt, depth)
+            mirror = hit.astype(bool) & (np.abs(u - (1 - u[0])) <= 2.0 ** -depth + 1e-9) & \
+                (np.abs(t - t[0]) <= 1e-9 * t[0])
+            assert mirror.any(), (eps, tilt, depth)
+
+
+def test_visibility_ties_never_decide_clear_cases():
+    """The outcome with every visibility tie decided visible only changes
+    comparisons within their error bounds: a ray that misses with the radius
+    1 % larger has only misses among its outcomes, and a ray that hits with
+    the radius 1 % smaller only hits (the outcome with every visibility tie
+    decided visible, second in the list, within 1e-5 of the unflipped
+    entry)."""
+    w = W.straight_and_curved(600, seed=404)
+    _, _, h_lo = oracle.intersect_depth(w.rays, w.fibers, 9, radius_scale=0.99)
+    _, _, h_hi = oracle.intersect_depth(w.rays, w.fibers, 9, radius_scale=1.01)
+    checked = 0
+    for i in range(600):
+        if h_lo[i] != h_hi[i]:
+            continue
+        t, u, hit = oracle.tie_outcomes(w.rays[:, i], w.fibers[:, i], 9, scale=1.0)
+        checked += 1
+        assert np.all(hit.astype(bool) == bool(h_hi[i])), i
+        if h_hi[i]:
+            assert abs(t[1] - t[0]) <= 1e-5 * t[0], i
+    assert checked >= 400
 
 
 def _fp32_descent_error(w, n, levels=23, seed=1):
