@@ -17,17 +17,18 @@
  * synchronised.
  *
  * Every call (and every batch) runs one persistent kernel: each 64-lane wave
- * takes an even share of the pairs and loads them into its free lanes (load,
+ * takes an even share of the pairs, prepares them in rounds of up to 64 (load,
  * FP64 move into the ray frame, root test; pairs decided at the root are
- * written out at once), keeping each busy lane's root in a slot of its own
- * (64 bytes) for the subdivision search. The library allocates nothing while
- * a call runs: the root slots (4 KiB per resident wave, about 24 MiB on
- * MI355X) and, for calls that gather fibers through an index, a copy of the
- * fibers as 64-byte records live in a workspace the caller sizes with
- * fiber_pairs_workspace_bytes (single calls), fiber_batched_workspace_bytes
- * (batches) or inside a plan. Device set-up (unit counts, occupancy, pinned
- * staging of batched scene tables) happens once per device, at
- * fi_init_device or at the first call on that device.
+ * written out at once) into a queue in LDS, from which each lane takes its
+ * next pair as soon as it is free; a lane keeps its pair's root in registers
+ * for the subdivision search. The library allocates nothing while a call
+ * runs. The only device memory a call needs beyond its inputs and outputs is
+ * a copy of the fibers as 64-byte records for calls that gather fibers
+ * through an index, in a workspace the caller sizes with
+ * fiber_pairs_workspace_bytes; a batch needs its scene table, in a workspace
+ * sized by fiber_batched_workspace_bytes, or inside a plan. Device set-up
+ * (unit counts, occupancy, pinned staging of batched scene tables) happens
+ * once per device, at fi_init_device or at the first call on that device.
  *
  * Layouts (structure of arrays, 32-bit floats, row-major):
  *   rays   : 7 rows of ray_stride floats  -- ox, oy, oz, dx, dy, dz, tmax.
@@ -55,7 +56,8 @@ extern "C" {
 #define FI_ERR_NULL      (-1)   /* a required pointer is NULL                         */
 #define FI_ERR_RANGE     (-2)   /* a count, stride or depth is out of range           */
 #define FI_ERR_HIP       (-3)   /* the HIP runtime reported an error at launch        */
-#define FI_ERR_WORKSPACE (-4)   /* workspace pointer missing or too small             */
+#define FI_ERR_WORKSPACE (-4)   /* workspace pointer missing, misaligned or too small */
+#define FI_ERR_SCRATCH   (-5)   /* more scratch than the no-allocation entry point holds */
 
 /* Flags. */
 /* FI_FP64_REFINE: for pairs of depth > 16, run the traversal with every
@@ -91,13 +93,10 @@ int fi_init_device(void);
 
 /* Bytes of device workspace one fiber_intersect_pairs or
  * fiber_intersect_counts call of n_pairs pairs over a table of n_fibers
- * fibers needs on the current device (0 for negative counts or when the
- * device cannot be queried): the root slots (4 KiB per resident wave; fixed
- * per device) plus, when gathered is non-zero (pair_fiber given) and
- * n_pairs >= n_fibers, n_fibers 64-byte fiber records (tables up to 1 GiB).
- * A workspace of at least the slot size but without room for the records
- * is accepted: the gather then reads the fiber rows in place (same
- * results). flags is reserved (the size does not depend on it). */
+ * fibers can use: when gathered is non-zero (pair_fiber given) and
+ * n_pairs >= n_fibers, the fibers' 64-byte records (tables up to 1 GiB);
+ * otherwise 0. A call with a smaller workspace (or none) reads the fiber rows
+ * in place, with the same results. flags is reserved. */
 size_t fiber_pairs_workspace_bytes(int64_t n_pairs, int64_t n_fibers, int32_t gathered, uint32_t flags);
 
 /*
@@ -127,10 +126,11 @@ size_t fiber_pairs_workspace_bytes(int64_t n_pairs, int64_t n_fibers, int32_t ga
  *   t64_out, u64_out               n_pairs doubles each; required with
  *                                  FI_FP64_REFINE, ignored (may be NULL) without.
  *   workspace, workspace_bytes     caller-owned device memory, 256-byte aligned,
- *                                  of at least fiber_pairs_workspace_bytes(...)
- *                                  bytes (see there). It must not be used by
- *                                  another call still in flight; its contents on
- *                                  entry do not matter.
+ *                                  for the fiber records of a gathered call
+ *                                  (size: fiber_pairs_workspace_bytes), or NULL
+ *                                  and 0. It must not be used by another call
+ *                                  still in flight; its contents on entry do not
+ *                                  matter.
  *   stream                         hipStream_t or NULL.
  *
  * FI_FP64_REFINE: the method's leaf cylinders converge to the solid swept by
@@ -155,9 +155,8 @@ size_t fiber_pairs_workspace_bytes(int64_t n_pairs, int64_t n_fibers, int32_t ga
  * counts, strides below the counts, a depth outside [0, 23], unknown flags,
  * an identity pairing longer than its ray or fiber table, or
  * n_pairs >= 2^31 - 64;
- * FI_ERR_WORKSPACE when the workspace is NULL, not 256-byte aligned or
- * smaller than the root slots; FI_ERR_HIP when the launch fails or the
- * device set-up fails. Nothing is enqueued on an argument error. The call
+ * FI_ERR_WORKSPACE when the workspace is not 256-byte aligned; FI_ERR_HIP
+ * when the launch fails or the device set-up fails. Nothing is enqueued on an argument error. The call
  * allocates, frees and waits for nothing.
  */
 int fiber_intersect_pairs(const float *rays, int64_t ray_stride, int64_t n_rays,
@@ -175,19 +174,18 @@ int fiber_intersect_pairs(const float *rays, int64_t ray_stride, int64_t n_rays,
  * capture, tight serving loops, harnesses that forbid allocation).
  *
  * Operation and arguments: those of fiber_intersect_pairs, minus the
- * workspace; the results are bit for bit the same. The root slots live in a
- * fixed array inside the library's code object (24 MiB, one copy per device,
- * held until the process ends; its address is taken once per device at the
- * device's set-up). It holds the slots of 6144 waves, the resident waves of
- * either kernel variant on MI355X; a device that could keep more waves
- * resident gets a grid of that many (results do not depend on the grid). No
- * argument sizes the array, so no input is refused for it. Fibers gathered
- * through pair_fiber are read in place (no record copy).
+ * workspace; the results are bit for bit the same. The fiber records of a
+ * gathered call (pair_fiber given, n_pairs >= n_fibers) go to a fixed array
+ * inside the library's code object (32 MiB, one copy per device, held until
+ * the process ends; its address is taken once per device at the device's
+ * set-up), which holds the records of up to 524,288 fibers: such a call over
+ * a larger fiber table is refused with FI_ERR_SCRATCH before anything is
+ * enqueued. Other calls use no scratch.
  *
  * Every call on a device shares that device's array, which keeps the last
- * call's contents (every slot is written before it is read, so nothing needs
- * clearing): calls that overlap on one device -- on two streams, or from two
- * host threads without ordering -- race and give undefined results.
+ * call's contents (a call writes the records it reads first, so nothing needs
+ * clearing): gathered calls that overlap on one device -- on two streams, or
+ * from two host threads without ordering -- race and give undefined results.
  *
  * Allocation: none on the call path (no hipMalloc, hipFree or allocating
  * library routine). The device's set-up (fi_init_device, or the first call of
@@ -195,7 +193,8 @@ int fiber_intersect_pairs(const float *rays, int64_t ray_stride, int64_t n_rays,
  * calls once; callers that must not allocate at all call fi_init_device
  * beforehand.
  *
- * Errors: as fiber_intersect_pairs, without FI_ERR_WORKSPACE.
+ * Errors: as fiber_intersect_pairs, without FI_ERR_WORKSPACE; FI_ERR_SCRATCH
+ * as above.
  */
 int fiber_intersect_pairs_noalloc(const float *rays, int64_t ray_stride, int64_t n_rays,
                                   const float *fibers, int64_t fiber_stride, int64_t n_fibers,
@@ -248,10 +247,10 @@ typedef struct fi_scene {
 } fi_scene;
 
 /* Launch tuning of the batched kernel (not part of the method):
- *   refill          refill a wave's finished lanes once at least this many
- *                   (1..64) are free (defaults: 48, and 8 with FI_FP64_REFINE);
+ *   refill          free lanes take queued pairs once at least this many
+ *                   (1..64) are free (default 1);
  *   waves_per_simd  cap on resident waves per SIMD (0..16, 0 = as many as fit,
- *                   which is 6 for the batched kernel).
+ *                   which is 4 for the batched kernel).
  * Results never depend on the tuning. */
 typedef struct fi_tuning {
     int32_t refill;
@@ -259,10 +258,9 @@ typedef struct fi_tuning {
 } fi_tuning;
 
 /* Bytes of device workspace fiber_intersect_batched needs for n_scenes
- * problems of total_pairs pairs in all, on the current device (0 for negative
- * arguments or when the device cannot be queried): the scene table and the
- * root slots of the resident waves (4 KiB each, about 24 MiB on MI355X); it
- * does not grow with total_pairs. */
+ * problems of total_pairs pairs in all (0 for negative arguments): the scene
+ * table and the pair offsets (about 140 bytes per scene); it does not grow
+ * with total_pairs. */
 size_t fiber_batched_workspace_bytes(int32_t n_scenes, int64_t total_pairs);
 
 /*
@@ -296,8 +294,8 @@ int fiber_intersect_batched(const fi_scene *scenes, int32_t n_scenes, const fi_t
                             uint32_t flags, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
- * Plans: the scene table is uploaded once into device memory the plan owns
- * (with its root slots), and the launch (one kernel) is captured into a HIP
+ * Plans: the scene table is uploaded once into device memory the plan owns,
+ * and the launch (one kernel) is captured into a HIP
  * graph that fiber_batch_plan_launch replays on any stream. Scenes, tuning
  * and flags mean what they mean for fiber_intersect_batched. Creating and
  * destroying a plan allocates and frees device memory; launching does not.

@@ -127,21 +127,25 @@ def _stream(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
-def pairs_workspace(n: int, n_fibers: int, gathered: bool, device) -> torch.Tensor:
-    """Device workspace of one fiber_intersect_pairs call (root slots, and
-    fiber records for a gathered call), sized by the library."""
-    with torch.cuda.device(device):
-        nbytes = lib().fiber_pairs_workspace_bytes(int(n), int(n_fibers), int(bool(gathered)), 0)
+def pairs_workspace(n: int, n_fibers: int, gathered: bool, device) -> Optional[torch.Tensor]:
+    """Device workspace of one fiber_intersect_pairs call (the fiber records
+    of a gathered call), sized by the library; None when the call needs
+    none."""
+    nbytes = lib().fiber_pairs_workspace_bytes(int(n), int(n_fibers), int(bool(gathered)), 0)
     if nbytes == 0:
-        raise FiberHitError("fiber_pairs_workspace_bytes failed (no usable device)")
+        return None
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
-def _keep_for(ws: torch.Tensor, stream):
+def _keep_for(ws: Optional[torch.Tensor], stream):
     """A workspace freed after a call on another stream than the current one
     must not be reused by the allocator before that stream passes the call."""
-    if stream is not None and stream != torch.cuda.current_stream(ws.device):
+    if ws is not None and stream is not None and stream != torch.cuda.current_stream(ws.device):
         ws.record_stream(stream)
+
+
+def _ws_args(ws: Optional[torch.Tensor]):
+    return (None, 0) if ws is None else (C.c_void_p(ws.data_ptr()), ws.numel())
 
 
 def intersect_pairs(rays: torch.Tensor, fibers: torch.Tensor, depth: int = 9,
@@ -158,7 +162,7 @@ def intersect_pairs(rays: torch.Tensor, fibers: torch.Tensor, depth: int = 9,
     tests / splits / backtracks / leaf level when ``counts`` is set, or the
     float64 (t64, u64) of the FP64 surface refinement when ``refine`` is set.
     ``workspace`` (uint8 device tensor, see ``pairs_workspace``) is allocated
-    per call when not given."""
+    per call when not given and the call gathers fibers."""
     rs = _table(rays, 7, "rays")
     fs = _table(fibers, 16, "fibers")
     pr = _index(pair_ray, torch.int32, "pair_ray")
@@ -174,7 +178,7 @@ def intersect_pairs(rays: torch.Tensor, fibers: torch.Tensor, depth: int = 9,
         _keep_for(workspace, stream)
     elif workspace.dtype != torch.uint8 or not workspace.is_cuda or not workspace.is_contiguous():
         raise ValueError("workspace must be a contiguous uint8 device tensor")
-    ws = (C.c_void_p(workspace.data_ptr()), workspace.numel())
+    ws = _ws_args(workspace)
     cn = torch.empty((n, 4), dtype=torch.int32, device=dev) if counts else None
     flags = FI_FP64_REFINE if refine else 0
     args = [_ptr(rays), rs, rays.shape[1], _ptr(fibers), fs, fibers.shape[1],
@@ -253,7 +257,7 @@ class PreparedPairs:
         self._args = (_ptr(rays), rs, rays.shape[1], _ptr(fibers), fs, fibers.shape[1],
                       _ptr(pr), _ptr(pf), _ptr(pd), int(depth), n, 0,
                       _ptr(self.t), _ptr(self.u), _ptr(self.hit), None, None,
-                      C.c_void_p(self.workspace.data_ptr()), self.workspace.numel())
+                      *_ws_args(self.workspace))
 
     def launch(self, stream=None):
         _check(self._fn(*self._args, _stream(stream)))
@@ -368,7 +372,7 @@ def _tuning(t):
 
 def workspace_for(problems, device=None):
     """Device workspace for a batched call over ``problems`` (a list of
-    Problem): scene table and root slots (sized for the current device)."""
+    Problem): the scene table and pair offsets."""
     total = sum(int(p.n) for p in problems)
     nbytes = _batched_lib().fiber_batched_workspace_bytes(len(problems), total)
     if device is None:

@@ -40,23 +40,29 @@
 namespace {
 
 constexpr int kWave = 64;                     // gfx950 wavefront
+#ifndef FIBERHIT_QUEUE
+#define FIBERHIT_QUEUE 64                     // build knob: queue entries per wave
+#endif
+constexpr int kQueue = FIBERHIT_QUEUE;        // prepared roots per wave (LDS queue)
+
+// Entry x of the queue ring, for 0 <= x < 3 kQueue.
+__device__ __forceinline__ int qslot(int x)
+{
+    x = x >= kQueue ? x - kQueue : x;
+    return x >= kQueue ? x - kQueue : x;
+}
+constexpr int kQWords = 21;                   // root node (16), lo, hi, tmax, pair, scene * 32 + depth
 constexpr uint32_t kRootSize = 1u << 23;      // parametric domain [0, 1) in units of 2^-23
 constexpr int kMaxTrips = 1 << 16;            // hang guard; real pairs need < 200 trips
 #ifndef FIBERHIT_PARENT_CACHE
 #define FIBERHIT_PARENT_CACHE 1
 #endif
 constexpr bool kParentCache = FIBERHIT_PARENT_CACHE != 0;   // cache the latest both-hit parent in LDS
-#ifndef FIBERHIT_FUSED_ROUNDS
-#define FIBERHIT_FUSED_ROUNDS 1                    // refill batches per trip of the one-kernel path
-#endif
 #ifndef FIBERHIT_FUSED_REFILL
-#define FIBERHIT_FUSED_REFILL 48                   // free lanes that trigger a one-kernel refill
+#define FIBERHIT_FUSED_REFILL 1                    // free lanes that take queued roots (single calls)
 #endif
 #ifndef FIBERHIT_REFINE_REFILL
-#define FIBERHIT_REFINE_REFILL 8                   // the same for refined calls (parked lanes wait for the others)
-#endif
-#ifndef FIBERHIT_FUSED_WAVES
-#define FIBERHIT_FUSED_WAVES 6                     // register budget of the one-kernel path (waves per SIMD)
+#define FIBERHIT_REFINE_REFILL 1                   // the same for refined calls
 #endif
 
 struct V4 { float x, y, z, w; };
@@ -617,6 +623,7 @@ __device__ __forceinline__ void leaf_candidates(const Curve64 &c, double ua, dou
 
 struct Lane {
     Node c;                       // current node, {p, d, t0, t1} in the ray frame
+    Node root;                    // the pair's root (replays of the split rules start here)
     float lo, hi;                 // cropped t interval of the current node
     float tmax, t;                // ray tmax; hit distance once found
     uint32_t bits, start, size;   // Section 3.3: pending-sibling bits, integer interval
@@ -824,15 +831,12 @@ __device__ __forceinline__ void descend_state(Lane &L, const Split &sp)
     L.splits++;
 }
 
-// Where a backtrack that misses the parent cache re-reads its pair's root.
-struct SlotRoot {
-    const float *slot;                        // this lane's root: 16 floats, one wave apart
-    __device__ __forceinline__ void get(const Lane &, Node &n) const
-    {
-        float *f = &n.p.x;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) f[k] = slot[k * kWave];
-    }
+// Where a backtrack that misses the parent cache finds its pair's root: in
+// the lane's registers (16 more VGPRs per lane, which the occupancy that
+// the LDS queue allows can hold), so a replay starts without a memory
+// access.
+struct RegRoot {
+    __device__ __forceinline__ void get(const Lane &L, Node &n) const { n = L.root; }
 };
 
 template <int MODE, class Root>
@@ -879,17 +883,7 @@ __device__ __forceinline__ int trip(Lane &L, const Root &root, float *col)
         if (kParentCache && L.cached == L.size) {
             lds_get(col, L.c);
         } else {
-            // keep the root's global loads inside this branch: hoisted above it
-            // they would delay every cached rebuild by a memory round trip
-            asm volatile("" ::: "memory");
             root.get(L, L.c);
-            // Wait for the root here: 0x0F70 is vmcnt(0) with expcnt and
-            // lgkmcnt at their maxima (no wait). Left pending, as it is when
-            // no level is replayed (a sibling of the root's child), its loads
-            // made the cached lanes' LDS reads into the same registers wait
-            // for them, and the end of the trip wait for every outstanding
-            // memory operation, finish stores included.
-            __builtin_amdgcn_s_waitcnt(0x0F70);
             for (uint32_t b = kRootSize >> 1; b > L.size; b >>= 1) {
                 V4 rdp, rtc;
                 split_terms(L.c, rdp, rtc);
@@ -990,19 +984,21 @@ __device__ __forceinline__ int find_scene(const int64_t *offsets, int n_scenes, 
 }
 
 // Load pair i and move it into the ray frame: the root node in the
-// {p, d, t0, t1} form (Section 3.1). False when the pair is a definite miss
-// (bad index, depth, direction or tmax).
+// {p, d, t0, t1} form (Section 3.1), written to q[k * kQueue] (k = 0..15: p,
+// d, t0, t1, each x, y, z, w) as each part is computed, so that the FP64
+// frame and the finished root never take registers at the same time. False
+// when the pair is a definite miss (bad index, depth, direction, tmax or a
+// non-finite root).
 // The projection runs once per pair in FP64 (full rate on this chip): the
 // differences of the float32 control points and of the origin are exact in
 // double, so p is the rounded frame position of p0 and d, t0, t1 are the
 // rounded frame images of p3-p0, p1-p0, p3-p2 -- each component accurate to
 // its own float32 ulp, including the tiny across-ray or along-ray parts of
-// nearly parallel or nearly perpendicular tangents. It goes one control point
-// at a time so that it fits beside the busy lanes' state in the refill.
+// nearly parallel or nearly perpendicular tangents.
 // `aos`, when given, holds the fibers as 16 consecutive floats each (see
 // k_fibers_aos): a gathered fiber is then one or two cache lines instead of
 // one line per coordinate row.
-__device__ __forceinline__ bool load_pair(const Args &a, int64_t i, Node &root, float &tmax, uint32_t &depth,
+__device__ __forceinline__ bool load_pair(const Args &a, int64_t i, float *q, float &tmax, uint32_t &depth,
                                           const float *aos)
 {
     const int64_t ri = a.pair_ray ? (int64_t)a.pair_ray[i] : i;
@@ -1022,53 +1018,71 @@ __device__ __forceinline__ bool load_pair(const Args &a, int64_t i, Node &root, 
     const double w[3] = {dx * il, dy * il, dz * il};
     double u[3], v[3];
     make_onb(w[0], w[1], w[2], u, v);
-    auto proj = [&](double ex, double ey, double ez, double ew, V4 &q) {
-        q.x = (float)fma(ex, u[0], fma(ey, u[1], ez * u[2]));
-        q.y = (float)fma(ex, v[0], fma(ey, v[1], ez * v[2]));
-        q.z = (float)fma(ex, w[0], fma(ey, w[1], ez * w[2]));
-        q.w = (float)ew;
+    bool finite = true;
+    auto proj = [&](double ex, double ey, double ez, double ew, int k, bool check) {
+        const float x = (float)fma(ex, u[0], fma(ey, u[1], ez * u[2]));
+        const float y = (float)fma(ex, v[0], fma(ey, v[1], ez * v[2]));
+        const float z = (float)fma(ex, w[0], fma(ey, w[1], ez * w[2]));
+        if (check) finite = finite && isfinite(x) && isfinite(y) && isfinite(z);
+        q[(4 * k) * kQueue] = x;
+        q[(4 * k + 1) * kQueue] = y;
+        q[(4 * k + 2) * kQueue] = z;
+        q[(4 * k + 3) * kQueue] = (float)ew;
     };
     const float p0x = F[0], p0y = F[fs], p0z = F[2 * fs], p0w = F[3 * fs];
-    proj((double)p0x - (double)R[0], (double)p0y - (double)R[rs], (double)p0z - (double)R[2 * rs], (double)p0w,
-         root.p);
+    proj((double)p0x - (double)R[0], (double)p0y - (double)R[rs], (double)p0z - (double)R[2 * rs], (double)p0w, 0,
+         true);
     const float p3x = F[12 * fs], p3y = F[13 * fs], p3z = F[14 * fs], p3w = F[15 * fs];
-    proj((double)p3x - p0x, (double)p3y - p0y, (double)p3z - p0z, (double)p3w - p0w, root.d);
-    proj((double)F[4 * fs] - p0x, (double)F[5 * fs] - p0y, (double)F[6 * fs] - p0z, (double)F[7 * fs] - p0w,
-         root.t0);
-    proj((double)p3x - F[8 * fs], (double)p3y - F[9 * fs], (double)p3z - F[10 * fs], (double)p3w - F[11 * fs],
-         root.t1);
-    return isfinite(root.p.x) && isfinite(root.p.y) && isfinite(root.p.z) &&
-           isfinite(root.d.x) && isfinite(root.d.y) && isfinite(root.d.z);
+    proj((double)p3x - p0x, (double)p3y - p0y, (double)p3z - p0z, (double)p3w - p0w, 1, true);
+    proj((double)F[4 * fs] - p0x, (double)F[5 * fs] - p0y, (double)F[6 * fs] - p0z, (double)F[7 * fs] - p0w, 2,
+         false);
+    proj((double)p3x - F[8 * fs], (double)p3y - F[9 * fs], (double)p3z - F[10 * fs], (double)p3w - F[11 * fs], 3,
+         false);
+    return finite;
 }
 
 // The kernel of every call: each persistent 64-lane wave takes an even share
-// of the call's pairs (of the whole scene table for a batch) and loads them
-// straight into its free lanes once `refill` lanes are free -- pair fetch,
-// FP64 move into the ray frame, root test and the root's first split in the
-// refill -- so that lanes of uneven trip counts keep the SIMD busy instead of
-// idling until the slowest lane of a fixed batch finishes. A lane that
-// survives its root test keeps the root in its own slot (16 floats, a wave's
-// lanes side by side) for the backtracks that miss the parent cache; pairs
-// decided at the root are written out during the refill, which takes up to
-// kFusedRounds batches of pairs per trip. The attribute sets the register
-// budget: the plain variant fits 6 waves per SIMD, counting 5, the refining
-// variant (FP64 search called as a function) 4.
-constexpr int kFusedRounds = FIBERHIT_FUSED_ROUNDS;
+// of the call's pairs (of the whole scene table for a batch), contiguous so
+// that its loads are coalesced. Pairs reach the lanes through a queue of
+// prepared roots in LDS:
+//  * a setup round, run by the whole wave when the queue cannot serve its
+//    free lanes, loads up to 64 pairs (one per lane), moves them into the
+//    ray frame in FP64 and tests their roots; pairs decided there (a miss, a
+//    root that is the leaf, a bad pair) are written out at once, the others
+//    are appended to the queue (root node, its cap interval, tmax, pair);
+//  * at every trip, each free lane takes the next queued root (copying it to
+//    its root slot for the backtracks that miss the parent cache), and its
+//    first trip tests the root and takes the first split.
+// Setup rounds thus run with every lane busy and pay their load latency
+// once per up to 64 pairs, while a lane that finishes a pair waits no more
+// than one trip for the next (a round of loads, the FP64 frame and the root
+// test costs about three trips' time). The attribute sets the register
+// budget; the LDS (queue and parent cache, 9.5 KiB) allows 16 waves per CU.
 
+// The wave's contiguous range of the call's pairs (an even share).
+__device__ __forceinline__ void wave_range(int64_t w, int64_t waves, int64_t count, int64_t &begin, int64_t &end)
+{
+    const int64_t share = (count + waves - 1) / waves;
+    begin = w * share < count ? w * share : count;
+    end = (w + 1) * share < count ? (w + 1) * share : count;
+}
+
+#ifndef FIBERHIT_WAVES
+#define FIBERHIT_WAVES 4                      // build knob: register budget (waves per SIMD)
+#endif
 template <int MODE, bool BATCHED>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MODE == kPlain ? FIBERHIT_FUSED_WAVES : MODE == kCount ? 5 : 4, 8)))
-void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, int64_t count, float *slots,
-             int refill, const float *aos)
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MODE == kConservative ? 4 : FIBERHIT_WAVES, 8)))
+void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, int64_t count, int refill,
+             const float *aos)
 {
     __shared__ float s_cache[16 * kWave];
+    __shared__ float s_queue[kQWords * kQueue];
     const int lane = (int)threadIdx.x;
     float *col = s_cache + lane;
     const int64_t w = blockIdx.x, waves = gridDim.x;
-    const int64_t share = (count + waves - 1) / waves;
-    int64_t next = w * share < count ? w * share : count;               // wave-uniform range
-    const int64_t end = (w + 1) * share < count ? (w + 1) * share : count;
-    float *slot = slots + (size_t)w * 16 * kWave + lane;
-    const SlotRoot root{slot};
+    int64_t next, end;                                                  // wave-uniform range
+    wave_range(w, waves, count, next, end);
+    const RegRoot root{};
     // batched: pairs are numbered across the scene table; the wave's share
     // is contiguous, so the scene of its next pair only moves forward
     int scene0 = 0;
@@ -1077,79 +1091,82 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
         scene0 = __builtin_amdgcn_readfirstlane(next < count ? find_scene(offsets, n_scenes, next) : 0);
         cur = outs_of(scenes[scene0]);
     }
+    int q_head = 0, q_count = 0;         // the queue: entries q_head .. q_head + q_count - 1 (mod kQueue)
     Lane L = {};
     L.lo = INFINITY;                                                   // an empty interval: no work
     L.hi = -INFINITY;
     bool active = false;
     for (;;) {
-        for (int round = 0; round < kFusedRounds; ++round) {
-            const uint64_t free_mask = __ballot(!active);
-            const int n_free = __popcll(free_mask);
-            if (next >= end || !(n_free >= refill || n_free == kWave)) break;
-            const int take = end - next < n_free ? (int)(end - next) : n_free;
-            if (!active) {
-                const int rank = (int)lanes_below(free_mask);
-                if (rank < take) {
-                    // the new pair goes straight into the (free) lane's state
-                    int64_t idx = next + rank;
-                    Args a = a0;
-                    if constexpr (BATCHED) {
-                        int sc = scene0;
-                        while (sc + 1 < n_scenes && offsets[sc + 1] <= idx) ++sc;
-                        idx -= offsets[sc];
-                        a = scenes[sc];
-                        L.scene = sc;
-                    }
-                    uint32_t depth = 0;
-                    if (!load_pair(a, idx, L.c, L.tmax, depth, aos)) {
-                        finish_invalid<MODE>(a, idx);
-                        L.lo = INFINITY;
-                        L.hi = -INFINITY;
-                        L.bits = 0;
-                    } else {
-                        cap_interval(L.c, L.tmax, L.lo, L.hi);
-                        float te, tx, lu, hu;
-                        const float slack = MODE == kConservative && depth > kRefineAbove ? root_slack(L.c) : -1.0f;
-                        const bool vis = node_visible<MODE>(L.c, L.lo, L.hi, slack, te, tx, lu, hu);
-                        L.slack = slack;
-                        L.start = 0;
-                        L.size = kRootSize;
-                        if (vis && depth > 0) {
-                            const float *f = &L.c.p.x;
+        const uint64_t free_mask = __ballot(!active);
+        const int n_free = __popcll(free_mask);
+        if (next < end && q_count < n_free) {
+            // setup round: lane k prepares pair next + k
+            const int take = end - next < kQueue - q_count ? (int)(end - next) : kQueue - q_count;
+            bool queued = false;
+            Node r = {};
+            float rlo = 0.0f, rhi = 0.0f, rtmax = 0.0f;
+            uint32_t depth = 0;
+            int64_t idx = next + lane;
+            int sc = scene0;
+            // each preparing lane stages its root in the queue entry after the
+            // current tail plus its lane number; survivors then move to
+            // consecutive entries (every lane has read its own entry back
+            // before any lane writes)
+            float *stage = s_queue + qslot(q_head + q_count + lane);
+            if (lane < take) {
+                Args a = a0;
+                if constexpr (BATCHED) {
+                    while (sc + 1 < n_scenes && offsets[sc + 1] <= idx) ++sc;
+                    idx -= offsets[sc];
+                    a = scenes[sc];
+                }
+                const bool ok = load_pair(a, idx, stage, rtmax, depth, aos);
+                asm volatile("" ::: "memory");
+                float *f = &r.p.x;
 #pragma unroll
-                            for (int k = 0; k < 16; ++k) slot[k * kWave] = f[k];
-                            L.min_size = kRootSize >> depth;
-                            L.pair = (int32_t)idx;
-                            L.bits = 0;
-                            L.cached = 0;
-                            L.waiting = 0;
-                            L.trips = 1;                 // the root test above
-                            L.splits = L.backtracks = 0;
-                            // the root is visible and not a leaf: its first
-                            // split is taken here, as the trip would take it
-                            // (a trip would only repeat the root test)
-                            Split sp;
-                            split_plane<MODE>(L, te, tx, sp);
-                            if (kParentCache && sp.both) lds_put(col, L.c);
-                            take_child(L.c, sp.dp, sp.tc, sp.near_right);
-                            descend_state(L, sp);
-                            active = true;
-                        } else {
-                            // decided at the root: a miss, or the root is the leaf
-                            L.t = fmaxf(te, lu);
-                            L.u = leaf_u(L);
-                            L.level = 0;
-                            L.trips = 1;
-                            L.splits = 0;
-                            L.backtracks = 0;
-                            finish<MODE>(outs_of(a), idx, L, vis);
-                            L.lo = INFINITY;
-                            L.hi = -INFINITY;
-                            L.bits = 0;
-                        }
+                for (int k = 0; k < 16; ++k) f[k] = stage[k * kQueue];
+                if (!ok) {
+                    finish_invalid<MODE>(a, idx);
+                } else {
+                    cap_interval(r, rtmax, rlo, rhi);
+                    float te, tx, lu, hu;
+                    const float slack = MODE == kConservative && depth > kRefineAbove ? root_slack(r) : -1.0f;
+                    const bool vis = node_visible<MODE>(r, rlo, rhi, slack, te, tx, lu, hu);
+                    if (vis && depth > 0) {
+                        queued = true;
+                    } else {
+                        // decided at the root: a miss, or the root is the leaf
+                        Lane D = {};
+                        D.c = r;
+                        D.tmax = rtmax;
+                        D.t = fmaxf(te, lu);
+                        D.start = 0;
+                        D.size = kRootSize;
+                        D.u = leaf_u(D);
+                        D.level = 0;
+                        D.trips = 1;
+                        D.slack = slack;
+                        finish<MODE>(outs_of(a), idx, D, vis);
                     }
                 }
             }
+            asm volatile("" ::: "memory");
+            const uint64_t qm = __ballot(queued);
+            if (queued) {
+                const int e = qslot(q_head + q_count + (int)lanes_below(qm));
+                float *q = s_queue + e;
+                if (q != stage) {
+                    const float *f = &r.p.x;
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) q[k * kQueue] = f[k];
+                }
+                q[16 * kQueue] = rlo;
+                q[17 * kQueue] = rhi;
+                q[18 * kQueue] = rtmax;
+                q[19 * kQueue] = __int_as_float((int)idx);
+                q[20 * kQueue] = __int_as_float((sc << 5) | (int)depth);
+            }
+            q_count += __popcll(qm);
             next += take;
             if constexpr (BATCHED) {
                 const int before = scene0;
@@ -1158,13 +1175,46 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
                 if (scene0 != before) cur = outs_of(scenes[scene0]);
             }
         }
-        // No edge back to the refill that bypasses the trip: a wave whose
+        if (q_count > 0 && n_free >= (refill < q_count ? refill : q_count)) {
+            // free lanes take the next queued roots
+            const int k = n_free < q_count ? n_free : q_count;
+            if (!active) {
+                const int rank = (int)lanes_below(free_mask);
+                if (rank < k) {
+                    const float *q = s_queue + qslot(q_head + rank);
+                    float *f = &L.c.p.x;
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) f[j] = q[j * kQueue];
+                    L.lo = q[16 * kQueue];
+                    L.hi = q[17 * kQueue];
+                    L.tmax = q[18 * kQueue];
+                    L.pair = __float_as_int(q[19 * kQueue]);
+                    const int ds = __float_as_int(q[20 * kQueue]);
+                    const uint32_t depth = (uint32_t)ds & 31u;
+                    L.scene = ds >> 5;
+                    L.root = L.c;
+                    L.min_size = kRootSize >> depth;
+                    L.slack = MODE == kConservative && depth > kRefineAbove ? root_slack(L.c) : -1.0f;
+                    L.start = 0;
+                    L.size = kRootSize;
+                    L.bits = 0;
+                    L.cached = 0;
+                    L.waiting = 0;
+                    L.trips = 0;
+                    L.splits = L.backtracks = 0;
+                    active = true;
+                }
+            }
+            q_head = qslot(q_head + k);
+            q_count -= k;
+        }
+        // No edge back to the setup that bypasses the trip: a wave whose
         // fresh pairs were all decided at the root runs one idle trip instead.
         // With a single path around the loop the lane state keeps one set of
         // registers; a bypass edge had made the compiler copy the node and
         // the traversal state at every trip (about 45 moves, measured 12-14 %
         // of the call).
-        if (__ballot(active) == 0 && next >= end) break;
+        if (__ballot(active) == 0 && next >= end && q_count == 0) break;
         const int st = trip<MODE>(L, root, col);
         if (active && st != kGoOn && !(MODE == kConservative && L.waiting)) {
             if constexpr (BATCHED) {
@@ -1250,7 +1300,7 @@ int check_common(const float *rays, int64_t ray_stride, int64_t n_rays,
 // Kernel variants and per-device state
 // ---------------------------------------------------------------------------
 
-using FusedFn = void (*)(Args, const Args *, const int64_t *, int, int64_t, float *, int, const float *);
+using FusedFn = void (*)(Args, const Args *, const int64_t *, int, int64_t, int, const float *);
 // [0] plain, [1] counting, [2] conservative (single calls), [3] plain and
 // [4] conservative over a scene table
 constexpr int kVariants = 5;
@@ -1260,21 +1310,19 @@ constexpr int kBatchedVariant = 3;
 constexpr int kBatchedRefineVariant = 4;
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-constexpr size_t kSlotBytesPerWave = 16 * kWave * sizeof(float);   // one root slot per lane
 constexpr size_t kMaxRecordBytes = (size_t)1 << 30;                 // fiber records, largest table
 
 constexpr int kMaxDevices = 64;
 constexpr int kStageSlots = 4;                 // pinned staging for batched scene tables
 constexpr size_t kStageBytes = 1u << 20;
 
-// Root slots of fiber_intersect_pairs_noalloc, for callers that cannot
-// allocate: a fixed array in the code object, one copy per device, holding
-// slots for kScratchWaves waves (the resident waves of the plain and the
-// refining single-call grids on a 256-CU MI355X; 24 MiB). Host code never
+// Fiber records of fiber_intersect_pairs_noalloc, for callers that cannot
+// allocate: a fixed array in the code object, one copy per device, of
+// kScratchBytes (32 MiB: the records of 524,288 fibers). Host code never
 // passes the array's name to a kernel: each device's copy is reached through
 // the address hipGetSymbolAddress gives for it (DeviceInfo::scratch).
-constexpr int kScratchWaves = 6144;
-static __device__ __align__(256) float scratch[(size_t)kScratchWaves * 16 * kWave];
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) float scratch[kScratchBytes / sizeof(float)];
 
 struct DeviceInfo {
     std::atomic<bool> ready;
@@ -1296,8 +1344,9 @@ int current_device(int &dev)
 }
 
 // Set-up of the current device, once: unit counts, occupancy of every kernel
-// variant and the pinned staging buffers of batched calls. Every entry point
-// runs it on its first call on a device (fi_init_device runs it ahead).
+// variant, the address of this device's scratch array and the pinned staging
+// buffers of batched calls. Every entry point runs it on its first call on a
+// device (fi_init_device runs it ahead).
 int device_info(DeviceInfo *&out)
 {
     int dev = 0;
@@ -1331,15 +1380,6 @@ int device_info(DeviceInfo *&out)
     return FI_OK;
 }
 
-// Root slots of single calls: one 4 KiB block per resident wave of the
-// largest single-call grid.
-size_t pairs_slot_bytes(const DeviceInfo &d)
-{
-    int most = 0;
-    for (int m = 0; m < 3; ++m) most = d.fused_resident[m] > most ? d.fused_resident[m] : most;
-    return align256((size_t)most * d.cus * kSlotBytesPerWave);
-}
-
 // Fiber records of a single call: when it gathers fibers through pair_fiber
 // and reads each fiber about once or more, the fibers are first copied to
 // 16-float records (one pass over the table): a gathered fiber is then one
@@ -1353,7 +1393,7 @@ size_t record_bytes(int64_t n_pairs, int64_t n_fibers, bool gathered)
 // Launch defaults of single-problem calls (and of batches without a tuned
 // entry); measured choices, overridable when building.
 #ifndef FIBERHIT_DEFAULT_REFILL
-#define FIBERHIT_DEFAULT_REFILL 48
+#define FIBERHIT_DEFAULT_REFILL 1
 #endif
 #ifndef FIBERHIT_DEFAULT_WAVES_PER_SIMD
 #define FIBERHIT_DEFAULT_WAVES_PER_SIMD 0
@@ -1408,10 +1448,21 @@ int check_tuning(const fi_tuning &t)
     return FI_OK;
 }
 
+// Persistent waves of a single call: the resident waves. Twice as many,
+// each with half the share, made single deep calls (depth 16 and 22 at 2^20
+// pairs) about 13 % faster but two calls overlapped on two streams 7 %
+// slower (the second call's waves wait behind the first's); a grid skewed
+// towards the waves that start first on each SIMD, and issue priority by
+// progress through the share, were slower still.
+int64_t single_call_waves(const DeviceInfo &d, int mode, const Args &)
+{
+    return (int64_t)d.fused_resident[mode] * d.cus;
+}
+
 // Enqueue one single call on `s`: the fiber records (when `aos` is given),
 // then one persistent launch of about one wave per 64 pairs, at most
-// `max_waves` (the resident waves, or fewer when the slots are smaller).
-int launch(int mode, const Args &a, float *slots, int64_t max_waves, float *aos, hipStream_t s)
+// `max_waves`.
+int launch(int mode, const Args &a, int64_t max_waves, float *aos, hipStream_t s)
 {
     if (aos)
         hipLaunchKernelGGL(k_fibers_aos, dim3((unsigned)((a.n_fibers + 255) / 256)), dim3(256), 0, s,
@@ -1420,25 +1471,22 @@ int launch(int mode, const Args &a, float *slots, int64_t max_waves, float *aos,
     if (g > max_waves) g = max_waves;
     if (g > 0)
         hipLaunchKernelGGL(kFused[mode], dim3((unsigned)g), dim3(kWave), 0, s, a, nullptr, nullptr, 0,
-                           a.n_pairs, slots, mode == kConservative ? FIBERHIT_REFINE_REFILL : FIBERHIT_FUSED_REFILL,
-                           aos);
+                           a.n_pairs, mode == kConservative ? FIBERHIT_REFINE_REFILL : FIBERHIT_FUSED_REFILL, aos);
     return hipGetLastError() == hipSuccess ? FI_OK : FI_ERR_HIP;
 }
 
-// A single call with its buffers in the caller's workspace: root slots
-// first, then (room permitting) the fiber records.
+// A single call with the fiber records (if it gathers fibers) in the
+// caller's workspace, room permitting.
 int launch_with_workspace(int mode, const Args &a, void *workspace, size_t workspace_bytes, void *stream)
 {
-    if (!workspace || ((uintptr_t)workspace & 255u) != 0u) return FI_ERR_WORKSPACE;
+    if (workspace && ((uintptr_t)workspace & 255u) != 0u) return FI_ERR_WORKSPACE;
     (void)hipGetLastError();
     DeviceInfo *d = nullptr;
     const int st = device_info(d);
     if (st != FI_OK) return st;
-    const size_t slot_bytes = pairs_slot_bytes(*d);
-    if (workspace_bytes < slot_bytes) return FI_ERR_WORKSPACE;
     const size_t rec = record_bytes(a.n_pairs, a.n_fibers, a.pair_fiber != nullptr);
-    float *aos = rec && workspace_bytes >= slot_bytes + rec ? (float *)((char *)workspace + slot_bytes) : nullptr;
-    return launch(mode, a, (float *)workspace, (int64_t)d->fused_resident[mode] * d->cus, aos, (hipStream_t)stream);
+    float *aos = rec && workspace && workspace_bytes >= rec ? (float *)workspace : nullptr;
+    return launch(mode, a, single_call_waves(*d, mode, a), aos, (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -1446,17 +1494,6 @@ int launch_with_workspace(int mode, const Args &a, void *workspace, size_t works
 // ---------------------------------------------------------------------------
 
 size_t scene_table_bytes(int n) { return align256((size_t)n * sizeof(Args)) + align256((size_t)(n + 1) * sizeof(int64_t)); }
-
-// Root slots of the one-kernel batched path: one 4 KiB block per resident
-// wave of the larger batched grid (plain or refining).
-size_t batched_slot_bytes(const DeviceInfo &d)
-{
-    const int most = d.fused_resident[kBatchedVariant] > d.fused_resident[kBatchedRefineVariant]
-                         ? d.fused_resident[kBatchedVariant] : d.fused_resident[kBatchedRefineVariant];
-    return align256((size_t)most * d.cus * kSlotBytesPerWave);
-}
-
-size_t batched_bytes(const DeviceInfo &d, int n) { return scene_table_bytes(n) + batched_slot_bytes(d); }
 
 int scenes_to_table(const fi_scene *sc, int32_t n, uint32_t flags, Args *tab, int64_t *off)
 {
@@ -1478,11 +1515,10 @@ int scenes_to_table(const fi_scene *sc, int32_t n, uint32_t flags, Args *tab, in
     return FI_OK;
 }
 
-// Layout of a batched workspace: scene table, pair offsets, root slots.
+// Layout of a batched workspace: scene table, pair offsets.
 struct BatchLayout {
     Args *scenes;
     int64_t *offsets;
-    float *slots;
 };
 
 BatchLayout layout_of(void *ws, int n)
@@ -1491,7 +1527,6 @@ BatchLayout layout_of(void *ws, int n)
     BatchLayout L;
     L.scenes = (Args *)p;
     L.offsets = (int64_t *)(p + align256((size_t)n * sizeof(Args)));
-    L.slots = (float *)(p + scene_table_bytes(n));
     return L;
 }
 
@@ -1508,7 +1543,7 @@ void launch_batched(const DeviceInfo &d, const fi_tuning &t, const BatchLayout &
     if (g > (int64_t)per_cu * d.cus) g = (int64_t)per_cu * d.cus;
     if (g > 0)
         hipLaunchKernelGGL(kFused[variant], dim3((unsigned)g), dim3(kWave), 0, s, Args{}, L.scenes, L.offsets,
-                           n_scenes, total, L.slots, t.refill, nullptr);
+                           n_scenes, total, t.refill, nullptr);
 }
 
 int batched_enqueue(const fi_scene *scenes, int32_t n_scenes, uint32_t flags, const fi_tuning &t, void *workspace,
@@ -1519,8 +1554,7 @@ int batched_enqueue(const fi_scene *scenes, int32_t n_scenes, uint32_t flags, co
     if (st != FI_OK) return st;
     const size_t tb = scene_table_bytes(n_scenes);
     if (tb > kStageBytes) return FI_ERR_RANGE;
-    if (!workspace || ((uintptr_t)workspace & 255u) != 0u || workspace_bytes < batched_bytes(*d, n_scenes))
-        return FI_ERR_WORKSPACE;
+    if (!workspace || ((uintptr_t)workspace & 255u) != 0u || workspace_bytes < tb) return FI_ERR_WORKSPACE;
     std::lock_guard<std::mutex> lock(d->stage_mutex);
     const int k = d->stage_next;
     // the staging buffer's previous upload must have left it (rarely waits:
@@ -1543,7 +1577,7 @@ int batched_enqueue(const fi_scene *scenes, int32_t n_scenes, uint32_t flags, co
 
 struct fi_batch_plan {
     int device;
-    void *mem;                 // device copy of the scene table and offsets; root slots
+    void *mem;                 // device copy of the scene table and offsets
     int n_scenes;
     int64_t total;
     uint32_t flags;
@@ -1553,7 +1587,7 @@ struct fi_batch_plan {
 };
 
 extern "C" {
-int fi_version(void) { return (0 << 16) | (5 << 8) | 0; }
+int fi_version(void) { return (0 << 16) | (6 << 8) | 0; }
 
 const char *fi_strerror(int status)
 {
@@ -1563,6 +1597,7 @@ const char *fi_strerror(int status)
     case FI_ERR_RANGE: return "a count, stride, depth or flag is out of range";
     case FI_ERR_HIP: return "the HIP runtime reported an error";
     case FI_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+    case FI_ERR_SCRATCH: return "the call needs more scratch than the no-allocation entry point holds";
     default: return "unknown status";
     }
 }
@@ -1578,9 +1613,7 @@ size_t fiber_pairs_workspace_bytes(int64_t n_pairs, int64_t n_fibers, int32_t ga
 {
     (void)flags;
     if (n_pairs < 0 || n_fibers < 0) return 0;
-    DeviceInfo *d = nullptr;
-    if (device_info(d) != FI_OK) return 0;
-    return pairs_slot_bytes(*d) + record_bytes(n_pairs, n_fibers, gathered != 0);
+    return record_bytes(n_pairs, n_fibers, gathered != 0);
 }
 
 int fiber_intersect_pairs(const float *rays, int64_t ray_stride, int64_t n_rays,
@@ -1617,19 +1650,19 @@ int fiber_intersect_pairs_noalloc(const float *rays, int64_t ray_stride, int64_t
     if (st != FI_OK || n_pairs == 0) return st;
     const bool refine = (flags & FI_FP64_REFINE) != 0u;
     if (refine && (!t64_out || !u64_out)) return FI_ERR_NULL;
+    const size_t rec = record_bytes(n_pairs, n_fibers, pair_fiber != nullptr);
+    if (rec > kScratchBytes) return FI_ERR_SCRATCH;
     (void)hipGetLastError();
     DeviceInfo *d = nullptr;
     const int ds = device_info(d);
     if (ds != FI_OK) return ds;
     const int mode = refine ? kConservative : kPlain;
-    // the grid never needs more slots than the array holds
-    int64_t waves = (int64_t)d->fused_resident[mode] * d->cus;
-    if (waves > kScratchWaves) waves = kScratchWaves;
     Args a{rays, ray_stride, n_rays, fibers, fiber_stride, n_fibers,
            pair_ray, pair_fiber, pair_depth, depth, n_pairs, t_out, u_out, hit_out, nullptr,
            refine ? t64_out : nullptr, refine ? u64_out : nullptr};
-    // fibers gathered through pair_fiber are read in place (no records)
-    return launch(mode, a, d->scratch, waves, nullptr, (hipStream_t)stream);
+    // the fiber records of a gathered call go to this device's copy of the
+    // scratch array (through its device address, never the array's name)
+    return launch(mode, a, single_call_waves(*d, mode, a), rec ? d->scratch : nullptr, (hipStream_t)stream);
 }
 
 int fiber_intersect_counts(const float *rays, int64_t ray_stride, int64_t n_rays,
@@ -1653,9 +1686,7 @@ int fiber_intersect_counts(const float *rays, int64_t ray_stride, int64_t n_rays
 size_t fiber_batched_workspace_bytes(int32_t n_scenes, int64_t total_pairs)
 {
     if (n_scenes < 0 || total_pairs < 0) return 0;
-    DeviceInfo *d = nullptr;
-    if (device_info(d) != FI_OK) return 0;
-    return batched_bytes(*d, n_scenes);
+    return scene_table_bytes(n_scenes);
 }
 
 int fiber_intersect_batched(const fi_scene *scenes, int32_t n_scenes, const fi_tuning *tuning,
@@ -1698,7 +1729,7 @@ int fiber_batch_plan_create(const fi_scene *scenes, int32_t n_scenes, const fi_t
     p->tuning = t;
     current_device(p->device);
     hipStream_t cs = nullptr;
-    const size_t bytes = batched_bytes(*d, n_scenes);
+    const size_t bytes = tb;
     bool ok = hipMalloc(&p->mem, bytes) == hipSuccess &&
               hipMemcpy(p->mem, host, tb, hipMemcpyHostToDevice) == hipSuccess &&
               hipStreamCreate(&cs) == hipSuccess;

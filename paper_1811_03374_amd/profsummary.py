@@ -103,9 +103,48 @@ def calibration(dispatches):
     raise SystemExit("no copy dispatch found for calibration")
 
 
+def sq_counters(paths):
+    """Counter sums of the k_fused dispatches of ``--traffic-probe`` runs (one
+    call per depth), in dispatch order, from rocprofv3 counter CSVs."""
+    per = collections.OrderedDict()
+    for path in paths:
+        for r in csv.DictReader(open(path)):
+            if "k_fused" not in r["Kernel_Name"]:
+                continue
+            key = (path, int(r["Dispatch_Id"]))
+            per.setdefault(key, collections.Counter())[r["Counter_Name"]] += float(r["Counter_Value"])
+    by_path = collections.OrderedDict()
+    for (path, _), c in per.items():
+        by_path.setdefault(path, []).append(c)
+    out = [collections.Counter() for _ in DEPTHS]
+    for calls in by_path.values():
+        for j, c in enumerate(calls[:len(DEPTHS)]):
+            for k, v in c.items():
+                out[j].setdefault(k, v)
+    return out
+
+
+def sq_lines(paths, durations=None):
+    cs = sq_counters(paths)
+    names = sorted(set().union(*[set(c) for c in cs]))
+    lines = ["| counter | " + " | ".join(f"depth {d}" for d in DEPTHS) + " |",
+             "|---|" + "---|" * len(DEPTHS)]
+    for n in names:
+        lines.append(f"| {n} | " + " | ".join(f"{int(c.get(n, 0))}" for c in cs) + " |")
+    if all("SQ_INSTS_VALU" in c for c in cs):
+        issue = [c["SQ_INSTS_VALU"] / 1024 * 4 / 2.4e3 for c in cs]
+        lines += ["", "VALU issue time (1024 SIMDs, 4 cycles per wave64 VALU instruction, 2.4 GHz): " +
+                  ", ".join(f"depth {d}: {t:.0f} us" for d, t in zip(DEPTHS, issue)) +
+                  (", against " + ", ".join(f"{u:.0f} us" for u in durations) + " per call in the kernel trace"
+                   if durations else "") + "."]
+    return lines
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--stats", required=True)
+    ap.add_argument("--stats")
+    ap.add_argument("--sq", action="append", default=[],
+                    help="rocprofv3 counter CSV of a --traffic-probe run (repeatable): SQ counter table")
     ap.add_argument("--fetch")
     ap.add_argument("--write")
     ap.add_argument("--name", required=True)
@@ -116,19 +155,25 @@ def main(argv=None):
                     help="command line that produced an input (repeatable)")
     a = ap.parse_args(argv)
     os.makedirs(a.out, exist_ok=True)
-    stats = read_stats(a.stats)
     lines = [f"# {a.name}", "", "Commands:", ""]
     lines += [f"    {c}" for c in a.command] + [""]
-    lines += ["| kernel | calls | avg us | min us | max us | % of GPU time |", "|---|---|---|---|---|---|"]
-    for s in stats:
-        lines.append(f"| {s['kernel']} | {s['calls']} | {s['avg_us']:.1f} | {s['min_us']:.1f} | "
-                     f"{s['max_us']:.1f} | {s['percent']:.1f} |")
+    if a.stats:
+        stats = read_stats(a.stats)
+        lines += ["| kernel | calls | avg us | min us | max us | % of GPU time |", "|---|---|---|---|---|---|"]
+        for s in stats:
+            lines.append(f"| {s['kernel']} | {s['calls']} | {s['avg_us']:.1f} | {s['min_us']:.1f} | "
+                         f"{s['max_us']:.1f} | {s['percent']:.1f} |")
+    iso = None
     if a.trace and a.steps > 0:
         iso, ovl = call_durations(a.trace, a.steps)
         lines += ["", f"Per-call durations of `k_fused<0, false>` from the kernel trace ({a.steps} steps):", "",
                   "| depth | one after another, us | overlapped (two streams), us |", "|---|---|---|"]
         for d in DEPTHS:
             lines.append(f"| {d} | {iso[d]:.1f} | {ovl[d]:.1f} |")
+    if a.sq:
+        lines += ["", "SQ counters summed over the device, one `k_fused<0, false>` dispatch per depth "
+                  "(`--traffic-probe`: one call at depth 9, then one at depth 22):", ""]
+        lines += sq_lines(a.sq, [iso[d] for d in DEPTHS] if iso else None)
     traffic = None
     if a.fetch and a.write:
         fd = read_counter(a.fetch, "FETCH_SIZE")

@@ -38,7 +38,7 @@ def test_library_exports_every_declared_function():
 def test_version_and_strerror():
     L = binding.lib()
     assert L.fi_version() > 0
-    for code in (0, -1, -2, -3, -4, -99):
+    for code in (0, -1, -2, -3, -4, -5, -99):
         assert len(L.fi_strerror(code)) > 0
 
 
@@ -58,9 +58,9 @@ def _call(**kw):
     (dict(rs=4), -2), (dict(fs=4), -2), (dict(n=9), -2),
     (dict(rays=None), -1), (dict(fibers=None), -1), (dict(t=None), -1), (dict(h=None), -1),
     (dict(flags=1), -1), (dict(flags=1, t64=1), -1), (dict(flags=5, t64=1, u64=1), -2),
-    # a missing or misaligned workspace is refused before any HIP call
-    (dict(), -4), (dict(ws=0x1008, wsb=1 << 30), -4), (dict(flags=2), -4),
-    (dict(flags=3, t64=1, u64=1), -4),
+    # a misaligned workspace is refused before any HIP call
+    (dict(ws=0x1008, wsb=1 << 30), -4), (dict(flags=2, ws=0x1010, wsb=64), -4),
+    (dict(flags=3, t64=1, u64=1, ws=0x1001, wsb=64), -4),
 ])
 def test_argument_errors_before_launch(kw, code):
     # these return before any HIP call, so they are safe without a device
@@ -102,3 +102,29 @@ def test_pair_count_rejects_mismatched_lengths():
         binding._pair_count(rays, fibers, None, None, torch.zeros(250, dtype=torch.uint8))
     with pytest.raises(ValueError):
         binding._pair_count(rays[:, :100], fibers, None, i, None)
+
+
+def test_workspace_sizes():
+    """The single-call workspace holds the fiber records of a gathered call
+    (64 bytes per fiber, 256-byte aligned) and is empty otherwise; the
+    batched workspace holds the scene table. Neither needs a device."""
+    L = binding.lib()
+    L.fiber_batched_workspace_bytes.argtypes = [C.c_int32, C.c_int64]
+    L.fiber_batched_workspace_bytes.restype = C.c_size_t
+    assert L.fiber_pairs_workspace_bytes(1000, 1000, 1, 0) == 64000
+    assert L.fiber_pairs_workspace_bytes(1001, 1001, 1, 0) == (1001 * 64 + 255) // 256 * 256
+    assert L.fiber_pairs_workspace_bytes(1000, 1000, 0, 0) == 0
+    assert L.fiber_pairs_workspace_bytes(999, 1000, 1, 0) == 0       # fewer pairs than fibers: in place
+    assert L.fiber_pairs_workspace_bytes(-1, 10, 1, 0) == 0
+    assert L.fiber_batched_workspace_bytes(10, 1 << 20) > 0
+
+
+def test_noalloc_refuses_more_records_than_its_scratch():
+    """A gathered call whose fiber records exceed the 32 MiB scratch of the
+    no-allocation entry point is refused before any HIP call."""
+    L = binding.lib()
+    n = 600_000
+    r = L.fiber_intersect_pairs_noalloc(C.c_void_p(256), n, n, C.c_void_p(256), n, n, None,
+                                        C.c_void_p(256), None, 9, n, 0, C.c_void_p(256), C.c_void_p(256),
+                                        C.c_void_p(256), None, None, None)
+    assert r == -5

@@ -38,6 +38,7 @@ def test_device_memory_unchanged_across_growing_calls():
         binding.intersect_pairs(rays[:, :n], fibers[:, :n], 22, out=o, workspace=ws)
 
     calls(64)                               # first launches (code objects, kernel scratch)
+    assert ws is not None
     binding.intersect_pairs(rays[:, :64], fibers[:, :64], 22, refine=True, workspace=ws)
     binding.intersect_pairs(rays[:, :64], fibers[:, :64], 9, counts=True, workspace=ws)
     torch.cuda.synchronize()
@@ -55,32 +56,43 @@ def test_device_memory_unchanged_across_growing_calls():
 
 
 def test_workspace_without_room_for_records():
-    """A gathered call whose workspace holds only the root slots reads the
-    fiber rows in place: same results, bit for bit."""
+    """A gathered call without a workspace, or with one too small for the
+    fiber records, reads the fiber rows in place: same results, bit for
+    bit."""
     n = 50_000
     w = W.straight_and_curved(n, 9)
     rays = torch.from_numpy(w.rays).to(DEV)
     fibers = torch.from_numpy(w.fibers).to(DEV)
     idx = torch.from_numpy(np.random.default_rng(3).permutation(n).astype(np.int32)).to(DEV)
     full = binding.pairs_workspace(n, n, True, torch.device(DEV))
-    slots_only = binding.pairs_workspace(n, n, False, torch.device(DEV))
-    assert full.numel() > slots_only.numel()
+    assert full is not None and full.numel() == n * 64
+    assert binding.pairs_workspace(n, n, False, torch.device(DEV)) is None
+    small = torch.empty(4096, dtype=torch.uint8, device=DEV)
     a = [x.cpu().numpy() for x in binding.intersect_pairs(rays, fibers, 9, idx, idx, workspace=full)]
-    b = [x.cpu().numpy() for x in binding.intersect_pairs(rays, fibers, 9, idx, idx, workspace=slots_only)]
-    for x, y in zip(a, b):
-        assert np.array_equal(_bits(x), _bits(y))
+    for ws in (small, None):
+        lib = binding.lib()
+        t, u, h = (torch.empty(n, device=DEV), torch.empty(n, device=DEV),
+                   torch.empty(n, dtype=torch.uint8, device=DEV))
+        st = lib.fiber_intersect_pairs(rays.data_ptr(), rays.stride(0), n, fibers.data_ptr(), fibers.stride(0), n,
+                                       idx.data_ptr(), idx.data_ptr(), None, 9, n, 0, t.data_ptr(), u.data_ptr(),
+                                       h.data_ptr(), None, None, None if ws is None else ws.data_ptr(),
+                                       0 if ws is None else ws.numel(),
+                                       torch.cuda.current_stream().cuda_stream)
+        assert st == 0
+        torch.cuda.synchronize()
+        for x, y in zip(a, (t, u, h)):
+            assert np.array_equal(_bits(x), _bits(y.cpu().numpy()))
 
 
 def test_workspace_errors():
-    w = W.straight_and_curved(256, 9)
+    n = 256
+    w = W.straight_and_curved(n, 9)
     rays = torch.from_numpy(w.rays).to(DEV)
     fibers = torch.from_numpy(w.fibers).to(DEV)
-    small = torch.empty(4096, dtype=torch.uint8, device=DEV)
-    with pytest.raises(binding.FiberHitError):
-        binding.intersect_pairs(rays, fibers, 9, workspace=small)
-    ws = binding.pairs_workspace(256, 256, False, torch.device(DEV))
+    idx = torch.arange(n, dtype=torch.int32, device=DEV)
+    ws = binding.pairs_workspace(n, n, True, torch.device(DEV))
     with pytest.raises(binding.FiberHitError):          # not 256-byte aligned
-        binding.intersect_pairs(rays, fibers, 9, workspace=ws[16:])
+        binding.intersect_pairs(rays, fibers, 9, idx, idx, workspace=ws[16:])
 
 
 def test_mismatched_per_pair_lengths_rejected_before_launch():
