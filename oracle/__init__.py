@@ -31,7 +31,7 @@ def lib():
         L.fo_batch_d.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_int64,
                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int64,
                                  C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
-                                 C.c_void_p]
+                                 C.c_void_p, C.c_void_p]
         L.fo_batch_d.restype = None
         L.fo_split_half.argtypes = [dp, dp, dp]
         L.fo_split_plane.argtypes = [dp, dp, dp]
@@ -51,9 +51,9 @@ def lib():
         if hasattr(L, "fx_batch"):
             L.fx_batch.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_int64,
                                    C.c_void_p, C.c_void_p, C.c_int64, C.c_double,
-                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
             L.fx_batch.restype = None
-            L.fx_intersect.argtypes = [dp, dp, dp, dp]
+            L.fx_intersect.argtypes = [dp, dp, dp, dp, dp]
             L.fx_intersect.restype = C.c_int
             L.fx_side_polynomial.argtypes = [dp, dp]
             L.fx_side_polynomial.restype = C.c_int
@@ -71,13 +71,20 @@ def _d(a):
 
 
 def intersect_depth(rays, fibers, depth=9, pair_ray=None, pair_fiber=None,
-                    pair_depth=None, radius_scale=1.0, stats=False, nthreads=0, t_err=False):
+                    pair_depth=None, radius_scale=1.0, stats=False, nthreads=0, t_err=False,
+                    normal=False):
     """ORACLE-D: the paper's depth-d method in FP64 for every pair.
 
     Returns (t float64, u float64, hit uint8[, stats int32 (n, 4)][, t_err
-    float64]). ``stats`` columns: node tests, splits, backtracks (second-child
-    visits), leaf level (-1 on a miss). ``t_err``: error bound of each hit's t
-    in an FP32 evaluation (reading R14's node error model; 0 on a miss)."""
+    float64][, normal float64 (n, 8)]). ``stats`` columns: node tests, splits,
+    backtracks (second-child visits), leaf level (-1 on a miss). ``t_err``:
+    error bound of each hit's t in an FP32 evaluation (reading R14's node
+    error model; 0 on a miss). ``normal`` columns: the unit normal at the hit
+    in world space (3), the normal of the other entry where a cap and a side
+    entry tie (3, else the same), the angle bound in radians of the normal in
+    an FP32 evaluation (1), how the leaf was entered (1: 0 through the
+    cylinder's side, 1 the curve's start cap plane, 2 its end cap plane, 3 an
+    inner plane, 4 at the origin); NaN on a miss."""
     rays = np.ascontiguousarray(rays, dtype=np.float32)
     fibers = np.ascontiguousarray(fibers, dtype=np.float32)
     pr = None if pair_ray is None else np.ascontiguousarray(pair_ray, dtype=np.int32)
@@ -94,19 +101,22 @@ def intersect_depth(rays, fibers, depth=9, pair_ray=None, pair_fiber=None,
     hit = np.empty(n, np.uint8)
     st = np.empty((n, 4), np.int32) if stats else None
     te = np.empty(n, np.float64) if t_err else None
+    nn = np.empty((n, 8), np.float64) if normal else None
     lib().fo_batch_d(_ptr(rays), rays.shape[1], rays.shape[1], _ptr(fibers), fibers.shape[1],
                      fibers.shape[1], _ptr(pr), _ptr(pf), _ptr(pd), int(depth), n,
                      float(radius_scale), _ptr(t), _ptr(u), _ptr(hit), _ptr(st), int(nthreads),
-                     _ptr(te))
-    out = (t, u, hit) + ((st,) if stats else ()) + ((te,) if t_err else ())
+                     _ptr(te), _ptr(nn))
+    out = (t, u, hit) + ((st,) if stats else ()) + ((te,) if t_err else ()) + ((nn,) if normal else ())
     return out
 
 
 def intersect_exact(rays, fibers, pair_ray=None, pair_fiber=None, radius_scale=1.0,
-                    nthreads=0):
+                    nthreads=0, normal=False):
     """ORACLE-X: first entry of the ray into the swept-disk solid (the limit
-    of the method), in FP64. Returns (t, u, hit, kind) where kind is 0 miss,
-    1 side surface, 2 start cap, 3 end cap, 4 origin inside."""
+    of the method), in FP64. Returns (t, u, hit, kind[, normal (n, 3)]) where
+    kind is 0 miss, 1 side surface, 2 start cap, 3 end cap, 4 origin inside;
+    ``normal`` is the outward unit normal at the entry in world space (NaN
+    on a miss or with the origin inside)."""
     L = lib()
     if not hasattr(L, "fx_batch"):
         raise RuntimeError("exact oracle not built")
@@ -123,20 +133,23 @@ def intersect_exact(rays, fibers, pair_ray=None, pair_fiber=None, radius_scale=1
     t = np.empty(n, np.float64)
     u = np.empty(n, np.float64)
     kind = np.empty(n, np.int32)
+    nn = np.empty((n, 3), np.float64) if normal else None
     L.fx_batch(_ptr(rays), rays.shape[1], rays.shape[1], _ptr(fibers), fibers.shape[1],
                fibers.shape[1], _ptr(pr), _ptr(pf), n, float(radius_scale),
-               _ptr(t), _ptr(u), _ptr(kind), int(nthreads))
-    return t, u, (kind > 0).astype(np.uint8), kind
+               _ptr(t), _ptr(u), _ptr(kind), int(nthreads), _ptr(nn))
+    return (t, u, (kind > 0).astype(np.uint8), kind) + ((nn,) if normal else ())
 
 
-def single_exact(ray, fiber):
-    """One pair through fx_intersect (float64 inputs). Returns (kind, t, u)."""
+def single_exact(ray, fiber, normal=False):
+    """One pair through fx_intersect (float64 inputs). Returns (kind, t, u[,
+    normal])."""
     r, rp = _d(ray)
     f, fp = _d(fiber)
     t = C.c_double()
     u = C.c_double()
-    kind = lib().fx_intersect(rp, fp, C.byref(t), C.byref(u))
-    return kind, t.value, u.value
+    n = np.empty(3)
+    kind = lib().fx_intersect(rp, fp, C.byref(t), C.byref(u), n.ctypes.data_as(C.POINTER(C.c_double)))
+    return (kind, t.value, u.value) + ((n,) if normal else ())
 
 
 def side_polynomial(q16):

@@ -482,6 +482,50 @@ static int exact_hit(const curve_t *c, double tmax, double *t_out, double *u_out
     return kind;
 }
 
+/* Outward unit normal of the solid at the entry (ray frame).
+ * Side (kind 1): the side surface is X(u, phi) = C(u) + r(u) e(u, phi) with e
+ * a unit vector normal to C'(u). Its normal is normal to the circle's
+ * tangent, so it lies in the plane of e and T = C'/|C'|; being normal to
+ * dX/du = C' + r' e + r de/du as well, with <T, de/du> = -<e, C''>/|C'|,
+ * it is e - r' / (|C'| - r <e, C''>/|C'|) T (a cone's tilt against its
+ * widening; zero for a constant radius). e is the unit direction from C(u)
+ * to the entry point (0, 0, t).
+ * Caps (kinds 2, 3): minus the start disc's normal, the end disc's normal.
+ * Origin inside (kind 4): no surface crossing, NaN. */
+static void exact_normal(const curve_t *c, int kind, double t, double u, double n[3])
+{
+    n[0] = n[1] = n[2] = NAN;
+    if (kind == 2 || kind == 3) {
+        end_normal(c, kind - 2, n);
+        const double s = (kind == 2 ? -1.0 : 1.0) / sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        for (int k = 0; k < 3; ++k) n[k] *= s;
+        return;
+    }
+    if (kind != 1) return;
+    const double (*q)[4] = c->q;
+    const double v = 1.0 - u;
+    double C[4], D1[4], D2[3];
+    for (int k = 0; k < 4; ++k) {
+        C[k] = v * v * v * q[0][k] + 3.0 * u * v * v * q[1][k] + 3.0 * u * u * v * q[2][k] + u * u * u * q[3][k];
+        D1[k] = 3.0 * (v * v * (q[1][k] - q[0][k]) + 2.0 * u * v * (q[2][k] - q[1][k]) + u * u * (q[3][k] - q[2][k]));
+        if (k < 3)
+            D2[k] = 6.0 * (v * (q[2][k] - 2.0 * q[1][k] + q[0][k]) + u * (q[3][k] - 2.0 * q[2][k] + q[1][k]));
+    }
+    double e[3] = {-C[0], -C[1], t - C[2]};
+    const double el = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+    const double dl = sqrt(D1[0] * D1[0] + D1[1] * D1[1] + D1[2] * D1[2]);
+    for (int k = 0; k < 3; ++k) e[k] /= el;
+    const double ec2 = e[0] * D2[0] + e[1] * D2[1] + e[2] * D2[2];
+    const double beta = -D1[3] / (dl - C[3] * ec2 / dl);
+    double len = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        n[k] = e[k] + beta * D1[k] / dl;
+        len += n[k] * n[k];
+    }
+    len = sqrt(len);
+    for (int k = 0; k < 3; ++k) n[k] /= len;
+}
+
 /* Duff et al. 2017 basis (same published construction as the depth oracle;
  * repeated here so that this file stands alone). */
 static void onb_x(const double w[3], double u[3], double v[3])
@@ -493,10 +537,14 @@ static void onb_x(const double w[3], double u[3], double v[3])
     v[0] = b;  v[1] = s + w[1] * w[1] * a;  v[2] = -w[1];
 }
 
-int fx_intersect(const double ray[7], const double fiber[16], double *t_out, double *u_out)
+/* n_out (may be NULL): the unit normal at the entry in world space (NaN on a
+ * miss or with the origin inside). */
+int fx_intersect(const double ray[7], const double fiber[16], double *t_out, double *u_out,
+                 double n_out[3])
 {
     *t_out = INFINITY;
     *u_out = NAN;
+    if (n_out) n_out[0] = n_out[1] = n_out[2] = NAN;
     const double *O = ray, *Dr = ray + 3;
     const double len = sqrt(Dr[0] * Dr[0] + Dr[1] * Dr[1] + Dr[2] * Dr[2]);
     if (!(len > 0.0) || !isfinite(len) || !(ray[6] == ray[6])) return 0;
@@ -516,6 +564,11 @@ int fx_intersect(const double ray[7], const double fiber[16], double *t_out, dou
     if (kind == 0) return 0;
     *t_out = t;
     *u_out = uu;
+    if (n_out) {
+        double n[3];
+        exact_normal(&c, kind, t, uu, n);
+        for (int k = 0; k < 3; ++k) n_out[k] = n[0] * u[k] + n[1] * v[k] + n[2] * w[k];
+    }
     return kind;
 }
 
@@ -523,7 +576,7 @@ void fx_batch(const float *rays, int64_t ray_stride, int64_t n_rays,
               const float *fibers, int64_t fiber_stride, int64_t n_fibers,
               const int32_t *pair_ray, const int32_t *pair_fiber, int64_t n,
               double radius_scale, double *t_out, double *u_out, int32_t *kind_out,
-              int nthreads)
+              int nthreads, double *normal_out)
 {
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -532,14 +585,16 @@ void fx_batch(const float *rays, int64_t ray_stride, int64_t n_rays,
     for (int64_t i = 0; i < n; ++i) {
         const int64_t ri = pair_ray ? pair_ray[i] : i;
         const int64_t fi = pair_fiber ? pair_fiber[i] : i;
-        double ray[7], fib[16], t = INFINITY, u = NAN;
+        double ray[7], fib[16], t = INFINITY, u = NAN, nn[3] = {NAN, NAN, NAN};
         int kind = 0;
         if (ri >= 0 && ri < n_rays && fi >= 0 && fi < n_fibers) {
             for (int r = 0; r < 7; ++r) ray[r] = rays[r * ray_stride + ri];
             for (int r = 0; r < 16; ++r) fib[r] = fibers[r * fiber_stride + fi];
             for (int k = 0; k < 4; ++k) fib[4 * k + 3] *= radius_scale;
-            kind = fx_intersect(ray, fib, &t, &u);
+            kind = fx_intersect(ray, fib, &t, &u, nn);
         }
+        if (normal_out)
+            for (int k = 0; k < 3; ++k) normal_out[3 * i + k] = nn[k];
         t_out[i] = t;
         u_out[i] = u;
         kind_out[i] = kind;

@@ -106,13 +106,16 @@ static void onb(const double w[3], double u[3], double v[3])
 /* Control points of one fiber in the frame of one ray. Returns 0 when the
  * ray direction is zero or not finite (then the pair is a miss). */
 static int ray_frame(const double O[3], const double D[3], const double P[16],
-                     v4 q[4], double *len_out)
+                     v4 q[4], double *len_out, double frame[9])
 {
     const double len = sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
     if (!(len > 0.0) || !isfinite(len)) return 0;
     const double w[3] = {D[0] / len, D[1] / len, D[2] / len};
     double u[3], v[3];
     onb(w, u, v);
+    if (frame) {
+        for (int k = 0; k < 3; ++k) { frame[k] = u[k]; frame[3 + k] = v[k]; frame[6 + k] = w[k]; }
+    }
     for (int k = 0; k < 4; ++k) {
         const double d0 = P[4 * k + 0] - O[0];
         const double d1 = P[4 * k + 1] - O[1];
@@ -176,15 +179,33 @@ static double plane_err(double delta, v4 n, double t)
  * point o and the control points relative to it (see node_t). elo/ehi (may be
  * NULL) receive the error bounds of the two ends for node coordinates known
  * to +-delta (0 for the ends 0 and tmax). */
+/* Where the entry bound of an interval comes from (for the normal, R9): the
+ * origin (t = 0), the curve's start or end cap, or an inner plane (a split
+ * plane, or the cap plane of an inner node, which is a split plane). */
+enum { LO_ORIGIN = 0, LO_START_CAP = 1, LO_END_CAP = 2, LO_INNER = 3 };
+
+static void cap_interval_src(v4 o, const v4 q[4], double tmax, double delta, int at_start, int at_end,
+                             double *lo, double *hi, double *elo, double *ehi, int *src);
+
 static void cap_interval_e(v4 o, const v4 q[4], double tmax, double delta, double *lo, double *hi,
                            double *elo, double *ehi)
 {
+    cap_interval_src(o, q, tmax, delta, 0, 0, lo, hi, elo, ehi, NULL);
+}
+
+/* As cap_interval_e, for a node whose parameter interval starts at the
+ * curve's start (at_start) and/or ends at its end (at_end); *src receives
+ * the origin of the entry bound. */
+static void cap_interval_src(v4 o, const v4 q[4], double tmax, double delta, int at_start, int at_end,
+                             double *lo, double *hi, double *elo, double *ehi, int *src)
+{
     double l = 0.0, h = tmax, el = 0.0, eh = 0.0;
+    int ls = LO_ORIGIN;
     const v4 n0 = start_cap_normal(q);
     const double c0 = dot3(o, n0) + dot3(q[0], n0);       /* inside <=> t*n0.z >= c0 */
     if (n0.z != 0.0) {
         const double t = c0 / n0.z;
-        if (n0.z > 0.0 && t > l) { l = t; el = plane_err(delta, n0, t); }
+        if (n0.z > 0.0 && t > l) { l = t; el = plane_err(delta, n0, t); ls = at_start ? LO_START_CAP : LO_INNER; }
         if (n0.z < 0.0 && t < h) { h = t; eh = plane_err(delta, n0, t); }
     } else if (c0 > 0.0) {
         l = INFINITY; h = -INFINITY;
@@ -194,7 +215,7 @@ static void cap_interval_e(v4 o, const v4 q[4], double tmax, double delta, doubl
     if (n1.z != 0.0) {
         const double t = c1 / n1.z;
         if (n1.z > 0.0 && t < h) { h = t; eh = plane_err(delta, n1, t); }
-        if (n1.z < 0.0 && t > l) { l = t; el = plane_err(delta, n1, t); }
+        if (n1.z < 0.0 && t > l) { l = t; el = plane_err(delta, n1, t); ls = at_end ? LO_END_CAP : LO_INNER; }
     } else if (c1 < 0.0) {
         l = INFINITY; h = -INFINITY;
     }
@@ -202,6 +223,7 @@ static void cap_interval_e(v4 o, const v4 q[4], double tmax, double delta, doubl
     *hi = h;
     if (elo) *elo = el;
     if (ehi) *ehi = eh;
+    if (src) *src = ls;
 }
 
 /* Squared distance of point e (relative to the axis origin) to the line
@@ -378,6 +400,11 @@ typedef struct {
     double t_err;       /* error bound of t in an FP32 evaluation (as for ties) */
     int level;
     ties_t ties;
+    v4 cap0, cap1;      /* the curve's start and end cap normals (ray frame, R13) */
+    double n[3];        /* normal at the hit, ray frame (R9) */
+    double n_alt[3];    /* the other normal where cap and side entry tie (else n) */
+    double n_err;       /* angle bound (radians) of n in an FP32 evaluation */
+    int entry;          /* 0 cylinder side, else the LO_* source of the entry plane */
 } search_t;
 
 static double node_err(const search_t *S, int level)
@@ -427,8 +454,47 @@ static int decide_vis(search_t *S, int value, double diff, double margin)
     return decide(S, value, diff, margin);
 }
 
+/* Normal at a leaf hit (R9: the paper's listing "Calculate the normal and u
+ * parameter", with its undefined names read as the leaf chord and the ray
+ * direction): a hit on the leaf cylinder's side (t from the cylinder entry)
+ * gets the direction from the chord point at the hit's projection to the hit
+ * point; a hit through the curve's start or end cap plane gets that cap's
+ * outward normal (minus the start tangent, the end tangent; their R13 limits
+ * where they vanish). An entry through an inner plane, or at the origin,
+ * keeps the radial direction. */
+static void unit3(v4 n, double out[3])
+{
+    const double len = sqrt(dot3(n, n));
+    out[0] = n.x / len;
+    out[1] = n.y / len;
+    out[2] = n.z / len;
+}
+
+/* te, lo: the cylinder entry and the interval's start, with error bounds ec
+ * and elo (R14); delta the node's coordinate error. Where te and lo are
+ * within those bounds of each other an FP32 evaluation may take either
+ * entry, so both normals are recorded. The angle bound of the side normal is
+ * the hit point's and the chord point's error over the normal's length; a
+ * cap normal comes from the root's tangent, exact up to rounding. */
+static void leaf_normal(search_t *S, const node_t *N, v4 a, double t, double ul, double te,
+                        double lo, double ec, double elo, double delta, int lsrc)
+{
+    const v4 ap = add4(mk4(N->o.x, N->o.y, N->o.z, 0.0), add4(N->q[0], scale4(a, ul)));
+    const v4 side = mk4(-ap.x, -ap.y, t - ap.z, 0.0);
+    const int capped = lsrc == LO_START_CAP || lsrc == LO_END_CAP;
+    const v4 cap = lsrc == LO_START_CAP ? scale4(S->cap0, -1.0) : S->cap1;
+    const int on_side = te >= lo || !capped;
+    S->entry = te >= lo ? 0 : (lsrc == LO_ORIGIN ? 4 : lsrc);
+    unit3(on_side ? side : cap, S->n);
+    const int tie = capped && fabs(te - lo) <= ec + elo;
+    unit3(tie ? (on_side ? cap : side) : (on_side ? side : cap), S->n_alt);
+    const double ns = sqrt(dot3(side, side));
+    const double e_side = 2.0 * (S->t_err + 3.0 * delta) / ns + 0x1p-20;
+    S->n_err = on_side ? e_side : (tie ? fmax(e_side, 0x1p-20) : 0x1p-20);
+}
+
 static int visit(search_t *S, const node_t *N, double lo, double hi, double elo, double ehi,
-                 int level, double u0, double u1)
+                 int lsrc, int level, double u0, double u1)
 {
     S->tests++;
     const v4 *q = N->q;
@@ -464,6 +530,7 @@ static int visit(search_t *S, const node_t *N, double lo, double hi, double elo,
         S->t_err = e_enter;
         S->u = u0 + ul * (u1 - u0);
         S->level = level;
+        leaf_normal(S, N, a, t, ul, te, lo, ec, elo, delta, lsrc);
         return 1;
     }
 
@@ -474,6 +541,7 @@ static int visit(search_t *S, const node_t *N, double lo, double hi, double elo,
     const double c = dot3(N->o, n) + dot3(Lc.q[3], n);    /* <split point, n> */
     int go_right, both;
     double flo = lo, fhi = hi, eflo = elo, efhi = ehi;
+    int flsrc = lsrc;
     if (n.z != 0.0) {
         const double tp = c / n.z;
         const double ep = plane_err(delta, n, tp);
@@ -488,7 +556,7 @@ static int visit(search_t *S, const node_t *N, double lo, double hi, double elo,
         go_right = beyond_entry != (n.z > 0.0);
         both = beyond_entry && before_exit;
         if (beyond_entry) { if (tpn < fhi) { fhi = tpn; efhi = ep; } }
-        else              { if (tpn > flo) { flo = tpn; eflo = ep; } }
+        else              { if (tpn > flo) { flo = tpn; eflo = ep; flsrc = LO_INNER; } }
     } else {
         const double side = -c;            /* <(0,0,t) - s, n> for every t */
         go_right = side > 0.0;
@@ -500,12 +568,14 @@ static int visit(search_t *S, const node_t *N, double lo, double hi, double elo,
     const double f0 = go_right ? um : u0, f1 = go_right ? u1 : um;
     const double s0 = go_right ? u0 : um, s1 = go_right ? um : u1;
 
-    if (visit(S, first, flo, fhi, eflo, efhi, level + 1, f0, f1)) return 1;
+    if (visit(S, first, flo, fhi, eflo, efhi, flsrc, level + 1, f0, f1)) return 1;
     if (!both) return 0;
     S->backtracks++;
     double blo, bhi, eblo, ebhi;
-    cap_interval_e(second->o, second->q, S->tmax, node_err(S, level + 1), &blo, &bhi, &eblo, &ebhi);
-    return visit(S, second, blo, bhi, eblo, ebhi, level + 1, s0, s1);
+    int bsrc;
+    cap_interval_src(second->o, second->q, S->tmax, node_err(S, level + 1), s0 == 0.0, s1 == 1.0,
+                     &blo, &bhi, &eblo, &ebhi, &bsrc);
+    return visit(S, second, blo, bhi, eblo, ebhi, bsrc, level + 1, s0, s1);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -519,8 +589,10 @@ int fo_version(void) { return 1; }
  * and the level of the leaf that was hit (-1 on a miss). Returns 1 on a hit. */
 static int intersect_with_ties(const double ray[7], const double fiber[16], int depth,
                                double scale, uint64_t flip_mask, int force_vis, int *n_ties,
-                               double *t_out, double *u_out, int64_t stats[4], double *t_err)
+                               double *t_out, double *u_out, int64_t stats[4], double *t_err,
+                               double normal_out[8])
 {
+    double frame[9];
     search_t S;
     memset(&S, 0, sizeof S);
     S.ties.scale = scale;
@@ -532,13 +604,16 @@ static int intersect_with_ties(const double ray[7], const double fiber[16], int 
     int hit = 0;
     v4 q[4];
     if (depth >= 0 && depth <= 23 && ray[6] == ray[6] &&
-        ray_frame(ray, ray + 3, fiber, q, NULL)) {
+        ray_frame(ray, ray + 3, fiber, q, NULL, frame)) {
         double lo, hi, elo, ehi;
         for (int k = 0; k < 4; ++k)
             S.ties.X = fmax(S.ties.X, fmax(fabs(q[k].x), fmax(fabs(q[k].y), fabs(q[k].z))));
         const node_t root = anchored(q);
-        cap_interval_e(root.o, root.q, S.tmax, node_err(&S, 0), &lo, &hi, &elo, &ehi);
-        if (visit(&S, &root, lo, hi, elo, ehi, 0, 0.0, 1.0) && S.t < S.tmax) hit = 1;
+        S.cap0 = start_cap_normal(root.q);
+        S.cap1 = end_cap_normal(root.q);
+        int src;
+        cap_interval_src(root.o, root.q, S.tmax, node_err(&S, 0), 1, 1, &lo, &hi, &elo, &ehi, &src);
+        if (visit(&S, &root, lo, hi, elo, ehi, src, 0, 0.0, 1.0) && S.t < S.tmax) hit = 1;
     }
     if (!hit) { S.t = INFINITY; S.u = NAN; S.level = -1; }
     *t_out = S.t;
@@ -551,13 +626,23 @@ static int intersect_with_ties(const double ray[7], const double fiber[16], int 
         /* the node error model needs X, which the tie search sets up */
         *t_err = hit ? S.t_err : 0.0;
     }
+    if (normal_out) {
+        /* back to world space: n = n.x u + n.y v + n.z w */
+        for (int k = 0; k < 3; ++k) {
+            normal_out[k] = hit ? S.n[0] * frame[k] + S.n[1] * frame[3 + k] + S.n[2] * frame[6 + k] : NAN;
+            normal_out[3 + k] = hit ? S.n_alt[0] * frame[k] + S.n_alt[1] * frame[3 + k] +
+                                      S.n_alt[2] * frame[6 + k] : NAN;
+        }
+        normal_out[6] = hit ? S.n_err : NAN;
+        normal_out[7] = hit ? (double)S.entry : NAN;
+    }
     return hit;
 }
 
 int fo_intersect_d(const double ray[7], const double fiber[16], int depth,
                    double *t_out, double *u_out, int64_t stats[4])
 {
-    return intersect_with_ties(ray, fiber, depth, 0.0, 0, 0, NULL, t_out, u_out, stats, NULL);
+    return intersect_with_ties(ray, fiber, depth, 0.0, 0, 0, NULL, t_out, u_out, stats, NULL, NULL);
 }
 
 /* Every result reachable from one pair by flipping at most max_flips (1 or 2)
@@ -570,21 +655,21 @@ int fo_tie_outcomes(const double ray[7], const double fiber[16], int depth, doub
 {
     int n = 0, k0 = 0;
     double t, u;
-    int h = intersect_with_ties(ray, fiber, depth, scale, 0, 0, &k0, &t, &u, NULL, NULL);
+    int h = intersect_with_ties(ray, fiber, depth, scale, 0, 0, &k0, &t, &u, NULL, NULL, NULL);
     if (max_out < 1) return 0;
     t_out[n] = t; u_out[n] = u; hit_out[n] = h; n++;
     if (scale > 0.0 && n < max_out) {
-        h = intersect_with_ties(ray, fiber, depth, scale, 0, 1, NULL, &t, &u, NULL, NULL);
+        h = intersect_with_ties(ray, fiber, depth, scale, 0, 1, NULL, &t, &u, NULL, NULL, NULL);
         t_out[n] = t; u_out[n] = u; hit_out[n] = h; n++;
     }
     for (int j = 0; j < k0 && j < 64 && n < max_out; ++j) {
         int kj = 0;
-        h = intersect_with_ties(ray, fiber, depth, scale, 1ull << j, 0, &kj, &t, &u, NULL, NULL);
+        h = intersect_with_ties(ray, fiber, depth, scale, 1ull << j, 0, &kj, &t, &u, NULL, NULL, NULL);
         t_out[n] = t; u_out[n] = u; hit_out[n] = h; n++;
         if (max_flips < 2) continue;
         for (int k = j + 1; k < kj && k < 64 && n < max_out; ++k) {
             h = intersect_with_ties(ray, fiber, depth, scale, (1ull << j) | (1ull << k), 0, NULL,
-                                    &t, &u, NULL, NULL);
+                                    &t, &u, NULL, NULL, NULL);
             t_out[n] = t; u_out[n] = u; hit_out[n] = h; n++;
         }
     }
@@ -598,14 +683,19 @@ int fo_tie_outcomes(const double ray[7], const double fiber[16], int depth, doub
  * radius_scale (silhouette-band probes). stats_out (may be NULL) holds 4
  * int32 per pair; terr_out (may be NULL) the error bound of each hit's t in
  * an FP32 evaluation (the entry's bound from the tie model, R14; 0 on a
- * miss). Pairs whose indices fall outside [0, n_rays) or [0, n_fibers) are
+ * miss); normal_out (may be NULL) 8 per pair: the unit normal at the hit in
+ * world space (R9), the normal of the other entry where the cap and side
+ * entries tie (else the same), the angle bound in radians of the normal in
+ * an FP32 evaluation, and how the leaf was entered (0 through its cylinder's
+ * side, 1 the curve's start cap plane, 2 its end cap plane, 3 an inner
+ * plane, 4 at the origin); NaN on a miss. Pairs whose indices fall outside [0, n_rays) or [0, n_fibers) are
  * misses. */
 void fo_batch_d(const float *rays, int64_t ray_stride, int64_t n_rays,
                 const float *fibers, int64_t fiber_stride, int64_t n_fibers,
                 const int32_t *pair_ray, const int32_t *pair_fiber,
                 const uint8_t *pair_depth, int depth, int64_t n,
                 double radius_scale, double *t_out, double *u_out,
-                uint8_t *hit_out, int32_t *stats_out, int nthreads, double *terr_out)
+                uint8_t *hit_out, int32_t *stats_out, int nthreads, double *terr_out, double *normal_out)
 {
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -622,7 +712,10 @@ void fo_batch_d(const float *rays, int64_t ray_stride, int64_t n_rays,
             for (int r = 0; r < 7; ++r) ray[r] = rays[r * ray_stride + ri];
             for (int r = 0; r < 16; ++r) fib[r] = fibers[r * fiber_stride + fi];
             for (int k = 0; k < 4; ++k) fib[4 * k + 3] *= radius_scale;
-            hit = intersect_with_ties(ray, fib, d, 0.0, 0, 0, NULL, &t, &u, st, &te);
+            hit = intersect_with_ties(ray, fib, d, 0.0, 0, 0, NULL, &t, &u, st, &te,
+                                      normal_out ? normal_out + 8 * i : NULL);
+        } else if (normal_out) {
+            for (int k = 0; k < 8; ++k) normal_out[8 * i + k] = NAN;
         }
         if (terr_out) terr_out[i] = te;
         t_out[i] = t;
@@ -695,7 +788,7 @@ void fo_cap_interval(const double q[16], double tmax, double out[2])
 int fo_ray_frame(const double ray[7], const double fiber[16], double out[16])
 {
     v4 q[4];
-    if (!ray_frame(ray, ray + 3, fiber, q, NULL)) return 0;
+    if (!ray_frame(ray, ray + 3, fiber, q, NULL, NULL)) return 0;
     for (int k = 0; k < 4; ++k) {
         out[4 * k] = q[k].x; out[4 * k + 1] = q[k].y; out[4 * k + 2] = q[k].z; out[4 * k + 3] = q[k].w;
     }

@@ -34,8 +34,8 @@ MUTANTS = [
     ("chord instead of tangent as split normal", D, "v4 t = sub4(add4(q[2], q[3]), add4(q[0], q[1]));",
      "v4 t = sub4(q[3], q[0]);"),
     ("no interval recomputation after backtracking", D,
-     "return visit(S, second, blo, bhi, eblo, ebhi, level + 1, s0, s1);",
-     "return visit(S, second, lo, hi, elo, ehi, level + 1, s0, s1);"),
+     "return visit(S, second, blo, bhi, eblo, ebhi, bsrc, level + 1, s0, s1);",
+     "return visit(S, second, lo, hi, elo, ehi, lsrc, level + 1, s0, s1);"),
     ("tangents negligible only when exactly zero", D, "return dot3(v, v) <= 0x1p-40 * dot3(chord, chord);",
      "return zero3(v);"),
     ("grazing ties never decided together", D, "return S->ties.force_vis > 0;", "return value;"),
@@ -48,10 +48,25 @@ MUTANTS = [
      "if (!negligible(sub4(l[3], l[2]), sub4(q[3], q[0]))) return;", "return;"),
     ("tie margin 2^10 too wide", D, "return (2.0 + 2.0 * level) * 0x1p-24 * S->ties.X;",
      "return (2.0 + 2.0 * level) * 0x1p-14 * S->ties.X;"),
+    ("start cap normal pointing inwards", D,
+     "const v4 cap = lsrc == LO_START_CAP ? scale4(S->cap0, -1.0) : S->cap1;",
+     "const v4 cap = lsrc == LO_START_CAP ? S->cap0 : S->cap1;"),
+    ("side normal from the leaf's start point", D,
+     "add4(N->q[0], scale4(a, ul)));", "N->q[0]);"),
+    ("cap entries given the side normal", D, "const int on_side = te >= lo || !capped;",
+     "const int on_side = 1;"),
+    ("backtracked nodes never at the curve's ends", D, "s0 == 0.0, s1 == 1.0,", "0, 0,"),
+    ("normal left in the ray frame", D,
+     "normal_out[k] = hit ? S.n[0] * frame[k] + S.n[1] * frame[3 + k] + S.n[2] * frame[6 + k] : NAN;",
+     "normal_out[k] = hit ? S.n[k] : NAN;"),
     ("exact oracle: radius term with the wrong sign", X, "F = badd(&F, &a3, -1.0);", "F = badd(&F, &a3, 1.0);"),
     ("exact oracle: no limit disc at a zero end tangent", X, "while (j < 2 && cand[j][0]", "while (0 && cand[j][0]"),
     ("exact oracle: edge-on rays through the expanded polynomial", X, "if (edge_on(c)) {", "if (0) {"),
     ("exact oracle: edge-on exit taken for the entry", X, "if (t) *t = C[2] + s * sr;", "if (t) *t = C[2] + sr;"),
+    ("exact oracle: taper tilt with the wrong sign", X, "const double beta = -D1[3] /",
+     "const double beta = D1[3] /"),
+    ("exact oracle: no curvature term in the tilt", X, "(dl - C[3] * ec2 / dl)", "(dl)"),
+    ("exact oracle: start cap normal pointing inwards", X, "(kind == 2 ? -1.0 : 1.0)", "(1.0)"),
     ("exact oracle: circle point on the wrong side", X,
      "tsq = fabs((tm - C[2]) * D[2] - xy) <= fabs((tp - C[2]) * D[2] - xy) ? tm : tp;",
      "tsq = fabs((tm - C[2]) * D[2] - xy) <= fabs((tp - C[2]) * D[2] - xy) ? tp : tm;"),
@@ -75,7 +90,8 @@ def _run_mutant(m, tmp):
     subprocess.run(oracle_build.gcc_cmd(srcs, lib), check=True, capture_output=True)
     env = dict(os.environ, FIBER_ORACLE_LIB=lib, OMP_NUM_THREADS="2")
     res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                          "tests/test_oracle_pins.py", "tests/test_oracle_exact.py"],
+                          "tests/test_oracle_pins.py", "tests/test_oracle_exact.py",
+                          "tests/test_oracle_normals.py"],
                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return name, res.returncode, res.stdout[-400:]
 
