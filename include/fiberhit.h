@@ -125,6 +125,10 @@ size_t fiber_pairs_workspace_bytes(int64_t n_pairs, int64_t n_fibers, int32_t ga
  *   t_out, u_out, hit_out          n_pairs each. On a miss: t = +inf, u = NaN, hit = 0.
  *   t64_out, u64_out               n_pairs doubles each; required with
  *                                  FI_FP64_REFINE, ignored (may be NULL) without.
+ *   normal_out                     3 * n_pairs floats (rows x, y, z, each of
+ *                                  n_pairs: normal_out[k * n_pairs + i]), or NULL
+ *                                  for none: the unit outward normal at each hit
+ *                                  in world space (see Normals); NaN on a miss.
  *   workspace, workspace_bytes     caller-owned device memory, 256-byte aligned,
  *                                  for the fiber records of a gathered call
  *                                  (size: fiber_pairs_workspace_bytes), or NULL
@@ -150,6 +154,21 @@ size_t fiber_pairs_workspace_bytes(int64_t n_pairs, int64_t n_fibers, int32_t ga
  * <= 16 keep the plain method's results; their t64/u64 are the float results
  * widened.
  *
+ * Normals (Appendix C, the final computation of an intersection; FP32 in the
+ * ray frame, turned back into world space with the ray's frame rebuilt in
+ * FP64): a hit that enters its leaf through the cylinder's side (or through
+ * an inner split plane) gets the direction from the leaf chord's point at the
+ * hit's projection to the hit point; a hit that enters through the curve's
+ * start (end) cap plane gets minus the start tangent (the end tangent), with
+ * the cap plane's fallbacks where that tangent vanishes. Which plane bounded
+ * the entry decides, not a clamped u. A refined pair (depth > 16 under
+ * FI_FP64_REFINE) gets the normal of the swept solid at its FP64 hit,
+ * computed in FP64: on the side the direction from C(u) to the hit, tilted
+ * against the tangent by the taper r'(u) (with the curvature term of the
+ * turning disc); at an end disc its outward normal; NaN with the origin
+ * inside (t = 0). The normal's rows are written only when normal_out is not
+ * NULL; the other results do not depend on it.
+ *
  * Errors: FI_ERR_NULL when rays, fibers or an output is NULL with n_pairs > 0
  * (t64_out/u64_out only with FI_FP64_REFINE); FI_ERR_RANGE for negative
  * counts, strides below the counts, a depth outside [0, 23], unknown flags,
@@ -165,7 +184,7 @@ int fiber_intersect_pairs(const float *rays, int64_t ray_stride, int64_t n_rays,
                           const uint8_t *pair_depth, int32_t depth, int64_t n_pairs,
                           uint32_t flags,
                           float *t_out, float *u_out, uint8_t *hit_out,
-                          double *t64_out, double *u64_out,
+                          double *t64_out, double *u64_out, float *normal_out,
                           void *workspace, size_t workspace_bytes, void *stream);
 
 /*
@@ -202,7 +221,7 @@ int fiber_intersect_pairs_noalloc(const float *rays, int64_t ray_stride, int64_t
                                   const uint8_t *pair_depth, int32_t depth, int64_t n_pairs,
                                   uint32_t flags,
                                   float *t_out, float *u_out, uint8_t *hit_out,
-                                  double *t64_out, double *u64_out,
+                                  double *t64_out, double *u64_out, float *normal_out,
                                   void *stream);
 
 /*
@@ -236,7 +255,7 @@ int fiber_intersect_counts(const float *rays, int64_t ray_stride, int64_t n_rays
 /* One problem: the arguments of one fiber_intersect_pairs call (the flags
  * are the batch's). All pointers are device pointers owned by the caller;
  * t64_out and u64_out are read only when the batch runs with
- * FI_FP64_REFINE. */
+ * FI_FP64_REFINE; normal_out may be NULL (no normals for that problem). */
 typedef struct fi_scene {
     const float *rays;   int64_t ray_stride;   int64_t n_rays;
     const float *fibers; int64_t fiber_stride; int64_t n_fibers;
@@ -244,6 +263,7 @@ typedef struct fi_scene {
     int32_t depth;       int64_t n_pairs;
     float *t_out; float *u_out; uint8_t *hit_out;
     double *t64_out; double *u64_out;
+    float *normal_out;
 } fi_scene;
 
 /* Launch tuning of the batched kernel (not part of the method):

@@ -83,8 +83,9 @@ def intersect_depth(rays, fibers, depth=9, pair_ray=None, pair_fiber=None,
     in world space (3), the normal of the other entry where a cap and a side
     entry tie (3, else the same), the angle bound in radians of the normal in
     an FP32 evaluation (1), how the leaf was entered (1: 0 through the
-    cylinder's side, 1 the curve's start cap plane, 2 its end cap plane, 3 an
-    inner plane, 4 at the origin); NaN on a miss."""
+    cylinder's side, 1 through a plane on the curve's start cap plane, 2 on
+    its end cap plane, 3 through another plane or at the origin); NaN on a
+    miss."""
     rays = np.ascontiguousarray(rays, dtype=np.float32)
     fibers = np.ascontiguousarray(fibers, dtype=np.float32)
     pr = None if pair_ray is None else np.ascontiguousarray(pair_ray, dtype=np.int32)

@@ -179,33 +179,15 @@ static double plane_err(double delta, v4 n, double t)
  * point o and the control points relative to it (see node_t). elo/ehi (may be
  * NULL) receive the error bounds of the two ends for node coordinates known
  * to +-delta (0 for the ends 0 and tmax). */
-/* Where the entry bound of an interval comes from (for the normal, R9): the
- * origin (t = 0), the curve's start or end cap, or an inner plane (a split
- * plane, or the cap plane of an inner node, which is a split plane). */
-enum { LO_ORIGIN = 0, LO_START_CAP = 1, LO_END_CAP = 2, LO_INNER = 3 };
-
-static void cap_interval_src(v4 o, const v4 q[4], double tmax, double delta, int at_start, int at_end,
-                             double *lo, double *hi, double *elo, double *ehi, int *src);
-
 static void cap_interval_e(v4 o, const v4 q[4], double tmax, double delta, double *lo, double *hi,
                            double *elo, double *ehi)
 {
-    cap_interval_src(o, q, tmax, delta, 0, 0, lo, hi, elo, ehi, NULL);
-}
-
-/* As cap_interval_e, for a node whose parameter interval starts at the
- * curve's start (at_start) and/or ends at its end (at_end); *src receives
- * the origin of the entry bound. */
-static void cap_interval_src(v4 o, const v4 q[4], double tmax, double delta, int at_start, int at_end,
-                             double *lo, double *hi, double *elo, double *ehi, int *src)
-{
     double l = 0.0, h = tmax, el = 0.0, eh = 0.0;
-    int ls = LO_ORIGIN;
     const v4 n0 = start_cap_normal(q);
     const double c0 = dot3(o, n0) + dot3(q[0], n0);       /* inside <=> t*n0.z >= c0 */
     if (n0.z != 0.0) {
         const double t = c0 / n0.z;
-        if (n0.z > 0.0 && t > l) { l = t; el = plane_err(delta, n0, t); ls = at_start ? LO_START_CAP : LO_INNER; }
+        if (n0.z > 0.0 && t > l) { l = t; el = plane_err(delta, n0, t); }
         if (n0.z < 0.0 && t < h) { h = t; eh = plane_err(delta, n0, t); }
     } else if (c0 > 0.0) {
         l = INFINITY; h = -INFINITY;
@@ -215,7 +197,7 @@ static void cap_interval_src(v4 o, const v4 q[4], double tmax, double delta, int
     if (n1.z != 0.0) {
         const double t = c1 / n1.z;
         if (n1.z > 0.0 && t < h) { h = t; eh = plane_err(delta, n1, t); }
-        if (n1.z < 0.0 && t > l) { l = t; el = plane_err(delta, n1, t); ls = at_end ? LO_END_CAP : LO_INNER; }
+        if (n1.z < 0.0 && t > l) { l = t; el = plane_err(delta, n1, t); }
     } else if (c1 < 0.0) {
         l = INFINITY; h = -INFINITY;
     }
@@ -223,7 +205,6 @@ static void cap_interval_src(v4 o, const v4 q[4], double tmax, double delta, int
     *hi = h;
     if (elo) *elo = el;
     if (ehi) *ehi = eh;
-    if (src) *src = ls;
 }
 
 /* Squared distance of point e (relative to the axis origin) to the line
@@ -401,10 +382,11 @@ typedef struct {
     int level;
     ties_t ties;
     v4 cap0, cap1;      /* the curve's start and end cap normals (ray frame, R13) */
+    v4 end0, end1;      /* the curve's end points p0, p3 (ray frame) */
     double n[3];        /* normal at the hit, ray frame (R9) */
     double n_alt[3];    /* the other normal where cap and side entry tie (else n) */
     double n_err;       /* angle bound (radians) of n in an FP32 evaluation */
-    int entry;          /* 0 cylinder side, else the LO_* source of the entry plane */
+    int entry;          /* 0 side, 1 start cap, 2 end cap, 3 another plane (split plane, origin) */
 } search_t;
 
 static double node_err(const search_t *S, int level)
@@ -454,14 +436,20 @@ static int decide_vis(search_t *S, int value, double diff, double margin)
     return decide(S, value, diff, margin);
 }
 
-/* Normal at a leaf hit (R9: the paper's listing "Calculate the normal and u
- * parameter", with its undefined names read as the leaf chord and the ray
- * direction): a hit on the leaf cylinder's side (t from the cylinder entry)
- * gets the direction from the chord point at the hit's projection to the hit
- * point; a hit through the curve's start or end cap plane gets that cap's
- * outward normal (minus the start tangent, the end tangent; their R13 limits
- * where they vanish). An entry through an inner plane, or at the origin,
- * keeps the radial direction. */
+/* Normal at a leaf hit (R9; the paper's final computation of an
+ * intersection, with its undefined names read as the leaf chord and the ray
+ * direction). A hit through the leaf cylinder's side gets the direction from
+ * the chord point at the hit's projection to the hit point. A hit through a
+ * plane (the interval's start: a cap or split plane, or the origin) that
+ * lies on the curve's start or end cap plane -- within (8 + 2 level) 2^-24 X
+ * (the node error bound of the leaf's level plus the rounding of the test
+ * itself in FP32), measured along the plane's unit normal -- gets
+ * that cap's outward normal (minus the start tangent, the end tangent; their
+ * R13 limits where they vanish); other plane entries keep the radial
+ * direction. The tolerance makes the rule independent of which of the
+ * first leaves an FP32 evaluation enters: at depth 22 a leaf is shorter than
+ * that error, and an empty-looking first leaf hands the hit to the next one
+ * through their common split plane. */
 static void unit3(v4 n, double out[3])
 {
     const double len = sqrt(dot3(n, n));
@@ -470,31 +458,43 @@ static void unit3(v4 n, double out[3])
     out[2] = n.z / len;
 }
 
+/* distance of the ray point at t to the plane through e with normal n */
+static double plane_dist(double t, v4 e, v4 n)
+{
+    return fabs(t * n.z - dot3(e, n)) / sqrt(dot3(n, n));
+}
+
 /* te, lo: the cylinder entry and the interval's start, with error bounds ec
- * and elo (R14); delta the node's coordinate error. Where te and lo are
- * within those bounds of each other an FP32 evaluation may take either
- * entry, so both normals are recorded. The angle bound of the side normal is
- * the hit point's and the chord point's error over the normal's length; a
- * cap normal comes from the root's tangent, exact up to rounding. */
+ * and elo (R14); delta the leaf's coordinate error. The side or plane entry
+ * may go either way where te and lo are within those bounds of each other,
+ * and the cap test where the distance is within a factor 2 of its tolerance: the
+ * other normal is recorded for those ties. The angle bound of the side
+ * normal is the hit point's and the chord point's error over the normal's
+ * length; a cap normal comes from the root's tangent, exact up to rounding. */
 static void leaf_normal(search_t *S, const node_t *N, v4 a, double t, double ul, double te,
-                        double lo, double ec, double elo, double delta, int lsrc)
+                        double lo, double ec, double elo, double delta)
 {
     const v4 ap = add4(mk4(N->o.x, N->o.y, N->o.z, 0.0), add4(N->q[0], scale4(a, ul)));
     const v4 side = mk4(-ap.x, -ap.y, t - ap.z, 0.0);
-    const int capped = lsrc == LO_START_CAP || lsrc == LO_END_CAP;
-    const v4 cap = lsrc == LO_START_CAP ? scale4(S->cap0, -1.0) : S->cap1;
-    const int on_side = te >= lo || !capped;
-    S->entry = te >= lo ? 0 : (lsrc == LO_ORIGIN ? 4 : lsrc);
-    unit3(on_side ? side : cap, S->n);
-    const int tie = capped && fabs(te - lo) <= ec + elo;
-    unit3(tie ? (on_side ? cap : side) : (on_side ? side : cap), S->n_alt);
+    const double tol = delta + 6.0 * 0x1p-24 * S->ties.X;
+    const double d0 = plane_dist(t, S->end0, S->cap0) / tol;
+    const double d1 = plane_dist(t, S->end1, S->cap1) / tol;
+    const int near1 = d1 < d0;
+    const double dc = near1 ? d1 : d0;
+    const v4 cap = near1 ? S->cap1 : scale4(S->cap0, -1.0);
+    const int plane = te < lo;
+    const int on_cap = plane && dc <= 1.0;
+    S->entry = !plane ? 0 : (on_cap ? 1 + near1 : 3);
+    unit3(on_cap ? cap : side, S->n);
+    const int tie = (fabs(te - lo) <= ec + elo && dc <= 2.0) || (plane && dc > 0.5 && dc < 2.0);
+    unit3(tie ? (on_cap ? side : cap) : (on_cap ? cap : side), S->n_alt);
     const double ns = sqrt(dot3(side, side));
     const double e_side = 2.0 * (S->t_err + 3.0 * delta) / ns + 0x1p-20;
-    S->n_err = on_side ? e_side : (tie ? fmax(e_side, 0x1p-20) : 0x1p-20);
+    S->n_err = !on_cap ? e_side : (tie ? fmax(e_side, 0x1p-20) : 0x1p-20);
 }
 
 static int visit(search_t *S, const node_t *N, double lo, double hi, double elo, double ehi,
-                 int lsrc, int level, double u0, double u1)
+                 int level, double u0, double u1)
 {
     S->tests++;
     const v4 *q = N->q;
@@ -530,7 +530,7 @@ static int visit(search_t *S, const node_t *N, double lo, double hi, double elo,
         S->t_err = e_enter;
         S->u = u0 + ul * (u1 - u0);
         S->level = level;
-        leaf_normal(S, N, a, t, ul, te, lo, ec, elo, delta, lsrc);
+        leaf_normal(S, N, a, t, ul, te, lo, ec, elo, delta);
         return 1;
     }
 
@@ -541,7 +541,6 @@ static int visit(search_t *S, const node_t *N, double lo, double hi, double elo,
     const double c = dot3(N->o, n) + dot3(Lc.q[3], n);    /* <split point, n> */
     int go_right, both;
     double flo = lo, fhi = hi, eflo = elo, efhi = ehi;
-    int flsrc = lsrc;
     if (n.z != 0.0) {
         const double tp = c / n.z;
         const double ep = plane_err(delta, n, tp);
@@ -556,7 +555,7 @@ static int visit(search_t *S, const node_t *N, double lo, double hi, double elo,
         go_right = beyond_entry != (n.z > 0.0);
         both = beyond_entry && before_exit;
         if (beyond_entry) { if (tpn < fhi) { fhi = tpn; efhi = ep; } }
-        else              { if (tpn > flo) { flo = tpn; eflo = ep; flsrc = LO_INNER; } }
+        else              { if (tpn > flo) { flo = tpn; eflo = ep; } }
     } else {
         const double side = -c;            /* <(0,0,t) - s, n> for every t */
         go_right = side > 0.0;
@@ -568,14 +567,12 @@ static int visit(search_t *S, const node_t *N, double lo, double hi, double elo,
     const double f0 = go_right ? um : u0, f1 = go_right ? u1 : um;
     const double s0 = go_right ? u0 : um, s1 = go_right ? um : u1;
 
-    if (visit(S, first, flo, fhi, eflo, efhi, flsrc, level + 1, f0, f1)) return 1;
+    if (visit(S, first, flo, fhi, eflo, efhi, level + 1, f0, f1)) return 1;
     if (!both) return 0;
     S->backtracks++;
     double blo, bhi, eblo, ebhi;
-    int bsrc;
-    cap_interval_src(second->o, second->q, S->tmax, node_err(S, level + 1), s0 == 0.0, s1 == 1.0,
-                     &blo, &bhi, &eblo, &ebhi, &bsrc);
-    return visit(S, second, blo, bhi, eblo, ebhi, bsrc, level + 1, s0, s1);
+    cap_interval_e(second->o, second->q, S->tmax, node_err(S, level + 1), &blo, &bhi, &eblo, &ebhi);
+    return visit(S, second, blo, bhi, eblo, ebhi, level + 1, s0, s1);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -611,9 +608,10 @@ static int intersect_with_ties(const double ray[7], const double fiber[16], int 
         const node_t root = anchored(q);
         S.cap0 = start_cap_normal(root.q);
         S.cap1 = end_cap_normal(root.q);
-        int src;
-        cap_interval_src(root.o, root.q, S.tmax, node_err(&S, 0), 1, 1, &lo, &hi, &elo, &ehi, &src);
-        if (visit(&S, &root, lo, hi, elo, ehi, src, 0, 0.0, 1.0) && S.t < S.tmax) hit = 1;
+        S.end0 = q[0];
+        S.end1 = q[3];
+        cap_interval_e(root.o, root.q, S.tmax, node_err(&S, 0), &lo, &hi, &elo, &ehi);
+        if (visit(&S, &root, lo, hi, elo, ehi, 0, 0.0, 1.0) && S.t < S.tmax) hit = 1;
     }
     if (!hit) { S.t = INFINITY; S.u = NAN; S.level = -1; }
     *t_out = S.t;
@@ -687,8 +685,8 @@ int fo_tie_outcomes(const double ray[7], const double fiber[16], int depth, doub
  * world space (R9), the normal of the other entry where the cap and side
  * entries tie (else the same), the angle bound in radians of the normal in
  * an FP32 evaluation, and how the leaf was entered (0 through its cylinder's
- * side, 1 the curve's start cap plane, 2 its end cap plane, 3 an inner
- * plane, 4 at the origin); NaN on a miss. Pairs whose indices fall outside [0, n_rays) or [0, n_fibers) are
+ * side, 1 through a plane on the curve's start cap plane, 2 on its end cap
+ * plane, 3 through another plane or at the origin); NaN on a miss. Pairs whose indices fall outside [0, n_rays) or [0, n_fibers) are
  * misses. */
 void fo_batch_d(const float *rays, int64_t ray_stride, int64_t n_rays,
                 const float *fibers, int64_t fiber_stride, int64_t n_fibers,

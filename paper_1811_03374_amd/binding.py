@@ -36,9 +36,9 @@ def lib():
         L = C.CDLL(build_lib.LIB)
         i64, vp, u32, i32 = C.c_int64, C.c_void_p, C.c_uint32, C.c_int32
         common = [vp, i64, i64, vp, i64, i64, vp, vp, vp, i32, i64, u32, vp, vp, vp]
-        L.fiber_intersect_pairs.argtypes = common + [vp, vp, vp, C.c_size_t, vp]
+        L.fiber_intersect_pairs.argtypes = common + [vp, vp, vp, vp, C.c_size_t, vp]
         L.fiber_intersect_pairs.restype = C.c_int
-        L.fiber_intersect_pairs_noalloc.argtypes = common + [vp, vp, vp]
+        L.fiber_intersect_pairs_noalloc.argtypes = common + [vp, vp, vp, vp]
         L.fiber_intersect_pairs_noalloc.restype = C.c_int
         L.fiber_intersect_counts.argtypes = common + [vp, vp, C.c_size_t, vp]
         L.fiber_intersect_counts.restype = C.c_int
@@ -148,21 +148,35 @@ def _ws_args(ws: Optional[torch.Tensor]):
     return (None, 0) if ws is None else (C.c_void_p(ws.data_ptr()), ws.numel())
 
 
+def _normal_tensor(normal, n, dev):
+    """The (3, n) float32 normal rows: None for none, True to allocate, or a
+    caller's tensor (checked)."""
+    if normal is None or normal is False:
+        return None
+    if normal is True:
+        return torch.empty((3, n), dtype=torch.float32, device=dev)
+    if (normal.dtype != torch.float32 or not normal.is_cuda or not normal.is_contiguous()
+            or normal.dim() != 2 or normal.shape[0] != 3 or normal.shape[1] != n):
+        raise ValueError(f"normal must be a contiguous (3, {n}) float32 device tensor")
+    return normal
+
+
 def intersect_pairs(rays: torch.Tensor, fibers: torch.Tensor, depth: int = 9,
                     pair_ray: Optional[torch.Tensor] = None,
                     pair_fiber: Optional[torch.Tensor] = None,
                     pair_depth: Optional[torch.Tensor] = None,
                     out=None, counts: bool = False, refine: bool = False, stream=None,
-                    workspace: Optional[torch.Tensor] = None):
+                    workspace: Optional[torch.Tensor] = None, normal=None):
     """Nearest hit (t, u, hit) of every (ray, fiber) pair at subdivision depth
     ``depth`` (or per-pair ``pair_depth``). See ``fiber_intersect_pairs``.
 
     rays: (7, n_rays) float32; fibers: (16, n_fibers) float32; indices int32.
     Returns (t, u, hit) device tensors, plus an (n, 4) int32 tensor of node
     tests / splits / backtracks / leaf level when ``counts`` is set, or the
-    float64 (t64, u64) of the FP64 surface refinement when ``refine`` is set.
-    ``workspace`` (uint8 device tensor, see ``pairs_workspace``) is allocated
-    per call when not given and the call gathers fibers."""
+    float64 (t64, u64) of the FP64 surface refinement when ``refine`` is set,
+    then the (3, n) float32 normals when ``normal`` is True (or a tensor to
+    fill). ``workspace`` (uint8 device tensor, see ``pairs_workspace``) is
+    allocated per call when not given and the call gathers fibers."""
     rs = _table(rays, 7, "rays")
     fs = _table(fibers, 16, "fibers")
     pr = _index(pair_ray, torch.int32, "pair_ray")
@@ -173,6 +187,9 @@ def intersect_pairs(rays: torch.Tensor, fibers: torch.Tensor, depth: int = 9,
     t, u, hit = _outs(out, n, dev)
     if counts and refine:
         raise ValueError("counts and refine are separate passes")
+    if counts and normal not in (None, False):
+        raise ValueError("counts and normals are separate passes")
+    nrm = _normal_tensor(normal, n, dev)
     if workspace is None:
         workspace = pairs_workspace(n, fibers.shape[1], pf is not None, dev)
         _keep_for(workspace, stream)
@@ -187,24 +204,26 @@ def intersect_pairs(rays: torch.Tensor, fibers: torch.Tensor, depth: int = 9,
     if counts:
         _check(lib().fiber_intersect_counts(*args, _ptr(cn), *ws, _stream(stream)))
         return t, u, hit, cn
+    extra = (nrm,) if nrm is not None else ()
     if refine:
         t64 = torch.empty(n, dtype=torch.float64, device=dev)
         u64 = torch.empty(n, dtype=torch.float64, device=dev)
-        _check(lib().fiber_intersect_pairs(*args, _ptr(t64), _ptr(u64), *ws, _stream(stream)))
-        return t, u, hit, t64, u64
-    _check(lib().fiber_intersect_pairs(*args, None, None, *ws, _stream(stream)))
-    return t, u, hit
+        _check(lib().fiber_intersect_pairs(*args, _ptr(t64), _ptr(u64), _ptr(nrm), *ws, _stream(stream)))
+        return (t, u, hit, t64, u64) + extra
+    _check(lib().fiber_intersect_pairs(*args, None, None, _ptr(nrm), *ws, _stream(stream)))
+    return (t, u, hit) + extra
 
 
 def intersect_pairs_noalloc(rays: torch.Tensor, fibers: torch.Tensor, depth: int = 9,
                             pair_ray: Optional[torch.Tensor] = None,
                             pair_fiber: Optional[torch.Tensor] = None,
                             pair_depth: Optional[torch.Tensor] = None,
-                            out=None, refine: bool = False, stream=None):
+                            out=None, refine: bool = False, stream=None, normal=None):
     """``intersect_pairs`` through ``fiber_intersect_pairs_noalloc``: no
-    workspace (the library's fixed per-device array holds the root slots).
-    With ``out`` (and, under ``refine``, ``out`` holding five tensors) the
-    call allocates nothing. Calls on one device must not overlap."""
+    workspace (the library's fixed per-device array holds the fiber records
+    of gathered calls). With ``out`` (and, under ``refine``, ``out`` holding
+    five tensors; ``normal`` a tensor when normals are asked for) the call
+    allocates nothing. Calls on one device must not overlap."""
     rs = _table(rays, 7, "rays")
     fs = _table(fibers, 16, "fibers")
     pr = _index(pair_ray, torch.int32, "pair_ray")
@@ -226,11 +245,13 @@ def intersect_pairs_noalloc(rays: torch.Tensor, fibers: torch.Tensor, depth: int
             t64 = torch.empty(n, dtype=torch.float64, device=dev)
             u64 = torch.empty(n, dtype=torch.float64, device=dev)
     t, u, hit = _outs(out, n, dev)
+    nrm = _normal_tensor(normal, n, dev)
     _check(lib().fiber_intersect_pairs_noalloc(
         _ptr(rays), rs, rays.shape[1], _ptr(fibers), fs, fibers.shape[1], _ptr(pr), _ptr(pf), _ptr(pd),
         int(depth), n, FI_FP64_REFINE if refine else 0, _ptr(t), _ptr(u), _ptr(hit), _ptr(t64), _ptr(u64),
-        _stream(stream)))
-    return (t, u, hit, t64, u64) if refine else (t, u, hit)
+        _ptr(nrm), _stream(stream)))
+    extra = (nrm,) if nrm is not None else ()
+    return ((t, u, hit, t64, u64) if refine else (t, u, hit)) + extra
 
 
 class PreparedPairs:
@@ -256,7 +277,7 @@ class PreparedPairs:
         self._fn = lib().fiber_intersect_pairs
         self._args = (_ptr(rays), rs, rays.shape[1], _ptr(fibers), fs, fibers.shape[1],
                       _ptr(pr), _ptr(pf), _ptr(pd), int(depth), n, 0,
-                      _ptr(self.t), _ptr(self.u), _ptr(self.hit), None, None,
+                      _ptr(self.t), _ptr(self.u), _ptr(self.hit), None, None, None,
                       *_ws_args(self.workspace))
 
     def launch(self, stream=None):
@@ -279,7 +300,7 @@ class FiScene(C.Structure):
                 ("pair_ray", C.c_void_p), ("pair_fiber", C.c_void_p), ("pair_depth", C.c_void_p),
                 ("depth", C.c_int32), ("n_pairs", C.c_int64),
                 ("t_out", C.c_void_p), ("u_out", C.c_void_p), ("hit_out", C.c_void_p),
-                ("t64_out", C.c_void_p), ("u64_out", C.c_void_p)]
+                ("t64_out", C.c_void_p), ("u64_out", C.c_void_p), ("normal_out", C.c_void_p)]
 
 
 class FiTuning(C.Structure):
@@ -319,7 +340,7 @@ class Problem:
     with its own outputs (allocated here; t64/u64 too when ``refine``)."""
 
     def __init__(self, rays, fibers, depth=9, pair_ray=None, pair_fiber=None, pair_depth=None,
-                 refine=False):
+                 refine=False, normal=False):
         _table(rays, 7, "rays")
         _table(fibers, 16, "fibers")
         self.rays, self.fibers = rays, fibers
@@ -335,6 +356,7 @@ class Problem:
         self.hit = torch.empty(n, dtype=torch.uint8, device=dev)
         self.t64 = torch.empty(n, dtype=torch.float64, device=dev) if refine else None
         self.u64 = torch.empty(n, dtype=torch.float64, device=dev) if refine else None
+        self.normal = torch.empty((3, n), dtype=torch.float32, device=dev) if normal else None
 
     def scene(self):
         rs = _table(self.rays, 7, "rays")
@@ -346,7 +368,8 @@ class Problem:
                        None if self.pair_depth is None else self.pair_depth.data_ptr(),
                        self.depth, self.n, self.t.data_ptr(), self.u.data_ptr(), self.hit.data_ptr(),
                        None if self.t64 is None else self.t64.data_ptr(),
-                       None if self.u64 is None else self.u64.data_ptr())
+                       None if self.u64 is None else self.u64.data_ptr(),
+                       None if self.normal is None else self.normal.data_ptr())
 
 
 def _batch_flags(problems, refine):

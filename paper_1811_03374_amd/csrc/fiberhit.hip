@@ -257,6 +257,7 @@ struct Args {
     float *t_out; float *u_out; uint8_t *hit_out;
     int32_t *counts;                       // counting mode
     double *t64_out; double *u64_out;      // refinement
+    float *normal_out;                     // normals (3 rows of n_pairs), or null
 };
 
 // ---------------------------------------------------------------------------
@@ -292,7 +293,7 @@ struct Curve64 {
 };
 
 __device__ __forceinline__ bool curve_in_ray_frame(const float *R, int64_t rs, const float *F,
-                                                   int64_t fs, Curve64 &c)
+                                                   int64_t fs, Curve64 &c, double *frame = nullptr)
 {
     const double ox = R[0], oy = R[rs], oz = R[2 * rs];
     const double dx = R[3 * rs], dy = R[4 * rs], dz = R[5 * rs];
@@ -302,6 +303,10 @@ __device__ __forceinline__ bool curve_in_ray_frame(const float *R, int64_t rs, c
     const double w[3] = {dx * il, dy * il, dz * il};
     double u[3], v[3];
     make_onb(w[0], w[1], w[2], u, v);
+    if (frame) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { frame[k] = u[k]; frame[3 + k] = v[k]; frame[6 + k] = w[k]; }
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const double ex = (double)F[(4 * k) * fs] - ox;
@@ -636,7 +641,6 @@ struct Lane {
     float slack;                  // conservative mode: bound on across-ray rounding of any node
                                   // (negative: a pair of depth <= 16, searched by the plain rules)
     int32_t trips, splits, backtracks;
-    double t64, u64;              // refined hit
     float u;                      // u of a leaf hit
     int32_t level;                // level of a leaf hit
 };
@@ -647,21 +651,6 @@ enum { kGoOn = 0, kHit = 1, kMiss = 2 };
 // every pruning test is enlarged by a bound on its FP32 rounding error, so no
 // surface point within that error is pruned; FP64 then decides).
 enum { kPlain = 0, kCount = 1, kConservative = 2 };
-
-// Output arrays of one problem (what the kernels write).
-struct Outs {
-    float *t;
-    float *u;
-    uint8_t *hit;
-    int32_t *counts;
-    double *t64;
-    double *u64;
-};
-
-__host__ __device__ __forceinline__ Outs outs_of(const Args &a)
-{
-    return Outs{a.t_out, a.u_out, a.hit_out, a.counts, a.t64_out, a.u64_out};
-}
 
 // Per-lane LDS column (conflict-free: lane-contiguous rows of 64 floats) that
 // caches the parent of the most recent split that left a sibling pending, so
@@ -748,23 +737,76 @@ __device__ __forceinline__ float leaf_u(const Lane &L)
 // or to the kernel's arguments would keep them in scratch memory for the
 // whole kernel (the call is not inlined), every trip included.
 struct Refined {
-    double t, u;
-    bool hit;
+    double t = INFINITY, u = __builtin_nan("");
+    bool hit = false;
+    float nx = __builtin_nanf(""), ny = __builtin_nanf(""), nz = __builtin_nanf("");   // world space
 };
+
+// Outward unit normal of the swept solid at a refined hit (ray frame):
+// at an end disc (u = 0 or 1) minus the start tangent or the end tangent
+// (their limits where they vanish); on the side, where the surface is
+// C(u) + r(u) e with e a unit vector normal to C'(u), the unit direction e
+// from C(u) to the hit, tilted against the tangent T by the taper:
+// e - r' / (|C'| - r <e, C''> / |C'|) T (the disc's normal plane turns with
+// the curve, hence the curvature term). In the units of eval_curve (D = C'/3
+// with r'/3, E = C''/6) the tilt is 3 D_r / (3 |D| - 2 r <e, E> / |D|). The
+// origin inside the solid (t = 0) has no surface crossing: NaN.
+__device__ __forceinline__ void solid_normal(const Curve64 &c, double t, double u, double n[3])
+{
+    double C[4], D[4], E[3];
+    eval_curve(c, u, C, D, E);
+    if (t == 0.0) {
+        n[0] = n[1] = n[2] = __builtin_nan("");
+        return;
+    }
+    if (u == 0.0 || u == 1.0) {
+        end_disc_normal(c, u, D);
+        const double s = (u == 0.0 ? -1.0 : 1.0) * rsqrt64(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+        n[0] = s * D[0];
+        n[1] = s * D[1];
+        n[2] = s * D[2];
+        return;
+    }
+    double ex = -C[0], ey = -C[1], ez = t - C[2];
+    const double ie = rsqrt64(ex * ex + ey * ey + ez * ez);
+    ex *= ie; ey *= ie; ez *= ie;
+    const double dl = sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+    const double tilt = -3.0 * D[3] / (3.0 * dl - 2.0 * C[3] * (ex * E[0] + ey * E[1] + ez * E[2]) / dl);
+    n[0] = ex + tilt * D[0] / dl;
+    n[1] = ey + tilt * D[1] / dl;
+    n[2] = ez + tilt * D[2] / dl;
+}
 
 __device__ __noinline__ Refined refine_whole_curve(const float *rays, int64_t ray_stride, const float *fibers,
                                                    int64_t fiber_stride, const int32_t *pair_ray,
                                                    const int32_t *pair_fiber, int64_t i, float tmax, float t0,
-                                                   float u0)
+                                                   float u0, bool normal)
 {
-    Refined r{INFINITY, __builtin_nan(""), false};
+    Refined r;
     const int64_t ri = pair_ray ? (int64_t)pair_ray[i] : i;
     const int64_t fi = pair_fiber ? (int64_t)pair_fiber[i] : i;
     Curve64 cv;
-    if (!curve_in_ray_frame(rays + ri, ray_stride, fibers + fi, fiber_stride, cv)) return r;
+    double frame[9];
+    if (!curve_in_ray_frame(rays + ri, ray_stride, fibers + fi, fiber_stride, cv, frame)) return r;
     double t = INFINITY, u = __builtin_nan("");
     leaf_candidates<kCurveSamples>(cv, 0.0, 1.0, 0.0, (double)tmax, (double)tmax, (double)t0, (double)u0, t, u);
-    if (t < INFINITY) r = Refined{t, u, true};
+    if (t < INFINITY) {
+        r.t = t;
+        r.u = u;
+        r.hit = true;
+        if (normal) {
+            double n[3];
+            solid_normal(cv, t, u, n);
+            // back to world space: n.x u + n.y v + n.z w, unit length
+            const double wx = n[0] * frame[0] + n[1] * frame[3] + n[2] * frame[6];
+            const double wy = n[0] * frame[1] + n[1] * frame[4] + n[2] * frame[7];
+            const double wz = n[0] * frame[2] + n[1] * frame[5] + n[2] * frame[8];
+            const double il = rsqrt64(wx * wx + wy * wy + wz * wz);
+            r.nx = (float)(wx * il);
+            r.ny = (float)(wy * il);
+            r.nz = (float)(wz * il);
+        }
+    }
     return r;
 }
 
@@ -828,7 +870,6 @@ __device__ __forceinline__ void descend_state(Lane &L, const Split &sp)
         if (kParentCache) L.cached = L.size;
     }
     if (sp.near_right) L.start ^= L.size;
-    L.splits++;
 }
 
 // Where a backtrack that misses the parent cache finds its pair's root: in
@@ -839,8 +880,29 @@ struct RegRoot {
     __device__ __forceinline__ void get(const Lane &L, Node &n) const { n = L.root; }
 };
 
+// What the normal of a leaf hit needs from the leaf, taken before the trip
+// moves on to a child: the ray-frame vector from the leaf chord's point at
+// the hit's projection to the hit point, and whether the hit entered the
+// leaf through a plane (the interval's start) rather than the cylinder's
+// side.
+struct HitGeo {
+    float vx, vy, vz;
+    bool plane;
+};
+
+__device__ __forceinline__ HitGeo hit_geo(const Node &c, float t, bool plane)
+{
+    const float cc = dot3(c.d.x, c.d.y, c.d.z, c.d.x, c.d.y, c.d.z);
+    float ul = 0.0f;
+    if (cc > 0.0f) {
+        ul = dot3(-c.p.x, -c.p.y, t - c.p.z, c.d.x, c.d.y, c.d.z) * rcp(cc);
+        ul = fminf(1.0f, fmaxf(0.0f, ul));
+    }
+    return HitGeo{-fmaf(ul, c.d.x, c.p.x), -fmaf(ul, c.d.y, c.p.y), t - fmaf(ul, c.d.z, c.p.z), plane};
+}
+
 template <int MODE, class Root>
-__device__ __forceinline__ int trip(Lane &L, const Root &root, float *col)
+__device__ __forceinline__ int trip(Lane &L, const Root &root, float *col, HitGeo &hg)
 {
     float te, tx, lo, hi;
     bool vis = node_visible<MODE>(L.c, L.lo, L.hi, L.slack, te, tx, lo, hi);
@@ -863,6 +925,7 @@ __device__ __forceinline__ int trip(Lane &L, const Root &root, float *col)
     int st = kGoOn;
     if (vis && leaf) {
         L.t = fmaxf(te, lo);
+        hg = hit_geo(L.c, L.t, te < lo);
         L.u = leaf_u(L);
         L.level = 23 - (31 - __builtin_clz(L.size));
         st = kHit;
@@ -902,26 +965,95 @@ __device__ __forceinline__ int trip(Lane &L, const Root &root, float *col)
     take_child(L.c, sp.dp, sp.tc, right);
     if (back) {
         cap_interval(L.c, L.tmax, L.lo, L.hi);
-        L.backtracks++;
     } else if (descend) {
         descend_state(L, sp);
     }
+    // work counters (counting variant only), branch-free
+    if (MODE == kCount) {
+        L.splits += descend ? 1 : 0;
+        L.backtracks += back ? 1 : 0;
+    }
     return st;
+}
+
+// Normal at a leaf hit (Appendix C, the final computation of an
+// intersection). A hit through the leaf cylinder's side gets the direction
+// from the leaf chord's point at the hit's projection to the hit point. A hit
+// through a plane (the start of the leaf's interval) whose point lies on the
+// curve's start or end cap plane -- within (8 + 2 level) 2^-24 X, the node
+// error bound of the leaf's level plus this test's own rounding, X the
+// largest ray-frame coordinate of the control points -- gets that cap's
+// outward normal: minus the start tangent, the end tangent, with the cap
+// planes' fallbacks where a tangent vanishes (the nearer plane when both
+// qualify). Other plane entries keep the radial direction. At depth 22 a
+// leaf is shorter than FP32 resolves along the ray, so the first leaf can
+// look empty and hand its hit to the next one through their common split
+// plane: the tolerance keeps such hits on the cap. The vector is formed in
+// the ray frame and turned back into world space with the frame of the
+// pair's ray (rebuilt in FP64, as for the projection).
+__device__ __forceinline__ void leaf_normal(const Args &a, int64_t i, const Lane &L, const HitGeo &hg, float &nx,
+                                            float &ny, float &nz)
+{
+    float vx = hg.vx, vy = hg.vy, vz = hg.vz;
+    if (hg.plane) {
+        const Node &r = L.root;
+        const float cc = dot3(r.d.x, r.d.y, r.d.z, r.d.x, r.d.y, r.d.z);
+        // cap normals: p1 - p0, else p2 - p0, else p3 - p0; p3 - p2, else p3 - p1, else p3 - p0
+        float ax = r.t0.x, ay = r.t0.y, az = r.t0.z;
+        if (negligible(ax, ay, az, cc)) { ax = r.d.x - r.t1.x; ay = r.d.y - r.t1.y; az = r.d.z - r.t1.z; }
+        if (negligible(ax, ay, az, cc)) { ax = r.d.x; ay = r.d.y; az = r.d.z; }
+        float bx = r.t1.x, by = r.t1.y, bz = r.t1.z;
+        if (negligible(bx, by, bz, cc)) { bx = r.d.x - r.t0.x; by = r.d.y - r.t0.y; bz = r.d.z - r.t0.z; }
+        if (negligible(bx, by, bz, cc)) { bx = r.d.x; by = r.d.y; bz = r.d.z; }
+        const float ex = r.p.x + r.d.x, ey = r.p.y + r.d.y, ez = r.p.z + r.d.z;     // p3
+        const float d0 = fabsf(L.t * az - dot3(r.p.x, r.p.y, r.p.z, ax, ay, az)) * rcp(vsqrt(dot3(ax, ay, az, ax, ay, az)));
+        const float d1 = fabsf(L.t * bz - dot3(ex, ey, ez, bx, by, bz)) * rcp(vsqrt(dot3(bx, by, bz, bx, by, bz)));
+        float X = 0.0f;
+        X = fmaxf(X, fmaxf(fabsf(r.p.x), fmaxf(fabsf(r.p.y), fabsf(r.p.z))));
+        X = fmaxf(X, fmaxf(fabsf(r.p.x + r.t0.x), fmaxf(fabsf(r.p.y + r.t0.y), fabsf(r.p.z + r.t0.z))));
+        X = fmaxf(X, fmaxf(fabsf(ex - r.t1.x), fmaxf(fabsf(ey - r.t1.y), fabsf(ez - r.t1.z))));
+        X = fmaxf(X, fmaxf(fabsf(ex), fmaxf(fabsf(ey), fabsf(ez))));
+        const float tol = (float)(8 + 2 * L.level) * 0x1p-24f * X;
+        const bool near1 = d1 < d0;
+        if (fminf(d0, d1) <= tol) {
+            vx = near1 ? bx : -ax;
+            vy = near1 ? by : -ay;
+            vz = near1 ? bz : -az;
+        }
+    }
+    const int64_t ri = a.pair_ray ? (int64_t)a.pair_ray[i] : i;
+    const float *R = a.rays + ri;
+    const int64_t rs = a.ray_stride;
+    const double dx = R[3 * rs], dy = R[4 * rs], dz = R[5 * rs];
+    const double il = rsqrt64(fma(dx, dx, fma(dy, dy, dz * dz)));
+    const double w[3] = {dx * il, dy * il, dz * il};
+    double u[3], v[3];
+    make_onb(w[0], w[1], w[2], u, v);
+    const double wx = fma((double)vx, u[0], fma((double)vy, v[0], (double)vz * w[0]));
+    const double wy = fma((double)vx, u[1], fma((double)vy, v[1], (double)vz * w[1]));
+    const double wz = fma((double)vx, u[2], fma((double)vy, v[2], (double)vz * w[2]));
+    const double in = rsqrt64(fma(wx, wx, fma(wy, wy, wz * wz)));
+    nx = (float)(wx * in);
+    ny = (float)(wy * in);
+    nz = (float)(wz * in);
 }
 
 // Write the result of pair i (Section 3.3: u from projecting the hit point
 // onto the leaf chord; hit when t < tmax). A refined pair (depth > 16 under
 // FI_FP64_REFINE) reports its FP64 surface hit, decided in FP64.
+// `hg` is the leaf geometry of a plain hit; `ref` the FP64 result of a
+// refined pair (used when `reached`).
 template <int MODE>
-__device__ __forceinline__ void finish(const Outs &a, int64_t i, const Lane &L, bool reached)
+__device__ __forceinline__ void finish(const Args &a, int64_t i, const Lane &L, bool reached,
+                                       HitGeo hg = HitGeo{}, Refined ref = Refined{})
 {
     float t = INFINITY, u = __builtin_nanf("");
     double t64 = INFINITY, u64 = __builtin_nan("");
     bool hit = false;
     if (MODE == kConservative && L.slack >= 0.0f) {
         if (reached) {
-            t64 = L.t64;
-            u64 = L.u64;
+            t64 = ref.t;
+            u64 = ref.u;
             t = (float)t64;
             u = (float)u64;
             hit = true;
@@ -933,12 +1065,23 @@ __device__ __forceinline__ void finish(const Outs &a, int64_t i, const Lane &L, 
         u64 = u;
         hit = true;
     }
-    a.t[i] = t;
-    a.u[i] = u;
-    a.hit[i] = hit ? 1 : 0;
+    a.t_out[i] = t;
+    a.u_out[i] = u;
+    a.hit_out[i] = hit ? 1 : 0;
     if (MODE == kConservative) {
-        a.t64[i] = t64;
-        a.u64[i] = u64;
+        a.t64_out[i] = t64;
+        a.u64_out[i] = u64;
+    }
+    if (MODE != kCount && a.normal_out) {
+        float nx = __builtin_nanf(""), ny = nx, nz = nx;
+        if (MODE == kConservative && L.slack >= 0.0f) {
+            if (hit) { nx = ref.nx; ny = ref.ny; nz = ref.nz; }
+        } else if (hit) {
+            leaf_normal(a, i, L, hg, nx, ny, nz);
+        }
+        a.normal_out[i] = nx;
+        a.normal_out[a.n_pairs + i] = ny;
+        a.normal_out[2 * a.n_pairs + i] = nz;
     }
     if (MODE == kCount) {
         int32_t *cn = a.counts + 4 * i;
@@ -958,6 +1101,11 @@ __device__ __forceinline__ void finish_invalid(const Args &a, int64_t i)
     if (MODE == kConservative) {
         a.t64_out[i] = INFINITY;
         a.u64_out[i] = __builtin_nan("");
+    }
+    if (MODE != kCount && a.normal_out) {
+        a.normal_out[i] = __builtin_nanf("");
+        a.normal_out[a.n_pairs + i] = __builtin_nanf("");
+        a.normal_out[2 * a.n_pairs + i] = __builtin_nanf("");
     }
     if (MODE == kCount) {
         int32_t *cn = a.counts + 4 * i;
@@ -1085,12 +1233,9 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
     const RegRoot root{};
     // batched: pairs are numbered across the scene table; the wave's share
     // is contiguous, so the scene of its next pair only moves forward
-    int scene0 = 0;
-    Outs cur = outs_of(a0);              // outputs of scene0 (wave-uniform)
-    if constexpr (BATCHED) {
+    int scene0 = 0;                      // scene of the wave's next pair (wave-uniform)
+    if constexpr (BATCHED)
         scene0 = __builtin_amdgcn_readfirstlane(next < count ? find_scene(offsets, n_scenes, next) : 0);
-        cur = outs_of(scenes[scene0]);
-    }
     int q_head = 0, q_count = 0;         // the queue: entries q_head .. q_head + q_count - 1 (mod kQueue)
     Lane L = {};
     L.lo = INFINITY;                                                   // an empty interval: no work
@@ -1138,15 +1283,17 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
                         // decided at the root: a miss, or the root is the leaf
                         Lane D = {};
                         D.c = r;
+                        D.root = r;
                         D.tmax = rtmax;
                         D.t = fmaxf(te, lu);
+
                         D.start = 0;
                         D.size = kRootSize;
                         D.u = leaf_u(D);
                         D.level = 0;
                         D.trips = 1;
                         D.slack = slack;
-                        finish<MODE>(outs_of(a), idx, D, vis);
+                        finish<MODE>(a, idx, D, vis, hit_geo(r, D.t, te < lu));
                     }
                 }
             }
@@ -1169,10 +1316,8 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
             q_count += __popcll(qm);
             next += take;
             if constexpr (BATCHED) {
-                const int before = scene0;
                 while (scene0 + 1 < n_scenes && next < count && offsets[scene0 + 1] <= next) ++scene0;
                 scene0 = __builtin_amdgcn_readfirstlane(scene0);
-                if (scene0 != before) cur = outs_of(scenes[scene0]);
             }
         }
         if (q_count > 0 && n_free >= (refill < q_count ? refill : q_count)) {
@@ -1215,16 +1360,17 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
         // the traversal state at every trip (about 45 moves, measured 12-14 %
         // of the call).
         if (__ballot(active) == 0 && next >= end && q_count == 0) break;
-        const int st = trip<MODE>(L, root, col);
+        HitGeo hg;
+        const int st = trip<MODE>(L, root, col, hg);
         if (active && st != kGoOn && !(MODE == kConservative && L.waiting)) {
             if constexpr (BATCHED) {
-                // lanes of the wave's current scene write through its
-                // uniform output pointers; others (a scene boundary inside
-                // the wave) load their scene's
-                if (L.scene == scene0) finish<MODE>(cur, L.pair, L, st == kHit);
-                else finish<MODE>(outs_of(scenes[L.scene]), L.pair, L, st == kHit);
+                // lanes of the wave's current scene read its output
+                // pointers with uniform loads; others (a scene boundary
+                // inside the wave) load their scene's
+                if (L.scene == scene0) finish<MODE>(scenes[scene0], L.pair, L, st == kHit, hg);
+                else finish<MODE>(scenes[L.scene], L.pair, L, st == kHit, hg);
             } else {
-                finish<MODE>(outs_of(a0), L.pair, L, st == kHit);
+                finish<MODE>(a0, L.pair, L, st == kHit, hg);
             }
             active = false;
         }
@@ -1241,18 +1387,20 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
                     const float *rays = a0.rays, *fibers = a0.fibers;
                     int64_t rs = a0.ray_stride, fs = a0.fiber_stride;
                     const int32_t *pr = a0.pair_ray, *pf = a0.pair_fiber;
-                    Outs o = outs_of(a0);
+                    bool want_n = a0.normal_out != nullptr;
                     if constexpr (BATCHED) {
                         const Args *sc = scenes + L.scene;
                         rays = sc->rays; fibers = sc->fibers;
                         rs = sc->ray_stride; fs = sc->fiber_stride;
                         pr = sc->pair_ray; pf = sc->pair_fiber;
-                        o = outs_of(*sc);
+                        want_n = sc->normal_out != nullptr;
                     }
-                    const Refined r = refine_whole_curve(rays, rs, fibers, fs, pr, pf, L.pair, L.tmax, L.t, L.ru);
-                    L.t64 = r.t;
-                    L.u64 = r.u;
-                    finish<MODE>(o, L.pair, L, r.hit);
+                    const Refined r = refine_whole_curve(rays, rs, fibers, fs, pr, pf, L.pair, L.tmax, L.t, L.ru,
+                                                         want_n);
+                    // the output pointers are read after the call (not kept
+                    // live across it)
+                    if constexpr (BATCHED) finish<MODE>(scenes[L.scene], L.pair, L, r.hit, HitGeo{}, r);
+                    else finish<MODE>(a0, L.pair, L, r.hit, HitGeo{}, r);
                     active = false;
                 }
             }
@@ -1508,7 +1656,7 @@ int scenes_to_table(const fi_scene *sc, int32_t n, uint32_t flags, Args *tab, in
         tab[k] = Args{x.rays, x.ray_stride, x.n_rays, x.fibers, x.fiber_stride, x.n_fibers,
                       x.pair_ray, x.pair_fiber, x.pair_depth, x.depth, x.n_pairs,
                       x.t_out, x.u_out, x.hit_out, nullptr,
-                      refine ? x.t64_out : nullptr, refine ? x.u64_out : nullptr};
+                      refine ? x.t64_out : nullptr, refine ? x.u64_out : nullptr, x.normal_out};
         off[k + 1] = off[k] + x.n_pairs;
     }
     if (off[n] > (int64_t)0x7fffffff - 64) return FI_ERR_RANGE;
@@ -1587,7 +1735,7 @@ struct fi_batch_plan {
 };
 
 extern "C" {
-int fi_version(void) { return (0 << 16) | (6 << 8) | 0; }
+int fi_version(void) { return (0 << 16) | (7 << 8) | 0; }
 
 const char *fi_strerror(int status)
 {
@@ -1622,7 +1770,7 @@ int fiber_intersect_pairs(const float *rays, int64_t ray_stride, int64_t n_rays,
                           const uint8_t *pair_depth, int32_t depth, int64_t n_pairs,
                           uint32_t flags,
                           float *t_out, float *u_out, uint8_t *hit_out,
-                          double *t64_out, double *u64_out,
+                          double *t64_out, double *u64_out, float *normal_out,
                           void *workspace, size_t workspace_bytes, void *stream)
 {
     const int st = check_common(rays, ray_stride, n_rays, fibers, fiber_stride, n_fibers,
@@ -1632,7 +1780,7 @@ int fiber_intersect_pairs(const float *rays, int64_t ray_stride, int64_t n_rays,
     if (refine && (!t64_out || !u64_out)) return FI_ERR_NULL;
     Args a{rays, ray_stride, n_rays, fibers, fiber_stride, n_fibers,
            pair_ray, pair_fiber, pair_depth, depth, n_pairs, t_out, u_out, hit_out, nullptr,
-           refine ? t64_out : nullptr, refine ? u64_out : nullptr};
+           refine ? t64_out : nullptr, refine ? u64_out : nullptr, normal_out};
     return launch_with_workspace(refine ? kConservative : kPlain, a, workspace, workspace_bytes, stream);
 }
 
@@ -1642,7 +1790,7 @@ int fiber_intersect_pairs_noalloc(const float *rays, int64_t ray_stride, int64_t
                                   const uint8_t *pair_depth, int32_t depth, int64_t n_pairs,
                                   uint32_t flags,
                                   float *t_out, float *u_out, uint8_t *hit_out,
-                                  double *t64_out, double *u64_out,
+                                  double *t64_out, double *u64_out, float *normal_out,
                                   void *stream)
 {
     const int st = check_common(rays, ray_stride, n_rays, fibers, fiber_stride, n_fibers,
@@ -1659,7 +1807,7 @@ int fiber_intersect_pairs_noalloc(const float *rays, int64_t ray_stride, int64_t
     const int mode = refine ? kConservative : kPlain;
     Args a{rays, ray_stride, n_rays, fibers, fiber_stride, n_fibers,
            pair_ray, pair_fiber, pair_depth, depth, n_pairs, t_out, u_out, hit_out, nullptr,
-           refine ? t64_out : nullptr, refine ? u64_out : nullptr};
+           refine ? t64_out : nullptr, refine ? u64_out : nullptr, normal_out};
     // the fiber records of a gathered call go to this device's copy of the
     // scratch array (through its device address, never the array's name)
     return launch(mode, a, single_call_waves(*d, mode, a), rec ? d->scratch : nullptr, (hipStream_t)stream);
@@ -1679,7 +1827,8 @@ int fiber_intersect_counts(const float *rays, int64_t ray_stride, int64_t n_rays
     if (!counts_out) return FI_ERR_NULL;
     if ((flags & FI_FP64_REFINE) != 0u) return FI_ERR_RANGE;
     Args a{rays, ray_stride, n_rays, fibers, fiber_stride, n_fibers,
-           pair_ray, pair_fiber, pair_depth, depth, n_pairs, t_out, u_out, hit_out, counts_out, nullptr, nullptr};
+           pair_ray, pair_fiber, pair_depth, depth, n_pairs, t_out, u_out, hit_out, counts_out, nullptr, nullptr,
+           nullptr};
     return launch_with_workspace(kCount, a, workspace, workspace_bytes, stream);
 }
 

@@ -50,7 +50,7 @@ def _call(**kw):
     return binding.lib().fiber_intersect_pairs(
         vp(a["rays"]), a["rs"], a["nr"], vp(a["fibers"]), a["fs"], a["nf"], vp(a["pr"]),
         vp(a["pf"]), vp(a["pd"]), a["depth"], a["n"], a["flags"], vp(a["t"]), vp(a["u"]),
-        vp(a["h"]), vp(a.get("t64")), vp(a.get("u64")), vp(a["ws"]), a["wsb"], None)
+        vp(a["h"]), vp(a.get("t64")), vp(a.get("u64")), vp(a.get("nrm")), vp(a["ws"]), a["wsb"], None)
 
 
 @pytest.mark.parametrize("kw,code", [
@@ -126,5 +126,5 @@ def test_noalloc_refuses_more_records_than_its_scratch():
     n = 600_000
     r = L.fiber_intersect_pairs_noalloc(C.c_void_p(256), n, n, C.c_void_p(256), n, n, None,
                                         C.c_void_p(256), None, 9, n, 0, C.c_void_p(256), C.c_void_p(256),
-                                        C.c_void_p(256), None, None, None)
+                                        C.c_void_p(256), None, None, None, None)
     assert r == -5

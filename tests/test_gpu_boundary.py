@@ -75,7 +75,7 @@ def test_workspace_without_room_for_records():
                    torch.empty(n, dtype=torch.uint8, device=DEV))
         st = lib.fiber_intersect_pairs(rays.data_ptr(), rays.stride(0), n, fibers.data_ptr(), fibers.stride(0), n,
                                        idx.data_ptr(), idx.data_ptr(), None, 9, n, 0, t.data_ptr(), u.data_ptr(),
-                                       h.data_ptr(), None, None, None if ws is None else ws.data_ptr(),
+                                       h.data_ptr(), None, None, None, None if ws is None else ws.data_ptr(),
                                        0 if ws is None else ws.numel(),
                                        torch.cuda.current_stream().cuda_stream)
         assert st == 0

@@ -34,8 +34,8 @@ MUTANTS = [
     ("chord instead of tangent as split normal", D, "v4 t = sub4(add4(q[2], q[3]), add4(q[0], q[1]));",
      "v4 t = sub4(q[3], q[0]);"),
     ("no interval recomputation after backtracking", D,
-     "return visit(S, second, blo, bhi, eblo, ebhi, bsrc, level + 1, s0, s1);",
-     "return visit(S, second, lo, hi, elo, ehi, lsrc, level + 1, s0, s1);"),
+     "return visit(S, second, blo, bhi, eblo, ebhi, level + 1, s0, s1);",
+     "return visit(S, second, lo, hi, elo, ehi, level + 1, s0, s1);"),
     ("tangents negligible only when exactly zero", D, "return dot3(v, v) <= 0x1p-40 * dot3(chord, chord);",
      "return zero3(v);"),
     ("grazing ties never decided together", D, "return S->ties.force_vis > 0;", "return value;"),
@@ -49,13 +49,15 @@ MUTANTS = [
     ("tie margin 2^10 too wide", D, "return (2.0 + 2.0 * level) * 0x1p-24 * S->ties.X;",
      "return (2.0 + 2.0 * level) * 0x1p-14 * S->ties.X;"),
     ("start cap normal pointing inwards", D,
-     "const v4 cap = lsrc == LO_START_CAP ? scale4(S->cap0, -1.0) : S->cap1;",
-     "const v4 cap = lsrc == LO_START_CAP ? S->cap0 : S->cap1;"),
+     "const v4 cap = near1 ? S->cap1 : scale4(S->cap0, -1.0);",
+     "const v4 cap = near1 ? S->cap1 : S->cap0;"),
     ("side normal from the leaf's start point", D,
      "add4(N->q[0], scale4(a, ul)));", "N->q[0]);"),
-    ("cap entries given the side normal", D, "const int on_side = te >= lo || !capped;",
-     "const int on_side = 1;"),
-    ("backtracked nodes never at the curve's ends", D, "s0 == 0.0, s1 == 1.0,", "0, 0,"),
+    ("cap entries given the side normal", D, "const int on_cap = plane && dc <= 1.0;",
+     "const int on_cap = 0;"),
+    ("cap plane test without its tolerance", D, "const int on_cap = plane && dc <= 1.0;",
+     "const int on_cap = plane && dc <= 0.0;"),
+    ("the farther cap plane taken", D, "const int near1 = d1 < d0;", "const int near1 = d1 > d0;"),
     ("normal left in the ray frame", D,
      "normal_out[k] = hit ? S.n[0] * frame[k] + S.n[1] * frame[3 + k] + S.n[2] * frame[6 + k] : NAN;",
      "normal_out[k] = hit ? S.n[k] : NAN;"),
