@@ -445,6 +445,26 @@ def main():
     launch_ms = {d: [ev[k][j][0].elapsed_time(ev[k][j][1]) for k in range(args.steps)]
                  for j, d in enumerate(DEPTHS)}
 
+    # the same calls writing the normal at each hit as well (not part of the
+    # step: the cost of the extra output)
+    ncall = {d: binding.PreparedPairs(rays, fibers, d, normal=True) for d in DEPTHS}
+    for _ in range(5):
+        for d in DEPTHS:
+            ncall[d].launch(stream)
+    nev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+            for _ in DEPTHS] for _ in range(args.steps)]
+    for k in range(args.steps):
+        for j, d in enumerate(DEPTHS):
+            nev[k][j][0].record(stream)
+            ncall[d].launch(stream)
+            nev[k][j][1].record(stream)
+    torch.cuda.synchronize()
+    normals = {str(d): {"launch_ms_avg": statistics.mean(nev[k][j][0].elapsed_time(nev[k][j][1])
+                                                         for k in range(args.steps)),
+                        "gpairs_per_s": n / (statistics.mean(nev[k][j][0].elapsed_time(nev[k][j][1])
+                                                             for k in range(args.steps)) * 1e-3) / 1e9}
+               for j, d in enumerate(DEPTHS)}
+
     per_depth = {}
     roof = {}
     for d in DEPTHS:
@@ -511,6 +531,7 @@ def main():
             "what": "both calls' algorithmic flops over the step time (calls overlapped on two streams)"},
         "cpu_baseline": cpu,
         "parity": parity,
+        "with_normals": normals,
     }
     print(json.dumps(line), flush=True)
 

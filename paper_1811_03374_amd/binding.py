@@ -264,7 +264,7 @@ class PreparedPairs:
     one object must not overlap (they share the workspace)."""
 
     def __init__(self, rays, fibers, depth=9, pair_ray=None, pair_fiber=None, pair_depth=None,
-                 out=None):
+                 out=None, normal=None):
         rs = _table(rays, 7, "rays")
         fs = _table(fibers, 16, "fibers")
         pr = _index(pair_ray, torch.int32, "pair_ray")
@@ -272,17 +272,18 @@ class PreparedPairs:
         pd = _index(pair_depth, torch.uint8, "pair_depth")
         n = _pair_count(rays, fibers, pr, pf, pd)
         self.t, self.u, self.hit = _outs(out, n, rays.device)
+        self.normal = _normal_tensor(normal, n, rays.device)
         self.workspace = pairs_workspace(n, fibers.shape[1], pf is not None, rays.device)
         self._keep = (rays, fibers, pr, pf, pd)
         self._fn = lib().fiber_intersect_pairs
         self._args = (_ptr(rays), rs, rays.shape[1], _ptr(fibers), fs, fibers.shape[1],
                       _ptr(pr), _ptr(pf), _ptr(pd), int(depth), n, 0,
-                      _ptr(self.t), _ptr(self.u), _ptr(self.hit), None, None, None,
+                      _ptr(self.t), _ptr(self.u), _ptr(self.hit), None, None, _ptr(self.normal),
                       *_ws_args(self.workspace))
 
     def launch(self, stream=None):
         _check(self._fn(*self._args, _stream(stream)))
-        return self.t, self.u, self.hit
+        return (self.t, self.u, self.hit) + (() if self.normal is None else (self.normal,))
 
 
 def raw_call(name: str, *args):
