@@ -46,6 +46,11 @@ def lib():
         L.fo_tie_outcomes.argtypes = [dp, dp, C.c_int, C.c_double, C.c_int, C.c_int, dp, dp,
                                       C.POINTER(C.c_int)]
         L.fo_tie_outcomes.restype = C.c_int
+        L.fo_nearest_d.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_int64,
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_double,
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
+                                   C.c_void_p]
+        L.fo_nearest_d.restype = None
         L.fo_cubic_constraints.argtypes = [dp]
         L.fo_cubic_constraints.restype = C.c_int
         if hasattr(L, "fx_batch"):
@@ -55,6 +60,10 @@ def lib():
             L.fx_batch.restype = None
             L.fx_intersect.argtypes = [dp, dp, dp, dp, dp]
             L.fx_intersect.restype = C.c_int
+            L.fx_nearest.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_int64,
+                                     C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
+            L.fx_nearest.restype = None
             L.fx_side_polynomial.argtypes = [dp, dp]
             L.fx_side_polynomial.restype = C.c_int
         _lib = L
@@ -139,6 +148,53 @@ def intersect_exact(rays, fibers, pair_ray=None, pair_fiber=None, radius_scale=1
                fibers.shape[1], _ptr(pr), _ptr(pf), n, float(radius_scale),
                _ptr(t), _ptr(u), _ptr(kind), int(nthreads), _ptr(nn))
     return (t, u, (kind > 0).astype(np.uint8), kind) + ((nn,) if normal else ())
+
+
+def intersect_nearest(rays, fibers, offsets, cand, depth=9, cand_depth=None, max_cand=None,
+                      radius_scale=1.0, nthreads=0, t_err=False, normal=False):
+    """Nearest hit over each ray's candidate list with the depth-d method
+    (fo_nearest_d): candidates cand[offsets[r]:offsets[r+1]] in order, each
+    against the ray shortened to the latest hit. Returns (t, u, hit, fiber[,
+    t_err][, normal (n_rays, 8)])."""
+    rays = np.ascontiguousarray(rays, dtype=np.float32)
+    fibers = np.ascontiguousarray(fibers, dtype=np.float32)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    cd = np.ascontiguousarray(cand, dtype=np.int32)
+    dd = None if cand_depth is None else np.ascontiguousarray(cand_depth, dtype=np.uint8)
+    n = rays.shape[1]
+    assert off.shape[0] == n + 1
+    mc = int(np.diff(off).max(initial=0)) if max_cand is None else int(max_cand)
+    t = np.empty(n)
+    u = np.empty(n)
+    hit = np.empty(n, np.uint8)
+    fib = np.empty(n, np.int32)
+    te = np.empty(n) if t_err else None
+    nn = np.empty((n, 8)) if normal else None
+    lib().fo_nearest_d(_ptr(rays), rays.shape[1], n, _ptr(fibers), fibers.shape[1], fibers.shape[1],
+                       _ptr(off), _ptr(cd), _ptr(dd), int(depth), mc, float(radius_scale), _ptr(t),
+                       _ptr(u), _ptr(hit), _ptr(fib), int(nthreads), _ptr(te), _ptr(nn))
+    return (t, u, hit, fib) + ((te,) if t_err else ()) + ((nn,) if normal else ())
+
+
+def nearest_exact(rays, fibers, offsets, cand, max_cand=None, radius_scale=1.0, nthreads=0,
+                  normal=False):
+    """Nearest entry over each ray's candidate list into the swept solids
+    (fx_nearest). Returns (t, u, hit, kind, fiber[, normal (n_rays, 3)])."""
+    rays = np.ascontiguousarray(rays, dtype=np.float32)
+    fibers = np.ascontiguousarray(fibers, dtype=np.float32)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    cd = np.ascontiguousarray(cand, dtype=np.int32)
+    n = rays.shape[1]
+    mc = int(np.diff(off).max(initial=0)) if max_cand is None else int(max_cand)
+    t = np.empty(n)
+    u = np.empty(n)
+    kind = np.empty(n, np.int32)
+    fib = np.empty(n, np.int32)
+    nn = np.empty((n, 3)) if normal else None
+    lib().fx_nearest(_ptr(rays), rays.shape[1], n, _ptr(fibers), fibers.shape[1], fibers.shape[1],
+                     _ptr(off), _ptr(cd), mc, float(radius_scale), _ptr(t), _ptr(u), _ptr(kind),
+                     _ptr(fib), int(nthreads), _ptr(nn))
+    return (t, u, (kind > 0).astype(np.uint8), kind, fib) + ((nn,) if normal else ())
 
 
 def single_exact(ray, fiber, normal=False):

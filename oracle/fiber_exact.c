@@ -601,6 +601,52 @@ void fx_batch(const float *rays, int64_t ray_stride, int64_t n_rays,
     }
 }
 
+/* Nearest entry over a candidate list per ray (the exact counterpart of
+ * fo_nearest_d): candidates in list order, each against the ray shortened to
+ * the latest entry found; the first of equal entries is kept. */
+void fx_nearest(const float *rays, int64_t ray_stride, int64_t n_rays,
+                const float *fibers, int64_t fiber_stride, int64_t n_fibers,
+                const int64_t *off, const int32_t *cand, int max_cand, double radius_scale,
+                double *t_out, double *u_out, int32_t *kind_out, int32_t *fiber_out, int nthreads,
+                double *normal_out)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+    for (int64_t r = 0; r < n_rays; ++r) {
+        double ray[7];
+        for (int k = 0; k < 7; ++k) ray[k] = rays[k * ray_stride + r];
+        double best_t = INFINITY, best_u = NAN, best_n[3] = {NAN, NAN, NAN};
+        int best_kind = 0;
+        int32_t best_f = -1;
+        int64_t end = off[r + 1];
+        if (end - off[r] > max_cand) end = off[r] + max_cand;
+        for (int64_t j = off[r]; j < end; ++j) {
+            const int64_t fi = cand[j];
+            if (fi < 0 || fi >= n_fibers) continue;
+            double fib[16], t, u, nn[3];
+            for (int k = 0; k < 16; ++k) fib[k] = fibers[k * fiber_stride + fi];
+            for (int k = 0; k < 4; ++k) fib[4 * k + 3] *= radius_scale;
+            const int kind = fx_intersect(ray, fib, &t, &u, nn);
+            if (kind) {
+                best_t = t;
+                best_u = u;
+                best_kind = kind;
+                best_f = (int32_t)fi;
+                for (int k = 0; k < 3; ++k) best_n[k] = nn[k];
+                ray[6] = t;
+            }
+        }
+        t_out[r] = best_t;
+        u_out[r] = best_u;
+        kind_out[r] = best_kind;
+        fiber_out[r] = best_f;
+        if (normal_out)
+            for (int k = 0; k < 3; ++k) normal_out[3 * r + k] = best_n[k];
+    }
+}
+
 /* Bernstein coefficients of F for a curve given in the ray frame (pins). */
 int fx_side_polynomial(const double q16[16], double coef[MAXDEG + 1])
 {

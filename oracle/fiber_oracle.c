@@ -725,6 +725,61 @@ void fo_batch_d(const float *rays, int64_t ray_stride, int64_t n_rays,
     }
 }
 
+/* Nearest hit over a candidate list per ray: the interface a renderer's
+ * top-level hierarchy uses (Sec. 1 and Sec. 4: the fibers referenced by the
+ * hierarchy leaves a ray reaches are tested one after another, and a hit
+ * shortens the ray for the fibers after it). Ray r's candidates are
+ * cand[off[r]] .. cand[off[r + 1] - 1], tested in that order at depth d (or
+ * cand_depth[k]) with tmax = the ray's tmax until the first hit and the
+ * latest hit's t after it; a hit counts when its t is below that tmax, so of
+ * equal hits the first in the list is kept. At most max_cand candidates of a
+ * ray are tested (the first ones). Per ray: t, u, hit, the fiber of the kept
+ * hit (-1 on a miss), and when given t_err and the 8 normal values as
+ * fo_batch_d. */
+void fo_nearest_d(const float *rays, int64_t ray_stride, int64_t n_rays,
+                  const float *fibers, int64_t fiber_stride, int64_t n_fibers,
+                  const int64_t *off, const int32_t *cand, const uint8_t *cand_depth, int depth,
+                  int max_cand, double radius_scale, double *t_out, double *u_out, uint8_t *hit_out,
+                  int32_t *fiber_out, int nthreads, double *terr_out, double *normal_out)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+    for (int64_t r = 0; r < n_rays; ++r) {
+        double ray[7];
+        for (int k = 0; k < 7; ++k) ray[k] = rays[k * ray_stride + r];
+        double best_t = INFINITY, best_u = NAN, best_e = 0.0, best_n[8];
+        int32_t best_f = -1;
+        for (int k = 0; k < 8; ++k) best_n[k] = NAN;
+        int64_t end = off[r + 1];
+        if (end - off[r] > max_cand) end = off[r] + max_cand;
+        for (int64_t j = off[r]; j < end; ++j) {
+            const int64_t fi = cand[j];
+            if (fi < 0 || fi >= n_fibers) continue;
+            const int d = cand_depth ? (int)cand_depth[j] : depth;
+            double fib[16], t, u, te = 0.0, nn[8];
+            for (int k = 0; k < 16; ++k) fib[k] = fibers[k * fiber_stride + fi];
+            for (int k = 0; k < 4; ++k) fib[4 * k + 3] *= radius_scale;
+            if (intersect_with_ties(ray, fib, d, 0.0, 0, 0, NULL, &t, &u, NULL, &te, nn)) {
+                best_t = t;
+                best_u = u;
+                best_e = te;
+                best_f = (int32_t)fi;
+                for (int k = 0; k < 8; ++k) best_n[k] = nn[k];
+                ray[6] = t;                     /* later candidates must come nearer */
+            }
+        }
+        t_out[r] = best_t;
+        u_out[r] = best_u;
+        hit_out[r] = best_f >= 0;
+        fiber_out[r] = best_f;
+        if (terr_out) terr_out[r] = best_e;
+        if (normal_out)
+            for (int k = 0; k < 8; ++k) normal_out[8 * r + k] = best_n[k];
+    }
+}
+
 /* Building blocks exported for the pins in the test suite. */
 
 void fo_split_half(const double q[16], double L[16], double R[16])

@@ -339,7 +339,8 @@ def hair_strands(n_strands: int = 100_000, seed: int = SEED_BASE + 3, offset: fl
 
 def hair_precision(n_rays: int = 1 << 24, n_strands: int = 100_000, depth: int = 9,
                    seed: int = SEED_BASE + 3, grazing_fraction: float = 0.1,
-                   rho: float = 0.25, chunk: int = 1 << 21, graze_width: float = 1e-3) -> Workload:
+                   rho: float = 0.25, chunk: int = 1 << 21, graze_width: float = 1e-3,
+                   targets: Optional[np.ndarray] = None, strands: Optional[np.ndarray] = None) -> Workload:
     """Rays aimed at uniformly chosen hair segments and parameters u0, from
     C(u0) + rho * s (s uniform on the sphere, rho = 0.25): 90 % regular rays
     displaced sideways by N(0, (1.4826 r)^2), 10 % grazing rays displaced by
@@ -347,13 +348,19 @@ def hair_precision(n_rays: int = 1 << 24, n_strands: int = 100_000, depth: int =
     both along the direction
     normal to the view vector and the tangent. The origin is rounded to
     float32 first, then D = target - O is formed in float64 and rounded.
-    Pairs are (ray i, its target segment) through pair_fiber."""
-    P = hair_strands(n_strands, seed)
-    fibers = pack_fibers(P)
-    P32 = unpack_fibers(fibers)
+    Pairs are (ray i, its target segment) through pair_fiber. ``targets``
+    (and ``strands``, the float32-exact control points of the table) aim the
+    rays at given segments instead of uniformly chosen ones."""
+    if strands is None:
+        P = hair_strands(n_strands, seed)
+        fibers = pack_fibers(P)
+        P32 = unpack_fibers(fibers)
+    else:
+        P32 = strands
+        fibers = pack_fibers(P32)
     rng = np.random.default_rng(seed + 7)
     n = int(n_rays)
-    seg = rng.integers(0, P32.shape[0], n).astype(np.int32)
+    seg = rng.integers(0, P32.shape[0], n).astype(np.int32) if targets is None else targets
     rays = np.empty((RAY_ROWS, n), np.float32)
     graze = np.zeros(n, bool)
     for a in range(0, n, chunk):
@@ -379,6 +386,60 @@ def hair_precision(n_rays: int = 1 << 24, n_strands: int = 100_000, depth: int =
         rays[6, a:b] = 100.0
         graze[a:b] = g
     return Workload(f"hair_{n}", rays, fibers, None, seg, depth, meta={"grazing": graze})
+
+
+def hair_candidates(n_rays: int = 1 << 20, n_strands: int = 100_000, depth: int = 22,
+                    seed: int = SEED_BASE + 6, chunk: int = 1 << 20) -> Workload:
+    """Candidate lists of a hierarchy leaf per ray over the hair table of
+    ``hair_strands``: each ray is aimed as in ``hair_precision`` (90 %
+    regular, 10 % grazing) at segment j of strand a; its candidates are
+    segments j-1 .. j+1 of strand a and of 1 to 4 other strands whose roots
+    lie in the same or a neighbouring cell of a 64 x 64 grid over the root
+    square (strands that cross the same region), 6 to 15 segments in all, in
+    random order (a leaf's order is not sorted by distance). Offsets (CSR,
+    int64) and candidate fibers (int32) are in ``meta`` as ``cand_off`` and
+    ``cand_fiber``; ``meta["target"]`` is the aimed segment."""
+    segments = 8
+    P = hair_strands(n_strands, SEED_BASE + 3)
+    fibers = pack_fibers(P)
+    P32 = unpack_fibers(fibers)
+    rng = np.random.default_rng(seed)
+    n = int(n_rays)
+    n_str = P32.shape[0] // segments
+    roots = P32[::segments, 0, :2] - 1000.0
+    g = 64
+    cell = np.clip((roots * g).astype(np.int64), 0, g - 1)
+    cid = cell[:, 0] * g + cell[:, 1]
+    order = np.argsort(cid, kind="stable")
+    start = np.searchsorted(cid[order], np.arange(g * g + 1))
+    strand = rng.integers(0, n_str, n)
+    j = rng.integers(0, segments, n)
+    target = (strand * segments + j).astype(np.int32)
+    n_other = rng.integers(1, 5, n)
+    lists = []
+    counts = np.empty(n, np.int64)
+    cx, cy = cell[strand, 0], cell[strand, 1]
+    for i in range(n):
+        segs = [strand[i] * segments + k for k in (j[i] - 1, j[i], j[i] + 1) if 0 <= k < segments]
+        for _ in range(int(n_other[i])):
+            ox = min(g - 1, max(0, cx[i] + int(rng.integers(-1, 2))))
+            oy = min(g - 1, max(0, cy[i] + int(rng.integers(-1, 2))))
+            c = ox * g + oy
+            if start[c + 1] == start[c]:
+                continue
+            b = order[rng.integers(start[c], start[c + 1])]
+            segs += [b * segments + k for k in (j[i] - 1, j[i], j[i] + 1) if 0 <= k < segments]
+        segs = np.array(segs, np.int32)
+        rng.shuffle(segs)
+        lists.append(segs)
+        counts[i] = len(segs)
+    off = np.zeros(n + 1, np.int64)
+    np.cumsum(counts, out=off[1:])
+    cand = np.concatenate(lists).astype(np.int32)
+    aim = hair_precision(n, n_strands, depth, seed=seed + 1, chunk=chunk, targets=target, strands=P32)
+    return Workload(f"hair_candidates_{n}", aim.rays, fibers, None, None, depth,
+                    meta={"cand_off": off, "cand_fiber": cand, "target": target,
+                          "grazing": aim.meta["grazing"]})
 
 
 # ---------------------------------------------------------------------------

@@ -61,6 +61,9 @@ MUTANTS = [
     ("normal left in the ray frame", D,
      "normal_out[k] = hit ? S.n[0] * frame[k] + S.n[1] * frame[3 + k] + S.n[2] * frame[6 + k] : NAN;",
      "normal_out[k] = hit ? S.n[k] : NAN;"),
+    ("later candidates not held to the nearest hit", D,
+     "ray[6] = t;                     /* later candidates must come nearer */", "(void)0;"),
+    ("candidate lists not truncated", D, "if (end - off[r] > max_cand) end = off[r] + max_cand;", "(void)0;"),
     ("exact oracle: radius term with the wrong sign", X, "F = badd(&F, &a3, -1.0);", "F = badd(&F, &a3, 1.0);"),
     ("exact oracle: no limit disc at a zero end tangent", X, "while (j < 2 && cand[j][0]", "while (0 && cand[j][0]"),
     ("exact oracle: edge-on rays through the expanded polynomial", X, "if (edge_on(c)) {", "if (0) {"),
@@ -69,6 +72,8 @@ MUTANTS = [
      "const double beta = D1[3] /"),
     ("exact oracle: no curvature term in the tilt", X, "(dl - C[3] * ec2 / dl)", "(dl)"),
     ("exact oracle: start cap normal pointing inwards", X, "(kind == 2 ? -1.0 : 1.0)", "(1.0)"),
+    ("exact oracle: later candidates not held to the nearest entry", X,
+     "best_n[k] = nn[k];\n                ray[6] = t;", "best_n[k] = nn[k];"),
     ("exact oracle: circle point on the wrong side", X,
      "tsq = fabs((tm - C[2]) * D[2] - xy) <= fabs((tp - C[2]) * D[2] - xy) ? tm : tp;",
      "tsq = fabs((tm - C[2]) * D[2] - xy) <= fabs((tp - C[2]) * D[2] - xy) ? tp : tm;"),
@@ -93,7 +98,7 @@ def _run_mutant(m, tmp):
     env = dict(os.environ, FIBER_ORACLE_LIB=lib, OMP_NUM_THREADS="2")
     res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                           "tests/test_oracle_pins.py", "tests/test_oracle_exact.py",
-                          "tests/test_oracle_normals.py"],
+                          "tests/test_oracle_normals.py", "tests/test_oracle_candidates.py"],
                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return name, res.returncode, res.stdout[-400:]
 
