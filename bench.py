@@ -31,7 +31,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--workload", choices=("straight_and_curved", "batched", "hair", "degenerate"),
+    ap.add_argument("--workload", choices=("straight_and_curved", "batched", "hair", "degenerate", "candidates"),
                     default="straight_and_curved",
                     help="batched: 256 uneven scenes (~13 M pairs, adaptive depth), one graph launch "
                          "against 256 plain launches; hair: precision stress with error report")
@@ -231,6 +231,81 @@ def bench_hair(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_candidates(args):
+    """Nearest hit over candidate lists: 2^20 rays over the hair table, each
+    with a shuffled list of 6..15 segments of neighbouring strands (about
+    10.1M candidates in all), at depth 9 and 22 in FP32 and at 22 with FP64
+    refinement; errors against the oracles' nearest hit on a seeded sample of
+    4,096 rays."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1811_03374_amd import binding
+    from paper_1811_03374_amd import workloads as W
+
+    w = W.hair_candidates(1 << 20)
+    off_np, cand_np = w.meta["cand_off"], w.meta["cand_fiber"]
+    dev = torch.device("cuda:0")
+    rays, fibers = torch.from_numpy(w.rays).to(dev), torch.from_numpy(w.fibers).to(dev)
+    off, cand = torch.from_numpy(off_np).to(dev), torch.from_numpy(cand_np).to(dev)
+    n, nc = rays.shape[1], cand.numel()
+    mc = int(np.diff(off_np).max())
+    stream = torch.cuda.current_stream()
+    nb = binding.lib().fiber_candidates_workspace_bytes(nc, fibers.shape[1], 0)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev) if nb else None
+    res, outs = {}, {}
+    for name, d, ref in (("fp32_d9", 9, False), ("fp32_d22", 22, False), ("fp64_refined_d22", 22, True)):
+        def call():
+            return binding.intersect_candidates(rays, fibers, off, cand, d, max_candidates=mc, refine=ref,
+                                                stream=stream, workspace=ws)
+        ms = _timed(call, args.steps, args.warmup, stream)
+        outs[name] = [o.cpu().numpy() for o in call()]
+        res[name] = {"ms": ms, "grays_per_s": n / (ms * 1e-3) / 1e9,
+                     "candidate_tests_per_s_G": nc / (ms * 1e-3) / 1e9,
+                     "hit_rate": float(outs[name][2].mean())}
+    # errors on a sample of rays (their whole lists)
+    idx = np.sort(np.random.default_rng(5).choice(n, 4096, replace=False))
+    lists = [cand_np[off_np[i]:off_np[i + 1]] for i in idx]
+    so = np.zeros(len(idx) + 1, np.int64)
+    np.cumsum([len(x) for x in lists], out=so[1:])
+    sc = np.concatenate(lists)
+    sr = w.rays[:, idx]
+    for name, d in (("fp32_d9", 9), ("fp32_d22", 22)):
+        t_o, u_o, h_o, f_o = oracle.intersect_nearest(sr, w.fibers, so, sc, d)
+        _, _, hl, _ = oracle.intersect_nearest(sr, w.fibers, so, sc, d, radius_scale=1 - 1e-4)
+        _, _, hh, _ = oracle.intersect_nearest(sr, w.fibers, so, sc, d, radius_scale=1 + 1e-4)
+        t, u, h, f = (a[idx] for a in outs[name][:4])
+        m = hl == hh
+        both = m & h.astype(bool) & h_o.astype(bool)
+        rel = np.abs(t[both] - t_o[both]) / t_o[both]
+        res[name]["vs_depth_oracle"] = {"rays": int(m.sum()),
+                                        "flag_disagree": int((h[m] != h_o[m]).sum()),
+                                        "fiber_disagree": int((f[both] != f_o[both]).sum()),
+                                        "max_rel_t": float(rel.max()) if rel.size else 0.0}
+    t_x, u_x, h_x, _, f_x = oracle.nearest_exact(sr, w.fibers, so, sc)
+    _, _, hl, _, _ = oracle.nearest_exact(sr, w.fibers, so, sc, radius_scale=1 - 1e-4)
+    _, _, hh, _, _ = oracle.nearest_exact(sr, w.fibers, so, sc, radius_scale=1 + 1e-4)
+    t64, h, f = outs["fp64_refined_d22"][4][idx], outs["fp64_refined_d22"][2][idx], outs["fp64_refined_d22"][3][idx]
+    m = hl == hh
+    both = m & h.astype(bool) & h_x.astype(bool)
+    rel = np.abs(t64[both] - t_x[both]) / t_x[both]
+    res["fp64_refined_d22"]["vs_exact_oracle"] = {"rays": int(m.sum()),
+                                                  "flag_disagree": int((h[m] != h_x[m]).sum()),
+                                                  "fiber_disagree": int((f[both] != f_x[both]).sum()),
+                                                  "max_rel_t": float(rel.max()) if rel.size else 0.0}
+    line = {"metric": "nearest hits over candidate lists per second (Grays/s)",
+            "value": res["fp32_d22"]["grays_per_s"], "unit": "Grays/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "dtype": "f32 (+f64 refinement)",
+            "data": "synthetic",
+            "config": {"workload": "hair candidate lists: 2^20 rays (10% grazing) over 100k strands x 8 "
+                                   "segments (+1e3 offset), 6..15 shuffled segments of neighbouring strands "
+                                   "per ray", "rays": n, "candidates": nc, "max_candidates": mc,
+                       "launch": "one initialising kernel, then one persistent k_fused launch per list "
+                                 "position (max_candidates launches)"},
+            "results": res}
+    print(json.dumps(line), flush=True)
+
+
 def bench_degenerate(args):
     """Degenerate-geometry batch: 2^22 pairs in four families (cusps,
     near-collinear points, zero end tangents, steep tapers), per-pair depth
@@ -325,6 +400,9 @@ def main():
         return
     if args.workload == "degenerate":
         bench_degenerate(args)
+        return
+    if args.workload == "candidates":
+        bench_candidates(args)
         return
 
     import numpy as np

@@ -249,6 +249,65 @@ int fiber_intersect_counts(const float *rays, int64_t ray_stride, int64_t n_rays
                            void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Nearest hit over candidate lists                                         */
+/* ------------------------------------------------------------------------ */
+
+/* Bytes of device workspace fiber_intersect_candidates can use: the fiber
+ * records (64 bytes per fiber, 256-byte aligned) when the lists hold at
+ * least as many candidates as the table has fibers, else 0. */
+size_t fiber_candidates_workspace_bytes(int64_t n_candidates, int64_t n_fibers, uint32_t flags);
+
+/*
+ * fiber_intersect_candidates -- nearest hit of each ray over its candidate
+ * list.
+ *
+ * Operation: the interface a renderer's top-level hierarchy calls (Sec. 1
+ * and Sec. 4 place the method below such a hierarchy: the fibers referenced
+ * by the leaves a ray reaches are tested one after another, and a hit
+ * shortens the ray for the fibers after it). Ray r's candidates are
+ * cand_fiber[cand_offsets[r]] .. cand_fiber[cand_offsets[r + 1] - 1]; each is
+ * tested with the per-pair routine of fiber_intersect_pairs at depth
+ * cand_depth[k] (or `depth`), against the ray's tmax until a hit and against
+ * the latest hit's t after it. A hit counts when its t lies below that
+ * limit, so of equal hits the first in the list is kept. The outputs
+ * describe the kept hit: t, u, hit and the normal as for
+ * fiber_intersect_pairs, and fiber_out the index of its fiber (-1 when no
+ * candidate is hit). With FI_FP64_REFINE, candidates of depth > 16 are
+ * decided in FP64 as there, against the FP64 nearest hit so far.
+ *
+ * Arguments: the ray and fiber tables as for fiber_intersect_pairs;
+ * cand_offsets: n_rays + 1 non-decreasing int64 (CSR), cand_offsets[0] >= 0,
+ * cand_offsets[n_rays] <= n_candidates; cand_fiber: n_candidates int32 fiber
+ * indices (an index outside the table is a candidate that misses);
+ * cand_depth: n_candidates uint8 depths, or NULL to use `depth`;
+ * max_candidates: the number of list positions tested -- at least the
+ * longest list; a longer list is tested on its first max_candidates entries
+ * only; outputs: n_rays entries each (normal_out: three rows of n_rays, or
+ * NULL); workspace as for fiber_intersect_pairs (size:
+ * fiber_candidates_workspace_bytes), or NULL.
+ *
+ * Implementation: an initialising kernel writes misses, then one persistent
+ * launch per list position k (max_candidates launches in stream order), each
+ * testing every ray's k-th candidate against the nearest hit of positions
+ * before k and writing only hits.
+ *
+ * Errors: FI_ERR_NULL (rays, fibers, cand_offsets or an output NULL with
+ * n_rays > 0; cand_fiber NULL with n_candidates > 0; t64_out/u64_out under
+ * FI_FP64_REFINE), FI_ERR_RANGE (negative counts, strides below the counts,
+ * depth outside [0, 23], unknown flags, n_rays >= 2^31 - 64),
+ * FI_ERR_WORKSPACE (misaligned), FI_ERR_HIP. Nothing is enqueued on an
+ * argument error; the call allocates, frees and waits for nothing.
+ */
+int fiber_intersect_candidates(const float *rays, int64_t ray_stride, int64_t n_rays,
+                               const float *fibers, int64_t fiber_stride, int64_t n_fibers,
+                               const int64_t *cand_offsets, const int32_t *cand_fiber,
+                               const uint8_t *cand_depth, int32_t depth, int32_t max_candidates,
+                               int64_t n_candidates, uint32_t flags,
+                               float *t_out, float *u_out, uint8_t *hit_out, int32_t *fiber_out,
+                               double *t64_out, double *u64_out, float *normal_out,
+                               void *workspace, size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Many independent problems in one launch                                  */
 /* ------------------------------------------------------------------------ */
 

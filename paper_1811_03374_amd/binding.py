@@ -44,6 +44,11 @@ def lib():
         L.fiber_intersect_counts.restype = C.c_int
         L.fiber_pairs_workspace_bytes.argtypes = [i64, i64, i32, u32]
         L.fiber_pairs_workspace_bytes.restype = C.c_size_t
+        L.fiber_candidates_workspace_bytes.argtypes = [i64, i64, u32]
+        L.fiber_candidates_workspace_bytes.restype = C.c_size_t
+        L.fiber_intersect_candidates.argtypes = [vp, i64, i64, vp, i64, i64, vp, vp, vp, i32, i32, i64, u32,
+                                                 vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
+        L.fiber_intersect_candidates.restype = C.c_int
         L.fi_init_device.restype = C.c_int
         L.fi_strerror.argtypes = [C.c_int]
         L.fi_strerror.restype = C.c_char_p
@@ -55,6 +60,7 @@ def lib():
 def exported_symbols():
     return ["fi_version", "fi_strerror", "fi_init_device", "fiber_pairs_workspace_bytes",
             "fiber_intersect_pairs", "fiber_intersect_pairs_noalloc", "fiber_intersect_counts",
+            "fiber_candidates_workspace_bytes", "fiber_intersect_candidates",
             "fiber_batched_workspace_bytes", "fiber_intersect_batched", "fiber_batch_plan_create",
             "fiber_batch_plan_launch", "fiber_batch_plan_tuning", "fiber_batch_plan_destroy",
             "fiber_batch_autotune"]
@@ -252,6 +258,56 @@ def intersect_pairs_noalloc(rays: torch.Tensor, fibers: torch.Tensor, depth: int
         _ptr(nrm), _stream(stream)))
     extra = (nrm,) if nrm is not None else ()
     return ((t, u, hit, t64, u64) if refine else (t, u, hit)) + extra
+
+
+def intersect_candidates(rays: torch.Tensor, fibers: torch.Tensor, offsets: torch.Tensor,
+                         cand_fiber: torch.Tensor, depth: int = 9,
+                         cand_depth: Optional[torch.Tensor] = None, max_candidates: Optional[int] = None,
+                         refine: bool = False, normal=None, stream=None,
+                         workspace: Optional[torch.Tensor] = None):
+    """Nearest hit of each ray over its candidate list (see
+    ``fiber_intersect_candidates``): ``offsets`` (n_rays + 1) int64 CSR over
+    ``cand_fiber`` int32 (and optional per-candidate uint8 ``cand_depth``).
+    Returns (t, u, hit, fiber) device tensors, then (t64, u64) when
+    ``refine``, then the (3, n_rays) normals when ``normal``. Without
+    ``max_candidates`` the longest list is measured (one device sync)."""
+    rs = _table(rays, 7, "rays")
+    fs = _table(fibers, 16, "fibers")
+    n = rays.shape[1]
+    off = _index(offsets, torch.int64, "offsets")
+    cf = _index(cand_fiber, torch.int32, "cand_fiber")
+    cd = _index(cand_depth, torch.uint8, "cand_depth")
+    if off is None or off.numel() != n + 1:
+        raise ValueError(f"offsets must hold n_rays + 1 = {n + 1} entries")
+    if cf is None:
+        raise ValueError("cand_fiber is required")
+    if cd is not None and cd.numel() != cf.numel():
+        raise ValueError("cand_depth must hold one depth per candidate")
+    if max_candidates is None:
+        max_candidates = int((off[1:] - off[:-1]).max().item()) if n else 0
+    dev = rays.device
+    t = torch.empty(n, dtype=torch.float32, device=dev)
+    u = torch.empty(n, dtype=torch.float32, device=dev)
+    hit = torch.empty(n, dtype=torch.uint8, device=dev)
+    fib = torch.empty(n, dtype=torch.int32, device=dev)
+    t64 = torch.empty(n, dtype=torch.float64, device=dev) if refine else None
+    u64 = torch.empty(n, dtype=torch.float64, device=dev) if refine else None
+    nrm = _normal_tensor(normal, n, dev)
+    if workspace is None:
+        nb = lib().fiber_candidates_workspace_bytes(int(cf.numel()), int(fibers.shape[1]), 0)
+        workspace = torch.empty(nb, dtype=torch.uint8, device=dev) if nb else None
+        _keep_for(workspace, stream)
+    ws = _ws_args(workspace)
+    _check(lib().fiber_intersect_candidates(
+        _ptr(rays), rs, n, _ptr(fibers), fs, fibers.shape[1], _ptr(off), _ptr(cf), _ptr(cd), int(depth),
+        int(max_candidates), int(cf.numel()), FI_FP64_REFINE if refine else 0, _ptr(t), _ptr(u), _ptr(hit),
+        _ptr(fib), _ptr(t64), _ptr(u64), _ptr(nrm), *ws, _stream(stream)))
+    out = (t, u, hit, fib)
+    if refine:
+        out += (t64, u64)
+    if nrm is not None:
+        out += (nrm,)
+    return out
 
 
 class PreparedPairs:

@@ -258,6 +258,12 @@ struct Args {
     int32_t *counts;                       // counting mode
     double *t64_out; double *u64_out;      // refinement
     float *normal_out;                     // normals (3 rows of n_pairs), or null
+    // candidate lists: pair i is ray i against its candidate number
+    // cand_round (cand_fiber[cand_off[i] + cand_round]), tested against the
+    // ray shortened to the nearest hit so far; pair_depth then indexes the
+    // candidates. Null cand_off: plain pairs.
+    const int64_t *cand_off; const int32_t *cand_fiber; int32_t cand_round; int64_t n_cand;
+    int32_t *fiber_out;                    // the fiber of each ray's nearest hit
 };
 
 // ---------------------------------------------------------------------------
@@ -777,19 +783,21 @@ __device__ __forceinline__ void solid_normal(const Curve64 &c, double t, double 
     n[2] = ez + tilt * D[2] / dl;
 }
 
+// `fiber` >= 0 names the fiber directly (candidate lists); `tmax` is the
+// FP64 limit of the search.
 __device__ __noinline__ Refined refine_whole_curve(const float *rays, int64_t ray_stride, const float *fibers,
                                                    int64_t fiber_stride, const int32_t *pair_ray,
-                                                   const int32_t *pair_fiber, int64_t i, float tmax, float t0,
-                                                   float u0, bool normal)
+                                                   const int32_t *pair_fiber, int64_t i, int64_t fiber,
+                                                   double tmax, float t0, float u0, bool normal)
 {
     Refined r;
     const int64_t ri = pair_ray ? (int64_t)pair_ray[i] : i;
-    const int64_t fi = pair_fiber ? (int64_t)pair_fiber[i] : i;
+    const int64_t fi = fiber >= 0 ? fiber : pair_fiber ? (int64_t)pair_fiber[i] : i;
     Curve64 cv;
     double frame[9];
     if (!curve_in_ray_frame(rays + ri, ray_stride, fibers + fi, fiber_stride, cv, frame)) return r;
     double t = INFINITY, u = __builtin_nan("");
-    leaf_candidates<kCurveSamples>(cv, 0.0, 1.0, 0.0, (double)tmax, (double)tmax, (double)t0, (double)u0, t, u);
+    leaf_candidates<kCurveSamples>(cv, 0.0, 1.0, 0.0, tmax, tmax, (double)t0, (double)u0, t, u);
     if (t < INFINITY) {
         r.t = t;
         r.u = u;
@@ -991,6 +999,7 @@ __device__ __forceinline__ int trip(Lane &L, const Root &root, float *col, HitGe
 // plane: the tolerance keeps such hits on the cap. The vector is formed in
 // the ray frame and turned back into world space with the frame of the
 // pair's ray (rebuilt in FP64, as for the projection).
+template <bool CAND>
 __device__ __forceinline__ void leaf_normal(const Args &a, int64_t i, const Lane &L, const HitGeo &hg, float &nx,
                                             float &ny, float &nz)
 {
@@ -1021,7 +1030,7 @@ __device__ __forceinline__ void leaf_normal(const Args &a, int64_t i, const Lane
             vz = near1 ? bz : -az;
         }
     }
-    const int64_t ri = a.pair_ray ? (int64_t)a.pair_ray[i] : i;
+    const int64_t ri = a.pair_ray && !CAND ? (int64_t)a.pair_ray[i] : i;
     const float *R = a.rays + ri;
     const int64_t rs = a.ray_stride;
     const double dx = R[3 * rs], dy = R[4 * rs], dz = R[5 * rs];
@@ -1042,8 +1051,8 @@ __device__ __forceinline__ void leaf_normal(const Args &a, int64_t i, const Lane
 // onto the leaf chord; hit when t < tmax). A refined pair (depth > 16 under
 // FI_FP64_REFINE) reports its FP64 surface hit, decided in FP64.
 // `hg` is the leaf geometry of a plain hit; `ref` the FP64 result of a
-// refined pair (used when `reached`).
-template <int MODE>
+// refined pair (used when `reached`). CAND: candidate lists (see Args).
+template <int MODE, bool CAND = false>
 __device__ __forceinline__ void finish(const Args &a, int64_t i, const Lane &L, bool reached,
                                        HitGeo hg = HitGeo{}, Refined ref = Refined{})
 {
@@ -1065,6 +1074,12 @@ __device__ __forceinline__ void finish(const Args &a, int64_t i, const Lane &L, 
         u64 = u;
         hit = true;
     }
+    if constexpr (CAND) {
+        // candidate lists: a miss leaves the ray's nearest hit so far; a
+        // hit (nearer by construction: tmax was shortened to it) replaces it
+        if (!hit) return;
+        a.fiber_out[i] = a.cand_fiber[a.cand_off[i] + a.cand_round];
+    }
     a.t_out[i] = t;
     a.u_out[i] = u;
     a.hit_out[i] = hit ? 1 : 0;
@@ -1077,7 +1092,7 @@ __device__ __forceinline__ void finish(const Args &a, int64_t i, const Lane &L, 
         if (MODE == kConservative && L.slack >= 0.0f) {
             if (hit) { nx = ref.nx; ny = ref.ny; nz = ref.nz; }
         } else if (hit) {
-            leaf_normal(a, i, L, hg, nx, ny, nz);
+            leaf_normal<CAND>(a, i, L, hg, nx, ny, nz);
         }
         a.normal_out[i] = nx;
         a.normal_out[a.n_pairs + i] = ny;
@@ -1146,17 +1161,43 @@ __device__ __forceinline__ int find_scene(const int64_t *offsets, int n_scenes, 
 // `aos`, when given, holds the fibers as 16 consecutive floats each (see
 // k_fibers_aos): a gathered fiber is then one or two cache lines instead of
 // one line per coordinate row.
+// In candidate mode (cand_off given) pair i is ray i against its candidate
+// number cand_round; a ray without that candidate, or with an invalid one,
+// is a definite miss too (its callers then leave the ray's nearest hit so far
+// as it is), and tmax is the ray's tmax shortened to that hit.
+template <bool CAND>
 __device__ __forceinline__ bool load_pair(const Args &a, int64_t i, float *q, float &tmax, uint32_t &depth,
                                           const float *aos)
 {
-    const int64_t ri = a.pair_ray ? (int64_t)a.pair_ray[i] : i;
-    const int64_t fi = a.pair_fiber ? (int64_t)a.pair_fiber[i] : i;
-    depth = a.pair_depth ? (uint32_t)a.pair_depth[i] : (uint32_t)a.depth;
+    int64_t ri, fi;
+    if constexpr (CAND) {
+        const int64_t o = a.cand_off[i] + a.cand_round;
+        if (o >= a.cand_off[i + 1] || o < 0 || o >= a.n_cand) return false;
+        ri = i;
+        fi = a.cand_fiber[o];
+        depth = a.pair_depth ? (uint32_t)a.pair_depth[o] : (uint32_t)a.depth;
+    } else {
+        ri = a.pair_ray ? (int64_t)a.pair_ray[i] : i;
+        fi = a.pair_fiber ? (int64_t)a.pair_fiber[i] : i;
+        depth = a.pair_depth ? (uint32_t)a.pair_depth[i] : (uint32_t)a.depth;
+    }
     if (ri < 0 || ri >= a.n_rays || fi < 0 || fi >= a.n_fibers || depth > FI_MAX_DEPTH) return false;
     const float *R = a.rays + ri;
     const int64_t rs = a.ray_stride;
     tmax = R[6 * rs];
     if (!(tmax == tmax)) return false;
+    if constexpr (CAND) {
+        if (a.t64_out) {
+            // refined candidates: the FP64 nearest hit so far, rounded up
+            // (the FP32 search prunes conservatively; FP64 decides)
+            const double b = a.t64_out[i];
+            float f = (float)b;
+            if ((double)f < b) f = __uint_as_float(__float_as_uint(f) + 1u);     // b >= 0: one ulp up
+            tmax = fminf(tmax, f);
+        } else {
+            tmax = fminf(tmax, a.t_out[i]);
+        }
+    }
     const float *F = aos ? aos + 16 * fi : a.fibers + fi;
     const int64_t fs = aos ? 1 : a.fiber_stride;
     const double dx = R[3 * rs], dy = R[4 * rs], dz = R[5 * rs];
@@ -1218,7 +1259,7 @@ __device__ __forceinline__ void wave_range(int64_t w, int64_t waves, int64_t cou
 #ifndef FIBERHIT_WAVES
 #define FIBERHIT_WAVES 4                      // build knob: register budget (waves per SIMD)
 #endif
-template <int MODE, bool BATCHED>
+template <int MODE, bool BATCHED, bool CAND = false>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MODE == kConservative ? 4 : FIBERHIT_WAVES, 8)))
 void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, int64_t count, int refill,
              const float *aos)
@@ -1265,13 +1306,13 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
                     idx -= offsets[sc];
                     a = scenes[sc];
                 }
-                const bool ok = load_pair(a, idx, stage, rtmax, depth, aos);
+                const bool ok = load_pair<CAND>(a, idx, stage, rtmax, depth, aos);
                 asm volatile("" ::: "memory");
                 float *f = &r.p.x;
 #pragma unroll
                 for (int k = 0; k < 16; ++k) f[k] = stage[k * kQueue];
                 if (!ok) {
-                    finish_invalid<MODE>(a, idx);
+                    if (!CAND) finish_invalid<MODE>(a, idx);
                 } else {
                     cap_interval(r, rtmax, rlo, rhi);
                     float te, tx, lu, hu;
@@ -1293,7 +1334,7 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
                         D.level = 0;
                         D.trips = 1;
                         D.slack = slack;
-                        finish<MODE>(a, idx, D, vis, hit_geo(r, D.t, te < lu));
+                        finish<MODE, CAND>(a, idx, D, vis, hit_geo(r, D.t, te < lu));
                     }
                 }
             }
@@ -1370,7 +1411,7 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
                 if (L.scene == scene0) finish<MODE>(scenes[scene0], L.pair, L, st == kHit, hg);
                 else finish<MODE>(scenes[L.scene], L.pair, L, st == kHit, hg);
             } else {
-                finish<MODE>(a0, L.pair, L, st == kHit, hg);
+                finish<MODE, CAND>(a0, L.pair, L, st == kHit, hg);
             }
             active = false;
         }
@@ -1395,12 +1436,20 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
                         pr = sc->pair_ray; pf = sc->pair_fiber;
                         want_n = sc->normal_out != nullptr;
                     }
-                    const Refined r = refine_whole_curve(rays, rs, fibers, fs, pr, pf, L.pair, L.tmax, L.t, L.ru,
+                    int64_t fi = -1;
+                    double tlim = L.tmax;
+                    if (CAND) {
+                        // candidate lists: the ray's tmax shortened to its
+                        // FP64 nearest hit so far
+                        fi = a0.cand_fiber[a0.cand_off[L.pair] + a0.cand_round];
+                        tlim = fmin((double)rays[6 * rs + L.pair], a0.t64_out[L.pair]);
+                    }
+                    const Refined r = refine_whole_curve(rays, rs, fibers, fs, pr, pf, L.pair, fi, tlim, L.t, L.ru,
                                                          want_n);
                     // the output pointers are read after the call (not kept
                     // live across it)
                     if constexpr (BATCHED) finish<MODE>(scenes[L.scene], L.pair, L, r.hit, HitGeo{}, r);
-                    else finish<MODE>(a0, L.pair, L, r.hit, HitGeo{}, r);
+                    else finish<MODE, CAND>(a0, L.pair, L, r.hit, HitGeo{}, r);
                     active = false;
                 }
             }
@@ -1424,6 +1473,27 @@ __global__ __launch_bounds__(256) void k_fibers_aos(const float *F, int64_t fs, 
     for (int k = 0; k < 4; ++k)
         out[4 * f + k] = make_float4(F[(4 * k) * fs + f], F[(4 * k + 1) * fs + f], F[(4 * k + 2) * fs + f],
                                      F[(4 * k + 3) * fs + f]);
+}
+
+// Candidate lists start as misses (each round then writes the hits).
+__global__ __launch_bounds__(256) void k_cand_init(int64_t n, float *t, float *u, uint8_t *hit, int32_t *fiber,
+                                                   double *t64, double *u64, float *nrm)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    t[i] = INFINITY;
+    u[i] = __builtin_nanf("");
+    hit[i] = 0;
+    fiber[i] = -1;
+    if (t64) {
+        t64[i] = INFINITY;
+        u64[i] = __builtin_nan("");
+    }
+    if (nrm) {
+        nrm[i] = __builtin_nanf("");
+        nrm[n + i] = __builtin_nanf("");
+        nrm[2 * n + i] = __builtin_nanf("");
+    }
 }
 
 int check_common(const float *rays, int64_t ray_stride, int64_t n_rays,
@@ -1450,12 +1520,15 @@ int check_common(const float *rays, int64_t ray_stride, int64_t n_rays,
 
 using FusedFn = void (*)(Args, const Args *, const int64_t *, int, int64_t, int, const float *);
 // [0] plain, [1] counting, [2] conservative (single calls), [3] plain and
-// [4] conservative over a scene table
-constexpr int kVariants = 5;
+// [4] conservative over a scene table, [5] plain and [6] conservative over
+// candidate lists
+constexpr int kVariants = 7;
 const FusedFn kFused[kVariants] = {k_fused<kPlain, false>, k_fused<kCount, false>, k_fused<kConservative, false>,
-                                   k_fused<kPlain, true>, k_fused<kConservative, true>};
+                                   k_fused<kPlain, true>, k_fused<kConservative, true>,
+                                   k_fused<kPlain, false, true>, k_fused<kConservative, false, true>};
 constexpr int kBatchedVariant = 3;
 constexpr int kBatchedRefineVariant = 4;
+constexpr int kCandVariant = 5;              // + 1: refined
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 constexpr size_t kMaxRecordBytes = (size_t)1 << 30;                 // fiber records, largest table
@@ -1607,19 +1680,22 @@ int64_t single_call_waves(const DeviceInfo &d, int mode, const Args &)
     return (int64_t)d.fused_resident[mode] * d.cus;
 }
 
-// Enqueue one single call on `s`: the fiber records (when `aos` is given),
-// then one persistent launch of about one wave per 64 pairs, at most
-// `max_waves`.
-int launch(int mode, const Args &a, int64_t max_waves, float *aos, hipStream_t s)
+// Enqueue one single call on `s`: the fiber records (when `aos` is given and
+// `convert`), then one persistent launch of about one wave per 64 pairs, at
+// most `max_waves`.
+int launch(int mode, const Args &a, int64_t max_waves, float *aos, hipStream_t s, bool convert = true)
 {
-    if (aos)
+    if (aos && convert)
         hipLaunchKernelGGL(k_fibers_aos, dim3((unsigned)((a.n_fibers + 255) / 256)), dim3(256), 0, s,
                            a.fibers, a.fiber_stride, a.n_fibers, (float4 *)aos);
     int64_t g = (a.n_pairs + kWave - 1) / kWave;
     if (g > max_waves) g = max_waves;
     if (g > 0)
         hipLaunchKernelGGL(kFused[mode], dim3((unsigned)g), dim3(kWave), 0, s, a, nullptr, nullptr, 0,
-                           a.n_pairs, mode == kConservative ? FIBERHIT_REFINE_REFILL : FIBERHIT_FUSED_REFILL, aos);
+                           a.n_pairs,
+                           mode == kConservative || mode == kCandVariant + 1 ? FIBERHIT_REFINE_REFILL
+                                                                             : FIBERHIT_FUSED_REFILL,
+                           aos);
     return hipGetLastError() == hipSuccess ? FI_OK : FI_ERR_HIP;
 }
 
@@ -1735,7 +1811,7 @@ struct fi_batch_plan {
 };
 
 extern "C" {
-int fi_version(void) { return (0 << 16) | (7 << 8) | 0; }
+int fi_version(void) { return (0 << 16) | (8 << 8) | 0; }
 
 const char *fi_strerror(int status)
 {
@@ -1830,6 +1906,58 @@ int fiber_intersect_counts(const float *rays, int64_t ray_stride, int64_t n_rays
            pair_ray, pair_fiber, pair_depth, depth, n_pairs, t_out, u_out, hit_out, counts_out, nullptr, nullptr,
            nullptr};
     return launch_with_workspace(kCount, a, workspace, workspace_bytes, stream);
+}
+
+size_t fiber_candidates_workspace_bytes(int64_t n_candidates, int64_t n_fibers, uint32_t flags)
+{
+    (void)flags;
+    if (n_candidates < 0 || n_fibers < 0) return 0;
+    return record_bytes(n_candidates, n_fibers, true);
+}
+
+int fiber_intersect_candidates(const float *rays, int64_t ray_stride, int64_t n_rays,
+                               const float *fibers, int64_t fiber_stride, int64_t n_fibers,
+                               const int64_t *cand_offsets, const int32_t *cand_fiber,
+                               const uint8_t *cand_depth, int32_t depth, int32_t max_candidates,
+                               int64_t n_candidates, uint32_t flags,
+                               float *t_out, float *u_out, uint8_t *hit_out, int32_t *fiber_out,
+                               double *t64_out, double *u64_out, float *normal_out,
+                               void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (n_rays < 0 || n_fibers < 0 || n_candidates < 0 || max_candidates < 0) return FI_ERR_RANGE;
+    if (depth < 0 || depth > FI_MAX_DEPTH) return FI_ERR_RANGE;
+    if ((flags & ~(uint32_t)(FI_FP64_REFINE | FI_COMPENSATED_PROJ)) != 0u) return FI_ERR_RANGE;
+    if (n_rays == 0) return FI_OK;
+    if (!rays || !fibers || !cand_offsets || !t_out || !u_out || !hit_out || !fiber_out) return FI_ERR_NULL;
+    if (n_candidates > 0 && !cand_fiber) return FI_ERR_NULL;
+    if (ray_stride < n_rays || fiber_stride < n_fibers) return FI_ERR_RANGE;
+    if (n_rays > (int64_t)0x7fffffff - 64) return FI_ERR_RANGE;
+    const bool refine = (flags & FI_FP64_REFINE) != 0u;
+    if (refine && (!t64_out || !u64_out)) return FI_ERR_NULL;
+    if (workspace && ((uintptr_t)workspace & 255u) != 0u) return FI_ERR_WORKSPACE;
+    (void)hipGetLastError();
+    DeviceInfo *d = nullptr;
+    const int ds = device_info(d);
+    if (ds != FI_OK) return ds;
+    const hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_cand_init, dim3((unsigned)((n_rays + 255) / 256)), dim3(256), 0, s, n_rays, t_out, u_out,
+                       hit_out, fiber_out, refine ? t64_out : nullptr, refine ? u64_out : nullptr, normal_out);
+    if (hipGetLastError() != hipSuccess) return FI_ERR_HIP;
+    const int mode = refine ? kCandVariant + 1 : kCandVariant;
+    Args a{rays, ray_stride, n_rays, fibers, fiber_stride, n_fibers,
+           nullptr, nullptr, cand_depth, depth, n_rays, t_out, u_out, hit_out, nullptr,
+           refine ? t64_out : nullptr, refine ? u64_out : nullptr, normal_out,
+           cand_offsets, cand_fiber, 0, n_candidates, fiber_out};
+    const size_t rec = record_bytes(n_candidates, n_fibers, true);
+    float *aos = rec && workspace && workspace_bytes >= rec ? (float *)workspace : nullptr;
+    // one launch per list position, in order: round k tests every ray's k-th
+    // candidate against the ray shortened to its nearest hit of rounds < k
+    for (int32_t k = 0; k < max_candidates; ++k) {
+        a.cand_round = k;
+        const int st = launch(mode, a, single_call_waves(*d, mode, a), aos, s, k == 0);
+        if (st != FI_OK) return st;
+    }
+    return FI_OK;
 }
 
 size_t fiber_batched_workspace_bytes(int32_t n_scenes, int64_t total_pairs)

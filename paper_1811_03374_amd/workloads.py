@@ -416,26 +416,34 @@ def hair_candidates(n_rays: int = 1 << 20, n_strands: int = 100_000, depth: int 
     j = rng.integers(0, segments, n)
     target = (strand * segments + j).astype(np.int32)
     n_other = rng.integers(1, 5, n)
-    lists = []
-    counts = np.empty(n, np.int64)
+    # strands: the aimed one, then up to 4 from the same or a neighbouring
+    # root cell (a cell may be empty: that strand is dropped)
+    st = np.empty((n, 5), np.int64)
+    have = np.zeros((n, 5), bool)
+    st[:, 0] = strand
+    have[:, 0] = True
     cx, cy = cell[strand, 0], cell[strand, 1]
-    for i in range(n):
-        segs = [strand[i] * segments + k for k in (j[i] - 1, j[i], j[i] + 1) if 0 <= k < segments]
-        for _ in range(int(n_other[i])):
-            ox = min(g - 1, max(0, cx[i] + int(rng.integers(-1, 2))))
-            oy = min(g - 1, max(0, cy[i] + int(rng.integers(-1, 2))))
-            c = ox * g + oy
-            if start[c + 1] == start[c]:
-                continue
-            b = order[rng.integers(start[c], start[c + 1])]
-            segs += [b * segments + k for k in (j[i] - 1, j[i], j[i] + 1) if 0 <= k < segments]
-        segs = np.array(segs, np.int32)
-        rng.shuffle(segs)
-        lists.append(segs)
-        counts[i] = len(segs)
+    for k in range(1, 5):
+        ox = np.clip(cx + rng.integers(-1, 2, n), 0, g - 1)
+        oy = np.clip(cy + rng.integers(-1, 2, n), 0, g - 1)
+        c = ox * g + oy
+        size = start[c + 1] - start[c]
+        pick = start[c] + (rng.random(n) * np.maximum(size, 1)).astype(np.int64)
+        st[:, k] = order[np.minimum(pick, len(order) - 1)]
+        have[:, k] = (k <= n_other) & (size > 0)
+    # segments j - 1 .. j + 1 of each strand, inside the strand
+    jj = j[:, None, None] + np.array([-1, 0, 1])[None, None, :]
+    segs = (st[:, :, None] * segments + jj).reshape(n, 15)
+    mask = (have[:, :, None] & (jj >= 0) & (jj < segments)).reshape(n, 15)
+    # each list in random order
+    keys = np.where(mask, rng.random((n, 15)), 2.0)
+    perm = np.argsort(keys, axis=1)
+    segs = np.take_along_axis(segs, perm, axis=1)
+    counts = mask.sum(axis=1).astype(np.int64)
+    keep = np.arange(15)[None, :] < counts[:, None]
     off = np.zeros(n + 1, np.int64)
     np.cumsum(counts, out=off[1:])
-    cand = np.concatenate(lists).astype(np.int32)
+    cand = segs[keep].astype(np.int32)
     aim = hair_precision(n, n_strands, depth, seed=seed + 1, chunk=chunk, targets=target, strands=P32)
     return Workload(f"hair_candidates_{n}", aim.rays, fibers, None, None, depth,
                     meta={"cand_off": off, "cand_fiber": cand, "target": target,
