@@ -31,6 +31,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the 2^20-pair line (no hair and batched blocks)")
     ap.add_argument("--workload", choices=("straight_and_curved", "batched", "hair", "degenerate", "candidates"),
                     default="straight_and_curved",
                     help="batched: 256 uneven scenes (~13 M pairs, adaptive depth), one graph launch "
@@ -46,6 +48,17 @@ def parse():
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1811_03374_amd", "csrc", "fiberhit.hip")
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def kernel_source_hash():
@@ -87,10 +100,10 @@ def _timed(fn, steps, warmup, stream):
     return e0.elapsed_time(e1) / steps
 
 
-def bench_batched(args):
+def batched_block(steps, warmup):
     """256 independent scenes of round(2^U(10, 18)) pairs with per-segment
     adaptive depth: autotune, then one captured-graph launch against one
-    plain launch per scene, on the same stream."""
+    plain launch per scene, on the same stream. Returns a dict."""
     import numpy as np
     import torch
     from concurrent.futures import ProcessPoolExecutor
@@ -118,23 +131,31 @@ def bench_batched(args):
             binding.intersect_pairs(p.rays, p.fibers, 22, pair_depth=p.pair_depth,
                                     out=(p.t, p.u, p.hit), stream=stream)
 
-    ms_graph = _timed(lambda: plan.launch(stream), args.steps, args.warmup, stream)
-    ms_plain = _timed(plain, args.steps, args.warmup, stream)
+    ms_graph = _timed(lambda: plan.launch(stream), steps, warmup, stream)
+    ms_plain = _timed(plain, steps, warmup, stream)
     depth_hist = np.bincount(np.concatenate([w.pair_depth for w in scenes]), minlength=23)
+    plan.close()
+    return {"gpairs_per_s": total / (ms_graph * 1e-3) / 1e9, "graph_launch_ms": ms_graph,
+            "plain_launches_ms": ms_plain, "plain_gpairs_per_s": total / (ms_plain * 1e-3) / 1e9,
+            "batched_over_plain": ms_plain / ms_graph, "autotuned": best, "autotune_best_ms": best_ms,
+            "workload": "256 scenes, round(2^U(10,18)) pairs each, curved random-walk fibers, "
+                        "per-segment adaptive depth 2..22",
+            "pairs": total, "scenes": 256, "depth_histogram": depth_hist.tolist()}
+
+
+def bench_batched(args):
+    b = batched_block(args.steps, args.warmup)
     line = {
         "metric": "ray-fiber intersections/sec (Gpairs/s), batched uneven scenes",
-        "value": total / (ms_graph * 1e-3) / 1e9, "unit": "Gpairs/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_graph,
+        "value": b["gpairs_per_s"], "unit": "Gpairs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": b["graph_launch_ms"],
         "higher_is_better": True, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "256 scenes, round(2^U(10,18)) pairs each, curved random-walk "
-                               "fibers, per-segment adaptive depth 2..22",
-                   "pairs": total, "scenes": 256, "depth_histogram": depth_hist.tolist()},
-        "graph_launch_ms": ms_graph, "plain_launches_ms": ms_plain,
-        "plain_gpairs_per_s": total / (ms_plain * 1e-3) / 1e9,
-        "batched_over_plain": ms_plain / ms_graph,
-        "autotuned": best, "autotune_best_ms": best_ms,
+        "config": {"workload": b["workload"], "pairs": b["pairs"], "scenes": b["scenes"],
+                   "depth_histogram": b["depth_histogram"]},
+        "graph_launch_ms": b["graph_launch_ms"], "plain_launches_ms": b["plain_launches_ms"],
+        "plain_gpairs_per_s": b["plain_gpairs_per_s"], "batched_over_plain": b["batched_over_plain"],
+        "autotuned": b["autotuned"], "autotune_best_ms": b["autotune_best_ms"],
     }
-    plan.close()
     print(json.dumps(line), flush=True)
 
 
@@ -157,6 +178,72 @@ def refine_probe():
     print(json.dumps({"refine_probe": True, "pairs": w.n_pairs,
                       "hit_rate": float(out[2].float().mean().item()),
                       "kernel_source_sha256_16": kernel_source_hash()}))
+
+
+def hair_block(steps, warmup, cpu=True):
+    """The hair configuration in FP32 as one block of the default line: 2^24
+    rays against 800,000 segments gathered through an int32 index, at depth
+    9 and 22. Per depth: the call time (HIP events around `steps` calls on
+    one stream), its roofline from the traversal's counted work, parity on a
+    seeded 4,096-pair sample against the depth oracle with the tie
+    resolver, and the oracle timed on a 2^14-pair sample."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1811_03374_amd import binding, workmodel
+    from paper_1811_03374_amd import workloads as W
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity import compare, oracle_with_band, tie_resolver
+
+    w = W.hair_precision(1 << 24, 100_000)
+    dev = torch.device("cuda:0")
+    rays, fibers = torch.from_numpy(w.rays).to(dev), torch.from_numpy(w.fibers).to(dev)
+    pf = torch.from_numpy(w.pair_fiber).to(dev)
+    n, nf = w.n_pairs, w.fibers.shape[1]
+    stream = torch.cuda.current_stream()
+    out = {}
+    idx = np.sort(np.random.default_rng(11).choice(n, 4096, replace=False))
+    ws = w.subset(idx)
+    for d in (9, 22):
+        _, _, h, cn = binding.intersect_pairs(rays, fibers, d, pair_fiber=pf, counts=True)
+        s_ = cn.to(torch.int64).sum(dim=0).cpu().numpy()
+        hits = int(h.sum().item())
+        fl = workmodel.flops(n, int(s_[0]), int(s_[1]), int(s_[2]), hits)
+        by = workmodel.bytes_gathered(n, nf)
+        call = binding.PreparedPairs(rays, fibers, d, pair_fiber=pf)
+        ms = _timed(lambda: call.launch(stream), steps, warmup, stream)
+        t, u, hh = (x.cpu().numpy() for x in call.launch(stream))
+        torch.cuda.synchronize()
+        (t_o, u_o, h_o), band = oracle_with_band(ws, d)
+        st = compare(t[idx], u[idx], hh[idx], t_o, u_o, h_o, band, d, alt=tie_resolver(ws, d))
+        tfl = fl / (ms * 1e-3) / 1e12
+        out[str(d)] = {"launch_ms_avg": ms, "gpairs_per_s": n / (ms * 1e-3) / 1e9,
+                       "roofline": {"bound": "alu", "achieved": tfl, "peak": workmodel.PEAK_FP32_TFLOPS,
+                                    "unit": "TFLOP/s", "frac": tfl / workmodel.PEAK_FP32_TFLOPS,
+                                    "traffic": None, "algorithmic_bytes": by,
+                                    "hbm_gbs_algorithmic": by / (ms * 1e-3) / 1e9},
+                       "tests_per_pair": int(s_[0]) / n, "hit_rate": hits / n,
+                       "parity_sample": {k: st[k] for k in ("ok", "pairs", "flag_disagree_outside_band",
+                                                            "max_rel_t", "max_abs_u", "tie_resolved")}}
+    cpu_res = None
+    if cpu:
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+        cs = w.subset(np.arange(1 << 21))
+        passes, spent = 0, 0.0
+        while spent < 3.0 and passes < 100:
+            c0 = time.perf_counter()
+            for d in (9, 22):
+                oracle.intersect_depth(cs.rays, cs.fibers, d, pair_fiber=cs.pair_fiber, nthreads=threads)
+            spent += time.perf_counter() - c0
+            passes += 1
+        cpu_res = {"value": passes * 2 * (1 << 21) / spent / 1e9, "unit": "Gpairs/s", "cores": threads,
+                   "kind": "oracle",
+                   "sample": f"the first 2,097,152 pairs at depths 9 and 22, {passes} times ({spent:.1f} s), "
+                             f"FP64 depth-d oracle"}
+    return {"workload": "hair: 100k strands x 8 C1 segments (800,000 fibers, +1e3 offset, r 1e-4..2e-5), "
+                        "2^24 rays aimed at random segments, 10% grazing within 1e-3 r, fibers gathered "
+                        "through an int32 index",
+            "pairs": n, "fibers": nf, "bytes_per_pair": 41, "per_depth": out, "cpu_baseline": cpu_res}
 
 
 def bench_hair(args):
@@ -586,6 +673,16 @@ def main():
                "kind": "oracle",
                "sample": f"the whole workload ({n} pairs at depths {list(DEPTHS)}) {passes} times "
                          f"({spent:.1f} s), FP64 depth-d oracle, OpenMP over pairs"}
+        # one core on the first 2^16 pairs, and the host CPU's model
+        sub = w.subset(np.arange(1 << 16))
+        c0 = time.perf_counter()
+        for d in DEPTHS:
+            oracle.intersect_depth(sub.rays, sub.fibers, d, pair_ray=sub.pair_ray, pair_fiber=sub.pair_fiber,
+                                   nthreads=1)
+        one = time.perf_counter() - c0
+        cpu["single_core"] = {"value": len(DEPTHS) * (1 << 16) / one / 1e9, "unit": "Gpairs/s",
+                              "sample": f"the first 65,536 pairs at depths {list(DEPTHS)} ({one:.2f} s), one thread"}
+        cpu["cpu_model"] = cpu_model()
 
     line = {
         "metric": "ray-fiber intersections/sec (Gpairs/s) at depth 9 and 22",
@@ -611,6 +708,12 @@ def main():
         "parity": parity,
         "with_normals": normals,
     }
+    if not args.no_extras:
+        # the other configurations: hair (gathered fibers) and batched scenes
+        print("bench: hair block", file=sys.stderr, flush=True)
+        line["hair"] = hair_block(args.steps, min(args.warmup, 10), cpu=not args.no_cpu_baseline)
+        print("bench: batched block", file=sys.stderr, flush=True)
+        line["batched"] = batched_block(min(args.steps, 20), min(args.warmup, 5))
     print(json.dumps(line), flush=True)
 
 

@@ -42,6 +42,13 @@ def bytes_streamed(n_pairs, indexed=False):
     return per * n_pairs
 
 
+def bytes_gathered(n_pairs, n_fibers):
+    """HBM bytes of a call with one ray per pair and fibers gathered through
+    an int32 index: each pair reads its ray and index and writes its outputs
+    (41 B), and the fiber table is read once (64 B per fiber)."""
+    return (BYTES_RAY + BYTES_INDEX + BYTES_OUT) * n_pairs + BYTES_FIBER * n_fibers
+
+
 # MI355X published peaks
 PEAK_FP32_TFLOPS = 157.3        # vector FP32, 256 CUs at 2.4 GHz
 PEAK_FP32_UNPACKED_TFLOPS = 78.6
