@@ -51,6 +51,12 @@ def lib():
                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
                                    C.c_void_p]
         L.fo_nearest_d.restype = None
+        L.fv_validate.argtypes = [dp, dp, dp]
+        L.fv_validate.restype = C.c_int
+        L.fv_presplit.argtypes = [dp, C.c_int, dp, dp, dp, C.c_void_p, C.c_int]
+        L.fv_presplit.restype = C.c_int
+        L.fv_validate_batch.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_int]
+        L.fv_validate_batch.restype = None
         L.fo_cubic_constraints.argtypes = [dp]
         L.fo_cubic_constraints.restype = C.c_int
         if hasattr(L, "fx_batch"):
@@ -307,3 +313,38 @@ def ray_frame(ray7, fiber16):
 def cubic_constraints(q16):
     q, qp = _d(q16)
     return lib().fo_cubic_constraints(qp)
+
+
+def validate(q16):
+    """Validity mask of one fiber (fv_validate; 0: valid): bits 0-4 the five
+    inequalities of Section 3.4 that fail, bit 5 thick at the start, bit 6
+    thick at the end, bit 7 non-finite. Returns (mask, start excess, end
+    excess), the excesses relative to the fiber's extent."""
+    q, qp = _d(q16)
+    e0, e1 = C.c_double(), C.c_double()
+    m = lib().fv_validate(qp, C.byref(e0), C.byref(e1))
+    return m, e0.value, e1.value
+
+
+def validate_table(fibers, nthreads=0):
+    """Masks (int32) and excesses (n, 2) of every fiber of a (16, n) table."""
+    f = np.ascontiguousarray(fibers, dtype=np.float32)
+    n = f.shape[1]
+    m = np.empty(n, np.int32)
+    ex = np.empty((n, 2))
+    lib().fv_validate_batch(_ptr(f), n, n, _ptr(m), _ptr(ex), int(nthreads))
+    return m, ex
+
+
+def presplit(q16, max_level=6):
+    """Pieces of one fiber (fv_presplit): (pieces (k, 16), u0, u1, masks)."""
+    q, qp = _d(q16)
+    cap = 1 << max_level
+    pieces = np.empty((cap, 16))
+    u0 = np.empty(cap)
+    u1 = np.empty(cap)
+    mk = np.empty(cap, np.int32)
+    k = lib().fv_presplit(qp, int(max_level), pieces.ctypes.data_as(C.POINTER(C.c_double)),
+                          u0.ctypes.data_as(C.POINTER(C.c_double)), u1.ctypes.data_as(C.POINTER(C.c_double)),
+                          _ptr(mk), cap)
+    return pieces[:k], u0[:k], u1[:k], mk[:k]

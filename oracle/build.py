@@ -11,7 +11,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["fiber_oracle.c", "fiber_exact.c"]
+SOURCES = ["fiber_oracle.c", "fiber_exact.c", "fiber_validate.c"]
 LIB = os.path.join(HERE, "liboracle_fiber.so")
 
 

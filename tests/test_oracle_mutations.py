@@ -16,7 +16,7 @@ import pytest
 from oracle import build as oracle_build
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-D, X = "fiber_oracle.c", "fiber_exact.c"
+D, X, V = "fiber_oracle.c", "fiber_exact.c", "fiber_validate.c"
 
 # (name, file, text, replacement): the first occurrence of text is replaced
 MUTANTS = [
@@ -64,6 +64,14 @@ MUTANTS = [
     ("later candidates not held to the nearest hit", D,
      "ray[6] = t;                     /* later candidates must come nearer */", "(void)0;"),
     ("candidate lists not truncated", D, "if (end - off[r] > max_cand) end = off[r] + max_cand;", "(void)0;"),
+    ("cap excess with the wrong sign of the along term", V, "return r * s - along;", "return r * s + along;"),
+    ("end cap normal taken at the start", V, "c[0] = end ? vsub(pt(q, 3), pt(q, 2)) : vsub(pt(q, 1), pt(q, 0));",
+     "c[0] = vsub(pt(q, 1), pt(q, 0));"),
+    ("cosine instead of sine of the disc tilt", V, "const double s = sqrt(vdot(x, x)) / dl;",
+     "const double s = vdot(D, n) / dl;"),
+    ("pieces not halved at the midpoint", V, "const double s = (m012 + m123) * 0.5;",
+     "const double s = (m012 + m12) * 0.5;"),
+    ("halving one level past the limit", V, "level >= max_level ||", "level > max_level ||"),
     ("exact oracle: radius term with the wrong sign", X, "F = badd(&F, &a3, -1.0);", "F = badd(&F, &a3, 1.0);"),
     ("exact oracle: no limit disc at a zero end tangent", X, "while (j < 2 && cand[j][0]", "while (0 && cand[j][0]"),
     ("exact oracle: edge-on rays through the expanded polynomial", X, "if (edge_on(c)) {", "if (0) {"),
@@ -98,7 +106,8 @@ def _run_mutant(m, tmp):
     env = dict(os.environ, FIBER_ORACLE_LIB=lib, OMP_NUM_THREADS="2")
     res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                           "tests/test_oracle_pins.py", "tests/test_oracle_exact.py",
-                          "tests/test_oracle_normals.py", "tests/test_oracle_candidates.py"],
+                          "tests/test_oracle_normals.py", "tests/test_oracle_candidates.py",
+                          "tests/test_oracle_validate.py"],
                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return name, res.returncode, res.stdout[-400:]
 
