@@ -308,6 +308,69 @@ int fiber_intersect_candidates(const float *rays, int64_t ray_stride, int64_t n_
                                void *workspace, size_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Validation and pre-subdivision of fibers (before the per-pair test)       */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * fiber_validate -- which fibers the method handles as they are.
+ *
+ * Operation (Section 3.4): a fiber is valid when the five inequalities
+ * <p2-p0, p1-p0>, <p3-p1, p1-p0>, <p3-p1, p3-p2>, <p2-p0, p3-p2>,
+ * <p2-p0, p3-p1> >= 0 hold (recursive halves are then separated by their
+ * split planes, Appendix B.2) and no disc of its swept solid reaches across
+ * the start or end cap plane (Fig. "EvilConfiguration": the disc at u reaches
+ * r(u) sin(angle(C'(u), n)) beyond its centre along the cap normal n, by
+ * Gram-Schmidt; the fiber is thick at that end when the largest excess over
+ * the plane exceeds 1e-9 of its extent |p3 - p0| + max radius). Computed in
+ * FP64, the excess searched on 105 parameters (63 even, 20 packed towards
+ * each end) and refined by golden section around the best one.
+ *
+ * Arguments: the fiber table (16 rows of fiber_stride floats, as for
+ * fiber_intersect_pairs); mask_out: n_fibers int32, 0 for a valid fiber,
+ * else bit k (0..4) for a failed inequality, bit 5 thick at the start, bit 6
+ * thick at the end, bit 7 a non-finite control point; excess_out: NULL or
+ * 2 * n_fibers floats, the largest start and end excesses relative to the
+ * extent. Errors: FI_ERR_RANGE, FI_ERR_NULL, FI_ERR_HIP; allocates nothing.
+ */
+int fiber_validate(const float *fibers, int64_t fiber_stride, int64_t n_fibers, int32_t *mask_out,
+                   float *excess_out, void *stream);
+
+/* Bytes of workspace fiber_presplit_count needs for n_fibers fibers (0 for
+ * a negative count or more than 2^31 - 2 fibers). */
+size_t fiber_presplit_workspace_bytes(int64_t n_fibers);
+
+/*
+ * fiber_presplit_count, fiber_presplit -- split invalid fibers beforehand.
+ *
+ * Operation (Section 3.4: curves that break the constraints, thick ends,
+ * cusps "require subdivision beforehand"): each fiber is halved by de
+ * Casteljau's construction at u = 1/2 (Appendix B.2; radius included),
+ * depth first and left half first, until a piece is valid in the sense of
+ * fiber_validate or max_level halvings deep (0..10; a piece stopped by the
+ * limit keeps its nonzero mask). A valid fiber is its own single piece.
+ * The halving is exact in FP64 at these levels; pieces are rounded to
+ * float32 once.
+ *
+ * fiber_presplit_count writes offsets_out (n_fibers + 1 int64): fiber i's
+ * pieces occupy [offsets_out[i], offsets_out[i + 1]), offsets_out[n_fibers]
+ * is the total. It needs a workspace of fiber_presplit_workspace_bytes
+ * (256-byte aligned). The caller reads the total, sizes the piece table and
+ * calls fiber_presplit with the same fibers, max_level and those offsets: it
+ * writes the pieces (a fiber table of 16 rows of piece_stride floats,
+ * piece_stride >= n_pieces), and per piece its fiber, its parameter interval
+ * [piece_u0, piece_u1) on that fiber (a hit at piece parameter v lies at
+ * u0 + v (u1 - u0) on the fiber) and its validity mask.
+ *
+ * Errors: FI_ERR_RANGE (counts, strides, max_level), FI_ERR_NULL,
+ * FI_ERR_WORKSPACE, FI_ERR_HIP. Neither call allocates.
+ */
+int fiber_presplit_count(const float *fibers, int64_t fiber_stride, int64_t n_fibers, int32_t max_level,
+                         int64_t *offsets_out, void *workspace, size_t workspace_bytes, void *stream);
+int fiber_presplit(const float *fibers, int64_t fiber_stride, int64_t n_fibers, int32_t max_level,
+                   const int64_t *offsets, int64_t n_pieces, float *pieces_out, int64_t piece_stride,
+                   int32_t *piece_fiber, float *piece_u0, float *piece_u1, int32_t *piece_mask, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Many independent problems in one launch                                  */
 /* ------------------------------------------------------------------------ */
 

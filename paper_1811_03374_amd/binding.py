@@ -49,6 +49,14 @@ def lib():
         L.fiber_intersect_candidates.argtypes = [vp, i64, i64, vp, i64, i64, vp, vp, vp, i32, i32, i64, u32,
                                                  vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
         L.fiber_intersect_candidates.restype = C.c_int
+        L.fiber_validate.argtypes = [vp, i64, i64, vp, vp, vp]
+        L.fiber_validate.restype = C.c_int
+        L.fiber_presplit_workspace_bytes.argtypes = [i64]
+        L.fiber_presplit_workspace_bytes.restype = C.c_size_t
+        L.fiber_presplit_count.argtypes = [vp, i64, i64, i32, vp, vp, C.c_size_t, vp]
+        L.fiber_presplit_count.restype = C.c_int
+        L.fiber_presplit.argtypes = [vp, i64, i64, i32, vp, i64, vp, i64, vp, vp, vp, vp, vp]
+        L.fiber_presplit.restype = C.c_int
         L.fi_init_device.restype = C.c_int
         L.fi_strerror.argtypes = [C.c_int]
         L.fi_strerror.restype = C.c_char_p
@@ -61,6 +69,7 @@ def exported_symbols():
     return ["fi_version", "fi_strerror", "fi_init_device", "fiber_pairs_workspace_bytes",
             "fiber_intersect_pairs", "fiber_intersect_pairs_noalloc", "fiber_intersect_counts",
             "fiber_candidates_workspace_bytes", "fiber_intersect_candidates",
+            "fiber_validate", "fiber_presplit_workspace_bytes", "fiber_presplit_count", "fiber_presplit",
             "fiber_batched_workspace_bytes", "fiber_intersect_batched", "fiber_batch_plan_create",
             "fiber_batch_plan_launch", "fiber_batch_plan_tuning", "fiber_batch_plan_destroy",
             "fiber_batch_autotune"]
@@ -308,6 +317,45 @@ def intersect_candidates(rays: torch.Tensor, fibers: torch.Tensor, offsets: torc
     if nrm is not None:
         out += (nrm,)
     return out
+
+
+def validate(fibers: torch.Tensor, excess: bool = False, stream=None):
+    """Validity mask (int32, 0 = valid) of every fiber of a (16, n) table, and
+    the (n, 2) float32 start/end cap excesses when ``excess``
+    (``fiber_validate``)."""
+    fs = _table(fibers, 16, "fibers")
+    n = fibers.shape[1]
+    mask = torch.empty(n, dtype=torch.int32, device=fibers.device)
+    ex = torch.empty((n, 2), dtype=torch.float32, device=fibers.device) if excess else None
+    _check(lib().fiber_validate(_ptr(fibers), fs, n, _ptr(mask), _ptr(ex), _stream(stream)))
+    return (mask, ex) if excess else mask
+
+
+def presplit(fibers: torch.Tensor, max_level: int = 6, stream=None):
+    """Split invalid fibers into valid pieces (``fiber_presplit_count`` then
+    ``fiber_presplit``; one device sync to read the piece count). Returns
+    (pieces (16, k) float32, piece_fiber int32, u0, u1 float32, mask int32,
+    offsets int64 (n + 1))."""
+    fs = _table(fibers, 16, "fibers")
+    n = fibers.shape[1]
+    dev = fibers.device
+    L = lib()
+    nb = L.fiber_presplit_workspace_bytes(n)
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
+    off = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    _check(L.fiber_presplit_count(_ptr(fibers), fs, n, int(max_level), _ptr(off), C.c_void_p(ws.data_ptr()),
+                                  ws.numel(), _stream(stream)))
+    if stream is not None:
+        stream.synchronize()
+    k = int(off[-1].item())
+    pieces = torch.empty((16, max(k, 1)), dtype=torch.float32, device=dev)[:, :k]
+    pf = torch.empty(k, dtype=torch.int32, device=dev)
+    u0 = torch.empty(k, dtype=torch.float32, device=dev)
+    u1 = torch.empty(k, dtype=torch.float32, device=dev)
+    mk = torch.empty(k, dtype=torch.int32, device=dev)
+    _check(L.fiber_presplit(_ptr(fibers), fs, n, int(max_level), _ptr(off), k, _ptr(pieces),
+                            pieces.stride(0), _ptr(pf), _ptr(u0), _ptr(u1), _ptr(mk), _stream(stream)))
+    return pieces, pf, u0, u1, mk, off
 
 
 class PreparedPairs:

@@ -15,6 +15,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc", "fiberhit.hip")
+SRCS = [SRC, os.path.join(PKG, "csrc", "presplit.hip")]
 OUT_DIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(OUT_DIR, "libfiberhit.so")
 ARCH = "gfx950"
@@ -25,7 +26,7 @@ def hipcc_cmd(out: str, extra=()):
             "-ffp-contract=off",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wall", "-Wno-unused-function",
-            "-I", os.path.join(ROOT, "include"), *extra, "-o", out, SRC]
+            "-I", os.path.join(ROOT, "include"), *extra, "-o", out, *SRCS]
 
 
 def build(verbose: bool = False) -> str:
