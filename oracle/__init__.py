@@ -31,8 +31,13 @@ def lib():
         L.fo_batch_d.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_int64,
                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int64,
                                  C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
-                                 C.c_void_p, C.c_void_p]
+                                 C.c_void_p, C.c_void_p, C.c_int]
         L.fo_batch_d.restype = None
+        L.fo_tie_outcomes_quad.argtypes = [dp, dp, C.c_int, C.c_double, C.c_int, C.c_int, dp, dp,
+                                           C.POINTER(C.c_int)]
+        L.fo_tie_outcomes_quad.restype = C.c_int
+        L.fo_quadratic_constraint.argtypes = [dp]
+        L.fo_quadratic_constraint.restype = C.c_int
         L.fo_split_half.argtypes = [dp, dp, dp]
         L.fo_split_plane.argtypes = [dp, dp, dp]
         L.fo_split_children.argtypes = [dp, dp, dp]
@@ -70,6 +75,10 @@ def lib():
                                      C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
             L.fx_nearest.restype = None
+            L.fx_batch_quad.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_int64,
+                                        C.c_void_p, C.c_void_p, C.c_int64, C.c_double,
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
+            L.fx_batch_quad.restype = None
             L.fx_side_polynomial.argtypes = [dp, dp]
             L.fx_side_polynomial.restype = C.c_int
         _lib = L
@@ -87,7 +96,7 @@ def _d(a):
 
 def intersect_depth(rays, fibers, depth=9, pair_ray=None, pair_fiber=None,
                     pair_depth=None, radius_scale=1.0, stats=False, nthreads=0, t_err=False,
-                    normal=False):
+                    normal=False, quadratic=False):
     """ORACLE-D: the paper's depth-d method in FP64 for every pair.
 
     Returns (t float64, u float64, hit uint8[, stats int32 (n, 4)][, t_err
@@ -100,7 +109,7 @@ def intersect_depth(rays, fibers, depth=9, pair_ray=None, pair_fiber=None,
     an FP32 evaluation (1), how the leaf was entered (1: 0 through the
     cylinder's side, 1 through a plane on the curve's start cap plane, 2 on
     its end cap plane, 3 through another plane or at the origin); NaN on a
-    miss."""
+    miss. ``quadratic``: fibers are (12, n) quadratics (Appendix B.1)."""
     rays = np.ascontiguousarray(rays, dtype=np.float32)
     fibers = np.ascontiguousarray(fibers, dtype=np.float32)
     pr = None if pair_ray is None else np.ascontiguousarray(pair_ray, dtype=np.int32)
@@ -121,13 +130,13 @@ def intersect_depth(rays, fibers, depth=9, pair_ray=None, pair_fiber=None,
     lib().fo_batch_d(_ptr(rays), rays.shape[1], rays.shape[1], _ptr(fibers), fibers.shape[1],
                      fibers.shape[1], _ptr(pr), _ptr(pf), _ptr(pd), int(depth), n,
                      float(radius_scale), _ptr(t), _ptr(u), _ptr(hit), _ptr(st), int(nthreads),
-                     _ptr(te), _ptr(nn))
+                     _ptr(te), _ptr(nn), int(bool(quadratic)))
     out = (t, u, hit) + ((st,) if stats else ()) + ((te,) if t_err else ()) + ((nn,) if normal else ())
     return out
 
 
 def intersect_exact(rays, fibers, pair_ray=None, pair_fiber=None, radius_scale=1.0,
-                    nthreads=0, normal=False):
+                    nthreads=0, normal=False, quadratic=False):
     """ORACLE-X: first entry of the ray into the swept-disk solid (the limit
     of the method), in FP64. Returns (t, u, hit, kind[, normal (n, 3)]) where
     kind is 0 miss, 1 side surface, 2 start cap, 3 end cap, 4 origin inside;
@@ -150,9 +159,10 @@ def intersect_exact(rays, fibers, pair_ray=None, pair_fiber=None, radius_scale=1
     u = np.empty(n, np.float64)
     kind = np.empty(n, np.int32)
     nn = np.empty((n, 3), np.float64) if normal else None
-    L.fx_batch(_ptr(rays), rays.shape[1], rays.shape[1], _ptr(fibers), fibers.shape[1],
-               fibers.shape[1], _ptr(pr), _ptr(pf), n, float(radius_scale),
-               _ptr(t), _ptr(u), _ptr(kind), int(nthreads), _ptr(nn))
+    fn = L.fx_batch_quad if quadratic else L.fx_batch
+    fn(_ptr(rays), rays.shape[1], rays.shape[1], _ptr(fibers), fibers.shape[1],
+       fibers.shape[1], _ptr(pr), _ptr(pf), n, float(radius_scale),
+       _ptr(t), _ptr(u), _ptr(kind), int(nthreads), _ptr(nn))
     return (t, u, (kind > 0).astype(np.uint8), kind) + ((nn,) if normal else ())
 
 
@@ -235,7 +245,7 @@ def single_depth(ray, fiber, depth):
     return bool(hit), t.value, u.value, tuple(st)
 
 
-def tie_outcomes(ray, fiber, depth, scale=1.0, max_flips=2, max_out=512):
+def tie_outcomes(ray, fiber, depth, scale=1.0, max_flips=2, max_out=512, quadratic=False):
     """Results of one pair reachable by flipping at most ``max_flips`` near-tie
     comparisons: comparisons whose two sides differ by at most ``scale`` times
     the sum of their FP32 error bounds (reading R14 of the oracle). Returns
@@ -245,7 +255,8 @@ def tie_outcomes(ray, fiber, depth, scale=1.0, max_flips=2, max_out=512):
     t = np.empty(max_out)
     u = np.empty(max_out)
     h = np.empty(max_out, np.int32)
-    n = lib().fo_tie_outcomes(rp, fp, int(depth), float(scale), int(max_flips), int(max_out),
+    fn = lib().fo_tie_outcomes_quad if quadratic else lib().fo_tie_outcomes
+    n = fn(rp, fp, int(depth), float(scale), int(max_flips), int(max_out),
                               t.ctypes.data_as(C.POINTER(C.c_double)),
                               u.ctypes.data_as(C.POINTER(C.c_double)),
                               h.ctypes.data_as(C.POINTER(C.c_int)))
@@ -348,3 +359,9 @@ def presplit(q16, max_level=6):
                           u0.ctypes.data_as(C.POINTER(C.c_double)), u1.ctypes.data_as(C.POINTER(C.c_double)),
                           _ptr(mk), cap)
     return pieces[:k], u0[:k], u1[:k], mk[:k]
+
+
+def quadratic_constraint(p12):
+    """The constraint of Appendix B.1, <p1 - p0, p1 - p2> <= 0 (bool)."""
+    q, qp = _d(p12)
+    return bool(lib().fo_quadratic_constraint(qp))

@@ -601,6 +601,43 @@ void fx_batch(const float *rays, int64_t ray_stride, int64_t n_rays,
     }
 }
 
+/* Quadratic fibers (12 rows: p0, p1, p2, each x, y, z, r): the swept solid
+ * of a quadratic is that of its exact cubic elevation. */
+void fx_batch_quad(const float *rays, int64_t ray_stride, int64_t n_rays,
+                   const float *fibers, int64_t fiber_stride, int64_t n_fibers,
+                   const int32_t *pair_ray, const int32_t *pair_fiber, int64_t n,
+                   double radius_scale, double *t_out, double *u_out, int32_t *kind_out,
+                   int nthreads, double *normal_out)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t ri = pair_ray ? pair_ray[i] : i;
+        const int64_t fi = pair_fiber ? pair_fiber[i] : i;
+        double ray[7], p[12], fib[16], t = INFINITY, u = NAN, nn[3] = {NAN, NAN, NAN};
+        int kind = 0;
+        if (ri >= 0 && ri < n_rays && fi >= 0 && fi < n_fibers) {
+            for (int r = 0; r < 7; ++r) ray[r] = rays[r * ray_stride + ri];
+            for (int r = 0; r < 12; ++r) p[r] = fibers[r * fiber_stride + fi];
+            for (int k = 0; k < 3; ++k) p[4 * k + 3] *= radius_scale;
+            for (int c = 0; c < 4; ++c) {
+                fib[c] = p[c];
+                fib[4 + c] = (p[c] + 2.0 * p[4 + c]) / 3.0;
+                fib[8 + c] = (2.0 * p[4 + c] + p[8 + c]) / 3.0;
+                fib[12 + c] = p[8 + c];
+            }
+            kind = fx_intersect(ray, fib, &t, &u, nn);
+        }
+        t_out[i] = t;
+        u_out[i] = u;
+        kind_out[i] = kind;
+        if (normal_out)
+            for (int k = 0; k < 3; ++k) normal_out[3 * i + k] = nn[k];
+    }
+}
+
 /* Nearest entry over a candidate list per ray (the exact counterpart of
  * fo_nearest_d): candidates in list order, each against the ray shortened to
  * the latest entry found; the first of equal entries is kept. */

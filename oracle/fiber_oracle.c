@@ -232,6 +232,36 @@ static double conservative_radius(const v4 q[4])
     return sqrt(fmax(d1, d2)) + rmax;
 }
 
+/* Quadratic fibers (Appendix B.1) are held as their exact cubic elevation
+ * (q1 = (p0 + 2 p1) / 3, q2 = (2 p1 + p2) / 3, radius included): the same
+ * curve and radius function, and de Casteljau halving commutes with
+ * elevation, so the recursion, the split planes (normal to the tangent at
+ * the centre, which for a quadratic is the chord p2 - p0) and the cap planes
+ * are the quadratic's own. Only the bound is the quadratic's: the distance
+ * of the middle control point p1 = (3 q1 - q0) / 2 = (3 q2 - q3) / 2 to the
+ * chord (3/2 of the elevated inner points' distance) plus the largest of
+ * the three radius control values. */
+static double quadratic_radius(const v4 q[4])
+{
+    const v4 a = sub4(q[3], q[0]);
+    const double d1 = dist2_to_axis(sub4(q[1], q[0]), a);
+    const double d2 = dist2_to_axis(sub4(q[2], q[0]), a);
+    const double r1a = 0.5 * (3.0 * q[1].w - q[0].w), r1b = 0.5 * (3.0 * q[2].w - q[3].w);
+    const double rmax = fmax(fmax(q[0].w, q[3].w), fmax(r1a, r1b));
+    return 1.5 * sqrt(fmax(d1, d2)) + rmax;
+}
+
+/* Exact cubic elevation of a quadratic (p0, p1, p2; x, y, z, r each). */
+static void elevate_quadratic(const double p[12], double q[16])
+{
+    for (int c = 0; c < 4; ++c) {
+        q[c] = p[c];
+        q[4 + c] = (p[c] + 2.0 * p[4 + c]) / 3.0;
+        q[8 + c] = (2.0 * p[4 + c] + p[8 + c]) / 3.0;
+        q[12 + c] = p[8 + c];
+    }
+}
+
 /* Unit ray (origin, +z) against the infinite cylinder of radius r whose axis
  * passes through o along a (Appendix A). With g = a.x^2 + a.y^2 the ray
  * meets it where e = r^2 - dist^2 >= 0 (dist: distance between the ray and
@@ -387,6 +417,7 @@ typedef struct {
     double n_alt[3];    /* the other normal where cap and side entry tie (else n) */
     double n_err;       /* angle bound (radians) of n in an FP32 evaluation */
     int entry;          /* 0 side, 1 start cap, 2 end cap, 3 another plane (split plane, origin) */
+    int quad;           /* the fiber is an elevated quadratic: its own bound */
 } search_t;
 
 static double node_err(const search_t *S, int level)
@@ -499,7 +530,7 @@ static int visit(search_t *S, const node_t *N, double lo, double hi, double elo,
     S->tests++;
     const v4 *q = N->q;
     const v4 a = sub4(q[3], q[0]);
-    const double R = conservative_radius(q);
+    const double R = S->quad ? quadratic_radius(q) : conservative_radius(q);
     const double delta = node_err(S, level);
     double te, tx, ec = 0.0;
     const cyl_t cy = cylinder_terms(N->o, a, R);
@@ -587,11 +618,12 @@ int fo_version(void) { return 1; }
 static int intersect_with_ties(const double ray[7], const double fiber[16], int depth,
                                double scale, uint64_t flip_mask, int force_vis, int *n_ties,
                                double *t_out, double *u_out, int64_t stats[4], double *t_err,
-                               double normal_out[8])
+                               double normal_out[8], int quad)
 {
     double frame[9];
     search_t S;
     memset(&S, 0, sizeof S);
+    S.quad = quad;
     S.ties.scale = scale;
     S.ties.flip_mask = flip_mask;
     S.ties.force_vis = force_vis;
@@ -640,7 +672,7 @@ static int intersect_with_ties(const double ray[7], const double fiber[16], int 
 int fo_intersect_d(const double ray[7], const double fiber[16], int depth,
                    double *t_out, double *u_out, int64_t stats[4])
 {
-    return intersect_with_ties(ray, fiber, depth, 0.0, 0, 0, NULL, t_out, u_out, stats, NULL, NULL);
+    return intersect_with_ties(ray, fiber, depth, 0.0, 0, 0, NULL, t_out, u_out, stats, NULL, NULL, 0);
 }
 
 /* Every result reachable from one pair by flipping at most max_flips (1 or 2)
@@ -648,30 +680,54 @@ int fo_intersect_d(const double ray[7], const double fiber[16], int depth,
  * R14), and the result with every visibility tie decided visible
  * (decide_vis). Writes up to max_out results (t, u, hit), the unflipped one
  * first; returns how many were written. */
-int fo_tie_outcomes(const double ray[7], const double fiber[16], int depth, double scale,
-                    int max_flips, int max_out, double *t_out, double *u_out, int *hit_out)
+static int tie_outcomes(const double ray[7], const double fiber[16], int depth, double scale,
+                        int max_flips, int max_out, double *t_out, double *u_out, int *hit_out, int quad)
 {
     int n = 0, k0 = 0;
     double t, u;
-    int h = intersect_with_ties(ray, fiber, depth, scale, 0, 0, &k0, &t, &u, NULL, NULL, NULL);
+    int h = intersect_with_ties(ray, fiber, depth, scale, 0, 0, &k0, &t, &u, NULL, NULL, NULL, quad);
     if (max_out < 1) return 0;
     t_out[n] = t; u_out[n] = u; hit_out[n] = h; n++;
     if (scale > 0.0 && n < max_out) {
-        h = intersect_with_ties(ray, fiber, depth, scale, 0, 1, NULL, &t, &u, NULL, NULL, NULL);
+        h = intersect_with_ties(ray, fiber, depth, scale, 0, 1, NULL, &t, &u, NULL, NULL, NULL, quad);
         t_out[n] = t; u_out[n] = u; hit_out[n] = h; n++;
     }
     for (int j = 0; j < k0 && j < 64 && n < max_out; ++j) {
         int kj = 0;
-        h = intersect_with_ties(ray, fiber, depth, scale, 1ull << j, 0, &kj, &t, &u, NULL, NULL, NULL);
+        h = intersect_with_ties(ray, fiber, depth, scale, 1ull << j, 0, &kj, &t, &u, NULL, NULL, NULL, quad);
         t_out[n] = t; u_out[n] = u; hit_out[n] = h; n++;
         if (max_flips < 2) continue;
         for (int k = j + 1; k < kj && k < 64 && n < max_out; ++k) {
             h = intersect_with_ties(ray, fiber, depth, scale, (1ull << j) | (1ull << k), 0, NULL,
-                                    &t, &u, NULL, NULL, NULL);
+                                    &t, &u, NULL, NULL, NULL, quad);
             t_out[n] = t; u_out[n] = u; hit_out[n] = h; n++;
         }
     }
     return n;
+}
+
+int fo_tie_outcomes(const double ray[7], const double fiber[16], int depth, double scale,
+                    int max_flips, int max_out, double *t_out, double *u_out, int *hit_out)
+{
+    return tie_outcomes(ray, fiber, depth, scale, max_flips, max_out, t_out, u_out, hit_out, 0);
+}
+
+/* The same for a quadratic fiber (12 values: p0, p1, p2, each x, y, z, r). */
+int fo_tie_outcomes_quad(const double ray[7], const double fiber12[12], int depth, double scale,
+                         int max_flips, int max_out, double *t_out, double *u_out, int *hit_out)
+{
+    double q[16];
+    elevate_quadratic(fiber12, q);
+    return tie_outcomes(ray, q, depth, scale, max_flips, max_out, t_out, u_out, hit_out, 1);
+}
+
+/* The constraint of Appendix B.1 for a quadratic: <p1 - p0, p1 - p2> <= 0
+ * (returns 1 when it holds). */
+int fo_quadratic_constraint(const double p[12])
+{
+    const v4 a = mk4(p[4] - p[0], p[5] - p[1], p[6] - p[2], 0.0);
+    const v4 b = mk4(p[4] - p[8], p[5] - p[9], p[6] - p[10], 0.0);
+    return dot3(a, b) <= 0.0;
 }
 
 /* Many pairs from the structure-of-arrays layout of the library (rays: 7 rows
@@ -686,14 +742,17 @@ int fo_tie_outcomes(const double ray[7], const double fiber[16], int depth, doub
  * entries tie (else the same), the angle bound in radians of the normal in
  * an FP32 evaluation, and how the leaf was entered (0 through its cylinder's
  * side, 1 through a plane on the curve's start cap plane, 2 on its end cap
- * plane, 3 through another plane or at the origin); NaN on a miss. Pairs whose indices fall outside [0, n_rays) or [0, n_fibers) are
- * misses. */
+ * plane, 3 through another plane or at the origin); NaN on a miss. Pairs
+ * whose indices fall outside [0, n_rays) or [0, n_fibers) are misses. With
+ * quad set, fibers are quadratics (12 rows: p0, p1, p2, each x, y, z, r),
+ * held as their exact cubic elevation with the quadratic's own bound. */
 void fo_batch_d(const float *rays, int64_t ray_stride, int64_t n_rays,
                 const float *fibers, int64_t fiber_stride, int64_t n_fibers,
                 const int32_t *pair_ray, const int32_t *pair_fiber,
                 const uint8_t *pair_depth, int depth, int64_t n,
                 double radius_scale, double *t_out, double *u_out,
-                uint8_t *hit_out, int32_t *stats_out, int nthreads, double *terr_out, double *normal_out)
+                uint8_t *hit_out, int32_t *stats_out, int nthreads, double *terr_out, double *normal_out,
+                int quad)
 {
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -708,10 +767,17 @@ void fo_batch_d(const float *rays, int64_t ray_stride, int64_t n_rays,
         int hit = 0;
         if (ri >= 0 && ri < n_rays && fi >= 0 && fi < n_fibers) {
             for (int r = 0; r < 7; ++r) ray[r] = rays[r * ray_stride + ri];
-            for (int r = 0; r < 16; ++r) fib[r] = fibers[r * fiber_stride + fi];
-            for (int k = 0; k < 4; ++k) fib[4 * k + 3] *= radius_scale;
+            if (quad) {
+                double p[12];
+                for (int r = 0; r < 12; ++r) p[r] = fibers[r * fiber_stride + fi];
+                for (int k = 0; k < 3; ++k) p[4 * k + 3] *= radius_scale;
+                elevate_quadratic(p, fib);
+            } else {
+                for (int r = 0; r < 16; ++r) fib[r] = fibers[r * fiber_stride + fi];
+                for (int k = 0; k < 4; ++k) fib[4 * k + 3] *= radius_scale;
+            }
             hit = intersect_with_ties(ray, fib, d, 0.0, 0, 0, NULL, &t, &u, st, &te,
-                                      normal_out ? normal_out + 8 * i : NULL);
+                                      normal_out ? normal_out + 8 * i : NULL, quad);
         } else if (normal_out) {
             for (int k = 0; k < 8; ++k) normal_out[8 * i + k] = NAN;
         }
@@ -761,7 +827,7 @@ void fo_nearest_d(const float *rays, int64_t ray_stride, int64_t n_rays,
             double fib[16], t, u, te = 0.0, nn[8];
             for (int k = 0; k < 16; ++k) fib[k] = fibers[k * fiber_stride + fi];
             for (int k = 0; k < 4; ++k) fib[4 * k + 3] *= radius_scale;
-            if (intersect_with_ties(ray, fib, d, 0.0, 0, 0, NULL, &t, &u, NULL, &te, nn)) {
+            if (intersect_with_ties(ray, fib, d, 0.0, 0, 0, NULL, &t, &u, NULL, &te, nn, 0)) {
                 best_t = t;
                 best_u = u;
                 best_e = te;

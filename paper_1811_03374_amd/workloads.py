@@ -450,6 +450,59 @@ def hair_candidates(n_rays: int = 1 << 20, n_strands: int = 100_000, depth: int 
                           "grazing": aim.meta["grazing"]})
 
 
+def elevate_quadratic(P3: np.ndarray) -> np.ndarray:
+    """(n, 3, 4) quadratic control points -> (n, 4, 4) exact cubic elevation
+    (float64): the same curve and radius function."""
+    P3 = np.asarray(P3, np.float64)
+    out = np.empty((P3.shape[0], 4, 4))
+    out[:, 0] = P3[:, 0]
+    out[:, 1] = (P3[:, 0] + 2.0 * P3[:, 1]) / 3.0
+    out[:, 2] = (2.0 * P3[:, 1] + P3[:, 2]) / 3.0
+    out[:, 3] = P3[:, 2]
+    return out
+
+
+def pack_quadratics(P3: np.ndarray) -> np.ndarray:
+    """(n, 3, 4) -> (12, n) float32 table (rows p0x, p0y, p0z, p0r, .., p2r)."""
+    return np.ascontiguousarray(np.asarray(P3).reshape(-1, 12).T.astype(np.float32))
+
+
+def unpack_quadratics(table: np.ndarray) -> np.ndarray:
+    return np.asarray(table, np.float64).T.reshape(-1, 3, 4)
+
+
+def quadratic_fibers(n: int, seed: int = SEED_BASE + 8, straight_fraction: float = 0.25) -> Workload:
+    """Quadratic Bezier fibers (Appendix B.1): chord of length 0.2..0.8 in a
+    random direction from a point of the unit cube, the middle control point
+    at the chord's centre displaced sideways by up to 0.45 of the chord (a
+    quarter of the fibers straight: the middle point exactly at the centre,
+    on a 2^-12 grid), radius tapering linearly between 0.002 and 0.02; rays
+    aimed as in ``straight_and_curved`` (about half hit)."""
+    rng = np.random.default_rng(seed)
+    grid = 2.0 ** -12
+    p0 = np.round(rng.uniform(0.1, 0.9, (n, 3)) / grid) * grid
+    ch = np.round(unit_vectors(rng, n) * rng.uniform(0.2, 0.8, (n, 1)) / (2 * grid)) * (2 * grid)
+    side = unit_vectors(rng, n)
+    side -= np.sum(side * ch, axis=1, keepdims=True) * ch / np.sum(ch * ch, axis=1, keepdims=True)
+    side /= np.linalg.norm(side, axis=1, keepdims=True)
+    bend = rng.uniform(0.0, 0.45, n) * np.linalg.norm(ch, axis=1)
+    straight = rng.uniform(0, 1, n) < straight_fraction
+    bend[straight] = 0.0
+    P = np.empty((n, 3, 4))
+    P[:, 0, :3] = p0
+    P[:, 1, :3] = p0 + 0.5 * ch + bend[:, None] * side
+    P[:, 2, :3] = p0 + ch
+    ra = rng.uniform(0.002, 0.02, n)
+    rb = rng.uniform(0.002, 0.02, n)
+    P[:, :, 3] = ra[:, None] + np.array([0.0, 0.5, 1.0])[None, :] * (rb - ra)[:, None]
+    fibers = pack_quadratics(P)
+    P32 = unpack_quadratics(fibers)
+    O, D, u0, off = _aim_rays(rng, elevate_quadratic(P32), 3.0, 1.4826)
+    rays = pack_rays(O, D, np.full(n, 100.0))
+    return Workload(f"quadratic_{n}", rays, fibers, None, None, 9,
+                    meta={"straight": straight, "u0": u0, "offset_over_r": off})
+
+
 # ---------------------------------------------------------------------------
 # Workload 4: batched uneven scenes with per-segment adaptive depth
 # ---------------------------------------------------------------------------

@@ -72,6 +72,10 @@ MUTANTS = [
     ("pieces not halved at the midpoint", V, "const double s = (m012 + m123) * 0.5;",
      "const double s = (m012 + m12) * 0.5;"),
     ("halving one level past the limit", V, "level >= max_level ||", "level > max_level ||"),
+    ("quadratic bound from the elevated inner points", D, "return 1.5 * sqrt(fmax(d1, d2)) + rmax;",
+     "return sqrt(fmax(d1, d2)) + rmax;"),
+    ("quadratic elevation with swapped weights", D, "q[4 + c] = (p[c] + 2.0 * p[4 + c]) / 3.0;",
+     "q[4 + c] = (2.0 * p[c] + p[4 + c]) / 3.0;"),
     ("exact oracle: radius term with the wrong sign", X, "F = badd(&F, &a3, -1.0);", "F = badd(&F, &a3, 1.0);"),
     ("exact oracle: no limit disc at a zero end tangent", X, "while (j < 2 && cand[j][0]", "while (0 && cand[j][0]"),
     ("exact oracle: edge-on rays through the expanded polynomial", X, "if (edge_on(c)) {", "if (0) {"),
@@ -107,7 +111,7 @@ def _run_mutant(m, tmp):
     res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                           "tests/test_oracle_pins.py", "tests/test_oracle_exact.py",
                           "tests/test_oracle_normals.py", "tests/test_oracle_candidates.py",
-                          "tests/test_oracle_validate.py"],
+                          "tests/test_oracle_validate.py", "tests/test_oracle_quadratic.py"],
                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return name, res.returncode, res.stdout[-400:]
 
