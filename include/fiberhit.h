@@ -73,6 +73,20 @@ extern "C" {
  * statistics flag would add are the separate entry point
  * fiber_intersect_counts. */
 #define FI_COMPENSATED_PROJ (1u << 1)
+/* FI_QUADRATIC: the fiber table holds quadratic Bezier curves (Appendix B.1;
+ * 12 rows: p0x, p0y, p0z, p0r, p1x, .., p2r). Each is traversed as its exact
+ * cubic elevation (q1 = (p0 + 2 p1) / 3, q2 = (2 p1 + p2) / 3: the same
+ * curve and radius function; de Casteljau halving commutes with elevation,
+ * so the halves, split planes -- normal to the chord at a quadratic's centre
+ * -- and cap planes are the quadratic's), bounded by the quadratic's own
+ * conservative radius (the middle control point's distance to the chord
+ * plus the largest of the three radius values). Refined pairs search the
+ * quadratic's swept solid. Accepted by fiber_intersect_pairs, its
+ * no-allocation variant and fiber_intersect_counts (not by batched or
+ * candidate-list calls: FI_ERR_RANGE); such calls use no workspace. The
+ * quadratic's constraint <p1 - p0, p1 - p2> <= 0 keeps every split
+ * separating (Appendix B.1). */
+#define FI_QUADRATIC (1u << 2)
 
 /* Largest subdivision depth: one bit per level in 32-bit integers and an
  * integer parametric position below 2^23 (Section 3.3, interval conversion). */
@@ -121,7 +135,8 @@ size_t fiber_pairs_workspace_bytes(int64_t n_pairs, int64_t n_fibers, int32_t ga
  *   depth                          0 .. FI_MAX_DEPTH (checked even when pair_depth
  *                                  is given).
  *   n_pairs                        >= 0; 0 enqueues nothing and returns FI_OK.
- *   flags                          FI_FP64_REFINE and/or FI_COMPENSATED_PROJ.
+ *   flags                          FI_FP64_REFINE, FI_COMPENSATED_PROJ,
+ *                                  FI_QUADRATIC (12-row fiber table).
  *   t_out, u_out, hit_out          n_pairs each. On a miss: t = +inf, u = NaN, hit = 0.
  *   t64_out, u64_out               n_pairs doubles each; required with
  *                                  FI_FP64_REFINE, ignored (may be NULL) without.

@@ -18,6 +18,7 @@ FI_OK = 0
 FI_MAX_DEPTH = 23
 FI_FP64_REFINE = 1
 FI_COMPENSATED_PROJ = 2
+FI_QUADRATIC = 4
 
 _lib = None
 
@@ -181,7 +182,7 @@ def intersect_pairs(rays: torch.Tensor, fibers: torch.Tensor, depth: int = 9,
                     pair_fiber: Optional[torch.Tensor] = None,
                     pair_depth: Optional[torch.Tensor] = None,
                     out=None, counts: bool = False, refine: bool = False, stream=None,
-                    workspace: Optional[torch.Tensor] = None, normal=None):
+                    workspace: Optional[torch.Tensor] = None, normal=None, quadratic: bool = False):
     """Nearest hit (t, u, hit) of every (ray, fiber) pair at subdivision depth
     ``depth`` (or per-pair ``pair_depth``). See ``fiber_intersect_pairs``.
 
@@ -191,9 +192,10 @@ def intersect_pairs(rays: torch.Tensor, fibers: torch.Tensor, depth: int = 9,
     float64 (t64, u64) of the FP64 surface refinement when ``refine`` is set,
     then the (3, n) float32 normals when ``normal`` is True (or a tensor to
     fill). ``workspace`` (uint8 device tensor, see ``pairs_workspace``) is
-    allocated per call when not given and the call gathers fibers."""
+    allocated per call when not given and the call gathers fibers.
+    ``quadratic``: fibers is a (12, n) table of quadratic curves."""
     rs = _table(rays, 7, "rays")
-    fs = _table(fibers, 16, "fibers")
+    fs = _table(fibers, 12 if quadratic else 16, "fibers")
     pr = _index(pair_ray, torch.int32, "pair_ray")
     pf = _index(pair_fiber, torch.int32, "pair_fiber")
     pd = _index(pair_depth, torch.uint8, "pair_depth")
@@ -206,13 +208,13 @@ def intersect_pairs(rays: torch.Tensor, fibers: torch.Tensor, depth: int = 9,
         raise ValueError("counts and normals are separate passes")
     nrm = _normal_tensor(normal, n, dev)
     if workspace is None:
-        workspace = pairs_workspace(n, fibers.shape[1], pf is not None, dev)
+        workspace = None if quadratic else pairs_workspace(n, fibers.shape[1], pf is not None, dev)
         _keep_for(workspace, stream)
     elif workspace.dtype != torch.uint8 or not workspace.is_cuda or not workspace.is_contiguous():
         raise ValueError("workspace must be a contiguous uint8 device tensor")
     ws = _ws_args(workspace)
     cn = torch.empty((n, 4), dtype=torch.int32, device=dev) if counts else None
-    flags = FI_FP64_REFINE if refine else 0
+    flags = (FI_FP64_REFINE if refine else 0) | (FI_QUADRATIC if quadratic else 0)
     args = [_ptr(rays), rs, rays.shape[1], _ptr(fibers), fs, fibers.shape[1],
             _ptr(pr), _ptr(pf), _ptr(pd), int(depth), n, flags,
             _ptr(t), _ptr(u), _ptr(hit)]
@@ -233,14 +235,15 @@ def intersect_pairs_noalloc(rays: torch.Tensor, fibers: torch.Tensor, depth: int
                             pair_ray: Optional[torch.Tensor] = None,
                             pair_fiber: Optional[torch.Tensor] = None,
                             pair_depth: Optional[torch.Tensor] = None,
-                            out=None, refine: bool = False, stream=None, normal=None):
+                            out=None, refine: bool = False, stream=None, normal=None,
+                            quadratic: bool = False):
     """``intersect_pairs`` through ``fiber_intersect_pairs_noalloc``: no
     workspace (the library's fixed per-device array holds the fiber records
     of gathered calls). With ``out`` (and, under ``refine``, ``out`` holding
     five tensors; ``normal`` a tensor when normals are asked for) the call
     allocates nothing. Calls on one device must not overlap."""
     rs = _table(rays, 7, "rays")
-    fs = _table(fibers, 16, "fibers")
+    fs = _table(fibers, 12 if quadratic else 16, "fibers")
     pr = _index(pair_ray, torch.int32, "pair_ray")
     pf = _index(pair_fiber, torch.int32, "pair_fiber")
     pd = _index(pair_depth, torch.uint8, "pair_depth")
@@ -263,8 +266,8 @@ def intersect_pairs_noalloc(rays: torch.Tensor, fibers: torch.Tensor, depth: int
     nrm = _normal_tensor(normal, n, dev)
     _check(lib().fiber_intersect_pairs_noalloc(
         _ptr(rays), rs, rays.shape[1], _ptr(fibers), fs, fibers.shape[1], _ptr(pr), _ptr(pf), _ptr(pd),
-        int(depth), n, FI_FP64_REFINE if refine else 0, _ptr(t), _ptr(u), _ptr(hit), _ptr(t64), _ptr(u64),
-        _ptr(nrm), _stream(stream)))
+        int(depth), n, (FI_FP64_REFINE if refine else 0) | (FI_QUADRATIC if quadratic else 0), _ptr(t), _ptr(u),
+        _ptr(hit), _ptr(t64), _ptr(u64), _ptr(nrm), _stream(stream)))
     extra = (nrm,) if nrm is not None else ()
     return ((t, u, hit, t64, u64) if refine else (t, u, hit)) + extra
 

@@ -168,6 +168,12 @@ __device__ __forceinline__ void cap_interval(const Node &c, float tmax, float &l
 // Conservative cylinder radius (Section 3.3): largest distance of the inner
 // control points (t0 and -t1 relative to the chord ends) to the chord line,
 // plus the largest radius control value (convex hull of the radius Bezier).
+// QUAD: the node is the exact cubic elevation of a quadratic (Appendix B.1:
+// q1 = (p0 + 2 p1) / 3, q2 = (2 p1 + p2) / 3): the same curve, halves and
+// planes. Its bound is the quadratic's: the middle control point p1 lies at
+// 3/2 of the elevated inner points' distance from the chord, and the middle
+// radius value is r0 + 3/2 t0.w = r2 - 3/2 t1.w.
+template <bool QUAD = false>
 __device__ __forceinline__ float conservative_radius(const Node &c)
 {
     const float cc = dot3(c.d.x, c.d.y, c.d.z, c.d.x, c.d.y, c.d.z);
@@ -178,6 +184,11 @@ __device__ __forceinline__ float conservative_radius(const Node &c)
     const float e1x = fmaf(-b1, c.d.x, c.t1.x), e1y = fmaf(-b1, c.d.y, c.t1.y), e1z = fmaf(-b1, c.d.z, c.t1.z);
     const float l0 = dot3(e0x, e0y, e0z, e0x, e0y, e0z);
     const float l1 = dot3(e1x, e1y, e1z, e1x, e1y, e1z);
+    if constexpr (QUAD) {
+        const float r1 = fmaxf(fmaf(1.5f, c.t0.w, 0.0f), fmaf(-1.5f, c.t1.w, c.d.w));
+        const float rmax = c.p.w + fmaxf(fmaxf(0.0f, c.d.w), r1);
+        return 1.5f * vsqrt(fmaxf(l0, l1)) + rmax;
+    }
     const float rmax = c.p.w + fmaxf(fmaxf(0.0f, c.t0.w), fmaxf(c.d.w, c.d.w - c.t1.w));
     return vsqrt(fmaxf(l0, l1)) + rmax;
 }
@@ -298,8 +309,10 @@ struct Curve64 {
     double scale;                        // largest control-point coordinate
 };
 
+// quad: F is a quadratic table (12 rows), taken as its exact cubic elevation
 __device__ __forceinline__ bool curve_in_ray_frame(const float *R, int64_t rs, const float *F,
-                                                   int64_t fs, Curve64 &c, double *frame = nullptr)
+                                                   int64_t fs, Curve64 &c, double *frame = nullptr,
+                                                   bool quad = false)
 {
     const double ox = R[0], oy = R[rs], oz = R[2 * rs];
     const double dx = R[3 * rs], dy = R[4 * rs], dz = R[5 * rs];
@@ -313,15 +326,33 @@ __device__ __forceinline__ bool curve_in_ray_frame(const float *R, int64_t rs, c
 #pragma unroll
         for (int k = 0; k < 3; ++k) { frame[k] = u[k]; frame[3 + k] = v[k]; frame[6 + k] = w[k]; }
     }
+    double P[4][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int row = quad ? 4 * (k == 3 ? 2 : k) + j : 4 * k + j;
+            P[k][j] = (double)F[row * fs];
+        }
+    if (quad) {                      // P holds p0, p1, p2, p2: elevate
+        double e1[4], e2[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            e1[j] = (P[0][j] + 2.0 * P[1][j]) / 3.0;
+            e2[j] = (2.0 * P[1][j] + P[2][j]) / 3.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) { P[1][j] = e1[j]; P[2][j] = e2[j]; }
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const double ex = (double)F[(4 * k) * fs] - ox;
-        const double ey = (double)F[(4 * k + 1) * fs] - oy;
-        const double ez = (double)F[(4 * k + 2) * fs] - oz;
+        const double ex = P[k][0] - ox;
+        const double ey = P[k][1] - oy;
+        const double ez = P[k][2] - oz;
         c.q[k][0] = fma(ex, u[0], fma(ey, u[1], ez * u[2]));
         c.q[k][1] = fma(ex, v[0], fma(ey, v[1], ez * v[2]));
         c.q[k][2] = fma(ex, w[0], fma(ey, w[1], ez * w[2]));
-        c.q[k][3] = F[(4 * k + 3) * fs];
+        c.q[k][3] = P[k][3];
     }
     c.scale = 0.0;
 #pragma unroll
@@ -691,11 +722,11 @@ __device__ __forceinline__ float root_slack(const Node &r)
 // cylinder inside the node's cropped interval? `lo_used` / `hi_used` are the
 // interval the test used (enlarged in conservative mode); a leaf's t is taken
 // from its start.
-template <int MODE>
+template <int MODE, bool QUAD = false>
 __device__ __forceinline__ bool node_visible(const Node &c, float lo, float hi, float slack, float &te,
                                              float &tx, float &lo_used, float &hi_used)
 {
-    float rad = conservative_radius(c);
+    float rad = conservative_radius<QUAD>(c);
     if (MODE == kConservative && slack >= 0.0f) {
         rad += slack + rad * 0x1p-18f;
         // an interval emptied on purpose (a parked lane, a cap plane parallel
@@ -788,14 +819,14 @@ __device__ __forceinline__ void solid_normal(const Curve64 &c, double t, double 
 __device__ __noinline__ Refined refine_whole_curve(const float *rays, int64_t ray_stride, const float *fibers,
                                                    int64_t fiber_stride, const int32_t *pair_ray,
                                                    const int32_t *pair_fiber, int64_t i, int64_t fiber,
-                                                   double tmax, float t0, float u0, bool normal)
+                                                   double tmax, float t0, float u0, bool normal, bool quad)
 {
     Refined r;
     const int64_t ri = pair_ray ? (int64_t)pair_ray[i] : i;
     const int64_t fi = fiber >= 0 ? fiber : pair_fiber ? (int64_t)pair_fiber[i] : i;
     Curve64 cv;
     double frame[9];
-    if (!curve_in_ray_frame(rays + ri, ray_stride, fibers + fi, fiber_stride, cv, frame)) return r;
+    if (!curve_in_ray_frame(rays + ri, ray_stride, fibers + fi, fiber_stride, cv, frame, quad)) return r;
     double t = INFINITY, u = __builtin_nan("");
     leaf_candidates<kCurveSamples>(cv, 0.0, 1.0, 0.0, tmax, tmax, (double)t0, (double)u0, t, u);
     if (t < INFINITY) {
@@ -909,11 +940,11 @@ __device__ __forceinline__ HitGeo hit_geo(const Node &c, float t, bool plane)
     return HitGeo{-fmaf(ul, c.d.x, c.p.x), -fmaf(ul, c.d.y, c.p.y), t - fmaf(ul, c.d.z, c.p.z), plane};
 }
 
-template <int MODE, class Root>
+template <int MODE, bool QUAD, class Root>
 __device__ __forceinline__ int trip(Lane &L, const Root &root, float *col, HitGeo &hg)
 {
     float te, tx, lo, hi;
-    bool vis = node_visible<MODE>(L.c, L.lo, L.hi, L.slack, te, tx, lo, hi);
+    bool vis = node_visible<MODE, QUAD>(L.c, L.lo, L.hi, L.slack, te, tx, lo, hi);
     const bool leaf = L.size <= L.min_size;
     if (MODE == kConservative && vis && leaf && L.slack >= 0.0f) {
         // refinement: the first leaf reached means the solid may be hit; park
@@ -1165,7 +1196,9 @@ __device__ __forceinline__ int find_scene(const int64_t *offsets, int n_scenes, 
 // number cand_round; a ray without that candidate, or with an invalid one,
 // is a definite miss too (its callers then leave the ray's nearest hit so far
 // as it is), and tmax is the ray's tmax shortened to that hit.
-template <bool CAND>
+// QUAD: the fiber table holds quadratics (12 rows: p0, p1, p2), loaded as
+// their exact cubic elevation (t0 = 2/3 (p1 - p0), t1 = 2/3 (p2 - p1)).
+template <bool CAND, bool QUAD = false>
 __device__ __forceinline__ bool load_pair(const Args &a, int64_t i, float *q, float &tmax, uint32_t &depth,
                                           const float *aos)
 {
@@ -1221,6 +1254,17 @@ __device__ __forceinline__ bool load_pair(const Args &a, int64_t i, float *q, fl
     const float p0x = F[0], p0y = F[fs], p0z = F[2 * fs], p0w = F[3 * fs];
     proj((double)p0x - (double)R[0], (double)p0y - (double)R[rs], (double)p0z - (double)R[2 * rs], (double)p0w, 0,
          true);
+    if constexpr (QUAD) {
+        const float p2x = F[8 * fs], p2y = F[9 * fs], p2z = F[10 * fs], p2w = F[11 * fs];
+        const float p1x = F[4 * fs], p1y = F[5 * fs], p1z = F[6 * fs], p1w = F[7 * fs];
+        constexpr double k23 = 2.0 / 3.0;
+        proj((double)p2x - p0x, (double)p2y - p0y, (double)p2z - p0z, (double)p2w - p0w, 1, true);
+        proj(((double)p1x - p0x) * k23, ((double)p1y - p0y) * k23, ((double)p1z - p0z) * k23,
+             ((double)p1w - p0w) * k23, 2, false);
+        proj(((double)p2x - p1x) * k23, ((double)p2y - p1y) * k23, ((double)p2z - p1z) * k23,
+             ((double)p2w - p1w) * k23, 3, false);
+        return finite;
+    }
     const float p3x = F[12 * fs], p3y = F[13 * fs], p3z = F[14 * fs], p3w = F[15 * fs];
     proj((double)p3x - p0x, (double)p3y - p0y, (double)p3z - p0z, (double)p3w - p0w, 1, true);
     proj((double)F[4 * fs] - p0x, (double)F[5 * fs] - p0y, (double)F[6 * fs] - p0z, (double)F[7 * fs] - p0w, 2,
@@ -1259,7 +1303,7 @@ __device__ __forceinline__ void wave_range(int64_t w, int64_t waves, int64_t cou
 #ifndef FIBERHIT_WAVES
 #define FIBERHIT_WAVES 4                      // build knob: register budget (waves per SIMD)
 #endif
-template <int MODE, bool BATCHED, bool CAND = false>
+template <int MODE, bool BATCHED, bool CAND = false, bool QUAD = false>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MODE == kConservative ? 4 : FIBERHIT_WAVES, 8)))
 void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, int64_t count, int refill,
              const float *aos)
@@ -1306,7 +1350,7 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
                     idx -= offsets[sc];
                     a = scenes[sc];
                 }
-                const bool ok = load_pair<CAND>(a, idx, stage, rtmax, depth, aos);
+                const bool ok = load_pair<CAND, QUAD>(a, idx, stage, rtmax, depth, aos);
                 asm volatile("" ::: "memory");
                 float *f = &r.p.x;
 #pragma unroll
@@ -1317,7 +1361,7 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
                     cap_interval(r, rtmax, rlo, rhi);
                     float te, tx, lu, hu;
                     const float slack = MODE == kConservative && depth > kRefineAbove ? root_slack(r) : -1.0f;
-                    const bool vis = node_visible<MODE>(r, rlo, rhi, slack, te, tx, lu, hu);
+                    const bool vis = node_visible<MODE, QUAD>(r, rlo, rhi, slack, te, tx, lu, hu);
                     if (vis && depth > 0) {
                         queued = true;
                     } else {
@@ -1402,7 +1446,7 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
         // of the call).
         if (__ballot(active) == 0 && next >= end && q_count == 0) break;
         HitGeo hg;
-        const int st = trip<MODE>(L, root, col, hg);
+        const int st = trip<MODE, QUAD>(L, root, col, hg);
         if (active && st != kGoOn && !(MODE == kConservative && L.waiting)) {
             if constexpr (BATCHED) {
                 // lanes of the wave's current scene read its output
@@ -1445,7 +1489,7 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
                         tlim = fmin((double)rays[6 * rs + L.pair], a0.t64_out[L.pair]);
                     }
                     const Refined r = refine_whole_curve(rays, rs, fibers, fs, pr, pf, L.pair, fi, tlim, L.t, L.ru,
-                                                         want_n);
+                                                         want_n, QUAD);
                     // the output pointers are read after the call (not kept
                     // live across it)
                     if constexpr (BATCHED) finish<MODE>(scenes[L.scene], L.pair, L, r.hit, HitGeo{}, r);
@@ -1504,7 +1548,7 @@ int check_common(const float *rays, int64_t ray_stride, int64_t n_rays,
 {
     if (n_pairs < 0 || n_rays < 0 || n_fibers < 0) return FI_ERR_RANGE;
     if (depth < 0 || depth > FI_MAX_DEPTH) return FI_ERR_RANGE;
-    if ((flags & ~(uint32_t)(FI_FP64_REFINE | FI_COMPENSATED_PROJ)) != 0u) return FI_ERR_RANGE;
+    if ((flags & ~(uint32_t)(FI_FP64_REFINE | FI_COMPENSATED_PROJ | FI_QUADRATIC)) != 0u) return FI_ERR_RANGE;
     if (n_pairs == 0) return FI_OK;
     if (!rays || !fibers || !t_out || !u_out || !hit_out) return FI_ERR_NULL;
     if (ray_stride < n_rays || fiber_stride < n_fibers) return FI_ERR_RANGE;
@@ -1522,13 +1566,16 @@ using FusedFn = void (*)(Args, const Args *, const int64_t *, int, int64_t, int,
 // [0] plain, [1] counting, [2] conservative (single calls), [3] plain and
 // [4] conservative over a scene table, [5] plain and [6] conservative over
 // candidate lists
-constexpr int kVariants = 7;
+constexpr int kVariants = 10;
 const FusedFn kFused[kVariants] = {k_fused<kPlain, false>, k_fused<kCount, false>, k_fused<kConservative, false>,
                                    k_fused<kPlain, true>, k_fused<kConservative, true>,
-                                   k_fused<kPlain, false, true>, k_fused<kConservative, false, true>};
+                                   k_fused<kPlain, false, true>, k_fused<kConservative, false, true>,
+                                   k_fused<kPlain, false, false, true>, k_fused<kCount, false, false, true>,
+                                   k_fused<kConservative, false, false, true>};
 constexpr int kBatchedVariant = 3;
 constexpr int kBatchedRefineVariant = 4;
 constexpr int kCandVariant = 5;              // + 1: refined
+constexpr int kQuadVariant = 7;              // + kPlain, kCount, kConservative: quadratic fibers
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 constexpr size_t kMaxRecordBytes = (size_t)1 << 30;                 // fiber records, largest table
@@ -1693,22 +1740,26 @@ int launch(int mode, const Args &a, int64_t max_waves, float *aos, hipStream_t s
     if (g > 0)
         hipLaunchKernelGGL(kFused[mode], dim3((unsigned)g), dim3(kWave), 0, s, a, nullptr, nullptr, 0,
                            a.n_pairs,
-                           mode == kConservative || mode == kCandVariant + 1 ? FIBERHIT_REFINE_REFILL
-                                                                             : FIBERHIT_FUSED_REFILL,
+                           mode == kConservative || mode == kCandVariant + 1 ||
+                                   mode == kQuadVariant + kConservative
+                               ? FIBERHIT_REFINE_REFILL
+                               : FIBERHIT_FUSED_REFILL,
                            aos);
     return hipGetLastError() == hipSuccess ? FI_OK : FI_ERR_HIP;
 }
 
 // A single call with the fiber records (if it gathers fibers) in the
 // caller's workspace, room permitting.
-int launch_with_workspace(int mode, const Args &a, void *workspace, size_t workspace_bytes, void *stream)
+int launch_with_workspace(int mode, const Args &a, void *workspace, size_t workspace_bytes, void *stream,
+                          bool quad = false)
 {
     if (workspace && ((uintptr_t)workspace & 255u) != 0u) return FI_ERR_WORKSPACE;
     (void)hipGetLastError();
     DeviceInfo *d = nullptr;
     const int st = device_info(d);
     if (st != FI_OK) return st;
-    const size_t rec = record_bytes(a.n_pairs, a.n_fibers, a.pair_fiber != nullptr);
+    // quadratic tables are read in place (the records hold cubic rows)
+    const size_t rec = quad ? 0 : record_bytes(a.n_pairs, a.n_fibers, a.pair_fiber != nullptr);
     float *aos = rec && workspace && workspace_bytes >= rec ? (float *)workspace : nullptr;
     return launch(mode, a, single_call_waves(*d, mode, a), aos, (hipStream_t)stream);
 }
@@ -1835,8 +1886,7 @@ int fi_init_device(void)
 
 size_t fiber_pairs_workspace_bytes(int64_t n_pairs, int64_t n_fibers, int32_t gathered, uint32_t flags)
 {
-    (void)flags;
-    if (n_pairs < 0 || n_fibers < 0) return 0;
+    if (n_pairs < 0 || n_fibers < 0 || (flags & FI_QUADRATIC) != 0u) return 0;
     return record_bytes(n_pairs, n_fibers, gathered != 0);
 }
 
@@ -1857,7 +1907,9 @@ int fiber_intersect_pairs(const float *rays, int64_t ray_stride, int64_t n_rays,
     Args a{rays, ray_stride, n_rays, fibers, fiber_stride, n_fibers,
            pair_ray, pair_fiber, pair_depth, depth, n_pairs, t_out, u_out, hit_out, nullptr,
            refine ? t64_out : nullptr, refine ? u64_out : nullptr, normal_out};
-    return launch_with_workspace(refine ? kConservative : kPlain, a, workspace, workspace_bytes, stream);
+    const bool quad = (flags & FI_QUADRATIC) != 0u;
+    return launch_with_workspace((refine ? kConservative : kPlain) + (quad ? kQuadVariant : 0), a, workspace,
+                                 workspace_bytes, stream, quad);
 }
 
 int fiber_intersect_pairs_noalloc(const float *rays, int64_t ray_stride, int64_t n_rays,
@@ -1874,13 +1926,14 @@ int fiber_intersect_pairs_noalloc(const float *rays, int64_t ray_stride, int64_t
     if (st != FI_OK || n_pairs == 0) return st;
     const bool refine = (flags & FI_FP64_REFINE) != 0u;
     if (refine && (!t64_out || !u64_out)) return FI_ERR_NULL;
-    const size_t rec = record_bytes(n_pairs, n_fibers, pair_fiber != nullptr);
+    const bool quad = (flags & FI_QUADRATIC) != 0u;
+    const size_t rec = quad ? 0 : record_bytes(n_pairs, n_fibers, pair_fiber != nullptr);
     if (rec > kScratchBytes) return FI_ERR_SCRATCH;
     (void)hipGetLastError();
     DeviceInfo *d = nullptr;
     const int ds = device_info(d);
     if (ds != FI_OK) return ds;
-    const int mode = refine ? kConservative : kPlain;
+    const int mode = (refine ? kConservative : kPlain) + (quad ? kQuadVariant : 0);
     Args a{rays, ray_stride, n_rays, fibers, fiber_stride, n_fibers,
            pair_ray, pair_fiber, pair_depth, depth, n_pairs, t_out, u_out, hit_out, nullptr,
            refine ? t64_out : nullptr, refine ? u64_out : nullptr, normal_out};
@@ -1905,7 +1958,8 @@ int fiber_intersect_counts(const float *rays, int64_t ray_stride, int64_t n_rays
     Args a{rays, ray_stride, n_rays, fibers, fiber_stride, n_fibers,
            pair_ray, pair_fiber, pair_depth, depth, n_pairs, t_out, u_out, hit_out, counts_out, nullptr, nullptr,
            nullptr};
-    return launch_with_workspace(kCount, a, workspace, workspace_bytes, stream);
+    const bool quad = (flags & FI_QUADRATIC) != 0u;
+    return launch_with_workspace(kCount + (quad ? kQuadVariant : 0), a, workspace, workspace_bytes, stream, quad);
 }
 
 size_t fiber_candidates_workspace_bytes(int64_t n_candidates, int64_t n_fibers, uint32_t flags)

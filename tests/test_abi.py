@@ -57,7 +57,7 @@ def _call(**kw):
     (dict(depth=24), -2), (dict(depth=-1), -2), (dict(n=-1), -2), (dict(flags=8), -2),
     (dict(rs=4), -2), (dict(fs=4), -2), (dict(n=9), -2),
     (dict(rays=None), -1), (dict(fibers=None), -1), (dict(t=None), -1), (dict(h=None), -1),
-    (dict(flags=1), -1), (dict(flags=1, t64=1), -1), (dict(flags=5, t64=1, u64=1), -2),
+    (dict(flags=1), -1), (dict(flags=1, t64=1), -1), (dict(flags=9, t64=1, u64=1), -2),
     # a misaligned workspace is refused before any HIP call
     (dict(ws=0x1008, wsb=1 << 30), -4), (dict(flags=2, ws=0x1010, wsb=64), -4),
     (dict(flags=3, t64=1, u64=1, ws=0x1001, wsb=64), -4),
