@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="only the 2^20-pair line (no hair and batched blocks)")
+                    help="only the 2^20-pair line (no normals, hair and batched blocks)")
     ap.add_argument("--workload", choices=("straight_and_curved", "batched", "hair", "degenerate", "candidates"),
                     default="straight_and_curved",
                     help="batched: 256 uneven scenes (~13 M pairs, adaptive depth), one graph launch "
@@ -458,6 +458,33 @@ def bench_degenerate(args):
                 if m.any():
                     per[f"{name}{'' if val else ' (breaks Sec. 3.4 constraints)'}"] = stats(h, t, m, h_o, t_o)
         res[key]["vs_oracle"] = per
+    # validation and pre-subdivision of the 2^22-fiber table (Section 3.4)
+    mask = binding.validate(fibers)
+    ms_v = _timed(lambda: binding.validate(fibers, stream=stream), 5, 1, stream)
+    nb = binding.lib().fiber_presplit_workspace_bytes(fibers.shape[1])
+    wsp = torch.empty(nb, dtype=torch.uint8, device=dev)
+    off = torch.empty(fibers.shape[1] + 1, dtype=torch.int64, device=dev)
+    import ctypes as C
+    count = lambda: binding.lib().fiber_presplit_count(fibers.data_ptr(), fibers.stride(0), fibers.shape[1], 6,
+                                                       off.data_ptr(), C.c_void_p(wsp.data_ptr()), wsp.numel(),
+                                                       stream.cuda_stream)
+    ms_c = _timed(count, 3, 1, stream)
+    t0 = time.perf_counter()
+    pieces, pf, u0, u1, mk, off2 = binding.presplit(fibers, 6)
+    torch.cuda.synchronize()
+    ms_split = (time.perf_counter() - t0) * 1e3
+    mask = mask.cpu().numpy()
+    fam_all = w.meta["family"]
+    npc = np.diff(off2.cpu().numpy())
+    mkn = mk.cpu().numpy()
+    still = np.logical_or.reduceat(mkn != 0, off2.cpu().numpy()[:-1])
+    res["presplit"] = {
+        "validate_ms": ms_v, "count_ms": ms_c, "count_and_write_wall_ms": ms_split,
+        "fibers": int(fibers.shape[1]), "pieces": int(pieces.shape[1]),
+        "per_family": {name: {"valid": float((mask[fam_all == f] == 0).mean()),
+                              "mean_pieces": float(npc[fam_all == f].mean()),
+                              "still_invalid_at_level_6": float(still[fam_all == f].mean())}
+                       for f, name in enumerate(names)}}
     line = {"metric": "ray-fiber intersections/sec (Gpairs/s), degenerate geometry",
             "value": res["fp32"]["gpairs_per_s"], "unit": "Gpairs/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "dtype": "f32 (+f64 refinement)",
@@ -612,23 +639,23 @@ def main():
 
     # the same calls writing the normal at each hit as well (not part of the
     # step: the cost of the extra output)
-    ncall = {d: binding.PreparedPairs(rays, fibers, d, normal=True) for d in DEPTHS}
-    for _ in range(5):
-        for d in DEPTHS:
-            ncall[d].launch(stream)
-    nev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
-            for _ in DEPTHS] for _ in range(args.steps)]
-    for k in range(args.steps):
-        for j, d in enumerate(DEPTHS):
-            nev[k][j][0].record(stream)
-            ncall[d].launch(stream)
-            nev[k][j][1].record(stream)
-    torch.cuda.synchronize()
-    normals = {str(d): {"launch_ms_avg": statistics.mean(nev[k][j][0].elapsed_time(nev[k][j][1])
-                                                         for k in range(args.steps)),
-                        "gpairs_per_s": n / (statistics.mean(nev[k][j][0].elapsed_time(nev[k][j][1])
-                                                             for k in range(args.steps)) * 1e-3) / 1e9}
+    normals = None
+    if not args.no_extras:
+        ncall = {d: binding.PreparedPairs(rays, fibers, d, normal=True) for d in DEPTHS}
+        for _ in range(5):
+            for d in DEPTHS:
+                ncall[d].launch(stream)
+        nev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+                for _ in DEPTHS] for _ in range(args.steps)]
+        for k in range(args.steps):
+            for j, d in enumerate(DEPTHS):
+                nev[k][j][0].record(stream)
+                ncall[d].launch(stream)
+                nev[k][j][1].record(stream)
+        torch.cuda.synchronize()
+        nms = {d: statistics.mean(nev[k][j][0].elapsed_time(nev[k][j][1]) for k in range(args.steps))
                for j, d in enumerate(DEPTHS)}
+        normals = {str(d): {"launch_ms_avg": nms[d], "gpairs_per_s": n / (nms[d] * 1e-3) / 1e9} for d in DEPTHS}
 
     per_depth = {}
     roof = {}

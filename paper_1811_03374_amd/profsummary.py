@@ -74,6 +74,7 @@ def read_counter(path, counter):
 
 
 CALL_KERNELS = ("k_fused",)
+PLAIN_KERNEL = "k_fused<0, false, false, false>"     # the plain single-call variant
 
 
 def per_call(dispatches, factor):
@@ -85,7 +86,7 @@ def per_call(dispatches, factor):
 def call_durations(trace_path, steps):
     """Average duration (us) per depth of the plain-mode calls of a bench
     run: (isolated, overlapped), each a dict depth -> us."""
-    rows = [r for r in csv.DictReader(open(trace_path)) if short(r["Kernel_Name"]) == "k_fused<0, false>"]
+    rows = [r for r in csv.DictReader(open(trace_path)) if short(r["Kernel_Name"]) == PLAIN_KERNEL]
     rows.sort(key=lambda r: int(r["Dispatch_Id"]))
     us = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows]
     if len(us) < 4 * steps:
@@ -140,6 +141,24 @@ def sq_lines(paths, durations=None):
     return lines
 
 
+def last_call_counters(paths):
+    """Counter sums of the last k_fused dispatch of each counter CSV (a probe
+    whose last call is the one to read), merged over the files."""
+    out = collections.Counter()
+    for path in paths:
+        per = collections.OrderedDict()
+        for r in csv.DictReader(open(path)):
+            if "k_fused" not in r["Kernel_Name"]:
+                continue
+            per.setdefault(int(r["Dispatch_Id"]), collections.Counter())[r["Counter_Name"]] += \
+                float(r["Counter_Value"])
+        if per:
+            last = per[max(per)]
+            for k, v in last.items():
+                out.setdefault(k, v)
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--stats")
@@ -153,10 +172,15 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=0)
     ap.add_argument("--command", action="append", default=[],
                     help="command line that produced an input (repeatable)")
+    ap.add_argument("--last-call", action="append", default=[],
+                    help="rocprofv3 counter CSV whose last k_fused dispatch is summarised (repeatable)")
+    ap.add_argument("--note", action="append", default=[], help="a line of text after the commands")
     a = ap.parse_args(argv)
     os.makedirs(a.out, exist_ok=True)
     lines = [f"# {a.name}", "", "Commands:", ""]
     lines += [f"    {c}" for c in a.command] + [""]
+    if a.note:
+        lines += [" ".join(a.note), ""]
     if a.stats:
         stats = read_stats(a.stats)
         lines += ["| kernel | calls | avg us | min us | max us | % of GPU time |", "|---|---|---|---|---|---|"]
@@ -166,14 +190,23 @@ def main(argv=None):
     iso = None
     if a.trace and a.steps > 0:
         iso, ovl = call_durations(a.trace, a.steps)
-        lines += ["", f"Per-call durations of `k_fused<0, false>` from the kernel trace ({a.steps} steps):", "",
+        lines += ["", f"Per-call durations of `{PLAIN_KERNEL}` from the kernel trace ({a.steps} steps):", "",
                   "| depth | one after another, us | overlapped (two streams), us |", "|---|---|---|"]
         for d in DEPTHS:
             lines.append(f"| {d} | {iso[d]:.1f} | {ovl[d]:.1f} |")
     if a.sq:
-        lines += ["", "SQ counters summed over the device, one `k_fused<0, false>` dispatch per depth "
+        lines += ["", f"SQ counters summed over the device, one `{PLAIN_KERNEL}` dispatch per depth "
                   "(`--traffic-probe`: one call at depth 9, then one at depth 22):", ""]
         lines += sq_lines(a.sq, [iso[d] for d in DEPTHS] if iso else None)
+    if a.last_call:
+        c = last_call_counters(a.last_call)
+        lines += ["", "Counters of the last k_fused dispatch, summed over the device:", "",
+                  "| counter | value |", "|---|---|"]
+        lines += [f"| {k} | {int(v)} |" for k, v in sorted(c.items())]
+        if "SQ_INSTS_VALU" in c:
+            issue = c["SQ_INSTS_VALU"] / 1024 * 4 / 2.4e3
+            lines += ["", f"VALU issue time (1024 SIMDs, 4 cycles per wave64 VALU instruction, 2.4 GHz): "
+                          f"{issue:.0f} us."]
     traffic = None
     if a.fetch and a.write:
         fd = read_counter(a.fetch, "FETCH_SIZE")
