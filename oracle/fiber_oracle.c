@@ -418,6 +418,8 @@ typedef struct {
     double n_err;       /* angle bound (radians) of n in an FP32 evaluation */
     int entry;          /* 0 side, 1 start cap, 2 end cap, 3 another plane (split plane, origin) */
     int quad;           /* the fiber is an elevated quadratic: its own bound */
+    double stall_abs;   /* R19: (2^-20 X)^2, the FP32 resolution of node positions, squared */
+    double stall_rel;   /* R19: 2^-16 times the root's extent (scaled by 4^-level per node) */
 } search_t;
 
 static double node_err(const search_t *S, int level)
@@ -524,6 +526,13 @@ static void leaf_normal(search_t *S, const node_t *N, v4 a, double t, double ul,
     S->n_err = !on_cap ? e_side : (tie ? fmax(e_side, 0x1p-20) : 0x1p-20);
 }
 
+/* largest squared length of a node's chord and end tangents */
+static double node_extent(const v4 q[4])
+{
+    const v4 a = sub4(q[3], q[0]), b = sub4(q[1], q[0]), c = sub4(q[3], q[2]);
+    return fmax(dot3(a, a), fmax(dot3(b, b), dot3(c, c)));
+}
+
 static int visit(search_t *S, const node_t *N, double lo, double hi, double elo, double ehi,
                  int level, double u0, double u1)
 {
@@ -549,7 +558,20 @@ static int visit(search_t *S, const node_t *N, double lo, double hi, double elo,
     const double e_enter = te >= lo ? ec : elo, e_leave = tx <= hi ? ec : ehi;
     if (!decide_vis(S, enter <= leave, leave - enter, e_enter + e_leave)) return 0;
 
-    if (level >= S->depth) {
+    /* R19: a stalled end node is a leaf. It holds an end of the curve
+     * (u = 0 or u = 1), and its extent (the largest squared length of its
+     * chord and end tangents) is below the FP32 resolution of node positions,
+     * (2^-20 X)^2, and below 2^-16 of the root's extent scaled to the level
+     * (4^-level): the curve's speed vanishes at that end, all the node's
+     * control points coincide to working precision, and halving it further
+     * resolves only rounding noise. Near a vanishing end tangent the curve
+     * leaves its end along a fixed direction, so the node's chord and end
+     * planes stay perpendicular and its cylinder stays closed; an interior
+     * stall (a cusp, where the direction reverses) is not cut short. */
+    const double ext = node_extent(q);
+    const int stalled = (u0 == 0.0 || u1 == 1.0) && ext <= S->stall_abs &&
+                        ext <= ldexp(S->stall_rel, -2 * level);
+    if (level >= S->depth || stalled) {
         const double t = enter;
         const double c = dot3(a, a);
         double ul = 0.0;
@@ -637,6 +659,8 @@ static int intersect_with_ties(const double ray[7], const double fiber[16], int 
         double lo, hi, elo, ehi;
         for (int k = 0; k < 4; ++k)
             S.ties.X = fmax(S.ties.X, fmax(fabs(q[k].x), fmax(fabs(q[k].y), fabs(q[k].z))));
+        S.stall_abs = 0x1p-40 * S.ties.X * S.ties.X;
+        S.stall_rel = 0x1p-16 * node_extent(q);
         const node_t root = anchored(q);
         S.cap0 = start_cap_normal(root.q);
         S.cap1 = end_cap_normal(root.q);

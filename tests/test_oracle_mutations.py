@@ -76,6 +76,11 @@ MUTANTS = [
      "return sqrt(fmax(d1, d2)) + rmax;"),
     ("quadratic elevation with swapped weights", D, "q[4 + c] = (p[c] + 2.0 * p[4 + c]) / 3.0;",
      "q[4 + c] = (2.0 * p[c] + p[4 + c]) / 3.0;"),
+    ("stalled nodes cut short anywhere on the curve", D, "const int stalled = (u0 == 0.0 || u1 == 1.0) &&",
+     "const int stalled = 1 &&"),
+    ("stall without the FP32 resolution bound", D, "const int stalled = (u0 == 0.0 || u1 == 1.0) && ext <= S->stall_abs &&",
+     "const int stalled = (u0 == 0.0 || u1 == 1.0) &&"),
+    ("stall without the bound relative to the root", D, "ext <= ldexp(S->stall_rel, -2 * level);", "1;"),
     ("exact oracle: radius term with the wrong sign", X, "F = badd(&F, &a3, -1.0);", "F = badd(&F, &a3, 1.0);"),
     ("exact oracle: no limit disc at a zero end tangent", X, "while (j < 2 && cand[j][0]", "while (0 && cand[j][0]"),
     ("exact oracle: edge-on rays through the expanded polynomial", X, "if (edge_on(c)) {", "if (0) {"),
@@ -111,7 +116,8 @@ def _run_mutant(m, tmp):
     res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                           "tests/test_oracle_pins.py", "tests/test_oracle_exact.py",
                           "tests/test_oracle_normals.py", "tests/test_oracle_candidates.py",
-                          "tests/test_oracle_validate.py", "tests/test_oracle_quadratic.py"],
+                          "tests/test_oracle_validate.py", "tests/test_oracle_quadratic.py",
+                          "tests/test_oracle_stall.py"],
                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return name, res.returncode, res.stdout[-400:]
 
