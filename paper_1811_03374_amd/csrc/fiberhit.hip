@@ -670,6 +670,7 @@ struct Lane {
     float tmax, t;                // ray tmax; hit distance once found
     uint32_t bits, start, size;   // Section 3.3: pending-sibling bits, integer interval
     uint32_t min_size;            // leaf size 2^(23 - depth)
+    float stall_abs, stall_rel;   // stalled end nodes: extent thresholds (see node_extent)
     uint32_t cached;              // size of the pending children whose parent is cached (0: none)
     int32_t waiting;              // refinement: parked at its first leaf until the wave decides it
     float ru;                     //   the FP32 u of the leaf hit (Newton's start)
@@ -940,12 +941,52 @@ __device__ __forceinline__ HitGeo hit_geo(const Node &c, float t, bool plane)
     return HitGeo{-fmaf(ul, c.d.x, c.p.x), -fmaf(ul, c.d.y, c.p.y), t - fmaf(ul, c.d.z, c.p.z), plane};
 }
 
+// Stalled end nodes. Where an end tangent vanishes the curve leaves that end
+// with vanishing speed, and the end nodes' chords shrink like 4^-level: from
+// some level on, all their control points coincide to FP32 precision, every
+// test on them is rounding noise, and a search through them can visit
+// thousands of nodes. A node that holds an end of the curve (u = 0 or u = 1)
+// and whose extent -- the largest squared length of its chord and end
+// tangents -- is at most (2^-20 X)^2 (X: the largest ray-frame coordinate of
+// the root's control points) and at most 2^-16 of the root's extent times
+// 4^-level, is therefore a leaf. Near a vanishing end tangent the curve keeps
+// a fixed direction, so such a node's end planes stay perpendicular to its
+// chord and its cylinder stays closed. Cusps (interior stalls, where the
+// direction reverses) are not cut short.
+__device__ __forceinline__ float node_extent(const Node &c)
+{
+    const float cc = dot3(c.d.x, c.d.y, c.d.z, c.d.x, c.d.y, c.d.z);
+    const float a0 = dot3(c.t0.x, c.t0.y, c.t0.z, c.t0.x, c.t0.y, c.t0.z);
+    const float a1 = dot3(c.t1.x, c.t1.y, c.t1.z, c.t1.x, c.t1.y, c.t1.z);
+    return fmaxf(cc, fmaxf(a0, a1));
+}
+
+__device__ __forceinline__ void stall_init(Lane &L)
+{
+    const Node &r = L.c;
+    const float ex = r.p.x + r.d.x, ey = r.p.y + r.d.y, ez = r.p.z + r.d.z;     // p3
+    float X = fmaxf(fabsf(r.p.x), fmaxf(fabsf(r.p.y), fabsf(r.p.z)));
+    X = fmaxf(X, fmaxf(fabsf(r.p.x + r.t0.x), fmaxf(fabsf(r.p.y + r.t0.y), fabsf(r.p.z + r.t0.z))));
+    X = fmaxf(X, fmaxf(fabsf(ex - r.t1.x), fmaxf(fabsf(ey - r.t1.y), fabsf(ez - r.t1.z))));
+    X = fmaxf(X, fmaxf(fabsf(ex), fmaxf(fabsf(ey), fabsf(ez))));
+    L.stall_abs = 0x1p-40f * X * X;
+    L.stall_rel = 0x1p-16f * node_extent(r);
+}
+
+__device__ __forceinline__ bool stalled_end(const Lane &L)
+{
+    const float s = (float)L.size * 0x1p-23f;                 // 2^-level
+    const float e = node_extent(L.c);
+    const bool end = L.start == 0u || L.start + L.size == kRootSize;
+    return end && e <= L.stall_abs && e <= L.stall_rel * s * s;
+}
+
 template <int MODE, bool QUAD, class Root>
 __device__ __forceinline__ int trip(Lane &L, const Root &root, float *col, HitGeo &hg)
 {
     float te, tx, lo, hi;
     bool vis = node_visible<MODE, QUAD>(L.c, L.lo, L.hi, L.slack, te, tx, lo, hi);
-    const bool leaf = L.size <= L.min_size;
+    const bool leaf = L.size <= L.min_size || stalled_end(L);
     if (MODE == kConservative && vis && leaf && L.slack >= 0.0f) {
         // refinement: the first leaf reached means the solid may be hit; park
         // the lane (empty interval, no pending sibling) until the wave decides
@@ -1424,6 +1465,7 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
                     L.scene = ds >> 5;
                     L.root = L.c;
                     L.min_size = kRootSize >> depth;
+                    stall_init(L);
                     L.slack = MODE == kConservative && depth > kRefineAbove ? root_slack(L.c) : -1.0f;
                     L.start = 0;
                     L.size = kRootSize;

@@ -103,3 +103,45 @@ def test_degenerate_refined_against_exact_oracle(degenerate):
             if val:
                 assert rate == 0.0, name
                 assert rel.size == 0 or rel.max() <= 1e-12, (name, rel.max())
+
+
+def test_stalled_end_levels_and_bounded_work():
+    """Stalled end nodes (reading R19) on the GPU: on straight fibers along
+    the ray with zero end tangents the kernel's first hit ends at the level
+    derived in closed form (the oracle's pin scenes), with the cap-plane t;
+    with regular tangents it runs to the depth. On the degenerate workload
+    every pair's node tests stay bounded (the zero-tangent family no longer
+    searches rounding noise) and the leaf levels equal the oracle's wherever
+    both hit with the same leaf kind."""
+    from test_oracle_stall import axis_scene, stall_level
+    g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    scenes = []
+    for L, s in ((1.0, 1.0), (1.0, 1024.0), (0.25, 3.0), (2.0, 62.0), (0.5, 0.5)):
+        for reverse in (False, True):
+            for tang in ("zero", "regular"):
+                scenes.append((L, s, reverse, tang, axis_scene(L, s, 0.0025, 0.01, tangents=tang, reverse=reverse)))
+    R = np.concatenate([sc[4][0] for sc in scenes], axis=1)
+    F = np.concatenate([sc[4][1] for sc in scenes], axis=1)
+    say(f"[degenerate] stalled-end scenes n={R.shape[1]}")
+    t, u, h, c = (x.cpu().numpy() for x in binding.intersect_pairs(g(R), g(F), 22, counts=True))
+    torch.cuda.synchronize()
+    for i, (L, s, reverse, tang, _) in enumerate(scenes):
+        want = stall_level(L, L + s) if tang == "zero" else 22
+        assert h[i] == 1 and t[i] == np.float32(s) and c[i, 3] == want, (L, s, reverse, tang, t[i], c[i])
+
+    w = W.degenerate_geometry(1 << 15)
+    say(f"[degenerate] bounded work n={w.n_pairs}")
+    t, u, h, c = (x.cpu().numpy() for x in binding.intersect_pairs(
+        g(w.rays), g(w.fibers), 22, pair_depth=g(w.pair_depth), counts=True))
+    torch.cuda.synchronize()
+    _, _, h_o, st = oracle.intersect_depth(w.rays, w.fibers, 22, pair_depth=w.pair_depth, stats=True)
+    fam = w.meta["family"]
+    for f, name in enumerate(FAMILIES):
+        m = fam == f
+        say(f"[degenerate]   {name:15s} trips mean {c[m, 0].mean():.1f} p99.9 "
+            f"{np.quantile(c[m, 0], 0.999):.0f} max {c[m, 0].max()} (oracle max {st[m, 0].max()})")
+    assert c[:, 0].max() <= 4096
+    both = (h == 1) & (h_o == 1) & (fam == 2)
+    same = np.mean(c[both, 3] == st[both, 3])
+    say(f"[degenerate]   zero-tangent leaf level equal to the oracle's: {same:.4f}")
+    assert same >= 0.99
