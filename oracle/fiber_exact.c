@@ -326,6 +326,10 @@ static int disc_t(const curve_t *c, double u, int on_circle, double *t, double *
     const double rest = C[3] * C[3] - C[0] * C[0] - C[1] * C[1];
     const double err_div = D[2] != 0.0 ? cn * dn / fabs(D[2]) : INFINITY;
     double err_sq = INFINITY, tsq = 0.0;
+    /* a point of the ray on the disc's circle needs rho <= r: a root of F
+     * reported where rho clearly exceeds r is a cluster of rounding (F's
+     * positive dip below its coefficients' resolution), not a boundary point */
+    if (on_circle && rest < -1e-9 * C[3] * C[3] - 1e-15 * (C[0] * C[0] + C[1] * C[1])) return 0;
     if (on_circle && rest >= 0.0) {
         const double sr = sqrt(rest);
         const double tm = C[2] - sr, tp = C[2] + sr;
@@ -376,6 +380,71 @@ static int end_disc(const curve_t *c, int e, double *t)
     if (F > 0.0L) return 0;
     *t = (double)((xy + Cz * nz) / nz);
     return 1;
+}
+
+/* Side points about the discs that nearly contain the ray. At a zero u0 of
+ * xy (where a disc plane contains the ray line's direction, or nearly so)
+ * with rho < r, F = -g_{+1} g_{-1} has two roots about u0: the ray enters
+ * and leaves the disc of u0's neighbourhood there, on its circle at
+ * t = Cz -+ sqrt(r^2 - rho^2). The roots lie about |Dz| sqrt(r^2 - rho^2) /
+ * |xy'| from u0; when the disc plane turns towards the ray (Dz -> 0) they
+ * merge below the rounding of F's coefficients, and F's sign pattern can
+ * lose one or both. Each factor g_s changes sign once near u0: its sign
+ * change is bracketed by widening steps from u0 and bisected in long
+ * double. Points where C' vanishes are not boundary points (no disc). */
+static void near_edge_on_sides(const curve_t *c, const bpoly *xy, double scale, double tmax,
+                               double *best, double *bu)
+{
+    double z[64];
+    int nz = 0;
+    isolate(c, XY_ld, xy, 0.0, 1.0, z, &nz, 64, 0);
+    for (int i = 0; i < nz; ++i) {
+        double Cu[4], Du[3];
+        eval(c, z[i], Cu, Du);
+        if (!(sqrt(Du[0] * Du[0] + Du[1] * Du[1] + Du[2] * Du[2]) > 1e-12 * scale)) continue;
+        for (int s = -1; s <= 1; s += 2) {
+            int ok0;
+            const long double g0 = gs_ld(c, z[i], s, &ok0, NULL);
+            if (!ok0) continue;
+            long double lo = z[i], hi = z[i], glo = g0;
+            int found = g0 == 0.0L;
+            for (double w = 0x1p-44; !found && w <= 0x1p-6; w *= 4.0) {
+                for (int side = -1; side <= 1 && !found; side += 2) {
+                    const double ub = z[i] + side * w;
+                    if (ub < 0.0 || ub > 1.0) continue;
+                    int okb;
+                    const long double gb = gs_ld(c, ub, s, &okb, NULL);
+                    if (okb && (gb < 0.0L) != (g0 < 0.0L)) {
+                        lo = z[i];
+                        hi = ub;
+                        found = 1;
+                    }
+                }
+            }
+            if (!found) continue;
+            /* bisected to adjacent long doubles, rho <= r all the way */
+            int conv = glo == 0.0L;
+            for (int it = 0; it < 200 && !conv; ++it) {
+                const long double mid = 0.5L * (lo + hi);
+                if (mid == lo || mid == hi) { conv = 1; break; }
+                int okm;
+                const long double gm = gs_ld(c, mid, s, &okm, NULL);
+                if (!okm) break;
+                if (gm == 0.0L) { lo = hi = mid; conv = 1; break; }
+                if ((gm < 0.0L) == (glo < 0.0L)) { lo = mid; glo = gm; }
+                else hi = mid;
+            }
+            if (!conv) continue;
+            const double ur = (double)(0.5L * (lo + hi));
+            double Cr[4], Dr[3];
+            eval(c, ur, Cr, Dr);
+            if (!(sqrt(Dr[0] * Dr[0] + Dr[1] * Dr[1] + Dr[2] * Dr[2]) > 1e-12 * scale)) continue;
+            int okt;
+            long double t;
+            gs_ld(c, ur, s, &okt, &t);
+            if (okt && t >= 0.0L && t < tmax && t < *best) { *best = (double)t; *bu = ur; }
+        }
+    }
 }
 
 /* Exact first entry; kind: 0 miss, 1 side, 2 start cap, 3 end cap, 4 inside */
@@ -446,7 +515,8 @@ static int exact_hit(const curve_t *c, double tmax, double *t_out, double *u_out
     /* side surface */
     double roots[128];
     int nr = 0;
-    if (edge_on(c)) {
+    const int eo = edge_on(c);
+    if (eo) {
         /* F's two roots about each zero of xy are then closer than the
          * rounding of its coefficients resolves: use its factors */
         double bs = INFINITY, bus = NAN;
@@ -458,6 +528,11 @@ static int exact_hit(const curve_t *c, double tmax, double *t_out, double *u_out
     double scale = 0.0;
     for (int j = 0; j < 4; ++j)
         for (int k = 0; k < 3; ++k) scale = fmax(scale, fabs(c->q[j][k]));
+    if (!eo) {
+        double bs = INFINITY, bus = NAN;
+        near_edge_on_sides(c, &xy, scale, tmax, &bs, &bus);
+        if (bs < best) { best = bs; bu = bus; kind = 1; }
+    }
     for (int i = 0; i < nr; ++i) {
         double t;
         double Cu[4], Du[3];

@@ -266,3 +266,62 @@ def test_edge_on_rays_equal_capped_cylinder(zero_tangents):
         kind[i], t[i], _ = oracle.single_exact(rays[:, i], fibers[:, i])
     assert np.all(kind == 1), np.unique(kind, return_counts=True)
     assert np.max(np.abs(t - t_cf) / t_cf) < 1e-12
+
+
+def _near_collinear_perpendicular(n, seed=11):
+    """Near-collinear fibers along x (control points at thirds, jittered by
+    1e-6 N(0, I)) and rays exactly along -z through the fiber: the disc plane
+    of one u nearly contains each ray, so the side polynomial's two roots
+    about that u (the ray entering and leaving the disc) lie about 1e-11
+    apart."""
+    rng = np.random.default_rng(seed)
+    L = rng.uniform(0.1, 1.0, n)
+    k = np.arange(4)[None, :, None] / 3.0
+    P = np.zeros((n, 4, 4))
+    P[:, :, :3] = k * np.stack([L, 0 * L, 0 * L], 1)[:, None, :] + 1e-6 * rng.standard_normal((n, 4, 3))
+    P[:, :, :3] += np.round(rng.uniform(0, 1, (n, 3)) * 64)[:, None, :] / 64
+    r = rng.uniform(0.001, 0.02, n)
+    P[:, :, 3] = r[:, None]
+    F = W.pack_fibers(P)
+    P = W.unpack_fibers(F)
+    s = rng.uniform(0.05, 0.95, n)
+    A, B = P[:, 0, :3], P[:, 3, :3]
+    X = A + s[:, None] * (B - A)
+    O = X + np.stack([0 * L, rng.uniform(-1.2, 1.2, n) * r, 0 * L + 3.0], 1)
+    R = W.pack_rays(O, np.tile([0.0, 0.0, -1.0], (n, 1)), np.full(n, 100.0))
+    return R, F, P, r
+
+
+def test_discs_nearly_containing_the_ray():
+    """Where one disc plane nearly contains the ray, the entry and exit of
+    that disc are roots of the side polynomial closer together than its
+    coefficients' rounding resolves. The oracle must find the entry: every
+    hit of the chord's capped cylinder (outside a 1e-4 r band) is a hit,
+    within the 1e-6 jitter's effect (relative t 1e-4); pairs that an
+    isolation of the side polynomial alone got wrong (the exit taken, no
+    hit, or a hit where the ray passes outside the disc) and a sample of the
+    rest equal a 50-digit solution to 1e-12."""
+    n = 20000
+    R, F, P, r = _near_collinear_perpendicular(n)
+    O, D = R[0:3].T.astype(float), R[3:6].T.astype(float)
+    tmax = np.full(n, 100.0)
+    t, u, h, kind = oracle.intersect_exact(R, F)
+    with np.errstate(invalid="ignore"):
+        tc, uc, hc = capped_cylinder(O, D, P[:, 0, :3], P[:, 3, :3], r, tmax)
+        # the jitter moves the surface by up to about 5e-6 from the chord's cylinder
+        _, _, hl = capped_cylinder(O, D, P[:, 0, :3], P[:, 3, :3], r * (1 - 1e-4) - 5e-6, tmax)
+        _, _, hh = capped_cylinder(O, D, P[:, 0, :3], P[:, 3, :3], r * (1 + 1e-4) + 5e-6, tmax)
+    stable = (hl == hh)
+    assert stable.sum() > 0.9 * n and hc[stable].mean() > 0.7
+    assert np.array_equal(h[stable].astype(bool), hc[stable])
+    both = stable & hc & h.astype(bool)
+    assert np.max(np.abs(t[both] - tc[both]) / tc[both]) < 1e-4
+    rng = np.random.default_rng(5)
+    check = [6579, 6875, 8067, 10714, 18743] + list(rng.choice(np.nonzero(both)[0], 6, replace=False))
+    for i in check:
+        tb, ub = _mp_exact(R[:, i].astype(float), F[:, i].astype(float), dps=60)
+        assert hc[i] and math.isfinite(float(tb)), i
+        assert abs(float(tb) - t[i]) <= 1e-12 * float(tb), (i, float(tb), t[i])
+    for i in (3022, 16054):
+        tb, ub = _mp_exact(R[:, i].astype(float), F[:, i].astype(float), dps=60)
+        assert not hc[i] and tb == math.inf and not h[i], i

@@ -81,6 +81,10 @@ MUTANTS = [
     ("stall without the FP32 resolution bound", D, "const int stalled = (u0 == 0.0 || u1 == 1.0) && ext <= S->stall_abs &&",
      "const int stalled = (u0 == 0.0 || u1 == 1.0) &&"),
     ("stall without the bound relative to the root", D, "ext <= ldexp(S->stall_rel, -2 * level);", "1;"),
+    ("exact oracle: no side points about discs that nearly contain the ray", X,
+     "    if (!eo) {\n        double bs = INFINITY, bus = NAN;", "    if (0) {\n        double bs = INFINITY, bus = NAN;"),
+    ("exact oracle: side roots taken off the disc's circle", X, "if (on_circle && rest < -1e-9",
+     "if (0 && rest < -1e-9"),
     ("exact oracle: radius term with the wrong sign", X, "F = badd(&F, &a3, -1.0);", "F = badd(&F, &a3, 1.0);"),
     ("exact oracle: no limit disc at a zero end tangent", X, "while (j < 2 && cand[j][0]", "while (0 && cand[j][0]"),
     ("exact oracle: edge-on rays through the expanded polynomial", X, "if (edge_on(c)) {", "if (0) {"),
