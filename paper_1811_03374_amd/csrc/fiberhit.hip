@@ -548,7 +548,7 @@ __device__ __forceinline__ void leaf_candidates(const Curve64 &c, double ua, dou
                                                 double tmax, double t0, double u0, double &t_best,
                                                 double &u_best)
 {
-    constexpr int kWords = (NS + 1 + 31) / 32;
+    constexpr int kWords = (NS + 2 + 31) / 32;          // bits 0..NS + 1
     auto take = [&](double t, double u) {
         if (t >= tlo && t <= thi && t < tmax && t < t_best) { t_best = t; u_best = u; }
     };
@@ -583,6 +583,10 @@ __device__ __forceinline__ void leaf_candidates(const Curve64 &c, double ua, dou
         ppphi = pok ? pphi : INFINITY;
         pt = ct; pphi = cphi; pok = cok;
     }
+    // phi still falling at the last sample: a dip can sit between the last
+    // two samples (a stalled end, where the disc planes turn fast as u -> 1);
+    // recorded as event NS + 1, searched on (u[NS-1], u[NS])
+    if (pok && pphi > 0.0 && ppphi > pphi) min_m[(NS + 1) >> 5] |= 1u << ((NS + 1) & 31);
     // masks are indexed with unrolled selects (no dynamic register indexing)
     auto flag = [&](const uint32_t *m, int k) {
         uint32_t w = 0u;
@@ -609,10 +613,11 @@ __device__ __forceinline__ void leaf_candidates(const Curve64 &c, double ua, dou
     }
     // a local minimum of phi above zero at sample k-1: a dip below zero
     // narrower than the sampling has two boundary points in (u[k-2], u[k])
+    // (event NS + 1: in (u[NS-1], u[NS]))
     for (int k; (k = next_event(min_m)) >= 0;) {
         {
             constexpr double g = 0.38196601125010515;         // golden-section step
-            double a = at(k >= 2 ? k - 2 : 0), b = at(k), tt;
+            double a = at(k >= 2 ? k - 2 : 0), b = at(k > NS ? NS : k), tt;
             double x1 = a + g * (b - a), x2 = b - g * (b - a), f1 = 0.0, f2 = 0.0;
             bool ok = disc_point(c, x1, tt, f1) && disc_point(c, x2, tt, f2);
             for (int it = 0; ok && it < 48 && f1 > 0.0 && f2 > 0.0; ++it) {
@@ -628,7 +633,7 @@ __device__ __forceinline__ void leaf_candidates(const Curve64 &c, double ua, dou
                 const double um = f1 <= f2 ? x1 : x2;
                 double t, u;
                 if (boundary_root(c, at(k >= 2 ? k - 2 : 0), um, false, t, u)) take(t, u);
-                if (boundary_root(c, um, at(k), true, t, u)) take(t, u);
+                if (boundary_root(c, um, at(k > NS ? NS : k), true, t, u)) take(t, u);
             }
         }
     }

@@ -145,3 +145,22 @@ def test_stalled_end_levels_and_bounded_work():
     same = np.mean(c[both, 3] == st[both, 3])
     say(f"[degenerate]   zero-tangent leaf level equal to the oracle's: {same:.4f}")
     assert same >= 0.99
+
+
+def test_refined_edge_on_pairs():
+    """Two valid pairs of the 2^22-pair degenerate workload, both seen
+    edge-on (the ray nearly in a disc plane): a near-collinear fiber crossed
+    perpendicularly, whose entry and exit of one disc are 1e-11 apart in u,
+    and a straight fiber with zero end tangents crossed 1e-4 in u from its
+    stalled end, where phi falls into a dip between the last two samples of
+    the FP64 scan. Refined results equal the exact oracle's to 1e-12."""
+    w = W.degenerate_geometry(1 << 22).subset(np.array([99169, 2648198]))
+    g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    say("[refined] edge-on regression pairs")
+    t32, u32, h, t64, u64 = [o.cpu().numpy() for o in binding.intersect_pairs(
+        g(w.rays), g(w.fibers), 22, refine=True)]
+    torch.cuda.synchronize()
+    t_x, u_x, h_x, kind = oracle.intersect_exact(w.rays, w.fibers)
+    assert h_x.all() and h.all(), (h, h_x)
+    assert np.all(np.abs(t64 - t_x) <= 1e-12 * t_x), (t64, t_x)
+    assert np.all(np.abs(u64 - u_x) <= 1e-9), (u64, u_x)
