@@ -58,6 +58,7 @@ extern "C" {
 #define FI_ERR_HIP       (-3)   /* the HIP runtime reported an error at launch        */
 #define FI_ERR_WORKSPACE (-4)   /* workspace pointer missing, misaligned or too small */
 #define FI_ERR_SCRATCH   (-5)   /* more scratch than the no-allocation entry point holds */
+#define FI_ERR_IO        (-6)   /* a tuning table file could not be opened or written  */
 
 /* Flags. */
 /* FI_FP64_REFINE: for pairs of depth > 16, run the traversal with every
@@ -407,11 +408,18 @@ typedef struct fi_scene {
  *   refill          free lanes take queued pairs once at least this many
  *                   (1..64) are free (default 1);
  *   waves_per_simd  cap on resident waves per SIMD (0..16, 0 = as many as fit,
- *                   which is 4 for the batched kernel).
+ *                   which is 4 for the batched kernel);
+ *   stack           layout of the traversal stack (Section 3.3 keeps only the
+ *                   bit string): 0 (default) caches the parent of the latest
+ *                   split that left a sibling pending in LDS, so the usual
+ *                   backtrack rebuilds that sibling with one split; 1 keeps
+ *                   no cache, and every backtrack replays the split rules
+ *                   from the root.
  * Results never depend on the tuning. */
 typedef struct fi_tuning {
     int32_t refill;
     int32_t waves_per_simd;
+    int32_t stack;
 } fi_tuning;
 
 /* Bytes of device workspace fiber_intersect_batched needs for n_scenes
@@ -470,18 +478,47 @@ int fiber_batch_plan_destroy(fi_batch_plan *plan);
 /*
  * fiber_batch_autotune -- time fiber_intersect_batched on these scenes over a
  * grid of tunings (refill 32, 48 or 56, with FI_FP64_REFINE 4, 8 or 16;
- * waves per SIMD 4, 5 or as many as fit), each `repeats`
+ * waves per SIMD 4, 5 or as many as fit; stack 0 or 1), each `repeats`
  * times after one warm-up, and return the fastest
  * in *best (and its time in *best_ms if not NULL). Overwrites the scenes'
  * outputs. Blocks the host until the timing runs finish. The result is also
- * remembered for the process, keyed by device and the batch's size class
- * (log2 of total pairs and of the problem count) and the refinement flag:
- * later batched calls and
- * plans of that class that pass tuning = NULL use it.
+ * remembered in the process's tuning table, keyed by the current device's
+ * architecture name (e.g. "gfx950"), the refinement flag and the batch's
+ * class: floor(log2) of its total pairs, floor(log2) of its problem count
+ * and the bucket of its largest scene depth field (0: <= 9, 1: <= 16,
+ * 2: deeper). Later batched calls and plans of that class that pass
+ * tuning = NULL use it.
  */
 int fiber_batch_autotune(const fi_scene *scenes, int32_t n_scenes, uint32_t flags, void *workspace,
                          size_t workspace_bytes, void *stream, int32_t repeats,
                          fi_tuning *best, float *best_ms);
+
+/*
+ * The tuning table across processes (host only; no GPU needed).
+ *
+ * fiber_tuning_save -- write every entry of the process's tuning table to the
+ * text file at path (created or replaced): the line "fiberhit-tuning 1", then
+ * one line per entry, "arch refine log2_pairs log2_scenes depth_bucket refill
+ * waves_per_simd stack". FI_ERR_NULL, FI_ERR_IO.
+ *
+ * fiber_tuning_load -- merge the entries of such a file into the table
+ * (entries of the same key are replaced). A file with a bad header, a
+ * malformed line or a value out of range merges nothing: FI_ERR_RANGE.
+ * FI_ERR_NULL, FI_ERR_IO (cannot open).
+ *
+ * fiber_tuning_lookup -- the table's entry for a batch of n_scenes problems
+ * (>= 1) with total_pairs pairs (>= 0) and largest depth max_depth (0..23)
+ * under flags (FI_FP64_REFINE selects the refined entries) on architecture
+ * arch: FI_OK and *out, or FI_ERR_RANGE when there is none (or an argument
+ * is out of range). FI_ERR_NULL.
+ *
+ * fiber_tuning_clear -- empty the table. FI_OK.
+ */
+int fiber_tuning_save(const char *path);
+int fiber_tuning_load(const char *path);
+int fiber_tuning_lookup(const char *arch, uint32_t flags, int64_t total_pairs, int32_t n_scenes,
+                        int32_t max_depth, fi_tuning *out);
+int fiber_tuning_clear(void);
 
 #ifdef __cplusplus
 }

@@ -15,6 +15,7 @@ import torch
 from . import build_lib
 
 FI_OK = 0
+FI_ERR_RANGE = -2
 FI_MAX_DEPTH = 23
 FI_FP64_REFINE = 1
 FI_COMPENSATED_PROJ = 2
@@ -73,7 +74,8 @@ def exported_symbols():
             "fiber_validate", "fiber_presplit_workspace_bytes", "fiber_presplit_count", "fiber_presplit",
             "fiber_batched_workspace_bytes", "fiber_intersect_batched", "fiber_batch_plan_create",
             "fiber_batch_plan_launch", "fiber_batch_plan_tuning", "fiber_batch_plan_destroy",
-            "fiber_batch_autotune"]
+            "fiber_batch_autotune", "fiber_tuning_save", "fiber_tuning_load", "fiber_tuning_lookup",
+            "fiber_tuning_clear"]
 
 
 def _check(status: int):
@@ -412,10 +414,10 @@ class FiScene(C.Structure):
 
 
 class FiTuning(C.Structure):
-    _fields_ = [("refill", C.c_int32), ("waves_per_simd", C.c_int32)]
+    _fields_ = [("refill", C.c_int32), ("waves_per_simd", C.c_int32), ("stack", C.c_int32)]
 
     def as_dict(self):
-        return {"refill": self.refill, "waves_per_simd": self.waves_per_simd}
+        return {"refill": self.refill, "waves_per_simd": self.waves_per_simd, "stack": self.stack}
 
 
 def _batched_lib():
@@ -439,6 +441,12 @@ def _batched_lib():
         L.fiber_batch_autotune.argtypes = [C.POINTER(FiScene), C.c_int32, C.c_uint32, vp, C.c_size_t,
                                            vp, C.c_int32, C.POINTER(FiTuning), C.POINTER(C.c_float)]
         L.fiber_batch_autotune.restype = C.c_int
+        L.fiber_tuning_save.argtypes = [C.c_char_p]
+        L.fiber_tuning_load.argtypes = [C.c_char_p]
+        L.fiber_tuning_lookup.argtypes = [C.c_char_p, C.c_uint32, C.c_int64, C.c_int32, C.c_int32,
+                                          C.POINTER(FiTuning)]
+        for f in (L.fiber_tuning_save, L.fiber_tuning_load, L.fiber_tuning_lookup, L.fiber_tuning_clear):
+            f.restype = C.c_int
         L._batched_ready = True
     return L
 
@@ -498,7 +506,7 @@ def _tuning(t):
         return None
     if isinstance(t, FiTuning):
         return C.byref(t)
-    return C.byref(FiTuning(int(t["refill"]), int(t["waves_per_simd"])))
+    return C.byref(FiTuning(int(t["refill"]), int(t["waves_per_simd"]), int(t.get("stack", 0))))
 
 
 def workspace_for(problems, device=None):
@@ -571,3 +579,30 @@ def autotune(problems, repeats=2, workspace=None, stream=None, refine=False):
                                   workspace.numel(), _stream(stream), int(repeats), C.byref(best),
                                   C.byref(ms)))
     return best.as_dict(), ms.value
+
+
+def save_tuning(path):
+    """Write the process's tuning table (every autotuned or loaded entry) to
+    a text file."""
+    _check(_batched_lib().fiber_tuning_save(os.fsencode(path)))
+
+
+def load_tuning(path):
+    """Merge a tuning table file into the process's table."""
+    _check(_batched_lib().fiber_tuning_load(os.fsencode(path)))
+
+
+def lookup_tuning(arch, total_pairs, n_scenes, max_depth, refine=False):
+    """The table's tuning (dict) for a batch of this class on ``arch``
+    (e.g. "gfx950"), or None."""
+    t = FiTuning()
+    st = _batched_lib().fiber_tuning_lookup(arch.encode(), FI_FP64_REFINE if refine else 0, int(total_pairs),
+                                            int(n_scenes), int(max_depth), C.byref(t))
+    if st == FI_ERR_RANGE:
+        return None
+    _check(st)
+    return t.as_dict()
+
+
+def clear_tuning():
+    _check(_batched_lib().fiber_tuning_clear())

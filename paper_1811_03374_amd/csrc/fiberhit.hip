@@ -32,8 +32,13 @@
 #include <atomic>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
+#include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
 
 #include "fiberhit.h"
 
@@ -906,13 +911,14 @@ __device__ __forceinline__ void split_plane(const Lane &L, float te, float tx, S
 
 // Bookkeeping of a descent into the near half (Section 3.3: one level down,
 // the far half pending when the ray meets both).
+template <bool PC>
 __device__ __forceinline__ void descend_state(Lane &L, const Split &sp)
 {
     if (sp.oblique) { L.lo = sp.nlo; L.hi = sp.nhi; }
     L.size >>= 1;
     if (sp.both) {
         L.bits ^= L.size;
-        if (kParentCache) L.cached = L.size;
+        if (PC) L.cached = L.size;
     }
     if (sp.near_right) L.start ^= L.size;
 }
@@ -981,12 +987,18 @@ __device__ __forceinline__ void stall_init(Lane &L)
 __device__ __forceinline__ bool stalled_end(const Lane &L)
 {
     const float s = (float)L.size * 0x1p-23f;                 // 2^-level
+    const float rel = L.stall_rel * s * s;
+    // the chord alone fails the relative bound at every regular node: the
+    // extent (at least the chord) is only formed where it passes
+    const float cc = dot3(L.c.d.x, L.c.d.y, L.c.d.z, L.c.d.x, L.c.d.y, L.c.d.z);
+    if (!(cc <= rel)) return false;
     const float e = node_extent(L.c);
     const bool end = L.start == 0u || L.start + L.size == kRootSize;
-    return end && e <= L.stall_abs && e <= L.stall_rel * s * s;
+    return end && e <= L.stall_abs && e <= rel;
 }
 
-template <int MODE, bool QUAD, class Root>
+// PC: the parent cache in LDS (else every backtrack replays from the root)
+template <int MODE, bool QUAD, bool PC, class Root>
 __device__ __forceinline__ int trip(Lane &L, const Root &root, float *col, HitGeo &hg)
 {
     float te, tx, lo, hi;
@@ -1028,7 +1040,7 @@ __device__ __forceinline__ int trip(Lane &L, const Root &root, float *col, HitGe
         L.start ^= L.size;
         L.bits ^= L.size;
         L.start &= ~(L.size - 1u);
-        if (kParentCache && L.cached == L.size) {
+        if (PC && L.cached == L.size) {
             lds_get(col, L.c);
         } else {
             root.get(L, L.c);
@@ -1045,13 +1057,13 @@ __device__ __forceinline__ int trip(Lane &L, const Root &root, float *col, HitGe
     Split sp;
     split_plane<MODE>(L, te, tx, sp);
     const bool descend = vis && st == kGoOn;
-    if (kParentCache && descend && sp.both) lds_put(col, L.c);
+    if (PC && descend && sp.both) lds_put(col, L.c);
     const bool right = back ? (L.start & L.size) != 0u : sp.near_right;
     take_child(L.c, sp.dp, sp.tc, right);
     if (back) {
         cap_interval(L.c, L.tmax, L.lo, L.hi);
     } else if (descend) {
-        descend_state(L, sp);
+        descend_state<PC>(L, sp);
     }
     // work counters (counting variant only), branch-free
     if (MODE == kCount) {
@@ -1349,7 +1361,7 @@ __device__ __forceinline__ void wave_range(int64_t w, int64_t waves, int64_t cou
 #ifndef FIBERHIT_WAVES
 #define FIBERHIT_WAVES 4                      // build knob: register budget (waves per SIMD)
 #endif
-template <int MODE, bool BATCHED, bool CAND = false, bool QUAD = false>
+template <int MODE, bool BATCHED, bool CAND = false, bool QUAD = false, bool PC = kParentCache>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MODE == kConservative ? 4 : FIBERHIT_WAVES, 8)))
 void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, int64_t count, int refill,
              const float *aos)
@@ -1493,7 +1505,7 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
         // of the call).
         if (__ballot(active) == 0 && next >= end && q_count == 0) break;
         HitGeo hg;
-        const int st = trip<MODE, QUAD>(L, root, col, hg);
+        const int st = trip<MODE, QUAD, PC>(L, root, col, hg);
         if (active && st != kGoOn && !(MODE == kConservative && L.waiting)) {
             if constexpr (BATCHED) {
                 // lanes of the wave's current scene read its output
@@ -1612,17 +1624,22 @@ int check_common(const float *rays, int64_t ray_stride, int64_t n_rays,
 using FusedFn = void (*)(Args, const Args *, const int64_t *, int, int64_t, int, const float *);
 // [0] plain, [1] counting, [2] conservative (single calls), [3] plain and
 // [4] conservative over a scene table, [5] plain and [6] conservative over
-// candidate lists
-constexpr int kVariants = 10;
+// candidate lists, [7..9] plain, counting and conservative on quadratic
+// fibers, [10] plain and [11] conservative over a scene table without the
+// parent cache (a tuning choice: every backtrack replays from the root)
+constexpr int kVariants = 12;
 const FusedFn kFused[kVariants] = {k_fused<kPlain, false>, k_fused<kCount, false>, k_fused<kConservative, false>,
                                    k_fused<kPlain, true>, k_fused<kConservative, true>,
                                    k_fused<kPlain, false, true>, k_fused<kConservative, false, true>,
                                    k_fused<kPlain, false, false, true>, k_fused<kCount, false, false, true>,
-                                   k_fused<kConservative, false, false, true>};
+                                   k_fused<kConservative, false, false, true>,
+                                   k_fused<kPlain, true, false, false, false>,
+                                   k_fused<kConservative, true, false, false, false>};
 constexpr int kBatchedVariant = 3;
 constexpr int kBatchedRefineVariant = 4;
 constexpr int kCandVariant = 5;              // + 1: refined
 constexpr int kQuadVariant = 7;              // + kPlain, kCount, kConservative: quadratic fibers
+constexpr int kBatchedReplayVariant = 10;    // + 1: refined
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 constexpr size_t kMaxRecordBytes = (size_t)1 << 30;                 // fiber records, largest table
@@ -1642,6 +1659,7 @@ static __device__ __align__(256) float scratch[kScratchBytes / sizeof(float)];
 struct DeviceInfo {
     std::atomic<bool> ready;
     int cus;
+    char arch[64];                             // architecture name (gfx950...), without feature flags
     int fused_resident[kVariants];             // resident waves per CU, per variant (as kFused)
     float *scratch;                            // this device's copy of `scratch`
     std::mutex stage_mutex;
@@ -1672,6 +1690,14 @@ int device_info(DeviceInfo *&out)
         if (!d.ready.load(std::memory_order_relaxed)) {
             if (hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
                 return FI_ERR_HIP;
+            hipDeviceProp_t prop;
+            if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return FI_ERR_HIP;
+            size_t n = 0;
+            while (n + 1 < sizeof d.arch && prop.gcnArchName[n] && prop.gcnArchName[n] != ':') {
+                d.arch[n] = prop.gcnArchName[n];
+                ++n;
+            }
+            d.arch[n] = '\0';
             for (int m = 0; m < kVariants; ++m) {
                 int nb = 0;
                 if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)kFused[m], kWave, 0) != hipSuccess)
@@ -1715,39 +1741,46 @@ size_t record_bytes(int64_t n_pairs, int64_t n_fibers, bool gathered)
 #endif
 fi_tuning default_tuning(bool refine)
 {
-    return fi_tuning{refine ? FIBERHIT_REFINE_REFILL : FIBERHIT_DEFAULT_REFILL, FIBERHIT_DEFAULT_WAVES_PER_SIMD};
+    return fi_tuning{refine ? FIBERHIT_REFINE_REFILL : FIBERHIT_DEFAULT_REFILL, FIBERHIT_DEFAULT_WAVES_PER_SIMD, 0};
 }
 
-// Autotune results, kept for the process: keyed by device, the refinement
-// flag and the size class of a batch (log2 of its total pairs and of its
-// problem count). A batch launched without an explicit tuning uses the entry
-// of its class if one exists.
+// Autotune results: keyed by the GPU architecture, the refinement flag and
+// the batch's class -- log2 of its total pairs, log2 of its problem count and
+// a depth bucket of its largest depth (<= 9, <= 16, deeper). A batch launched
+// without an explicit tuning uses the entry of its class if one exists. The
+// table lives for the process; fiber_tuning_save / fiber_tuning_load keep it
+// in a text file across processes.
+using TuneKey = std::tuple<std::string, int, int, int, int>;
 std::mutex g_tune_mutex;
-std::map<uint64_t, fi_tuning> g_tune_cache;
+std::map<TuneKey, fi_tuning> g_tune_cache;
 
-uint64_t tune_key(int device, int64_t total, int n_scenes, bool refine)
+int log2_floor(int64_t x)
 {
-    int lt = 0, ls = 0;
-    while ((int64_t)1 << (lt + 1) <= total && lt < 62) ++lt;
-    while ((1 << (ls + 1)) <= n_scenes && ls < 30) ++ls;
-    return ((uint64_t)device << 24) | ((uint64_t)refine << 16) | ((uint64_t)lt << 8) | (uint64_t)ls;
+    int l = 0;
+    while (l < 62 && ((int64_t)1 << (l + 1)) <= x) ++l;
+    return l;
 }
 
-fi_tuning tuned_or_default(int64_t total, int n_scenes, bool refine)
+int depth_bucket(int max_depth) { return max_depth <= 9 ? 0 : max_depth <= 16 ? 1 : 2; }
+
+TuneKey tune_key(const std::string &arch, int64_t total, int n_scenes, int max_depth, bool refine)
 {
-    int dev = 0;
-    if (current_device(dev) != FI_OK) return default_tuning(refine);
-    std::lock_guard<std::mutex> lock(g_tune_mutex);
-    const auto it = g_tune_cache.find(tune_key(dev, total, n_scenes, refine));
-    return it == g_tune_cache.end() ? default_tuning(refine) : it->second;
+    return TuneKey{arch, refine ? 1 : 0, log2_floor(total), log2_floor(n_scenes), depth_bucket(max_depth)};
 }
 
-void remember_tuning(int64_t total, int n_scenes, bool refine, const fi_tuning &t)
+int check_tuning(const fi_tuning &t)
 {
-    int dev = 0;
-    if (current_device(dev) != FI_OK) return;
-    std::lock_guard<std::mutex> lock(g_tune_mutex);
-    g_tune_cache[tune_key(dev, total, n_scenes, refine)] = t;
+    if (t.refill < 1 || t.refill > kWave || t.waves_per_simd < 0 || t.waves_per_simd > 16 || t.stack < 0 ||
+        t.stack > 1)
+        return FI_ERR_RANGE;
+    return FI_OK;
+}
+
+int max_scene_depth(const fi_scene *sc, int32_t n)
+{
+    int d = 0;
+    for (int k = 0; k < n; ++k) d = sc[k].depth > d ? sc[k].depth : d;
+    return d;
 }
 
 int64_t total_pairs(const fi_scene *sc, int32_t n)
@@ -1757,11 +1790,25 @@ int64_t total_pairs(const fi_scene *sc, int32_t n)
     return t;
 }
 
-int check_tuning(const fi_tuning &t)
+// The remembered tuning of this batch's class on the current device, else
+// the defaults.
+fi_tuning tuned_or_default(const fi_scene *sc, int32_t n, bool refine)
 {
-    if (t.refill < 1 || t.refill > kWave || t.waves_per_simd < 0 || t.waves_per_simd > 16) return FI_ERR_RANGE;
-    return FI_OK;
+    DeviceInfo *d = nullptr;
+    if (device_info(d) != FI_OK) return default_tuning(refine);
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    const auto it = g_tune_cache.find(tune_key(d->arch, total_pairs(sc, n), n, max_scene_depth(sc, n), refine));
+    return it == g_tune_cache.end() ? default_tuning(refine) : it->second;
 }
+
+void remember_tuning(const fi_scene *sc, int32_t n, bool refine, const fi_tuning &t)
+{
+    DeviceInfo *d = nullptr;
+    if (device_info(d) != FI_OK) return;
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tune_cache[tune_key(d->arch, total_pairs(sc, n), n, max_scene_depth(sc, n), refine)] = t;
+}
+
 
 // Persistent waves of a single call: the resident waves. Twice as many,
 // each with half the share, made single deep calls (depth 16 and 22 at 2^20
@@ -1858,7 +1905,8 @@ BatchLayout layout_of(void *ws, int n)
 void launch_batched(const DeviceInfo &d, const fi_tuning &t, const BatchLayout &L, int n_scenes, int64_t total,
                     bool refine, hipStream_t s)
 {
-    const int variant = refine ? kBatchedRefineVariant : kBatchedVariant;
+    const int variant = t.stack == 1 ? kBatchedReplayVariant + (refine ? 1 : 0)
+                                     : (refine ? kBatchedRefineVariant : kBatchedVariant);
     int per_cu = d.fused_resident[variant];
     if (t.waves_per_simd > 0 && 4 * t.waves_per_simd < per_cu) per_cu = 4 * t.waves_per_simd;
     int64_t g = (total + kWave - 1) / kWave;
@@ -1909,7 +1957,7 @@ struct fi_batch_plan {
 };
 
 extern "C" {
-int fi_version(void) { return (0 << 16) | (8 << 8) | 0; }
+int fi_version(void) { return (0 << 16) | (9 << 8) | 0; }
 
 const char *fi_strerror(int status)
 {
@@ -1920,6 +1968,7 @@ const char *fi_strerror(int status)
     case FI_ERR_HIP: return "the HIP runtime reported an error";
     case FI_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
     case FI_ERR_SCRATCH: return "the call needs more scratch than the no-allocation entry point holds";
+    case FI_ERR_IO: return "a tuning table file could not be opened or written";
     default: return "unknown status";
     }
 }
@@ -2074,7 +2123,7 @@ int fiber_intersect_batched(const fi_scene *scenes, int32_t n_scenes, const fi_t
     if (n_scenes == 0) return FI_OK;
     if (!scenes) return FI_ERR_NULL;
     const bool refine = (flags & FI_FP64_REFINE) != 0u;
-    const fi_tuning t = tuning ? *tuning : tuned_or_default(total_pairs(scenes, n_scenes), n_scenes, refine);
+    const fi_tuning t = tuning ? *tuning : tuned_or_default(scenes, n_scenes, refine);
     if (check_tuning(t) != FI_OK) return FI_ERR_RANGE;
     (void)hipGetLastError();
     return batched_enqueue(scenes, n_scenes, flags, t, workspace, workspace_bytes, (hipStream_t)stream);
@@ -2088,7 +2137,7 @@ int fiber_batch_plan_create(const fi_scene *scenes, int32_t n_scenes, const fi_t
     if (n_scenes <= 0 || (flags & ~(uint32_t)(FI_FP64_REFINE | FI_COMPENSATED_PROJ)) != 0u) return FI_ERR_RANGE;
     if (!scenes) return FI_ERR_NULL;
     const bool refine = (flags & FI_FP64_REFINE) != 0u;
-    const fi_tuning t = tuning ? *tuning : tuned_or_default(total_pairs(scenes, n_scenes), n_scenes, refine);
+    const fi_tuning t = tuning ? *tuning : tuned_or_default(scenes, n_scenes, refine);
     if (check_tuning(t) != FI_OK) return FI_ERR_RANGE;
     (void)hipGetLastError();
     DeviceInfo *d = nullptr;
@@ -2179,9 +2228,10 @@ int fiber_batch_autotune(const fi_scene *scenes, int32_t n_scenes, uint32_t flag
     float best_t = INFINITY;
     fi_tuning bt = default_tuning(refine);
     int st = FI_OK;
+    for (int sk = 0; sk < 2 && st == FI_OK; ++sk)
     for (int oi = 0; oi < 3 && st == FI_OK; ++oi)
         for (int ri = 0; ri < 3 && st == FI_OK; ++ri) {
-            const fi_tuning t{refills[ri], occ[oi]};
+            const fi_tuning t{refills[ri], occ[oi], sk};
             float tmin = INFINITY;
             for (int r = 0; r <= repeats && st == FI_OK; ++r) {       // first run warms up
                 if (hipEventRecord(e0, s) != hipSuccess) { st = FI_ERR_HIP; break; }
@@ -2199,7 +2249,79 @@ int fiber_batch_autotune(const fi_scene *scenes, int32_t n_scenes, uint32_t flag
     if (st != FI_OK) return st;
     *best = bt;
     if (best_ms) *best_ms = best_t;
-    remember_tuning(total_pairs(scenes, n_scenes), n_scenes, refine, bt);
+    remember_tuning(scenes, n_scenes, refine, bt);
+    return FI_OK;
+}
+
+// Tuning table files: a header line, then one entry per line --
+// arch refine log2_pairs log2_scenes depth_bucket refill waves_per_simd stack
+int fiber_tuning_save(const char *path)
+{
+    if (!path) return FI_ERR_NULL;
+    std::vector<std::pair<TuneKey, fi_tuning>> rows;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mutex);
+        rows.assign(g_tune_cache.begin(), g_tune_cache.end());
+    }
+    FILE *f = fopen(path, "w");
+    if (!f) return FI_ERR_IO;
+    bool ok = fprintf(f, "fiberhit-tuning 1\n") > 0;
+    for (const auto &r : rows)
+        ok = ok && fprintf(f, "%s %d %d %d %d %d %d %d\n", std::get<0>(r.first).c_str(), std::get<1>(r.first),
+                           std::get<2>(r.first), std::get<3>(r.first), std::get<4>(r.first), r.second.refill,
+                           r.second.waves_per_simd, r.second.stack) > 0;
+    ok = (fclose(f) == 0) && ok;
+    return ok ? FI_OK : FI_ERR_IO;
+}
+
+int fiber_tuning_load(const char *path)
+{
+    if (!path) return FI_ERR_NULL;
+    FILE *f = fopen(path, "r");
+    if (!f) return FI_ERR_IO;
+    std::vector<std::pair<TuneKey, fi_tuning>> rows;
+    char line[256];
+    bool ok = fgets(line, sizeof line, f) && strcmp(line, "fiberhit-tuning 1\n") == 0;
+    while (ok && fgets(line, sizeof line, f)) {
+        char arch[64];
+        int rf, lt, ls, db;
+        fi_tuning t;
+        char tail;
+        if (sscanf(line, "%63s %d %d %d %d %d %d %d %c", arch, &rf, &lt, &ls, &db, &t.refill, &t.waves_per_simd,
+                   &t.stack, &tail) != 8 ||
+            rf < 0 || rf > 1 || lt < 0 || lt > 62 || ls < 0 || ls > 31 || db < 0 || db > 2 ||
+            check_tuning(t) != FI_OK) {
+            ok = false;
+            break;
+        }
+        rows.push_back({TuneKey{arch, rf, lt, ls, db}, t});
+    }
+    fclose(f);
+    if (!ok) return FI_ERR_RANGE;
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    for (const auto &r : rows) g_tune_cache[r.first] = r.second;
+    return FI_OK;
+}
+
+int fiber_tuning_lookup(const char *arch, uint32_t flags, int64_t total_pairs, int32_t n_scenes, int32_t max_depth,
+                        fi_tuning *out)
+{
+    if (!arch || !out) return FI_ERR_NULL;
+    if (total_pairs < 0 || n_scenes < 1 || max_depth < 0 || max_depth > FI_MAX_DEPTH ||
+        (flags & ~(uint32_t)(FI_FP64_REFINE | FI_COMPENSATED_PROJ)) != 0u)
+        return FI_ERR_RANGE;
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    const auto it =
+        g_tune_cache.find(tune_key(arch, total_pairs, n_scenes, max_depth, (flags & FI_FP64_REFINE) != 0u));
+    if (it == g_tune_cache.end()) return FI_ERR_RANGE;
+    *out = it->second;
+    return FI_OK;
+}
+
+int fiber_tuning_clear(void)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tune_cache.clear();
     return FI_OK;
 }
 

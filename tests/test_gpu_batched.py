@@ -77,7 +77,8 @@ def test_results_do_not_depend_on_tuning():
     ws, sizes, probs = make_scenes(seed=9)
     ref = plain_reference(probs)
     for t in ({"refill": 8, "waves_per_simd": 2}, {"refill": 64, "waves_per_simd": 0},
-              {"refill": 1, "waves_per_simd": 1}, {"refill": 32, "waves_per_simd": 16}):
+              {"refill": 1, "waves_per_simd": 1}, {"refill": 32, "waves_per_simd": 16},
+              {"refill": 56, "waves_per_simd": 0, "stack": 1}, {"refill": 4, "waves_per_simd": 4, "stack": 1}):
         clear(probs)
         binding.intersect_batched(probs, tuning=t)
         torch.cuda.synchronize()
@@ -135,12 +136,27 @@ def test_batched_parity_against_oracle():
         assert st["ok"], st
 
 
-def test_autotune_returns_a_grid_point():
+def test_autotune_returns_a_grid_point(tmp_path):
+    """The fastest grid point is remembered under the device's architecture
+    and the batch's class, used by later calls, and survives a save and a
+    load of the table."""
     ws, sizes, probs = make_scenes(seed=17)
+    binding.clear_tuning()
     best, ms = binding.autotune(probs, repeats=1)
     say(f"[autotune] {best} {ms:.3f} ms")
-    assert best["refill"] in (32, 48, 56) and best["waves_per_simd"] in (4, 5, 0)
+    assert best["refill"] in (32, 48, 56) and best["waves_per_simd"] in (4, 5, 0) and best["stack"] in (0, 1)
     assert ms > 0
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    total = sum(int(p.n) for p in probs)
+    depth = max(int(p.depth) for p in probs)
+    assert binding.lookup_tuning(arch, total, len(probs), depth) == best
+    assert binding.BatchPlan(probs).tuning() == best
+    path = str(tmp_path / "tuning.txt")
+    binding.save_tuning(path)
+    binding.clear_tuning()
+    binding.load_tuning(path)
+    assert binding.lookup_tuning(arch, total, len(probs), depth) == best
+    binding.clear_tuning()
 
 
 def test_batched_argument_errors():
@@ -156,6 +172,8 @@ def test_batched_argument_errors():
         binding.intersect_batched(probs, tuning={"refill": 65, "waves_per_simd": 0})
     with pytest.raises(binding.FiberHitError):
         binding.intersect_batched(probs, tuning={"refill": 32, "waves_per_simd": 17})
+    with pytest.raises(binding.FiberHitError):
+        binding.intersect_batched(probs, tuning={"refill": 32, "waves_per_simd": 0, "stack": 2})
 
 
 def test_batched_four_million_pairs():
