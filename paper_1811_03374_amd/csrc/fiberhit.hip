@@ -56,7 +56,7 @@ __device__ __forceinline__ int qslot(int x)
     x = x >= kQueue ? x - kQueue : x;
     return x >= kQueue ? x - kQueue : x;
 }
-constexpr int kQWords = 21;                   // root node (16), lo, hi, tmax, pair, scene * 32 + depth
+constexpr int kQWords = 21;                   // root node (16), lo, hi, tmax, pair, scene * 64 + stall * 32 + depth
 constexpr uint32_t kRootSize = 1u << 23;      // parametric domain [0, 1) in units of 2^-23
 constexpr int kMaxTrips = 1 << 16;            // hang guard; real pairs need < 200 trips
 #ifndef FIBERHIT_PARENT_CACHE
@@ -680,7 +680,7 @@ struct Lane {
     float tmax, t;                // ray tmax; hit distance once found
     uint32_t bits, start, size;   // Section 3.3: pending-sibling bits, integer interval
     uint32_t min_size;            // leaf size 2^(23 - depth)
-    float stall_abs, stall_rel;   // stalled end nodes: extent thresholds (see node_extent)
+    int32_t stall;                // the pair's end nodes may stall (see stall_possible)
     uint32_t cached;              // size of the pending children whose parent is cached (0: none)
     int32_t waiting;              // refinement: parked at its first leaf until the wave decides it
     float ru;                     //   the FP32 u of the leaf hit (Newton's start)
@@ -972,29 +972,43 @@ __device__ __forceinline__ float node_extent(const Node &c)
     return fmaxf(cc, fmaxf(a0, a1));
 }
 
-__device__ __forceinline__ void stall_init(Lane &L)
+// The end nodes' outer tangents shrink exactly like 2^-level (halving is
+// exact), so their extents stay at least |t0|^2 4^-level (start) and
+// |t1|^2 4^-level (end): a pair whose root end tangents both exceed 2^-15 of
+// the root's extent (a factor 2 above the bound, against rounding) can never
+// stall, and its lanes skip the test. Decided in the setup round, with the
+// root's other tests.
+__device__ __forceinline__ bool stall_possible(const Node &r)
 {
-    const Node &r = L.c;
+    const float a0 = dot3(r.t0.x, r.t0.y, r.t0.z, r.t0.x, r.t0.y, r.t0.z);
+    const float a1 = dot3(r.t1.x, r.t1.y, r.t1.z, r.t1.x, r.t1.y, r.t1.z);
+    const float ext = node_extent(r);
+    return a0 <= 0x1p-15f * ext || a1 <= 0x1p-15f * ext;
+}
+
+// (2^-20 X)^2 of the pair's root (X: its largest ray-frame coordinate)
+__device__ __forceinline__ float stall_abs(const Node &r)
+{
     const float ex = r.p.x + r.d.x, ey = r.p.y + r.d.y, ez = r.p.z + r.d.z;     // p3
     float X = fmaxf(fabsf(r.p.x), fmaxf(fabsf(r.p.y), fabsf(r.p.z)));
     X = fmaxf(X, fmaxf(fabsf(r.p.x + r.t0.x), fmaxf(fabsf(r.p.y + r.t0.y), fabsf(r.p.z + r.t0.z))));
     X = fmaxf(X, fmaxf(fabsf(ex - r.t1.x), fmaxf(fabsf(ey - r.t1.y), fabsf(ez - r.t1.z))));
     X = fmaxf(X, fmaxf(fabsf(ex), fmaxf(fabsf(ey), fabsf(ez))));
-    L.stall_abs = 0x1p-40f * X * X;
-    L.stall_rel = 0x1p-16f * node_extent(r);
+    return 0x1p-40f * X * X;
 }
 
 __device__ __forceinline__ bool stalled_end(const Lane &L)
 {
+    if (!L.stall) return false;
     const float s = (float)L.size * 0x1p-23f;                 // 2^-level
-    const float rel = L.stall_rel * s * s;
+    const float rel = 0x1p-16f * node_extent(L.root) * s * s;
     // the chord alone fails the relative bound at every regular node: the
     // extent (at least the chord) is only formed where it passes
     const float cc = dot3(L.c.d.x, L.c.d.y, L.c.d.z, L.c.d.x, L.c.d.y, L.c.d.z);
     if (!(cc <= rel)) return false;
     const float e = node_extent(L.c);
     const bool end = L.start == 0u || L.start + L.size == kRootSize;
-    return end && e <= L.stall_abs && e <= rel;
+    return end && e <= rel && e <= stall_abs(L.root);
 }
 
 // PC: the parent cache in LDS (else every backtrack replays from the root)
@@ -1454,7 +1468,7 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
                 q[17 * kQueue] = rhi;
                 q[18 * kQueue] = rtmax;
                 q[19 * kQueue] = __int_as_float((int)idx);
-                q[20 * kQueue] = __int_as_float((sc << 5) | (int)depth);
+                q[20 * kQueue] = __int_as_float((sc << 6) | (stall_possible(r) ? 32 : 0) | (int)depth);
             }
             q_count += __popcll(qm);
             next += take;
@@ -1479,10 +1493,10 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
                     L.pair = __float_as_int(q[19 * kQueue]);
                     const int ds = __float_as_int(q[20 * kQueue]);
                     const uint32_t depth = (uint32_t)ds & 31u;
-                    L.scene = ds >> 5;
+                    L.scene = ds >> 6;
+                    L.stall = ds & 32;
                     L.root = L.c;
                     L.min_size = kRootSize >> depth;
-                    stall_init(L);
                     L.slack = MODE == kConservative && depth > kRefineAbove ? root_slack(L.c) : -1.0f;
                     L.start = 0;
                     L.size = kRootSize;

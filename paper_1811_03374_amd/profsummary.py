@@ -74,7 +74,7 @@ def read_counter(path, counter):
 
 
 CALL_KERNELS = ("k_fused",)
-PLAIN_KERNEL = "k_fused<0, false, false, false>"     # the plain single-call variant
+PLAIN_KERNEL = "k_fused<0, false, false, false, true>"     # the plain single-call variant
 
 
 def per_call(dispatches, factor):
