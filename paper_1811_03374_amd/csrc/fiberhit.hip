@@ -58,6 +58,8 @@ __device__ __forceinline__ int qslot(int x)
 }
 constexpr int kQWords = 21;                   // root node (16), lo, hi, tmax, pair, scene * 64 + stall * 32 + depth
 constexpr uint32_t kRootSize = 1u << 23;      // parametric domain [0, 1) in units of 2^-23
+constexpr uint32_t kStallBit = 1u << 31;       // flag bit kept in a lane's interval start
+constexpr uint32_t kStartMask = kRootSize - 1u;
 constexpr int kMaxTrips = 1 << 16;            // hang guard; real pairs need < 200 trips
 #ifndef FIBERHIT_PARENT_CACHE
 #define FIBERHIT_PARENT_CACHE 1
@@ -423,6 +425,29 @@ __device__ __forceinline__ bool disc_point(const Curve64 &c, double u, double &t
     return true;
 }
 
+// Does phi have a minimum inside the sample interval next to the end u (0 or
+// 1), given that the end sample is the lower of the two? Only if phi turns
+// there: it falls from u = 0, or rises into u = 1. From the slope of phi at
+// the end (t = N / D_z with N = <C, D>, D = C'/3, D' = 2E):
+//   phi' = 6 (C_x D_x + C_y D_y) + 2 (t - C_z)(t' - 3 D_z) - 6 r D_r,
+//   t'   = ((3 |D|^2 + 2 <C, E>) D_z - 2 N E_z) / D_z^2.
+// At a vanishing end tangent (no disc plane of its own; the limit plane
+// serves) the slope is not formed and the interval is searched.
+__device__ __forceinline__ bool end_turns(const Curve64 &c, double u)
+{
+    double C[4], D[4], E[3];
+    eval_curve(c, u, C, D, E);
+    const double ax = c.q[3][0] - c.q[0][0], ay = c.q[3][1] - c.q[0][1], az = c.q[3][2] - c.q[0][2];
+    if (D[0] * D[0] + D[1] * D[1] + D[2] * D[2] <= 0x1p-40 * (ax * ax + ay * ay + az * az)) return true;
+    if (D[2] == 0.0) return true;
+    const double N = C[0] * D[0] + C[1] * D[1] + C[2] * D[2];
+    const double t = N / D[2];
+    const double dN = 3.0 * (D[0] * D[0] + D[1] * D[1] + D[2] * D[2]) + 2.0 * (C[0] * E[0] + C[1] * E[1] + C[2] * E[2]);
+    const double dt = (dN * D[2] - 2.0 * N * E[2]) / (D[2] * D[2]);
+    const double dphi = 6.0 * (C[0] * D[0] + C[1] * D[1]) + 2.0 * (t - C[2]) * (dt - 3.0 * D[2]) - 6.0 * C[3] * D[3];
+    return u == 0.0 ? !(dphi >= 0.0) : !(dphi <= 0.0);       // NaN: searched
+}
+
 // t of a boundary point known to lie on the circle of the disc at u (C, D
 // from eval_curve) whose plane crossing is t_plane = <C, D> / D_z. On the
 // circle the same point is also C_z +- sqrt(r^2 - C_x^2 - C_y^2). The plane
@@ -553,7 +578,7 @@ __device__ __forceinline__ void leaf_candidates(const Curve64 &c, double ua, dou
                                                 double tmax, double t0, double u0, double &t_best,
                                                 double &u_best)
 {
-    constexpr int kWords = (NS + 2 + 31) / 32;          // bits 0..NS + 1
+    constexpr int kWords = (NS + 1 + 31) / 32;
     auto take = [&](double t, double u) {
         if (t >= tlo && t <= thi && t < tmax && t < t_best) { t_best = t; u_best = u; }
     };
@@ -570,7 +595,9 @@ __device__ __forceinline__ void leaf_candidates(const Curve64 &c, double ua, dou
     uint32_t in_m[kWords], tneg_m[kWords], sign_m[kWords], min_m[kWords], org_m[kWords];
 #pragma unroll
     for (int q = 0; q < kWords; ++q) in_m[q] = tneg_m[q] = sign_m[q] = min_m[q] = org_m[q] = 0u;
-    double pt = 0.0, pphi = 0.0, ppphi = INFINITY;
+    // the first sample counts as a minimum (event 1) only where phi turns
+    // inside the first interval
+    double pt = 0.0, pphi = 0.0, ppphi = ua == 0.0 && !end_turns(c, 0.0) ? -INFINITY : INFINITY;
     bool pok = disc_point(c, ua, pt, pphi);
     if (pok && pphi <= 0.0) in_m[0] |= 1u;
     if (pok && pt <= 0.0) tneg_m[0] |= 1u;
@@ -589,9 +616,11 @@ __device__ __forceinline__ void leaf_candidates(const Curve64 &c, double ua, dou
         pt = ct; pphi = cphi; pok = cok;
     }
     // phi still falling at the last sample: a dip can sit between the last
-    // two samples (a stalled end, where the disc planes turn fast as u -> 1);
-    // recorded as event NS + 1, searched on (u[NS-1], u[NS])
-    if (pok && pphi > 0.0 && ppphi > pphi) min_m[(NS + 1) >> 5] |= 1u << ((NS + 1) & 31);
+    // two samples (as at a stalled end, where the disc planes turn fast as
+    // u -> 1), where phi turns before the end; recorded as the event of a
+    // minimum at sample NS - 1 (searched on (u[NS-2], u[NS]), which holds it)
+    if (pok && pphi > 0.0 && ppphi > pphi && (ub < 1.0 || end_turns(c, 1.0)))
+        min_m[NS >> 5] |= 1u << (NS & 31);
     // masks are indexed with unrolled selects (no dynamic register indexing)
     auto flag = [&](const uint32_t *m, int k) {
         uint32_t w = 0u;
@@ -618,11 +647,10 @@ __device__ __forceinline__ void leaf_candidates(const Curve64 &c, double ua, dou
     }
     // a local minimum of phi above zero at sample k-1: a dip below zero
     // narrower than the sampling has two boundary points in (u[k-2], u[k])
-    // (event NS + 1: in (u[NS-1], u[NS]))
     for (int k; (k = next_event(min_m)) >= 0;) {
         {
             constexpr double g = 0.38196601125010515;         // golden-section step
-            double a = at(k >= 2 ? k - 2 : 0), b = at(k > NS ? NS : k), tt;
+            double a = at(k >= 2 ? k - 2 : 0), b = at(k), tt;
             double x1 = a + g * (b - a), x2 = b - g * (b - a), f1 = 0.0, f2 = 0.0;
             bool ok = disc_point(c, x1, tt, f1) && disc_point(c, x2, tt, f2);
             for (int it = 0; ok && it < 48 && f1 > 0.0 && f2 > 0.0; ++it) {
@@ -638,7 +666,7 @@ __device__ __forceinline__ void leaf_candidates(const Curve64 &c, double ua, dou
                 const double um = f1 <= f2 ? x1 : x2;
                 double t, u;
                 if (boundary_root(c, at(k >= 2 ? k - 2 : 0), um, false, t, u)) take(t, u);
-                if (boundary_root(c, um, at(k > NS ? NS : k), true, t, u)) take(t, u);
+                if (boundary_root(c, um, at(k), true, t, u)) take(t, u);
             }
         }
     }
@@ -678,9 +706,10 @@ struct Lane {
     Node root;                    // the pair's root (replays of the split rules start here)
     float lo, hi;                 // cropped t interval of the current node
     float tmax, t;                // ray tmax; hit distance once found
-    uint32_t bits, start, size;   // Section 3.3: pending-sibling bits, integer interval
+    uint32_t bits, start, size;   // Section 3.3: pending-sibling bits, integer interval (start:
+                                  // bits 0..22; bit 31 set when the pair's end nodes may stall,
+                                  // see stall_possible)
     uint32_t min_size;            // leaf size 2^(23 - depth)
-    int32_t stall;                // the pair's end nodes may stall (see stall_possible)
     uint32_t cached;              // size of the pending children whose parent is cached (0: none)
     int32_t waiting;              // refinement: parked at its first leaf until the wave decides it
     float ru;                     //   the FP32 u of the leaf hit (Newton's start)
@@ -771,7 +800,7 @@ __device__ __forceinline__ float leaf_u(const Lane &L)
         ul = dot3(-L.c.p.x, -L.c.p.y, L.t - L.c.p.z, L.c.d.x, L.c.d.y, L.c.d.z) * rcp(cc);
         ul = fminf(1.0f, fmaxf(0.0f, ul));
     }
-    return fmaf(ul, (float)L.size * 0x1p-23f, (float)L.start * 0x1p-23f);
+    return fmaf(ul, (float)L.size * 0x1p-23f, (float)(L.start & kStartMask) * 0x1p-23f);
 }
 
 // FP64 decision of a pair of depth > 16 once the conservative search reaches
@@ -999,7 +1028,7 @@ __device__ __forceinline__ float stall_abs(const Node &r)
 
 __device__ __forceinline__ bool stalled_end(const Lane &L)
 {
-    if (!L.stall) return false;
+    if (!(L.start & kStallBit)) return false;
     const float s = (float)L.size * 0x1p-23f;                 // 2^-level
     const float rel = 0x1p-16f * node_extent(L.root) * s * s;
     // the chord alone fails the relative bound at every regular node: the
@@ -1007,7 +1036,8 @@ __device__ __forceinline__ bool stalled_end(const Lane &L)
     const float cc = dot3(L.c.d.x, L.c.d.y, L.c.d.z, L.c.d.x, L.c.d.y, L.c.d.z);
     if (!(cc <= rel)) return false;
     const float e = node_extent(L.c);
-    const bool end = L.start == 0u || L.start + L.size == kRootSize;
+    const uint32_t start = L.start & kStartMask;
+    const bool end = start == 0u || start + L.size == kRootSize;
     return end && e <= rel && e <= stall_abs(L.root);
 }
 
@@ -1494,11 +1524,10 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
                     const int ds = __float_as_int(q[20 * kQueue]);
                     const uint32_t depth = (uint32_t)ds & 31u;
                     L.scene = ds >> 6;
-                    L.stall = ds & 32;
                     L.root = L.c;
                     L.min_size = kRootSize >> depth;
                     L.slack = MODE == kConservative && depth > kRefineAbove ? root_slack(L.c) : -1.0f;
-                    L.start = 0;
+                    L.start = (ds & 32) ? kStallBit : 0u;
                     L.size = kRootSize;
                     L.bits = 0;
                     L.cached = 0;
