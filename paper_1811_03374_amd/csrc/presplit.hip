@@ -190,9 +190,36 @@ __device__ __forceinline__ void node_of(const float *F, int64_t fs, int64_t i, i
     for (int l = level - 1; l >= 0; --l) halve(q, ((index >> l) & 1u) != 0u);
 }
 
+// Does node q become a piece (emitted), and its mask: a node below the
+// level limit that fails an inequality is halved whatever its cap-plane
+// excesses, so they are only searched where they decide (the inequalities
+// hold) or where the piece's mask is wanted (`leaf_mask`).
+__device__ __forceinline__ bool piece_decision(const Q16 &q, int level, int max_level, bool leaf_mask, int &m)
+{
+    for (int k = 0; k < 16; ++k)
+        if (!isfinite(q.v[k])) {
+            m = 1 << 7;
+            return true;
+        }
+    const int ineq = constraint_bits(q);
+    if (level >= max_level && !leaf_mask) {
+        m = ineq;
+        return true;
+    }
+    if (level < max_level && ineq != 0) {
+        m = ineq;
+        return false;
+    }
+    float e0, e1;
+    m = fiber_mask(q, &e0, &e1);
+    return m == 0 || level >= max_level;
+}
+
 // Depth-first walk over the pieces of fiber i: `emit(level, index, q, mask)`
-// for every piece in order; returns their number.
-template <class Emit>
+// for every piece in order; returns their number. LEAF_MASK: the pieces'
+// masks are wanted (else a piece at the level limit may carry its
+// inequality bits only).
+template <bool LEAF_MASK, class Emit>
 __device__ int64_t walk_pieces(const float *F, int64_t fs, int64_t i, int max_level, Emit emit)
 {
     int level = 0;
@@ -201,9 +228,8 @@ __device__ int64_t walk_pieces(const float *F, int64_t fs, int64_t i, int max_le
     for (;;) {
         Q16 q;
         node_of(F, fs, i, level, index, q);
-        float e0, e1;
-        const int m = fiber_mask(q, &e0, &e1);
-        if (m == 0 || level >= max_level || (m & (1 << 7))) {
+        int m;
+        if (piece_decision(q, level, max_level, LEAF_MASK, m)) {
             emit(level, index, q, m, count);
             ++count;
             // next node in depth-first order: climb while this is a right child
@@ -242,7 +268,7 @@ __global__ __launch_bounds__(256) void k_presplit_count(const float *F, int64_t 
         counts[n] = 0;
         return;
     }
-    counts[i] = walk_pieces(F, fs, i, max_level, [](int, uint32_t, const Q16 &, int, int64_t) {});
+    counts[i] = walk_pieces<false>(F, fs, i, max_level, [](int, uint32_t, const Q16 &, int, int64_t) {});
 }
 
 __global__ __launch_bounds__(256) void k_presplit_write(const float *F, int64_t fs, int64_t n, int max_level,
@@ -253,7 +279,7 @@ __global__ __launch_bounds__(256) void k_presplit_write(const float *F, int64_t 
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     const int64_t base = offsets[i];
-    walk_pieces(F, fs, i, max_level, [&](int level, uint32_t index, const Q16 &q, int m, int64_t k) {
+    walk_pieces<true>(F, fs, i, max_level, [&](int level, uint32_t index, const Q16 &q, int m, int64_t k) {
         const int64_t j = base + k;
         if (j < 0 || j >= n_pieces) return;
         for (int c = 0; c < 16; ++c) P[c * ps + j] = (float)q.v[c];
