@@ -1394,6 +1394,30 @@ __device__ __forceinline__ bool load_pair(const Args &a, int64_t i, float *q, fl
 // test costs about three trips' time). The attribute sets the register
 // budget; the LDS (queue and parent cache, 9.5 KiB) allows 16 waves per CU.
 
+// The output side of a scene descriptor (what finish reads), as wave-uniform
+// values.
+template <class T>
+__device__ __forceinline__ T *uniform_ptr(T *p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (T *)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ void uniform_outputs(const Args &s, Args &o)
+{
+    o.t_out = uniform_ptr(s.t_out);
+    o.u_out = uniform_ptr(s.u_out);
+    o.hit_out = uniform_ptr(s.hit_out);
+    o.counts = uniform_ptr(s.counts);
+    o.t64_out = uniform_ptr(s.t64_out);
+    o.u64_out = uniform_ptr(s.u64_out);
+    o.normal_out = uniform_ptr(s.normal_out);
+    o.n_pairs = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)s.n_pairs >> 32)) << 32) |
+                          __builtin_amdgcn_readfirstlane((uint32_t)s.n_pairs));
+}
+
 // The wave's contiguous range of the call's pairs (an even share).
 __device__ __forceinline__ void wave_range(int64_t w, int64_t waves, int64_t count, int64_t &begin, int64_t &end)
 {
@@ -1421,8 +1445,11 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
     // batched: pairs are numbered across the scene table; the wave's share
     // is contiguous, so the scene of its next pair only moves forward
     int scene0 = 0;                      // scene of the wave's next pair (wave-uniform)
-    if constexpr (BATCHED)
+    Args cur = a0;                       // batched: scene0's outputs, read once per change
+    if constexpr (BATCHED) {
         scene0 = __builtin_amdgcn_readfirstlane(next < count ? find_scene(offsets, n_scenes, next) : 0);
+        uniform_outputs(scenes[scene0], cur);
+    }
     int q_head = 0, q_count = 0;         // the queue: entries q_head .. q_head + q_count - 1 (mod kQueue)
     Lane L = {};
     L.lo = INFINITY;                                                   // an empty interval: no work
@@ -1503,8 +1530,10 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
             q_count += __popcll(qm);
             next += take;
             if constexpr (BATCHED) {
+                const int prev = scene0;
                 while (scene0 + 1 < n_scenes && next < count && offsets[scene0 + 1] <= next) ++scene0;
                 scene0 = __builtin_amdgcn_readfirstlane(scene0);
+                if (scene0 != prev) uniform_outputs(scenes[scene0], cur);
             }
         }
         if (q_count > 0 && n_free >= (refill < q_count ? refill : q_count)) {
@@ -1554,7 +1583,7 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
                 // lanes of the wave's current scene read its output
                 // pointers with uniform loads; others (a scene boundary
                 // inside the wave) load their scene's
-                if (L.scene == scene0) finish<MODE>(scenes[scene0], L.pair, L, st == kHit, hg);
+                if (L.scene == scene0) finish<MODE>(cur, L.pair, L, st == kHit, hg);
                 else finish<MODE>(scenes[L.scene], L.pair, L, st == kHit, hg);
             } else {
                 finish<MODE, CAND>(a0, L.pair, L, st == kHit, hg);
