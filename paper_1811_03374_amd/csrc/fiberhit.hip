@@ -1394,8 +1394,8 @@ __device__ __forceinline__ bool load_pair(const Args &a, int64_t i, float *q, fl
 // test costs about three trips' time). The attribute sets the register
 // budget; the LDS (queue and parent cache, 9.5 KiB) allows 16 waves per CU.
 
-// The output side of a scene descriptor (what finish reads), as wave-uniform
-// values.
+// A scene descriptor's fields that pair loading and finishing read, as
+// wave-uniform values.
 template <class T>
 __device__ __forceinline__ T *uniform_ptr(T *p)
 {
@@ -1405,8 +1405,24 @@ __device__ __forceinline__ T *uniform_ptr(T *p)
     return (T *)(((uint64_t)hi << 32) | lo);
 }
 
-__device__ __forceinline__ void uniform_outputs(const Args &s, Args &o)
+__device__ __forceinline__ int64_t uniform_i64(int64_t x)
 {
+    return (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32)) << 32) |
+                     __builtin_amdgcn_readfirstlane((uint32_t)x));
+}
+
+__device__ __forceinline__ void uniform_scene(const Args &s, Args &o)
+{
+    o.rays = uniform_ptr(s.rays);
+    o.ray_stride = uniform_i64(s.ray_stride);
+    o.n_rays = uniform_i64(s.n_rays);
+    o.fibers = uniform_ptr(s.fibers);
+    o.fiber_stride = uniform_i64(s.fiber_stride);
+    o.n_fibers = uniform_i64(s.n_fibers);
+    o.pair_ray = uniform_ptr(s.pair_ray);
+    o.pair_fiber = uniform_ptr(s.pair_fiber);
+    o.pair_depth = uniform_ptr(s.pair_depth);
+    o.depth = __builtin_amdgcn_readfirstlane(s.depth);
     o.t_out = uniform_ptr(s.t_out);
     o.u_out = uniform_ptr(s.u_out);
     o.hit_out = uniform_ptr(s.hit_out);
@@ -1414,8 +1430,7 @@ __device__ __forceinline__ void uniform_outputs(const Args &s, Args &o)
     o.t64_out = uniform_ptr(s.t64_out);
     o.u64_out = uniform_ptr(s.u64_out);
     o.normal_out = uniform_ptr(s.normal_out);
-    o.n_pairs = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)s.n_pairs >> 32)) << 32) |
-                          __builtin_amdgcn_readfirstlane((uint32_t)s.n_pairs));
+    o.n_pairs = uniform_i64(s.n_pairs);
 }
 
 // The wave's contiguous range of the call's pairs (an even share).
@@ -1445,10 +1460,13 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
     // batched: pairs are numbered across the scene table; the wave's share
     // is contiguous, so the scene of its next pair only moves forward
     int scene0 = 0;                      // scene of the wave's next pair (wave-uniform)
-    Args cur = a0;                       // batched: scene0's outputs, read once per change
+    Args cur = a0;                       // batched: scene0's descriptor, read once per change
+    int64_t base0 = 0, bound0 = count;   // batched: scene0's first pair, and the next scene's
     if constexpr (BATCHED) {
         scene0 = __builtin_amdgcn_readfirstlane(next < count ? find_scene(offsets, n_scenes, next) : 0);
-        uniform_outputs(scenes[scene0], cur);
+        uniform_scene(scenes[scene0], cur);
+        base0 = uniform_i64(offsets[scene0]);
+        bound0 = uniform_i64(offsets[scene0 + 1]);
     }
     int q_head = 0, q_count = 0;         // the queue: entries q_head .. q_head + q_count - 1 (mod kQueue)
     Lane L = {};
@@ -1475,9 +1493,14 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
             if (lane < take) {
                 Args a = a0;
                 if constexpr (BATCHED) {
-                    while (sc + 1 < n_scenes && offsets[sc + 1] <= idx) ++sc;
-                    idx -= offsets[sc];
-                    a = scenes[sc];
+                    if (idx < bound0) {
+                        idx -= base0;
+                        a = cur;
+                    } else {
+                        while (sc + 1 < n_scenes && offsets[sc + 1] <= idx) ++sc;
+                        idx -= offsets[sc];
+                        a = scenes[sc];
+                    }
                 }
                 const bool ok = load_pair<CAND, QUAD>(a, idx, stage, rtmax, depth, aos);
                 asm volatile("" ::: "memory");
@@ -1530,10 +1553,13 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
             q_count += __popcll(qm);
             next += take;
             if constexpr (BATCHED) {
-                const int prev = scene0;
-                while (scene0 + 1 < n_scenes && next < count && offsets[scene0 + 1] <= next) ++scene0;
-                scene0 = __builtin_amdgcn_readfirstlane(scene0);
-                if (scene0 != prev) uniform_outputs(scenes[scene0], cur);
+                if (next < count && next >= bound0) {
+                    while (scene0 + 1 < n_scenes && offsets[scene0 + 1] <= next) ++scene0;
+                    scene0 = __builtin_amdgcn_readfirstlane(scene0);
+                    uniform_scene(scenes[scene0], cur);
+                    base0 = uniform_i64(offsets[scene0]);
+                    bound0 = uniform_i64(offsets[scene0 + 1]);
+                }
             }
         }
         if (q_count > 0 && n_free >= (refill < q_count ? refill : q_count)) {
