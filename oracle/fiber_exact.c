@@ -232,6 +232,9 @@ static int edge_on(const curve_t *c)
  * t in [0, tmax) is kept in (best, bu). */
 static void edge_on_sides(const curve_t *c, double tmax, double *best, double *bu)
 {
+    double scale = 0.0;
+    for (int j = 0; j < 4; ++j)
+        for (int k = 0; k < 3; ++k) scale = fmax(scale, fabs(c->q[j][k]));
     enum { N = 1 << 14 };
     for (int s = -1; s <= 1; s += 2) {
         int pok;
@@ -254,7 +257,15 @@ static void edge_on_sides(const curve_t *c, double tmax, double *best, double *b
                 long double t;
                 int tok;
                 gs_ld(c, 0.5L * (lo + hi), s, &tok, &t);
-                if (tok && t >= 0.0L && t < tmax && t < *best) { *best = (double)t; *bu = (double)(0.5L * (lo + hi)); }
+                /* where C' vanishes (a stalled end) g_s vanishes with it:
+                 * no disc plane, no boundary point */
+                double Cu[4], Du[3];
+                eval(c, (double)(0.5L * (lo + hi)), Cu, Du);
+                const int has_disc = sqrt(Du[0] * Du[0] + Du[1] * Du[1] + Du[2] * Du[2]) > 1e-12 * scale;
+                if (tok && has_disc && t >= 0.0L && t < tmax && t < *best) {
+                    *best = (double)t;
+                    *bu = (double)(0.5L * (lo + hi));
+                }
             }
             pg = cg;
             pok = cok;

@@ -325,3 +325,38 @@ def test_discs_nearly_containing_the_ray():
     for i in (3022, 16054):
         tb, ub = _mp_exact(R[:, i].astype(float), F[:, i].astype(float), dps=60)
         assert not hc[i] and tb == math.inf and not h[i], i
+
+
+def test_edge_on_rays_past_stalled_ends_miss():
+    """Rays within 1e-10..1e-7 rad of perpendicular to straight fibers with
+    p1 = p0 and p2 = p3, passing 2-30 % of the length beyond an end (within
+    the radius of the axis line): the capped cylinder is missed, and so must
+    the solid be. At a stalled end C' vanishes with both factors of the side
+    polynomial, which is no boundary point (no disc plane); taking it had
+    given hits here."""
+    rng = np.random.default_rng(62)
+    n = 400
+    a = rng.uniform(0, 1, (n, 3))
+    ax = rng.standard_normal((n, 3))
+    ax /= np.linalg.norm(ax, axis=1, keepdims=True)
+    L = rng.uniform(0.05, 0.5, n)
+    r = rng.uniform(0.001, 0.01, n)
+    perp = np.cross(ax, rng.standard_normal((n, 3)))
+    perp /= np.linalg.norm(perp, axis=1, keepdims=True)
+    tilt = 10.0 ** rng.uniform(-10, -7, n)
+    Dn = perp * np.cos(tilt)[:, None] + ax * np.sin(tilt)[:, None]
+    s = np.where(rng.uniform(0, 1, n) < 0.5, rng.uniform(1.02, 1.3, n), rng.uniform(-0.3, -0.02, n))
+    off = rng.uniform(-0.9, 0.9, n) * r
+    side = np.cross(Dn, ax)
+    side /= np.linalg.norm(side, axis=1, keepdims=True)
+    O = a + (s * L)[:, None] * ax + off[:, None] * side - 2.0 * Dn
+    P = np.empty((n, 4, 4))
+    for k in range(4):
+        P[:, k, :3] = a + ((0.0 if k < 2 else 1.0) * L)[:, None] * ax
+        P[:, k, 3] = r
+    rays = np.concatenate([O, Dn, np.full((n, 1), 10.0)], axis=1).T.copy()
+    fibers = P.reshape(n, 16).T.copy()
+    _, _, h_cf = capped_cylinder(O, Dn, P[:, 0, :3], P[:, 3, :3], r, np.full(n, 10.0))
+    assert not h_cf.any()
+    kinds = [oracle.single_exact(rays[:, i], fibers[:, i])[0] for i in range(n)]
+    assert all(k == 0 for k in kinds), np.unique(kinds, return_counts=True)

@@ -85,6 +85,8 @@ MUTANTS = [
      "    if (!eo) {\n        double bs = INFINITY, bus = NAN;", "    if (0) {\n        double bs = INFINITY, bus = NAN;"),
     ("exact oracle: side roots taken off the disc's circle", X, "if (on_circle && rest < -1e-9",
      "if (0 && rest < -1e-9"),
+    ("exact oracle: edge-on side points taken where C' vanishes", X,
+     "if (tok && has_disc && t >= 0.0L", "if (tok && t >= 0.0L"),
     ("exact oracle: radius term with the wrong sign", X, "F = badd(&F, &a3, -1.0);", "F = badd(&F, &a3, 1.0);"),
     ("exact oracle: no limit disc at a zero end tangent", X, "while (j < 2 && cand[j][0]", "while (0 && cand[j][0]"),
     ("exact oracle: edge-on rays through the expanded polynomial", X, "    if (eo) {\n        /* F's two roots",
