@@ -309,7 +309,7 @@ struct Args {
 
 constexpr int kRefineAbove = 16;         // refine pairs of depth > 16
 constexpr double kNewtonTol = 1e-9;      // relative residuals of an accepted Newton point
-constexpr int kCurveSamples = 128;       // phi samples over the whole curve (local minima are searched)
+constexpr int kCurveSamples = 64;        // phi samples over the whole curve (local minima are searched)
 
 struct Curve64 {
     double q[4][4];                      // control points in the FP64 ray frame (x, y, z, r)
