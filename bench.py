@@ -500,8 +500,8 @@ def bench_degenerate(args):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the per-pair test has no cross-GPU step, "
-              "and multi-GPU runs are not part of this build (use --gpus 1).", file=sys.stderr)
+        print("bench.py measures one GPU: the per-pair test has no cross-GPU step, and "
+              "this benchmark runs on a single GPU only (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
     if args.refine_probe:
         refine_probe()
