@@ -254,6 +254,45 @@ def test_full_size_sampled(depth):
     assert 0.45 < hit.mean() < 0.55
 
 
+@pytest.mark.parametrize("depth", [9, 22])
+def test_hair_full_size_sampled(depth):
+    """The hair configuration at its full size (2^24 rays against 800,000
+    segments gathered through an index), in the benchmark's launch
+    configuration, checked on a seeded sample of 8192 pairs against the depth
+    oracle; at depth 22 also the refined call against the exact oracle
+    (flags identical outside the 1e-4 r band, relative t <= 1e-12). Every
+    pair's miss encoding and t range are checked too."""
+    w = W.hair_precision(1 << 24, 100_000, depth=depth)
+    say(f"[parity] hair full size 2^24 depth={depth}")
+    t_g, u_g, h_g = run_gpu(w, depth)
+    idx = np.sort(np.random.default_rng(100 + depth).choice(w.n_pairs, 8192, replace=False))
+    ws = w.subset(idx)
+    (t_o, u_o, h_o), band = oracle_with_band(ws, depth)
+    st = compare(t_g[idx], u_g[idx], h_g[idx], t_o, u_o, h_o, band, depth, alt=tie_resolver(ws, depth))
+    say(f"[parity]   {st}")
+    assert st["ok"], st
+    hit = h_g.astype(bool)
+    assert np.all(np.isinf(t_g[~hit])) and np.all(np.isnan(u_g[~hit]))
+    tmax = w.rays[6][w.pair_ray[hit]] if w.pair_ray is not None else w.rays[6][hit]
+    assert np.all((t_g[hit] >= 0) & (t_g[hit] < tmax))
+    if depth != 22:
+        return
+    g = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    r = binding.intersect_pairs(g(w.rays), g(w.fibers), depth, g(w.pair_ray), g(w.pair_fiber), refine=True)
+    torch.cuda.synchronize()
+    h64, t64 = r[2].cpu().numpy()[idx].astype(bool), r[3].cpu().numpy()[idx]
+    tx, ux, hx, _ = oracle.intersect_exact(ws.rays, ws.fibers, ws.pair_ray, ws.pair_fiber)
+    _, _, hl, _ = oracle.intersect_exact(ws.rays, ws.fibers, ws.pair_ray, ws.pair_fiber, radius_scale=1 - 1e-4)
+    _, _, hh, _ = oracle.intersect_exact(ws.rays, ws.fibers, ws.pair_ray, ws.pair_fiber, radius_scale=1 + 1e-4)
+    m = hl == hh
+    both = m & h64 & hx.astype(bool)
+    rel = np.abs(t64[both] - tx[both]) / tx[both]
+    say(f"[parity]   refined: outside band {m.sum()}, flag disagree {(h64[m] != hx.astype(bool)[m]).sum()}, "
+        f"max rel t {rel.max():.2e}")
+    assert np.array_equal(h64[m], hx.astype(bool)[m])
+    assert rel.max() <= 1e-12
+
+
 def _bits(a):
     return np.ascontiguousarray(a).view(np.uint32 if a.dtype == np.float32 else np.uint8)
 
