@@ -164,3 +164,38 @@ def test_refined_edge_on_pairs():
     assert h_x.all() and h.all(), (h, h_x)
     assert np.all(np.abs(t64 - t_x) <= 1e-12 * t_x), (t64, t_x)
     assert np.all(np.abs(u64 - u_x) <= 1e-9), (u64, u_x)
+
+
+def test_degenerate_full_size_sampled():
+    """The 2^22-pair degenerate batch in the benchmark's launch configuration
+    (per-pair depth 16..22), checked on a seeded sample of 8192 pairs: FP32
+    against the depth oracle for every family, and the refined call against
+    the exact oracle for the curves that pass the whole validation of
+    Sec. 3.4 (the five inequalities and the cap-plane test), with identical
+    flags outside the 1e-4 r band and relative t <= 1e-12."""
+    w = W.degenerate_geometry(1 << 22)
+    g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    say(f"[degenerate] full size 2^22 n={w.n_pairs}")
+    rays, fibers, pd = g(w.rays), g(w.fibers), g(w.pair_depth)
+    t, u, h = [o.cpu().numpy() for o in binding.intersect_pairs(rays, fibers, 22, pair_depth=pd)]
+    r = binding.intersect_pairs(rays, fibers, 22, pair_depth=pd, refine=True)
+    torch.cuda.synchronize()
+    h64, t64 = r[2].cpu().numpy().astype(bool), r[3].cpu().numpy()
+    idx = np.sort(np.random.default_rng(77).choice(w.n_pairs, 8192, replace=False))
+    ws = w.subset(idx)
+    (t_o, u_o, h_o), band = oracle_with_band(ws)
+    st = compare(t[idx], u[idx], h[idx], t_o, u_o, h_o, band, ws.pair_depth, alt=tie_resolver(ws))
+    say(f"[degenerate]   FP32 sample: {st}")
+    assert st["ok"], st
+    mask, _ = oracle.validate_table(ws.fibers)
+    tx, ux, hx, _ = oracle.intersect_exact(ws.rays, ws.fibers)
+    _, _, hl, _ = oracle.intersect_exact(ws.rays, ws.fibers, radius_scale=1 - 1e-4)
+    _, _, hh, _ = oracle.intersect_exact(ws.rays, ws.fibers, radius_scale=1 + 1e-4)
+    m = (mask == 0) & (hl == hh) & (ws.pair_depth > 16)
+    hxb = hx.astype(bool)
+    both = m & h64[idx] & hxb
+    rel = np.abs(t64[idx][both] - tx[both]) / tx[both]
+    say(f"[degenerate]   refined sample: valid outside band {m.sum()}, flag disagree "
+        f"{(h64[idx][m] != hxb[m]).sum()}, max rel t {rel.max() if rel.size else 0:.2e}")
+    assert np.array_equal(h64[idx][m], hxb[m])
+    assert rel.size == 0 or rel.max() <= 1e-12
