@@ -680,7 +680,9 @@ def main():
         roof[d] = {"bound": "alu", "achieved": tflops, "peak": workmodel.PEAK_FP32_TFLOPS,
                    "unit": "TFLOP/s", "frac": tflops / workmodel.PEAK_FP32_TFLOPS,
                    "traffic": measured_traffic(d), "kernel": "k_fused (one call)", "depth": d,
-                   "algorithmic_bytes": work[d]["bytes"]}
+                   "algorithmic_bytes": work[d]["bytes"],
+                   # the same against the peak without packed FP32 (not used here)
+                   "frac_unpacked": tflops / workmodel.PEAK_FP32_UNPACKED_TFLOPS}
     dominant = max(DEPTHS, key=lambda d: statistics.mean(launch_ms[d]))
     step_flops = sum(work[d]["flops"] for d in DEPTHS)
 
