@@ -33,7 +33,8 @@ def parse():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the 2^20-pair line (no normals, hair and batched blocks)")
-    ap.add_argument("--workload", choices=("straight_and_curved", "batched", "hair", "degenerate", "candidates"),
+    ap.add_argument("--workload", choices=("straight_and_curved", "batched", "hair", "degenerate", "candidates",
+                                                    "quadratic"),
                     default="straight_and_curved",
                     help="batched: 256 uneven scenes (~13 M pairs, adaptive depth), one graph launch "
                          "against 256 plain launches; hair: precision stress with error report")
@@ -393,6 +394,71 @@ def bench_candidates(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_quadratic(args):
+    """Quadratic fibers (Appendix B.1, FI_QUADRATIC): 2^20 pairs of the
+    quadratic recipe at depth 9 and 22 in FP32 and at 22 with FP64
+    refinement, with the cubic calls on the same curves (their exact
+    elevations, as 16-row tables) beside them; errors on a seeded sample of
+    4,096 pairs against the depth oracle's quadratic mode, and refined
+    against the exact oracle on the quadratics that meet the constraint."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1811_03374_amd import binding
+    from paper_1811_03374_amd import workloads as W
+
+    w = W.quadratic_fibers(1 << 20)
+    dev = torch.device("cuda:0")
+    g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    rays, fibers = g(w.rays), g(w.fibers)
+    cubic = g(W.pack_fibers(W.elevate_quadratic(W.unpack_quadratics(w.fibers))))
+    n = rays.shape[1]
+    stream = torch.cuda.current_stream()
+    res, outs = {}, {}
+    for name, d, ref, tab, quad in (("fp32_d9", 9, False, fibers, True), ("fp32_d22", 22, False, fibers, True),
+                                    ("fp64_refined_d22", 22, True, fibers, True),
+                                    ("cubic_fp32_d9", 9, False, cubic, False),
+                                    ("cubic_fp32_d22", 22, False, cubic, False)):
+        def call():
+            return binding.intersect_pairs(rays, tab, d, refine=ref, quadratic=quad, stream=stream)
+        ms = _timed(call, args.steps, args.warmup, stream)
+        outs[name] = [o.cpu().numpy() for o in call()]
+        res[name] = {"ms": ms, "gpairs_per_s": n / (ms * 1e-3) / 1e9, "hit_rate": float(outs[name][2].mean())}
+    idx = np.sort(np.random.default_rng(5).choice(n, 4096, replace=False))
+    ws = w.subset(idx)
+    for name, d in (("fp32_d9", 9), ("fp32_d22", 22)):
+        t_o, u_o, h_o = oracle.intersect_depth(ws.rays, ws.fibers, d, quadratic=True)
+        _, _, hl = oracle.intersect_depth(ws.rays, ws.fibers, d, radius_scale=1 - 1e-4, quadratic=True)
+        _, _, hh = oracle.intersect_depth(ws.rays, ws.fibers, d, radius_scale=1 + 1e-4, quadratic=True)
+        t, u, h = (a[idx] for a in outs[name][:3])
+        m = hl == hh
+        both = m & h.astype(bool) & h_o.astype(bool)
+        rel = np.abs(t[both] - t_o[both]) / t_o[both]
+        res[name]["vs_depth_oracle"] = {"pairs": int(m.sum()), "flag_disagree": int((h[m] != h_o[m]).sum()),
+                                        "max_rel_t": float(rel.max()) if rel.size else 0.0}
+    P = W.unpack_quadratics(ws.fibers)
+    valid = np.array([oracle.quadratic_constraint(P[i].reshape(12)) for i in range(P.shape[0])])
+    t_x, _, h_x, _ = oracle.intersect_exact(ws.rays, ws.fibers, quadratic=True)
+    _, _, hl, _ = oracle.intersect_exact(ws.rays, ws.fibers, radius_scale=1 - 1e-4, quadratic=True)
+    _, _, hh, _ = oracle.intersect_exact(ws.rays, ws.fibers, radius_scale=1 + 1e-4, quadratic=True)
+    h, t64 = outs["fp64_refined_d22"][2][idx], outs["fp64_refined_d22"][3][idx]
+    m = valid & (hl == hh)
+    both = m & h.astype(bool) & h_x.astype(bool)
+    rel = np.abs(t64[both] - t_x[both]) / t_x[both]
+    res["fp64_refined_d22"]["vs_exact_oracle"] = {"valid_pairs": int(m.sum()),
+                                                  "flag_disagree": int((h[m] != h_x[m]).sum()),
+                                                  "max_rel_t": float(rel.max()) if rel.size else 0.0}
+    line = {"metric": "ray-fiber intersections/sec (Gpairs/s), quadratic fibers",
+            "value": res["fp32_d22"]["gpairs_per_s"], "unit": "Gpairs/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "dtype": "f32 (+f64 refinement)",
+            "data": "synthetic",
+            "config": {"workload": "quadratic Bezier fibers: 2^20 pairs, chords 0.2..0.8, middle point "
+                                   "displaced up to 0.45 chord (a quarter straight), radius 0.002..0.02, "
+                                   "about half hit", "pairs": n},
+            "results": res}
+    print(json.dumps(line), flush=True)
+
+
 def bench_degenerate(args):
     """Degenerate-geometry batch: 2^22 pairs in four families (cusps,
     near-collinear points, zero end tangents, steep tapers), per-pair depth
@@ -514,6 +580,9 @@ def main():
         return
     if args.workload == "degenerate":
         bench_degenerate(args)
+        return
+    if args.workload == "quadratic":
+        bench_quadratic(args)
         return
     if args.workload == "candidates":
         bench_candidates(args)
