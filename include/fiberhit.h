@@ -124,7 +124,15 @@ size_t fiber_pairs_workspace_bytes(int64_t n_pairs, int64_t n_fibers, int32_t ga
  * subdivision depth pair_depth[i] (or `depth`): t is the entry into the
  * capped leaf cylinder, u is the curve parameter of the hit point projected
  * onto the leaf chord (Section 3.3, last paragraph), hit is 1 when
- * 0 <= t < tmax.
+ * 0 <= t < tmax. Degenerate tangents: a tangent whose squared length is at
+ * most 2^-40 of the squared chord counts as zero (its cap plane falls back
+ * to the next control-polygon edge; a zero split tangent is a cusp, where
+ * the split plane is normal to the chord), and a node that holds an end of
+ * the curve whose extent (largest squared length of chord and end
+ * tangents) is at most (2^-20 X)^2 (X the largest ray-frame coordinate of
+ * the control points) and at most 2^-16 of the root's extent times
+ * 4^-level is a leaf before the depth (a stalled end, where the curve's
+ * speed vanishes and further halving resolves only rounding).
  *
  * Arguments:
  *   rays, ray_stride, n_rays       ray table (see layout), ray_stride >= n_rays.
