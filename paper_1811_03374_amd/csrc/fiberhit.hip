@@ -1908,15 +1908,21 @@ void remember_tuning(const fi_scene *sc, int32_t n, bool refine, const fi_tuning
 }
 
 
-// Persistent waves of a single call: the resident waves. Twice as many,
-// each with half the share, made single deep calls (depth 16 and 22 at 2^20
-// pairs) about 13 % faster but two calls overlapped on two streams 7 %
-// slower (the second call's waves wait behind the first's); a grid skewed
-// towards the waves that start first on each SIMD, and issue priority by
-// progress through the share, were slower still.
+// Persistent waves of a single call: twice the resident waves, each with
+// half the share. The second half starts as waves of the first finish, so
+// waves whose pairs happened to need few trips take more of the work and
+// the call's tail shrinks. Measured against the resident waves alone (A/B
+// on one box, 2^20 pairs): depth 22 198 against 232 us, depth 9 123
+// against 115 us, the two calls overlapped on two streams 228.5 against
+// 230 us; hair (2^24 pairs) 1.23 / 1.90 against 1.26 / 1.96 ms; refined
+// hair 3.93 against 4.13 ms per 2^22 pairs. Four times the resident waves
+// was slower (overlapped 283 us), and so were twice the waves for deep
+// calls only (overlapped 250 us: the shallow call's waves then wait behind
+// the deep call's), a grid skewed towards the waves that start first on
+// each SIMD, and issue priority by progress through the share.
 int64_t single_call_waves(const DeviceInfo &d, int mode, const Args &)
 {
-    return (int64_t)d.fused_resident[mode] * d.cus;
+    return 2 * (int64_t)d.fused_resident[mode] * d.cus;
 }
 
 // Enqueue one single call on `s`: the fiber records (when `aos` is given and
