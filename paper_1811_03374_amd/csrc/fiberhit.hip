@@ -1919,10 +1919,13 @@ void remember_tuning(const fi_scene *sc, int32_t n, bool refine, const fi_tuning
 // was slower (overlapped 283 us), and so were twice the waves for deep
 // calls only (overlapped 250 us: the shallow call's waves then wait behind
 // the deep call's), a grid skewed towards the waves that start first on
-// each SIMD, and issue priority by progress through the share.
+// each SIMD, and issue priority by progress through the share. The rounds
+// of candidate lists keep the resident waves: most of their pairs end at
+// the root, and twice the waves made them 15 % (refined 39 %) slower.
 int64_t single_call_waves(const DeviceInfo &d, int mode, const Args &)
 {
-    return 2 * (int64_t)d.fused_resident[mode] * d.cus;
+    const bool cand = mode == kCandVariant || mode == kCandVariant + 1;
+    return (cand ? 1 : 2) * (int64_t)d.fused_resident[mode] * d.cus;
 }
 
 // Enqueue one single call on `s`: the fiber records (when `aos` is given and
