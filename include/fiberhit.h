@@ -415,8 +415,10 @@ typedef struct fi_scene {
 /* Launch tuning of the batched kernel (not part of the method):
  *   refill          free lanes take queued pairs once at least this many
  *                   (1..64) are free (default 1);
- *   waves_per_simd  cap on resident waves per SIMD (0..16, 0 = as many as fit,
- *                   which is 4 for the batched kernel);
+ *   waves_per_simd  waves of the grid per SIMD (0..16; 0 = as many as fit,
+ *                   which is 4 for the batched kernel; fewer leave slots
+ *                   free, more are started by the dispatcher as resident
+ *                   waves end, each wave with an equal share of the pairs);
  *   stack           layout of the traversal stack (Section 3.3 keeps only the
  *                   bit string): 0 (default) caches the parent of the latest
  *                   split that left a sibling pending in LDS, so the usual
@@ -486,7 +488,7 @@ int fiber_batch_plan_destroy(fi_batch_plan *plan);
 /*
  * fiber_batch_autotune -- time fiber_intersect_batched on these scenes over a
  * grid of tunings (refill 32, 48 or 56, with FI_FP64_REFINE 4, 8 or 16;
- * waves per SIMD 4, 5 or as many as fit; stack 0 or 1), each `repeats`
+ * waves per SIMD as many as fit, 8 or 16; stack 0 or 1), each `repeats`
  * times after one warm-up, and return the fastest
  * in *best (and its time in *best_ms if not NULL). Overwrites the scenes'
  * outputs. Blocks the host until the timing runs finish. The result is also

@@ -2007,15 +2007,17 @@ BatchLayout layout_of(void *ws, int n)
 }
 
 // One persistent launch over all scenes of a batch: about one wave per 64
-// pairs, at most the resident waves (fewer when the tuning caps the waves
-// per SIMD).
+// pairs, at most the resident waves, or the tuning's waves per SIMD (fewer
+// or more than fit).
 void launch_batched(const DeviceInfo &d, const fi_tuning &t, const BatchLayout &L, int n_scenes, int64_t total,
                     bool refine, hipStream_t s)
 {
     const int variant = t.stack == 1 ? kBatchedReplayVariant + (refine ? 1 : 0)
                                      : (refine ? kBatchedRefineVariant : kBatchedVariant);
     int per_cu = d.fused_resident[variant];
-    if (t.waves_per_simd > 0 && 4 * t.waves_per_simd < per_cu) per_cu = 4 * t.waves_per_simd;
+    // below the resident waves per SIMD: fewer waves; above: the grid holds
+    // more waves than fit, and the dispatcher starts them as others end
+    if (t.waves_per_simd > 0) per_cu = 4 * t.waves_per_simd;
     int64_t g = (total + kWave - 1) / kWave;
     if (g > (int64_t)per_cu * d.cus) g = (int64_t)per_cu * d.cus;
     if (g > 0)
@@ -2331,7 +2333,7 @@ int fiber_batch_autotune(const fi_scene *scenes, int32_t n_scenes, uint32_t flag
     const int plain_refills[] = {32, 48, 56};
     const int refine_refills[] = {4, 8, 16};
     const int *refills = refine ? refine_refills : plain_refills;
-    const int occ[] = {4, 5, 0};
+    const int occ[] = {0, 8, 16};         // as many as fit (4), twice, four times
     float best_t = INFINITY;
     fi_tuning bt = default_tuning(refine);
     int st = FI_OK;

@@ -144,7 +144,7 @@ def test_autotune_returns_a_grid_point(tmp_path):
     binding.clear_tuning()
     best, ms = binding.autotune(probs, repeats=1)
     say(f"[autotune] {best} {ms:.3f} ms")
-    assert best["refill"] in (32, 48, 56) and best["waves_per_simd"] in (4, 5, 0) and best["stack"] in (0, 1)
+    assert best["refill"] in (32, 48, 56) and best["waves_per_simd"] in (0, 8, 16) and best["stack"] in (0, 1)
     assert ms > 0
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     total = sum(int(p.n) for p in probs)
