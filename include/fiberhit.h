@@ -171,10 +171,10 @@ size_t fiber_pairs_workspace_bytes(int64_t n_pairs, int64_t n_fibers, int32_t ga
  * first point of that solid along the ray, t in [0, tmax), over the whole
  * curve (boundary points from Newton's method on <P - C(u), C'(u)> = 0,
  * |P - C(u)| = r(u) started at the FP32 leaf hit, from 64 samples of the
- * disc excess with bisection at sign changes and golden-section search at
- * local minima, the end discs, t = 0 for an origin inside). All five outputs
- * then describe that point (hit decided in FP64; hit = 0, t = +inf when
- * there is none). Pairs of depth
+ * disc excess with a bracketed root search at sign changes and a bracketed
+ * minimisation at local minima, the end discs, t = 0 for an origin inside).
+ * All five outputs then describe that point (hit decided in FP64; hit = 0,
+ * t = +inf when there is none). Pairs of depth
  * <= 16 keep the plain method's results; their t64/u64 are the float results
  * widened.
  *

@@ -303,7 +303,7 @@ struct Args {
 //   it lies in that disc when              phi(u) = |P(t(u)) - C(u)|^2 - r(u)^2 <= 0
 //   boundary points solve                  f1 = <P - C, C'> = 0, f2 = |P - C|^2 - r^2 = 0
 // Candidates: Newton's method on (f1, f2) from the FP32 leaf hit; roots of
-// phi on the leaf interval (sampled, bisected, then polished by Newton);
+// phi on the leaf interval (sampled, bracketed, then polished by Newton);
 // the end discs when the leaf touches u = 0 or 1; t = 0 when the origin lies
 // in one of the leaf's discs. The smallest candidate in [0, tmax) is the hit.
 
@@ -505,19 +505,62 @@ __device__ __forceinline__ bool newton_surface(const Curve64 &c, double &t, doub
     return has_disc(c, D) && fabs(f2) <= kNewtonTol * scale && fabs(f1) <= kNewtonTol * C[3] * dn;
 }
 
-// Bisect a sign change of phi on [lo, hi] (lo_in: phi(lo) <= 0), then polish
-// the root by Newton's method, kept only if it stays within a few final
-// brackets (a polish that wanders further follows the residual's rounding,
-// not the root); returns the boundary point in (t, u).
+// Narrow a sign change of phi on [lo, hi] (lo_in: phi(lo) <= 0) to a
+// bracket of at most 2^-53, then polish the root by Newton's method, kept
+// only if it stays within a few final brackets (a polish that wanders
+// further follows the residual's rounding, not the root); returns the
+// boundary point in (t, u).
+// The bracket is narrowed by the ITP method (interpolate, truncate, project;
+// Oliveira and Takahashi, ACM Trans. Math. Softw. 47(1), 2020): each step
+// takes the false-position estimate from the end values, moves it towards
+// the midpoint by 0.2 (width)^2 / (initial width) (at least the final
+// bracket), and keeps it within a distance of the midpoint that shrinks as
+// the step budget is used up. It never takes more than one step beyond
+// bisection, and on the simple roots that phi has where the ray crosses the
+// boundary it takes about ten (a wave runs the steps of its slowest lane;
+// bisection took 44).
 __device__ __forceinline__ bool boundary_root(const Curve64 &c, double lo, double hi, bool lo_in, double &t,
                                               double &u)
 {
-    for (int it = 0; it < 44; ++it) {               // to 2^-44 of the bracket; Newton finishes
-        const double mid = 0.5 * (lo + hi);
-        if (!(mid > lo && mid < hi)) break;
-        double mt, mphi;
-        if (!disc_point(c, mid, mt, mphi)) return false;
-        if ((mphi <= 0.0) == lo_in) lo = mid; else hi = mid;
+    constexpr double kEps = 0x1p-54;                // half the final bracket
+    // g = phi with the sign that makes g(lo) <= 0 <= g(hi). It only places
+    // the estimate (the bracket follows the sign of phi, as in bisection),
+    // so it is kept in FP32, which saves registers: the estimate's relative
+    // error of about 2^-24 still shrinks the bracket by about that factor a
+    // step near the root.
+    const float sg = lo_in ? 1.0f : -1.0f;
+    float gl = 0.0f, gh = 0.0f;
+    {
+        double tt, pl, ph;
+        if (disc_point(c, lo, tt, pl) && disc_point(c, hi, tt, ph)) {
+            gl = sg * (float)pl;
+            gh = sg * (float)ph;
+        }
+    }
+    const float k1 = 0.2f / (float)(hi - lo);
+    const int nmax = ilogb((hi - lo) / (2.0 * kEps)) + 2;       // bisection's steps, rounded up, plus one
+    for (int j = 0; j <= nmax && hi - lo > 2.0 * kEps; ++j) {
+        const double w = hi - lo, mid = 0.5 * (lo + hi);
+        double xf = mid;
+        if (gl <= 0.0f && gh >= 0.0f && gh > gl) xf = lo + w * (double)(gl / (gl - gh));
+        const double s = mid >= xf ? 1.0 : -1.0;
+        // at least the final bracket: an estimate that lands on the root
+        // then still steps past it, and the far end moves as well
+        const double delta = fmax((double)k1 * w * w, 2.0 * kEps);
+        const double xt = delta <= fabs(mid - xf) ? xf + s * delta : mid;
+        const double r = ldexp(kEps, nmax - j) - 0.5 * w;
+        double x = fabs(xt - mid) <= r ? xt : mid - s * r;
+        if (!(x > lo && x < hi)) x = mid;
+        if (!(x > lo && x < hi)) break;
+        double xt_, xphi;
+        if (!disc_point(c, x, xt_, xphi)) return false;
+        if ((xphi <= 0.0) == lo_in) {
+            lo = x;
+            gl = sg * (float)xphi;
+        } else {
+            hi = x;
+            gh = sg * (float)xphi;
+        }
     }
     u = 0.5 * (lo + hi);
     double phi;
@@ -541,7 +584,7 @@ __device__ __forceinline__ bool boundary_root(const Curve64 &c, double lo, doubl
 // to pass Newton's test still moves t by far more than rounding (a residual
 // e * r^2 moves t by about e * r / sqrt(2 * penetration / r)). Brackets of
 // growing width around u are tried; the first with a sign change is
-// bisected. Without one the point is kept.
+// narrowed to its root. Without one the point is kept.
 __device__ __forceinline__ void bracket_polish(const Curve64 &c, double &t, double &u)
 {
     double w = 0x1p-32;
@@ -646,24 +689,69 @@ __device__ __forceinline__ void leaf_candidates(const Curve64 &c, double ua, dou
         }
     }
     // a local minimum of phi above zero at sample k-1: a dip below zero
-    // narrower than the sampling has two boundary points in (u[k-2], u[k])
+    // narrower than the sampling has two boundary points in (u[k-2], u[k]).
+    // The dip is searched by Brent's minimisation (Brent, Algorithms for
+    // Minimization without Derivatives, 1973, ch. 5): a parabola through
+    // the three best points so far, replaced by a golden-section step
+    // whenever its step is not acceptable, from the lowest sample. It stops
+    // at the first point with phi <= 0, or once the bracket around the best
+    // point is 2^-33 of the initial one (where 48 golden-section steps end,
+    // 0.618^48), in about a third of their evaluations.
     for (int k; (k = next_event(min_m)) >= 0;) {
         {
             constexpr double g = 0.38196601125010515;         // golden-section step
             double a = at(k >= 2 ? k - 2 : 0), b = at(k), tt;
-            double x1 = a + g * (b - a), x2 = b - g * (b - a), f1 = 0.0, f2 = 0.0;
-            bool ok = disc_point(c, x1, tt, f1) && disc_point(c, x2, tt, f2);
-            for (int it = 0; ok && it < 48 && f1 > 0.0 && f2 > 0.0; ++it) {
-                if (f1 < f2) {
-                    b = x2; x2 = x1; f2 = f1; x1 = a + g * (b - a);
-                    ok = disc_point(c, x1, tt, f1);
+            const double tol = (b - a) * 0x1p-35;
+            double x = at(k - 1), fx = 0.0;
+            bool ok = disc_point(c, x, tt, fx);
+            double xw = x, xv = x, fw = fx, fv = fx, d = 0.0, e = 0.0;
+            for (int it = 0; ok && it < 64 && fx > 0.0; ++it) {
+                const double m = 0.5 * (a + b);
+                if (fabs(x - m) <= 2.0 * tol - 0.5 * (b - a)) break;
+                bool gold = true;
+                if (fabs(e) > tol) {
+                    const double r = (x - xw) * (fx - fv);
+                    double q = (x - xv) * (fx - fw);
+                    double p = (x - xv) * q - (x - xw) * r;
+                    q = 2.0 * (q - r);
+                    if (q > 0.0) p = -p;
+                    else q = -q;
+                    const double e_old = e;
+                    e = d;
+                    if (fabs(p) < fabs(0.5 * q * e_old) && p > q * (a - x) && p < q * (b - x)) {
+                        d = p / q;                               // the parabola's step
+                        const double un = x + d;
+                        if (un - a < 2.0 * tol || b - un < 2.0 * tol) d = m >= x ? tol : -tol;
+                        gold = false;
+                    }
+                }
+                if (gold) {
+                    e = (x >= m ? a : b) - x;
+                    d = g * e;
+                }
+                const double un = fabs(d) >= tol ? x + d : x + (d > 0.0 ? tol : -tol);
+                double fu;
+                ok = disc_point(c, un, tt, fu);
+                if (!ok) break;
+                if (fu <= fx) {
+                    if (un >= x) a = x;
+                    else b = x;
+                    xv = xw; fv = fw;
+                    xw = x; fw = fx;
+                    x = un; fx = fu;
                 } else {
-                    a = x1; x1 = x2; f1 = f2; x2 = b - g * (b - a);
-                    ok = disc_point(c, x2, tt, f2);
+                    if (un < x) a = un;
+                    else b = un;
+                    if (fu <= fw || xw == x) {
+                        xv = xw; fv = fw;
+                        xw = un; fw = fu;
+                    } else if (fu <= fv || xv == x || xv == xw) {
+                        xv = un; fv = fu;
+                    }
                 }
             }
-            if (ok && fmin(f1, f2) <= 0.0) {
-                const double um = f1 <= f2 ? x1 : x2;
+            if (ok && fx <= 0.0) {
+                const double um = x;
                 double t, u;
                 if (boundary_root(c, at(k >= 2 ? k - 2 : 0), um, false, t, u)) take(t, u);
                 if (boundary_root(c, um, at(k), true, t, u)) take(t, u);
@@ -1645,14 +1733,21 @@ void k_fused(Args a0, const Args *scenes, const int64_t *offsets, int n_scenes, 
                         fi = a0.cand_fiber[a0.cand_off[L.pair] + a0.cand_round];
                         tlim = fmin((double)rays[6 * rs + L.pair], a0.t64_out[L.pair]);
                     }
-                    const Refined r = refine_whole_curve(rays, rs, fibers, fs, pr, pf, L.pair, fi, tlim, L.t, L.ru,
+                    const int32_t pair = L.pair, scene = L.scene;
+                    const Refined r = refine_whole_curve(rays, rs, fibers, fs, pr, pf, pair, fi, tlim, L.t, L.ru,
                                                          want_n, QUAD);
                     // the output pointers are read after the call (not kept
-                    // live across it)
-                    if constexpr (BATCHED) finish<MODE>(scenes[L.scene], L.pair, L, r.hit, HitGeo{}, r);
-                    else finish<MODE, CAND>(a0, L.pair, L, r.hit, HitGeo{}, r);
+                    // live across it); a refined pair's finish reads only the
+                    // search's result from the lane (slack >= 0)
+                    Lane R = {};
+                    if constexpr (BATCHED) finish<MODE>(scenes[scene], pair, R, r.hit, HitGeo{}, r);
+                    else finish<MODE, CAND>(a0, pair, R, r.hit, HitGeo{}, r);
                     active = false;
                 }
+                // every lane is free now. Its traversal state is reset, so
+                // that none of it is live across the searches (kept, it
+                // had to be saved and restored around the call)
+                L = Lane{};
             }
         }
         if (!active) {
