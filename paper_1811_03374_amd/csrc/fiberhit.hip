@@ -751,10 +751,14 @@ __device__ __forceinline__ void leaf_candidates(const Curve64 &c, double ua, dou
                 }
             }
             if (ok && fx <= 0.0) {
+                // the minimisation's bracket ends lie above zero (samples,
+                // or points it evaluated before the first one at or below
+                // zero), so they bracket the two boundary points more
+                // tightly than the samples
                 const double um = x;
                 double t, u;
-                if (boundary_root(c, at(k >= 2 ? k - 2 : 0), um, false, t, u)) take(t, u);
-                if (boundary_root(c, um, at(k), true, t, u)) take(t, u);
+                if (boundary_root(c, a, um, false, t, u)) take(t, u);
+                if (boundary_root(c, um, b, true, t, u)) take(t, u);
             }
         }
     }
