@@ -425,6 +425,22 @@ __device__ __forceinline__ bool disc_point(const Curve64 &c, double u, double &t
     return true;
 }
 
+// phi(u) D_z^2 without the division: (C_x^2 + C_y^2 - r^2) D_z^2 +
+// (C_x D_x + C_y D_y)^2 (the ray point's offset from the disc centre along
+// the ray is (C_x D_x + C_y D_y) / D_z). Same sign as phi where the disc
+// plane crosses the ray (D_z != 0); for the root search, which needs the
+// sign and, within a narrow bracket where D_z barely changes, the shape.
+__device__ __forceinline__ bool disc_excess_scaled(const Curve64 &c, double u, double &g)
+{
+    double C[4], D[4], E[3];
+    eval_curve(c, u, C, D, E);
+    end_disc_normal(c, u, D);
+    if (D[2] == 0.0) return false;
+    const double a = C[0] * D[0] + C[1] * D[1];
+    g = (C[0] * C[0] + C[1] * C[1] - C[3] * C[3]) * (D[2] * D[2]) + a * a;
+    return true;
+}
+
 // Does phi have a minimum inside the sample interval next to the end u (0 or
 // 1), given that the end sample is the lower of the two? Only if phi turns
 // there: it falls from u = 0, or rises into u = 1. From the slope of phi at
@@ -531,8 +547,8 @@ __device__ __forceinline__ bool boundary_root(const Curve64 &c, double lo, doubl
     const float sg = lo_in ? 1.0f : -1.0f;
     float gl = 0.0f, gh = 0.0f;
     {
-        double tt, pl, ph;
-        if (disc_point(c, lo, tt, pl) && disc_point(c, hi, tt, ph)) {
+        double pl, ph;
+        if (disc_excess_scaled(c, lo, pl) && disc_excess_scaled(c, hi, ph)) {
             gl = sg * (float)pl;
             gh = sg * (float)ph;
         }
@@ -552,8 +568,8 @@ __device__ __forceinline__ bool boundary_root(const Curve64 &c, double lo, doubl
         double x = fabs(xt - mid) <= r ? xt : mid - s * r;
         if (!(x > lo && x < hi)) x = mid;
         if (!(x > lo && x < hi)) break;
-        double xt_, xphi;
-        if (!disc_point(c, x, xt_, xphi)) return false;
+        double xphi;
+        if (!disc_excess_scaled(c, x, xphi)) return false;
         if ((xphi <= 0.0) == lo_in) {
             lo = x;
             gl = sg * (float)xphi;
